@@ -1,0 +1,248 @@
+/*
+ * rns.h -- C ABI of the MI355X (gfx950) exact multi-modular integer matrix
+ * product and the Smith-form driver built on it.
+ *
+ * The method (Section 3.1 of Wang, Birmpilis, Labahn, Storjohann, "A C
+ * implementation of the Smith massager algorithm"): an integer matrix is
+ * reduced modulo L word-size primes, the L residue matrices are multiplied
+ * independently modulo their prime, and the integer product is rebuilt by the
+ * Chinese Remainder Theorem.  The Smith normal form (Section 1) is the
+ * consumer: its lifting and massager steps reduce to such products.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrices are row-major.  A "plane stride" is the distance, in
+ *   elements, between the residue matrices of consecutive primes.
+ * - Residues are uint32 in the canonical range [0, p).
+ * - Pointers named d_* or documented as device pointers are HIP device
+ *   memory owned by the caller; the library never frees caller memory.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Work is enqueued asynchronously on it; the return code reports argument
+ *   validation and launch errors only.  Device-side conditions (CRT overflow)
+ *   are reported through a status word read after synchronisation.
+ * - A primes range (prime_begin, L) selects the basis primes
+ *   prime_begin .. prime_begin+L-1 of the context; plane j of every operand
+ *   belongs to prime prime_begin+j.
+ * - No call throws; every failure is a status code (rns_strerror names it).
+ * - A context may be used by one host thread at a time.  Independent
+ *   contexts may be used concurrently from different threads.
+ */
+#ifndef RNS_H
+#define RNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    RNS_OK = 0,
+    RNS_EINVAL = 1,     /* bad argument: null pointer, negative size, bad range */
+    RNS_ENOMEM = 2,     /* device or host allocation failed */
+    RNS_EDEVICE = 3,    /* a HIP call failed */
+    RNS_EBOUND = 4,     /* an exactness bound of the chosen path is violated */
+    RNS_EOVERFLOW = 5,  /* a reconstructed value does not fit the output words */
+    RNS_ESINGULAR = 6,  /* the input matrix is singular */
+    RNS_ERETRY = 7,     /* the Las Vegas restart budget was exhausted */
+    RNS_ENOTSUP = 8     /* the request is outside what this build implements */
+};
+
+/* Product paths of modmatmul_batched. */
+enum {
+    RNS_PATH_AUTO = 0,  /* the library chooses (autotuned per shape class) */
+    RNS_PATH_FP64 = 1,  /* balanced residues in FP64 MFMA, reduced every 8 terms */
+    RNS_PATH_INT8 = 2   /* 4 signed byte digits per residue, INT8 MFMA, int32 sums */
+};
+
+typedef struct rns_ctx rns_ctx;
+
+/* Human-readable name of a status code.  Never NULL. */
+const char *rns_strerror(int status);
+
+/*
+ * rns_primes_below -- the `count` largest primes strictly below `bound`,
+ * descending (Section 3.1: primes are taken consecutively below a bound).
+ * `out` is a host array of `count` entries.  bound <= 2^32.
+ * Returns RNS_EINVAL if there are fewer than `count` primes below `bound`.
+ */
+int rns_primes_below(uint64_t bound, int count, uint32_t *out);
+
+/*
+ * rns_ctx_create -- a context on HIP device `device` holding an RNS basis and
+ * the constants derived from it (Section 3.1, the bullet on precomputed RNS
+ * constants): per prime p, its double and double reciprocal, 2^(8s) mod p for
+ * the byte-digit recombination, the pairwise inverses of the Garner form of
+ * the CRT, and the symmetric-range constants.
+ *   primes: host array of L distinct odd primes, each < 2^26; NULL selects the
+ *           L largest primes below 2^26.
+ *   L:      1 <= L <= 4096.
+ *   flags:  reserved, pass 0.
+ * The context owns its device tables and a growable workspace; free it with
+ * rns_ctx_destroy.  Returns RNS_EINVAL for a bad basis, RNS_EDEVICE or
+ * RNS_ENOMEM on HIP failures.
+ */
+int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes, int L,
+                   uint64_t flags);
+void rns_ctx_destroy(rns_ctx *ctx);
+
+/* Number of primes and the primes themselves (host array of L entries). */
+int rns_ctx_num_primes(const rns_ctx *ctx);
+int rns_ctx_primes(const rns_ctx *ctx, uint32_t *out);
+
+/*
+ * rns_ctx_reserve -- grow the context's device workspace to at least `bytes`
+ * now, so that later calls of that size allocate nothing.  modmatmul_batched
+ * grows the workspace by itself when needed (a synchronous allocation).
+ */
+int rns_ctx_reserve(rns_ctx *ctx, size_t bytes);
+
+/*
+ * rns_primes_for_bound -- smallest L such that the product of the first L
+ * basis primes is at least 2*B + 1, where B is the non-negative integer given
+ * by `W` little-endian 64-bit words.  Every integer of absolute value at most
+ * B is then determined by its residues modulo those primes.
+ * Returns RNS_EBOUND if the whole basis is too short.
+ */
+int rns_primes_for_bound(const rns_ctx *ctx, const uint64_t *bound_words,
+                         int W, int *L_out);
+
+/*
+ * rns_reduce -- Section 3.1, reduction of an integer matrix modulo each prime:
+ *   res[j*plane_stride + i*ldr + c] = x[i*ldx + c] mod p_{prime_begin+j},
+ * floor semantics (the result is in [0, p) also for negative x).
+ *   x:   device int64, rows x cols, leading dimension ldx >= cols.
+ *   res: device uint32, L planes, leading dimension ldr >= cols,
+ *        plane_stride >= rows*ldr (planes must not overlap).
+ * rows == 0 or cols == 0 is a no-op.
+ */
+int rns_reduce(rns_ctx *ctx, const int64_t *x, int64_t rows, int64_t cols,
+               int64_t ldx, int prime_begin, int L, uint32_t *res,
+               int64_t ldr, int64_t plane_stride, void *stream);
+
+/*
+ * One residue product problem of modmatmul_batched:
+ *   for j in [0, L):  C_j = A_j * B_j mod p_{prime_begin+j}
+ * with A_j = A + j*a_plane_stride (m x k, leading dimension lda),
+ *      B_j = B + j*b_plane_stride (k x n, leading dimension ldb),
+ *      C_j = C + j*c_plane_stride (m x n, leading dimension ldc).
+ * A and B hold residues in [0, p); C receives residues in [0, p).
+ * All three are device pointers.
+ */
+typedef struct rns_gemm_desc {
+    int64_t m, n, k;
+    const uint32_t *A;
+    int64_t lda, a_plane_stride;
+    const uint32_t *B;
+    int64_t ldb, b_plane_stride;
+    uint32_t *C;
+    int64_t ldc, c_plane_stride;
+    int32_t prime_begin;
+    int32_t L;
+} rns_gemm_desc;
+
+/* Workspace bytes modmatmul_batched needs for these problems on this path. */
+int rns_workspace_bytes(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
+                        int path, size_t *bytes);
+
+/*
+ * modmatmul_batched -- Section 3.1, one independent product per prime, for
+ * `count` problems of any sizes, all primes of all problems in one pass.
+ *   descs: host array of `count` descriptors (read during the call only).
+ *   path:  RNS_PATH_FP64, RNS_PATH_INT8 or RNS_PATH_AUTO.
+ * Exactness: the FP64 path keeps every partial sum an integer below 2^53 by
+ * reducing every 8 terms, for any k.  The INT8 path keeps every int32 digit
+ * sum exact for k <= 43690 and returns RNS_EBOUND beyond.
+ * The result is bit-exact and does not depend on the path, the tiling, the
+ * launch order or the number of problems in the batch.  count == 0 is a
+ * no-op.  Input residues outside [0, p) give unspecified (but in-range)
+ * outputs.
+ */
+int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
+                      int path, void *stream);
+
+/*
+ * crt_reconstruct -- Section 3.1, Chinese-remainder reconstruction of every
+ * entry of an L-plane residue matrix: the unique integer x with
+ * |x| <= (M-1)/2, M = p_{prime_begin} ... p_{prime_begin+L-1}, and
+ * x = res_j (mod p_{prime_begin+j}) for all j.
+ *   res:  device uint32, L planes (rows x cols, leading dimension ldr,
+ *         plane_stride apart), residues in [0, p).
+ *   out:  device uint64; entry (i, c) occupies the W words
+ *         out[(i*ldo + c)*W + 0 .. W-1], little-endian two's complement
+ *         (W == 1 is a plain int64 matrix with leading dimension ldo).
+ *   bound_words / Wb: optional promise |x| <= B (Wb little-endian words; NULL
+ *         for none).  A promise that leaves a margin selects the Lagrange form
+ *         with a floating-point correction (Section 3.1, the bullet on fast
+ *         base conversion); otherwise the exact mixed-radix (Garner) form is
+ *         used.  A false promise gives unspecified outputs.
+ *   d_status: optional device int32; the kernel ORs 1 into it when some x
+ *         does not fit in W words (that entry holds x mod 2^(64W)).  NULL
+ *         uses the context's status word, read by rns_ctx_status.
+ * Limits: 1 <= L <= 64 primes, 1 <= W <= 32 words.
+ */
+int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows,
+                    int64_t cols, int64_t ldr, int64_t plane_stride,
+                    int prime_begin, int L, const uint64_t *bound_words,
+                    int Wb, uint64_t *out, int W, int64_t ldo,
+                    int32_t *d_status, void *stream);
+
+/*
+ * rns_ctx_status -- synchronise `stream`, then read and clear the context's
+ * device status word.  Returns RNS_EOVERFLOW if a CRT call that used it
+ * overflowed since the last read, RNS_OK otherwise.
+ */
+int rns_ctx_status(rns_ctx *ctx, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Smith normal form driver (Section 2.2, the three-phase Las Vegas method,
+ * in a reduced form that calls the RNS primitives above for every product).
+ * ---------------------------------------------------------------------- */
+
+typedef struct rns_smith_result rns_smith_result;
+
+typedef struct rns_smith_stats {
+    double t_lif;          /* seconds: largest invariant factor (Phase 1) */
+    double t_im;           /* seconds: projection and modular Smith form (Phase 2) */
+    double t_uc;           /* seconds: certification (Phase 3) */
+    double t_total;        /* seconds: whole call */
+    int restarts;          /* Las Vegas restarts taken */
+    int lift_steps;        /* p-adic lifting steps, all phases */
+    int64_t products;      /* modmatmul_batched calls issued */
+    double residue_ops;    /* 2*m*n*k*L summed over all products */
+    int cert_primes;       /* primes used by the determinant certificate */
+    int columns;           /* projection width of the last Phase-2 attempt */
+} rns_smith_stats;
+
+/*
+ * smith_form -- the Smith normal form S = diag(s_1, ..., s_n),
+ * s_1 | s_2 | ... | s_n, s_i > 0, of a nonsingular n x n integer matrix
+ * (Section 1).
+ *   A_host: host int64, n x n row-major (copied during the call).
+ *   seed:   drives the random choices only; S does not depend on it.
+ *   out:    receives a library-allocated result; free with rns_smith_free.
+ * Returns RNS_ESINGULAR when det A = 0, RNS_ERETRY when the restart budget is
+ * exhausted.  Uses the context's stream-less default stream internally and
+ * synchronises before returning.
+ */
+int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
+               rns_smith_result **out);
+
+/* Invariant factor i (0-based) as little-endian 64-bit magnitude words. */
+int rns_smith_get(const rns_smith_result *r, int64_t i, const uint64_t **words,
+                  int *nwords);
+int64_t rns_smith_size(const rns_smith_result *r);
+int rns_smith_stats_get(const rns_smith_result *r, rns_smith_stats *st);
+void rns_smith_free(rns_smith_result *r);
+
+/* Test hook: make the next `count` certifications of this context fail, to
+ * exercise the Las Vegas restart (Section 2.2, Phase 3).  0 disables. */
+int rns_ctx_force_cert_failures(rns_ctx *ctx, int count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RNS_H */

@@ -1,0 +1,11 @@
+"""MI355X-native exact multi-modular (RNS) integer matrix product and a
+Smith-form driver built on it.
+
+The computation lives in librns.so (HIP kernels for gfx950 behind the C ABI of
+include/rns.h); ``binding`` marshals torch device tensors into it.  Importing
+the binding without the built library raises ImportError: there is no CPU
+fallback.
+"""
+from .binding import (Context, GemmProblem, RnsError, SmithResult, crt_reconstruct,  # noqa: F401
+                      modmatmul_batched, rns_primes_below, rns_reduce, rns_strerror,
+                      smith_form, words_to_ints, workspace_bytes)

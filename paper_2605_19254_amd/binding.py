@@ -1,0 +1,351 @@
+"""ctypes binding of librns.so (the C ABI declared in include/rns.h).
+
+Argument marshalling only: device tensors are passed by pointer and stride,
+streams as torch's current HIP stream.  Every step of the computation runs in
+the library's HIP kernels; there is no fallback.  Importing this module on a
+tree without the built library raises ImportError.
+
+Residue planes are torch.int32 tensors (values in [0, 2^26) fit) of shape
+[L, rows, cols]; the C ABI sees them as uint32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librns.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("librns.so is not built (run __graft_entry__.build() or "
+                      "python paper_2605_19254_amd/build.py)")
+
+
+
+def _preload_torch_hip_runtime():
+    """Load the HIP runtime that torch carries (if any) with RTLD_GLOBAL before
+    librns, so that librns binds to the same runtime as torch: one process must
+    not drive the GPU through two HIP runtimes."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return None
+    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+        return path
+    return None
+
+
+HIP_RUNTIME = _preload_torch_hip_runtime()
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+def loaded_hip_runtimes():
+    """Paths of every libamdhip64 mapped into this process (should be one)."""
+    out = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    out.add(line.split()[-1])
+    except OSError:
+        pass
+    return sorted(out)
+
+OK, EINVAL, ENOMEM, EDEVICE, EBOUND, EOVERFLOW, ESINGULAR, ERETRY, ENOTSUP = range(9)
+PATH_AUTO, PATH_FP64, PATH_INT8 = 0, 1, 2
+_PATHS = {"auto": PATH_AUTO, "fp64": PATH_FP64, "int8": PATH_INT8}
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int
+
+
+class RnsGemmDesc(ctypes.Structure):
+    _fields_ = [("m", _I64), ("n", _I64), ("k", _I64),
+                ("A", _P), ("lda", _I64), ("a_plane_stride", _I64),
+                ("B", _P), ("ldb", _I64), ("b_plane_stride", _I64),
+                ("C", _P), ("ldc", _I64), ("c_plane_stride", _I64),
+                ("prime_begin", ctypes.c_int32), ("L", ctypes.c_int32)]
+
+
+class RnsSmithStats(ctypes.Structure):
+    _fields_ = [("t_lif", ctypes.c_double), ("t_im", ctypes.c_double),
+                ("t_uc", ctypes.c_double), ("t_total", ctypes.c_double),
+                ("restarts", _I32), ("lift_steps", _I32), ("products", _I64),
+                ("residue_ops", ctypes.c_double), ("cert_primes", _I32),
+                ("columns", _I32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_lib_strerror = _sig("rns_strerror", ctypes.c_char_p, [_I32])
+_lib_primes_below = _sig("rns_primes_below", _I32, [ctypes.c_uint64, _I32, _P])
+_lib_ctx_create = _sig("rns_ctx_create", _I32, [ctypes.POINTER(_P), _I32, _P, _I32, ctypes.c_uint64])
+_lib_ctx_destroy = _sig("rns_ctx_destroy", None, [_P])
+_lib_ctx_num_primes = _sig("rns_ctx_num_primes", _I32, [_P])
+_lib_ctx_primes = _sig("rns_ctx_primes", _I32, [_P, _P])
+_lib_ctx_reserve = _sig("rns_ctx_reserve", _I32, [_P, ctypes.c_size_t])
+_lib_workspace_bytes = _sig("rns_workspace_bytes", _I32,
+                            [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32, ctypes.POINTER(ctypes.c_size_t)])
+_lib_primes_for_bound = _sig("rns_primes_for_bound", _I32, [_P, _P, _I32, ctypes.POINTER(_I32)])
+_lib_reduce = _sig("rns_reduce", _I32, [_P, _P, _I64, _I64, _I64, _I32, _I32, _P, _I64, _I64, _P])
+_lib_modmatmul = _sig("modmatmul_batched", _I32, [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32, _P])
+_lib_crt = _sig("crt_reconstruct", _I32, [_P, _P, _I64, _I64, _I64, _I64, _I32, _I32, _P, _I32,
+                                          _P, _I32, _I64, _P, _P])
+_lib_status = _sig("rns_ctx_status", _I32, [_P, _P])
+_lib_force = _sig("rns_ctx_force_cert_failures", _I32, [_P, _I32])
+_lib_smith = _sig("smith_form", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_P)])
+_lib_smith_get = _sig("rns_smith_get", _I32, [_P, _I64, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64)),
+                                              ctypes.POINTER(_I32)])
+_lib_smith_size = _sig("rns_smith_size", _I64, [_P])
+_lib_smith_stats = _sig("rns_smith_stats_get", _I32, [_P, ctypes.POINTER(RnsSmithStats)])
+_lib_smith_free = _sig("rns_smith_free", None, [_P])
+
+EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destroy",
+           "rns_ctx_num_primes", "rns_ctx_primes", "rns_ctx_reserve", "rns_workspace_bytes",
+           "rns_primes_for_bound", "rns_reduce", "modmatmul_batched", "crt_reconstruct",
+           "rns_ctx_status", "smith_form", "rns_smith_get", "rns_smith_size",
+           "rns_smith_stats_get", "rns_smith_free", "rns_ctx_force_cert_failures"]
+
+
+class RnsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, rns_strerror(status), status))
+
+
+def rns_strerror(status: int) -> str:
+    return _lib_strerror(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise RnsError(status, what)
+
+
+def rns_primes_below(bound: int, count: int) -> List[int]:
+    out = (ctypes.c_uint32 * count)()
+    _check(_lib_primes_below(bound, count, ctypes.cast(out, _P)), "rns_primes_below")
+    return list(out)
+
+
+def _words(x: int) -> List[int]:
+    x = int(x)
+    assert x >= 0
+    w = []
+    while True:
+        w.append(x & 0xFFFFFFFFFFFFFFFF)
+        x >>= 64
+        if not x:
+            return w
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t) -> int:
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda, "device tensor expected"
+    return t.data_ptr()
+
+
+class Context:
+    """An RNS basis on one GPU (rns_ctx)."""
+
+    def __init__(self, device: int = 0, primes: Optional[Sequence[int]] = None, L: int = 24):
+        h = _P()
+        if primes is not None:
+            arr = (ctypes.c_uint32 * len(primes))(*[int(p) for p in primes])
+            _check(_lib_ctx_create(ctypes.byref(h), device, ctypes.cast(arr, _P), len(primes), 0),
+                   "rns_ctx_create")
+        else:
+            _check(_lib_ctx_create(ctypes.byref(h), device, None, L, 0), "rns_ctx_create")
+        self.handle = h
+        self.device = device
+        n = _lib_ctx_num_primes(h)
+        out = (ctypes.c_uint32 * n)()
+        _check(_lib_ctx_primes(h, ctypes.cast(out, _P)), "rns_ctx_primes")
+        self.primes = list(out)
+
+    def close(self):
+        if self.handle:
+            _lib_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def L(self) -> int:
+        return len(self.primes)
+
+    def reserve(self, nbytes: int):
+        _check(_lib_ctx_reserve(self.handle, nbytes), "rns_ctx_reserve")
+
+    def primes_for_bound(self, bound: int) -> int:
+        w = _words(bound)
+        arr = (ctypes.c_uint64 * len(w))(*w)
+        out = _I32()
+        _check(_lib_primes_for_bound(self.handle, ctypes.cast(arr, _P), len(w), ctypes.byref(out)),
+               "rns_primes_for_bound")
+        return out.value
+
+    def status(self, stream=None) -> int:
+        return _lib_status(self.handle, _stream(stream))
+
+    def force_cert_failures(self, count: int):
+        _check(_lib_force(self.handle, count), "rns_ctx_force_cert_failures")
+
+
+def rns_reduce(ctx: Context, x, prime_begin: int = 0, L: Optional[int] = None, out=None, stream=None):
+    """x: int64 device tensor (rows, cols), row stride >= cols, unit column
+    stride.  Returns int32 residue planes [L, rows, cols]."""
+    import torch
+    L = ctx.L - prime_begin if L is None else L
+    assert x.dtype == torch.int64 and x.dim() == 2 and x.stride(1) == 1
+    rows, cols = x.shape
+    if out is None:
+        out = torch.empty((L, rows, cols), dtype=torch.int32, device=x.device)
+    assert out.dtype == torch.int32 and out.stride(2) == 1
+    _check(_lib_reduce(ctx.handle, _dev_ptr(x), rows, cols, x.stride(0), prime_begin, L,
+                       _dev_ptr(out), out.stride(1), out.stride(0), _stream(stream)), "rns_reduce")
+    return out
+
+
+@dataclass
+class GemmProblem:
+    """C[j] = A[j] @ B[j] mod p_{prime_begin+j}; A [L, m, k], B [L, k, n],
+    C [L, m, n], int32 device tensors with unit column stride."""
+    A: object
+    B: object
+    C: object
+    prime_begin: int = 0
+
+    def desc(self) -> RnsGemmDesc:
+        L, m, k = self.A.shape
+        L2, k2, n = self.B.shape
+        assert L == L2 and k == k2 and tuple(self.C.shape) == (L, m, n)
+        for t in (self.A, self.B, self.C):
+            assert t.stride(2) == 1
+        d = RnsGemmDesc()
+        d.m, d.n, d.k = m, n, k
+        d.A, d.lda, d.a_plane_stride = _dev_ptr(self.A), self.A.stride(1), self.A.stride(0)
+        d.B, d.ldb, d.b_plane_stride = _dev_ptr(self.B), self.B.stride(1), self.B.stride(0)
+        d.C, d.ldc, d.c_plane_stride = _dev_ptr(self.C), self.C.stride(1), self.C.stride(0)
+        d.prime_begin, d.L = self.prime_begin, L
+        return d
+
+
+def _descs(problems: Sequence[GemmProblem]):
+    arr = (RnsGemmDesc * max(1, len(problems)))()
+    for i, p in enumerate(problems):
+        arr[i] = p.desc()
+    return arr
+
+
+def modmatmul_batched(ctx: Context, problems: Sequence[GemmProblem], path="auto", stream=None):
+    path = _PATHS[path] if isinstance(path, str) else int(path)
+    arr = _descs(problems)
+    _check(_lib_modmatmul(ctx.handle, arr, len(problems), path, _stream(stream)), "modmatmul_batched")
+
+
+def workspace_bytes(ctx: Context, problems: Sequence[GemmProblem], path="auto") -> int:
+    path = _PATHS[path] if isinstance(path, str) else int(path)
+    arr = _descs(problems)
+    out = ctypes.c_size_t()
+    _check(_lib_workspace_bytes(ctx.handle, arr, len(problems), path, ctypes.byref(out)),
+           "rns_workspace_bytes")
+    return out.value
+
+
+def crt_reconstruct(ctx: Context, res, prime_begin: int = 0, L: Optional[int] = None,
+                    bound: Optional[int] = None, W: int = 1, out=None, status=None, stream=None):
+    """res: int32 planes [L, rows, cols].  Returns int64 [rows, cols, W] words
+    (two's complement, little-endian); for W == 1 a [rows, cols] tensor."""
+    import torch
+    L = res.shape[0] if L is None else L
+    _, rows, cols = res.shape
+    assert res.dtype == torch.int32 and res.stride(2) == 1
+    if out is None:
+        out = torch.empty((rows, cols, W), dtype=torch.int64, device=res.device)
+    assert out.dtype == torch.int64 and out.is_contiguous()
+    if bound is not None:
+        w = _words(bound)
+        barr = (ctypes.c_uint64 * len(w))(*w)
+        bptr, bw = ctypes.cast(barr, _P), len(w)
+    else:
+        bptr, bw = None, 0
+    sptr = _dev_ptr(status) if status is not None else None
+    _check(_lib_crt(ctx.handle, _dev_ptr(res), rows, cols, res.stride(1), res.stride(0),
+                    prime_begin, L, bptr, bw, _dev_ptr(out), W, cols, sptr, _stream(stream)),
+           "crt_reconstruct")
+    return out[:, :, 0] if W == 1 else out
+
+
+def words_to_ints(words: np.ndarray) -> np.ndarray:
+    """int64 [..., W] two's-complement words -> object array of Python ints."""
+    w = np.asarray(words).astype(np.uint64)
+    W = w.shape[-1]
+    flat = w.reshape(-1, W)
+    out = np.empty(flat.shape[0], dtype=object)
+    for e in range(flat.shape[0]):
+        u = 0
+        for k in range(W):
+            u |= int(flat[e, k]) << (64 * k)
+        if u >> (64 * W - 1):
+            u -= 1 << (64 * W)
+        out[e] = u
+    return out.reshape(w.shape[:-1])
+
+
+@dataclass
+class SmithResult:
+    s: List[int]
+    stats: dict
+
+
+def smith_form(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    h = _P()
+    _check(_lib_smith(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "smith_form")
+    try:
+        s = []
+        words = ctypes.POINTER(ctypes.c_uint64)()
+        nw = _I32()
+        for i in range(_lib_smith_size(h)):
+            _check(_lib_smith_get(h, i, ctypes.byref(words), ctypes.byref(nw)), "rns_smith_get")
+            v = 0
+            for k in range(nw.value):
+                v |= int(words[k]) << (64 * k)
+            s.append(v)
+        st = RnsSmithStats()
+        _check(_lib_smith_stats(h, ctypes.byref(st)), "rns_smith_stats_get")
+        stats = {f: getattr(st, f) for f, _ in RnsSmithStats._fields_}
+    finally:
+        _lib_smith_free(h)
+    return SmithResult(s, stats)

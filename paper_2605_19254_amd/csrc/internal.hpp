@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP translation units of librns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rns.h"
+
+namespace rns {
+
+constexpr uint32_t kPrimeLimit = 1u << 26;   // every basis prime is below 2^26
+constexpr int kMaxPrimes = 4096;
+constexpr int kCrtMaxL = 64;                 // primes per CRT call
+constexpr int kCrtMaxW = 32;                 // output words per CRT entry
+constexpr int64_t kInt8MaxK = 43690;         // int32 digit sums stay exact below
+
+// Per-prime constants, read by every kernel (Section 3.1: precomputed once
+// per basis).  All doubles hold exact integers except pinv.
+struct PrimeConst {
+    double pf;        // p
+    double pinv;      // 1/p rounded to nearest
+    double c21;       // 2^21 mod p
+    double c42;       // 2^42 mod p
+    double w[7];      // 2^(8s) mod p in the balanced range (-p/2, p/2), s = 0..6
+    uint32_t p;
+    uint32_t half;    // (p-1)/2: residues above it are negative in balanced form
+};
+
+// Garner band: for a prime index j and a distance d in [1, kCrtMaxL),
+// garner[j*kCrtMaxL + d] = p_{j-d}^{-1} mod p_j (as a double), 0 where j < d.
+
+// Constants of the Lagrange form of the CRT for one primes range and output
+// width, built on first use and kept in the context.
+struct LagrangeTable {
+    double *d_c = nullptr;          // L: (M/p_j)^{-1} mod p_j
+    uint64_t *d_mj = nullptr;       // L x W: (M/p_j) mod 2^(64W)
+    uint64_t *d_m = nullptr;        // W: M mod 2^(64W)
+    std::vector<uint32_t> M;        // M as 32-bit limbs (host)
+};
+
+}  // namespace rns
+
+struct rns_ctx {
+    int device = 0;
+    int L = 0;
+    std::vector<uint32_t> primes;
+    rns::PrimeConst *d_prime = nullptr;
+    double *d_garner = nullptr;
+    uint32_t *d_mr_half = nullptr;     // mixed-radix digits of (M_r-1)/2 per range, built lazily
+    int32_t *d_status = nullptr;
+    void *d_work = nullptr;
+    size_t work_bytes = 0;
+    void *d_desc = nullptr;            // device copy of the problem table
+    size_t desc_bytes = 0;
+    void *h_desc = nullptr;            // pinned host staging of the problem table
+    std::map<std::tuple<int, int, int>, rns::LagrangeTable> lagrange;
+    std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
+    int force_cert_failures = 0;
+    std::mutex mu;
+};
+
+namespace rns {
+
+// HIP error handling: every HIP call in the library goes through this.
+#define RNS_HIP(call)                                                    \
+    do {                                                                 \
+        hipError_t e_ = (call);                                          \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? RNS_ENOMEM : RNS_EDEVICE; \
+    } while (0)
+
+int ensure_workspace(rns_ctx *ctx, size_t bytes);
+int ensure_desc(rns_ctx *ctx, size_t bytes);
+
+// Small host-side multiword unsigned integers (32-bit limbs, little-endian).
+using Limbs = std::vector<uint32_t>;
+void limbs_mul_small(Limbs &a, uint32_t m);
+uint32_t limbs_divmod_small(Limbs &a, uint32_t d);     // a /= d, returns a mod d
+uint32_t limbs_mod_small(const Limbs &a, uint32_t d);
+int limbs_cmp(const Limbs &a, const Limbs &b);
+void limbs_trim(Limbs &a);
+uint64_t mulmod_u64(uint64_t a, uint64_t b, uint64_t m);
+uint64_t powmod_u64(uint64_t a, uint64_t e, uint64_t m);
+uint64_t invmod_u64(uint64_t a, uint64_t m);            // m prime
+
+int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **out);
+int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out);
+
+}  // namespace rns

@@ -1,0 +1,297 @@
+"""GPU parity of the RNS primitives against the CPU oracle (bit-exact).
+
+Every case prints its name before touching the GPU.  Inputs come from synth
+(seeded), expected values from oracle/ only.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import native, primes as op, rns as orns
+import synth
+
+pytestmark = pytest.mark.gpu
+
+P26 = 1 << 26
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def rg():
+    import paper_2605_19254_amd as rg
+    return rg
+
+
+@pytest.fixture(scope="module")
+def ctx(rg, torch_dev):
+    c = rg.Context(device=0, L=26)
+    yield c
+    c.close()
+
+
+PRIMES = op.largest_primes_below(P26, 26)
+
+
+def _res(rng, ps, rows, cols, edge=False):
+    out = np.empty((len(ps), rows, cols), dtype=np.int64)
+    for j, p in enumerate(ps):
+        out[j] = rng.integers(0, p, size=(rows, cols))
+        if edge:
+            special = np.array([0, 1, p - 1, (p - 1) // 2, (p + 1) // 2, 2, p - 2], dtype=np.int64)
+            mask = rng.random((rows, cols)) < 0.3
+            out[j][mask] = rng.choice(special, size=int(mask.sum()))
+    return out.astype(np.int32)
+
+
+# ------------------------------------------------------------------ reduce --
+
+@pytest.mark.parametrize("rows,cols,begin,L", [(1, 1, 0, 1), (3, 300, 0, 24), (257, 129, 2, 24),
+                                               (64, 64, 0, 26)])
+def test_reduce_matches_oracle(ctx, rg, torch_dev, rows, cols, begin, L):
+    torch, dev = torch_dev
+    _say("reduce", rows, cols, begin, L)
+    rng = np.random.default_rng(rows * 1000 + cols)
+    x = rng.integers(-(1 << 63), (1 << 63) - 1, size=(rows, cols), dtype=np.int64)
+    flat = x.reshape(-1)
+    ext = [0, 1, -1, -(1 << 63), (1 << 63) - 1, PRIMES[0], -PRIMES[0], 1 << 42, -(1 << 42), (1 << 21) - 1]
+    flat[:min(len(ext), flat.size)] = ext[:flat.size]
+    got = rg.rns_reduce(ctx, torch.from_numpy(x).to(dev), prime_begin=begin, L=L).cpu().numpy()
+    want = orns.reduce(x, PRIMES[begin:begin + L]).astype(np.int32)
+    assert np.array_equal(got, want)
+
+
+def test_reduce_strided_and_empty(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("reduce strided")
+    rng = np.random.default_rng(7)
+    big = rng.integers(-(1 << 40), 1 << 40, size=(50, 80), dtype=np.int64)
+    xt = torch.from_numpy(big).to(dev)[5:45, 10:70]     # row stride 80
+    out = torch.full((4, 40, 64), -1, dtype=torch.int32, device=dev)[:, :, :60]
+    rg.rns_reduce(ctx, xt, prime_begin=0, L=4, out=out)
+    want = orns.reduce(big[5:45, 10:70], PRIMES[:4]).astype(np.int32)
+    assert np.array_equal(out.cpu().numpy(), want)
+    e = torch.empty((0, 5), dtype=torch.int64, device=dev)
+    assert rg.rns_reduce(ctx, e, L=3).shape == (3, 0, 5)
+
+
+# --------------------------------------------------------------- modmatmul --
+
+SHAPES = [(1, 1, 1), (1, 5, 1), (16, 16, 64), (17, 33, 70), (64, 128, 64), (65, 129, 65),
+          (100, 200, 300), (130, 257, 129), (7, 300, 1000), (300, 7, 2100)]
+
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+@pytest.mark.parametrize("m,n,k", SHAPES)
+def test_modmatmul_matches_oracle(ctx, rg, torch_dev, path, m, n, k):
+    torch, dev = torch_dev
+    _say("modmatmul", path, m, n, k)
+    rng = np.random.default_rng(m * 7 + n * 13 + k)
+    begin, L = (0, 3) if m * n * k > 1e6 else (20, 6)
+    ps = PRIMES[begin:begin + L]
+    a = _res(rng, ps, m, k, edge=True)
+    b = _res(rng, ps, k, n, edge=True)
+    c = torch.full((L, m, n), -1, dtype=torch.int32, device=dev)
+    rg.modmatmul_batched(ctx, [rg.GemmProblem(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev),
+                                              c, begin)], path=path)
+    got = c.cpu().numpy()
+    for j, p in enumerate(ps):
+        want = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int32)
+        assert np.array_equal(got[j], want), (path, j)
+
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_modmatmul_worst_case_values(ctx, rg, torch_dev, path):
+    """All residues at the balanced extremes: every digit product and every
+    8-term block sits at its bound."""
+    torch, dev = torch_dev
+    _say("modmatmul worst", path)
+    ps = PRIMES[:2] + PRIMES[23:24]
+    L, m, n, k = 3, 64, 128, 4096 + 64
+    a = np.empty((L, m, k), dtype=np.int32)
+    b = np.empty((L, k, n), dtype=np.int32)
+    rng = np.random.default_rng(3)
+    for j, p in enumerate(ps):
+        h = (p - 1) // 2
+        a[j] = rng.choice(np.array([h, h + 1, p - 1, 1], dtype=np.int64), size=(m, k))
+        b[j] = rng.choice(np.array([h, h + 1], dtype=np.int64), size=(k, n))
+    c = torch.empty((L, m, n), dtype=torch.int32, device=dev)
+    pb = [0, 1, 23]
+    for j in range(L):
+        rg.modmatmul_batched(ctx, [rg.GemmProblem(torch.from_numpy(a[j:j + 1]).to(dev),
+                                                  torch.from_numpy(b[j:j + 1]).to(dev),
+                                                  c[j:j + 1], pb[j])], path=path)
+    got = c.cpu().numpy()
+    for j, p in enumerate(ps):
+        want = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int32)
+        assert np.array_equal(got[j], want)
+
+
+def test_modmatmul_batch_equals_single_and_paths_agree(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("modmatmul batch")
+    rng = np.random.default_rng(11)
+    probs, cs_batch = [], []
+    specs = [(33, 17, 65, 0, 2), (128, 64, 64, 3, 1), (1, 200, 7, 5, 3), (90, 90, 90, 24, 2)]
+    tensors = []
+    for (m, n, k, begin, L) in specs:
+        ps = PRIMES[begin:begin + L]
+        a = torch.from_numpy(_res(rng, ps, m, k)).to(dev)
+        b = torch.from_numpy(_res(rng, ps, k, n)).to(dev)
+        tensors.append((a, b, begin, L, m, n))
+    for path in ("int8", "fp64"):
+        batch = [torch.empty((L, m, n), dtype=torch.int32, device=dev) for (_, _, _, L, m, n) in tensors]
+        rg.modmatmul_batched(ctx, [rg.GemmProblem(a, b, c, bg) for (a, b, bg, _, _, _), c in zip(tensors, batch)],
+                             path=path)
+        for (a, b, bg, L, m, n), cb in zip(tensors, batch):
+            single = torch.empty((L, m, n), dtype=torch.int32, device=dev)
+            rg.modmatmul_batched(ctx, [rg.GemmProblem(a, b, single, bg)], path=path)
+            assert torch.equal(single, cb)
+        cs_batch.append([c.cpu() for c in batch])
+    for x, y in zip(cs_batch[0], cs_batch[1]):
+        assert torch.equal(x, y)
+    rg.modmatmul_batched(ctx, [], path="int8")   # count 0 is a no-op
+
+
+def test_modmatmul_k_zero_and_bound(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("modmatmul k=0 / bound")
+    a = torch.empty((2, 5, 0), dtype=torch.int32, device=dev)
+    b = torch.empty((2, 0, 7), dtype=torch.int32, device=dev)
+    c = torch.full((2, 5, 7), 9, dtype=torch.int32, device=dev)
+    rg.modmatmul_batched(ctx, [rg.GemmProblem(a, b, c)], path="int8")
+    assert int(c.abs().sum()) == 0
+    big_a = torch.zeros((1, 1, 43691), dtype=torch.int32, device=dev)
+    big_b = torch.zeros((1, 43691, 1), dtype=torch.int32, device=dev)
+    c1 = torch.empty((1, 1, 1), dtype=torch.int32, device=dev)
+    with pytest.raises(rg.RnsError) as e:
+        rg.modmatmul_batched(ctx, [rg.GemmProblem(big_a, big_b, c1)], path="int8")
+    assert e.value.status == 4
+    rg.modmatmul_batched(ctx, [rg.GemmProblem(big_a, big_b, c1)], path="fp64")
+    assert int(c1.item()) == 0
+
+
+# --------------------------------------------------------------------- CRT --
+
+@pytest.mark.parametrize("L,W", [(1, 1), (2, 1), (3, 2), (24, 10), (24, 3), (26, 11), (5, 32)])
+def test_crt_garner_matches_oracle(ctx, rg, torch_dev, L, W):
+    torch, dev = torch_dev
+    _say("crt garner", L, W)
+    ps = PRIMES[:L]
+    rng = np.random.default_rng(L * 100 + W)
+    rows, cols = 9, 150
+    res = _res(rng, ps, rows, cols, edge=True)
+    basis = orns.CRTBasis(ps)
+    h = (basis.M - 1) // 2
+    # plant the extremes and values near the sign boundary
+    special = [0, 1, -1, h, -h, h - 1, -h + 1, (1 << 63) - 1, -(1 << 63), 1 << 63, -(1 << 63) - 1]
+    for e, x in enumerate(special):
+        if abs(x) <= h:
+            res[:, 0, e] = np.array(orns.reduce_int(x, ps), dtype=np.int64).astype(np.int32)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = rg.crt_reconstruct(ctx, torch.from_numpy(res).to(dev), L=L, W=W, status=status)
+    got = out.cpu().numpy()
+    got = got.reshape(rows, cols, W)
+    want_overflow = False
+    for i in range(rows):
+        for c in range(cols):
+            x = basis.reconstruct(res[:, i, c].astype(np.int64))
+            try:
+                words = orns.to_words(x, W)
+            except orns.Overflow:
+                want_overflow = True
+                words = [(x % (1 << (64 * W))) >> (64 * w) & 0xFFFFFFFFFFFFFFFF for w in range(W)]
+            assert [int(v) & 0xFFFFFFFFFFFFFFFF for v in got[i, c]] == words, (i, c, x)
+    assert bool(status.item()) == want_overflow
+
+
+def test_crt_lagrange_with_bound(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("crt lagrange")
+    rng = np.random.default_rng(21)
+    for L, W, bits in [(24, 1, 52), (3, 1, 62), (24, 2, 100), (10, 4, 200)]:
+        ps = PRIMES[:L]
+        vals = [int(v) for v in rng.integers(-(1 << 62), 1 << 62, size=200)]
+        vals = [(v << (bits - 62)) if bits > 62 else (v >> (62 - bits)) for v in vals]
+        vals[:4] = [0, -1, (1 << bits) - 1, -((1 << bits) - 1)]
+        res = np.ascontiguousarray(np.array([orns.reduce_int(v, ps) for v in vals], dtype=np.int64).T.reshape(L, 1, -1))
+        out = rg.crt_reconstruct(ctx, torch.from_numpy(res.astype(np.int32)).to(dev), L=L, W=W,
+                                 bound=(1 << bits) - 1)
+        got = out.cpu().numpy().reshape(1, -1, W)
+        for e, v in enumerate(vals):
+            assert [int(x) & 0xFFFFFFFFFFFFFFFF for x in got[0, e]] == orns.to_words(v, W), (L, W, e)
+
+
+def test_crt_overflow_reported_via_context(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("crt overflow ctx")
+    ps = PRIMES[:4]
+    x = 1 << 70
+    res = np.array(orns.reduce_int(x, ps), dtype=np.int64).reshape(4, 1, 1).astype(np.int32)
+    assert ctx.status() == 0
+    rg.crt_reconstruct(ctx, torch.from_numpy(res).to(dev), L=4, W=1)
+    assert ctx.status() == 5
+    assert ctx.status() == 0
+
+
+# --------------------------------------------------------- whole products --
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_exact_product_small(ctx, rg, torch_dev, path):
+    torch, dev = torch_dev
+    _say("exact product small", path)
+    a, b = synth.square_pair(n=300, bound=1 << 20, seed_a=0, seed_b=1)
+    a, b = a[:211, :300].copy(), b[:300, :173].copy()
+    ra = rg.rns_reduce(ctx, torch.from_numpy(a).to(dev), L=24)
+    rb = rg.rns_reduce(ctx, torch.from_numpy(b).to(dev), L=24)
+    rc = torch.empty((24, 211, 173), dtype=torch.int32, device=dev)
+    rg.modmatmul_batched(ctx, [rg.GemmProblem(ra, rb, rc)], path=path)
+    got = rg.crt_reconstruct(ctx, rc, L=24, W=1, bound=300 << 40).cpu().numpy()
+    assert np.array_equal(got, orns.exact_matmul(a, b))
+    got2 = rg.crt_reconstruct(ctx, rc, L=24, W=1).cpu().numpy()     # exact form, no bound
+    assert np.array_equal(got2, got)
+    assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
+    """The full n = 4096, 24-prime product in the benchmark's configuration;
+    sampled outputs against the oracle, plus every residue of sampled rows."""
+    torch, dev = torch_dev
+    _say("exact product n=4096", path)
+    n, L = 4096, 24
+    a, b = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    ra = rg.rns_reduce(ctx, ta, L=L)
+    rb = rg.rns_reduce(ctx, tb, L=L)
+    rc = torch.empty((L, n, n), dtype=torch.int32, device=dev)
+    rg.modmatmul_batched(ctx, [rg.GemmProblem(ra, rb, rc)], path=path)
+    out = rg.crt_reconstruct(ctx, rc, L=L, W=1, bound=n << 40)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    rows = rng.integers(0, n, size=3)
+    got = out[torch.from_numpy(rows).to(dev)].cpu().numpy()
+    want = native.exact_matmul(a[rows], b)
+    assert np.array_equal(got, want)
+    # residues of the sampled rows, every prime
+    rcs = rc[:, torch.from_numpy(rows).to(dev), :].cpu().numpy()
+    for j, p in enumerate(PRIMES[:L]):
+        assert np.array_equal(rcs[j], np.mod(want, p).astype(np.int32))
+    # sampled single entries anywhere
+    idx = rng.integers(0, n, size=(64, 2))
+    o = out.cpu().numpy()
+    for i, c in idx:
+        assert int(o[i, c]) == orns.exact_entry(a[i], b[:, c])
+    assert ctx.status() == 0
