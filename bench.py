@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact multi-modular integer matrix product on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input that is
+already resident in HBM:
+    rns_reduce(A), rns_reduce(B)            int64 -> 24 residue planes each
+    modmatmul_batched(..., path)            24 exact products mod p
+    crt_reconstruct(..., bound)             24 planes -> int64 result
+Workload: A, B 4096 x 4096, entries uniform in [-2^20, 2^20] (seeds 0 and 1),
+the 24 largest primes below 2^26.  The headline runs the INT8-limb path; the
+FP64-MFMA path is timed beside it on the same inputs.
+
+Prints one JSON line.  `value` is residue int-ops per second of the whole step,
+2*m*n*k*L per step.  The roofline entry is for the dominant kernel (the GEMM):
+its average launch duration is measured with HIP events recorded on the stream
+the kernel runs on, and its achieved rate counts the MFMA operations the path
+executes (16 digit-pair products per residue product on the INT8 path).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "exact modmatmul int-ops/s (INT8-limb vs FP64 path); SNF solves/s, p50/p99"
+PEAK_INT8_TOPS = 5000.0      # MI355X dense INT8 MFMA, TOP/s
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix, TFLOP/s
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--primes", type=int, default=24)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--cpu-rows", type=int, default=16,
+                    help="rows of C the oracle computes for the CPU baseline (0 = skip)")
+    ap.add_argument("--out", default="")
+    return ap.parse_args()
+
+
+def cpu_baseline(a, b, primes, rows):
+    """The oracle as it stands, on the first `rows` rows of C: reduce, the
+    per-prime schoolbook products (plain C loops, OpenMP), CRT in Python ints."""
+    import numpy as np
+    from oracle import native, rns as orns
+    t0 = time.perf_counter()
+    ra = orns.reduce(a[:rows], primes)
+    rb = orns.reduce(b, primes)
+    rc = orns.modmatmul_planes(ra, rb, primes)
+    c = orns.crt_planes(rc, primes)
+    t = time.perf_counter() - t0
+    n = a.shape[1]
+    ops = 2.0 * rows * n * b.shape[1] * len(primes)
+    # spot-check the sample against the exact product
+    want = native.exact_matmul(a[:2], b)
+    assert all(int(c[i, j]) == int(want[i, j]) for i in range(2) for j in range(0, b.shape[1], 97))
+    return {"value": ops / t, "unit": "int-ops/s", "cores": native.num_threads(), "kind": "oracle",
+            "sample": "rows 0..%d of C (%d x %d x %d, %d primes): reduce, per-prime schoolbook "
+                      "modmatmul, CRT; %.1f s" % (rows - 1, rows, n, b.shape[1], len(primes), t),
+            "seconds": t}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU "
+              "sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2605_19254_amd as rg
+    import synth
+
+    n, L = args.n, args.primes
+    dev = torch.device("cuda:0")
+    a_np, b_np = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
+    A = torch.from_numpy(a_np).to(dev)
+    B = torch.from_numpy(b_np).to(dev)
+    ctx = rg.Context(device=0, L=L)
+    ra = torch.empty((L, n, n), dtype=torch.int32, device=dev)
+    rb = torch.empty((L, n, n), dtype=torch.int32, device=dev)
+    rc = torch.empty((L, n, n), dtype=torch.int32, device=dev)
+    out = torch.empty((n, n, 1), dtype=torch.int64, device=dev)
+    bound = n * (1 << 40)          # |C_ij| <= k * 2^20 * 2^20
+    prob = [rg.GemmProblem(ra, rb, rc)]
+
+    def step(path):
+        rg.rns_reduce(ctx, A, L=L, out=ra)
+        rg.rns_reduce(ctx, B, L=L, out=rb)
+        rg.modmatmul_batched(ctx, prob, path=path)
+        rg.crt_reconstruct(ctx, rc, L=L, W=1, bound=bound, out=out)
+
+    def timed(path, steps, warmup):
+        for _ in range(warmup):
+            step(path)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read("")          # drop warm-up records
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(path)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.profile(False)
+        kern = {}
+        for name in ("k_reduce", "k_prep", "k_gemm", "k_crt"):
+            ms, cnt = ctx.profile_read(name)
+            if cnt:
+                kern[name] = {"avg_ms": ms / cnt, "launches": cnt}
+        return t, kern
+
+    res_ops = 2.0 * n * n * n * L
+    t8, k8 = timed("int8", args.steps, args.warmup)
+    # correctness of what was timed: sampled entries against the oracle's exact product
+    from oracle import native
+    rows = np.array([0, n // 3, n - 1])
+    got = out[torch.from_numpy(rows).to(dev), :, 0].cpu().numpy()
+    want = native.exact_matmul(a_np[rows], b_np)
+    if not np.array_equal(got, want):
+        print("bench.py: INT8 path result differs from the oracle", file=sys.stderr)
+        sys.exit(1)
+    assert ctx.status() == 0
+    ms8 = 1000.0 * t8 / args.steps
+    gemm_ms = k8["k_gemm"]["avg_ms"]
+    mfma_ops = 16.0 * res_ops                       # executed INT8 MFMA ops per launch
+    achieved = mfma_ops / (gemm_ms * 1e-3) / 1e12    # TOP/s
+
+    fp64 = None
+    if args.fp64_steps > 0:
+        t64, k64 = timed("fp64", args.fp64_steps, 1)
+        got = out[torch.from_numpy(rows).to(dev), :, 0].cpu().numpy()
+        if not np.array_equal(got, want):
+            print("bench.py: FP64 path result differs from the oracle", file=sys.stderr)
+            sys.exit(1)
+        ms64 = 1000.0 * t64 / args.fp64_steps
+        g64 = k64["k_gemm"]["avg_ms"]
+        fp64 = {"value": res_ops / (ms64 * 1e-3), "ms_per_step": ms64, "steps": args.fp64_steps,
+                "kernels": k64, "gemm_tflops": res_ops / (g64 * 1e-3) / 1e12,
+                "gemm_frac_of_fp64_peak": res_ops / (g64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+
+    red_bytes = 2.0 * n * n * (8 + 4 * L)
+    crt_bytes = n * n * (4.0 * L + 8)
+    rec = {
+        "metric": METRIC,
+        "value": res_ops / (ms8 * 1e-3),
+        "unit": "int-ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms8,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "exact multi-modular GEMM, A and B %dx%d int64 uniform in "
+                               "[-2^20, 2^20] (seeds 0, 1), %d primes below 2^26, INT8-limb path, "
+                               "reduce + modmatmul + CRT per step" % (n, n, L),
+                   "m": n, "n": n, "k": n, "primes": L, "path": "int8"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
+                     "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
+                     "kernel": "k_gemm_i8", "avg_launch_ms": gemm_ms,
+                     "ops_per_launch": mfma_ops},
+        "kernels": k8,
+        "hbm_passes": {
+            "reduce_GBps": red_bytes / 2 / (k8["k_reduce"]["avg_ms"] * 1e-3) / 1e9,
+            "crt_GBps": crt_bytes / (k8["k_crt"]["avg_ms"] * 1e-3) / 1e9,
+            "peak_GBps": PEAK_HBM_GBS},
+        "fp64_path": fp64,
+        "int8_vs_fp64_speedup": (fp64["ms_per_step"] / ms8) if fp64 else None,
+    }
+    if args.cpu_rows > 0:
+        primes = ctx.primes[:L]
+        rec["cpu_baseline"] = cpu_baseline(a_np, b_np, primes, args.cpu_rows)
+    else:
+        rec["cpu_baseline"] = None
+    line = json.dumps(rec)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -237,6 +237,17 @@ int64_t rns_smith_size(const rns_smith_result *r);
 int rns_smith_stats_get(const rns_smith_result *r, rns_smith_stats *st);
 void rns_smith_free(rns_smith_result *r);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing (tracing).  When enabled, every kernel the library launches
+ * is bracketed by two HIP events recorded on the caller's stream.
+ * rns_ctx_profile_read synchronises those events and returns, for kernels
+ * whose name contains `name` (NULL or "" = all), the summed duration in
+ * milliseconds and the number of launches, then forgets them.
+ * ---------------------------------------------------------------------- */
+int rns_ctx_profile(rns_ctx *ctx, int enable);
+int rns_ctx_profile_read(rns_ctx *ctx, const char *name, double *total_ms,
+                         int64_t *launches);
+
 /* Test hook: make the next `count` certifications of this context fail, to
  * exercise the Las Vegas restart (Section 2.2, Phase 3).  0 disables. */
 int rns_ctx_force_cert_failures(rns_ctx *ctx, int count);

@@ -111,12 +111,16 @@ _lib_smith_get = _sig("rns_smith_get", _I32, [_P, _I64, ctypes.POINTER(ctypes.PO
 _lib_smith_size = _sig("rns_smith_size", _I64, [_P])
 _lib_smith_stats = _sig("rns_smith_stats_get", _I32, [_P, ctypes.POINTER(RnsSmithStats)])
 _lib_smith_free = _sig("rns_smith_free", None, [_P])
+_lib_profile = _sig("rns_ctx_profile", _I32, [_P, _I32])
+_lib_profile_read = _sig("rns_ctx_profile_read", _I32, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                                        ctypes.POINTER(_I64)])
 
 EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destroy",
            "rns_ctx_num_primes", "rns_ctx_primes", "rns_ctx_reserve", "rns_workspace_bytes",
            "rns_primes_for_bound", "rns_reduce", "modmatmul_batched", "crt_reconstruct",
            "rns_ctx_status", "smith_form", "rns_smith_get", "rns_smith_size",
-           "rns_smith_stats_get", "rns_smith_free", "rns_ctx_force_cert_failures"]
+           "rns_smith_stats_get", "rns_smith_free", "rns_ctx_force_cert_failures",
+           "rns_ctx_profile", "rns_ctx_profile_read"]
 
 
 class RnsError(RuntimeError):
@@ -215,6 +219,19 @@ class Context:
 
     def status(self, stream=None) -> int:
         return _lib_status(self.handle, _stream(stream))
+
+    def profile(self, enable: bool = True):
+        """Bracket every library kernel launch with HIP events."""
+        _check(_lib_profile(self.handle, 1 if enable else 0), "rns_ctx_profile")
+
+    def profile_read(self, name: str = ""):
+        """(total ms, launches) of traced kernels whose name contains `name`;
+        the matching records are consumed."""
+        ms = ctypes.c_double()
+        cnt = _I64()
+        _check(_lib_profile_read(self.handle, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+               "rns_ctx_profile_read")
+        return ms.value, cnt.value
 
     def force_cert_failures(self, count: int):
         _check(_lib_force(self.handle, count), "rns_ctx_force_cert_failures")

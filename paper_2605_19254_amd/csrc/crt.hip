@@ -287,6 +287,7 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
         const LagrangeTable *lt = nullptr;
         int st = lagrange_table(ctx, prime_begin, L, W, &lt);
         if (st != RNS_OK) return st;
+        ProfScope ps(ctx, "k_crt_lagrange", s);
 #define RNS_LAG(WT_)                                                                       \
     hipLaunchKernelGGL(k_crt_lagrange<WT_>, dim3(grid), dim3(kBlock), 0, s, res, rows, cols, \
                        ldr, plane_stride, pc, lt->d_c, lt->d_mj, lt->d_m, L, out, W, ldo,   \
@@ -304,6 +305,7 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
         if (st != RNS_OK) return st;
         int32_t *status = d_status ? d_status : ctx->d_status;
         const double *garner = ctx->d_garner + (int64_t)prime_begin * kCrtMaxL;
+        ProfScope ps(ctx, "k_crt_garner", s);
 #define RNS_GAR(WT_)                                                                      \
     hipLaunchKernelGGL(k_crt_garner<WT_>, dim3(grid), dim3(kBlock), 0, s, res, rows, cols, \
                        ldr, plane_stride, pc, garner, half, L, out, W, ldo, status,        \

@@ -359,3 +359,62 @@ extern "C" int rns_ctx_force_cert_failures(rns_ctx *ctx, int count) {
     ctx->force_cert_failures = count;
     return RNS_OK;
 }
+
+// ----------------------------------------------------------------- tracing --
+
+namespace rns {
+
+ProfScope::ProfScope(rns_ctx *c, const char *n, hipStream_t st) : ctx(c), name(n), s(st) {
+    if (!ctx->prof) return;
+    if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
+    if (hipEventRecord(a, s) != hipSuccess) { (void)hipEventDestroy(a); a = nullptr; }
+}
+
+ProfScope::~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        return;
+    }
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
+    ctx->prof_recs.push_back({name, a, b});
+}
+
+}  // namespace rns
+
+extern "C" int rns_ctx_profile(rns_ctx *ctx, int enable) {
+    if (!ctx) return RNS_EINVAL;
+    ctx->prof = enable != 0;
+    return RNS_OK;
+}
+
+extern "C" int rns_ctx_profile_read(rns_ctx *ctx, const char *name, double *total_ms,
+                                    int64_t *launches) {
+    if (!ctx || !total_ms || !launches) return RNS_EINVAL;
+    RNS_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    std::vector<rns_ctx::ProfRec> keep;
+    int st = RNS_OK;
+    for (auto &r : ctx->prof_recs) {
+        const bool match = !name || !*name || std::strstr(r.name, name) != nullptr;
+        if (!match) {
+            keep.push_back(r);
+            continue;
+        }
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            st = RNS_EDEVICE;
+        tot += ms;
+        ++cnt;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    ctx->prof_recs.swap(keep);
+    *total_ms = tot;
+    *launches = cnt;
+    return st;
+}

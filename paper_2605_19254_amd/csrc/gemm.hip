@@ -469,19 +469,25 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
     const GemmProblem *dP = static_cast<const GemmProblem *>(ctx->d_desc);
     const int np = (int)plan.probs.size();
     const int64_t prep_blocks = (plan.total_units + 3) / 4;
+    {
+    ProfScope ps(ctx, int8 ? "k_prep_i8" : "k_prep_f64", s);
     if (int8)
         hipLaunchKernelGGL(k_prep<true>, dim3((unsigned)prep_blocks), dim3(256), 0, s, dP, np,
                            plan.total_units, (const PrimeConst *)ctx->d_prime);
     else
         hipLaunchKernelGGL(k_prep<false>, dim3((unsigned)prep_blocks), dim3(256), 0, s, dP, np,
                            plan.total_units, (const PrimeConst *)ctx->d_prime);
+    }
     RNS_HIP(hipGetLastError());
+    {
+    ProfScope ps(ctx, int8 ? "k_gemm_i8" : "k_gemm_f64", s);
     if (int8)
         hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)plan.total_tiles), dim3(256), 0, s, dP, np,
                            plan.total_tiles, (const PrimeConst *)ctx->d_prime);
     else
         hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)plan.total_tiles), dim3(256), 0, s, dP, np,
                            plan.total_tiles, (const PrimeConst *)ctx->d_prime);
+    }
     RNS_HIP(hipGetLastError());
     return RNS_OK;
 }

@@ -63,6 +63,14 @@ struct rns_ctx {
     std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
     int force_cert_failures = 0;
     std::mutex mu;
+    // tracing: (kernel name, start event, stop event) per launch
+    bool prof = false;
+    struct ProfRec {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    std::vector<ProfRec> prof_recs;
+    std::mutex prof_mu;
 };
 
 namespace rns {
@@ -87,6 +95,16 @@ void limbs_trim(Limbs &a);
 uint64_t mulmod_u64(uint64_t a, uint64_t b, uint64_t m);
 uint64_t powmod_u64(uint64_t a, uint64_t e, uint64_t m);
 uint64_t invmod_u64(uint64_t a, uint64_t m);            // m prime
+
+// Tracing helpers: bracket one kernel launch with events when enabled.
+struct ProfScope {
+    rns_ctx *ctx;
+    const char *name;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(rns_ctx *c, const char *n, hipStream_t st);
+    ~ProfScope();
+};
 
 int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **out);
 int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out);

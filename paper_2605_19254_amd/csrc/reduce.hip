@@ -58,6 +58,7 @@ extern "C" int rns_reduce(rns_ctx *ctx, const int64_t *x, int64_t rows, int64_t 
     const int64_t col_tiles = (cols + kTile - 1) / kTile;
     const int64_t ntiles = rows * col_tiles;
     const int64_t grid = ntiles < (1 << 20) ? ntiles : (1 << 20);
+    ProfScope ps(ctx, "k_reduce", (hipStream_t)stream);
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)grid), dim3(kTile), 0, (hipStream_t)stream,
                        x, rows, cols, ldx, ctx->d_prime + prime_begin, L, res, ldr,
                        plane_stride, col_tiles);
