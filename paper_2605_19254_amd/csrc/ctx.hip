@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -156,6 +157,7 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
     if (!ctx) return RNS_ENOMEM;
     ctx->device = device;
     ctx->L = L;
+    if (const char *e = std::getenv("RNS_INT8_KERNEL")) ctx->int8_kernel = std::atoi(e);
     ctx->primes = ps;
 
     std::vector<PrimeConst> pc(L);

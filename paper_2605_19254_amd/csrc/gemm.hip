@@ -277,6 +277,133 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const GemmProblem *__restrict__
             }
 }
 
+// ------------------------------------------------- INT8 GEMM, LDS pipeline --
+// Same tiles and arithmetic as k_gemm_i8, but the work-group's A and B digit
+// tiles of one 64-k step (4 + 8 row/col blocks x 4 digits = 48 fragments of
+// 1 KiB) are copied global -> LDS with 16-byte direct loads into two
+// alternating buffers, and each wave reads its fragments from LDS.  The two
+// waves that share an A (B) panel read it once from L2 instead of twice, and
+// no registers hold prefetched fragments.
+//
+// Order inside a step: wait for this wave's copies of step kt, barrier (now
+// every wave's copies of step kt are in LDS and every wave has finished
+// reading step kt-1), read the fragments of step kt, start the copies of step
+// kt+1 into the other buffer, then run the 128 MFMAs of step kt while those
+// copies are in flight.
+
+constexpr int kI8FragA = 2 * kI8WaveRB * 4;           // A fragments per 64-k step
+constexpr int kI8FragB = 2 * kI8WaveCB * 4;           // B fragments per 64-k step
+constexpr int kI8Frag = kI8FragA + kI8FragB;          // 48
+constexpr int kI8FragPerWave = kI8Frag / 4;           // 12
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void vm_wait_0() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
+__device__ __forceinline__ void plain_barrier() {
+    // A fenced barrier would make the compiler wait for every outstanding
+    // copy; the copies this barrier must cover were already waited for.  The
+    // empty asm statements keep the compiler from moving memory accesses
+    // across the barrier.
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+__global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restrict__ P, int nprob,
+                                                     int64_t total_tiles,
+                                                     const PrimeConst *__restrict__ pc) {
+    __shared__ v4i sbuf[2][kI8Frag * 64];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= total_tiles) return;
+    const TileCoord tc = map_tile(P, nprob, t);
+    const GemmProblem &g = P[tc.q];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    const int KT = g.KT;
+    const char *Ag = g.At + (int64_t)tc.plane * g.a_plane_bytes +
+                     (int64_t)tc.tm * (2 * kI8WaveRB) * KT * 4096 + lane * 16;
+    const char *Bg = g.Bt + (int64_t)tc.plane * g.b_plane_bytes +
+                     (int64_t)tc.tn * (2 * kI8WaveCB) * KT * 4096 + lane * 16;
+    // Fragment f of a step: f < kI8FragA is A block f/4, digit f%4; otherwise
+    // B block (f-kI8FragA)/4, digit (f-kI8FragA)%4.  Wave w copies f = 12w..12w+11.
+    const char *src[kI8FragPerWave];
+#pragma unroll
+    for (int i = 0; i < kI8FragPerWave; ++i) {
+        const int f = wave * kI8FragPerWave + i;
+        src[i] = f < kI8FragA ? Ag + ((int64_t)(f >> 2) * KT) * 4096 + (f & 3) * 1024
+                              : Bg + ((int64_t)((f - kI8FragA) >> 2) * KT) * 4096 + ((f - kI8FragA) & 3) * 1024;
+    }
+    auto issue = [&](v4i *buf, int kt) {
+#pragma unroll
+        for (int i = 0; i < kI8FragPerWave; ++i) {
+            const int f = wave * kI8FragPerWave + i;
+            __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)kt * 4096),
+                                             (lds_void *)(buf + f * 64), 16, 0, 0);
+        }
+    };
+
+    v4i acc[7][kI8WaveRB][kI8WaveCB];
+#pragma unroll
+    for (int s = 0; s < 7; ++s)
+#pragma unroll
+        for (int i = 0; i < kI8WaveRB; ++i)
+#pragma unroll
+            for (int j = 0; j < kI8WaveCB; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+
+    issue(sbuf[0], 0);
+    for (int kt = 0; kt < KT; ++kt) {
+        const v4i *cur = sbuf[kt & 1];
+        vm_wait_0();
+        plain_barrier();
+        v4i a[kI8WaveRB][4], b[kI8WaveCB][4];
+#pragma unroll
+        for (int i = 0; i < kI8WaveRB; ++i)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) a[i][d] = cur[((wy * kI8WaveRB + i) * 4 + d) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < kI8WaveCB; ++j)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) b[j][d] = cur[(kI8FragA + (wx * kI8WaveCB + j) * 4 + d) * 64 + lane];
+        if (kt + 1 < KT) issue(sbuf[(kt + 1) & 1], kt + 1);
+#pragma unroll
+        for (int da = 0; da < 4; ++da)
+#pragma unroll
+            for (int db = 0; db < 4; ++db)
+#pragma unroll
+                for (int i = 0; i < kI8WaveRB; ++i)
+#pragma unroll
+                    for (int j = 0; j < kI8WaveCB; ++j)
+                        acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            a[i][da], b[j][db], acc[da + db][i][j], 0, 0, 0);
+    }
+
+    const int rb0 = tc.tm * (2 * kI8WaveRB) + wy * kI8WaveRB;
+    const int cb0 = tc.tn * (2 * kI8WaveCB) + wx * kI8WaveCB;
+    const PrimeConst pr = pc[g.prime_begin + tc.plane];
+    uint32_t *C = g.C + (int64_t)tc.plane * g.cps;
+#pragma unroll
+    for (int i = 0; i < kI8WaveRB; ++i)
+#pragma unroll
+        for (int j = 0; j < kI8WaveCB; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double sum = 0.0;
+#pragma unroll
+                for (int s = 0; s < 7; ++s) {
+                    const double cs = (double)acc[s][i][j][v];
+                    const double r = fma(-rint(cs * pr.pinv), pr.pf, cs);
+                    sum = fma(r, pr.w[s], sum);
+                }
+                double r = fma(-rint(sum * pr.pinv), pr.pf, sum);
+                r = r < 0.0 ? r + pr.pf : r;
+                const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + v;
+                const int col = (cb0 + j) * 16 + (lane & 15);
+                if (row < g.m && col < g.n) C[(int64_t)row * g.ldc + col] = (uint32_t)r;
+            }
+}
+
 // ------------------------------------------------------------- FP64 GEMM --
 
 __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProblem *__restrict__ P, int nprob,
@@ -481,8 +608,11 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
     RNS_HIP(hipGetLastError());
     {
     ProfScope ps(ctx, int8 ? "k_gemm_i8" : "k_gemm_f64", s);
-    if (int8)
+    if (int8 && ctx->int8_kernel == 1)
         hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)plan.total_tiles), dim3(256), 0, s, dP, np,
+                           plan.total_tiles, (const PrimeConst *)ctx->d_prime);
+    else if (int8)
+        hipLaunchKernelGGL(k_gemm_i8_lds, dim3((unsigned)plan.total_tiles), dim3(256), 0, s, dP, np,
                            plan.total_tiles, (const PrimeConst *)ctx->d_prime);
     else
         hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)plan.total_tiles), dim3(256), 0, s, dP, np,

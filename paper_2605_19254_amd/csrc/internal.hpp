@@ -62,6 +62,7 @@ struct rns_ctx {
     std::map<std::tuple<int, int, int>, rns::LagrangeTable> lagrange;
     std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
     int force_cert_failures = 0;
+    int int8_kernel = 0;               // 0: LDS-staged GEMM, 1: direct-from-L2 GEMM (RNS_INT8_KERNEL)
     std::mutex mu;
     // tracing: (kernel name, start event, stop event) per launch
     bool prof = false;
