@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="rows of C the oracle computes for the CPU baseline (0 = skip)")
     ap.add_argument("--out", default="")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one plain device copy of this many bytes (a known-size "
+                         "reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -88,6 +91,13 @@ def main():
     A = torch.from_numpy(a_np).to(dev)
     B = torch.from_numpy(b_np).to(dev)
     ctx = rg.Context(device=0, L=L)
+    if args.copy_bytes > 0:
+        src = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ra = torch.empty((L, n, n), dtype=torch.int32, device=dev)
     rb = torch.empty((L, n, n), dtype=torch.int32, device=dev)
     rc = torch.empty((L, n, n), dtype=torch.int32, device=dev)

@@ -1,0 +1,98 @@
+// Shared pieces of the residue-product kernels: the problem table that the
+// host builds for one modmatmul_batched call, the work-group tile shapes, the
+// XCD-aware tile order and the balanced-residue conversion.
+#pragma once
+
+#include "internal.hpp"
+
+namespace rns {
+namespace gemm {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Work-group tiles.  INT8: 4 waves in 2x2, each 32 x 64 -> 64 x 128.
+// FP64: 4 waves in 2x2, each 64 x 64 -> 128 x 128.
+constexpr int kI8WaveRB = 2, kI8WaveCB = 4;
+constexpr int kF64WaveRB = 4, kF64WaveCB = 4;
+constexpr int kI8TileM = 2 * 16 * kI8WaveRB, kI8TileN = 2 * 16 * kI8WaveCB;
+constexpr int kF64TileM = 2 * 16 * kF64WaveRB, kF64TileN = 2 * 16 * kF64WaveCB;
+constexpr int kKTile = 64;   // k extent of one prep unit (both paths)
+
+struct GemmProblem {
+    const uint32_t *A, *B;
+    uint32_t *C;
+    int64_t lda, aps, ldb, bps, ldc, cps;
+    int32_t m, n, k;
+    int32_t L, prime_begin;
+    int32_t RB, CB, KT;          // padded 16-row blocks of A, 16-col blocks of B, 64-k tiles
+    int32_t tm, tn;              // work-group tiles along m and n
+    char *At, *Bt;               // tiled operands in the workspace
+    int64_t a_plane_bytes, b_plane_bytes;
+    int64_t tile_begin;          // prefix over problems of L*tm*tn
+    int64_t unitA_begin;         // prefix over problems of prep units (A then B)
+    int64_t unitB_begin;
+};
+
+__device__ __forceinline__ int find_problem(const GemmProblem *P, int nprob, int64_t t,
+                                            int64_t GemmProblem::*field) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (P[mid].*field <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// XCD-aware remap: work-group b runs on XCD b % 8.  Give each XCD one
+// contiguous range of logical tiles so that the tiles sharing operand panels
+// share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t q = G / 8, r = G % 8;
+    const int64_t x = b % 8, i = b / 8;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ __forceinline__ int32_t balanced(uint32_t r, uint32_t p, uint32_t half) {
+    return r > half ? (int32_t)r - (int32_t)p : (int32_t)r;
+}
+
+// ----------------------------------------------------------- tile mapping --
+
+struct TileCoord {
+    int q, plane, tm, tn;
+};
+
+__device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, int64_t t) {
+    TileCoord c;
+    c.q = find_problem(P, nprob, t, &GemmProblem::tile_begin);
+    const GemmProblem &g = P[c.q];
+    int64_t u = t - g.tile_begin;
+    const int64_t per_plane = (int64_t)g.tm * g.tn;
+    c.plane = (int)(u / per_plane);
+    u -= (int64_t)c.plane * per_plane;
+    // Grouped raster inside a plane: 8 tile-rows at a time, column-major
+    // within the group, so neighbouring work-groups share A and B panels.
+    const int group = 8;
+    const int64_t gsize = (int64_t)group * g.tn;
+    const int gi = (int)(u / gsize);
+    const int first = gi * group;
+    const int rows_in = min(group, g.tm - first);
+    const int64_t v = u - (int64_t)gi * gsize;
+    c.tm = first + (int)(v % rows_in);
+    c.tn = (int)(v / rows_in);
+    return c;
+}
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Launchers (one per kernel family), all asynchronous on `s`.
+void launch_prep(bool int8, const GemmProblem *P, int nprob, int64_t units,
+                 const PrimeConst *pc, hipStream_t s);
+void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
+                    const PrimeConst *pc, hipStream_t s);
+void launch_gemm_f64(const GemmProblem *P, int nprob, int64_t tiles, const PrimeConst *pc,
+                     hipStream_t s);
+
+}  // namespace gemm
+}  // namespace rns
