@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=16,
                     help="rows of C the oracle computes for the CPU baseline (0 = skip)")
     ap.add_argument("--out", default="")
+    ap.add_argument("--batched", type=int, default=512,
+                    help="also time the batched workload with this many uneven products (0 = skip)")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--only", default="", choices=["", "batched"],
+                    help="run only this workload (for profiling)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size "
                          "reference for hardware byte counters)")
@@ -73,6 +78,83 @@ def cpu_baseline(a, b, primes, rows):
             "seconds": t}
 
 
+def run_batched(rg, torch, dev, count, steps):
+    """512 independent products C_i = A_i B_i, n_i log-uniform in [32, 1024]
+    (seed 0), entries uniform in [-2^16, 2^16], 2 primes each (|C| <= n 2^32).
+    One whole-product plan (resident residue planes; reduce, prep, GEMM and CRT
+    launches over the whole batch), autotuned, captured in a HIP graph and
+    replayed.  Ablation: one plan per problem, launched one after another."""
+    import numpy as np
+    import synth
+    from oracle import native, rns as orns
+    batch = synth.uneven_batch(count=count, lo=32, hi=1024, bound=1 << 16, seed=0)
+    ctx = rg.Context(device=0, L=2)
+    probs = []
+    for pr in batch:
+        probs.append(rg.MatmulProblem(torch.from_numpy(pr.a).to(dev), torch.from_numpy(pr.b).to(dev),
+                                      torch.empty((pr.m, pr.n), dtype=torch.int64, device=dev),
+                                      prime_begin=0, L=2, bound=pr.k << 32))
+    ops = sum(2.0 * p.m * p.n * p.k * 2 for p in batch)
+    plan = rg.MatmulPlan(ctx, probs, path="int8")
+    variant = plan.autotune()
+    plan.execute()
+    torch.cuda.synchronize()
+    # correctness: smallest, median and largest problem against the oracle
+    order = sorted(range(count), key=lambda i: batch[i].n)
+    for i in (order[0], order[count // 2], order[-1]):
+        rows = np.array([0, batch[i].m - 1])
+        got = probs[i].C[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        if not np.array_equal(got, native.exact_matmul(batch[i].a[rows], batch[i].b)):
+            raise SystemExit("bench.py: batched result differs from the oracle")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.execute()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    # ablation: a plan per problem, launched in a host loop, no graph
+    singles = [rg.MatmulPlan(ctx, [p], path="int8") for p in probs]
+    for sp in singles:
+        sp.set_variant(variant)
+        sp.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sp in singles:
+        sp.execute()
+    torch.cuda.synchronize()
+    ms_loop = 1000.0 * (time.perf_counter() - t0)
+    for sp in singles:
+        sp.close()
+    info = plan.info()
+    # oracle on a sample of the batch (the first 24 problems of the draw)
+    sample = batch[:24]
+    t0 = time.perf_counter()
+    for pr in sample:
+        ps = ctx.primes[:2]
+        rc = orns.modmatmul_planes(orns.reduce(pr.a, ps), orns.reduce(pr.b, ps), ps)
+        orns.crt_planes(rc, ps)
+    tc = time.perf_counter() - t0
+    sops = sum(2.0 * p.m * p.n * p.k * 2 for p in sample)
+    del g
+    plan.close()
+    ctx.close()
+    return {"workload": "%d independent products, n log-uniform in [32, 1024] (seed 0), entries in "
+                        "[-2^16, 2^16], 2 primes each; one plan under a HIP graph" % count,
+            "value": ops / (ms * 1e-3), "unit": "int-ops/s", "ms_per_step": ms, "steps": steps,
+            "residue_ops": ops, "variant": variant, "tiles": info["tiles"],
+            "mfma_frac_of_int8_peak": 16.0 * ops / (ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
+            "per_problem_launch_loop_ms": ms_loop,
+            "cpu_baseline": {"value": sops / tc, "unit": "int-ops/s", "cores": native.num_threads(),
+                             "kind": "oracle", "sample": "first 24 problems of the batch, %.1f s" % tc}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -87,6 +169,9 @@ def main():
 
     n, L = args.n, args.primes
     dev = torch.device("cuda:0")
+    if args.only == "batched":
+        print(json.dumps(run_batched(rg, torch, dev, args.batched, args.batched_steps)), flush=True)
+        return
     a_np, b_np = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
     A = torch.from_numpy(a_np).to(dev)
     B = torch.from_numpy(b_np).to(dev)
@@ -191,6 +276,7 @@ def main():
         "fp64_path": fp64,
         "int8_vs_fp64_speedup": (fp64["ms_per_step"] / ms8) if fp64 else None,
     }
+    rec["batched"] = run_batched(rg, torch, dev, args.batched, args.batched_steps) if args.batched > 0 else None
     if args.cpu_rows > 0:
         primes = ctx.primes[:L]
         rec["cpu_baseline"] = cpu_baseline(a_np, b_np, primes, args.cpu_rows)

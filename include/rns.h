@@ -163,6 +163,85 @@ int rns_workspace_bytes(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
 int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
                       int path, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Plans: the same products as modmatmul_batched, set up once and run many
+ * times.  Creation validates the problems, sorts them by decreasing tile cost,
+ * allocates a plan-owned workspace and uploads the problem table; execution
+ * only enqueues kernels (one operand-conversion launch and one GEMM launch for
+ * the whole batch), so it may be captured into a HIP graph.  The operand and
+ * result pointers are fixed at creation: an executed plan reads A and B and
+ * writes C as they are at execution time.
+ * ---------------------------------------------------------------------- */
+typedef struct rns_gemm_plan rns_gemm_plan;
+
+typedef struct rns_plan_info {
+    int path;              /* RNS_PATH_FP64 or RNS_PATH_INT8 */
+    int variant;           /* INT8 GEMM kernel: 0 LDS-staged, 1 direct from L2,
+                              2 LDS-staged persistent (one work-group per CU
+                              taking tiles, longest first, from a counter) */
+    int64_t tiles;         /* work-group tiles over all primes and problems */
+    size_t workspace_bytes;
+    double residue_ops;    /* 2*m*n*k*L summed over the problems */
+} rns_plan_info;
+
+int rns_gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
+                         int path, rns_gemm_plan **out);
+int rns_gemm_plan_execute(rns_gemm_plan *plan, void *stream);
+int rns_gemm_plan_info(const rns_gemm_plan *plan, rns_plan_info *info);
+int rns_gemm_plan_set_variant(rns_gemm_plan *plan, int variant);
+void rns_gemm_plan_destroy(rns_gemm_plan *plan);
+
+/*
+ * Autotuner.  rns_autotune times every INT8 GEMM variant on these problems
+ * (it runs them: C is overwritten), records the fastest for the batch's shape
+ * class (path, number of problems, largest dimension and total work, on log2
+ * scales) in the context, and appends it to the cache file if one is set.
+ * Plans and modmatmul_batched created afterwards use the recorded variant.
+ * rns_ctx_set_tune_cache loads an existing cache file ("key variant" lines).
+ */
+int rns_ctx_set_tune_cache(rns_ctx *ctx, const char *path);
+int rns_autotune(rns_ctx *ctx, const rns_gemm_desc *descs, int count, int path,
+                 void *stream, int *variant_out);
+/* The same for an existing plan (which then keeps the chosen variant). */
+int rns_gemm_plan_autotune(rns_gemm_plan *plan, void *stream, int *variant_out);
+
+/*
+ * Whole-product plans (Section 3.1 end to end): C = A B over the integers for
+ * `count` independent problems.  The plan owns the residue planes of A, B and
+ * C for every problem (they stay resident in HBM between executions), and one
+ * execution runs one reduction launch over all A and B, the operand
+ * conversion and GEMM launches of a gemm plan, and one CRT launch over all C.
+ *   A, B: device int64, row-major (m x k, k x n), leading dimensions lda, ldb.
+ *   C:    device uint64, W words per entry (entry (i, j) at
+ *         C[(i*ldc + j)*W + w]), two's complement; W == 1 is an int64 matrix.
+ *   bound: a promise |C_ij| <= bound for every entry (0 = no promise).  When
+ *         every problem has a promise with margin the Lagrange CRT form is used,
+ *         otherwise the exact mixed-radix form.
+ *   prime_begin, L: the primes of the problem, 1 <= L <= 64.
+ * Overflow of W words is reported through the context status word.
+ */
+typedef struct rns_matmul_desc {
+    int64_t m, n, k;
+    const int64_t *A;
+    int64_t lda;
+    const int64_t *B;
+    int64_t ldb;
+    uint64_t *C;
+    int64_t ldc;
+    int32_t prime_begin;
+    int32_t L;
+    uint64_t bound;
+} rns_matmul_desc;
+
+typedef struct rns_matmul_plan rns_matmul_plan;
+
+int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *descs, int count,
+                           int path, int W, rns_matmul_plan **out);
+int rns_matmul_plan_execute(rns_matmul_plan *plan, void *stream);
+int rns_matmul_plan_info(const rns_matmul_plan *plan, rns_plan_info *info);
+rns_gemm_plan *rns_matmul_plan_gemm(rns_matmul_plan *plan);
+void rns_matmul_plan_destroy(rns_matmul_plan *plan);
+
 /*
  * crt_reconstruct -- Section 3.1, Chinese-remainder reconstruction of every
  * entry of an L-plane residue matrix: the unique integer x with

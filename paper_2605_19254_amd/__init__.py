@@ -6,6 +6,7 @@ include/rns.h); ``binding`` marshals torch device tensors into it.  Importing
 the binding without the built library raises ImportError: there is no CPU
 fallback.
 """
-from .binding import (Context, GemmProblem, RnsError, SmithResult, crt_reconstruct,  # noqa: F401
-                      modmatmul_batched, rns_primes_below, rns_reduce, rns_strerror,
-                      smith_form, words_to_ints, workspace_bytes)
+from .binding import (Context, GemmPlan, GemmProblem, MatmulPlan, MatmulProblem,  # noqa: F401
+                      RnsError, SmithResult, autotune, crt_reconstruct, modmatmul_batched,
+                      rns_primes_below, rns_reduce, rns_strerror, smith_form, words_to_ints,
+                      workspace_bytes)

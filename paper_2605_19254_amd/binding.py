@@ -111,6 +111,33 @@ _lib_smith_get = _sig("rns_smith_get", _I32, [_P, _I64, ctypes.POINTER(ctypes.PO
 _lib_smith_size = _sig("rns_smith_size", _I64, [_P])
 _lib_smith_stats = _sig("rns_smith_stats_get", _I32, [_P, ctypes.POINTER(RnsSmithStats)])
 _lib_smith_free = _sig("rns_smith_free", None, [_P])
+class RnsPlanInfo(ctypes.Structure):
+    _fields_ = [("path", _I32), ("variant", _I32), ("tiles", _I64), ("workspace_bytes", ctypes.c_size_t),
+                ("residue_ops", ctypes.c_double)]
+
+
+class RnsMatmulDesc(ctypes.Structure):
+    _fields_ = [("m", _I64), ("n", _I64), ("k", _I64), ("A", _P), ("lda", _I64), ("B", _P), ("ldb", _I64),
+                ("C", _P), ("ldc", _I64), ("prime_begin", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("bound", ctypes.c_uint64)]
+
+
+_lib_gplan_create = _sig("rns_gemm_plan_create", _I32, [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32,
+                                                       ctypes.POINTER(_P)])
+_lib_gplan_execute = _sig("rns_gemm_plan_execute", _I32, [_P, _P])
+_lib_gplan_info = _sig("rns_gemm_plan_info", _I32, [_P, ctypes.POINTER(RnsPlanInfo)])
+_lib_gplan_set_variant = _sig("rns_gemm_plan_set_variant", _I32, [_P, _I32])
+_lib_gplan_destroy = _sig("rns_gemm_plan_destroy", None, [_P])
+_lib_gplan_autotune = _sig("rns_gemm_plan_autotune", _I32, [_P, _P, ctypes.POINTER(_I32)])
+_lib_set_tune_cache = _sig("rns_ctx_set_tune_cache", _I32, [_P, ctypes.c_char_p])
+_lib_autotune = _sig("rns_autotune", _I32, [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32, _P,
+                                            ctypes.POINTER(_I32)])
+_lib_mplan_create = _sig("rns_matmul_plan_create", _I32, [_P, ctypes.POINTER(RnsMatmulDesc), _I32, _I32,
+                                                         _I32, ctypes.POINTER(_P)])
+_lib_mplan_execute = _sig("rns_matmul_plan_execute", _I32, [_P, _P])
+_lib_mplan_info = _sig("rns_matmul_plan_info", _I32, [_P, ctypes.POINTER(RnsPlanInfo)])
+_lib_mplan_gemm = _sig("rns_matmul_plan_gemm", _P, [_P])
+_lib_mplan_destroy = _sig("rns_matmul_plan_destroy", None, [_P])
 _lib_profile = _sig("rns_ctx_profile", _I32, [_P, _I32])
 _lib_profile_read = _sig("rns_ctx_profile_read", _I32, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                                         ctypes.POINTER(_I64)])
@@ -120,7 +147,10 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_primes_for_bound", "rns_reduce", "modmatmul_batched", "crt_reconstruct",
            "rns_ctx_status", "smith_form", "rns_smith_get", "rns_smith_size",
            "rns_smith_stats_get", "rns_smith_free", "rns_ctx_force_cert_failures",
-           "rns_ctx_profile", "rns_ctx_profile_read"]
+           "rns_ctx_profile", "rns_ctx_profile_read", "rns_gemm_plan_create", "rns_gemm_plan_execute",
+           "rns_gemm_plan_info", "rns_gemm_plan_set_variant", "rns_gemm_plan_destroy",
+           "rns_ctx_set_tune_cache", "rns_autotune", "rns_gemm_plan_autotune", "rns_matmul_plan_create", "rns_matmul_plan_execute",
+           "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy"]
 
 
 class RnsError(RuntimeError):
@@ -233,6 +263,9 @@ class Context:
                "rns_ctx_profile_read")
         return ms.value, cnt.value
 
+    def set_tune_cache(self, path: str):
+        _check(_lib_set_tune_cache(self.handle, path.encode() if path else None), "rns_ctx_set_tune_cache")
+
     def force_cert_failures(self, count: int):
         _check(_lib_force(self.handle, count), "rns_ctx_force_cert_failures")
 
@@ -296,6 +329,127 @@ def workspace_bytes(ctx: Context, problems: Sequence[GemmProblem], path="auto") 
     _check(_lib_workspace_bytes(ctx.handle, arr, len(problems), path, ctypes.byref(out)),
            "rns_workspace_bytes")
     return out.value
+
+
+def _path(path):
+    return _PATHS[path] if isinstance(path, str) else int(path)
+
+
+def _info(fn, h) -> dict:
+    info = RnsPlanInfo()
+    _check(fn(h, ctypes.byref(info)), "plan info")
+    return {"path": {1: "fp64", 2: "int8"}.get(info.path, info.path), "variant": info.variant,
+            "tiles": info.tiles, "workspace_bytes": info.workspace_bytes, "residue_ops": info.residue_ops}
+
+
+class GemmPlan:
+    """rns_gemm_plan: modmatmul_batched set up once; execute() only launches
+    kernels and may be captured into a HIP graph.  Keeps the tensors alive."""
+
+    def __init__(self, ctx: Context, problems: Sequence[GemmProblem], path="auto"):
+        self.ctx = ctx
+        self._keep = list(problems)
+        arr = _descs(problems)
+        h = _P()
+        _check(_lib_gplan_create(ctx.handle, arr, len(problems), _path(path), ctypes.byref(h)),
+               "rns_gemm_plan_create")
+        self.handle = h
+
+    def execute(self, stream=None):
+        _check(_lib_gplan_execute(self.handle, _stream(stream)), "rns_gemm_plan_execute")
+
+    def info(self) -> dict:
+        return _info(_lib_gplan_info, self.handle)
+
+    def set_variant(self, v: int):
+        _check(_lib_gplan_set_variant(self.handle, v), "rns_gemm_plan_set_variant")
+
+    def autotune(self, stream=None) -> int:
+        v = _I32()
+        _check(_lib_gplan_autotune(self.handle, _stream(stream), ctypes.byref(v)), "rns_gemm_plan_autotune")
+        return v.value
+
+    def close(self):
+        if self.handle:
+            _lib_gplan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ctx: Context, problems: Sequence[GemmProblem], path="auto", stream=None) -> int:
+    arr = _descs(problems)
+    v = _I32()
+    _check(_lib_autotune(ctx.handle, arr, len(problems), _path(path), _stream(stream), ctypes.byref(v)),
+           "rns_autotune")
+    return v.value
+
+
+@dataclass
+class MatmulProblem:
+    """C = A @ B over the integers: A (m, k), B (k, n) int64 device tensors;
+    C int64 (m, n) for W == 1 or (m, n, W) words."""
+    A: object
+    B: object
+    C: object
+    prime_begin: int = 0
+    L: int = 24
+    bound: int = 0
+
+
+class MatmulPlan:
+    """rns_matmul_plan: reduce -> products -> CRT for a batch, with resident
+    residue planes; execute() is four kernel launches."""
+
+    def __init__(self, ctx: Context, problems: Sequence[MatmulProblem], path="auto", W: int = 1):
+        self.ctx = ctx
+        self._keep = list(problems)
+        arr = (RnsMatmulDesc * max(1, len(problems)))()
+        for i, p in enumerate(problems):
+            m, k = p.A.shape
+            k2, n = p.B.shape
+            assert k == k2 and p.A.stride(1) == 1 and p.B.stride(1) == 1 and p.C.is_contiguous()
+            d = arr[i]
+            d.m, d.n, d.k = m, n, k
+            d.A, d.lda = _dev_ptr(p.A), p.A.stride(0)
+            d.B, d.ldb = _dev_ptr(p.B), p.B.stride(0)
+            d.C, d.ldc = _dev_ptr(p.C), n
+            d.prime_begin, d.L, d.bound = p.prime_begin, p.L, int(p.bound)
+        h = _P()
+        _check(_lib_mplan_create(ctx.handle, arr, len(problems), _path(path), W, ctypes.byref(h)),
+               "rns_matmul_plan_create")
+        self.handle = h
+
+    def execute(self, stream=None):
+        _check(_lib_mplan_execute(self.handle, _stream(stream)), "rns_matmul_plan_execute")
+
+    def info(self) -> dict:
+        return _info(_lib_mplan_info, self.handle)
+
+    def set_variant(self, v: int):
+        _check(_lib_gplan_set_variant(_lib_mplan_gemm(self.handle), v), "rns_gemm_plan_set_variant")
+
+    def autotune(self, stream=None) -> int:
+        """Time the INT8 GEMM variants on this plan's products and keep the fastest."""
+        v = _I32()
+        _check(_lib_gplan_autotune(_lib_mplan_gemm(self.handle), _stream(stream), ctypes.byref(v)),
+               "rns_gemm_plan_autotune")
+        return v.value
+
+    def close(self):
+        if self.handle:
+            _lib_mplan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def crt_reconstruct(ctx: Context, res, prime_begin: int = 0, L: Optional[int] = None,

@@ -20,7 +20,10 @@
 // leaves the margin B/M <= 1/2 - 2^-40 (the double sum of at most 64 terms
 // below 1 errs by less than 2^-40.9), which the host checks before choosing
 // this form; it also requires B < 2^(64W-1), so the result cannot overflow.
-#include "internal.hpp"
+//
+// Both kernels take one job by value or a table of jobs in device memory
+// (every product of a batched plan in one launch).
+#include "reduce_crt.hpp"
 
 #include <algorithm>
 
@@ -34,20 +37,34 @@ __device__ __forceinline__ double modp(double x, const PrimeConst &P) {
     return fma(-rint(x * P.pinv), P.pf, x);                 // |result| <= (p+1)/2
 }
 
+__device__ __forceinline__ int find_job(const CrtJob *jobs, int njobs, int64_t t) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int WT>
-__global__ __launch_bounds__(kBlock) void k_crt_garner(
-    const uint32_t *__restrict__ res, int64_t rows, int64_t cols, int64_t ldr, int64_t ps,
-    const PrimeConst *__restrict__ pc, const double *__restrict__ garner,
-    const uint32_t *__restrict__ half, int L, uint64_t *__restrict__ out, int W, int64_t ldo,
-    int32_t *__restrict__ status, int64_t col_tiles) {
+__global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob *__restrict__ jobs,
+                                                      int njobs, int64_t total_tiles,
+                                                      const PrimeConst *__restrict__ pc_all,
+                                                      const double *__restrict__ garner_all, int W) {
     __shared__ uint32_t vd[kCrtMaxL][kBlock];
     const int tid = threadIdx.x;
-    const int64_t ntiles = rows * col_tiles;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t i = t / col_tiles;
-        const int64_t c = (t - i * col_tiles) * kBlock + tid;
-        if (c >= cols) continue;
-        const uint32_t *src = res + i * ldr + c;
+    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        const CrtJob &J = njobs > 0 ? jobs[find_job(jobs, njobs, t)] : job0;
+        const int64_t u = t - J.tile_begin;
+        const int64_t i = u / J.col_tiles;
+        const int64_t c = (u - i * J.col_tiles) * kBlock + tid;
+        if (c >= J.cols) continue;
+        const uint32_t *src = J.res + i * J.ldr + c;
+        const PrimeConst *pc = pc_all + J.prime_begin;
+        const double *garner = garner_all + (int64_t)J.prime_begin * kCrtMaxL;
+        const uint32_t *half = J.half;
+        const int L = J.L;
+        const int64_t ps = J.ps;
         // Garner digits.
         for (int j = 0; j < L; ++j) {
             const PrimeConst P = pc[j];
@@ -113,9 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(
         bool fits;
         if (!neg) fits = high_zero && (top >> 63) == 0;
         else fits = high_zero && ((top >> 63) == 0 || (top == (1ull << 63) && low_zero));
-        if (!fits) atomicOr(status, 1);
+        if (!fits) atomicOr(J.status, 1);
         // Two's complement of the signed value, low W words.
-        uint64_t *dst = out + (i * ldo + c) * W;
+        uint64_t *dst = J.out + (i * J.ldo + c) * W;
         uint64_t carry = 1;
 #pragma unroll
         for (int k = 0; k < WT; ++k) {
@@ -133,17 +150,22 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(
 }
 
 template <int WT>
-__global__ __launch_bounds__(kBlock) void k_crt_lagrange(
-    const uint32_t *__restrict__ res, int64_t rows, int64_t cols, int64_t ldr, int64_t ps,
-    const PrimeConst *__restrict__ pc, const double *__restrict__ cinv,
-    const uint64_t *__restrict__ mj, const uint64_t *__restrict__ mw, int L,
-    uint64_t *__restrict__ out, int W, int64_t ldo, int64_t col_tiles) {
-    const int64_t ntiles = rows * col_tiles;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t i = t / col_tiles;
-        const int64_t c = (t - i * col_tiles) * kBlock + threadIdx.x;
-        if (c >= cols) continue;
-        const uint32_t *src = res + i * ldr + c;
+__global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJob *__restrict__ jobs,
+                                                        int njobs, int64_t total_tiles,
+                                                        const PrimeConst *__restrict__ pc_all, int W) {
+    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        const CrtJob &J = njobs > 0 ? jobs[find_job(jobs, njobs, t)] : job0;
+        const int64_t u = t - J.tile_begin;
+        const int64_t i = u / J.col_tiles;
+        const int64_t c = (u - i * J.col_tiles) * kBlock + threadIdx.x;
+        if (c >= J.cols) continue;
+        const uint32_t *src = J.res + i * J.ldr + c;
+        const PrimeConst *pc = pc_all + J.prime_begin;
+        const double *cinv = J.lag_c;
+        const uint64_t *mj = J.lag_mj;
+        const uint64_t *mw = J.lag_m;
+        const int L = J.L;
+        const int64_t ps = J.ps;
         uint64_t x[WT];
 #pragma unroll
         for (int k = 0; k < WT; ++k) x[k] = 0;
@@ -188,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_crt_lagrange(
                 borrow = b1 + b2;
             }
         }
-        uint64_t *dst = out + (i * ldo + c) * W;
+        uint64_t *dst = J.out + (i * J.ldo + c) * W;
 #pragma unroll
         for (int k = 0; k < WT; ++k)
             if (k < W) dst[k] = x[k];
@@ -248,6 +270,54 @@ Limbs limbs_shr(const Limbs &a, int bits, bool round_up) {
 
 }  // namespace
 
+namespace rns {
+
+int64_t crt_col_tiles(int64_t cols) { return (cols + kBlock - 1) / kBlock; }
+int64_t crt_tiles(int64_t rows, int64_t cols) { return rows * crt_col_tiles(cols); }
+
+bool crt_fast_ok(const rns_ctx *ctx, int begin, int L, const uint64_t *bound_words, int Wb, int W) {
+    if (!bound_words || Wb <= 0) return false;
+    Limbs B = limbs_from_words(bound_words, Wb);
+    Limbs M{1};
+    for (int j = 0; j < L; ++j) limbs_mul_small(M, ctx->primes[begin + j]);
+    Limbs twoB = B;
+    limbs_mul_small(twoB, 2);
+    Limbs lim_w{1};                    // 2^(64W-1)
+    for (int k = 0; k < 64 * W - 1; ++k) limbs_mul_small(lim_w, 2);
+    if (limbs_cmp(twoB, M) >= 0 || limbs_cmp(B, lim_w) >= 0) return false;
+    Limbs D = limbs_sub(M, twoB);
+    Limbs T = limbs_shr(M, 39, true);
+    return limbs_cmp(D, T) >= 0;
+}
+
+void launch_crt(bool fast, int W, const CrtJob &job0, const CrtJob *jobs, int njobs,
+                int64_t total_tiles, const PrimeConst *pc, const double *garner, hipStream_t s) {
+    const unsigned grid = (unsigned)std::min<int64_t>(total_tiles, 1 << 20);
+    if (fast) {
+#define RNS_LAG(WT_) \
+    hipLaunchKernelGGL(k_crt_lagrange<WT_>, dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, W)
+        if (W <= 1) RNS_LAG(1);
+        else if (W <= 2) RNS_LAG(2);
+        else if (W <= 4) RNS_LAG(4);
+        else if (W <= 8) RNS_LAG(8);
+        else if (W <= 16) RNS_LAG(16);
+        else RNS_LAG(32);
+#undef RNS_LAG
+    } else {
+#define RNS_GAR(WT_) \
+    hipLaunchKernelGGL(k_crt_garner<WT_>, dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, garner, W)
+        if (W <= 1) RNS_GAR(1);
+        else if (W <= 2) RNS_GAR(2);
+        else if (W <= 4) RNS_GAR(4);
+        else if (W <= 8) RNS_GAR(8);
+        else if (W <= 16) RNS_GAR(16);
+        else RNS_GAR(32);
+#undef RNS_GAR
+    }
+}
+
+}  // namespace rns
+
 extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, int64_t cols,
                                int64_t ldr, int64_t plane_stride, int prime_begin, int L,
                                const uint64_t *bound_words, int Wb, uint64_t *out, int W,
@@ -262,62 +332,24 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
     std::lock_guard<std::mutex> guard(ctx->mu);
     RNS_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    const int64_t col_tiles = (cols + kBlock - 1) / kBlock;
-    const int64_t ntiles = rows * col_tiles;
-    const unsigned grid = (unsigned)std::min<int64_t>(ntiles, 1 << 20);
-    const PrimeConst *pc = ctx->d_prime + prime_begin;
-
-    // Decide whether the caller's bound allows the Lagrange form.
-    bool fast = false;
-    if (bound_words && Wb > 0) {
-        Limbs B = limbs_from_words(bound_words, Wb);
-        Limbs M{1};
-        for (int j = 0; j < L; ++j) limbs_mul_small(M, ctx->primes[prime_begin + j]);
-        Limbs twoB = B;
-        limbs_mul_small(twoB, 2);
-        Limbs lim_w{1};                    // 2^(64W-1)
-        for (int k = 0; k < 64 * W - 1; ++k) limbs_mul_small(lim_w, 2);
-        if (limbs_cmp(twoB, M) < 0 && limbs_cmp(B, lim_w) < 0) {
-            Limbs D = limbs_sub(M, twoB);
-            Limbs T = limbs_shr(M, 39, true);
-            fast = limbs_cmp(D, T) >= 0;
-        }
-    }
+    CrtJob j{};
+    j.res = res; j.rows = rows; j.cols = cols; j.ldr = ldr; j.ps = plane_stride;
+    j.prime_begin = prime_begin; j.L = L; j.out = out; j.ldo = ldo;
+    j.status = d_status ? d_status : ctx->d_status;
+    j.col_tiles = crt_col_tiles(cols);
+    j.tile_begin = 0;
+    const bool fast = crt_fast_ok(ctx, prime_begin, L, bound_words, Wb, W);
     if (fast) {
         const LagrangeTable *lt = nullptr;
         int st = lagrange_table(ctx, prime_begin, L, W, &lt);
         if (st != RNS_OK) return st;
-        ProfScope ps(ctx, "k_crt_lagrange", s);
-#define RNS_LAG(WT_)                                                                       \
-    hipLaunchKernelGGL(k_crt_lagrange<WT_>, dim3(grid), dim3(kBlock), 0, s, res, rows, cols, \
-                       ldr, plane_stride, pc, lt->d_c, lt->d_mj, lt->d_m, L, out, W, ldo,   \
-                       col_tiles)
-        if (W <= 1) RNS_LAG(1);
-        else if (W <= 2) RNS_LAG(2);
-        else if (W <= 4) RNS_LAG(4);
-        else if (W <= 8) RNS_LAG(8);
-        else if (W <= 16) RNS_LAG(16);
-        else RNS_LAG(32);
-#undef RNS_LAG
+        j.lag_c = lt->d_c; j.lag_mj = lt->d_mj; j.lag_m = lt->d_m;
     } else {
-        const uint32_t *half = nullptr;
-        int st = mixed_radix_half(ctx, prime_begin, L, &half);
+        int st = mixed_radix_half(ctx, prime_begin, L, &j.half);
         if (st != RNS_OK) return st;
-        int32_t *status = d_status ? d_status : ctx->d_status;
-        const double *garner = ctx->d_garner + (int64_t)prime_begin * kCrtMaxL;
-        ProfScope ps(ctx, "k_crt_garner", s);
-#define RNS_GAR(WT_)                                                                      \
-    hipLaunchKernelGGL(k_crt_garner<WT_>, dim3(grid), dim3(kBlock), 0, s, res, rows, cols, \
-                       ldr, plane_stride, pc, garner, half, L, out, W, ldo, status,        \
-                       col_tiles)
-        if (W <= 1) RNS_GAR(1);
-        else if (W <= 2) RNS_GAR(2);
-        else if (W <= 4) RNS_GAR(4);
-        else if (W <= 8) RNS_GAR(8);
-        else if (W <= 16) RNS_GAR(16);
-        else RNS_GAR(32);
-#undef RNS_GAR
     }
+    ProfScope ps(ctx, fast ? "k_crt_lagrange" : "k_crt_garner", s);
+    launch_crt(fast, W, j, nullptr, 0, crt_tiles(rows, cols), ctx->d_prime, ctx->d_garner, s);
     RNS_HIP(hipGetLastError());
     return RNS_OK;
 }

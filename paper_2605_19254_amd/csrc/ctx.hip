@@ -178,6 +178,13 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
     if (hipMemcpy(ctx->d_garner, garner.data(), sizeof(double) * garner.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(RNS_EDEVICE);
     if (hipMemset(ctx->d_status, 0, sizeof(int32_t)) != hipSuccess) return fail(RNS_EDEVICE);
+    if (hipMalloc(&ctx->d_counter, sizeof(unsigned)) != hipSuccess) return fail(RNS_ENOMEM);
+    if (hipMemset(ctx->d_counter, 0, sizeof(unsigned)) != hipSuccess) return fail(RNS_EDEVICE);
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+            ctx->num_cus = prop.multiProcessorCount;
+    }
     (void)st;
     *out = ctx;
     return RNS_OK;
@@ -191,6 +198,7 @@ extern "C" void rns_ctx_destroy(rns_ctx *ctx) {
     if (ctx->d_prime) (void)hipFree(ctx->d_prime);
     if (ctx->d_garner) (void)hipFree(ctx->d_garner);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
+    if (ctx->d_counter) (void)hipFree(ctx->d_counter);
     if (ctx->d_work) (void)hipFree(ctx->d_work);
     if (ctx->d_desc) (void)hipFree(ctx->d_desc);
     if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);

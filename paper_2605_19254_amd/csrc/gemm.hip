@@ -10,7 +10,10 @@
 #include "gemm_common.hpp"
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <new>
+#include <string>
 #include <vector>
 
 using namespace rns;
@@ -23,28 +26,48 @@ struct Plan {
     size_t work_bytes = 0;
     int64_t total_tiles = 0;
     int64_t total_units = 0;
+    double residue_ops = 0;
+    int64_t max_dim = 0;
 };
 
+int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x) {
+    if (x.m < 0 || x.n < 0 || x.k < 0 || x.L < 0) return RNS_EINVAL;
+    if (x.prime_begin < 0 || x.prime_begin + x.L > ctx->L) return RNS_EINVAL;
+    if (x.m > INT32_MAX / 2 || x.n > INT32_MAX / 2 || x.k > INT32_MAX / 2) return RNS_EINVAL;
+    if (x.m == 0 || x.n == 0 || x.L == 0) return RNS_OK;
+    if (!x.C || x.ldc < x.n) return RNS_EINVAL;
+    if (x.L > 1 && x.c_plane_stride < (x.m - 1) * x.ldc + x.n) return RNS_EINVAL;
+    if (x.k > 0) {
+        if (!x.A || !x.B || x.lda < x.k || x.ldb < x.n) return RNS_EINVAL;
+        if (x.L > 1 && (x.a_plane_stride < (x.m - 1) * x.lda + x.k ||
+                        x.b_plane_stride < (x.k - 1) * x.ldb + x.n))
+            return RNS_EINVAL;
+    }
+    return RNS_OK;
+}
+
+// Builds the problem table.  Problems are ordered by decreasing tile cost
+// (k, then m*n), so that a persistent launch hands out the longest tiles
+// first; workspace offsets are relative (the caller adds the base).
 int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &plan) {
     const int TM = int8 ? kI8TileM : kF64TileM;
     const int TN = int8 ? kI8TileN : kF64TileN;
     const int64_t elem = int8 ? 4 : 8;   // bytes per operand entry in the tiled layout
-    size_t off = 0;
+    std::vector<int> order;
     for (int i = 0; i < count; ++i) {
+        int st = check_desc(ctx, d[i]);
+        if (st != RNS_OK) return st;
+        if (d[i].m == 0 || d[i].n == 0 || d[i].L == 0) continue;
+        if (int8 && d[i].k > kInt8MaxK) return RNS_EBOUND;
+        order.push_back(i);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (d[a].k != d[b].k) return d[a].k > d[b].k;
+        return d[a].m * d[a].n > d[b].m * d[b].n;
+    });
+    size_t off = 0;
+    for (int i : order) {
         const rns_gemm_desc &x = d[i];
-        if (x.m < 0 || x.n < 0 || x.k < 0 || x.L < 0) return RNS_EINVAL;
-        if (x.prime_begin < 0 || x.prime_begin + x.L > ctx->L) return RNS_EINVAL;
-        if (x.m > INT32_MAX / 2 || x.n > INT32_MAX / 2 || x.k > INT32_MAX / 2) return RNS_EINVAL;
-        if (x.m == 0 || x.n == 0 || x.L == 0) continue;
-        if (!x.C || x.ldc < x.n) return RNS_EINVAL;
-        if (x.L > 1 && x.c_plane_stride < (x.m - 1) * x.ldc + x.n) return RNS_EINVAL;
-        if (x.k > 0) {
-            if (!x.A || !x.B || x.lda < x.k || x.ldb < x.n) return RNS_EINVAL;
-            if (x.L > 1 && (x.a_plane_stride < (x.m - 1) * x.lda + x.k ||
-                            x.b_plane_stride < (x.k - 1) * x.ldb + x.n))
-                return RNS_EINVAL;
-        }
-        if (int8 && x.k > kInt8MaxK) return RNS_EBOUND;
         GemmProblem g{};
         g.A = x.A; g.B = x.B; g.C = x.C;
         g.lda = x.lda; g.aps = x.a_plane_stride;
@@ -68,20 +91,258 @@ int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &
         g.unitA_begin = plan.total_units;
         g.unitB_begin = g.unitA_begin + (int64_t)g.L * g.RB * g.KT;
         plan.total_units = g.unitB_begin + (int64_t)g.L * g.CB * g.KT;
+        plan.residue_ops += 2.0 * x.m * x.n * x.k * x.L;
+        plan.max_dim = std::max<int64_t>(plan.max_dim, std::max(x.m, std::max(x.n, x.k)));
         plan.probs.push_back(g);
     }
     plan.work_bytes = off;
     return RNS_OK;
 }
 
+// Plans for a path; AUTO takes INT8 unless k exceeds its exactness bound.
+int make_plan_path(rns_ctx *ctx, const rns_gemm_desc *d, int count, int path, bool &int8, Plan &plan) {
+    int8 = path != RNS_PATH_FP64;
+    int st = make_plan(ctx, d, count, int8, plan);
+    if (st == RNS_EBOUND && path == RNS_PATH_AUTO) {
+        int8 = false;
+        plan = Plan();
+        st = make_plan(ctx, d, count, int8, plan);
+    }
+    return st;
+}
+
+int ilog2_ceil(double x) {
+    int e = 0;
+    while (x > 1.0) { x /= 2.0; ++e; }
+    return e;
+}
+
+// Shape class of a batch for the autotuner: path, number of problems, largest
+// dimension and total residue work, each on a log2 scale.
+std::string tune_key(bool int8, const Plan &plan) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "gfx950/%s/count%d/dim%d/ops%d", int8 ? "int8" : "fp64",
+                  ilog2_ceil((double)plan.probs.size()), ilog2_ceil((double)plan.max_dim),
+                  ilog2_ceil(plan.residue_ops));
+    return buf;
+}
+
+int choose_variant(rns_ctx *ctx, bool int8, const Plan &plan) {
+    if (!int8) return 0;
+    if (ctx->int8_kernel >= 0) return ctx->int8_kernel;
+    auto it = ctx->tune.find(tune_key(int8, plan));
+    return it != ctx->tune.end() ? it->second : kI8Lds;
+}
+
+int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np, int64_t tiles,
+             int64_t units, unsigned *counter, hipStream_t s) {
+    const bool persistent = int8 && variant == kI8LdsPersistent;
+    {
+        ProfScope ps(ctx, int8 ? "k_prep_i8" : "k_prep_f64", s);
+        launch_prep(int8, dP, np, units, (const PrimeConst *)ctx->d_prime,
+                    persistent ? counter : nullptr, s);
+    }
+    RNS_HIP(hipGetLastError());
+    {
+        ProfScope ps(ctx, int8 ? "k_gemm_i8" : "k_gemm_f64", s);
+        if (int8)
+            launch_gemm_i8(variant, dP, np, tiles, (const PrimeConst *)ctx->d_prime, counter,
+                           ctx->num_cus, s);
+        else
+            launch_gemm_f64(dP, np, tiles, (const PrimeConst *)ctx->d_prime, s);
+    }
+    RNS_HIP(hipGetLastError());
+    return RNS_OK;
+}
+
 }  // namespace
+
+// ------------------------------------------------------------------ plans --
+
+struct rns_gemm_plan {
+    rns_ctx *ctx = nullptr;
+    bool int8 = true;
+    int variant = 0;
+    int nprob = 0;
+    int64_t total_tiles = 0, total_units = 0;
+    size_t work_bytes = 0;
+    double residue_ops = 0;
+    std::string key;
+    GemmProblem *d_probs = nullptr;
+    void *d_work = nullptr;
+    unsigned *d_counter = nullptr;
+};
+
+extern "C" void rns_gemm_plan_destroy(rns_gemm_plan *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (p->d_probs) (void)hipFree(p->d_probs);
+    if (p->d_work) (void)hipFree(p->d_work);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    delete p;
+}
+
+extern "C" int rns_gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, int count, int path,
+                                    rns_gemm_plan **out) {
+    if (!ctx || !out || count < 0 || (count > 0 && !descs)) return RNS_EINVAL;
+    if (path != RNS_PATH_AUTO && path != RNS_PATH_FP64 && path != RNS_PATH_INT8) return RNS_EINVAL;
+    *out = nullptr;
+    bool int8 = true;
+    Plan plan;
+    int st = make_plan_path(ctx, descs, count, path, int8, plan);
+    if (st != RNS_OK) return st;
+    rns_gemm_plan *p = new (std::nothrow) rns_gemm_plan;
+    if (!p) return RNS_ENOMEM;
+    p->ctx = ctx;
+    p->int8 = int8;
+    p->nprob = (int)plan.probs.size();
+    p->total_tiles = plan.total_tiles;
+    p->total_units = plan.total_units;
+    p->work_bytes = plan.work_bytes;
+    p->residue_ops = plan.residue_ops;
+    p->key = tune_key(int8, plan);
+    {
+        std::lock_guard<std::mutex> guard(ctx->mu);
+        p->variant = choose_variant(ctx, int8, plan);
+    }
+    auto fail = [&](int s) { rns_gemm_plan_destroy(p); return s; };
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RNS_EDEVICE);
+    if (p->nprob > 0) {
+        if (hipMalloc(&p->d_work, std::max<size_t>(plan.work_bytes, 256)) != hipSuccess) return fail(RNS_ENOMEM);
+        for (auto &g : plan.probs) {
+            g.At = static_cast<char *>(p->d_work) + reinterpret_cast<size_t>(g.At);
+            g.Bt = static_cast<char *>(p->d_work) + reinterpret_cast<size_t>(g.Bt);
+        }
+        const size_t tbytes = sizeof(GemmProblem) * plan.probs.size();
+        if (hipMalloc(&p->d_probs, tbytes) != hipSuccess) return fail(RNS_ENOMEM);
+        if (hipMemcpy(p->d_probs, plan.probs.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(RNS_EDEVICE);
+        if (hipMalloc(&p->d_counter, sizeof(unsigned)) != hipSuccess) return fail(RNS_ENOMEM);
+        if (hipMemset(p->d_counter, 0, sizeof(unsigned)) != hipSuccess) return fail(RNS_EDEVICE);
+    }
+    *out = p;
+    return RNS_OK;
+}
+
+extern "C" int rns_gemm_plan_execute(rns_gemm_plan *p, void *stream) {
+    if (!p) return RNS_EINVAL;
+    if (p->nprob == 0) return RNS_OK;
+    RNS_HIP(hipSetDevice(p->ctx->device));
+    return run_plan(p->ctx, p->int8, p->variant, p->d_probs, p->nprob, p->total_tiles,
+                    p->total_units, p->d_counter, (hipStream_t)stream);
+}
+
+extern "C" int rns_gemm_plan_info(const rns_gemm_plan *p, rns_plan_info *info) {
+    if (!p || !info) return RNS_EINVAL;
+    info->path = p->int8 ? RNS_PATH_INT8 : RNS_PATH_FP64;
+    info->variant = p->variant;
+    info->tiles = p->total_tiles;
+    info->workspace_bytes = p->work_bytes;
+    info->residue_ops = p->residue_ops;
+    return RNS_OK;
+}
+
+extern "C" int rns_gemm_plan_set_variant(rns_gemm_plan *p, int variant) {
+    if (!p || variant < 0 || (p->int8 ? variant >= kI8NumVariants : variant != 0)) return RNS_EINVAL;
+    p->variant = variant;
+    return RNS_OK;
+}
+
+// ------------------------------------------------------------- autotuner --
+
+namespace {
+
+void tune_store(rns_ctx *ctx, const std::string &key, int variant) {
+    ctx->tune[key] = variant;
+    if (!ctx->tune_path.empty()) {
+        if (FILE *f = std::fopen(ctx->tune_path.c_str(), "a")) {
+            std::fprintf(f, "%s %d\n", key.c_str(), variant);
+            std::fclose(f);
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int rns_ctx_set_tune_cache(rns_ctx *ctx, const char *path) {
+    if (!ctx) return RNS_EINVAL;
+    std::lock_guard<std::mutex> guard(ctx->mu);
+    ctx->tune_path = path ? path : "";
+    if (ctx->tune_path.empty()) return RNS_OK;
+    if (FILE *f = std::fopen(ctx->tune_path.c_str(), "r")) {
+        char key[256];
+        int v = 0;
+        while (std::fscanf(f, "%255s %d", key, &v) == 2)
+            if (v >= 0 && v < kI8NumVariants) ctx->tune[key] = v;   // later lines win
+        std::fclose(f);
+    }
+    return RNS_OK;
+}
+
+extern "C" int rns_gemm_plan_autotune(rns_gemm_plan *p, void *stream, int *variant_out) {
+    if (!p || !variant_out) return RNS_EINVAL;
+    rns_ctx *ctx = p->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    int best = p->variant, st = RNS_OK;
+    if (p->int8 && p->nprob > 0) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return RNS_EDEVICE;
+        float best_ms = 1e30f;
+        for (int v = 0; v < kI8NumVariants && st == RNS_OK; ++v) {
+            p->variant = v;
+            st = rns_gemm_plan_execute(p, stream);            // warm-up
+            if (st != RNS_OK) break;
+            float tot = 0.f;
+            for (int r = 0; r < 3 && st == RNS_OK; ++r) {
+                float ms = 0.f;
+                if (hipEventRecord(a, s) != hipSuccess) { st = RNS_EDEVICE; break; }
+                st = rns_gemm_plan_execute(p, stream);
+                if (st != RNS_OK) break;
+                if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                    hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+                    st = RNS_EDEVICE;
+                    break;
+                }
+                tot += ms;
+            }
+            if (st == RNS_OK && tot < best_ms) {
+                best_ms = tot;
+                best = v;
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    if (st != RNS_OK) return st;
+    p->variant = best;
+    {
+        std::lock_guard<std::mutex> guard(ctx->mu);
+        tune_store(ctx, p->key, best);
+    }
+    *variant_out = best;
+    return RNS_OK;
+}
+
+extern "C" int rns_autotune(rns_ctx *ctx, const rns_gemm_desc *descs, int count, int path,
+                            void *stream, int *variant_out) {
+    if (!ctx || !variant_out) return RNS_EINVAL;
+    rns_gemm_plan *p = nullptr;
+    int st = rns_gemm_plan_create(ctx, descs, count, path, &p);
+    if (st != RNS_OK) return st;
+    st = rns_gemm_plan_autotune(p, stream, variant_out);
+    rns_gemm_plan_destroy(p);
+    return st;
+}
+
+// ------------------------------------------------- one-shot batched call --
 
 extern "C" int rns_workspace_bytes(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
                                    int path, size_t *bytes) {
     if (!ctx || !bytes || count < 0 || (count > 0 && !descs)) return RNS_EINVAL;
-    const bool int8 = path != RNS_PATH_FP64;
+    bool int8 = true;
     Plan plan;
-    int st = make_plan(ctx, descs, count, int8, plan);
+    int st = make_plan_path(ctx, descs, count, path, int8, plan);
     if (st != RNS_OK) return st;
     *bytes = plan.work_bytes;
     return RNS_OK;
@@ -92,15 +353,10 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
     if (!ctx || count < 0 || (count > 0 && !descs)) return RNS_EINVAL;
     if (path != RNS_PATH_AUTO && path != RNS_PATH_FP64 && path != RNS_PATH_INT8) return RNS_EINVAL;
     if (count == 0) return RNS_OK;
-    bool int8 = path != RNS_PATH_FP64;
     std::lock_guard<std::mutex> guard(ctx->mu);
+    bool int8 = true;
     Plan plan;
-    int st = make_plan(ctx, descs, count, int8, plan);
-    if (st == RNS_EBOUND && path == RNS_PATH_AUTO) {
-        int8 = false;
-        plan = Plan();
-        st = make_plan(ctx, descs, count, int8, plan);
-    }
+    int st = make_plan_path(ctx, descs, count, path, int8, plan);
     if (st != RNS_OK) return st;
     if (plan.probs.empty()) return RNS_OK;
     RNS_HIP(hipSetDevice(ctx->device));
@@ -115,24 +371,11 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
     if (st != RNS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     // The pinned staging buffer may still be read by an earlier copy on this
-    // stream; wait for it before overwriting.
+    // stream; wait for it before overwriting.  (Plans avoid this round trip.)
     RNS_HIP(hipStreamSynchronize(s));
     std::memcpy(ctx->h_desc, plan.probs.data(), tbytes);
     RNS_HIP(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, tbytes, hipMemcpyHostToDevice, s));
-    const GemmProblem *dP = static_cast<const GemmProblem *>(ctx->d_desc);
-    const int np = (int)plan.probs.size();
-    {
-    ProfScope ps(ctx, int8 ? "k_prep_i8" : "k_prep_f64", s);
-    launch_prep(int8, dP, np, plan.total_units, (const PrimeConst *)ctx->d_prime, s);
-    }
-    RNS_HIP(hipGetLastError());
-    {
-    ProfScope ps(ctx, int8 ? "k_gemm_i8" : "k_gemm_f64", s);
-    if (int8)
-        launch_gemm_i8(ctx->int8_kernel, dP, np, plan.total_tiles, (const PrimeConst *)ctx->d_prime, s);
-    else
-        launch_gemm_f64(dP, np, plan.total_tiles, (const PrimeConst *)ctx->d_prime, s);
-    }
-    RNS_HIP(hipGetLastError());
-    return RNS_OK;
+    const int variant = choose_variant(ctx, int8, plan);
+    return run_plan(ctx, int8, variant, static_cast<const GemmProblem *>(ctx->d_desc),
+                    (int)plan.probs.size(), plan.total_tiles, plan.total_units, ctx->d_counter, s);
 }

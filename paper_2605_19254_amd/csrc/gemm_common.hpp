@@ -87,10 +87,13 @@ __device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, i
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Launchers (one per kernel family), all asynchronous on `s`.
+// INT8 GEMM variants (the autotuner chooses among them per shape class).
+enum { kI8Lds = 0, kI8Direct = 1, kI8LdsPersistent = 2, kI8NumVariants = 3 };
+
 void launch_prep(bool int8, const GemmProblem *P, int nprob, int64_t units,
-                 const PrimeConst *pc, hipStream_t s);
+                 const PrimeConst *pc, unsigned *counter, hipStream_t s);
 void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
-                    const PrimeConst *pc, hipStream_t s);
+                    const PrimeConst *pc, unsigned *counter, int num_cus, hipStream_t s);
 void launch_gemm_f64(const GemmProblem *P, int nprob, int64_t tiles, const PrimeConst *pc,
                      hipStream_t s);
 

@@ -14,6 +14,8 @@
 // (2 x 4 blocks of 16 x 16) for all 7 groups, i.e. 224 accumulator registers.
 #include "gemm_common.hpp"
 
+#include <algorithm>
+
 namespace rns {
 namespace gemm {
 namespace {
@@ -141,12 +143,9 @@ __device__ __forceinline__ void plain_barrier() {
     asm volatile("" ::: "memory");
 }
 
-__global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restrict__ P, int nprob,
-                                                     int64_t total_tiles,
-                                                     const PrimeConst *__restrict__ pc) {
-    __shared__ v4i sbuf[2][kI8Frag * 64];
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t >= total_tiles) return;
+__device__ __forceinline__ void i8_lds_tile(const GemmProblem *__restrict__ P, int nprob,
+                                            int64_t t, const PrimeConst *__restrict__ pc,
+                                            v4i (*sbuf)[kI8Frag * 64]) {
     const TileCoord tc = map_tile(P, nprob, t);
     const GemmProblem &g = P[tc.q];
     const int lane = threadIdx.x & 63;
@@ -235,14 +234,47 @@ __global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restri
             }
 }
 
+__global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restrict__ P, int nprob,
+                                                     int64_t total_tiles,
+                                                     const PrimeConst *__restrict__ pc) {
+    __shared__ v4i sbuf[2][kI8Frag * 64];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= total_tiles) return;
+    i8_lds_tile(P, nprob, t, pc, sbuf);
+}
+
+// Persistent form: one work-group per CU takes tiles from a counter in tile
+// order (the host sorts problems by decreasing tile cost, so the longest
+// tiles go first).  The counter is reset by the prep kernel of the same call.
+__global__ __launch_bounds__(256) void k_gemm_i8_lds_persistent(const GemmProblem *__restrict__ P,
+                                                                int nprob, int64_t total_tiles,
+                                                                const PrimeConst *__restrict__ pc,
+                                                                unsigned *__restrict__ counter) {
+    __shared__ v4i sbuf[2][kI8Frag * 64];
+    __shared__ unsigned next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t t = next;
+        __syncthreads();
+        if (t >= total_tiles) break;
+        i8_lds_tile(P, nprob, t, pc, sbuf);
+    }
+}
+
 }  // namespace
 
 void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
-                    const PrimeConst *pc, hipStream_t s) {
-    if (variant == 1)
+                    const PrimeConst *pc, unsigned *counter, int num_cus, hipStream_t s) {
+    if (variant == kI8Direct) {
         hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc);
-    else
+    } else if (variant == kI8LdsPersistent && counter) {
+        const int64_t grid = std::min<int64_t>(tiles, num_cus);
+        hipLaunchKernelGGL(k_gemm_i8_lds_persistent, dim3((unsigned)grid), dim3(256), 0, s, P, nprob,
+                           tiles, pc, counter);
+    } else {
         hipLaunchKernelGGL(k_gemm_i8_lds, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc);
+    }
 }
 
 }  // namespace gemm

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -62,7 +63,11 @@ struct rns_ctx {
     std::map<std::tuple<int, int, int>, rns::LagrangeTable> lagrange;
     std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
     int force_cert_failures = 0;
-    int int8_kernel = 0;               // 0: LDS-staged GEMM, 1: direct-from-L2 GEMM (RNS_INT8_KERNEL)
+    int int8_kernel = -1;              // forced INT8 GEMM variant (RNS_INT8_KERNEL), -1 = tuned
+    int num_cus = 256;
+    unsigned *d_counter = nullptr;     // work counter of persistent launches of modmatmul_batched
+    std::map<std::string, int> tune;   // autotuned INT8 variant per shape class
+    std::string tune_path;
     std::mutex mu;
     // tracing: (kernel name, start event, stop event) per launch
     bool prof = false;

@@ -1,0 +1,167 @@
+// Whole-product plans: reduce -> per-prime products -> CRT for a batch of
+// independent integer products (Section 3.1 end to end), with the residue
+// planes of every operand and result resident in a plan-owned buffer.
+#include "reduce_crt.hpp"
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+using namespace rns;
+
+struct rns_matmul_plan {
+    rns_ctx *ctx = nullptr;
+    int W = 1;
+    bool fast_crt = false;
+    void *d_planes = nullptr;
+    ReduceJob *d_rjobs = nullptr;
+    int nr = 0;
+    int64_t rtiles = 0;
+    CrtJob *d_cjobs = nullptr;
+    int nc = 0;
+    int64_t ctiles = 0;
+    rns_gemm_plan *gemm = nullptr;
+};
+
+extern "C" void rns_matmul_plan_destroy(rns_matmul_plan *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (p->gemm) rns_gemm_plan_destroy(p->gemm);
+    if (p->d_planes) (void)hipFree(p->d_planes);
+    if (p->d_rjobs) (void)hipFree(p->d_rjobs);
+    if (p->d_cjobs) (void)hipFree(p->d_cjobs);
+    delete p;
+}
+
+extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, int count, int path,
+                                      int W, rns_matmul_plan **out) {
+    if (!ctx || !out || count < 0 || (count > 0 && !d)) return RNS_EINVAL;
+    if (W < 1 || W > kCrtMaxW) return RNS_EINVAL;
+    *out = nullptr;
+    // Validate and lay out the resident planes.
+    std::vector<size_t> offA(count), offB(count), offC(count);
+    size_t off = 0;
+    bool all_fast = count > 0;
+    for (int i = 0; i < count; ++i) {
+        const rns_matmul_desc &x = d[i];
+        if (x.m < 0 || x.n < 0 || x.k < 0) return RNS_EINVAL;
+        if (x.L < 1 || x.L > kCrtMaxL || x.prime_begin < 0 || x.prime_begin + x.L > ctx->L)
+            return RNS_EINVAL;
+        if (x.m > 0 && x.n > 0) {
+            if (!x.C || x.ldc < x.n) return RNS_EINVAL;
+            if (x.k > 0 && (!x.A || !x.B || x.lda < x.k || x.ldb < x.n)) return RNS_EINVAL;
+        }
+        auto take = [&](int64_t r, int64_t c) {
+            const size_t at = off;
+            off += ((size_t)x.L * r * c * sizeof(uint32_t) + 255) & ~(size_t)255;
+            return at;
+        };
+        offA[i] = take(x.m, x.k);
+        offB[i] = take(x.k, x.n);
+        offC[i] = take(x.m, x.n);
+        if (!(x.bound > 0 && crt_fast_ok(ctx, x.prime_begin, x.L, &x.bound, 1, W))) all_fast = false;
+    }
+    rns_matmul_plan *p = new (std::nothrow) rns_matmul_plan;
+    if (!p) return RNS_ENOMEM;
+    p->ctx = ctx;
+    p->W = W;
+    p->fast_crt = all_fast;
+    auto fail = [&](int s) { rns_matmul_plan_destroy(p); return s; };
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RNS_EDEVICE);
+    if (hipMalloc(&p->d_planes, std::max<size_t>(off, 256)) != hipSuccess) return fail(RNS_ENOMEM);
+    char *base = static_cast<char *>(p->d_planes);
+
+    std::vector<ReduceJob> rj;
+    std::vector<rns_gemm_desc> gd;
+    std::vector<CrtJob> cj;
+    int64_t rt = 0, ct = 0;
+    for (int i = 0; i < count; ++i) {
+        const rns_matmul_desc &x = d[i];
+        if (x.m == 0 || x.n == 0) continue;
+        uint32_t *A = reinterpret_cast<uint32_t *>(base + offA[i]);
+        uint32_t *B = reinterpret_cast<uint32_t *>(base + offB[i]);
+        uint32_t *C = reinterpret_cast<uint32_t *>(base + offC[i]);
+        if (x.k > 0) {
+            ReduceJob a = make_reduce_job(x.A, x.m, x.k, x.lda, x.prime_begin, x.L, A, x.k, x.m * x.k, rt);
+            rt += reduce_tiles(a);
+            rj.push_back(a);
+            ReduceJob b = make_reduce_job(x.B, x.k, x.n, x.ldb, x.prime_begin, x.L, B, x.n, x.k * x.n, rt);
+            rt += reduce_tiles(b);
+            rj.push_back(b);
+        }
+        rns_gemm_desc g{};
+        g.m = x.m; g.n = x.n; g.k = x.k;
+        g.A = A; g.lda = std::max<int64_t>(x.k, 1); g.a_plane_stride = x.m * x.k;
+        g.B = B; g.ldb = x.n; g.b_plane_stride = x.k * x.n;
+        g.C = C; g.ldc = x.n; g.c_plane_stride = x.m * x.n;
+        g.prime_begin = x.prime_begin; g.L = x.L;
+        gd.push_back(g);
+        CrtJob c{};
+        c.res = C; c.rows = x.m; c.cols = x.n; c.ldr = x.n; c.ps = x.m * x.n;
+        c.prime_begin = x.prime_begin; c.L = x.L; c.out = x.C; c.ldo = x.ldc;
+        c.status = ctx->d_status;
+        c.col_tiles = crt_col_tiles(x.n);
+        c.tile_begin = ct;
+        ct += crt_tiles(x.m, x.n);
+        {
+            std::lock_guard<std::mutex> guard(ctx->mu);
+            if (all_fast) {
+                const LagrangeTable *lt = nullptr;
+                int st = lagrange_table(ctx, x.prime_begin, x.L, W, &lt);
+                if (st != RNS_OK) return fail(st);
+                c.lag_c = lt->d_c; c.lag_mj = lt->d_mj; c.lag_m = lt->d_m;
+            } else {
+                int st = mixed_radix_half(ctx, x.prime_begin, x.L, &c.half);
+                if (st != RNS_OK) return fail(st);
+            }
+        }
+        cj.push_back(c);
+    }
+    int st = rns_gemm_plan_create(ctx, gd.data(), (int)gd.size(), path, &p->gemm);
+    if (st != RNS_OK) return fail(st);
+    p->nr = (int)rj.size();
+    p->rtiles = rt;
+    p->nc = (int)cj.size();
+    p->ctiles = ct;
+    if (p->nr) {
+        if (hipMalloc(&p->d_rjobs, sizeof(ReduceJob) * p->nr) != hipSuccess) return fail(RNS_ENOMEM);
+        if (hipMemcpy(p->d_rjobs, rj.data(), sizeof(ReduceJob) * p->nr, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(RNS_EDEVICE);
+    }
+    if (p->nc) {
+        if (hipMalloc(&p->d_cjobs, sizeof(CrtJob) * p->nc) != hipSuccess) return fail(RNS_ENOMEM);
+        if (hipMemcpy(p->d_cjobs, cj.data(), sizeof(CrtJob) * p->nc, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(RNS_EDEVICE);
+    }
+    *out = p;
+    return RNS_OK;
+}
+
+extern "C" int rns_matmul_plan_execute(rns_matmul_plan *p, void *stream) {
+    if (!p) return RNS_EINVAL;
+    rns_ctx *ctx = p->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    RNS_HIP(hipSetDevice(ctx->device));
+    if (p->nr) {
+        ProfScope ps(ctx, "k_reduce", s);
+        launch_reduce(ReduceJob{}, p->d_rjobs, p->nr, p->rtiles, ctx->d_prime, s);
+    }
+    RNS_HIP(hipGetLastError());
+    int st = rns_gemm_plan_execute(p->gemm, stream);
+    if (st != RNS_OK) return st;
+    if (p->nc) {
+        ProfScope ps(ctx, p->fast_crt ? "k_crt_lagrange" : "k_crt_garner", s);
+        launch_crt(p->fast_crt, p->W, CrtJob{}, p->d_cjobs, p->nc, p->ctiles, ctx->d_prime,
+                   ctx->d_garner, s);
+    }
+    RNS_HIP(hipGetLastError());
+    return RNS_OK;
+}
+
+extern "C" int rns_matmul_plan_info(const rns_matmul_plan *p, rns_plan_info *info) {
+    if (!p || !info) return RNS_EINVAL;
+    return rns_gemm_plan_info(p->gemm, info);
+}
+
+extern "C" rns_gemm_plan *rns_matmul_plan_gemm(rns_matmul_plan *p) { return p ? p->gemm : nullptr; }

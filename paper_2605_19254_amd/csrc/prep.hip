@@ -40,7 +40,10 @@ __device__ __forceinline__ void split_pack(int32_t v, int byte, Digits &o) {
 template <bool kInt8>
 __global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P, int nprob,
                                               int64_t total_units,
-                                              const PrimeConst *__restrict__ pc) {
+                                              const PrimeConst *__restrict__ pc,
+                                              unsigned *__restrict__ counter) {
+    // Reset the work counter of a persistent GEMM launched after this kernel.
+    if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
     const int lane = threadIdx.x & 63;
     const int64_t unit = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (unit >= total_units) return;
@@ -129,12 +132,12 @@ __global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P,
 }  // namespace
 
 void launch_prep(bool int8, const GemmProblem *P, int nprob, int64_t units,
-                 const PrimeConst *pc, hipStream_t s) {
+                 const PrimeConst *pc, unsigned *counter, hipStream_t s) {
     const unsigned blocks = (unsigned)((units + 3) / 4);
     if (int8)
-        hipLaunchKernelGGL(k_prep<true>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc);
+        hipLaunchKernelGGL(k_prep<true>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc, counter);
     else
-        hipLaunchKernelGGL(k_prep<false>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc);
+        hipLaunchKernelGGL(k_prep<false>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc, counter);
 }
 
 }  // namespace gemm

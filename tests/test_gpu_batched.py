@@ -1,0 +1,206 @@
+"""GPU parity of the batched forms: plans over many uneven products, every
+INT8 GEMM variant, whole-product plans with resident residue planes, HIP
+graph capture and replay, and the autotuner's cache.
+
+Expected values come from oracle/ only; inputs from synth."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import native, primes as op, rns as orns
+import synth
+
+pytestmark = pytest.mark.gpu
+
+PRIMES = op.largest_primes_below(1 << 26, 26)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def rg():
+    import paper_2605_19254_amd as rg
+    return rg
+
+
+@pytest.fixture(scope="module")
+def ctx(rg, torch_dev):
+    c = rg.Context(device=0, L=26)
+    yield c
+    c.close()
+
+
+def _uneven_residue_batch(torch, dev, count, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    sizes = synth.uneven_sizes(count, lo, hi, seed)
+    probs, host = [], []
+    for i, n in enumerate(sizes):
+        m, k = max(1, n - 3 * (i % 3)), n + (i % 5)
+        L = 1 + (i % 3)
+        begin = (5 * i) % (26 - L)
+        ps = PRIMES[begin:begin + L]
+        a = np.stack([rng.integers(0, p, size=(m, k)) for p in ps]).astype(np.int32)
+        b = np.stack([rng.integers(0, p, size=(k, n)) for p in ps]).astype(np.int32)
+        c = torch.full((L, m, n), -1, dtype=torch.int32, device=dev)
+        host.append((a, b, ps))
+        probs.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), c, begin))
+    return probs, host
+
+
+def _check_residues(got, a, b, ps):
+    for j, p in enumerate(ps):
+        want = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int32)
+        assert np.array_equal(got[j], want)
+
+
+def test_gemm_plan_all_variants_uneven(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("gemm plan variants")
+    probs, host = _uneven_residue_batch(torch, dev, 24, 5, 300, seed=31)
+    gps = [rg.GemmProblem(a, b, c, bg) for a, b, c, bg in probs]
+    plan = rg.GemmPlan(ctx, gps, path="int8")
+    outs = []
+    for v in (0, 1, 2):
+        for _, _, c, _ in probs:
+            c.fill_(-1)
+        plan.set_variant(v)
+        plan.execute()
+        plan.execute()          # a second run reuses the work counter
+        torch.cuda.synchronize()
+        outs.append([c.cpu().numpy() for _, _, c, _ in probs])
+    for (a, b, ps), got in zip(host, outs[0]):
+        _check_residues(got, a, b, ps)
+    for v in (1, 2):
+        for x, y in zip(outs[0], outs[v]):
+            assert np.array_equal(x, y)
+    info = plan.info()
+    assert info["path"] == "int8" and info["tiles"] > 0
+    plan.close()
+    fplan = rg.GemmPlan(ctx, gps, path="fp64")
+    for _, _, c, _ in probs:
+        c.fill_(-1)
+    fplan.execute()
+    torch.cuda.synchronize()
+    for (_, _, c, _), ref in zip(probs, outs[0]):
+        assert np.array_equal(c.cpu().numpy(), ref)
+    fplan.close()
+
+
+def test_gemm_plan_empty_and_zero_sized(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("gemm plan empty")
+    plan = rg.GemmPlan(ctx, [], path="int8")
+    plan.execute()
+    a = torch.empty((1, 0, 4), dtype=torch.int32, device=dev)
+    b = torch.empty((1, 4, 3), dtype=torch.int32, device=dev)
+    c = torch.empty((1, 0, 3), dtype=torch.int32, device=dev)
+    plan2 = rg.GemmPlan(ctx, [rg.GemmProblem(a, b, c)], path="int8")
+    plan2.execute()
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("with_bound", [True, False])
+def test_matmul_plan_uneven_batch(ctx, rg, torch_dev, with_bound):
+    torch, dev = torch_dev
+    _say("matmul plan", with_bound)
+    batch = synth.uneven_batch(count=20, lo=8, hi=200, bound=1 << 16, seed=41)
+    probs = []
+    for i, pr in enumerate(batch):
+        A = torch.from_numpy(pr.a).to(dev)
+        B = torch.from_numpy(pr.b).to(dev)
+        C = torch.empty((pr.m, pr.n), dtype=torch.int64, device=dev)
+        bound = pr.k << 32 if with_bound else 0
+        probs.append(rg.MatmulProblem(A, B, C, prime_begin=i % 3, L=2, bound=bound))
+    plan = rg.MatmulPlan(ctx, probs, path="int8", W=1)
+    plan.execute()
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for pr, p in zip(batch, probs):
+        assert np.array_equal(p.C.cpu().numpy(), native.exact_matmul(pr.a, pr.b))
+    # alone equals in the batch
+    single = rg.MatmulProblem(probs[3].A, probs[3].B, torch.empty_like(probs[3].C), prime_begin=0, L=2,
+                              bound=probs[3].bound)
+    p1 = rg.MatmulPlan(ctx, [single], path="int8")
+    p1.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(single.C, probs[3].C)
+    plan.close()
+    p1.close()
+
+
+def test_matmul_plan_graph_replay(ctx, rg, torch_dev):
+    """Capture the whole product (reduce, prep, GEMM, CRT) into a HIP graph and
+    replay it several times with eager work in between; every replay must equal
+    the eager result for the current inputs."""
+    torch, dev = torch_dev
+    _say("graph replay")
+    batch = synth.uneven_batch(count=12, lo=16, hi=160, bound=1 << 16, seed=51)
+    probs = []
+    for pr in batch:
+        probs.append(rg.MatmulProblem(torch.from_numpy(pr.a).to(dev), torch.from_numpy(pr.b).to(dev),
+                                      torch.empty((pr.m, pr.n), dtype=torch.int64, device=dev),
+                                      prime_begin=0, L=2, bound=pr.k << 32))
+    want = [native.exact_matmul(pr.a, pr.b) for pr in batch]
+    for variant in (0, 2):
+        plan = rg.MatmulPlan(ctx, probs, path="int8")
+        plan.set_variant(variant)
+        plan.execute()                       # warm-up outside the capture
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.execute()
+        torch.cuda.synchronize()
+        sign = 1
+        for rep in range(4):                 # 4 flips: inputs end as they began
+            for p in probs:                  # eager work between replays
+                p.A.mul_(-1)
+                p.C.fill_(7)
+            sign = -sign
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for w, p in zip(want, probs):
+                assert np.array_equal(p.C.cpu().numpy(), sign * w), (variant, rep)
+        del g
+        plan.close()
+    assert ctx.status() == 0
+
+
+def test_autotune_and_cache(ctx, rg, torch_dev):
+    torch, dev = torch_dev
+    _say("autotune")
+    probs, host = _uneven_residue_batch(torch, dev, 6, 64, 400, seed=61)
+    gps = [rg.GemmProblem(a, b, c, bg) for a, b, c, bg in probs]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        ctx.set_tune_cache(path)
+        v = rg.autotune(ctx, gps, path="int8")
+        assert v in (0, 1, 2)
+        torch.cuda.synchronize()
+        for (a, b, ps), (_, _, c, _) in zip(host, probs):
+            _check_residues(c.cpu().numpy(), a, b, ps)
+        text = open(path).read().split()
+        assert text[-1] == str(v) and text[-2].startswith("gfx950/int8/")
+        c2 = rg.Context(device=0, L=26)
+        c2.set_tune_cache(path)
+        plan = rg.GemmPlan(c2, gps, path="int8")
+        assert plan.info()["variant"] == v
+        plan.close()
+        c2.close()
+        ctx.set_tune_cache("")
