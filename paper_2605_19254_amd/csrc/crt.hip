@@ -33,9 +33,18 @@ namespace {
 
 constexpr int kBlock = 128;
 
-__device__ __forceinline__ double modp(double x, const PrimeConst &P) {
+struct PC2 {
+    double pf, pinv;
+};
+
+__device__ __forceinline__ double modp(double x, const PC2 &P) {
     return fma(-rint(x * P.pinv), P.pf, x);                 // |result| <= (p+1)/2
 }
+
+// With a job table, blocks take runs of `chunk` consecutive tiles; the job of a
+// run's first tile is found by binary search and later tiles advance the job
+// index linearly.  A single job uses runs of one tile.
+constexpr int kChunk = 8;
 
 __device__ __forceinline__ int find_job(const CrtJob *jobs, int njobs, int64_t t) {
     int lo = 0, hi = njobs - 1;
@@ -50,26 +59,37 @@ template <int WT>
 __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob *__restrict__ jobs,
                                                       int njobs, int64_t total_tiles,
                                                       const PrimeConst *__restrict__ pc_all,
-                                                      const double *__restrict__ garner_all, int W) {
+                                                      const double *__restrict__ garner_all, int W,
+                                                      int chunk) {
     __shared__ uint32_t vd[kCrtMaxL][kBlock];
     const int tid = threadIdx.x;
-    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-        const CrtJob &J = njobs > 0 ? jobs[find_job(jobs, njobs, t)] : job0;
+    const int64_t nchunks = (total_tiles + chunk - 1) / chunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+      const int64_t t0 = ch * chunk;
+      const int64_t t1 = t0 + chunk < total_tiles ? t0 + chunk : total_tiles;
+      int qj = njobs > 0 ? find_job(jobs, njobs, t0) : 0;
+      for (int64_t t = t0; t < t1; ++t) {
+        if (njobs > 0)
+            while (qj + 1 < njobs && jobs[qj + 1].tile_begin <= t) ++qj;
+        // The job index is the same on every lane; saying so lets the job and
+        // the per-prime constants come through scalar loads.
+        qj = __builtin_amdgcn_readfirstlane(qj);
+        const CrtJob J = njobs > 0 ? jobs[qj] : job0;
         const int64_t u = t - J.tile_begin;
         const int64_t i = u / J.col_tiles;
         const int64_t c = (u - i * J.col_tiles) * kBlock + tid;
         if (c >= J.cols) continue;
-        const uint32_t *src = J.res + i * J.ldr + c;
-        const PrimeConst *pc = pc_all + J.prime_begin;
-        const double *garner = garner_all + (int64_t)J.prime_begin * kCrtMaxL;
-        const uint32_t *half = J.half;
+        const auto src = gptr(J.res + i * J.ldr + c);
+        const auto pc = gptr(pc_all + J.prime_begin);
+        const auto garner = gptr(garner_all + (int64_t)J.prime_begin * kCrtMaxL);
+        const auto half = gptr(J.half);
         const int L = J.L;
         const int64_t ps = J.ps;
         // Garner digits.
         for (int j = 0; j < L; ++j) {
-            const PrimeConst P = pc[j];
+            const PC2 P{pc[j].pf, pc[j].pinv};
             double tj = (double)src[(int64_t)j * ps];
-            const double *gj = garner + (int64_t)j * kCrtMaxL;
+            const auto gj = garner + (int64_t)j * kCrtMaxL;
             for (int q = 0; q < j; ++q) {
                 const double x = (tj - (double)vd[q][tid]) * gj[j - q];
                 tj = modp(x, P);
@@ -132,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
         else fits = high_zero && ((top >> 63) == 0 || (top == (1ull << 63) && low_zero));
         if (!fits) atomicOr(J.status, 1);
         // Two's complement of the signed value, low W words.
-        uint64_t *dst = J.out + (i * J.ldo + c) * W;
+        const auto dst = gptr_w(J.out + (i * J.ldo + c) * W);
         uint64_t carry = 1;
 #pragma unroll
         for (int k = 0; k < WT; ++k) {
@@ -146,24 +166,36 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
                 dst[k] = v;
             }
         }
+      }
     }
 }
 
 template <int WT>
 __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJob *__restrict__ jobs,
                                                         int njobs, int64_t total_tiles,
-                                                        const PrimeConst *__restrict__ pc_all, int W) {
-    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-        const CrtJob &J = njobs > 0 ? jobs[find_job(jobs, njobs, t)] : job0;
+                                                        const PrimeConst *__restrict__ pc_all, int W,
+                                                        int chunk) {
+    const int64_t nchunks = (total_tiles + chunk - 1) / chunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+      const int64_t t0 = ch * chunk;
+      const int64_t t1 = t0 + chunk < total_tiles ? t0 + chunk : total_tiles;
+      int qj = njobs > 0 ? find_job(jobs, njobs, t0) : 0;
+      for (int64_t t = t0; t < t1; ++t) {
+        if (njobs > 0)
+            while (qj + 1 < njobs && jobs[qj + 1].tile_begin <= t) ++qj;
+        // The job index is the same on every lane; saying so lets the job and
+        // the per-prime constants come through scalar loads.
+        qj = __builtin_amdgcn_readfirstlane(qj);
+        const CrtJob J = njobs > 0 ? jobs[qj] : job0;
         const int64_t u = t - J.tile_begin;
         const int64_t i = u / J.col_tiles;
         const int64_t c = (u - i * J.col_tiles) * kBlock + threadIdx.x;
         if (c >= J.cols) continue;
-        const uint32_t *src = J.res + i * J.ldr + c;
-        const PrimeConst *pc = pc_all + J.prime_begin;
-        const double *cinv = J.lag_c;
-        const uint64_t *mj = J.lag_mj;
-        const uint64_t *mw = J.lag_m;
+        const auto src = gptr(J.res + i * J.ldr + c);
+        const auto pc = gptr(pc_all + J.prime_begin);
+        const auto cinv = gptr(J.lag_c);
+        const auto mj = gptr(J.lag_mj);
+        const auto mw = gptr(J.lag_m);
         const int L = J.L;
         const int64_t ps = J.ps;
         uint64_t x[WT];
@@ -171,12 +203,12 @@ __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJ
         for (int k = 0; k < WT; ++k) x[k] = 0;
         double alpha = 0.0;
         for (int j = 0; j < L; ++j) {
-            const PrimeConst P = pc[j];
+            const PC2 P{pc[j].pf, pc[j].pinv};
             double y = modp((double)src[(int64_t)j * ps] * cinv[j], P);
             y = y < 0.0 ? y + P.pf : y;
             alpha = fma(y, P.pinv, alpha);
             const uint64_t yi = (uint64_t)y;
-            const uint64_t *m = mj + (int64_t)j * W;
+            const auto m = mj + (int64_t)j * W;
             uint64_t carry = 0;
 #pragma unroll
             for (int k = 0; k < WT; ++k) {
@@ -210,10 +242,11 @@ __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJ
                 borrow = b1 + b2;
             }
         }
-        uint64_t *dst = J.out + (i * J.ldo + c) * W;
+        const auto dst = gptr_w(J.out + (i * J.ldo + c) * W);
 #pragma unroll
         for (int k = 0; k < WT; ++k)
             if (k < W) dst[k] = x[k];
+      }
     }
 }
 
@@ -292,10 +325,11 @@ bool crt_fast_ok(const rns_ctx *ctx, int begin, int L, const uint64_t *bound_wor
 
 void launch_crt(bool fast, int W, const CrtJob &job0, const CrtJob *jobs, int njobs,
                 int64_t total_tiles, const PrimeConst *pc, const double *garner, hipStream_t s) {
-    const unsigned grid = (unsigned)std::min<int64_t>(total_tiles, 1 << 20);
+    const int chunk = njobs > 1 ? kChunk : 1;
+    const unsigned grid = (unsigned)std::min<int64_t>((total_tiles + chunk - 1) / chunk, 1 << 20);
     if (fast) {
 #define RNS_LAG(WT_) \
-    hipLaunchKernelGGL(k_crt_lagrange<WT_>, dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, W)
+    hipLaunchKernelGGL(k_crt_lagrange<WT_>, dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, W, chunk)
         if (W <= 1) RNS_LAG(1);
         else if (W <= 2) RNS_LAG(2);
         else if (W <= 4) RNS_LAG(4);
@@ -305,7 +339,7 @@ void launch_crt(bool fast, int W, const CrtJob &job0, const CrtJob *jobs, int nj
 #undef RNS_LAG
     } else {
 #define RNS_GAR(WT_) \
-    hipLaunchKernelGGL(k_crt_garner<WT_>, dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, garner, W)
+    hipLaunchKernelGGL(k_crt_garner<WT_>, dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, garner, W, chunk)
         if (W <= 1) RNS_GAR(1);
         else if (W <= 2) RNS_GAR(2);
         else if (W <= 4) RNS_GAR(4);

@@ -135,7 +135,7 @@ int choose_variant(rns_ctx *ctx, bool int8, const Plan &plan) {
 }
 
 int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np, int64_t tiles,
-             int64_t units, unsigned *counter, hipStream_t s) {
+             int64_t units, const int32_t *tile_prob, unsigned *counter, hipStream_t s) {
     const bool persistent = int8 && variant == kI8LdsPersistent;
     {
         ProfScope ps(ctx, int8 ? "k_prep_i8" : "k_prep_f64", s);
@@ -146,10 +146,10 @@ int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np
     {
         ProfScope ps(ctx, int8 ? "k_gemm_i8" : "k_gemm_f64", s);
         if (int8)
-            launch_gemm_i8(variant, dP, np, tiles, (const PrimeConst *)ctx->d_prime, counter,
-                           ctx->num_cus, s);
+            launch_gemm_i8(variant, dP, np, tiles, (const PrimeConst *)ctx->d_prime, tile_prob,
+                           counter, ctx->num_cus, s);
         else
-            launch_gemm_f64(dP, np, tiles, (const PrimeConst *)ctx->d_prime, s);
+            launch_gemm_f64(dP, np, tiles, (const PrimeConst *)ctx->d_prime, tile_prob, s);
     }
     RNS_HIP(hipGetLastError());
     return RNS_OK;
@@ -169,6 +169,7 @@ struct rns_gemm_plan {
     double residue_ops = 0;
     std::string key;
     GemmProblem *d_probs = nullptr;
+    int32_t *d_tile_prob = nullptr;
     void *d_work = nullptr;
     unsigned *d_counter = nullptr;
 };
@@ -178,6 +179,7 @@ extern "C" void rns_gemm_plan_destroy(rns_gemm_plan *p) {
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
     if (p->d_probs) (void)hipFree(p->d_probs);
+    if (p->d_tile_prob) (void)hipFree(p->d_tile_prob);
     if (p->d_work) (void)hipFree(p->d_work);
     if (p->d_counter) (void)hipFree(p->d_counter);
     delete p;
@@ -218,6 +220,17 @@ extern "C" int rns_gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, in
         if (hipMalloc(&p->d_probs, tbytes) != hipSuccess) return fail(RNS_ENOMEM);
         if (hipMemcpy(p->d_probs, plan.probs.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess)
             return fail(RNS_EDEVICE);
+        if (p->nprob > 1) {
+            std::vector<int32_t> tp((size_t)plan.total_tiles);
+            for (int q = 0; q < p->nprob; ++q) {
+                const int64_t end = q + 1 < p->nprob ? plan.probs[q + 1].tile_begin : plan.total_tiles;
+                for (int64_t t = plan.probs[q].tile_begin; t < end; ++t) tp[(size_t)t] = q;
+            }
+            if (hipMalloc(&p->d_tile_prob, tp.size() * sizeof(int32_t)) != hipSuccess) return fail(RNS_ENOMEM);
+            if (hipMemcpy(p->d_tile_prob, tp.data(), tp.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                hipSuccess)
+                return fail(RNS_EDEVICE);
+        }
         if (hipMalloc(&p->d_counter, sizeof(unsigned)) != hipSuccess) return fail(RNS_ENOMEM);
         if (hipMemset(p->d_counter, 0, sizeof(unsigned)) != hipSuccess) return fail(RNS_EDEVICE);
     }
@@ -230,7 +243,7 @@ extern "C" int rns_gemm_plan_execute(rns_gemm_plan *p, void *stream) {
     if (p->nprob == 0) return RNS_OK;
     RNS_HIP(hipSetDevice(p->ctx->device));
     return run_plan(p->ctx, p->int8, p->variant, p->d_probs, p->nprob, p->total_tiles,
-                    p->total_units, p->d_counter, (hipStream_t)stream);
+                    p->total_units, p->d_tile_prob, p->d_counter, (hipStream_t)stream);
 }
 
 extern "C" int rns_gemm_plan_info(const rns_gemm_plan *p, rns_plan_info *info) {
@@ -377,5 +390,6 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
     RNS_HIP(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, tbytes, hipMemcpyHostToDevice, s));
     const int variant = choose_variant(ctx, int8, plan);
     return run_plan(ctx, int8, variant, static_cast<const GemmProblem *>(ctx->d_desc),
-                    (int)plan.probs.size(), plan.total_tiles, plan.total_units, ctx->d_counter, s);
+                    (int)plan.probs.size(), plan.total_tiles, plan.total_units, nullptr,
+                    ctx->d_counter, s);
 }

@@ -63,9 +63,12 @@ struct TileCoord {
     int q, plane, tm, tn;
 };
 
-__device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, int64_t t) {
+// tile_prob (optional): the problem index of every tile, built by plans so
+// that a batch of many problems needs one load instead of a search per tile.
+__device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, int64_t t,
+                                              const int32_t *tile_prob) {
     TileCoord c;
-    c.q = find_problem(P, nprob, t, &GemmProblem::tile_begin);
+    c.q = tile_prob ? tile_prob[t] : find_problem(P, nprob, t, &GemmProblem::tile_begin);
     const GemmProblem &g = P[c.q];
     int64_t u = t - g.tile_begin;
     const int64_t per_plane = (int64_t)g.tm * g.tn;
@@ -93,9 +96,10 @@ enum { kI8Lds = 0, kI8Direct = 1, kI8LdsPersistent = 2, kI8NumVariants = 3 };
 void launch_prep(bool int8, const GemmProblem *P, int nprob, int64_t units,
                  const PrimeConst *pc, unsigned *counter, hipStream_t s);
 void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
-                    const PrimeConst *pc, unsigned *counter, int num_cus, hipStream_t s);
+                    const PrimeConst *pc, const int32_t *tile_prob, unsigned *counter,
+                    int num_cus, hipStream_t s);
 void launch_gemm_f64(const GemmProblem *P, int nprob, int64_t tiles, const PrimeConst *pc,
-                     hipStream_t s);
+                     const int32_t *tile_prob, hipStream_t s);
 
 }  // namespace gemm
 }  // namespace rns

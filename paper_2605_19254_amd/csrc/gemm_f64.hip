@@ -22,10 +22,11 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProblem *__restrict__ P, int nprob,
                                                   int64_t total_tiles,
-                                                  const PrimeConst *__restrict__ pc) {
+                                                  const PrimeConst *__restrict__ pc,
+        const int32_t *__restrict__ tile_prob) {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     if (t >= total_tiles) return;
-    const TileCoord tc = map_tile(P, nprob, t);
+    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
     const GemmProblem &g = P[tc.q];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -107,8 +108,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProblem *__restrict_
 }  // namespace
 
 void launch_gemm_f64(const GemmProblem *P, int nprob, int64_t tiles, const PrimeConst *pc,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc);
+                     const int32_t *tile_prob, hipStream_t s) {
+    hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
 }
 
 }  // namespace gemm

@@ -24,10 +24,11 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_gemm_i8(const GemmProblem *__restrict__ P, int nprob,
                                                  int64_t total_tiles,
-                                                 const PrimeConst *__restrict__ pc) {
+                                                 const PrimeConst *__restrict__ pc,
+        const int32_t *__restrict__ tile_prob) {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     if (t >= total_tiles) return;
-    const TileCoord tc = map_tile(P, nprob, t);
+    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
     const GemmProblem &g = P[tc.q];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -145,8 +146,9 @@ __device__ __forceinline__ void plain_barrier() {
 
 __device__ __forceinline__ void i8_lds_tile(const GemmProblem *__restrict__ P, int nprob,
                                             int64_t t, const PrimeConst *__restrict__ pc,
+                                            const int32_t *__restrict__ tile_prob,
                                             v4i (*sbuf)[kI8Frag * 64]) {
-    const TileCoord tc = map_tile(P, nprob, t);
+    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
     const GemmProblem &g = P[tc.q];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -236,11 +238,12 @@ __device__ __forceinline__ void i8_lds_tile(const GemmProblem *__restrict__ P, i
 
 __global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restrict__ P, int nprob,
                                                      int64_t total_tiles,
-                                                     const PrimeConst *__restrict__ pc) {
+                                                     const PrimeConst *__restrict__ pc,
+        const int32_t *__restrict__ tile_prob) {
     __shared__ v4i sbuf[2][kI8Frag * 64];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     if (t >= total_tiles) return;
-    i8_lds_tile(P, nprob, t, pc, sbuf);
+    i8_lds_tile(P, nprob, t, pc, tile_prob, sbuf);
 }
 
 // Persistent form: one work-group per CU takes tiles from a counter in tile
@@ -249,31 +252,33 @@ __global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restri
 __global__ __launch_bounds__(256) void k_gemm_i8_lds_persistent(const GemmProblem *__restrict__ P,
                                                                 int nprob, int64_t total_tiles,
                                                                 const PrimeConst *__restrict__ pc,
+                                                                const int32_t *__restrict__ tile_prob,
                                                                 unsigned *__restrict__ counter) {
     __shared__ v4i sbuf[2][kI8Frag * 64];
     __shared__ unsigned next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
         __syncthreads();
-        const int64_t t = next;
+        const int64_t t = __builtin_amdgcn_readfirstlane((int)next);   // uniform tile index
         __syncthreads();
         if (t >= total_tiles) break;
-        i8_lds_tile(P, nprob, t, pc, sbuf);
+        i8_lds_tile(P, nprob, t, pc, tile_prob, sbuf);
     }
 }
 
 }  // namespace
 
 void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
-                    const PrimeConst *pc, unsigned *counter, int num_cus, hipStream_t s) {
+                    const PrimeConst *pc, const int32_t *tile_prob, unsigned *counter,
+                    int num_cus, hipStream_t s) {
     if (variant == kI8Direct) {
-        hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc);
+        hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
     } else if (variant == kI8LdsPersistent && counter) {
         const int64_t grid = std::min<int64_t>(tiles, num_cus);
         hipLaunchKernelGGL(k_gemm_i8_lds_persistent, dim3((unsigned)grid), dim3(256), 0, s, P, nprob,
-                           tiles, pc, counter);
+                           tiles, pc, tile_prob, counter);
     } else {
-        hipLaunchKernelGGL(k_gemm_i8_lds, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc);
+        hipLaunchKernelGGL(k_gemm_i8_lds, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
     }
 }
 

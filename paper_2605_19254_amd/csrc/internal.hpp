@@ -33,6 +33,18 @@ struct PrimeConst {
     uint32_t half;    // (p-1)/2: residues above it are negative in balanced form
 };
 
+// Pointers read from job or problem tables are generic (flat) to the
+// compiler; these casts state that they point to global memory, so that
+// uniform reads become scalar loads and the others global (not flat) loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gptr(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr_w(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Garner band: for a prime index j and a distance d in [1, kCrtMaxL),
 // garner[j*kCrtMaxL + d] = p_{j-d}^{-1} mod p_j (as a double), 0 where j < d.
 

@@ -20,6 +20,8 @@ namespace rns {
 namespace gemm {
 namespace {
 
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
 struct Digits {
     uint32_t d[4];
 };
@@ -38,17 +40,8 @@ __device__ __forceinline__ void split_pack(int32_t v, int byte, Digits &o) {
 }
 
 template <bool kInt8>
-__global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P, int nprob,
-                                              int64_t total_units,
-                                              const PrimeConst *__restrict__ pc,
-                                              unsigned *__restrict__ counter) {
-    // Reset the work counter of a persistent GEMM launched after this kernel.
-    if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
-    const int lane = threadIdx.x & 63;
-    const int64_t unit = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (unit >= total_units) return;
-    const int q = find_problem(P, nprob, unit, &GemmProblem::unitA_begin);
-    const GemmProblem &g = P[q];
+__device__ __forceinline__ void prep_unit(const GemmProblem &g, int64_t unit, int lane,
+                                          const PrimeConst *__restrict__ pc) {
     const bool isB = unit >= g.unitB_begin;
     int64_t u = unit - (isB ? g.unitB_begin : g.unitA_begin);
     const int32_t nblk = isB ? g.CB : g.RB;
@@ -61,7 +54,7 @@ __global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P,
     const uint32_t half = (p - 1) / 2;
     const int row = blk * 16 + (lane & 15);
     const int rows_valid = isB ? g.n : g.m;
-    const uint32_t *src = isB ? g.B + (int64_t)plane * g.bps : g.A + (int64_t)plane * g.aps;
+    const auto src = gptr(isB ? g.B + (int64_t)plane * g.bps : g.A + (int64_t)plane * g.aps);
     const int64_t ld = isB ? g.ldb : g.lda;
     const bool interior = (blk + 1) * 16 <= rows_valid && (kt + 1) * 64 <= g.k;
     auto bal = [&](uint32_t r) -> int32_t { return r > half ? (int32_t)r - (int32_t)p : (int32_t)r; };
@@ -69,27 +62,27 @@ __global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P,
         if (row >= rows_valid || kk >= g.k) return 0;
         return bal(isB ? src[(int64_t)kk * ld + row] : src[(int64_t)row * ld + kk]);
     };
-    char *dst = isB ? g.Bt + (int64_t)plane * g.b_plane_bytes : g.At + (int64_t)plane * g.a_plane_bytes;
+    const auto dst = gptr_w(isB ? g.Bt + (int64_t)plane * g.b_plane_bytes : g.At + (int64_t)plane * g.a_plane_bytes);
     if constexpr (kInt8) {
         const int k0 = kt * 64 + (lane >> 4) * 16;
         int32_t v[16];
         if (interior) {
-            if (!isB && (ld & 3) == 0 && ((uintptr_t)src & 15) == 0) {
-                const uint4 *s4 = reinterpret_cast<const uint4 *>(src + (int64_t)row * ld + k0);
+            if (!isB && (ld & 3) == 0 && ((uintptr_t)(isB ? g.B : g.A) & 15) == 0 && ((plane * (isB ? g.bps : g.aps)) & 3) == 0) {
+                const auto s4 = reinterpret_cast<const __attribute__((address_space(1))) v4u *>(src + (int64_t)row * ld + k0);
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
-                    const uint4 x = s4[w];
-                    v[4 * w + 0] = bal(x.x);
-                    v[4 * w + 1] = bal(x.y);
-                    v[4 * w + 2] = bal(x.z);
-                    v[4 * w + 3] = bal(x.w);
+                    const v4u x = s4[w];
+                    v[4 * w + 0] = bal(x[0]);
+                    v[4 * w + 1] = bal(x[1]);
+                    v[4 * w + 2] = bal(x[2]);
+                    v[4 * w + 3] = bal(x[3]);
                 }
             } else if (!isB) {
-                const uint32_t *s1 = src + (int64_t)row * ld + k0;
+                const auto s1 = src + (int64_t)row * ld + k0;
 #pragma unroll
                 for (int t = 0; t < 16; ++t) v[t] = bal(s1[t]);
             } else {
-                const uint32_t *s1 = src + (int64_t)k0 * ld + row;
+                const auto s1 = src + (int64_t)k0 * ld + row;
 #pragma unroll
                 for (int t = 0; t < 16; ++t) v[t] = bal(s1[(int64_t)t * ld]);
             }
@@ -104,14 +97,14 @@ __global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P,
 #pragma unroll
             for (int b = 0; b < 4; ++b) split_pack(v[4 * w + b], b, dg[w]);
         }
-        v4i *out = reinterpret_cast<v4i *>(dst) + ((int64_t)blk * g.KT + kt) * 256;
+        const auto out = reinterpret_cast<__attribute__((address_space(1))) v4i *>(dst) + ((int64_t)blk * g.KT + kt) * 256;
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             v4i t = {(int)dg[0].d[d], (int)dg[1].d[d], (int)dg[2].d[d], (int)dg[3].d[d]};
             out[d * 64 + lane] = t;
         }
     } else {
-        double *out = reinterpret_cast<double *>(dst) + ((int64_t)blk * g.KT + kt) * 1024;
+        const auto out = reinterpret_cast<__attribute__((address_space(1))) double *>(dst) + ((int64_t)blk * g.KT + kt) * 1024;
         const int kl = kt * 64 + (lane >> 4);
         if (interior) {
             double vals[16];
@@ -129,15 +122,43 @@ __global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P,
     }
 }
 
+// With several problems each wave converts kUnitsPerWave consecutive tiles; the
+// problem of the first is found by binary search and later ones advance
+// linearly.  A single problem uses one tile per wave.
+constexpr int kUnitsPerWave = 4;
+
+template <bool kInt8>
+__global__ __launch_bounds__(256) void k_prep(const GemmProblem *__restrict__ P, int nprob,
+                                              int64_t total_units,
+                                              const PrimeConst *__restrict__ pc,
+                                              unsigned *__restrict__ counter, int per_wave) {
+    // Reset the work counter of a persistent GEMM launched after this kernel.
+    if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+    const int lane = threadIdx.x & 63;
+    // The wave index is uniform within a wave; saying so keeps the problem
+    // table reads scalar.
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t u0 = ((int64_t)blockIdx.x * 4 + wave) * per_wave;
+    if (u0 >= total_units) return;
+    int q = find_problem(P, nprob, u0, &GemmProblem::unitA_begin);
+    for (int r = 0; r < per_wave; ++r) {
+        const int64_t unit = u0 + r;
+        if (unit >= total_units) break;
+        while (q + 1 < nprob && P[q + 1].unitA_begin <= unit) ++q;
+        prep_unit<kInt8>(P[q], unit, lane, pc);
+    }
+}
+
 }  // namespace
 
 void launch_prep(bool int8, const GemmProblem *P, int nprob, int64_t units,
                  const PrimeConst *pc, unsigned *counter, hipStream_t s) {
-    const unsigned blocks = (unsigned)((units + 3) / 4);
+    const int per_wave = nprob > 1 ? kUnitsPerWave : 1;
+    const unsigned blocks = (unsigned)((units + 4 * per_wave - 1) / (4 * per_wave));
     if (int8)
-        hipLaunchKernelGGL(k_prep<true>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc, counter);
+        hipLaunchKernelGGL(k_prep<true>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc, counter, per_wave);
     else
-        hipLaunchKernelGGL(k_prep<false>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc, counter);
+        hipLaunchKernelGGL(k_prep<false>, dim3(blocks), dim3(256), 0, s, P, nprob, units, pc, counter, per_wave);
 }
 
 }  // namespace gemm

@@ -22,37 +22,51 @@ namespace {
 
 constexpr int kTile = 256;
 
+// With a job table, each block takes runs of `chunk` consecutive tiles (tile =
+// up to 256 entries of one row of one job); the job of the first tile is found
+// by binary search and later tiles advance the job index linearly.  A single
+// job uses runs of one tile.
+constexpr int kChunk = 8;
+
 __global__ __launch_bounds__(kTile) void k_reduce(ReduceJob job0, const ReduceJob *__restrict__ jobs,
                                                   int njobs, int64_t total_tiles,
-                                                  const PrimeConst *__restrict__ pc_all) {
-    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+                                                  const PrimeConst *__restrict__ pc_all, int chunk) {
+    const int64_t nchunks = (total_tiles + chunk - 1) / chunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t t0 = ch * chunk;
+        const int64_t t1 = t0 + chunk < total_tiles ? t0 + chunk : total_tiles;
         int q = 0;
         if (njobs > 0) {
             int lo = 0, hi = njobs - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+                if (jobs[mid].tile_begin <= t0) lo = mid; else hi = mid - 1;
             }
             q = lo;
         }
-        const ReduceJob &J = njobs > 0 ? jobs[q] : job0;
-        const int64_t u = t - J.tile_begin;
-        const int64_t i = u / J.col_tiles;
-        const int64_t c = (u - i * J.col_tiles) * kTile + threadIdx.x;
-        if (c >= J.cols) continue;
-        const int64_t v = J.x[i * J.ldx + c];
-        const double a0 = (double)(int32_t)(v & 0x1FFFFF);
-        const double a1 = (double)(int32_t)((v >> 21) & 0x1FFFFF);
-        const double a2 = (double)(int32_t)(v >> 42);
-        uint32_t *dst = J.res + i * J.ldr + c;
-        const PrimeConst *pc = pc_all + J.prime_begin;
-        for (int j = 0; j < J.L; ++j) {
-            const PrimeConst &P = pc[j];
-            const double s = fma(a2, P.c42, fma(a1, P.c21, a0));
-            const double q2 = rint(s * P.pinv);
-            double r = fma(-q2, P.pf, s);
-            r = r < 0.0 ? r + P.pf : r;
-            dst[(int64_t)j * J.ps] = (uint32_t)r;
+        for (int64_t t = t0; t < t1; ++t) {
+            if (njobs > 0)
+                while (q + 1 < njobs && jobs[q + 1].tile_begin <= t) ++q;
+            q = __builtin_amdgcn_readfirstlane(q);   // uniform: scalar loads of the job
+            const ReduceJob J = njobs > 0 ? jobs[q] : job0;
+            const int64_t u = t - J.tile_begin;
+            const int64_t i = u / J.col_tiles;
+            const int64_t c = (u - i * J.col_tiles) * kTile + threadIdx.x;
+            if (c >= J.cols) continue;
+            const int64_t v = *gptr(J.x + i * J.ldx + c);
+            const double a0 = (double)(int32_t)(v & 0x1FFFFF);
+            const double a1 = (double)(int32_t)((v >> 21) & 0x1FFFFF);
+            const double a2 = (double)(int32_t)(v >> 42);
+            const auto dst = gptr_w(J.res + i * J.ldr + c);
+            const auto pc = gptr(pc_all + J.prime_begin);
+            for (int j = 0; j < J.L; ++j) {
+                const auto &P = pc[j];
+                const double s = fma(a2, P.c42, fma(a1, P.c21, a0));
+                const double q2 = rint(s * P.pinv);
+                double r = fma(-q2, P.pf, s);
+                r = r < 0.0 ? r + P.pf : r;
+                dst[(int64_t)j * J.ps] = (uint32_t)r;
+            }
         }
     }
 }
@@ -87,9 +101,11 @@ int64_t reduce_tiles(const ReduceJob &j) { return j.rows * j.col_tiles; }
 
 void launch_reduce(const ReduceJob &job0, const ReduceJob *jobs, int njobs, int64_t total_tiles,
                    const PrimeConst *pc, hipStream_t s) {
-    const int64_t grid = total_tiles < (1 << 20) ? total_tiles : (1 << 20);
+    const int chunk = njobs > 1 ? kChunk : 1;
+    const int64_t nchunks = (total_tiles + chunk - 1) / chunk;
+    const int64_t grid = nchunks < (1 << 20) ? nchunks : (1 << 20);
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)grid), dim3(kTile), 0, s, job0, jobs, njobs,
-                       total_tiles, pc);
+                       total_tiles, pc, chunk);
 }
 
 }  // namespace rns
