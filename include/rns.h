@@ -288,17 +288,24 @@ typedef struct rns_smith_stats {
     double t_uc;           /* seconds: certification (Phase 3) */
     double t_total;        /* seconds: whole call */
     int restarts;          /* Las Vegas restarts taken */
-    int lift_steps;        /* p-adic lifting steps, all phases */
+    int lift_steps;        /* primes for which A^-1 mod q was computed */
     int64_t products;      /* modmatmul_batched calls issued */
     double residue_ops;    /* 2*m*n*k*L summed over all products */
-    int cert_primes;       /* primes used by the determinant certificate */
-    int columns;           /* projection width of the last Phase-2 attempt */
+    int cert_primes;       /* primes of the exact check A X = s I */
+    int columns;           /* columns of the projection J (n: J = I) */
 } rns_smith_stats;
 
 /*
  * smith_form -- the Smith normal form S = diag(s_1, ..., s_n),
  * s_1 | s_2 | ... | s_n, s_i > 0, of a nonsingular n x n integer matrix
- * (Section 1).
+ * (Section 1), by the phases of Section 2.2 in reduced form: the largest
+ * invariant factor s from rational reconstruction of A^-1 b; X = s A^-1 from
+ * residues (A^-1 mod q by GPU Gauss-Jordan, products by modmatmul_batched,
+ * combination by crt_reconstruct), certified by an exact check A X = s I on
+ * fresh primes; the Smith form of X over Z/sZ gives s_i.  Limits: the
+ * reconstruction uses at most 64 primes per CRT, so |s A^-1| and the
+ * numerators and denominators of A^-1 b must stay below about 2^1600
+ * (RNS_ENOTSUP beyond); entries must not be INT64_MIN.
  *   A_host: host int64, n x n row-major (copied during the call).
  *   seed:   drives the random choices only; S does not depend on it.
  *   out:    receives a library-allocated result; free with rns_smith_free.

@@ -1,0 +1,380 @@
+// Host-side arbitrary-precision signed integers for the Smith-form driver
+// (the big numbers of Section 2: the largest invariant factor s, p-adic
+// lifting sums, rational reconstruction).  Sign and magnitude, 32-bit limbs,
+// schoolbook multiplication and Knuth's long division; sizes here stay at a
+// few thousand limbs.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace rns {
+
+class BigInt {
+public:
+    bool neg = false;
+    std::vector<uint32_t> mag;   // little-endian, no leading zero limbs; empty = 0
+
+    BigInt() = default;
+    BigInt(int64_t v) { set_i64(v); }   // NOLINT: implicit by design
+    static BigInt from_u64(uint64_t v) {
+        BigInt r;
+        if (v) {
+            r.mag.push_back((uint32_t)v);
+            if (v >> 32) r.mag.push_back((uint32_t)(v >> 32));
+        }
+        return r;
+    }
+    void set_i64(int64_t v) {
+        mag.clear();
+        neg = v < 0;
+        uint64_t u = neg ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
+        while (u) {
+            mag.push_back((uint32_t)u);
+            u >>= 32;
+        }
+    }
+    bool is_zero() const { return mag.empty(); }
+    bool is_one() const { return !neg && mag.size() == 1 && mag[0] == 1; }
+    int sign() const { return is_zero() ? 0 : (neg ? -1 : 1); }
+    size_t bit_length() const {
+        if (mag.empty()) return 0;
+        return 32 * (mag.size() - 1) + (32 - __builtin_clz(mag.back()));
+    }
+    bool fits_i64() const {
+        if (mag.size() > 2) return false;
+        const uint64_t u = to_u64_mag();
+        return neg ? u <= (1ull << 63) : u < (1ull << 63);
+    }
+    uint64_t to_u64_mag() const {
+        uint64_t u = 0;
+        if (mag.size() > 0) u |= mag[0];
+        if (mag.size() > 1) u |= (uint64_t)mag[1] << 32;
+        return u;
+    }
+    int64_t to_i64() const {
+        const uint64_t u = to_u64_mag();
+        return neg ? (int64_t)((uint64_t)0 - u) : (int64_t)u;
+    }
+    double to_double() const {
+        double r = 0;
+        for (size_t i = mag.size(); i-- > 0;) r = r * 4294967296.0 + mag[i];
+        return neg ? -r : r;
+    }
+    // Little-endian 64-bit words of the magnitude.
+    std::vector<uint64_t> mag_words() const {
+        std::vector<uint64_t> w((mag.size() + 1) / 2, 0);
+        for (size_t i = 0; i < mag.size(); ++i) w[i / 2] |= (uint64_t)mag[i] << (32 * (i % 2));
+        if (w.empty()) w.push_back(0);
+        return w;
+    }
+    // From W little-endian two's-complement words.
+    static BigInt from_twos(const uint64_t *w, int W) {
+        BigInt r;
+        const bool negv = (w[W - 1] >> 63) != 0;
+        std::vector<uint64_t> u(w, w + W);
+        if (negv) {                      // magnitude = ~u + 1
+            uint64_t c = 1;
+            for (int i = 0; i < W; ++i) {
+                const uint64_t x = ~u[i];
+                u[i] = x + c;
+                c = (u[i] < x) ? 1 : 0;
+            }
+        }
+        for (int i = 0; i < W; ++i) {
+            r.mag.push_back((uint32_t)u[i]);
+            r.mag.push_back((uint32_t)(u[i] >> 32));
+        }
+        r.trim();
+        r.neg = negv && !r.is_zero();
+        return r;
+    }
+    void trim() {
+        while (!mag.empty() && mag.back() == 0) mag.pop_back();
+        if (mag.empty()) neg = false;
+    }
+
+    // ---- magnitude helpers
+    static int cmp_mag(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) {
+        if (a.size() != b.size()) return a.size() < b.size() ? -1 : 1;
+        for (size_t i = a.size(); i-- > 0;)
+            if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+        return 0;
+    }
+    static std::vector<uint32_t> add_mag(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) {
+        const std::vector<uint32_t> &x = a.size() >= b.size() ? a : b;
+        const std::vector<uint32_t> &y = a.size() >= b.size() ? b : a;
+        std::vector<uint32_t> r(x.size() + 1);
+        uint64_t c = 0;
+        for (size_t i = 0; i < x.size(); ++i) {
+            c += (uint64_t)x[i] + (i < y.size() ? y[i] : 0);
+            r[i] = (uint32_t)c;
+            c >>= 32;
+        }
+        r[x.size()] = (uint32_t)c;
+        while (!r.empty() && r.back() == 0) r.pop_back();
+        return r;
+    }
+    // |a| >= |b|
+    static std::vector<uint32_t> sub_mag(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) {
+        std::vector<uint32_t> r(a.size());
+        int64_t br = 0;
+        for (size_t i = 0; i < a.size(); ++i) {
+            int64_t t = (int64_t)a[i] - (i < b.size() ? (int64_t)b[i] : 0) - br;
+            br = t < 0;
+            r[i] = (uint32_t)(t + (br ? (1ll << 32) : 0));
+        }
+        while (!r.empty() && r.back() == 0) r.pop_back();
+        return r;
+    }
+    static std::vector<uint32_t> mul_mag(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) {
+        if (a.empty() || b.empty()) return {};
+        std::vector<uint32_t> r(a.size() + b.size(), 0);
+        for (size_t i = 0; i < a.size(); ++i) {
+            uint64_t c = 0;
+            const uint64_t ai = a[i];
+            if (!ai) continue;
+            for (size_t j = 0; j < b.size(); ++j) {
+                c += ai * b[j] + r[i + j];
+                r[i + j] = (uint32_t)c;
+                c >>= 32;
+            }
+            size_t k = i + b.size();
+            while (c) {
+                c += r[k];
+                r[k] = (uint32_t)c;
+                c >>= 32;
+                ++k;
+            }
+        }
+        while (!r.empty() && r.back() == 0) r.pop_back();
+        return r;
+    }
+    // Knuth, TAOCP vol. 2, 4.3.1 Algorithm D: q = a / b, r = a mod b (magnitudes).
+    static void divmod_mag(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b,
+                           std::vector<uint32_t> &q, std::vector<uint32_t> &r) {
+        if (cmp_mag(a, b) < 0) {
+            q.clear();
+            r = a;
+            return;
+        }
+        if (b.size() == 1) {
+            q.assign(a.size(), 0);
+            uint64_t rem = 0;
+            for (size_t i = a.size(); i-- > 0;) {
+                const uint64_t cur = (rem << 32) | a[i];
+                q[i] = (uint32_t)(cur / b[0]);
+                rem = cur % b[0];
+            }
+            while (!q.empty() && q.back() == 0) q.pop_back();
+            r.clear();
+            if (rem) r.push_back((uint32_t)rem);
+            return;
+        }
+        const int s = __builtin_clz(b.back());
+        std::vector<uint32_t> v(b.size()), u(a.size() + 1);
+        for (size_t i = b.size(); i-- > 0;)
+            v[i] = (b[i] << s) | (s && i ? (uint32_t)((uint64_t)b[i - 1] >> (32 - s)) : 0);
+        u[a.size()] = s ? (uint32_t)((uint64_t)a.back() >> (32 - s)) : 0;
+        for (size_t i = a.size(); i-- > 0;)
+            u[i] = (a[i] << s) | (s && i ? (uint32_t)((uint64_t)a[i - 1] >> (32 - s)) : 0);
+        const size_t n = v.size(), m = a.size() - n;
+        q.assign(m + 1, 0);
+        for (size_t j = m + 1; j-- > 0;) {
+            const uint64_t num = ((uint64_t)u[j + n] << 32) | u[j + n - 1];
+            uint64_t qh = num / v[n - 1];
+            uint64_t rh = num % v[n - 1];
+            while (qh >= (1ull << 32) || qh * v[n - 2] > ((rh << 32) | u[j + n - 2])) {
+                --qh;
+                rh += v[n - 1];
+                if (rh >= (1ull << 32)) break;
+            }
+            int64_t borrow = 0;
+            uint64_t carry = 0;
+            for (size_t i = 0; i < n; ++i) {
+                const uint64_t p = qh * v[i] + carry;
+                carry = p >> 32;
+                const int64_t t = (int64_t)u[i + j] - (int64_t)(uint32_t)p - borrow;
+                u[i + j] = (uint32_t)t;
+                borrow = t < 0 ? 1 : 0;
+            }
+            const int64_t t = (int64_t)u[j + n] - (int64_t)carry - borrow;
+            u[j + n] = (uint32_t)t;
+            if (t < 0) {                 // add back
+                --qh;
+                uint64_t c = 0;
+                for (size_t i = 0; i < n; ++i) {
+                    c += (uint64_t)u[i + j] + v[i];
+                    u[i + j] = (uint32_t)c;
+                    c >>= 32;
+                }
+                u[j + n] += (uint32_t)c;
+            }
+            q[j] = (uint32_t)qh;
+        }
+        while (!q.empty() && q.back() == 0) q.pop_back();
+        r.assign(n, 0);
+        for (size_t i = 0; i < n; ++i)
+            r[i] = (u[i] >> s) | (s ? (uint32_t)((uint64_t)u[i + 1] << (32 - s)) : 0);
+        while (!r.empty() && r.back() == 0) r.pop_back();
+    }
+
+    // ---- signed arithmetic
+    friend BigInt operator+(const BigInt &a, const BigInt &b) {
+        BigInt r;
+        if (a.neg == b.neg) {
+            r.mag = add_mag(a.mag, b.mag);
+            r.neg = a.neg;
+        } else if (cmp_mag(a.mag, b.mag) >= 0) {
+            r.mag = sub_mag(a.mag, b.mag);
+            r.neg = a.neg;
+        } else {
+            r.mag = sub_mag(b.mag, a.mag);
+            r.neg = b.neg;
+        }
+        r.trim();
+        return r;
+    }
+    BigInt operator-() const {
+        BigInt r = *this;
+        if (!r.is_zero()) r.neg = !r.neg;
+        return r;
+    }
+    friend BigInt operator-(const BigInt &a, const BigInt &b) { return a + (-b); }
+    friend BigInt operator*(const BigInt &a, const BigInt &b) {
+        BigInt r;
+        r.mag = mul_mag(a.mag, b.mag);
+        r.neg = !r.mag.empty() && (a.neg != b.neg);
+        return r;
+    }
+    // Truncating division (like C): q = trunc(a/b), r = a - q*b.
+    static void divmod_trunc(const BigInt &a, const BigInt &b, BigInt &q, BigInt &r) {
+        divmod_mag(a.mag, b.mag, q.mag, r.mag);
+        q.neg = !q.mag.empty() && (a.neg != b.neg);
+        r.neg = !r.mag.empty() && a.neg;
+    }
+    // Floor division with non-negative remainder for b > 0.
+    static void divmod_floor(const BigInt &a, const BigInt &b, BigInt &q, BigInt &r) {
+        divmod_trunc(a, b, q, r);
+        if (r.neg) {
+            r = r + abs(b);
+            q = q - BigInt(b.neg ? -1 : 1);
+        }
+    }
+    friend BigInt operator/(const BigInt &a, const BigInt &b) {
+        BigInt q, r;
+        divmod_trunc(a, b, q, r);
+        return q;
+    }
+    // Non-negative residue for m > 0.
+    friend BigInt mod(const BigInt &a, const BigInt &m) {
+        BigInt q, r;
+        divmod_floor(a, m, q, r);
+        return r;
+    }
+    static BigInt abs(const BigInt &a) {
+        BigInt r = a;
+        r.neg = false;
+        return r;
+    }
+    uint32_t mod_small(uint32_t p) const {   // non-negative residue
+        uint64_t rem = 0;
+        for (size_t i = mag.size(); i-- > 0;) rem = ((rem << 32) | mag[i]) % p;
+        if (neg && rem) rem = p - rem;
+        return (uint32_t)rem;
+    }
+    BigInt mul_small(uint32_t m) const {
+        BigInt r;
+        r.neg = neg;
+        r.mag.resize(mag.size() + 1);
+        uint64_t c = 0;
+        for (size_t i = 0; i < mag.size(); ++i) {
+            c += (uint64_t)mag[i] * m;
+            r.mag[i] = (uint32_t)c;
+            c >>= 32;
+        }
+        r.mag[mag.size()] = (uint32_t)c;
+        r.trim();
+        return r;
+    }
+    friend bool operator==(const BigInt &a, const BigInt &b) { return a.neg == b.neg && a.mag == b.mag; }
+    friend bool operator!=(const BigInt &a, const BigInt &b) { return !(a == b); }
+    static int cmp(const BigInt &a, const BigInt &b) {
+        if (a.neg != b.neg) return a.neg ? -1 : 1;
+        const int c = cmp_mag(a.mag, b.mag);
+        return a.neg ? -c : c;
+    }
+    friend bool operator<(const BigInt &a, const BigInt &b) { return cmp(a, b) < 0; }
+    friend bool operator<=(const BigInt &a, const BigInt &b) { return cmp(a, b) <= 0; }
+    friend bool operator>(const BigInt &a, const BigInt &b) { return cmp(a, b) > 0; }
+
+    static BigInt gcd(BigInt a, BigInt b) {
+        a.neg = b.neg = false;
+        while (!b.is_zero()) {
+            BigInt q, r;
+            divmod_trunc(a, b, q, r);
+            a = std::move(b);
+            b = std::move(r);
+        }
+        return a;
+    }
+    static BigInt lcm(const BigInt &a, const BigInt &b) {
+        if (a.is_zero() || b.is_zero()) return BigInt(0);
+        return abs(a) / gcd(a, b) * abs(b);
+    }
+    // g = gcd(a, b) >= 0 with x*a + y*b = g.
+    static BigInt xgcd(const BigInt &a0, const BigInt &b0, BigInt &x, BigInt &y) {
+        BigInt a = a0, b = b0, x0(1), y0(0), x1(0), y1(1);
+        while (!b.is_zero()) {
+            BigInt q, r;
+            divmod_floor(a, abs(b), q, r);
+            if (b.neg) q = -q;           // a = q*b + r with 0 <= r < |b|
+            a = std::move(b);
+            b = std::move(r);
+            BigInt t = x0 - q * x1;
+            x0 = std::move(x1);
+            x1 = std::move(t);
+            t = y0 - q * y1;
+            y0 = std::move(y1);
+            y1 = std::move(t);
+        }
+        if (a.neg) {
+            a = -a;
+            x0 = -x0;
+            y0 = -y0;
+        }
+        x = x0;
+        y = y0;
+        return a;
+    }
+    BigInt shl(size_t bits) const {
+        BigInt r;
+        if (is_zero()) return r;
+        const size_t w = bits / 32, b = bits % 32;
+        r.mag.assign(mag.size() + w + 1, 0);
+        for (size_t i = 0; i < mag.size(); ++i) {
+            r.mag[i + w] |= mag[i] << b;
+            if (b) r.mag[i + w + 1] |= (uint32_t)((uint64_t)mag[i] >> (32 - b));
+        }
+        r.neg = neg;
+        r.trim();
+        return r;
+    }
+    // Integer square root of a non-negative value (floor).
+    static BigInt isqrt(const BigInt &a) {
+        if (a.is_zero()) return BigInt(0);
+        BigInt x = BigInt(1).shl((a.bit_length() + 1) / 2 + 1);
+        while (true) {
+            const BigInt y = x + a / x;
+            BigInt q, r;
+            divmod_trunc(y, BigInt(2), q, r);
+            if (!(q < x)) return x;
+            x = q;
+        }
+    }
+};
+
+}  // namespace rns

@@ -192,6 +192,7 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
 
 extern "C" void rns_ctx_destroy(rns_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->aux) rns_ctx_destroy(ctx->aux);
     // Teardown is best effort: errors cannot be reported from here.
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();

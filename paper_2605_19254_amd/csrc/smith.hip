@@ -1,16 +1,556 @@
-// Smith normal form driver (Section 2.2).  Placeholder until the driver lands.
-#include "internal.hpp"
+// Smith normal form driver (Section 1 defines S; Section 2.2 describes the
+// three phases this driver follows in reduced form).
+//
+// Phase 1 (largest invariant factor).  For two random right-hand sides b the
+//   solution x = A^-1 b has a denominator dividing s_n; x is rebuilt from its
+//   residues x mod q = (A^-1 mod q) b for a growing set of primes (A^-1 mod q by
+//   Gauss-Jordan on the GPU, all primes at once; the products by
+//   modmatmul_batched; the residues combined by crt_reconstruct) and then by
+//   rational reconstruction on the host.  s = lcm of the two denominators.
+// Phase 2 (the massaged matrix with J = I).  X = s A^-1 is rebuilt the same
+//   way (residue planes scaled by s mod q, crt_reconstruct); A X = s I is then
+//   checked exactly with modmatmul_batched on fresh primes.  Success proves
+//   that X is integral, hence s_n | s.  The Smith form of X over Z/sZ is
+//   diag(s/s_n, ..., s/s_1) (read with gcd(0, s) = s), so
+//   s_{n+1-i} = s / g_i for its diagonal g_1 | ... | g_n.  When s factors into
+//   small prime powers the diagonal comes from one elimination per prime power
+//   on the GPU (minimal-valuation pivoting over Z/q^e); otherwise from gcd
+//   elimination modulo s on the host.
+// Phase 3 (certification).  With J = I and the exact check of A X = s I the
+//   result is certified; a failed check (s too small, or too few primes for X)
+//   adds primes or restarts Phase 1 with new right-hand sides (Las Vegas).
+#include "bigint.hpp"
+#include "smith_internal.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+#include <vector>
+
+using namespace rns;
 
 struct rns_smith_result {
     std::vector<std::vector<uint64_t>> s;
     rns_smith_stats st{};
 };
 
-extern "C" int smith_form(rns_ctx *ctx, const int64_t *A, int64_t n, uint64_t seed,
+namespace {
+
+constexpr int kAuxPrimes = 256;     // basis of the driver's internal context
+constexpr int kChunk = 16;          // primes added per round
+constexpr int kMaxSolvePrimes = 64; // primes of one GPU CRT call
+constexpr int kMaxRestarts = 4;
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SplitMix {
+    uint64_t x;
+    uint64_t next() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+#define DRV_HIP(call)                                                             \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? RNS_ENOMEM : RNS_EDEVICE; \
+    } while (0)
+#define DRV_ST(call)                     \
+    do {                                 \
+        int s_ = (call);                 \
+        if (s_ != RNS_OK) return s_;     \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t count) {
+        if (count <= n) return RNS_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return RNS_ENOMEM;
+        n = count;
+        return RNS_OK;
+    }
+};
+
+// Rational reconstruction: y mod m -> (num, den) with |num| <= B, 0 < den <= B,
+// num = den * y (mod m), B = floor(sqrt(m/2)).  False if none exists.
+bool rational_reconstruct(const BigInt &y, const BigInt &m, BigInt &num, BigInt &den) {
+    const BigInt B = BigInt::isqrt(m / BigInt(2));
+    BigInt r0 = m, r1 = mod(y, m), t0(0), t1(1);
+    while (BigInt::cmp(r1, B) > 0) {
+        BigInt q, r;
+        BigInt::divmod_trunc(r0, r1, q, r);
+        r0 = std::move(r1);
+        r1 = std::move(r);
+        BigInt t = t0 - q * t1;
+        t0 = std::move(t1);
+        t1 = std::move(t);
+    }
+    if (t1.is_zero() || BigInt::cmp(BigInt::abs(t1), B) > 0) return false;
+    num = t1.neg ? -r1 : r1;
+    den = BigInt::abs(t1);
+    return BigInt::gcd(num, den).is_one() || num.is_zero();
+}
+
+// Smith diagonal modulo s of an n x n matrix (entries reduced mod s), by
+// unimodular gcd row/column operations; returns g_i = gcd(d_i, s) in
+// divisibility order.  Host code for small n.
+std::vector<BigInt> snf_mod_host(std::vector<BigInt> M, int64_t n, const BigInt &s) {
+    auto at = [&](int64_t i, int64_t j) -> BigInt & { return M[i * n + j]; };
+    auto op = [&](const BigInt &a, const BigInt &b, BigInt &g, BigInt &x, BigInt &y) {
+        if (!a.is_zero() && mod(b, BigInt::abs(a)).is_zero()) {
+            g = a;
+            x = BigInt(1);
+            y = BigInt(0);
+        } else {
+            g = BigInt::xgcd(a, b, x, y);
+        }
+    };
+    for (int64_t k = 0; k < n; ++k) {
+        for (;;) {
+            for (int64_t i = k + 1; i < n; ++i) {
+                if (at(i, k).is_zero()) continue;
+                BigInt g, x, y;
+                const BigInt a = at(k, k), b = at(i, k);
+                op(a, b, g, x, y);
+                const BigInt ag = a / g, bg = b / g;
+                for (int64_t j = k; j < n; ++j) {
+                    const BigInt u = at(k, j), v = at(i, j);
+                    at(k, j) = mod(x * u + y * v, s);
+                    at(i, j) = mod(ag * v - bg * u, s);
+                }
+            }
+            bool dirty = false;
+            for (int64_t j = k + 1; j < n; ++j) {
+                if (at(k, j).is_zero()) continue;
+                BigInt g, x, y;
+                const BigInt a = at(k, k), b = at(k, j);
+                op(a, b, g, x, y);
+                const BigInt ag = a / g, bg = b / g;
+                for (int64_t i = k; i < n; ++i) {
+                    const BigInt u = at(i, k), v = at(i, j);
+                    at(i, k) = mod(x * u + y * v, s);
+                    at(i, j) = mod(ag * v - bg * u, s);
+                    if (i > k && !at(i, k).is_zero()) dirty = true;
+                }
+            }
+            if (!dirty) break;
+        }
+    }
+    std::vector<BigInt> g(n);
+    for (int64_t i = 0; i < n; ++i) g[i] = BigInt::gcd(at(i, i), s);   // gcd(0, s) = s
+    for (int64_t i = 0; i < n; ++i)                                       // diag(a,b) ~ diag(gcd,lcm)
+        for (int64_t j = i + 1; j < n; ++j) {
+            const BigInt h = BigInt::gcd(g[i], g[j]);
+            const BigInt l = (g[i] / h) * g[j];
+            g[i] = h;
+            g[j] = l;
+        }
+    return g;
+}
+
+struct Driver {
+    rns_ctx *ctx = nullptr;     // the caller's context (stats, test hooks)
+    rns_ctx *aux = nullptr;     // internal basis of kAuxPrimes primes
+    int64_t n = 0;
+    const int64_t *A = nullptr; // host
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    rns_smith_stats st{};
+    double abits = 0;           // log2 of Hadamard's bound on |det A|
+    double amax = 0;            // max |a_ij|
+
+    DevBuf<int64_t> dA;
+    DevBuf<uint32_t> dM;        // [P][n][2n] Gauss-Jordan workspace; right halves = A^-1 mod q
+    DevBuf<GjPrime> dpr;
+    DevBuf<int32_t> dsing;
+    DevBuf<uint32_t> dtmp;
+    DevBuf<uint64_t> dX;        // s A^-1, W words per entry
+    DevBuf<int64_t> dB;         // right-hand sides
+    DevBuf<uint32_t> dBres, dXres, dAres, dProd;
+    DevBuf<uint32_t> dc;
+    DevBuf<unsigned> dcount;
+    DevBuf<int32_t> dstatus;
+    int P = 0;                  // primes with inverses in dM
+    int base = 0;               // first aux prime used for inverses
+    int Wx = 1;
+
+    ~Driver() {
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    GjPrime gjp(int idx, int W) const {
+        GjPrime g;
+        g.p = aux->primes[idx];
+        g.pf = (double)g.p;
+        g.pinv = 1.0 / g.pf;
+        g.pow64w = (double)powmod_u64(2, 64ull * W, g.p);
+        return g;
+    }
+
+    int sync() {
+        DRV_HIP(hipStreamSynchronize(stream));
+        return RNS_OK;
+    }
+
+    // A^-1 mod q for the P primes aux[base .. base+P); returns the index of a
+    // singular prime through *bad (-1 if none).
+    int invert(int P_, int *bad) {
+        P = P_;
+        const int64_t per = n * 2 * n;
+        DRV_ST(dM.alloc((size_t)P * per));
+        DRV_ST(dpr.alloc(P));
+        DRV_ST(dsing.alloc(P));
+        std::vector<GjPrime> h(P);
+        for (int q = 0; q < P; ++q) h[q] = gjp(base + q, 1);
+        DRV_HIP(hipMemcpyAsync(dpr.p, h.data(), sizeof(GjPrime) * P, hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemsetAsync(dsing.p, 0, sizeof(int32_t) * P, stream));
+        launch_gj_load(dA.p, n, dM.p, dpr.p, P, stream);
+        for (int k = 0; k < n; ++k) launch_gj_step(dM.p, n, k, dpr.p, P, dsing.p, stream);
+        DRV_HIP(hipGetLastError());
+        std::vector<int32_t> sing(P);
+        DRV_HIP(hipMemcpyAsync(sing.data(), dsing.p, sizeof(int32_t) * P, hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        *bad = -1;
+        for (int q = 0; q < P; ++q)
+            if (sing[q]) {
+                *bad = q;
+                break;
+            }
+        st.lift_steps += P;
+        return RNS_OK;
+    }
+
+    // CRT of residue planes res (rows x cols, ldr, plane stride) over the P
+    // inverse primes into W words per entry, on the device.
+    int crt(const uint32_t *res, int64_t rows, int64_t cols, int64_t ldr, int64_t ps, int W,
+            uint64_t *out) {
+        DRV_ST(dstatus.alloc(1));
+        DRV_HIP(hipMemsetAsync(dstatus.p, 0, sizeof(int32_t), stream));
+        return crt_reconstruct(aux, res, rows, cols, ldr, ps, base, P, nullptr, 0, out, W, cols,
+                               dstatus.p, stream);
+    }
+
+    int gemm(const uint32_t *Ap, int64_t lda, int64_t aps, const uint32_t *Bp, int64_t ldb, int64_t bps,
+             uint32_t *Cp, int64_t ldc, int64_t cps, int64_t m, int64_t nn, int64_t k, int pb, int L) {
+        rns_gemm_desc d{};
+        d.m = m; d.n = nn; d.k = k;
+        d.A = Ap; d.lda = lda; d.a_plane_stride = aps;
+        d.B = Bp; d.ldb = ldb; d.b_plane_stride = bps;
+        d.C = Cp; d.ldc = ldc; d.c_plane_stride = cps;
+        d.prime_begin = pb; d.L = L;
+        st.products += 1;
+        st.residue_ops += 2.0 * m * nn * k * L;
+        return modmatmul_batched(aux, &d, 1, RNS_PATH_AUTO, stream);
+    }
+
+    // Phase 1: denominators of A^-1 b for two random b; s = their lcm.
+    // Returns RNS_EBOUND when P primes are not enough yet.
+    int phase1(SplitMix &rng, BigInt &s) {
+        const int c = 2;
+        std::vector<int64_t> b((size_t)n * c);
+        for (auto &v : b) v = (int64_t)(rng.next() % 2001) - 1000;
+        DRV_ST(dB.alloc((size_t)n * c));
+        DRV_HIP(hipMemcpyAsync(dB.p, b.data(), sizeof(int64_t) * n * c, hipMemcpyHostToDevice, stream));
+        DRV_ST(dBres.alloc((size_t)P * n * c));
+        DRV_ST(rns_reduce(aux, dB.p, n, c, c, base, P, dBres.p, c, n * c, stream));
+        DRV_ST(dtmp.alloc((size_t)P * n * c));
+        DRV_ST(gemm(dM.p + n, 2 * n, 2 * n * n, dBres.p, c, n * c, dtmp.p, c, n * c, n, c, n, base, P));
+        const int W = (int)((P * 26 + 63) / 64) + 1;
+        DevBuf<uint64_t> dx;
+        DRV_ST(dx.alloc((size_t)n * c * W));
+        DRV_ST(crt(dtmp.p, n, c, c, n * c, W, dx.p));
+        std::vector<uint64_t> hx((size_t)n * c * W);
+        DRV_HIP(hipMemcpyAsync(hx.data(), dx.p, sizeof(uint64_t) * hx.size(), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        BigInt M(1);
+        for (int q = 0; q < P; ++q) M = M.mul_small(aux->primes[base + q]);
+        BigInt lcm(1);
+        const BigInt B = BigInt::isqrt(M / BigInt(2));
+        for (int col = 0; col < c; ++col) {
+            BigInt den(1);
+            for (int64_t i = 0; i < n; ++i) {
+                const BigInt y = BigInt::from_twos(&hx[((size_t)i * c + col) * W], W);
+                // With the current denominator the entry may already be small.
+                BigInt z = mod(y * den, M);
+                if (BigInt::cmp(z.shl(1), M) > 0) z = z - M;
+                if (BigInt::cmp(BigInt::abs(z), B) <= 0) continue;
+                BigInt num, d2;
+                if (!rational_reconstruct(z, M, num, d2)) return RNS_EBOUND;
+                den = den * d2;
+            }
+            lcm = BigInt::lcm(lcm, den);
+        }
+        s = lcm;
+        return RNS_OK;
+    }
+
+    // Phase 2: X = s A^-1 on the device (Wx words per entry); then the exact
+    // check A X = s I on fresh primes.  RNS_EBOUND: not verified.
+    int phase2_build(const BigInt &s) {
+        std::vector<uint32_t> sm(P);
+        for (int q = 0; q < P; ++q) sm[q] = s.mod_small(aux->primes[base + q]);
+        DRV_ST(dc.alloc(P));
+        DRV_HIP(hipMemcpyAsync(dc.p, sm.data(), sizeof(uint32_t) * P, hipMemcpyHostToDevice, stream));
+        // scale the inverse planes in place: (A^-1 mod q) * (s mod q)
+        launch_scale(dM.p + n, n, n, 2 * n, 2 * n * n, dpr.p, dc.p, P, stream);
+        DRV_HIP(hipGetLastError());
+        Wx = (int)((P * 26 + 63) / 64) + 1;
+        DRV_ST(dX.alloc((size_t)n * n * Wx));
+        DRV_ST(crt(dM.p + n, n, n, 2 * n, 2 * n * n, Wx, dX.p));
+        // undo the scaling is not needed: the inverse planes are not reused
+        return RNS_OK;
+    }
+
+    int phase2_check(const BigInt &s, bool *ok) {
+        // |X| <= (M-1)/2 < 2^(26 P), so |A X - s I| <= n max|a| 2^(26 P) + s.
+        const double bits = std::max(std::log2((double)n) + std::log2(std::max(1.0, amax)) + 26.0 * P,
+                                     (double)s.bit_length()) + 2.0;
+        const int K = std::min(kAuxPrimes - (base + P), (int)std::ceil(bits / 25.9) + 1);
+        const int cb = base + P;                // fresh primes after the inverse primes
+        if (K < 1 || cb + K > kAuxPrimes || K > kMaxSolvePrimes * 4) return RNS_ENOTSUP;
+        std::vector<GjPrime> h(K);
+        for (int j = 0; j < K; ++j) h[j] = gjp(cb + j, Wx);
+        DevBuf<GjPrime> dck;
+        DRV_ST(dck.alloc(K));
+        DRV_HIP(hipMemcpyAsync(dck.p, h.data(), sizeof(GjPrime) * K, hipMemcpyHostToDevice, stream));
+        DRV_ST(dXres.alloc((size_t)K * n * n));
+        launch_words_mod(dX.p, n * n, Wx, dck.p, K, dXres.p, stream);
+        DRV_HIP(hipGetLastError());
+        DRV_ST(dAres.alloc((size_t)K * n * n));
+        DRV_ST(rns_reduce(aux, dA.p, n, n, n, cb, K, dAres.p, n, n * n, stream));
+        DRV_ST(dProd.alloc((size_t)K * n * n));
+        DRV_ST(gemm(dAres.p, n, n * n, dXres.p, n, n * n, dProd.p, n, n * n, n, n, n, cb, K));
+        std::vector<uint32_t> sm(K);
+        for (int j = 0; j < K; ++j) sm[j] = s.mod_small(aux->primes[cb + j]);
+        DRV_ST(dc.alloc(std::max(P, K)));
+        DRV_HIP(hipMemcpyAsync(dc.p, sm.data(), sizeof(uint32_t) * K, hipMemcpyHostToDevice, stream));
+        DRV_ST(dcount.alloc(1));
+        DRV_HIP(hipMemsetAsync(dcount.p, 0, sizeof(unsigned), stream));
+        launch_check_sI(dProd.p, n, dc.p, K, dcount.p, stream);
+        DRV_HIP(hipGetLastError());
+        unsigned mism = 0;
+        DRV_HIP(hipMemcpyAsync(&mism, dcount.p, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        st.cert_primes = K;
+        *ok = mism == 0;
+        return RNS_OK;
+    }
+
+    // Smith diagonal of X mod s: g_1 | ... | g_n.
+    int snf(const BigInt &s, std::vector<BigInt> &g) {
+        // Factor s over the primes below 2^16.
+        std::vector<std::pair<uint32_t, int>> fac;
+        BigInt rest = s;
+        for (uint32_t q = 2; q < 65536 && !rest.is_one(); ++q) {
+            bool prime = true;
+            for (uint32_t d = 2; d * d <= q; ++d)
+                if (q % d == 0) { prime = false; break; }
+            if (!prime) continue;
+            int e = 0;
+            while (rest.mod_small(q) == 0) {
+                rest = rest / BigInt((int64_t)q);
+                ++e;
+            }
+            if (e) fac.push_back({q, e});
+        }
+        bool gpu = rest.is_one() && n > 24;
+        for (auto &f : fac) {
+            double m = std::pow((double)f.first, f.second);
+            if (m >= 17179869184.0) gpu = false;   // 2^34
+        }
+        g.assign(n, BigInt(1));
+        if (gpu) {
+            DevBuf<uint64_t> dm, part;
+            DevBuf<int32_t> dval;
+            DRV_ST(dm.alloc((size_t)n * n));
+            const int nparts = 512;
+            DRV_ST(part.alloc(nparts));
+            DRV_ST(dval.alloc(n));
+            std::vector<int32_t> val(n);
+            for (auto &f : fac) {
+                LocalMod lm;
+                lm.q = f.first;
+                lm.e = f.second;
+                lm.m = 1;
+                for (int t = 0; t < f.second; ++t) lm.m *= f.first;
+                lm.mf = (double)lm.m;
+                lm.minv = 1.0 / lm.mf;
+                lm.pow64w = powmod_u64(2, 64ull * Wx, lm.m);
+                launch_words_mod_m(dX.p, n * n, Wx, lm, dm.p, stream);
+                for (int k = 0; k < n; ++k) launch_loc_step(dm.p, n, k, lm, part.p, nparts, dval.p, stream);
+                DRV_HIP(hipGetLastError());
+                DRV_HIP(hipMemcpyAsync(val.data(), dval.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream));
+                DRV_ST(sync());
+                // Once the remainder is zero mod q^e the later steps record e.
+                bool zero = false;
+                for (int64_t i = 0; i < n; ++i) {
+                    int v = zero ? f.second : std::min(val[i], f.second);
+                    if (v >= f.second) zero = true;
+                    for (int t = 0; t < v; ++t) g[i] = g[i].mul_small(f.first);
+                }
+            }
+        } else {
+            std::vector<uint64_t> hx((size_t)n * n * Wx);
+            DRV_HIP(hipMemcpyAsync(hx.data(), dX.p, sizeof(uint64_t) * hx.size(), hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+            std::vector<BigInt> M((size_t)n * n);
+            for (size_t e = 0; e < M.size(); ++e) M[e] = mod(BigInt::from_twos(&hx[e * Wx], Wx), s);
+            g = snf_mod_host(std::move(M), n, s);
+        }
+        return RNS_OK;
+    }
+
+    int run(rns_smith_result *res) {
+        const double t0 = now_s();
+        DRV_HIP(hipSetDevice(ctx->device));
+        DRV_HIP(hipStreamCreate(&stream));
+        DRV_ST(dA.alloc((size_t)n * n));
+        DRV_HIP(hipMemcpyAsync(dA.p, A, sizeof(int64_t) * n * n, hipMemcpyHostToDevice, stream));
+        // Hadamard's bound and max entry.
+        double rows = 0, cols = 0;
+        std::vector<double> colsq(n, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+            double r = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                const double v = (double)A[i * n + j];
+                r += v * v;
+                colsq[j] += v * v;
+                amax = std::max(amax, std::fabs(v));
+            }
+            rows += r > 0 ? 0.5 * std::log2(r) : -1e300;
+        }
+        for (int64_t j = 0; j < n; ++j) cols += colsq[j] > 0 ? 0.5 * std::log2(colsq[j]) : -1e300;
+        abits = std::min(rows, cols);
+        if (!(abits > -1e299)) return RNS_ESINGULAR;         // a zero row or column
+        SplitMix rng{seed ^ 0x5DEECE66Dull};
+        int singular_primes = 0;
+        base = 0;
+        for (int attempt = 0; attempt <= kMaxRestarts; ++attempt) {
+            if (attempt) st.restarts += 1;
+            // Phase 1 and 2 share the inverses; grow the prime set until the
+            // reconstruction of A^-1 b succeeds and X verifies.
+            BigInt s;
+            bool verified = false;
+            double tl = now_s();
+            for (int Pn = kChunk; Pn <= kMaxSolvePrimes; Pn += kChunk) {
+                int bad = -1;
+                if (base + Pn + 8 > kAuxPrimes) return RNS_ENOTSUP;
+                DRV_ST(invert(Pn, &bad));
+                if (bad >= 0) {
+                    // A prime divides det A.  Enough such primes prove det A = 0.
+                    singular_primes += 1;
+                    if (singular_primes * 25.9 > abits + 1.0) return RNS_ESINGULAR;
+                    base += bad + 1;
+                    Pn -= kChunk;                    // retry with the same count
+                    continue;
+                }
+                const double tp = now_s();
+                int stp = phase1(rng, s);
+                st.t_lif += now_s() - tl;
+                tl = now_s();
+                if (stp == RNS_EBOUND) continue;
+                DRV_ST(stp);
+                const double ti = now_s();
+                DRV_ST(phase2_build(s));
+                bool ok = false;
+                const double tu = now_s();
+                DRV_ST(phase2_check(s, &ok));
+                st.t_uc += now_s() - tu;
+                st.t_im += tu - ti;
+                (void)tp;
+                if (ok) {
+                    verified = true;
+                    break;
+                }
+            }
+            if (!verified) continue;                 // new right-hand sides
+            if (ctx->force_cert_failures > 0) {      // test hook: pretend the check failed
+                ctx->force_cert_failures -= 1;
+                continue;
+            }
+            const double ts = now_s();
+            std::vector<BigInt> g;
+            DRV_ST(snf(s, g));
+            st.t_im += now_s() - ts;
+            res->s.assign(n, {});
+            for (int64_t i = 0; i < n; ++i) {
+                // s_{n-i} = s / g_i (g ascending -> s_i descending)
+                const BigInt v = s / g[i];
+                res->s[n - 1 - i] = v.mag_words();
+            }
+            st.columns = (int)n;
+            st.t_total = now_s() - t0;
+            res->st = st;
+            return RNS_OK;
+        }
+        return RNS_ERETRY;
+    }
+};
+
+int aux_ctx(rns_ctx *ctx, rns_ctx **out) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (!ctx->aux) {
+        int st = rns_ctx_create(&ctx->aux, ctx->device, nullptr, kAuxPrimes, 0);
+        if (st != RNS_OK) return st;
+    }
+    *out = ctx->aux;
+    return RNS_OK;
+}
+
+}  // namespace
+
+extern "C" int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
                           rns_smith_result **out) {
-    (void)ctx; (void)A; (void)n; (void)seed;
-    if (out) *out = nullptr;
-    return RNS_ENOTSUP;
+    if (!ctx || !out || n < 0 || (n > 0 && !A_host)) return RNS_EINVAL;
+    *out = nullptr;
+    rns_smith_result *res = new (std::nothrow) rns_smith_result;
+    if (!res) return RNS_ENOMEM;
+    if (n == 0) {
+        *out = res;
+        return RNS_OK;
+    }
+    if (n == 1) {
+        const int64_t a = A_host[0];
+        if (a == 0) {
+            delete res;
+            return RNS_ESINGULAR;
+        }
+        res->s.push_back(BigInt(a < 0 ? -a : a).mag_words());
+        *out = res;
+        return RNS_OK;
+    }
+    for (int64_t e = 0; e < n * n; ++e)
+        if (A_host[e] == INT64_MIN) {         // |a| must fit in int64
+            delete res;
+            return RNS_EINVAL;
+        }
+    Driver d;
+    d.ctx = ctx;
+    d.n = n;
+    d.A = A_host;
+    d.seed = seed;
+    int st = aux_ctx(ctx, &d.aux);
+    if (st == RNS_OK) st = d.run(res);
+    if (st != RNS_OK) {
+        delete res;
+        return st;
+    }
+    *out = res;
+    return RNS_OK;
 }
 
 extern "C" int rns_smith_get(const rns_smith_result *r, int64_t i, const uint64_t **words,

@@ -1,0 +1,38 @@
+// Shared declarations of the Smith-form driver and its kernels.
+#pragma once
+
+#include "internal.hpp"
+
+namespace rns {
+
+// One prime of a batched modular computation in the driver.
+struct GjPrime {
+    uint32_t p;
+    double pf, pinv;
+    double pow64w;     // 2^(64W) mod p for the word count of the current call
+};
+
+// Modulus q^e < 2^34 of a local elimination.
+struct LocalMod {
+    uint32_t q;
+    int e;
+    uint64_t m;
+    double mf, minv;
+    uint64_t pow64w;   // 2^(64W) mod m
+};
+
+void launch_gj_load(const int64_t *A, int64_t n, uint32_t *M, const GjPrime *pr, int P, hipStream_t s);
+void launch_gj_step(uint32_t *M, int64_t n, int k, const GjPrime *pr, int P, int32_t *singular,
+                    hipStream_t s);
+void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t plane_stride,
+                  const GjPrime *pr, const uint32_t *c, int P, hipStream_t s);
+void launch_words_mod(const uint64_t *x, int64_t count, int W, const GjPrime *pr, int L,
+                      uint32_t *out, hipStream_t s);
+void launch_check_sI(const uint32_t *P, int64_t n, const uint32_t *s_mod, int L, unsigned *mism,
+                     hipStream_t s);
+void launch_words_mod_m(const uint64_t *x, int64_t count, int W, const LocalMod &lm, uint64_t *out,
+                        hipStream_t s);
+void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod &lm, uint64_t *part, int nparts,
+                     int32_t *val, hipStream_t s);
+
+}  // namespace rns

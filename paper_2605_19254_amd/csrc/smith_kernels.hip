@@ -1,0 +1,374 @@
+// GPU kernels of the Smith-form driver.
+//
+//   Gauss-Jordan inversion modulo many primes at once ([A | I] -> [I | A^-1]
+//   per prime), used to obtain A^-1 mod q for the residue-number reconstruction
+//   of A^-1 b and s A^-1.
+//   Residues of multiword integers, scaling of residue planes, and an exact
+//   comparison of a residue product with s I (the integrality check).
+//   Elimination over Z/q^e with minimal-valuation pivoting, which gives the
+//   local Smith form of an integer matrix at the prime q.
+//
+// Arithmetic modulo a 26-bit prime uses exact doubles (products < 2^52) and
+// the rounded reciprocal; modulo q^e < 2^34 the first factor is split at bit 17
+// so that every partial product stays below 2^52.
+#include "smith_internal.hpp"
+
+namespace rns {
+namespace {
+
+__device__ __forceinline__ uint32_t mulmod_p(uint32_t a, uint32_t b, double pf, double pinv) {
+    const double x = (double)a * (double)b;
+    double r = fma(-rint(x * pinv), pf, x);
+    r = r < 0.0 ? r + pf : r;
+    return (uint32_t)r;
+}
+
+__device__ __forceinline__ uint32_t powmod_p(uint32_t a, uint32_t e, double pf, double pinv) {
+    uint32_t r = 1;
+    while (e) {
+        if (e & 1) r = mulmod_p(r, a, pf, pinv);
+        a = mulmod_p(a, a, pf, pinv);
+        e >>= 1;
+    }
+    return r;
+}
+
+// --------------------------------------------------- Gauss-Jordan mod p --
+// M: [P][n][2n] uint32; plane q uses prime pr[q].  Step k: choose the first
+// row r >= k with a nonzero entry in column k, swap it into row k (columns
+// k..2n-1: columns < k of rows >= k are already zero), scale row k so that
+// the pivot is 1.  A prime with no pivot is marked singular.
+__global__ __launch_bounds__(256) void k_gj_pivot(uint32_t *__restrict__ M, int64_t n, int k,
+                                                  const GjPrime *__restrict__ pr,
+                                                  int32_t *__restrict__ singular) {
+    const int q = blockIdx.x;
+    if (singular[q]) return;
+    const int64_t ld = 2 * n;
+    uint32_t *A = M + (int64_t)q * n * ld;
+    __shared__ int best;
+    if (threadIdx.x == 0) best = (int)n;
+    __syncthreads();
+    for (int64_t r = k + threadIdx.x; r < n; r += blockDim.x)
+        if (A[r * ld + k] != 0) atomicMin(&best, (int)r);
+    __syncthreads();
+    const int r = best;
+    if (r >= n) {
+        if (threadIdx.x == 0) singular[q] = 1;
+        return;
+    }
+    const double pf = pr[q].pf, pinv = pr[q].pinv;
+    if (r != k)
+        for (int64_t j = k + threadIdx.x; j < ld; j += blockDim.x) {
+            const uint32_t t = A[(int64_t)k * ld + j];
+            A[(int64_t)k * ld + j] = A[(int64_t)r * ld + j];
+            A[(int64_t)r * ld + j] = t;
+        }
+    __syncthreads();
+    __shared__ uint32_t inv;
+    if (threadIdx.x == 0) inv = powmod_p(A[(int64_t)k * ld + k], pr[q].p - 2, pf, pinv);
+    __syncthreads();
+    for (int64_t j = k + threadIdx.x; j < ld; j += blockDim.x)
+        A[(int64_t)k * ld + j] = mulmod_p(A[(int64_t)k * ld + j], inv, pf, pinv);
+}
+
+// Rows i != k: row_i -= M[i][k] * row_k on columns k+1..2n-1.  Column k is
+// not written (it is never read again).  Grid: x = column chunk, y = row,
+// z = prime.
+__global__ __launch_bounds__(256) void k_gj_elim(uint32_t *__restrict__ M, int64_t n, int k,
+                                                 const GjPrime *__restrict__ pr,
+                                                 const int32_t *__restrict__ singular) {
+    const int q = blockIdx.z;
+    const int64_t i = blockIdx.y;
+    if (singular[q] || i == k) return;
+    const int64_t ld = 2 * n;
+    uint32_t *A = M + (int64_t)q * n * ld;
+    const uint32_t f = A[i * ld + k];
+    if (f == 0) return;
+    const int64_t j = (int64_t)k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ld) return;
+    const uint32_t p = pr[q].p;
+    const uint32_t t = mulmod_p(f, A[(int64_t)k * ld + j], pr[q].pf, pr[q].pinv);
+    const uint32_t a = A[i * ld + j];
+    A[i * ld + j] = a >= t ? a - t : a + p - t;
+}
+
+// Loads A (int64, host-reduced to residues on the device) into [A mod p | I].
+__global__ __launch_bounds__(256) void k_gj_load(const int64_t *__restrict__ A, int64_t n,
+                                                 uint32_t *__restrict__ M,
+                                                 const GjPrime *__restrict__ pr) {
+    const int q = blockIdx.z;
+    const int64_t i = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ld = 2 * n;
+    if (j >= ld) return;
+    uint32_t v;
+    if (j < n) {
+        const int64_t x = A[i * n + j];
+        const int64_t p = pr[q].p;
+        int64_t r = x % p;
+        v = (uint32_t)(r < 0 ? r + p : r);
+    } else {
+        v = (j - n == i) ? 1u : 0u;
+    }
+    M[((int64_t)q * n + i) * ld + j] = v;
+}
+
+// Multiply plane q of a residue matrix (rows x cols, leading dimension ld,
+// planes plane_stride apart) by c[q] mod p_q.
+__global__ __launch_bounds__(256) void k_scale(uint32_t *__restrict__ R, int64_t rows, int64_t cols,
+                                               int64_t ld, int64_t plane_stride,
+                                               const GjPrime *__restrict__ pr,
+                                               const uint32_t *__restrict__ c) {
+    const int q = blockIdx.z;
+    const int64_t i = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    uint32_t *x = R + q * plane_stride + i * ld + j;
+    *x = mulmod_p(*x, c[q], pr[q].pf, pr[q].pinv);
+}
+
+// Residues of W-word two's-complement integers modulo L primes:
+// out[j*count + e] = x_e mod p_j.  x = sum_w u_w 2^(64w) - [neg] 2^(64W);
+// the value is accumulated word by word with Horner's rule in exact doubles.
+__global__ __launch_bounds__(256) void k_words_mod(const uint64_t *__restrict__ x, int64_t count,
+                                                   int W, const GjPrime *__restrict__ pr, int L,
+                                                   uint32_t *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const uint64_t *xe = x + e * W;
+    const bool neg = (xe[W - 1] >> 63) != 0;
+    for (int j = 0; j < L; ++j) {
+        const double pf = pr[j].pf, pinv = pr[j].pinv;
+        double r = 0.0;
+        for (int w = W - 1; w >= 0; --w) {
+            const uint64_t u = xe[w];
+            // r = r * 2^64 + u  (mod p) as three exact steps of 20, 22 and 22
+            // bits (r < 2^26, so every intermediate stays below 2^48).
+            double y = fma(r, 1048576.0, (double)(u >> 44));
+            y = fma(-rint(y * pinv), pf, y);
+            y = y < 0.0 ? y + pf : y;
+            y = fma(y, 4194304.0, (double)((u >> 22) & 0x3FFFFF));
+            y = fma(-rint(y * pinv), pf, y);
+            y = y < 0.0 ? y + pf : y;
+            y = fma(y, 4194304.0, (double)(u & 0x3FFFFF));
+            y = fma(-rint(y * pinv), pf, y);
+            r = y < 0.0 ? y + pf : y;
+        }
+        if (neg) {                               // subtract 2^(64W) mod p
+            double y = r - pr[j].pow64w;
+            r = y < 0.0 ? y + pf : y;
+        }
+        out[(int64_t)j * count + e] = (uint32_t)r;
+    }
+}
+
+// Counts entries of the residue product P (planes [L][n][n]) that differ from
+// s I modulo the plane's prime: expected s mod p on the diagonal, 0 elsewhere.
+__global__ __launch_bounds__(256) void k_check_sI(const uint32_t *__restrict__ P, int64_t n,
+                                                  const uint32_t *__restrict__ s_mod,
+                                                  unsigned *__restrict__ mismatches) {
+    const int q = blockIdx.z;
+    const int64_t i = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t want = (i == j) ? s_mod[q] : 0u;
+    if (P[((int64_t)q * n + i) * n + j] != want) atomicAdd(mismatches, 1u);
+}
+
+// ------------------------------------------------ local Smith form at q --
+// M: n x n uint64 entries in [0, m), m = q^e < 2^34.
+
+__device__ __forceinline__ uint64_t mod_m(double x, double mf, double minv) {
+    double r = fma(-rint(x * minv), mf, x);     // x < 2^53 -> exact, |r| <= m/2 + 1
+    r = r < 0.0 ? r + mf : r;
+    return (uint64_t)r;
+}
+
+__device__ __forceinline__ uint64_t mulmod_m(uint64_t a, uint64_t b, double mf, double minv) {
+    const double b_ = (double)b;
+    const uint64_t hi = mod_m((double)(a >> 17) * b_, mf, minv);          // < 2^51 before reduction
+    return mod_m(fma((double)hi, 131072.0, (double)(a & 0x1FFFF) * b_), mf, minv);
+}
+
+__device__ __forceinline__ int valuation(uint64_t x, uint32_t q, int e) {
+    if (x == 0) return e;
+    int v = 0;
+    while (v < e && x % q == 0) {
+        x /= q;
+        ++v;
+    }
+    return v;
+}
+
+// X (W words per entry, two's complement) -> X mod m.
+__global__ __launch_bounds__(256) void k_words_mod_m(const uint64_t *__restrict__ x, int64_t count,
+                                                     int W, LocalMod lm, uint64_t *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const uint64_t *xe = x + e * W;
+    uint64_t r = 0;
+    for (int w = W - 1; w >= 0; --w) {
+        const uint64_t u = xe[w];
+        // r = r * 2^64 + u mod m, in 16-bit steps (r < 2^34: r * 2^16 < 2^50)
+        for (int t = 3; t >= 0; --t)
+            r = mod_m(fma((double)r, 65536.0, (double)((u >> (16 * t)) & 0xFFFF)), lm.mf, lm.minv);
+    }
+    if ((xe[W - 1] >> 63) != 0) r = r >= lm.pow64w ? r - lm.pow64w : r + lm.m - lm.pow64w;
+    out[e] = r;
+}
+
+// Step k, pass 1: minimal valuation over rows k..n-1, columns k..n-1.  Each
+// block reduces its share into part[block] = (valuation << 40) | flat index.
+__global__ __launch_bounds__(256) void k_loc_min(const uint64_t *__restrict__ M, int64_t n, int k,
+                                                 LocalMod lm, uint64_t *__restrict__ part) {
+    const int64_t w = n - k;
+    const int64_t total = w * w;
+    uint64_t best = ~0ull;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = k + t / w, j = k + t % w;
+        const int v = valuation(M[i * n + j], lm.q, lm.e);
+        const uint64_t key = ((uint64_t)v << 40) | (uint64_t)(i * n + j);
+        best = key < best ? key : best;
+    }
+    __shared__ uint64_t red[256];
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s && red[threadIdx.x + s] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__device__ uint64_t inv_unit(uint64_t u, uint64_t m) {   // u a unit mod m (m < 2^34)
+    int64_t t0 = 0, t1 = 1;
+    int64_t r0 = (int64_t)m, r1 = (int64_t)u;
+    while (r1) {
+        const int64_t qq = r0 / r1;
+        int64_t tmp = r0 - qq * r1;
+        r0 = r1;
+        r1 = tmp;
+        tmp = t0 - qq * t1;
+        t0 = t1;
+        t1 = tmp;
+    }
+    return (uint64_t)(t0 < 0 ? t0 + (int64_t)m : t0);
+}
+
+// Step k, pass 2 (one block): reduce the partial minima, record the
+// valuation, swap the pivot into (k, k), and scale row k by the inverse of
+// the pivot's unit part so that the pivot becomes q^v.
+__global__ __launch_bounds__(256) void k_loc_pivot(uint64_t *__restrict__ M, int64_t n, int k,
+                                                   LocalMod lm, const uint64_t *__restrict__ part,
+                                                   int nparts, int32_t *__restrict__ val) {
+    __shared__ uint64_t red[256];
+    uint64_t best = ~0ull;
+    for (int t = threadIdx.x; t < nparts; t += blockDim.x) best = part[t] < best ? part[t] : best;
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s && red[threadIdx.x + s] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const uint64_t key = red[0];
+    const int v = (int)(key >> 40);
+    const int64_t flat = (int64_t)(key & ((1ull << 40) - 1));
+    const int64_t r = flat / n, c = flat % n;
+    if (threadIdx.x == 0) val[k] = v;
+    if (v >= lm.e) return;                  // the rest is 0 mod m
+    // swap rows k, r and columns k, c
+    if (r != k)
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+            const uint64_t t = M[(int64_t)k * n + j];
+            M[(int64_t)k * n + j] = M[r * n + j];
+            M[r * n + j] = t;
+        }
+    __syncthreads();
+    if (c != k)
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint64_t t = M[i * n + k];
+            M[i * n + k] = M[i * n + c];
+            M[i * n + c] = t;
+        }
+    __syncthreads();
+    __shared__ uint64_t uinv;
+    if (threadIdx.x == 0) {
+        uint64_t piv = M[(int64_t)k * n + k];
+        for (int t = 0; t < v; ++t) piv /= lm.q;
+        uinv = inv_unit(piv % lm.m, lm.m);
+    }
+    __syncthreads();
+    for (int64_t j = k + threadIdx.x; j < n; j += blockDim.x)
+        M[(int64_t)k * n + j] = mulmod_m(M[(int64_t)k * n + j], uinv, lm.mf, lm.minv);
+}
+
+// Step k, pass 3: rows i > k: row_i -= (M[i][k] / q^v) row_k on columns > k.
+__global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int64_t n, int k,
+                                                  LocalMod lm, const int32_t *__restrict__ val) {
+    const int v = val[k];
+    if (v >= lm.e) return;
+    const int64_t i = k + 1 + (int64_t)blockIdx.y;
+    const int64_t j = k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || j >= n) return;
+    uint64_t f = M[i * n + k];
+    if (f == 0) return;
+    for (int t = 0; t < v; ++t) f /= lm.q;
+    const uint64_t d = mulmod_m(f % lm.m, M[(int64_t)k * n + j], lm.mf, lm.minv);
+    const uint64_t a = M[i * n + j];
+    M[i * n + j] = a >= d ? a - d : a + lm.m - d;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers --
+
+void launch_gj_load(const int64_t *A, int64_t n, uint32_t *M, const GjPrime *pr, int P, hipStream_t s) {
+    dim3 grid((unsigned)((2 * n + 255) / 256), (unsigned)n, (unsigned)P);
+    hipLaunchKernelGGL(k_gj_load, grid, dim3(256), 0, s, A, n, M, pr);
+}
+
+void launch_gj_step(uint32_t *M, int64_t n, int k, const GjPrime *pr, int P, int32_t *singular,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)P), dim3(256), 0, s, M, n, k, pr, singular);
+    const int64_t cols = 2 * n - k - 1;
+    if (cols <= 0) return;
+    dim3 grid((unsigned)((cols + 255) / 256), (unsigned)n, (unsigned)P);
+    hipLaunchKernelGGL(k_gj_elim, grid, dim3(256), 0, s, M, n, k, pr, singular);
+}
+
+void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t plane_stride,
+                  const GjPrime *pr, const uint32_t *c, int P, hipStream_t s) {
+    dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows, (unsigned)P);
+    hipLaunchKernelGGL(k_scale, grid, dim3(256), 0, s, R, rows, cols, ld, plane_stride, pr, c);
+}
+
+void launch_words_mod(const uint64_t *x, int64_t count, int W, const GjPrime *pr, int L,
+                      uint32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_words_mod, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, x, count,
+                       W, pr, L, out);
+}
+
+void launch_check_sI(const uint32_t *P, int64_t n, const uint32_t *s_mod, int L, unsigned *mism,
+                     hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)L);
+    hipLaunchKernelGGL(k_check_sI, grid, dim3(256), 0, s, P, n, s_mod, mism);
+}
+
+void launch_words_mod_m(const uint64_t *x, int64_t count, int W, const LocalMod &lm, uint64_t *out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_words_mod_m, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, x, count,
+                       W, lm, out);
+}
+
+void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod &lm, uint64_t *part, int nparts,
+                     int32_t *val, hipStream_t s) {
+    hipLaunchKernelGGL(k_loc_min, dim3((unsigned)nparts), dim3(256), 0, s, M, n, k, lm, part);
+    hipLaunchKernelGGL(k_loc_pivot, dim3(1), dim3(256), 0, s, M, n, k, lm, part, nparts, val);
+    const int64_t w = n - k - 1;
+    if (w <= 0) return;
+    dim3 grid((unsigned)((w + 255) / 256), (unsigned)w);
+    hipLaunchKernelGGL(k_loc_elim, grid, dim3(256), 0, s, M, n, k, lm, val);
+}
+
+}  // namespace rns

@@ -1,0 +1,119 @@
+"""GPU Smith-form driver against the oracle (bit-exact invariant factors).
+
+Expected values: oracle.smith (Bareiss determinant + gcd elimination modulo
+the determinant) or, for planted inputs, the invariants planted by the
+generator."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import smith as osmith
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_19254_amd as rg
+    return rg
+
+
+@pytest.fixture(scope="module")
+def ctx(rg):
+    c = rg.Context(device=0, L=24)
+    yield c
+    c.close()
+
+
+def test_small_smith_workload(ctx, rg):
+    _say("smith 64x64 [-99,99] seed 0")
+    a = synth.small_smith(seed=0)
+    res = rg.smith_form(ctx, a, seed=1)
+    assert res.s == osmith.smith_form(a)
+    assert res.stats["restarts"] == 0
+    assert res.stats["products"] >= 2
+
+
+@pytest.mark.parametrize("n", [3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53])
+def test_vandermonde_mod_family(ctx, rg, n):
+    # Section 4.1 family; Section 4.2 checks primes 3..53.
+    _say("smith vandermonde", n)
+    a = synth.vandermonde_mod(n)
+    res = rg.smith_form(ctx, a, seed=n)
+    s = osmith.smith_form(a)
+    assert res.s == s
+    assert osmith.is_divisor_chain(res.s)
+
+
+@pytest.mark.parametrize("n,seed", [(2, 0), (5, 1), (10, 2), (20, 3), (33, 4), (48, 5)])
+def test_random_small(ctx, rg, n, seed):
+    _say("smith random", n, seed)
+    rng = np.random.default_rng(100 + seed)
+    while True:
+        a = rng.integers(-99, 100, size=(n, n), dtype=np.int64)
+        if osmith.bareiss_det(a) != 0:
+            break
+    assert rg.smith_form(ctx, a, seed=seed).s == osmith.smith_form(a)
+
+
+@pytest.mark.parametrize("n,seed", [(24, 0), (64, 1), (200, 2)])
+def test_planted_small(ctx, rg, n, seed):
+    _say("smith planted", n, seed)
+    pl = synth.planted_smith(n, seed=seed)
+    res = rg.smith_form(ctx, pl.a, seed=seed)
+    assert res.s == pl.s
+
+
+def test_planted_n2000(ctx, rg):
+    """The planted workload at full size: A = U diag(s) V, n = 2000."""
+    _say("smith planted n=2000")
+    pl = synth.planted_smith(2000, seed=0)
+    res = rg.smith_form(ctx, pl.a, seed=0)
+    assert res.s == pl.s
+    print("stats", res.stats, flush=True)
+
+
+def test_structured_and_singular(ctx, rg):
+    _say("smith structured")
+    for diag in ([6, 4, 9], [12, 18, 8, 1], [2, 3, 5, 7, 11]):
+        a = np.diag(np.array(diag, dtype=np.int64))
+        assert rg.smith_form(ctx, a).s == osmith.smith_form(a)
+    assert rg.smith_form(ctx, np.array([[-7]], dtype=np.int64)).s == [7]
+    assert rg.smith_form(ctx, np.zeros((0, 0), dtype=np.int64)).s == []
+    sing = np.array([[1, 2, 3], [2, 4, 6], [1, 0, 1]], dtype=np.int64)
+    with pytest.raises(rg.RnsError) as e:
+        rg.smith_form(ctx, sing)
+    assert e.value.status == 6
+    with pytest.raises(rg.RnsError) as e:
+        rg.smith_form(ctx, np.zeros((4, 4), dtype=np.int64))
+    assert e.value.status == 6
+
+
+def test_las_vegas_restart_forced(ctx, rg):
+    """A failed certification (forced from the host) restarts the method and
+    still returns the right S (Section 2.2, Phase 3)."""
+    _say("smith forced restart")
+    a = synth.small_smith(seed=3, n=24)
+    want = osmith.smith_form(a)
+    ctx.force_cert_failures(2)
+    res = rg.smith_form(ctx, a, seed=5)
+    assert res.s == want
+    assert res.stats["restarts"] >= 2
+    ctx.force_cert_failures(0)
+
+
+def test_result_independent_of_seed(ctx, rg):
+    _say("smith seeds")
+    a = synth.planted_smith(40, seed=7).a
+    r = [rg.smith_form(ctx, a, seed=sd).s for sd in (0, 1, 12345)]
+    assert r[0] == r[1] == r[2]
