@@ -47,7 +47,8 @@ enum {
     RNS_EOVERFLOW = 5,  /* a reconstructed value does not fit the output words */
     RNS_ESINGULAR = 6,  /* the input matrix is singular */
     RNS_ERETRY = 7,     /* the Las Vegas restart budget was exhausted */
-    RNS_ENOTSUP = 8     /* the request is outside what this build implements */
+    RNS_ENOTSUP = 8,    /* the request is outside what this build implements */
+    RNS_EPENDING = 9    /* a served request has not finished within the wait */
 };
 
 /* Product paths of modmatmul_batched. */
@@ -333,6 +334,50 @@ void rns_smith_free(rns_smith_result *r);
 int rns_ctx_profile(rns_ctx *ctx, int enable);
 int rns_ctx_profile_read(rns_ctx *ctx, const char *name, double *total_ms,
                          int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Serving: Smith-form requests of different sizes from a queue, several at
+ * once on one GPU.  Worker threads each own a context (so their streams are
+ * separate and admitted requests overlap on the device); a request is
+ * admitted when its estimated device-memory footprint fits the budget
+ * (oldest first, later requests may pass an older one that does not fit
+ * until the older one has waited `aging` seconds, default 2).  A request
+ * larger than the whole budget runs alone.  Each request has its own status;
+ * a singular or failing request does not affect the others.
+ * ---------------------------------------------------------------------- */
+typedef struct rns_server rns_server;
+
+typedef struct rns_request_info {
+    int status;            /* smith_form status of this request */
+    double t_submit;       /* seconds since the server started */
+    double t_start;        /* admitted (work began) */
+    double t_end;          /* finished */
+    size_t footprint;      /* bytes reserved for it at admission */
+    int worker;
+} rns_request_info;
+
+typedef struct rns_server_counters {
+    size_t budget, in_use, high_water;
+    int running, max_running, queued;
+} rns_server_counters;
+
+/* hbm_budget 0 = seven eighths of the device memory free at creation. */
+int rns_server_create(int device, int workers, size_t hbm_budget, rns_server **out);
+int rns_server_set_aging(rns_server *s, double seconds);
+/* Copies A (n x n, host int64); *ticket identifies the request. */
+int rns_server_submit(rns_server *s, const int64_t *A_host, int64_t n, uint64_t seed,
+                      uint64_t *ticket);
+/* Waits up to timeout_s seconds (negative = no limit).  Returns the request's
+ * status (RNS_EPENDING if still running: wait again); on RNS_OK *out receives
+ * the result (free with rns_smith_free).  A ticket can be waited for once. */
+int rns_server_wait(rns_server *s, uint64_t ticket, double timeout_s,
+                    rns_smith_result **out, rns_request_info *info);
+int rns_server_stats(rns_server *s, rns_server_counters *st);
+/* Estimated device bytes of one request of size n (the admission charge). */
+int rns_server_footprint(int64_t n, size_t *bytes);
+/* Stops the workers after the requests they are running; queued requests
+ * are dropped. */
+void rns_server_destroy(rns_server *s);
 
 /* Test hook: make the next `count` certifications of this context fail, to
  * exercise the Las Vegas restart (Section 2.2, Phase 3).  0 disables. */

@@ -7,6 +7,6 @@ the binding without the built library raises ImportError: there is no CPU
 fallback.
 """
 from .binding import (Context, GemmPlan, GemmProblem, MatmulPlan, MatmulProblem,  # noqa: F401
-                      RnsError, SmithResult, autotune, crt_reconstruct, modmatmul_batched,
+                      RnsError, Server, SmithResult, autotune, server_footprint, crt_reconstruct, modmatmul_batched,
                       rns_primes_below, rns_reduce, rns_strerror, smith_form, words_to_ints,
                       workspace_bytes)

@@ -57,7 +57,7 @@ def loaded_hip_runtimes():
         pass
     return sorted(out)
 
-OK, EINVAL, ENOMEM, EDEVICE, EBOUND, EOVERFLOW, ESINGULAR, ERETRY, ENOTSUP = range(9)
+OK, EINVAL, ENOMEM, EDEVICE, EBOUND, EOVERFLOW, ESINGULAR, ERETRY, ENOTSUP, EPENDING = range(10)
 PATH_AUTO, PATH_FP64, PATH_INT8 = 0, 1, 2
 _PATHS = {"auto": PATH_AUTO, "fp64": PATH_FP64, "int8": PATH_INT8}
 
@@ -138,6 +138,24 @@ _lib_mplan_execute = _sig("rns_matmul_plan_execute", _I32, [_P, _P])
 _lib_mplan_info = _sig("rns_matmul_plan_info", _I32, [_P, ctypes.POINTER(RnsPlanInfo)])
 _lib_mplan_gemm = _sig("rns_matmul_plan_gemm", _P, [_P])
 _lib_mplan_destroy = _sig("rns_matmul_plan_destroy", None, [_P])
+class RnsRequestInfo(ctypes.Structure):
+    _fields_ = [("status", _I32), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_end", ctypes.c_double), ("footprint", ctypes.c_size_t), ("worker", _I32)]
+
+
+class RnsServerStats(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_size_t), ("in_use", ctypes.c_size_t), ("high_water", ctypes.c_size_t),
+                ("running", _I32), ("max_running", _I32), ("queued", _I32)]
+
+
+_lib_srv_create = _sig("rns_server_create", _I32, [_I32, _I32, ctypes.c_size_t, ctypes.POINTER(_P)])
+_lib_srv_aging = _sig("rns_server_set_aging", _I32, [_P, ctypes.c_double])
+_lib_srv_submit = _sig("rns_server_submit", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)])
+_lib_srv_wait = _sig("rns_server_wait", _I32, [_P, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_P),
+                                               ctypes.POINTER(RnsRequestInfo)])
+_lib_srv_stats = _sig("rns_server_stats", _I32, [_P, ctypes.POINTER(RnsServerStats)])
+_lib_srv_footprint = _sig("rns_server_footprint", _I32, [_I64, ctypes.POINTER(ctypes.c_size_t)])
+_lib_srv_destroy = _sig("rns_server_destroy", None, [_P])
 _lib_profile = _sig("rns_ctx_profile", _I32, [_P, _I32])
 _lib_profile_read = _sig("rns_ctx_profile_read", _I32, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                                         ctypes.POINTER(_I64)])
@@ -150,7 +168,9 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_ctx_profile", "rns_ctx_profile_read", "rns_gemm_plan_create", "rns_gemm_plan_execute",
            "rns_gemm_plan_info", "rns_gemm_plan_set_variant", "rns_gemm_plan_destroy",
            "rns_ctx_set_tune_cache", "rns_autotune", "rns_gemm_plan_autotune", "rns_matmul_plan_create", "rns_matmul_plan_execute",
-           "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy"]
+           "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy",
+           "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
+           "rns_server_stats", "rns_server_footprint", "rns_server_destroy"]
 
 
 class RnsError(RuntimeError):
@@ -498,12 +518,7 @@ class SmithResult:
     stats: dict
 
 
-def smith_form(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
-    a = np.ascontiguousarray(a, dtype=np.int64)
-    n = a.shape[0]
-    assert a.shape == (n, n)
-    h = _P()
-    _check(_lib_smith(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "smith_form")
+def _smith_result(h) -> SmithResult:
     try:
         s = []
         words = ctypes.POINTER(ctypes.c_uint64)()
@@ -520,3 +535,63 @@ def smith_form(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
     finally:
         _lib_smith_free(h)
     return SmithResult(s, stats)
+
+
+def smith_form(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    h = _P()
+    _check(_lib_smith(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "smith_form")
+    return _smith_result(h)
+
+
+def server_footprint(n: int) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib_srv_footprint(n, ctypes.byref(out)), "rns_server_footprint")
+    return out.value
+
+
+class Server:
+    """rns_server: Smith-form requests served concurrently on one GPU."""
+
+    def __init__(self, device: int = 0, workers: int = 4, hbm_budget: int = 0, aging: float = 2.0):
+        h = _P()
+        _check(_lib_srv_create(device, workers, hbm_budget, ctypes.byref(h)), "rns_server_create")
+        self.handle = h
+        _check(_lib_srv_aging(h, aging), "rns_server_set_aging")
+
+    def submit(self, a: np.ndarray, seed: int = 0) -> int:
+        a = np.ascontiguousarray(a, dtype=np.int64)
+        t = ctypes.c_uint64()
+        _check(_lib_srv_submit(self.handle, a.ctypes.data, a.shape[0], seed, ctypes.byref(t)),
+               "rns_server_submit")
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """-> (status, SmithResult or None, info dict)."""
+        h = _P()
+        info = RnsRequestInfo()
+        st = _lib_srv_wait(self.handle, ticket, timeout, ctypes.byref(h), ctypes.byref(info))
+        d = {f: getattr(info, f) for f, _ in RnsRequestInfo._fields_}
+        if st == OK:
+            return st, _smith_result(h), d
+        if h:
+            _lib_smith_free(h)
+        return st, None, d
+
+    def stats(self) -> dict:
+        s = RnsServerStats()
+        _check(_lib_srv_stats(self.handle, ctypes.byref(s)), "rns_server_stats")
+        return {f: getattr(s, f) for f, _ in RnsServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _lib_srv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -98,6 +98,7 @@ extern "C" const char *rns_strerror(int s) {
     case RNS_ESINGULAR: return "matrix is singular";
     case RNS_ERETRY: return "Las Vegas restart budget exhausted";
     case RNS_ENOTSUP: return "not supported by this build";
+    case RNS_EPENDING: return "request still running";
     default: return "unknown status";
     }
 }
