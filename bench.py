@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--batched", type=int, default=512,
                     help="also time the batched workload with this many uneven products (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
-    ap.add_argument("--only", default="", choices=["", "batched"],
+    ap.add_argument("--smith", type=int, default=1, help="time the Smith-form workloads (0 = skip)")
+    ap.add_argument("--serving", type=int, default=24,
+                    help="requests per open-loop serving point (0 = skip)")
+    ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving"],
                     help="run only this workload (for profiling)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size "
@@ -155,6 +158,131 @@ def run_batched(rg, torch, dev, count, steps):
                              "kind": "oracle", "sample": "first 24 problems of the batch, %.1f s" % tc}}
 
 
+def run_smith(rg, reps=10):
+    """Smith forms: the 64 x 64 matrix with entries in [-99, 99] (seed 0) and
+    the planted n = 2000 matrix (A = U diag(s) V, seed 0), each checked against
+    the oracle or the planted invariants; the oracle is timed on the 64 x 64
+    matrix and on a planted n = 100 matrix."""
+    import synth
+    from oracle import smith as osmith
+    out = {}
+    with rg.Context(device=0, L=24) as ctx:
+        a = synth.small_smith(seed=0)
+        want = osmith.smith_form(a)
+        rg.smith_form(ctx, a)                      # warm-up (internal basis, kernels)
+        t0 = time.perf_counter()
+        for r in range(reps):
+            res = rg.smith_form(ctx, a, seed=r)
+        t = (time.perf_counter() - t0) / reps
+        if res.s != want:
+            raise SystemExit("bench.py: Smith form (64x64) differs from the oracle")
+        t0 = time.perf_counter()
+        osmith.smith_form(a)
+        to = time.perf_counter() - t0
+        out["small_64"] = {"workload": "64x64, entries uniform in [-99, 99], seed 0", "solves_per_s": 1.0 / t,
+                           "ms_per_solve": 1000 * t, "stats": res.stats,
+                           "cpu_baseline": {"value": 1.0 / to, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                            "sample": "the same matrix"}}
+        pl = synth.planted_smith(2000, seed=0)
+        t0 = time.perf_counter()
+        res = rg.smith_form(ctx, pl.a, seed=0)
+        t = time.perf_counter() - t0
+        if res.s != pl.s:
+            raise SystemExit("bench.py: planted Smith form (n=2000) differs")
+        p100 = synth.planted_smith(100, seed=0)
+        t0 = time.perf_counter()
+        osmith.smith_form(p100.a)
+        to = time.perf_counter() - t0
+        out["planted_2000"] = {"workload": "A = U diag(s) V, n = 2000, 4n random row and column operations, "
+                                           "5 planted factors from the primes below 100, seed 0",
+                               "seconds": t, "stats": res.stats,
+                               "cpu_baseline": {"value": to, "unit": "s", "cores": 1, "kind": "oracle",
+                                                "sample": "planted n = 100 (the oracle is O(n^3) in Python)"}}
+    return out
+
+
+def _serving_requests(count, seed):
+    """Sizes log-uniform in [100, 1500] (planted, so that the Smith form is
+    nontrivial and known), one request in four a dense random matrix with
+    entries in [-2^10, 2^10] and n log-uniform in [8, 48], and one singular
+    request at position 5."""
+    import math
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        if i == 5:
+            a = np.ones((6, 6), dtype=np.int64)
+            reqs.append((a, None))
+        elif i % 4 == 3:
+            n = int(round(math.exp(rng.uniform(math.log(8), math.log(48)))))
+            reqs.append((synth.small_smith(seed=int(seed * 1000 + i), n=n, bound=1 << 10), "random"))
+        else:
+            n = int(round(math.exp(rng.uniform(math.log(100), math.log(1500)))))
+            pl = synth.planted_smith(n, seed=int(seed * 1000 + i))
+            reqs.append((pl.a, pl.s))
+    return reqs
+
+
+def run_serving(rg, count):
+    """Closed-loop capacity, then open-loop Poisson arrivals at 0.5x and 1.0x
+    of it; latency = completion - arrival."""
+    import numpy as np
+    workers = 4
+    out = {"workers": workers}
+    srv = rg.Server(device=0, workers=workers)
+    warm = _serving_requests(8, seed=7)
+    for a, _ in warm[:2]:
+        srv.wait(srv.submit(a))
+    t0 = time.perf_counter()
+    ts = [srv.submit(a, seed=i) for i, (a, _) in enumerate(warm)]
+    for t in ts:
+        srv.wait(t)
+    cap = len(warm) / (time.perf_counter() - t0)
+    out["closed_loop_solves_per_s"] = cap
+    points = []
+    for frac, seed in ((0.5, 11), (1.0, 12)):
+        reqs = _serving_requests(count, seed=seed)
+        rate = frac * cap
+        gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
+        arrive = np.cumsum(gaps) - gaps[0]
+        start = time.perf_counter()
+        tickets = []
+        for (a, _), ta in zip(reqs, arrive):
+            d = start + ta - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets.append((srv.submit(a, seed=1), time.perf_counter()))
+        lat, queue, service, ok, bad = [], [], [], 0, 0
+        for (t, t_arr), (a, want) in zip(tickets, reqs):
+            st, res, info = srv.wait(t)
+            if want is None:
+                bad += int(st == 6)
+                continue
+            if st != 0 or (want != "random" and res.s != want):
+                raise SystemExit("bench.py: served Smith form differs from the planted invariants")
+            ok += 1
+            lat.append(info["t_end"] - info["t_submit"])
+            queue.append(info["t_start"] - info["t_submit"])
+            service.append(info["t_end"] - info["t_start"])
+        span = time.perf_counter() - start
+        points.append({"rate_frac_of_capacity": frac, "arrival_rate": rate, "requests": count,
+                       "solves_per_s": ok / span, "p50_latency_s": float(np.percentile(lat, 50)),
+                       "p99_latency_s": float(np.percentile(lat, 99)),
+                       "p50_queue_s": float(np.percentile(queue, 50)),
+                       "p50_service_s": float(np.percentile(service, 50)),
+                       "singular_rejected": bad})
+    st = srv.stats()
+    srv.close()
+    out["points"] = points
+    out["max_running"] = st["max_running"]
+    out["hbm_high_water_bytes"] = st["high_water"]
+    out["workload"] = ("Poisson arrivals; n log-uniform in [100, 1500] planted (A = U diag(s) V), every 4th "
+                       "request random n in [8, 48] with entries in [-2^10, 2^10], one singular request")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -171,6 +299,12 @@ def main():
     dev = torch.device("cuda:0")
     if args.only == "batched":
         print(json.dumps(run_batched(rg, torch, dev, args.batched, args.batched_steps)), flush=True)
+        return
+    if args.only == "smith":
+        print(json.dumps(run_smith(rg)), flush=True)
+        return
+    if args.only == "serving":
+        print(json.dumps(run_serving(rg, args.serving)), flush=True)
         return
     a_np, b_np = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
     A = torch.from_numpy(a_np).to(dev)
@@ -277,6 +411,8 @@ def main():
         "int8_vs_fp64_speedup": (fp64["ms_per_step"] / ms8) if fp64 else None,
     }
     rec["batched"] = run_batched(rg, torch, dev, args.batched, args.batched_steps) if args.batched > 0 else None
+    rec["smith"] = run_smith(rg) if args.smith else None
+    rec["serving"] = run_serving(rg, args.serving) if args.serving > 0 else None
     if args.cpu_rows > 0:
         primes = ctx.primes[:L]
         rec["cpu_baseline"] = cpu_baseline(a_np, b_np, primes, args.cpu_rows)
