@@ -236,6 +236,159 @@ __device__ __forceinline__ void i8_lds_tile(const GemmProblem *__restrict__ P, i
             }
 }
 
+// ------------------------------------------- three-stage LDS pipeline --
+// As i8_lds_tile, with three LDS buffers so that the copies of two later steps
+// are in flight while a step computes.  The fragments of a step are read with
+// one inline-assembly block of 24 ds_read_b128 that waits for its own reads
+// before it ends; the compiler therefore does not wait for the outstanding
+// copies before those reads (it cannot tell the buffers apart), and the
+// explicit vmcnt wait before the barrier covers exactly the copies of the
+// step about to be read.
+
+__device__ __forceinline__ void vm_wait_12() { __builtin_amdgcn_s_waitcnt(0x0F7C); }  // vmcnt(12)
+
+__device__ __forceinline__ void lds_read_step(uint32_t a_addr, uint32_t b_addr,
+                                              v4i (&a)[kI8WaveRB][4], v4i (&b)[kI8WaveCB][4]) {
+    static_assert(kI8WaveRB == 2 && kI8WaveCB == 4, "read block is written for 2 x 4 blocks");
+    asm volatile(
+        "ds_read_b128 %0, %24\n"
+        "ds_read_b128 %1, %24 offset:1024\n"
+        "ds_read_b128 %2, %24 offset:2048\n"
+        "ds_read_b128 %3, %24 offset:3072\n"
+        "ds_read_b128 %4, %24 offset:4096\n"
+        "ds_read_b128 %5, %24 offset:5120\n"
+        "ds_read_b128 %6, %24 offset:6144\n"
+        "ds_read_b128 %7, %24 offset:7168\n"
+        "ds_read_b128 %8, %25\n"
+        "ds_read_b128 %9, %25 offset:1024\n"
+        "ds_read_b128 %10, %25 offset:2048\n"
+        "ds_read_b128 %11, %25 offset:3072\n"
+        "ds_read_b128 %12, %25 offset:4096\n"
+        "ds_read_b128 %13, %25 offset:5120\n"
+        "ds_read_b128 %14, %25 offset:6144\n"
+        "ds_read_b128 %15, %25 offset:7168\n"
+        "ds_read_b128 %16, %25 offset:8192\n"
+        "ds_read_b128 %17, %25 offset:9216\n"
+        "ds_read_b128 %18, %25 offset:10240\n"
+        "ds_read_b128 %19, %25 offset:11264\n"
+        "ds_read_b128 %20, %25 offset:12288\n"
+        "ds_read_b128 %21, %25 offset:13312\n"
+        "ds_read_b128 %22, %25 offset:14336\n"
+        "ds_read_b128 %23, %25 offset:15360\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        : "=&v"(a[0][0]), "=&v"(a[0][1]), "=&v"(a[0][2]), "=&v"(a[0][3]),
+          "=&v"(a[1][0]), "=&v"(a[1][1]), "=&v"(a[1][2]), "=&v"(a[1][3]),
+          "=&v"(b[0][0]), "=&v"(b[0][1]), "=&v"(b[0][2]), "=&v"(b[0][3]),
+          "=&v"(b[1][0]), "=&v"(b[1][1]), "=&v"(b[1][2]), "=&v"(b[1][3]),
+          "=&v"(b[2][0]), "=&v"(b[2][1]), "=&v"(b[2][2]), "=&v"(b[2][3]),
+          "=&v"(b[3][0]), "=&v"(b[3][1]), "=&v"(b[3][2]), "=&v"(b[3][3])
+        : "v"(a_addr), "v"(b_addr));
+}
+
+__device__ __forceinline__ void i8_lds3_tile(const GemmProblem *__restrict__ P, int nprob,
+                                             int64_t t, const PrimeConst *__restrict__ pc,
+                                             const int32_t *__restrict__ tile_prob,
+                                             v4i (*sbuf)[kI8Frag * 64]) {
+    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
+    const GemmProblem &g = P[tc.q];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    const int KT = g.KT;
+    const char *Ag = g.At + (int64_t)tc.plane * g.a_plane_bytes +
+                     (int64_t)tc.tm * (2 * kI8WaveRB) * KT * 4096 + lane * 16;
+    const char *Bg = g.Bt + (int64_t)tc.plane * g.b_plane_bytes +
+                     (int64_t)tc.tn * (2 * kI8WaveCB) * KT * 4096 + lane * 16;
+    const char *src[kI8FragPerWave];
+#pragma unroll
+    for (int i = 0; i < kI8FragPerWave; ++i) {
+        const int f = wave * kI8FragPerWave + i;
+        src[i] = f < kI8FragA ? Ag + ((int64_t)(f >> 2) * KT) * 4096 + (f & 3) * 1024
+                              : Bg + ((int64_t)((f - kI8FragA) >> 2) * KT) * 4096 + ((f - kI8FragA) & 3) * 1024;
+    }
+    auto issue = [&](v4i *buf, int kt) {
+#pragma unroll
+        for (int i = 0; i < kI8FragPerWave; ++i) {
+            const int f = wave * kI8FragPerWave + i;
+            __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)kt * 4096),
+                                             (lds_void *)(buf + f * 64), 16, 0, 0);
+        }
+    };
+    // LDS byte addresses of this wave's A and B fragments in each buffer.
+    uint32_t a_addr[3], b_addr[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const uint32_t base = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) v4i *)sbuf[u];
+        a_addr[u] = base + (uint32_t)((wy * kI8WaveRB * 4) * 1024 + lane * 16);
+        b_addr[u] = base + (uint32_t)((kI8FragA + wx * kI8WaveCB * 4) * 1024 + lane * 16);
+    }
+
+    v4i acc[7][kI8WaveRB][kI8WaveCB];
+#pragma unroll
+    for (int s = 0; s < 7; ++s)
+#pragma unroll
+        for (int i = 0; i < kI8WaveRB; ++i)
+#pragma unroll
+            for (int j = 0; j < kI8WaveCB; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+
+    issue(sbuf[0], 0);
+    if (KT > 1) issue(sbuf[1], 1);
+    int cur = 0;
+    for (int kt = 0; kt < KT; ++kt) {
+        if (kt + 1 < KT) vm_wait_12(); else vm_wait_0();
+        plain_barrier();
+        v4i a[kI8WaveRB][4], b[kI8WaveCB][4];
+        lds_read_step(a_addr[cur], b_addr[cur], a, b);
+        const int nxt2 = cur == 0 ? 2 : cur - 1;      // buffer of step kt+2 = buffer of step kt-1
+        if (kt + 2 < KT) issue(sbuf[nxt2], kt + 2);
+#pragma unroll
+        for (int da = 0; da < 4; ++da)
+#pragma unroll
+            for (int db = 0; db < 4; ++db)
+#pragma unroll
+                for (int i = 0; i < kI8WaveRB; ++i)
+#pragma unroll
+                    for (int j = 0; j < kI8WaveCB; ++j)
+                        acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            a[i][da], b[j][db], acc[da + db][i][j], 0, 0, 0);
+        cur = cur == 2 ? 0 : cur + 1;
+    }
+
+    const int rb0 = tc.tm * (2 * kI8WaveRB) + wy * kI8WaveRB;
+    const int cb0 = tc.tn * (2 * kI8WaveCB) + wx * kI8WaveCB;
+    const PrimeConst pr = pc[g.prime_begin + tc.plane];
+    uint32_t *C = g.C + (int64_t)tc.plane * g.cps;
+#pragma unroll
+    for (int i = 0; i < kI8WaveRB; ++i)
+#pragma unroll
+        for (int j = 0; j < kI8WaveCB; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double sum = 0.0;
+#pragma unroll
+                for (int s = 0; s < 7; ++s) {
+                    const double cs = (double)acc[s][i][j][v];
+                    const double r = fma(-rint(cs * pr.pinv), pr.pf, cs);
+                    sum = fma(r, pr.w[s], sum);
+                }
+                double r = fma(-rint(sum * pr.pinv), pr.pf, sum);
+                r = r < 0.0 ? r + pr.pf : r;
+                const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + v;
+                const int col = (cb0 + j) * 16 + (lane & 15);
+                if (row < g.m && col < g.n) C[(int64_t)row * g.ldc + col] = (uint32_t)r;
+            }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_i8_lds3(const GemmProblem *__restrict__ P, int nprob,
+                                                      int64_t total_tiles,
+                                                      const PrimeConst *__restrict__ pc,
+                                                      const int32_t *__restrict__ tile_prob) {
+    __shared__ v4i sbuf[3][kI8Frag * 64];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= total_tiles) return;
+    i8_lds3_tile(P, nprob, t, pc, tile_prob, sbuf);
+}
+
 __global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restrict__ P, int nprob,
                                                      int64_t total_tiles,
                                                      const PrimeConst *__restrict__ pc,
@@ -273,6 +426,8 @@ void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
                     int num_cus, hipStream_t s) {
     if (variant == kI8Direct) {
         hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
+    } else if (variant == kI8Lds3) {
+        hipLaunchKernelGGL(k_gemm_i8_lds3, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
     } else if (variant == kI8LdsPersistent && counter) {
         const int64_t grid = std::min<int64_t>(tiles, num_cus);
         hipLaunchKernelGGL(k_gemm_i8_lds_persistent, dim3((unsigned)grid), dim3(256), 0, s, P, nprob,

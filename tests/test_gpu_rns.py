@@ -265,7 +265,7 @@ def test_exact_product_small(ctx, rg, torch_dev, path):
     assert ctx.status() == 0
 
 
-@pytest.mark.parametrize("path", ["int8", "fp64"])
+@pytest.mark.parametrize("path", ["int8", "fp64", "int8-lds3"])
 def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
     """The full n = 4096, 24-prime product in the benchmark's configuration;
     sampled outputs against the oracle, plus every residue of sampled rows."""
@@ -277,7 +277,12 @@ def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
     ra = rg.rns_reduce(ctx, ta, L=L)
     rb = rg.rns_reduce(ctx, tb, L=L)
     rc = torch.empty((L, n, n), dtype=torch.int32, device=dev)
-    rg.modmatmul_batched(ctx, [rg.GemmProblem(ra, rb, rc)], path=path)
+    if path == "int8-lds3":
+        plan = rg.GemmPlan(ctx, [rg.GemmProblem(ra, rb, rc)], path="int8")
+        plan.set_variant(3)
+        plan.execute()
+    else:
+        rg.modmatmul_batched(ctx, [rg.GemmProblem(ra, rb, rc)], path=path)
     out = rg.crt_reconstruct(ctx, rc, L=L, W=1, bound=n << 40)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
