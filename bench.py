@@ -34,6 +34,43 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix, TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
 
+GEMM_SOURCES = ("paper_2605_19254_amd/csrc/gemm_i8.hip", "paper_2605_19254_amd/csrc/gemm_common.hpp",
+                "paper_2605_19254_amd/csrc/internal.hpp")
+TRAFFIC_SUMMARY = "profiles/k_gemm_i8_half_n4096_L24_traffic.md"
+I8_KERNEL_NAMES = {0: "k_gemm_i8_lds", 1: "k_gemm_i8", 2: "k_gemm_i8_half_persistent",
+                   3: "k_gemm_i8_w8", 4: "k_gemm_i8_half"}
+
+
+def gemm_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in GEMM_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of the GEMM kernel from the committed counter
+    summary, or None when that summary is missing, is for another kernel, or
+    was taken on GEMM sources other than the ones in this tree."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    try:
+        if fields.get("kernel") != kernel or fields.get("gemm_sources_sha256") != gemm_source_hash():
+            return None
+        return float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,7 +79,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--primes", type=int, default=24)
     ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-rows", type=int, default=16,
+    ap.add_argument("--cpu-rows", type=int, default=96,
                     help="rows of C the oracle computes for the CPU baseline (0 = skip)")
     ap.add_argument("--out", default="")
     ap.add_argument("--batched", type=int, default=512,
@@ -53,6 +90,8 @@ def parse():
                     help="requests per open-loop serving point (0 = skip)")
     ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving"],
                     help="run only this workload (for profiling)")
+    ap.add_argument("--calibrate-iters", type=int, default=300000,
+                    help="iterations of the random-operand INT8 MFMA ceiling probe (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size "
                          "reference for hardware byte counters)")
@@ -365,6 +404,18 @@ def main():
     gemm_ms = k8["k_gemm"]["avg_ms"]
     mfma_ops = 16.0 * res_ops                       # executed INT8 MFMA ops per launch
     achieved = mfma_ops / (gemm_ms * 1e-3) / 1e12    # TOP/s
+    probe = rg.GemmPlan(ctx, prob, path="int8")
+    kernel = I8_KERNEL_NAMES.get(probe.info()["variant"], "k_gemm_i8")
+    probe.close()
+    ceiling = None
+    if args.calibrate_iters > 0:
+        # Sustained rate of the same MFMA instruction with random register
+        # operands and no memory traffic: the ceiling this part holds under
+        # the power draw of real data (the published peak assumes full clock).
+        rate, cal_ms = ctx.calibrate("i8_16x16x64", iters=args.calibrate_iters, random_operands=True)
+        ceiling = {"value": rate / 1e12, "unit": "TOP/s", "frac": achieved / (rate / 1e12),
+                   "probe": "rns_calibrate kind 0: v_mfma_i32_16x16x64_i8, 8 waves/CU, random "
+                            "register operands, %d iterations, %.1f ms" % (args.calibrate_iters, cal_ms)}
 
     fp64 = None
     if args.fp64_steps > 0:
@@ -399,9 +450,10 @@ def main():
                                "reduce + modmatmul + CRT per step" % (n, n, L),
                    "m": n, "n": n, "k": n, "primes": L, "path": "int8"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
-                     "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
-                     "kernel": "k_gemm_i8", "avg_launch_ms": gemm_ms,
-                     "ops_per_launch": mfma_ops},
+                     "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS,
+                     "traffic": recorded_traffic(kernel),
+                     "kernel": kernel, "avg_launch_ms": gemm_ms,
+                     "ops_per_launch": mfma_ops, "measured_ceiling": ceiling},
         "kernels": k8,
         "hbm_passes": {
             "reduce_GBps": red_bytes / 2 / (k8["k_reduce"]["avg_ms"] * 1e-3) / 1e9,

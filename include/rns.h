@@ -177,9 +177,16 @@ typedef struct rns_gemm_plan rns_gemm_plan;
 
 typedef struct rns_plan_info {
     int path;              /* RNS_PATH_FP64 or RNS_PATH_INT8 */
-    int variant;           /* INT8 GEMM kernel: 0 LDS-staged, 1 direct from L2,
-                              2 LDS-staged persistent (one work-group per CU
-                              taking tiles, longest first, from a counter) */
+    int variant;           /* INT8 GEMM kernel (all compute the same 64 x 128
+                              output tiles):
+                              0 LDS-staged, four waves of 32 x 64 outputs;
+                              1 operands straight from L2, four waves;
+                              2 as 4, persistent: two work-groups per CU take
+                                half-tiles, longest first, from a counter;
+                              3 LDS-staged, eight waves of 32 x 32 outputs;
+                              4 (default) two independent four-wave
+                                work-groups per tile, one per 64-column half,
+                                two work-groups per CU */
     int64_t tiles;         /* work-group tiles over all primes and problems */
     size_t workspace_bytes;
     double residue_ops;    /* 2*m*n*k*L summed over the problems */
@@ -334,6 +341,24 @@ void rns_smith_free(rns_smith_result *r);
 int rns_ctx_profile(rns_ctx *ctx, int enable);
 int rns_ctx_profile_read(rns_ctx *ctx, const char *name, double *total_ms,
                          int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Calibration: the sustained rate of one arithmetic unit on this device, to
+ * state achieved rates beside the published peaks.  Every wave (eight per
+ * CU) runs independent accumulation chains with register operands, no memory
+ * traffic in the timed loop; `iters` iterations of 16 instructions per wave.
+ * kind 0: v_mfma_i32_16x16x64_i8 (the instruction of the INT8-limb GEMM),
+ *      1: v_mfma_i32_32x32x32_i8, 2: v_mfma_f64_16x16x4f64 (FP64 GEMM),
+ *      3: vector v_fma_f64.
+ * random_operands != 0 fills the operand registers with random bits (the
+ * switching activity of real data, which decides the clock the chip holds
+ * under load); 0 uses constant operands.  One untimed warm-up launch, then
+ * one launch timed with HIP events on `stream`.  Outputs: integer ops (or
+ * flops) per second and the timed launch in milliseconds.  Allocates and
+ * frees a small device buffer.  Blocks until the timed launch ends.
+ * ---------------------------------------------------------------------- */
+int rns_calibrate(rns_ctx *ctx, int kind, int iters, int random_operands, void *stream,
+                  double *ops_per_s, double *ms);
 
 /* ------------------------------------------------------------------------
  * Serving: Smith-form requests of different sizes from a queue, several at

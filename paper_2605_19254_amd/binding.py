@@ -157,6 +157,8 @@ _lib_srv_stats = _sig("rns_server_stats", _I32, [_P, ctypes.POINTER(RnsServerSta
 _lib_srv_footprint = _sig("rns_server_footprint", _I32, [_I64, ctypes.POINTER(ctypes.c_size_t)])
 _lib_srv_destroy = _sig("rns_server_destroy", None, [_P])
 _lib_profile = _sig("rns_ctx_profile", _I32, [_P, _I32])
+_lib_calibrate = _sig("rns_calibrate", _I32, [_P, _I32, _I32, _I32, _P, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)])
 _lib_profile_read = _sig("rns_ctx_profile_read", _I32, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                                         ctypes.POINTER(_I64)])
 
@@ -170,7 +172,7 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_ctx_set_tune_cache", "rns_autotune", "rns_gemm_plan_autotune", "rns_matmul_plan_create", "rns_matmul_plan_execute",
            "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy",
            "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
-           "rns_server_stats", "rns_server_footprint", "rns_server_destroy"]
+           "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate"]
 
 
 class RnsError(RuntimeError):
@@ -282,6 +284,16 @@ class Context:
         _check(_lib_profile_read(self.handle, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
                "rns_ctx_profile_read")
         return ms.value, cnt.value
+
+    CALIBRATE_KINDS = {"i8_16x16x64": 0, "i8_32x32x32": 1, "f64_mfma": 2, "f64_fma": 3}
+
+    def calibrate(self, kind: str, iters: int = 20000, random_operands: bool = True, stream=None):
+        """(ops per second, ms) of one unit's sustained rate on this device."""
+        rate = ctypes.c_double()
+        ms = ctypes.c_double()
+        _check(_lib_calibrate(self.handle, self.CALIBRATE_KINDS[kind], iters, 1 if random_operands else 0,
+                              _stream(stream), ctypes.byref(rate), ctypes.byref(ms)), "rns_calibrate")
+        return rate.value, ms.value
 
     def set_tune_cache(self, path: str):
         _check(_lib_set_tune_cache(self.handle, path.encode() if path else None), "rns_ctx_set_tune_cache")

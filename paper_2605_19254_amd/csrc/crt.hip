@@ -77,18 +77,31 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
         const CrtJob J = njobs > 0 ? jobs[qj] : job0;
         const int64_t u = t - J.tile_begin;
         const int64_t i = u / J.col_tiles;
-        const int64_t c = (u - i * J.col_tiles) * kBlock + tid;
-        if (c >= J.cols) continue;
+        // Lanes past the last column work on the last column and store
+        // nothing, so control flow stays uniform (uniform loads stay scalar).
+        const int64_t c_lane = (u - i * J.col_tiles) * kBlock + tid;
+        const bool valid = c_lane < J.cols;
+        const int64_t c = valid ? c_lane : J.cols - 1;
         const auto src = gptr(J.res + i * J.ldr + c);
-        const auto pc = gptr(pc_all + J.prime_begin);
-        const auto garner = gptr(garner_all + (int64_t)J.prime_begin * kCrtMaxL);
-        const auto half = gptr(J.half);
+        const auto pc = cptr(pc_all + J.prime_begin);
+        const auto garner = cptr(garner_all + (int64_t)J.prime_begin * kCrtMaxL);
+        const auto half = cptr(J.half);
         const int L = J.L;
         const int64_t ps = J.ps;
-        // Garner digits.
+        // All residues of this entry into its digit column, eight loads in
+        // flight at a time.
+        for (int j0 = 0; j0 < L; j0 += 8) {
+            uint32_t r[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = src[(int64_t)min(j0 + q, L - 1) * ps];   // in bounds
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (j0 + q < L) vd[j0 + q][tid] = r[q];
+        }
+        // Garner digits, each overwriting its residue.
         for (int j = 0; j < L; ++j) {
             const PC2 P{pc[j].pf, pc[j].pinv};
-            double tj = (double)src[(int64_t)j * ps];
+            double tj = (double)vd[j][tid];
             const auto gj = garner + (int64_t)j * kCrtMaxL;
             for (int q = 0; q < j; ++q) {
                 const double x = (tj - (double)vd[q][tid]) * gj[j - q];
@@ -150,6 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
         bool fits;
         if (!neg) fits = high_zero && (top >> 63) == 0;
         else fits = high_zero && ((top >> 63) == 0 || (top == (1ull << 63) && low_zero));
+        if (!valid) continue;
         if (!fits) atomicOr(J.status, 1);
         // Two's complement of the signed value, low W words.
         const auto dst = gptr_w(J.out + (i * J.ldo + c) * W);
@@ -189,38 +203,49 @@ __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJ
         const CrtJob J = njobs > 0 ? jobs[qj] : job0;
         const int64_t u = t - J.tile_begin;
         const int64_t i = u / J.col_tiles;
-        const int64_t c = (u - i * J.col_tiles) * kBlock + threadIdx.x;
-        if (c >= J.cols) continue;
+        // Lanes past the last column work on the last column and store
+        // nothing, so control flow stays uniform (uniform loads stay scalar).
+        const int64_t c_lane = (u - i * J.col_tiles) * kBlock + threadIdx.x;
+        const bool valid = c_lane < J.cols;
+        const int64_t c = valid ? c_lane : J.cols - 1;
         const auto src = gptr(J.res + i * J.ldr + c);
-        const auto pc = gptr(pc_all + J.prime_begin);
-        const auto cinv = gptr(J.lag_c);
-        const auto mj = gptr(J.lag_mj);
-        const auto mw = gptr(J.lag_m);
+        const auto pc = cptr(pc_all + J.prime_begin);
+        const auto cinv = cptr(J.lag_c);
+        const auto mj = cptr(J.lag_mj);
+        const auto mw = cptr(J.lag_m);
         const int L = J.L;
         const int64_t ps = J.ps;
         uint64_t x[WT];
 #pragma unroll
         for (int k = 0; k < WT; ++k) x[k] = 0;
         double alpha = 0.0;
-        for (int j = 0; j < L; ++j) {
-            const PC2 P{pc[j].pf, pc[j].pinv};
-            double y = modp((double)src[(int64_t)j * ps] * cinv[j], P);
-            y = y < 0.0 ? y + P.pf : y;
-            alpha = fma(y, P.pinv, alpha);
-            const uint64_t yi = (uint64_t)y;
-            const auto m = mj + (int64_t)j * W;
-            uint64_t carry = 0;
+        for (int j0 = 0; j0 < L; j0 += 8) {
+            uint32_t r[8];                        // eight loads in flight at a time
 #pragma unroll
-            for (int k = 0; k < WT; ++k) {
-                if (k < W) {
-                    const uint64_t lo = m[k] * yi;
-                    const uint64_t hi = __umul64hi(m[k], yi);
-                    const uint64_t s1 = lo + carry;
-                    const uint64_t c1 = s1 < lo ? 1 : 0;
-                    const uint64_t s2 = x[k] + s1;
-                    const uint64_t c2 = s2 < x[k] ? 1 : 0;
-                    x[k] = s2;
-                    carry = hi + c1 + c2;
+            for (int q = 0; q < 8; ++q) r[q] = src[(int64_t)min(j0 + q, L - 1) * ps];   // in bounds
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + q;
+                if (j >= L) break;
+                const PC2 P{pc[j].pf, pc[j].pinv};
+                double y = modp((double)r[q] * cinv[j], P);
+                y = y < 0.0 ? y + P.pf : y;
+                alpha = fma(y, P.pinv, alpha);
+                const uint64_t yi = (uint64_t)y;
+                const auto m = mj + (int64_t)j * W;
+                uint64_t carry = 0;
+#pragma unroll
+                for (int k = 0; k < WT; ++k) {
+                    if (k < W) {
+                        const uint64_t lo = m[k] * yi;
+                        const uint64_t hi = __umul64hi(m[k], yi);
+                        const uint64_t s1 = lo + carry;
+                        const uint64_t c1 = s1 < lo ? 1 : 0;
+                        const uint64_t s2 = x[k] + s1;
+                        const uint64_t c2 = s2 < x[k] ? 1 : 0;
+                        x[k] = s2;
+                        carry = hi + c1 + c2;
+                    }
                 }
             }
         }
@@ -242,6 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJ
                 borrow = b1 + b2;
             }
         }
+        if (!valid) continue;
         const auto dst = gptr_w(J.out + (i * J.ldo + c) * W);
 #pragma unroll
         for (int k = 0; k < WT; ++k)

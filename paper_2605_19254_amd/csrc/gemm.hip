@@ -131,12 +131,12 @@ int choose_variant(rns_ctx *ctx, bool int8, const Plan &plan) {
     if (!int8) return 0;
     if (ctx->int8_kernel >= 0) return ctx->int8_kernel;
     auto it = ctx->tune.find(tune_key(int8, plan));
-    return it != ctx->tune.end() ? it->second : kI8Lds;
+    return it != ctx->tune.end() ? it->second : kI8Default;
 }
 
 int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np, int64_t tiles,
              int64_t units, const int32_t *tile_prob, unsigned *counter, hipStream_t s) {
-    const bool persistent = int8 && variant == kI8LdsPersistent;
+    const bool persistent = int8 && variant == kI8HalfPersistent;
     {
         ProfScope ps(ctx, int8 ? "k_prep_i8" : "k_prep_f64", s);
         launch_prep(int8, dP, np, units, (const PrimeConst *)ctx->d_prime,

@@ -91,7 +91,8 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Launchers (one per kernel family), all asynchronous on `s`.
 // INT8 GEMM variants (the autotuner chooses among them per shape class).
-enum { kI8Lds = 0, kI8Direct = 1, kI8LdsPersistent = 2, kI8Lds3 = 3, kI8NumVariants = 4 };
+enum { kI8Lds = 0, kI8Direct = 1, kI8HalfPersistent = 2, kI8Wave8 = 3, kI8Half = 4, kI8NumVariants = 5 };
+constexpr int kI8Default = kI8Half;
 
 void launch_prep(bool int8, const GemmProblem *P, int nprob, int64_t units,
                  const PrimeConst *pc, unsigned *counter, hipStream_t s);

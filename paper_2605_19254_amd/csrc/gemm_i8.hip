@@ -10,8 +10,17 @@
 // every product of two balanced residues is below 2^50 and seven of them
 // stay below 2^53.
 //
-// Work-group tile 64 x 128: four waves in 2 x 2, each owning 32 x 64 outputs
-// (2 x 4 blocks of 16 x 16) for all 7 groups, i.e. 224 accumulator registers.
+// Every variant covers the same 64 x 128 output tiles (the host's tiling):
+//   direct   four waves in 2 x 2, each 32 x 64 outputs, operands straight from
+//            L2 into registers;
+//   lds      the same waves, operands staged through LDS;
+//   wave8    eight waves in 2 x 4, each 32 x 32 outputs, two waves per SIMD;
+//   half     two independent work-groups per tile (one per 64-column half),
+//            four waves of 32 x 32 each, two work-groups per CU;
+//   half, persistent  the half kernel taking half-tiles from a work counter.
+// Measured on MI355X: a single wave per SIMD cannot keep the matrix unit busy
+// with 16x16x64 INT8 MFMAs, so the two-waves-per-SIMD forms are faster; the
+// half form, whose work-groups do not share a barrier, is the default.
 #include "gemm_common.hpp"
 
 #include <algorithm>
@@ -111,24 +120,36 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const GemmProblem *__restrict__
             }
 }
 
-// ------------------------------------------------- INT8 GEMM, LDS pipeline --
-// Same tiles and arithmetic as k_gemm_i8, but the work-group's A and B digit
-// tiles of one 64-k step (4 + 8 row/col blocks x 4 digits = 48 fragments of
-// 1 KiB) are copied global -> LDS with 16-byte direct loads into two
-// alternating buffers, and each wave reads its fragments from LDS.  The two
-// waves that share an A (B) panel read it once from L2 instead of twice, and
-// no registers hold prefetched fragments.
+// ------------------------------------------------- LDS-staged INT8 tiles --
+// A work-group of WY x WX waves, each owning RB x CB blocks of 16 x 16
+// outputs for all 7 shift groups, covers WY*RB 16-row blocks and WX*CB
+// 16-column blocks.  The operand fragments of one 64-k step (A: WY*RB blocks x
+// 4 digits, B: WX*CB blocks x 4 digits, 1 KiB each) are copied global -> LDS
+// with 16-byte direct loads into two alternating buffers, split evenly over
+// the waves, and each wave reads its own fragments from LDS.
 //
-// Order inside a step: wait for this wave's copies of step kt, barrier (now
-// every wave's copies of step kt are in LDS and every wave has finished
-// reading step kt-1), read the fragments of step kt, start the copies of step
-// kt+1 into the other buffer, then run the 128 MFMAs of step kt while those
-// copies are in flight.
-
-constexpr int kI8FragA = 2 * kI8WaveRB * 4;           // A fragments per 64-k step
-constexpr int kI8FragB = 2 * kI8WaveCB * 4;           // B fragments per 64-k step
-constexpr int kI8Frag = kI8FragA + kI8FragB;          // 48
-constexpr int kI8FragPerWave = kI8Frag / 4;           // 12
+// Order inside a step: wait for this wave's copies of step kt, barrier (every
+// wave's copies of step kt are in LDS and every wave has finished reading
+// step kt-1), read the fragments of step kt, start the copies of step kt+1
+// into the other buffer, then run the MFMAs of step kt while those copies are
+// in flight.  Reading before starting the next copies keeps the compiler from
+// waiting for those copies before the reads.
+template <int WY, int WX, int RB, int CB>
+struct I8Shape {
+    static constexpr int kWY = WY, kWX = WX, kRB = RB, kCB = CB;
+    static constexpr int kWaves = WY * WX;
+    static constexpr int kFragA = WY * RB * 4, kFragB = WX * CB * 4, kFrag = kFragA + kFragB;
+    static constexpr int kFragPerWave = kFrag / kWaves;
+    static_assert(kFrag % kWaves == 0, "copies split evenly over the waves");
+};
+using ShapeLds = I8Shape<2, 2, 2, 4>;     // 64 x 128, 4 waves of 32 x 64
+using ShapeW8 = I8Shape<2, 4, 2, 2>;      // 64 x 128, 8 waves of 32 x 32
+using ShapeHalf = I8Shape<2, 2, 2, 2>;    // 64 x 64, 4 waves of 32 x 32
+static_assert(ShapeLds::kWY * ShapeLds::kRB * 16 == kI8TileM && ShapeLds::kWX * ShapeLds::kCB * 16 == kI8TileN,
+              "tile shape");
+static_assert(ShapeW8::kWY * ShapeW8::kRB * 16 == kI8TileM && ShapeW8::kWX * ShapeW8::kCB * 16 == kI8TileN,
+              "tile shape");
+static_assert(2 * ShapeHalf::kWX * ShapeHalf::kCB * 16 == kI8TileN, "two halves make a tile");
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -144,278 +165,148 @@ __device__ __forceinline__ void plain_barrier() {
     asm volatile("" ::: "memory");
 }
 
-__device__ __forceinline__ void i8_lds_tile(const GemmProblem *__restrict__ P, int nprob,
-                                            int64_t t, const PrimeConst *__restrict__ pc,
-                                            const int32_t *__restrict__ tile_prob,
-                                            v4i (*sbuf)[kI8Frag * 64]) {
-    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
-    const GemmProblem &g = P[tc.q];
+// One work-group tile: 16-row blocks from rblk0, 16-column blocks from cblk0.
+template <class S>
+__device__ __forceinline__ void i8_lds_tile(const GemmProblem &g, int plane, int rblk0, int cblk0,
+                                            const PrimeConst *__restrict__ pc,
+                                            v4i (*sbuf)[S::kFrag * 64]) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int wy = wave >> 1, wx = wave & 1;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wy = wave / S::kWX, wx = wave % S::kWX;
     const int KT = g.KT;
-    const char *Ag = g.At + (int64_t)tc.plane * g.a_plane_bytes +
-                     (int64_t)tc.tm * (2 * kI8WaveRB) * KT * 4096 + lane * 16;
-    const char *Bg = g.Bt + (int64_t)tc.plane * g.b_plane_bytes +
-                     (int64_t)tc.tn * (2 * kI8WaveCB) * KT * 4096 + lane * 16;
-    // Fragment f of a step: f < kI8FragA is A block f/4, digit f%4; otherwise
-    // B block (f-kI8FragA)/4, digit (f-kI8FragA)%4.  Wave w copies f = 12w..12w+11.
-    const char *src[kI8FragPerWave];
+    const char *Ag = g.At + (int64_t)plane * g.a_plane_bytes + (int64_t)rblk0 * KT * 4096 + lane * 16;
+    const char *Bg = g.Bt + (int64_t)plane * g.b_plane_bytes + (int64_t)cblk0 * KT * 4096 + lane * 16;
+    // Fragment f of a step: f < kFragA is A block f/4, digit f%4; otherwise
+    // B block (f-kFragA)/4, digit (f-kFragA)%4.  Wave w copies
+    // f = w*kFragPerWave .. (w+1)*kFragPerWave-1.
+    const char *src[S::kFragPerWave];
 #pragma unroll
-    for (int i = 0; i < kI8FragPerWave; ++i) {
-        const int f = wave * kI8FragPerWave + i;
-        src[i] = f < kI8FragA ? Ag + ((int64_t)(f >> 2) * KT) * 4096 + (f & 3) * 1024
-                              : Bg + ((int64_t)((f - kI8FragA) >> 2) * KT) * 4096 + ((f - kI8FragA) & 3) * 1024;
+    for (int i = 0; i < S::kFragPerWave; ++i) {
+        const int f = wave * S::kFragPerWave + i;
+        src[i] = f < S::kFragA ? Ag + ((int64_t)(f >> 2) * KT) * 4096 + (f & 3) * 1024
+                               : Bg + ((int64_t)((f - S::kFragA) >> 2) * KT) * 4096 + ((f - S::kFragA) & 3) * 1024;
     }
     auto issue = [&](v4i *buf, int kt) {
 #pragma unroll
-        for (int i = 0; i < kI8FragPerWave; ++i) {
-            const int f = wave * kI8FragPerWave + i;
+        for (int i = 0; i < S::kFragPerWave; ++i) {
+            const int f = wave * S::kFragPerWave + i;
             __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)kt * 4096),
                                              (lds_void *)(buf + f * 64), 16, 0, 0);
         }
     };
 
-    v4i acc[7][kI8WaveRB][kI8WaveCB];
+    v4i acc[7][S::kRB][S::kCB];
 #pragma unroll
     for (int s = 0; s < 7; ++s)
 #pragma unroll
-        for (int i = 0; i < kI8WaveRB; ++i)
+        for (int i = 0; i < S::kRB; ++i)
 #pragma unroll
-            for (int j = 0; j < kI8WaveCB; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+            for (int j = 0; j < S::kCB; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
 
     issue(sbuf[0], 0);
     for (int kt = 0; kt < KT; ++kt) {
         const v4i *cur = sbuf[kt & 1];
         vm_wait_0();
         plain_barrier();
-        v4i a[kI8WaveRB][4], b[kI8WaveCB][4];
+        v4i a[S::kRB][4], b[S::kCB][4];
 #pragma unroll
-        for (int i = 0; i < kI8WaveRB; ++i)
+        for (int i = 0; i < S::kRB; ++i)
 #pragma unroll
-            for (int d = 0; d < 4; ++d) a[i][d] = cur[((wy * kI8WaveRB + i) * 4 + d) * 64 + lane];
+            for (int d = 0; d < 4; ++d) a[i][d] = cur[((wy * S::kRB + i) * 4 + d) * 64 + lane];
 #pragma unroll
-        for (int j = 0; j < kI8WaveCB; ++j)
+        for (int j = 0; j < S::kCB; ++j)
 #pragma unroll
-            for (int d = 0; d < 4; ++d) b[j][d] = cur[(kI8FragA + (wx * kI8WaveCB + j) * 4 + d) * 64 + lane];
+            for (int d = 0; d < 4; ++d) b[j][d] = cur[(S::kFragA + (wx * S::kCB + j) * 4 + d) * 64 + lane];
         if (kt + 1 < KT) issue(sbuf[(kt + 1) & 1], kt + 1);
 #pragma unroll
         for (int da = 0; da < 4; ++da)
 #pragma unroll
             for (int db = 0; db < 4; ++db)
 #pragma unroll
-                for (int i = 0; i < kI8WaveRB; ++i)
+                for (int i = 0; i < S::kRB; ++i)
 #pragma unroll
-                    for (int j = 0; j < kI8WaveCB; ++j)
+                    for (int j = 0; j < S::kCB; ++j)
                         acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
                             a[i][da], b[j][db], acc[da + db][i][j], 0, 0, 0);
     }
 
-    const int rb0 = tc.tm * (2 * kI8WaveRB) + wy * kI8WaveRB;
-    const int cb0 = tc.tn * (2 * kI8WaveCB) + wx * kI8WaveCB;
-    const PrimeConst pr = pc[g.prime_begin + tc.plane];
-    uint32_t *C = g.C + (int64_t)tc.plane * g.cps;
+    const PrimeConst pr = pc[g.prime_begin + plane];
+    uint32_t *C = g.C + (int64_t)plane * g.cps;
 #pragma unroll
-    for (int i = 0; i < kI8WaveRB; ++i)
+    for (int i = 0; i < S::kRB; ++i)
 #pragma unroll
-        for (int j = 0; j < kI8WaveCB; ++j)
+        for (int j = 0; j < S::kCB; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 double sum = 0.0;
 #pragma unroll
                 for (int s = 0; s < 7; ++s) {
                     const double cs = (double)acc[s][i][j][v];
-                    const double r = fma(-rint(cs * pr.pinv), pr.pf, cs);
-                    sum = fma(r, pr.w[s], sum);
+                    const double r = fma(-rint(cs * pr.pinv), pr.pf, cs);   // |r| <= p/2
+                    sum = fma(r, pr.w[s], sum);                              // |sum| < 7*2^50
                 }
                 double r = fma(-rint(sum * pr.pinv), pr.pf, sum);
                 r = r < 0.0 ? r + pr.pf : r;
-                const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + v;
-                const int col = (cb0 + j) * 16 + (lane & 15);
+                const int row = (rblk0 + wy * S::kRB + i) * 16 + 4 * (lane >> 4) + v;
+                const int col = (cblk0 + wx * S::kCB + j) * 16 + (lane & 15);
                 if (row < g.m && col < g.n) C[(int64_t)row * g.ldc + col] = (uint32_t)r;
             }
-}
-
-// ------------------------------------------- three-stage LDS pipeline --
-// As i8_lds_tile, with three LDS buffers so that the copies of two later steps
-// are in flight while a step computes.  The fragments of a step are read with
-// one inline-assembly block of 24 ds_read_b128 that waits for its own reads
-// before it ends; the compiler therefore does not wait for the outstanding
-// copies before those reads (it cannot tell the buffers apart), and the
-// explicit vmcnt wait before the barrier covers exactly the copies of the
-// step about to be read.
-
-__device__ __forceinline__ void vm_wait_12() { __builtin_amdgcn_s_waitcnt(0x0F7C); }  // vmcnt(12)
-
-__device__ __forceinline__ void lds_read_step(uint32_t a_addr, uint32_t b_addr,
-                                              v4i (&a)[kI8WaveRB][4], v4i (&b)[kI8WaveCB][4]) {
-    static_assert(kI8WaveRB == 2 && kI8WaveCB == 4, "read block is written for 2 x 4 blocks");
-    asm volatile(
-        "ds_read_b128 %0, %24\n"
-        "ds_read_b128 %1, %24 offset:1024\n"
-        "ds_read_b128 %2, %24 offset:2048\n"
-        "ds_read_b128 %3, %24 offset:3072\n"
-        "ds_read_b128 %4, %24 offset:4096\n"
-        "ds_read_b128 %5, %24 offset:5120\n"
-        "ds_read_b128 %6, %24 offset:6144\n"
-        "ds_read_b128 %7, %24 offset:7168\n"
-        "ds_read_b128 %8, %25\n"
-        "ds_read_b128 %9, %25 offset:1024\n"
-        "ds_read_b128 %10, %25 offset:2048\n"
-        "ds_read_b128 %11, %25 offset:3072\n"
-        "ds_read_b128 %12, %25 offset:4096\n"
-        "ds_read_b128 %13, %25 offset:5120\n"
-        "ds_read_b128 %14, %25 offset:6144\n"
-        "ds_read_b128 %15, %25 offset:7168\n"
-        "ds_read_b128 %16, %25 offset:8192\n"
-        "ds_read_b128 %17, %25 offset:9216\n"
-        "ds_read_b128 %18, %25 offset:10240\n"
-        "ds_read_b128 %19, %25 offset:11264\n"
-        "ds_read_b128 %20, %25 offset:12288\n"
-        "ds_read_b128 %21, %25 offset:13312\n"
-        "ds_read_b128 %22, %25 offset:14336\n"
-        "ds_read_b128 %23, %25 offset:15360\n"
-        "s_waitcnt lgkmcnt(0)\n"
-        : "=&v"(a[0][0]), "=&v"(a[0][1]), "=&v"(a[0][2]), "=&v"(a[0][3]),
-          "=&v"(a[1][0]), "=&v"(a[1][1]), "=&v"(a[1][2]), "=&v"(a[1][3]),
-          "=&v"(b[0][0]), "=&v"(b[0][1]), "=&v"(b[0][2]), "=&v"(b[0][3]),
-          "=&v"(b[1][0]), "=&v"(b[1][1]), "=&v"(b[1][2]), "=&v"(b[1][3]),
-          "=&v"(b[2][0]), "=&v"(b[2][1]), "=&v"(b[2][2]), "=&v"(b[2][3]),
-          "=&v"(b[3][0]), "=&v"(b[3][1]), "=&v"(b[3][2]), "=&v"(b[3][3])
-        : "v"(a_addr), "v"(b_addr));
-}
-
-__device__ __forceinline__ void i8_lds3_tile(const GemmProblem *__restrict__ P, int nprob,
-                                             int64_t t, const PrimeConst *__restrict__ pc,
-                                             const int32_t *__restrict__ tile_prob,
-                                             v4i (*sbuf)[kI8Frag * 64]) {
-    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
-    const GemmProblem &g = P[tc.q];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int wy = wave >> 1, wx = wave & 1;
-    const int KT = g.KT;
-    const char *Ag = g.At + (int64_t)tc.plane * g.a_plane_bytes +
-                     (int64_t)tc.tm * (2 * kI8WaveRB) * KT * 4096 + lane * 16;
-    const char *Bg = g.Bt + (int64_t)tc.plane * g.b_plane_bytes +
-                     (int64_t)tc.tn * (2 * kI8WaveCB) * KT * 4096 + lane * 16;
-    const char *src[kI8FragPerWave];
-#pragma unroll
-    for (int i = 0; i < kI8FragPerWave; ++i) {
-        const int f = wave * kI8FragPerWave + i;
-        src[i] = f < kI8FragA ? Ag + ((int64_t)(f >> 2) * KT) * 4096 + (f & 3) * 1024
-                              : Bg + ((int64_t)((f - kI8FragA) >> 2) * KT) * 4096 + ((f - kI8FragA) & 3) * 1024;
-    }
-    auto issue = [&](v4i *buf, int kt) {
-#pragma unroll
-        for (int i = 0; i < kI8FragPerWave; ++i) {
-            const int f = wave * kI8FragPerWave + i;
-            __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)kt * 4096),
-                                             (lds_void *)(buf + f * 64), 16, 0, 0);
-        }
-    };
-    // LDS byte addresses of this wave's A and B fragments in each buffer.
-    uint32_t a_addr[3], b_addr[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        const uint32_t base = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) v4i *)sbuf[u];
-        a_addr[u] = base + (uint32_t)((wy * kI8WaveRB * 4) * 1024 + lane * 16);
-        b_addr[u] = base + (uint32_t)((kI8FragA + wx * kI8WaveCB * 4) * 1024 + lane * 16);
-    }
-
-    v4i acc[7][kI8WaveRB][kI8WaveCB];
-#pragma unroll
-    for (int s = 0; s < 7; ++s)
-#pragma unroll
-        for (int i = 0; i < kI8WaveRB; ++i)
-#pragma unroll
-            for (int j = 0; j < kI8WaveCB; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
-
-    issue(sbuf[0], 0);
-    if (KT > 1) issue(sbuf[1], 1);
-    int cur = 0;
-    for (int kt = 0; kt < KT; ++kt) {
-        if (kt + 1 < KT) vm_wait_12(); else vm_wait_0();
-        plain_barrier();
-        v4i a[kI8WaveRB][4], b[kI8WaveCB][4];
-        lds_read_step(a_addr[cur], b_addr[cur], a, b);
-        const int nxt2 = cur == 0 ? 2 : cur - 1;      // buffer of step kt+2 = buffer of step kt-1
-        if (kt + 2 < KT) issue(sbuf[nxt2], kt + 2);
-#pragma unroll
-        for (int da = 0; da < 4; ++da)
-#pragma unroll
-            for (int db = 0; db < 4; ++db)
-#pragma unroll
-                for (int i = 0; i < kI8WaveRB; ++i)
-#pragma unroll
-                    for (int j = 0; j < kI8WaveCB; ++j)
-                        acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                            a[i][da], b[j][db], acc[da + db][i][j], 0, 0, 0);
-        cur = cur == 2 ? 0 : cur + 1;
-    }
-
-    const int rb0 = tc.tm * (2 * kI8WaveRB) + wy * kI8WaveRB;
-    const int cb0 = tc.tn * (2 * kI8WaveCB) + wx * kI8WaveCB;
-    const PrimeConst pr = pc[g.prime_begin + tc.plane];
-    uint32_t *C = g.C + (int64_t)tc.plane * g.cps;
-#pragma unroll
-    for (int i = 0; i < kI8WaveRB; ++i)
-#pragma unroll
-        for (int j = 0; j < kI8WaveCB; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double sum = 0.0;
-#pragma unroll
-                for (int s = 0; s < 7; ++s) {
-                    const double cs = (double)acc[s][i][j][v];
-                    const double r = fma(-rint(cs * pr.pinv), pr.pf, cs);
-                    sum = fma(r, pr.w[s], sum);
-                }
-                double r = fma(-rint(sum * pr.pinv), pr.pf, sum);
-                r = r < 0.0 ? r + pr.pf : r;
-                const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + v;
-                const int col = (cb0 + j) * 16 + (lane & 15);
-                if (row < g.m && col < g.n) C[(int64_t)row * g.ldc + col] = (uint32_t)r;
-            }
-}
-
-__global__ __launch_bounds__(256) void k_gemm_i8_lds3(const GemmProblem *__restrict__ P, int nprob,
-                                                      int64_t total_tiles,
-                                                      const PrimeConst *__restrict__ pc,
-                                                      const int32_t *__restrict__ tile_prob) {
-    __shared__ v4i sbuf[3][kI8Frag * 64];
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t >= total_tiles) return;
-    i8_lds3_tile(P, nprob, t, pc, tile_prob, sbuf);
 }
 
 __global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restrict__ P, int nprob,
                                                      int64_t total_tiles,
                                                      const PrimeConst *__restrict__ pc,
-        const int32_t *__restrict__ tile_prob) {
-    __shared__ v4i sbuf[2][kI8Frag * 64];
+                                                     const int32_t *__restrict__ tile_prob) {
+    __shared__ v4i sbuf[2][ShapeLds::kFrag * 64];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     if (t >= total_tiles) return;
-    i8_lds_tile(P, nprob, t, pc, tile_prob, sbuf);
+    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
+    i8_lds_tile<ShapeLds>(P[tc.q], tc.plane, tc.tm * 4, tc.tn * 8, pc, sbuf);
 }
 
-// Persistent form: one work-group per CU takes tiles from a counter in tile
-// order (the host sorts problems by decreasing tile cost, so the longest
+__global__ __launch_bounds__(512) void k_gemm_i8_w8(const GemmProblem *__restrict__ P, int nprob,
+                                                    int64_t total_tiles,
+                                                    const PrimeConst *__restrict__ pc,
+                                                    const int32_t *__restrict__ tile_prob) {
+    __shared__ v4i sbuf[2][ShapeW8::kFrag * 64];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= total_tiles) return;
+    const TileCoord tc = map_tile(P, nprob, t, tile_prob);
+    i8_lds_tile<ShapeW8>(P[tc.q], tc.plane, tc.tm * 4, tc.tn * 8, pc, sbuf);
+}
+
+// Half tiles: launch index h2 covers tile h2/2, column half h2%2.  The two
+// halves of a tile are adjacent in launch order and so run on the same XCD,
+// where they share the A panel in L2.
+__global__ __launch_bounds__(256, 2) void k_gemm_i8_half(const GemmProblem *__restrict__ P, int nprob,
+                                                         int64_t total_tiles,
+                                                         const PrimeConst *__restrict__ pc,
+                                                         const int32_t *__restrict__ tile_prob) {
+    __shared__ v4i sbuf[2][ShapeHalf::kFrag * 64];
+    const int64_t h2 = xcd_remap(blockIdx.x, gridDim.x);
+    if (h2 >= 2 * total_tiles) return;
+    const TileCoord tc = map_tile(P, nprob, h2 >> 1, tile_prob);
+    i8_lds_tile<ShapeHalf>(P[tc.q], tc.plane, tc.tm * 4, tc.tn * 8 + (int)(h2 & 1) * 4, pc, sbuf);
+}
+
+// Persistent form: two work-groups per CU take half-tiles from a counter in
+// tile order (the host sorts problems by decreasing tile cost, so the longest
 // tiles go first).  The counter is reset by the prep kernel of the same call.
-__global__ __launch_bounds__(256) void k_gemm_i8_lds_persistent(const GemmProblem *__restrict__ P,
-                                                                int nprob, int64_t total_tiles,
-                                                                const PrimeConst *__restrict__ pc,
-                                                                const int32_t *__restrict__ tile_prob,
-                                                                unsigned *__restrict__ counter) {
-    __shared__ v4i sbuf[2][kI8Frag * 64];
+__global__ __launch_bounds__(256, 2) void k_gemm_i8_half_persistent(const GemmProblem *__restrict__ P,
+                                                                    int nprob, int64_t total_tiles,
+                                                                    const PrimeConst *__restrict__ pc,
+                                                                    const int32_t *__restrict__ tile_prob,
+                                                                    unsigned *__restrict__ counter) {
+    __shared__ v4i sbuf[2][ShapeHalf::kFrag * 64];
     __shared__ unsigned next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
         __syncthreads();
-        const int64_t t = __builtin_amdgcn_readfirstlane((int)next);   // uniform tile index
+        const int64_t h2 = (unsigned)__builtin_amdgcn_readfirstlane((int)next);   // uniform
         __syncthreads();
-        if (t >= total_tiles) break;
-        i8_lds_tile(P, nprob, t, pc, tile_prob, sbuf);
+        if (h2 >= 2 * total_tiles) break;
+        const TileCoord tc = map_tile(P, nprob, h2 >> 1, tile_prob);
+        i8_lds_tile<ShapeHalf>(P[tc.q], tc.plane, tc.tm * 4, tc.tn * 8 + (int)(h2 & 1) * 4, pc, sbuf);
     }
 }
 
@@ -426,14 +317,17 @@ void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
                     int num_cus, hipStream_t s) {
     if (variant == kI8Direct) {
         hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
-    } else if (variant == kI8Lds3) {
-        hipLaunchKernelGGL(k_gemm_i8_lds3, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
-    } else if (variant == kI8LdsPersistent && counter) {
-        const int64_t grid = std::min<int64_t>(tiles, num_cus);
-        hipLaunchKernelGGL(k_gemm_i8_lds_persistent, dim3((unsigned)grid), dim3(256), 0, s, P, nprob,
+    } else if (variant == kI8Lds) {
+        hipLaunchKernelGGL(k_gemm_i8_lds, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
+    } else if (variant == kI8Wave8) {
+        hipLaunchKernelGGL(k_gemm_i8_w8, dim3((unsigned)tiles), dim3(512), 0, s, P, nprob, tiles, pc, tile_prob);
+    } else if (variant == kI8HalfPersistent && counter) {
+        const int64_t grid = std::min<int64_t>(2 * tiles, 2 * (int64_t)num_cus);
+        hipLaunchKernelGGL(k_gemm_i8_half_persistent, dim3((unsigned)grid), dim3(256), 0, s, P, nprob,
                            tiles, pc, tile_prob, counter);
     } else {
-        hipLaunchKernelGGL(k_gemm_i8_lds, dim3((unsigned)tiles), dim3(256), 0, s, P, nprob, tiles, pc, tile_prob);
+        hipLaunchKernelGGL(k_gemm_i8_half, dim3((unsigned)(2 * tiles)), dim3(256), 0, s, P, nprob, tiles,
+                           pc, tile_prob);
     }
 }
 

@@ -44,6 +44,12 @@ template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T *gptr_w(T *p) {
     return (__attribute__((address_space(1))) T *)p;
 }
+// Tables that no kernel writes while it reads them (prime constants, CRT
+// weights): the constant address space lets uniform loads use the scalar path.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *cptr(const T *p) {
+    return (const __attribute__((address_space(4))) T *)p;
+}
 
 // Garner band: for a prime index j and a distance d in [1, kCrtMaxL),
 // garner[j*kCrtMaxL + d] = p_{j-d}^{-1} mod p_j (as a double), 0 where j < d.

@@ -74,7 +74,7 @@ def test_gemm_plan_all_variants_uneven(ctx, rg, torch_dev):
     gps = [rg.GemmProblem(a, b, c, bg) for a, b, c, bg in probs]
     plan = rg.GemmPlan(ctx, gps, path="int8")
     outs = []
-    for v in (0, 1, 2, 3):
+    for v in (0, 1, 2, 3, 4):
         for _, _, c, _ in probs:
             c.fill_(-1)
         plan.set_variant(v)
@@ -84,7 +84,7 @@ def test_gemm_plan_all_variants_uneven(ctx, rg, torch_dev):
         outs.append([c.cpu().numpy() for _, _, c, _ in probs])
     for (a, b, ps), got in zip(host, outs[0]):
         _check_residues(got, a, b, ps)
-    for v in (1, 2, 3):
+    for v in (1, 2, 3, 4):
         for x, y in zip(outs[0], outs[v]):
             assert np.array_equal(x, y)
     info = plan.info()
@@ -155,7 +155,7 @@ def test_matmul_plan_graph_replay(ctx, rg, torch_dev):
                                       torch.empty((pr.m, pr.n), dtype=torch.int64, device=dev),
                                       prime_begin=0, L=2, bound=pr.k << 32))
     want = [native.exact_matmul(pr.a, pr.b) for pr in batch]
-    for variant in (0, 2):
+    for variant in (0, 2, 4):
         plan = rg.MatmulPlan(ctx, probs, path="int8")
         plan.set_variant(variant)
         plan.execute()                       # warm-up outside the capture
@@ -191,7 +191,7 @@ def test_autotune_and_cache(ctx, rg, torch_dev):
         path = os.path.join(d, "tune.txt")
         ctx.set_tune_cache(path)
         v = rg.autotune(ctx, gps, path="int8")
-        assert v in (0, 1, 2, 3)
+        assert v in (0, 1, 2, 3, 4)
         torch.cuda.synchronize()
         for (a, b, ps), (_, _, c, _) in zip(host, probs):
             _check_residues(c.cpu().numpy(), a, b, ps)

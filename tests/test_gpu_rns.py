@@ -265,7 +265,7 @@ def test_exact_product_small(ctx, rg, torch_dev, path):
     assert ctx.status() == 0
 
 
-@pytest.mark.parametrize("path", ["int8", "fp64", "int8-lds3"])
+@pytest.mark.parametrize("path", ["int8", "fp64", "int8-v0", "int8-v2", "int8-v3"])
 def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
     """The full n = 4096, 24-prime product in the benchmark's configuration;
     sampled outputs against the oracle, plus every residue of sampled rows."""
@@ -277,9 +277,9 @@ def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
     ra = rg.rns_reduce(ctx, ta, L=L)
     rb = rg.rns_reduce(ctx, tb, L=L)
     rc = torch.empty((L, n, n), dtype=torch.int32, device=dev)
-    if path == "int8-lds3":
+    if path.startswith("int8-v"):
         plan = rg.GemmPlan(ctx, [rg.GemmProblem(ra, rb, rc)], path="int8")
-        plan.set_variant(3)
+        plan.set_variant(int(path[len("int8-v"):]))
         plan.execute()
     else:
         rg.modmatmul_batched(ctx, [rg.GemmProblem(ra, rb, rc)], path=path)
