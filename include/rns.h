@@ -296,12 +296,24 @@ typedef struct rns_smith_stats {
     double t_uc;           /* seconds: certification (Phase 3) */
     double t_total;        /* seconds: whole call */
     int restarts;          /* Las Vegas restarts taken */
-    int lift_steps;        /* primes for which A^-1 mod q was computed */
+    int lift_steps;        /* path 0: primes for which A^-1 mod q was
+                              computed; path 1: p-adic lifting steps */
     int64_t products;      /* modmatmul_batched calls issued */
     double residue_ops;    /* 2*m*n*k*L summed over all products */
-    int cert_primes;       /* primes of the exact check A X = s I */
+    int cert_primes;       /* path 0: primes of the exact check A X = s I;
+                              path 1: primes of det A / s */
     int columns;           /* columns of the projection J (n: J = I) */
+    int path;              /* 0: residues of s A^-1 (J = I); 1: p-adic lifting */
+    int cert_exact;        /* 1: the certificate is exact; 0: det A / s was
+                              taken from an early-terminated reconstruction */
 } rns_smith_stats;
+
+/*
+ * rns_ctx_set_smith_path -- which Smith-form path smith_form takes:
+ * 0 (default) chooses, 1 residue reconstruction of s A^-1 only, 2 p-adic
+ * lifting only (RNS_ENOTSUP from smith_form where that path does not apply).
+ */
+int rns_ctx_set_smith_path(rns_ctx *ctx, int path);
 
 /*
  * smith_form -- the Smith normal form S = diag(s_1, ..., s_n),
@@ -310,10 +322,19 @@ typedef struct rns_smith_stats {
  * invariant factor s from rational reconstruction of A^-1 b; X = s A^-1 from
  * residues (A^-1 mod q by GPU Gauss-Jordan, products by modmatmul_batched,
  * combination by crt_reconstruct), certified by an exact check A X = s I on
- * fresh primes; the Smith form of X over Z/sZ gives s_i.  Limits: the
- * reconstruction uses at most 64 primes per CRT, so |s A^-1| and the
- * numerators and denominators of A^-1 b must stay below about 2^1600
- * (RNS_ENOTSUP beyond); entries must not be INT64_MIN.
+ * fresh primes; the Smith form of X over Z/sZ gives s_i.  This path (0)
+ * uses at most 64 primes per CRT, so |s A^-1| and the numerators and
+ * denominators of A^-1 b must stay below about 2^1600.
+ * Larger invariants take the p-adic lifting path (1) when n >= 16 and
+ * n max|a_ij| < 2^36: one inverse C = A^-1 mod p stays resident and
+ * Y = A^-1 J for a random n x t matrix J is lifted p-adically on the GPU; the
+ * common denominator of random projections of Y gives s; the Smith form over
+ * Z/sZ of s R Y (R random t+2 x n) gives the t largest invariants (t doubles
+ * up to 16 while fewer than two of them are 1); the certificate checks
+ * prod s_i = |det A| with det A / s rebuilt from det A mod primes (exact when
+ * at most 48 primes cover Hadamard's bound over s, else early-terminated:
+ * stats.cert_exact says which).  RNS_ENOTSUP when neither path applies;
+ * entries must not be INT64_MIN.
  *   A_host: host int64, n x n row-major (copied during the call).
  *   seed:   drives the random choices only; S does not depend on it.
  *   out:    receives a library-allocated result; free with rns_smith_free.

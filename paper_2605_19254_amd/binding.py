@@ -79,7 +79,7 @@ class RnsSmithStats(ctypes.Structure):
                 ("t_uc", ctypes.c_double), ("t_total", ctypes.c_double),
                 ("restarts", _I32), ("lift_steps", _I32), ("products", _I64),
                 ("residue_ops", ctypes.c_double), ("cert_primes", _I32),
-                ("columns", _I32)]
+                ("columns", _I32), ("path", _I32), ("cert_exact", _I32)]
 
 
 def _sig(name, res, args):
@@ -105,6 +105,7 @@ _lib_crt = _sig("crt_reconstruct", _I32, [_P, _P, _I64, _I64, _I64, _I64, _I32, 
                                           _P, _I32, _I64, _P, _P])
 _lib_status = _sig("rns_ctx_status", _I32, [_P, _P])
 _lib_force = _sig("rns_ctx_force_cert_failures", _I32, [_P, _I32])
+_lib_smith_path = _sig("rns_ctx_set_smith_path", _I32, [_P, _I32])
 _lib_smith = _sig("smith_form", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_P)])
 _lib_smith_get = _sig("rns_smith_get", _I32, [_P, _I64, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64)),
                                               ctypes.POINTER(_I32)])
@@ -172,7 +173,8 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_ctx_set_tune_cache", "rns_autotune", "rns_gemm_plan_autotune", "rns_matmul_plan_create", "rns_matmul_plan_execute",
            "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy",
            "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
-           "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate"]
+           "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate",
+           "rns_ctx_set_smith_path"]
 
 
 class RnsError(RuntimeError):
@@ -300,6 +302,12 @@ class Context:
 
     def force_cert_failures(self, count: int):
         _check(_lib_force(self.handle, count), "rns_ctx_force_cert_failures")
+
+    SMITH_PATHS = {"auto": 0, "residue": 1, "lifting": 2}
+
+    def set_smith_path(self, path: str):
+        """Which Smith-form path smith_form takes: auto, residue or lifting."""
+        _check(_lib_smith_path(self.handle, self.SMITH_PATHS[path]), "rns_ctx_set_smith_path")
 
 
 def rns_reduce(ctx: Context, x, prime_begin: int = 0, L: Optional[int] = None, out=None, stream=None):

@@ -311,14 +311,124 @@ public:
     friend bool operator<=(const BigInt &a, const BigInt &b) { return cmp(a, b) <= 0; }
     friend bool operator>(const BigInt &a, const BigInt &b) { return cmp(a, b) > 0; }
 
+    // ---- Euclid's algorithm, Lehmer's way (Knuth TAOCP 4.5.2, Algorithm L):
+    // far from the end, runs of quotients are found from the leading 62 bits
+    // of the two remainders and applied to the full numbers as one 2 x 2
+    // matrix; the cofactor sequence (t0, t1) follows the same matrices.
+
+    // One exact step: (r0, r1) <- (r1, r0 - q r1), (t0, t1) <- (t1, t0 - q t1).
+    static void euclid_step(BigInt &r0, BigInt &r1, BigInt &t0, BigInt &t1, bool track) {
+        BigInt q, r;
+        divmod_trunc(r0, r1, q, r);
+        r0 = std::move(r1);
+        r1 = std::move(r);
+        if (track) {
+            BigInt t = t0 - q * t1;
+            t0 = std::move(t1);
+            t1 = std::move(t);
+        }
+    }
+    // floor(|x| / 2^shift) mod 2^64.
+    static uint64_t shifted_u64(const BigInt &x, size_t shift) {
+        const size_t w = shift / 32, b = shift % 32;
+        unsigned __int128 v = 0;
+        for (int i = 2; i >= 0; --i) {
+            const size_t idx = w + (size_t)i;
+            v = (v << 32) | (idx < x.mag.size() ? x.mag[idx] : 0u);
+        }
+        return (uint64_t)(v >> b);
+    }
+    // a x - b y for magnitudes when the result is >= 0 (a, b < 2^63).
+    static std::vector<uint32_t> lin_sub_mag(const std::vector<uint32_t> &x, uint64_t a,
+                                             const std::vector<uint32_t> &y, uint64_t b) {
+        const size_t n = std::max(x.size(), y.size()) + 2;
+        std::vector<uint32_t> r(n);
+        __int128 carry = 0;
+        for (size_t i = 0; i < n; ++i) {
+            const __int128 t = (__int128)(i < x.size() ? x[i] : 0u) * a -
+                               (__int128)(i < y.size() ? y[i] : 0u) * b + carry;
+            const uint32_t lo = (uint32_t)(uint64_t)t;
+            r[i] = lo;
+            carry = (t - (__int128)lo) >> 32;            // exact: t - lo is a multiple of 2^32
+        }
+        while (!r.empty() && r.back() == 0) r.pop_back();
+        return r;
+    }
+    // a x + b y for magnitudes.
+    static std::vector<uint32_t> lin_add_mag(const std::vector<uint32_t> &x, uint64_t a,
+                                             const std::vector<uint32_t> &y, uint64_t b) {
+        const size_t n = std::max(x.size(), y.size()) + 3;
+        std::vector<uint32_t> r(n);
+        unsigned __int128 carry = 0;
+        for (size_t i = 0; i < n; ++i) {
+            const unsigned __int128 t = (unsigned __int128)(i < x.size() ? x[i] : 0u) * a +
+                                        (unsigned __int128)(i < y.size() ? y[i] : 0u) * b + carry;
+            r[i] = (uint32_t)t;
+            carry = t >> 32;
+        }
+        while (!r.empty() && r.back() == 0) r.pop_back();
+        return r;
+    }
+    // Advances r0 >= r1 >= 0 (and the cofactors when track) by Lehmer runs
+    // while r1 has more than stop_bits + 130 bits; the caller finishes with
+    // euclid_step.
+    static void lehmer_run(BigInt &r0, BigInt &r1, BigInt &t0, BigInt &t1, size_t stop_bits, bool track) {
+        const __int128 lim = (__int128)1 << 62;
+        while (!r1.is_zero() && r1.bit_length() > stop_bits + 130) {
+            const size_t shift = r0.bit_length() - 62;
+            int64_t uh = (int64_t)shifted_u64(r0, shift), vh = (int64_t)shifted_u64(r1, shift);
+            int64_t A = 1, B = 0, C = 0, D = 1;
+            for (;;) {
+                const __int128 dc = (__int128)vh + C, dd = (__int128)vh + D;
+                if (dc == 0 || dd == 0) break;
+                const __int128 q1 = ((__int128)uh + A) / dc, q2 = ((__int128)uh + B) / dd;
+                if (q1 != q2) break;
+                const __int128 nC = (__int128)A - q1 * C, nD = (__int128)B - q1 * D;
+                if (nC >= lim || nC <= -lim || nD >= lim || nD <= -lim) break;
+                A = C; C = (int64_t)nC;
+                B = D; D = (int64_t)nD;
+                const int64_t nv = uh - (int64_t)q1 * vh;
+                uh = vh; vh = nv;
+            }
+            if (B == 0) {                                 // no run found: one exact step
+                euclid_step(r0, r1, t0, t1, track);
+                continue;
+            }
+            // Each matrix row (a, b) has entries of opposite signs (or a zero):
+            // a r0 + b r1 is a difference of magnitudes (the result is a
+            // remainder, >= 0); the cofactors alternate in sign, so a t0 + b t1
+            // is a sum of magnitudes with the sign of its nonzero terms.
+            auto rem = [&](int64_t a, int64_t b) {
+                BigInt r;
+                r.mag = b <= 0 ? lin_sub_mag(r0.mag, (uint64_t)a, r1.mag, (uint64_t)(-b))
+                               : lin_sub_mag(r1.mag, (uint64_t)b, r0.mag, (uint64_t)(-a));
+                return r;
+            };
+            auto cof = [&](int64_t a, int64_t b) {
+                BigInt r;
+                const uint64_t ua = (uint64_t)(a < 0 ? -a : a), ub = (uint64_t)(b < 0 ? -b : b);
+                r.mag = lin_add_mag(t0.mag, ua, t1.mag, ub);
+                const bool neg_ = (a != 0 && !t0.is_zero()) ? ((a < 0) != t0.neg) : ((b < 0) != t1.neg);
+                r.neg = neg_ && !r.mag.empty();
+                return r;
+            };
+            BigInt n0 = rem(A, B), n1 = rem(C, D);
+            if (track) {
+                BigInt s0 = cof(A, B), s1 = cof(C, D);
+                t0 = std::move(s0);
+                t1 = std::move(s1);
+            }
+            r0 = std::move(n0);
+            r1 = std::move(n1);
+        }
+    }
+
     static BigInt gcd(BigInt a, BigInt b) {
         a.neg = b.neg = false;
-        while (!b.is_zero()) {
-            BigInt q, r;
-            divmod_trunc(a, b, q, r);
-            a = std::move(b);
-            b = std::move(r);
-        }
+        if (cmp_mag(a.mag, b.mag) < 0) std::swap(a, b);
+        BigInt t0, t1;
+        lehmer_run(a, b, t0, t1, 0, false);
+        while (!b.is_zero()) euclid_step(a, b, t0, t1, false);
         return a;
     }
     static BigInt lcm(const BigInt &a, const BigInt &b) {
@@ -327,28 +437,35 @@ public:
     }
     // g = gcd(a, b) >= 0 with x*a + y*b = g.
     static BigInt xgcd(const BigInt &a0, const BigInt &b0, BigInt &x, BigInt &y) {
-        BigInt a = a0, b = b0, x0(1), y0(0), x1(0), y1(1);
-        while (!b.is_zero()) {
-            BigInt q, r;
-            divmod_floor(a, abs(b), q, r);
-            if (b.neg) q = -q;           // a = q*b + r with 0 <= r < |b|
-            a = std::move(b);
-            b = std::move(r);
-            BigInt t = x0 - q * x1;
-            x0 = std::move(x1);
-            x1 = std::move(t);
-            t = y0 - q * y1;
-            y0 = std::move(y1);
-            y1 = std::move(t);
+        if (b0.is_zero()) {
+            x = BigInt(a0.neg ? -1 : (a0.is_zero() ? 0 : 1));
+            y = BigInt(0);
+            return abs(a0);
         }
-        if (a.neg) {
-            a = -a;
-            x0 = -x0;
-            y0 = -y0;
-        }
-        x = x0;
-        y = y0;
-        return a;
+        BigInt r0 = abs(a0), r1 = abs(b0), t0(1), t1(0);     // t: cofactor of |a0|
+        if (cmp_mag(r0.mag, r1.mag) < 0) euclid_step(r0, r1, t0, t1, true);
+        lehmer_run(r0, r1, t0, t1, 0, true);
+        while (!r1.is_zero()) euclid_step(r0, r1, t0, t1, true);
+        // t0 |a0| = r0 (mod |b0|): the cofactor of |b0| follows exactly.
+        const BigInt yb = (r0 - t0 * abs(a0)) / abs(b0);
+        x = a0.neg ? -t0 : t0;
+        y = b0.neg ? -yb : yb;
+        return r0;
+    }
+    // Rational reconstruction: y mod m -> (num, den) with |num| < B, 0 < den < B
+    // and num = den y (mod m), for B = 2^floor((bits(m) - 2) / 2), so that
+    // 2 B^2 < m and such a fraction is unique.  False if none exists.  The
+    // caller checks that den is prime to m where that matters.
+    static bool rat_recon(const BigInt &y, const BigInt &m, BigInt &num, BigInt &den) {
+        const size_t bb = (m.bit_length() - 2) / 2;
+        const BigInt Bnd = BigInt(1).shl(bb);
+        BigInt r0 = m, r1 = mod(y, m), t0(0), t1(1);
+        lehmer_run(r0, r1, t0, t1, bb, true);
+        while (cmp(r1, Bnd) >= 0) euclid_step(r0, r1, t0, t1, true);
+        if (t1.is_zero() || cmp(abs(t1), Bnd) >= 0) return false;
+        num = t1.neg ? -r1 : r1;
+        den = abs(t1);
+        return true;
     }
     BigInt shl(size_t bits) const {
         BigInt r;

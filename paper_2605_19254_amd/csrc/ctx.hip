@@ -366,6 +366,12 @@ extern "C" int rns_ctx_status(rns_ctx *ctx, void *stream) {
     return h ? RNS_EOVERFLOW : RNS_OK;
 }
 
+extern "C" int rns_ctx_set_smith_path(rns_ctx *ctx, int path) {
+    if (!ctx || path < 0 || path > 2) return RNS_EINVAL;
+    ctx->smith_path = path;
+    return RNS_OK;
+}
+
 extern "C" int rns_ctx_force_cert_failures(rns_ctx *ctx, int count) {
     if (!ctx || count < 0) return RNS_EINVAL;
     ctx->force_cert_failures = count;

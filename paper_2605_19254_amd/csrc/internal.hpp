@@ -81,6 +81,7 @@ struct rns_ctx {
     std::map<std::tuple<int, int, int>, rns::LagrangeTable> lagrange;
     std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
     int force_cert_failures = 0;
+    int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
     rns_ctx *aux = nullptr;            // wide-basis context of the Smith-form driver
     int int8_kernel = -1;              // forced INT8 GEMM variant (RNS_INT8_KERNEL), -1 = tuned
     int num_cus = 256;

@@ -19,6 +19,31 @@
 // Phase 3 (certification).  With J = I and the exact check of A X = s I the
 //   result is certified; a failed check (s too small, or too few primes for X)
 //   adds primes or restarts Phase 1 with new right-hand sides (Las Vegas).
+//
+// p-adic lifting path, for matrices with small entries whose invariants are
+// too large to rebuild s A^-1 from residues (Section 3 names Dixon's lifting
+// as the solver of the integrality certification; Section 3.2 notes that its
+// set-up, A^-1 mod p, costs about as much as the lifting, which is why C stays
+// resident here across right-hand sides and restarts).
+//   Lifting.  C = A^-1 mod p once (GPU Gauss-Jordan); for a random n x t
+//     matrix J the GPU runs X_i = C R_i mod p, R_{i+1} = (R_i - A X_i) / p, so
+//     that Y = A^-1 J = sum_i X_i p^i, keeping every digit X_i; the digits are
+//     projected on the device by a random (t+2) x n matrix R (Z_i = R X_i) and
+//     only Z_i comes to the host, where Y' = R Y mod p^K is accumulated.
+//   Phase 1.  Rational reconstruction of two random combinations of Y' gives
+//     denominators whose lcm s divides s_n and, with high probability, equals
+//     it.  Lifting stops at the first checkpoint (32, 64, ... steps) whose s and
+//     X' agree with the previous one, or at the step count that Hadamard's
+//     bound guarantees.
+//   Phase 2.  X' = s Y' (mod p^K, symmetric) is the integer matrix s R A^-1 J;
+//     an entry that is not small shows that s misses a factor, and that
+//     entry's own denominator joins s.  The Smith form of X' over Z/sZ gives
+//     g_1 | ... | g_t, and s_{n+1-i} = s / g_i; while fewer than two of these
+//     are 1, t doubles (up to 16) and the lifting runs again with the same C.
+//   Phase 3.  prod s_i = |det A| is checked with det A / s rebuilt from
+//     det A mod primes (forward elimination on the GPU, many primes at once);
+//     |det A / s| <= H / s for Hadamard's bound H, so enough primes make the
+//     check exact.  A failed check restarts with new random J and R.
 #include "bigint.hpp"
 #include "smith_internal.hpp"
 
@@ -41,6 +66,7 @@ constexpr int kAuxPrimes = 256;     // basis of the driver's internal context
 constexpr int kChunk = 16;          // primes added per round
 constexpr int kMaxSolvePrimes = 64; // primes of one GPU CRT call
 constexpr int kMaxRestarts = 4;
+constexpr int kCertMaxPrimes = 48;  // lifting path: exact det certificate up to this many primes
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -85,23 +111,10 @@ struct DevBuf {
     }
 };
 
-// Rational reconstruction: y mod m -> (num, den) with |num| <= B, 0 < den <= B,
-// num = den * y (mod m), B = floor(sqrt(m/2)).  False if none exists.
+// Rational reconstruction with the coprimality check: y mod m -> num / den
+// (BigInt::rat_recon gives the bounds; Lehmer's method).
 bool rational_reconstruct(const BigInt &y, const BigInt &m, BigInt &num, BigInt &den) {
-    const BigInt B = BigInt::isqrt(m / BigInt(2));
-    BigInt r0 = m, r1 = mod(y, m), t0(0), t1(1);
-    while (BigInt::cmp(r1, B) > 0) {
-        BigInt q, r;
-        BigInt::divmod_trunc(r0, r1, q, r);
-        r0 = std::move(r1);
-        r1 = std::move(r);
-        BigInt t = t0 - q * t1;
-        t0 = std::move(t1);
-        t1 = std::move(t);
-    }
-    if (t1.is_zero() || BigInt::cmp(BigInt::abs(t1), B) > 0) return false;
-    num = t1.neg ? -r1 : r1;
-    den = BigInt::abs(t1);
+    if (!BigInt::rat_recon(y, m, num, den)) return false;
     return BigInt::gcd(num, den).is_one() || num.is_zero();
 }
 
@@ -218,8 +231,8 @@ struct Driver {
         for (int q = 0; q < P; ++q) h[q] = gjp(base + q, 1);
         DRV_HIP(hipMemcpyAsync(dpr.p, h.data(), sizeof(GjPrime) * P, hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemsetAsync(dsing.p, 0, sizeof(int32_t) * P, stream));
-        launch_gj_load(dA.p, n, dM.p, dpr.p, P, stream);
-        for (int k = 0; k < n; ++k) launch_gj_step(dM.p, n, k, dpr.p, P, dsing.p, stream);
+        launch_gj_load(dA.p, n, 2 * n, dM.p, dpr.p, P, stream);
+        for (int k = 0; k < n; ++k) launch_gj_step(dM.p, n, 2 * n, k, dpr.p, P, dsing.p, nullptr, stream);
         DRV_HIP(hipGetLastError());
         std::vector<int32_t> sing(P);
         DRV_HIP(hipMemcpyAsync(sing.data(), dsing.p, sizeof(int32_t) * P, hipMemcpyDeviceToHost, stream));
@@ -416,26 +429,8 @@ struct Driver {
 
     int run(rns_smith_result *res) {
         const double t0 = now_s();
-        DRV_HIP(hipSetDevice(ctx->device));
-        DRV_HIP(hipStreamCreate(&stream));
-        DRV_ST(dA.alloc((size_t)n * n));
-        DRV_HIP(hipMemcpyAsync(dA.p, A, sizeof(int64_t) * n * n, hipMemcpyHostToDevice, stream));
-        // Hadamard's bound and max entry.
-        double rows = 0, cols = 0;
-        std::vector<double> colsq(n, 0.0);
-        for (int64_t i = 0; i < n; ++i) {
-            double r = 0;
-            for (int64_t j = 0; j < n; ++j) {
-                const double v = (double)A[i * n + j];
-                r += v * v;
-                colsq[j] += v * v;
-                amax = std::max(amax, std::fabs(v));
-            }
-            rows += r > 0 ? 0.5 * std::log2(r) : -1e300;
-        }
-        for (int64_t j = 0; j < n; ++j) cols += colsq[j] > 0 ? 0.5 * std::log2(colsq[j]) : -1e300;
-        abits = std::min(rows, cols);
-        if (!(abits > -1e299)) return RNS_ESINGULAR;         // a zero row or column
+        st.path = 0;
+        st.cert_exact = 1;
         SplitMix rng{seed ^ 0x5DEECE66Dull};
         int singular_primes = 0;
         base = 0;
@@ -499,6 +494,365 @@ struct Driver {
         }
         return RNS_ERETRY;
     }
+
+    // --------------------------------------------------- p-adic lifting --
+    DevBuf<int32_t> dA32;       // A as int32 (the lifting path requires |a| < 2^31)
+    DevBuf<uint32_t> dG;        // [n][2n] Gauss-Jordan of the lifting prime; right half = C
+    DevBuf<uint32_t> dXh;       // lifted digits [K][t][n]
+    DevBuf<int64_t> dR0, dR1;   // residuals [t][n]
+    DevBuf<uint32_t> dRm0, dRm1;
+    DevBuf<int32_t> dRp;        // projection [tp][n]
+    DevBuf<int64_t> dZ;         // projected digits of one checkpoint interval
+    DevBuf<int32_t> derr;
+    DevBuf<uint32_t> ddet;
+    bool cert_exact = true;
+
+    // det A mod aux primes idx[0..count) by forward elimination, all at once.
+    int det_mod_primes(const std::vector<int> &idx, std::vector<uint32_t> &det) {
+        const int Pd = (int)idx.size();
+        det.assign(Pd, 0);
+        if (Pd == 0) return RNS_OK;
+        DRV_ST(dM.alloc((size_t)Pd * n * n));
+        DRV_ST(dpr.alloc(Pd));
+        DRV_ST(dsing.alloc(Pd));
+        DRV_ST(ddet.alloc(Pd));
+        std::vector<GjPrime> h(Pd);
+        for (int q = 0; q < Pd; ++q) h[q] = gjp(idx[q], 1);
+        std::vector<uint32_t> ones(Pd, 1u);
+        DRV_HIP(hipMemcpyAsync(dpr.p, h.data(), sizeof(GjPrime) * Pd, hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(ddet.p, ones.data(), sizeof(uint32_t) * Pd, hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemsetAsync(dsing.p, 0, sizeof(int32_t) * Pd, stream));
+        launch_gj_load(dA.p, n, n, dM.p, dpr.p, Pd, stream);
+        for (int k = 0; k < n; ++k) launch_gj_step(dM.p, n, n, k, dpr.p, Pd, dsing.p, ddet.p, stream);
+        DRV_HIP(hipGetLastError());
+        std::vector<int32_t> sing(Pd);
+        DRV_HIP(hipMemcpyAsync(det.data(), ddet.p, sizeof(uint32_t) * Pd, hipMemcpyDeviceToHost, stream));
+        DRV_HIP(hipMemcpyAsync(sing.data(), dsing.p, sizeof(int32_t) * Pd, hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        for (int q = 0; q < Pd; ++q)
+            if (sing[q]) det[q] = 0;
+        return RNS_OK;
+    }
+
+    // C = A^-1 mod p for the first aux prime from *pidx on that does not
+    // divide det A; det A mod p through *detp.
+    int lift_prime(int *pidx, uint32_t *detp) {
+        int singular = 0;
+        for (;;) {
+            if (*pidx >= kAuxPrimes) return RNS_ENOTSUP;
+            DRV_ST(dG.alloc((size_t)n * 2 * n));
+            DRV_ST(dpr.alloc(1));
+            DRV_ST(dsing.alloc(1));
+            DRV_ST(ddet.alloc(1));
+            const GjPrime h = gjp(*pidx, 1);
+            const uint32_t one = 1u;
+            DRV_HIP(hipMemcpyAsync(dpr.p, &h, sizeof(GjPrime), hipMemcpyHostToDevice, stream));
+            DRV_HIP(hipMemcpyAsync(ddet.p, &one, sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+            DRV_HIP(hipMemsetAsync(dsing.p, 0, sizeof(int32_t), stream));
+            launch_gj_load(dA.p, n, 2 * n, dG.p, dpr.p, 1, stream);
+            for (int k = 0; k < n; ++k) launch_gj_step(dG.p, n, 2 * n, k, dpr.p, 1, dsing.p, ddet.p, stream);
+            DRV_HIP(hipGetLastError());
+            int32_t sing = 0;
+            DRV_HIP(hipMemcpyAsync(&sing, dsing.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+            DRV_HIP(hipMemcpyAsync(detp, ddet.p, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+            if (!sing) return RNS_OK;
+            // A prime divides det A.  Enough such primes prove det A = 0.
+            singular += 1;
+            if (singular * 25.9 > abits + 1.0) return RNS_ESINGULAR;
+            *pidx += 1;
+        }
+    }
+
+    // Lifts Y = A^-1 J for a random n x t J and returns s and X' = s R Y
+    // ((t+2) x t, row-major) as described in the file comment.  RNS_EBOUND:
+    // no consistent reconstruction within the guaranteed step count.
+    int lift_solve(int pidx, int t, SplitMix &rng, BigInt &s_out, std::vector<BigInt> &Xp) {
+        const int tp = t + 2;
+        const uint32_t p = aux->primes[pidx];
+        const double lp = std::log2((double)p);
+        const double ln = std::log2((double)n);
+        // Guaranteed step count: the combinations' numerators stay below
+        // H n 2^30 t, their denominators below H; |s R A^-1 J| < H n^2 2^14.
+        const int64_t Kmax = (int64_t)std::ceil((2.0 * abits + 4.0 * ln + 64.0) / lp) + 1;
+        std::vector<int64_t> J((size_t)t * n);
+        std::vector<uint32_t> Jm((size_t)t * n);
+        for (size_t e = 0; e < J.size(); ++e) {
+            J[e] = (int64_t)(rng.next() % 257) - 128;
+            Jm[e] = (uint32_t)(J[e] < 0 ? J[e] + (int64_t)p : J[e]);
+        }
+        std::vector<int32_t> Rp((size_t)tp * n);
+        for (auto &v : Rp) v = (int32_t)(rng.next() % 257) - 128;
+        std::vector<uint32_t> w1(t), w2(t);
+        for (int c = 0; c < t; ++c) {
+            w1[c] = 1 + (uint32_t)(rng.next() % 65535);
+            w2[c] = 1 + (uint32_t)(rng.next() % 65535);
+        }
+        DRV_ST(dXh.alloc((size_t)Kmax * t * n));
+        DRV_ST(dR0.alloc((size_t)t * n));
+        DRV_ST(dR1.alloc((size_t)t * n));
+        DRV_ST(dRm0.alloc((size_t)t * n));
+        DRV_ST(dRm1.alloc((size_t)t * n));
+        DRV_ST(dRp.alloc((size_t)tp * n));
+        DRV_ST(derr.alloc(1));
+        DRV_HIP(hipMemcpyAsync(dR0.p, J.data(), sizeof(int64_t) * J.size(), hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(dRm0.p, Jm.data(), sizeof(uint32_t) * Jm.size(), hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(dRp.p, Rp.data(), sizeof(int32_t) * Rp.size(), hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), stream));
+        const int ne = tp * t;
+        std::vector<BigInt> Y(ne, BigInt(0));
+        BigInt pw(1);                                    // p^K_done
+        int64_t K_done = 0, K_chk = 32;
+        int64_t *R[2] = {dR0.p, dR1.p};
+        uint32_t *Rm[2] = {dRm0.p, dRm1.p};
+        int cur = 0;
+        bool have_prev = false;
+        BigInt prev_s;
+        std::vector<BigInt> prev_X;
+        std::vector<int64_t> hz;
+        for (;;) {
+            K_chk = std::min(K_chk, Kmax);
+            for (int64_t i = K_done; i < K_chk; ++i) {
+                launch_lift_step(dG.p + n, 2 * n, dA32.p, n, t, p, Rm[cur], R[cur], dXh.p + i * t * n,
+                                 R[1 - cur], Rm[1 - cur], derr.p, stream);
+                cur ^= 1;
+            }
+            const int64_t nb = K_chk - K_done;
+            DRV_ST(dZ.alloc((size_t)nb * ne));
+            launch_lift_proj(dXh.p, n, t, dRp.p, tp, K_done, K_chk, dZ.p, stream);
+            DRV_HIP(hipGetLastError());
+            hz.resize((size_t)nb * ne);
+            int32_t err = 0;
+            DRV_HIP(hipMemcpyAsync(hz.data(), dZ.p, sizeof(int64_t) * hz.size(), hipMemcpyDeviceToHost, stream));
+            DRV_HIP(hipMemcpyAsync(&err, derr.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+            if (err) return RNS_EDEVICE;                 // an inexact division: C is not A^-1 mod p
+            // Y' += (sum over the interval of Z_i p^(i - K_done)) p^K_done, the
+            // inner sum by Horner's rule from the top digit.
+            BigInt pnb(1);
+            for (int64_t i = 0; i < nb; ++i) pnb = pnb.mul_small(p);
+            for (int e = 0; e < ne; ++e) {
+                BigInt v(0);
+                for (int64_t i = nb - 1; i >= 0; --i) v = v.mul_small(p) + BigInt(hz[(size_t)i * ne + e]);
+                Y[e] = Y[e] + v * pw;
+            }
+            pw = pw * pnb;
+            K_done = K_chk;
+            st.lift_steps = (int)K_done;
+            // Phase 1 on two random combinations of the columns of rows 0, 1.
+            bool ok = false;
+            BigInt s;
+            std::vector<BigInt> X(ne);
+            {
+                BigInt W1(0), W2(0);
+                for (int c = 0; c < t; ++c) {
+                    W1 = W1 + Y[c].mul_small(w1[c]);
+                    W2 = W2 + Y[t + c].mul_small(w2[c]);
+                }
+                BigInt n1, d1, n2, d2;
+                ok = BigInt::rat_recon(mod(W1, pw), pw, n1, d1) && BigInt::rat_recon(mod(W2, pw), pw, n2, d2) &&
+                     d1.mod_small(p) != 0 && d2.mod_small(p) != 0;
+                if (ok) s = BigInt::lcm(d1, d2);
+            }
+            // Phase 2: X' = s Y' must be small; an entry that is not shows a
+            // factor missing from s (its own denominator is then added).
+            const size_t bb = (pw.bit_length() - 2) / 2;
+            const BigInt Bnd = BigInt(1).shl(bb);
+            for (int pass = 0; ok && pass <= ne; ++pass) {
+                int bad = -1;
+                for (int e = 0; e < ne && bad < 0; ++e) {
+                    BigInt x = mod(s * Y[e], pw);
+                    if (BigInt::cmp(x.shl(1), pw) > 0) x = x - pw;
+                    if (BigInt::cmp(BigInt::abs(x), Bnd) >= 0) bad = e;
+                    X[e] = std::move(x);
+                }
+                if (bad < 0) break;
+                BigInt nu, de;
+                if (!BigInt::rat_recon(mod(Y[bad], pw), pw, nu, de) || de.mod_small(p) == 0) {
+                    ok = false;
+                    break;
+                }
+                const BigInt s2 = BigInt::lcm(s, de);
+                if (s2 == s) {
+                    ok = false;
+                    break;
+                }
+                s = s2;
+            }
+            if (ok) {
+                const bool stable = have_prev && s == prev_s && X == prev_X;
+                if (stable || K_done >= Kmax) {
+                    s_out = s;
+                    Xp = std::move(X);
+                    return RNS_OK;
+                }
+                prev_s = s;
+                prev_X = X;
+                have_prev = true;
+            } else {
+                have_prev = false;
+            }
+            if (K_done >= Kmax) return RNS_EBOUND;
+            K_chk = 2 * K_chk;
+        }
+    }
+
+    // prod of the extracted invariants == |det A|, with det A / s rebuilt from
+    // det A mod primes (exact once the primes' product exceeds 2 H / s + 1).
+    int lift_certify(int pidx, uint32_t detp, const BigInt &s, const BigInt &prod, bool *ok) {
+        *ok = false;
+        const double need = abits - (double)s.bit_length() + 3.0;     // bits of 2 H / s, generously
+        const int exact_primes = std::max(1, (int)std::ceil(need / 25.9));
+        cert_exact = exact_primes <= kCertMaxPrimes;
+        BigInt D(0), Q(1), prevD;
+        int used = 0, stable = 0;
+        auto add = [&](uint32_t q, uint32_t dq) {
+            const uint32_t sq = s.mod_small(q);
+            if (sq == 0) return;                         // q divides s, hence det A: no information
+            // dq / sq mod q, then D <- the CRT combination of D mod Q and it mod q.
+            const uint32_t sinv = (uint32_t)powmod_u64(sq, q - 2, q);
+            const uint64_t target = (uint64_t)dq * sinv % q;
+            const uint64_t dmod = D.mod_small(q);
+            const uint64_t qinv = powmod_u64(Q.mod_small(q), q - 2, q);
+            const uint64_t k = (target + q - dmod) % q * qinv % q;
+            D = D + Q.mul_small((uint32_t)k);
+            Q = Q.mul_small(q);
+            used += 1;
+        };
+        add(aux->primes[pidx], detp);
+        int next = pidx + 1;
+        const int chunk = 16;
+        while (used < std::max(exact_primes, 3) + 2 && used < kCertMaxPrimes + 8) {
+            std::vector<int> idx;
+            for (int j = 0; j < chunk && next < kAuxPrimes; ++j) idx.push_back(next++);
+            if (idx.empty()) return RNS_ENOTSUP;
+            std::vector<uint32_t> det;
+            DRV_ST(det_mod_primes(idx, det));
+            bool done = false;
+            for (size_t j = 0; j < idx.size() && !done; ++j) {
+                add(aux->primes[idx[j]], det[j]);
+                BigInt Ds = D;                           // symmetric representative
+                if (BigInt::cmp(Ds.shl(1), Q) > 0) Ds = Ds - Q;
+                if (cert_exact) {
+                    done = used >= exact_primes;
+                } else {
+                    stable = (used > 1 && Ds == prevD) ? stable + 1 : 0;
+                    done = stable >= 2;
+                }
+                prevD = Ds;
+            }
+            if (done) break;
+        }
+        st.cert_primes = used;
+        BigInt Ds = D;
+        if (BigInt::cmp(Ds.shl(1), Q) > 0) Ds = Ds - Q;
+        *ok = prod == s * BigInt::abs(Ds);
+        return RNS_OK;
+    }
+
+    int run_lifting(rns_smith_result *res) {
+        const double t0 = now_s();
+        st.path = 1;
+        std::vector<int32_t> a32((size_t)n * n);
+        for (size_t e = 0; e < a32.size(); ++e) a32[e] = (int32_t)A[e];
+        DRV_ST(dA32.alloc(a32.size()));
+        DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice, stream));
+        SplitMix rng{seed ^ 0xA0761D6478BD642Full};
+        int pidx = 0;
+        uint32_t detp = 0;
+        double tl = now_s();
+        DRV_ST(lift_prime(&pidx, &detp));
+        st.t_lif += now_s() - tl;
+        int t = 4;
+        for (int attempt = 0; attempt <= kMaxRestarts + 3; ++attempt) {
+            tl = now_s();
+            BigInt s;
+            std::vector<BigInt> X;
+            const int stl = lift_solve(pidx, t, rng, s, X);
+            st.t_lif += now_s() - tl;
+            if (stl == RNS_EBOUND) {
+                st.restarts += 1;
+                continue;
+            }
+            DRV_ST(stl);
+            const double ti = now_s();
+            const int tp = t + 2;
+            std::vector<BigInt> M((size_t)tp * tp, BigInt(0));       // padded with zero columns
+            for (int a = 0; a < tp; ++a)
+                for (int c = 0; c < t; ++c) M[(size_t)a * tp + c] = mod(X[(size_t)a * t + c], s);
+            std::vector<BigInt> g = snf_mod_host(std::move(M), tp, s);
+            int nontrivial = 0;
+            for (int i = 0; i < t; ++i) nontrivial += g[i] != s;
+            st.t_im += now_s() - ti;
+            if (nontrivial > t - 2) {                    // more invariants may be > 1
+                if (2 * t > kLiftMaxCols) return RNS_ENOTSUP;
+                t *= 2;
+                continue;
+            }
+            const double tu = now_s();
+            BigInt prod(1);
+            for (int i = 0; i < t; ++i) prod = prod * (s / g[i]);
+            bool ok = false;
+            DRV_ST(lift_certify(pidx, detp, s, prod, &ok));
+            st.t_uc += now_s() - tu;
+            if (ok && ctx->force_cert_failures > 0) {   // test hook: pretend the check failed
+                ctx->force_cert_failures -= 1;
+                ok = false;
+            }
+            if (!ok) {
+                st.restarts += 1;
+                continue;
+            }
+            res->s.assign(n, BigInt(1).mag_words());
+            for (int i = 0; i < t; ++i) res->s[n - 1 - i] = (s / g[i]).mag_words();
+            st.columns = t;
+            st.cert_exact = cert_exact ? 1 : 0;
+            st.t_total = now_s() - t0;
+            res->st = st;
+            return RNS_OK;
+        }
+        return RNS_ERETRY;
+    }
+
+    // Hadamard's bound (log2) and the largest entry, from the host matrix.
+    int bounds() {
+        double rows = 0, cols = 0;
+        std::vector<double> colsq(n, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+            double r = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                const double v = (double)A[i * n + j];
+                r += v * v;
+                colsq[j] += v * v;
+                amax = std::max(amax, std::fabs(v));
+            }
+            rows += r > 0 ? 0.5 * std::log2(r) : -1e300;
+        }
+        for (int64_t j = 0; j < n; ++j) cols += colsq[j] > 0 ? 0.5 * std::log2(colsq[j]) : -1e300;
+        abits = std::min(rows, cols);
+        return abits > -1e299 ? RNS_OK : RNS_ESINGULAR;   // a zero row or column
+    }
+
+    bool lifting_applies() const {
+        return n >= 16 && amax * (double)n < 68719476736.0;   // n max|a| < 2^36
+    }
+
+    // Chooses the path: residues of s A^-1 while its sizes fit the CRT of 64
+    // primes, p-adic lifting beyond when the entries are small enough.
+    int solve(rns_smith_result *res) {
+        DRV_HIP(hipSetDevice(ctx->device));
+        DRV_HIP(hipStreamCreate(&stream));
+        DRV_ST(bounds());
+        DRV_ST(dA.alloc((size_t)n * n));
+        DRV_HIP(hipMemcpyAsync(dA.p, A, sizeof(int64_t) * n * n, hipMemcpyHostToDevice, stream));
+        const int mode = ctx->smith_path;
+        const bool fits_residues = 2.0 * abits + std::log2((double)n) + 64.0 < kMaxSolvePrimes * 25.9;
+        if (mode == 2 || (mode == 0 && !fits_residues && lifting_applies())) {
+            if (!lifting_applies()) return RNS_ENOTSUP;
+            return run_lifting(res);
+        }
+        return run(res);
+    }
 };
 
 int aux_ctx(rns_ctx *ctx, rns_ctx **out) {
@@ -544,7 +898,7 @@ extern "C" int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64
     d.A = A_host;
     d.seed = seed;
     int st = aux_ctx(ctx, &d.aux);
-    if (st == RNS_OK) st = d.run(res);
+    if (st == RNS_OK) st = d.solve(res);
     if (st != RNS_OK) {
         delete res;
         return st;

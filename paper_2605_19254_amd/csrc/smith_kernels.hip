@@ -34,16 +34,20 @@ __device__ __forceinline__ uint32_t powmod_p(uint32_t a, uint32_t e, double pf, 
 }
 
 // --------------------------------------------------- Gauss-Jordan mod p --
-// M: [P][n][2n] uint32; plane q uses prime pr[q].  Step k: choose the first
-// row r >= k with a nonzero entry in column k, swap it into row k (columns
-// k..2n-1: columns < k of rows >= k are already zero), scale row k so that
+// M: [P][n][ld] uint32; plane q uses prime pr[q].  With ld = 2n the planes hold
+// [A | I] and the elimination is Gauss-Jordan (every row i != k), which leaves
+// A^-1 in the right halves; with ld = n they hold A and only rows below the
+// pivot are eliminated (enough for the determinant).
+// Step k: choose the first row r >= k with a nonzero entry in column k, swap
+// it into row k (columns k..ld-1: columns < k of rows >= k are already zero),
+// multiply det[q] by the pivot (negated for a swap), and scale row k so that
 // the pivot is 1.  A prime with no pivot is marked singular.
-__global__ __launch_bounds__(256) void k_gj_pivot(uint32_t *__restrict__ M, int64_t n, int k,
-                                                  const GjPrime *__restrict__ pr,
-                                                  int32_t *__restrict__ singular) {
+__global__ __launch_bounds__(256) void k_gj_pivot(uint32_t *__restrict__ M, int64_t n, int64_t ld,
+                                                  int k, const GjPrime *__restrict__ pr,
+                                                  int32_t *__restrict__ singular,
+                                                  uint32_t *__restrict__ det) {
     const int q = blockIdx.x;
     if (singular[q]) return;
-    const int64_t ld = 2 * n;
     uint32_t *A = M + (int64_t)q * n * ld;
     __shared__ int best;
     if (threadIdx.x == 0) best = (int)n;
@@ -65,22 +69,28 @@ __global__ __launch_bounds__(256) void k_gj_pivot(uint32_t *__restrict__ M, int6
         }
     __syncthreads();
     __shared__ uint32_t inv;
-    if (threadIdx.x == 0) inv = powmod_p(A[(int64_t)k * ld + k], pr[q].p - 2, pf, pinv);
+    if (threadIdx.x == 0) {
+        const uint32_t piv = A[(int64_t)k * ld + k];
+        if (det) {
+            const uint32_t d = mulmod_p(det[q], piv, pf, pinv);
+            det[q] = (r != k && d != 0) ? pr[q].p - d : d;
+        }
+        inv = powmod_p(piv, pr[q].p - 2, pf, pinv);
+    }
     __syncthreads();
     for (int64_t j = k + threadIdx.x; j < ld; j += blockDim.x)
         A[(int64_t)k * ld + j] = mulmod_p(A[(int64_t)k * ld + j], inv, pf, pinv);
 }
 
-// Rows i != k: row_i -= M[i][k] * row_k on columns k+1..2n-1.  Column k is
-// not written (it is never read again).  Grid: x = column chunk, y = row,
-// z = prime.
-__global__ __launch_bounds__(256) void k_gj_elim(uint32_t *__restrict__ M, int64_t n, int k,
-                                                 const GjPrime *__restrict__ pr,
+// row_i -= M[i][k] * row_k on columns k+1..ld-1 for the rows i = row0 +
+// blockIdx.y (skipping k).  Column k is not written (it is never read again).
+// Grid: x = column chunk, y = row, z = prime.
+__global__ __launch_bounds__(256) void k_gj_elim(uint32_t *__restrict__ M, int64_t n, int64_t ld,
+                                                 int k, int64_t row0, const GjPrime *__restrict__ pr,
                                                  const int32_t *__restrict__ singular) {
     const int q = blockIdx.z;
-    const int64_t i = blockIdx.y;
+    const int64_t i = row0 + blockIdx.y;
     if (singular[q] || i == k) return;
-    const int64_t ld = 2 * n;
     uint32_t *A = M + (int64_t)q * n * ld;
     const uint32_t f = A[i * ld + k];
     if (f == 0) return;
@@ -92,14 +102,14 @@ __global__ __launch_bounds__(256) void k_gj_elim(uint32_t *__restrict__ M, int64
     A[i * ld + j] = a >= t ? a - t : a + p - t;
 }
 
-// Loads A (int64, host-reduced to residues on the device) into [A mod p | I].
-__global__ __launch_bounds__(256) void k_gj_load(const int64_t *__restrict__ A, int64_t n,
+// Loads A (int64) reduced mod each prime into [A mod p | I] (ld = 2n) or
+// A mod p (ld = n).
+__global__ __launch_bounds__(256) void k_gj_load(const int64_t *__restrict__ A, int64_t n, int64_t ld,
                                                  uint32_t *__restrict__ M,
                                                  const GjPrime *__restrict__ pr) {
     const int q = blockIdx.z;
     const int64_t i = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ld = 2 * n;
     if (j >= ld) return;
     uint32_t v;
     if (j < n) {
@@ -111,6 +121,114 @@ __global__ __launch_bounds__(256) void k_gj_load(const int64_t *__restrict__ A, 
         v = (j - n == i) ? 1u : 0u;
     }
     M[((int64_t)q * n + i) * ld + j] = v;
+}
+
+// ----------------------------------------------------- p-adic lifting --
+// Dixon's iteration for A Y = J with C = A^-1 mod p resident: with R_0 = J,
+//   X_i = C R_i mod p,   R_{i+1} = (R_i - A X_i) / p   (an exact division),
+// so that Y = sum_i X_i p^i in the p-adic integers.  The t right-hand sides
+// are stored column by column ([t][n]); one wave handles one row.
+
+constexpr int kLiftMaxT = 16;
+
+// X[c][r] = sum_k C[r][k] Rm[c][k] mod p.  Each lane sums at most
+// ceil(n/64) products below 2^52 (n <= 65536 keeps that below 2^62), reduces
+// its sum mod p, and the wave adds the 64 reduced sums.
+template <int T>
+__global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, int64_t ldc, int64_t n,
+                                                const uint32_t *__restrict__ Rm, int t, uint32_t p,
+                                                uint32_t *__restrict__ X) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;                                  // whole waves only
+    const uint32_t *Cr = C + r * ldc;
+    uint64_t acc[T];
+#pragma unroll
+    for (int c = 0; c < T; ++c) acc[c] = 0;
+    for (int64_t k = lane; k < n; k += 64) {
+        const uint64_t cv = Cr[k];
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+            if (c < t) acc[c] += cv * Rm[(int64_t)c * n + k];
+    }
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+        if (c < t) {
+            uint64_t v = acc[c] % p;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) X[(int64_t)c * n + r] = (uint32_t)(v % p);
+        }
+    }
+}
+
+// R'[c][r] = (R[c][r] - sum_k A[r][k] X[c][k]) / p and Rm'[c][r] = R' mod p.
+// The host admits this form only when n max|a| p < 2^62, so every sum fits in
+// an int64.  A division that is not exact (impossible for a correct C) sets
+// *err instead of producing a wrong residual silently.
+template <int T>
+__global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, int64_t n,
+                                                const uint32_t *__restrict__ X,
+                                                const int64_t *__restrict__ R, int t, uint32_t p,
+                                                int64_t *__restrict__ Rn, uint32_t *__restrict__ Rmn,
+                                                int32_t *__restrict__ err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    const int32_t *Ar = A + r * n;
+    int64_t acc[T];
+#pragma unroll
+    for (int c = 0; c < T; ++c) acc[c] = 0;
+    for (int64_t k = lane; k < n; k += 64) {
+        const int64_t av = Ar[k];
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+            if (c < t) acc[c] += av * (int64_t)X[(int64_t)c * n + k];
+    }
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+        if (c >= t) continue;
+        int64_t v = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) {
+            const int64_t num = R[(int64_t)c * n + r] - v;
+            const int64_t q = num / (int64_t)p;
+            if (q * (int64_t)p != num) atomicOr(err, 1);
+            Rn[(int64_t)c * n + r] = q;
+            const int64_t m = q % (int64_t)p;
+            Rmn[(int64_t)c * n + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+        }
+    }
+}
+
+// Projections of stored digits: Z[i][a][c] = sum_r Rp[a][r] Xh[i][c][r] for
+// steps i in [i0, i1), a < tp, c < t.  One block per (step, column); each
+// thread sums a strided share of the rows, then the block adds the shares.
+// |Rp| <= 2^8 and X < 2^26, so the sums stay far inside int64.
+__global__ __launch_bounds__(256) void k_lift_proj(const uint32_t *__restrict__ Xh, int64_t n, int t,
+                                                   const int32_t *__restrict__ Rp, int tp, int64_t i0,
+                                                   int64_t *__restrict__ Z) {
+    const int64_t i = i0 + blockIdx.x / t;
+    const int c = blockIdx.x % t;
+    const uint32_t *x = Xh + (i * t + c) * n;
+    int64_t acc[kLiftMaxT + 2];
+    for (int a = 0; a < tp; ++a) acc[a] = 0;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const int64_t xv = x[r];
+        for (int a = 0; a < tp; ++a) acc[a] += (int64_t)Rp[(int64_t)a * n + r] * xv;
+    }
+    __shared__ int64_t red[256];
+    for (int a = 0; a < tp; ++a) {
+        red[threadIdx.x] = acc[a];
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) Z[((i - i0) * tp + a) * t + c] = red[0];
+        __syncthreads();
+    }
 }
 
 // Multiply plane q of a residue matrix (rows x cols, leading dimension ld,
@@ -323,18 +441,46 @@ __global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int6
 
 // ------------------------------------------------------------- launchers --
 
-void launch_gj_load(const int64_t *A, int64_t n, uint32_t *M, const GjPrime *pr, int P, hipStream_t s) {
-    dim3 grid((unsigned)((2 * n + 255) / 256), (unsigned)n, (unsigned)P);
-    hipLaunchKernelGGL(k_gj_load, grid, dim3(256), 0, s, A, n, M, pr);
+void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const GjPrime *pr, int P,
+                    hipStream_t s) {
+    dim3 grid((unsigned)((ld + 255) / 256), (unsigned)n, (unsigned)P);
+    hipLaunchKernelGGL(k_gj_load, grid, dim3(256), 0, s, A, n, ld, M, pr);
 }
 
-void launch_gj_step(uint32_t *M, int64_t n, int k, const GjPrime *pr, int P, int32_t *singular,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)P), dim3(256), 0, s, M, n, k, pr, singular);
-    const int64_t cols = 2 * n - k - 1;
-    if (cols <= 0) return;
-    dim3 grid((unsigned)((cols + 255) / 256), (unsigned)n, (unsigned)P);
-    hipLaunchKernelGGL(k_gj_elim, grid, dim3(256), 0, s, M, n, k, pr, singular);
+void launch_gj_step(uint32_t *M, int64_t n, int64_t ld, int k, const GjPrime *pr, int P,
+                    int32_t *singular, uint32_t *det, hipStream_t s) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)P), dim3(256), 0, s, M, n, ld, k, pr, singular, det);
+    const int64_t cols = ld - k - 1;
+    const bool full = ld == 2 * n;                      // Gauss-Jordan: every row; else below k
+    const int64_t row0 = full ? 0 : k + 1;
+    const int64_t rows = n - row0;
+    if (cols <= 0 || rows <= 0) return;
+    dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows, (unsigned)P);
+    hipLaunchKernelGGL(k_gj_elim, grid, dim3(256), 0, s, M, n, ld, k, row0, pr, singular);
+}
+
+template <int T>
+static void lift_step_t(const uint32_t *C, int64_t ldc, const int32_t *A, int64_t n, int t, uint32_t p,
+                        const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
+                        int32_t *err, hipStream_t s) {
+    const unsigned blocks = (unsigned)((n + 3) / 4);
+    hipLaunchKernelGGL(k_lift_x<T>, dim3(blocks), dim3(256), 0, s, C, ldc, n, Rm, t, p, X);
+    hipLaunchKernelGGL(k_lift_r<T>, dim3(blocks), dim3(256), 0, s, A, n, X, R, t, p, Rn, Rmn, err);
+}
+
+void launch_lift_step(const uint32_t *C, int64_t ldc, const int32_t *A, int64_t n, int t, uint32_t p,
+                      const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
+                      int32_t *err, hipStream_t s) {
+    if (t <= 4) lift_step_t<4>(C, ldc, A, n, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else if (t <= 8) lift_step_t<8>(C, ldc, A, n, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else lift_step_t<kLiftMaxT>(C, ldc, A, n, t, p, Rm, R, X, Rn, Rmn, err, s);
+}
+
+void launch_lift_proj(const uint32_t *Xh, int64_t n, int t, const int32_t *Rp, int tp, int64_t i0,
+                      int64_t i1, int64_t *Z, hipStream_t s) {
+    if (i1 <= i0) return;
+    hipLaunchKernelGGL(k_lift_proj, dim3((unsigned)((i1 - i0) * t)), dim3(256), 0, s, Xh, n, t, Rp, tp,
+                       i0, Z);
 }
 
 void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t plane_stride,

@@ -128,6 +128,38 @@ def planted_smith(n: int, seed: int = 0, ops_per_dim: int = 4,
     raise RuntimeError("planted_smith: entries kept exceeding the int64 limit")
 
 
+def planted_small(n: int, seed: int = 0, factors=(2, 3, 2, 5, 2, 7, 3, 2), ops_per_dim: int = 2,
+                  cap: int = 1 << 20) -> Planted:
+    """A = U diag(s) V with small entries and several invariants above 1: the
+    k-th factor multiplies s_{n-k}, ..., s_n (k = 1, 2, ...), so the last
+    len(factors) invariants are nontrivial and form a divisor chain.  U and V
+    are products of ops_per_dim*n random operations x_i += c x_j, c = +-1 (on
+    columns, then rows of diag(s)); an operation that would make an entry
+    reach ``cap`` is skipped, so |a_ij| < cap."""
+    rng = np.random.default_rng(seed)
+    s = [1] * n
+    for k, f in enumerate(factors, start=1):
+        for i in range(n - k, n):
+            s[i] *= f
+    a = np.zeros((n, n), dtype=np.int64)
+    a[np.arange(n), np.arange(n)] = np.array(s, dtype=np.int64)
+    for axis in (1, 0):
+        i = rng.integers(0, n, size=ops_per_dim * n)
+        j = rng.integers(0, n - 1, size=ops_per_dim * n)
+        j = j + (j >= i)
+        c = rng.choice(np.array([-1, 1], dtype=np.int64), size=ops_per_dim * n)
+        for ii, jj, cc in zip(i, j, c):
+            if axis == 1:
+                new = a[:, ii] + cc * a[:, jj]
+                if np.abs(new).max() < cap:
+                    a[:, ii] = new
+            else:
+                new = a[ii, :] + cc * a[jj, :]
+                if np.abs(new).max() < cap:
+                    a[ii, :] = new
+    return Planted(a=a, s=s)
+
+
 @dataclass
 class Problem:
     m: int

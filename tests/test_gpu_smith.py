@@ -117,3 +117,85 @@ def test_result_independent_of_seed(ctx, rg):
     a = synth.planted_smith(40, seed=7).a
     r = [rg.smith_form(ctx, a, seed=sd).s for sd in (0, 1, 12345)]
     assert r[0] == r[1] == r[2]
+
+
+# ------------------------------------------------------- p-adic lifting path --
+import json
+import os
+
+_GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "smith_lifting.json")))
+
+
+def _golden_matrix(case):
+    if case["gen"] == "small_smith":
+        return synth.small_smith(seed=case["seed"], attempt=case["attempt"], n=case["n"], bound=case["bound"])
+    return synth.planted_small(case["n"], seed=case["seed"]).a
+
+
+def _golden_s(case):
+    return [1] * case["ones"] + [int(v) for v in case["tail"]]
+
+
+@pytest.fixture
+def lifting_ctx(ctx):
+    yield ctx
+    ctx.set_smith_path("auto")
+
+
+@pytest.mark.parametrize("case", _GOLDEN["cases"], ids=lambda c: "%s-n%d" % (c["gen"], c["n"]))
+def test_lifting_golden(lifting_ctx, rg, case):
+    """Inputs whose invariants are too large for the residue path: the auto
+    choice takes p-adic lifting (planted inputs are forced onto it to make the
+    projection grow); S equals the oracle's."""
+    ctx = lifting_ctx
+    _say("smith lifting", case)
+    a = _golden_matrix(case)
+    if case["gen"] == "planted_small":
+        ctx.set_smith_path("lifting")
+    res = rg.smith_form(ctx, a, seed=case["seed"])
+    assert res.s == _golden_s(case)
+    assert res.stats["path"] == 1
+    assert res.stats["lift_steps"] > 0
+    if case["gen"] == "planted_small":
+        assert res.stats["columns"] == 16          # 8 invariants > 1: t grew 4 -> 8 -> 16
+    print("stats", res.stats, flush=True)
+
+
+@pytest.mark.parametrize("n,seed", [(16, 0), (24, 1), (40, 2), (64, 3)])
+def test_lifting_forced_matches_oracle(lifting_ctx, rg, n, seed):
+    ctx = lifting_ctx
+    _say("smith lifting forced", n, seed)
+    rng = np.random.default_rng(500 + seed)
+    while True:
+        a = rng.integers(-99, 100, size=(n, n), dtype=np.int64)
+        if osmith.bareiss_det(a) != 0:
+            break
+    ctx.set_smith_path("lifting")
+    res = rg.smith_form(ctx, a, seed=seed)
+    assert res.s == osmith.smith_form(a)
+    assert res.stats["path"] == 1 and res.stats["cert_exact"] == 1
+
+
+def test_lifting_restart_seed_and_errors(lifting_ctx, rg):
+    ctx = lifting_ctx
+    _say("smith lifting restart / seed / singular / not applicable")
+    case = _GOLDEN["cases"][0]
+    a = _golden_matrix(case)
+    want = _golden_s(case)
+    ctx.force_cert_failures(2)
+    res = rg.smith_form(ctx, a, seed=9)
+    ctx.force_cert_failures(0)
+    assert res.s == want and res.stats["restarts"] >= 2
+    assert rg.smith_form(ctx, a, seed=12345).s == want
+    # singular with small entries: every lifting prime divides det A = 0
+    sing = synth.small_smith(seed=4, n=32, bound=99).copy()
+    sing[5] = sing[7] * 2
+    ctx.set_smith_path("lifting")
+    with pytest.raises(rg.RnsError) as e:
+        rg.smith_form(ctx, sing)
+    assert e.value.status == 6
+    # entries too large for the lifting path
+    big = synth.planted_smith(24, seed=0).a
+    with pytest.raises(rg.RnsError) as e:
+        rg.smith_form(ctx, big)
+    assert e.value.status == 8
