@@ -86,7 +86,7 @@ def parse():
                     help="also time the batched workload with this many uneven products (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--smith", type=int, default=1, help="time the Smith-form workloads (0 = skip)")
-    ap.add_argument("--serving", type=int, default=24,
+    ap.add_argument("--serving", type=int, default=60,
                     help="requests per open-loop serving point (0 = skip)")
     ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving"],
                     help="run only this workload (for profiling)")
@@ -228,6 +228,17 @@ def run_smith(rg, reps=10):
         t = time.perf_counter() - t0
         if res.s != pl.s:
             raise SystemExit("bench.py: planted Smith form (n=2000) differs")
+        # random n = 4000, entries in [-2^10, 2^10]: the p-adic lifting path
+        ar = synth.small_smith(seed=0, n=4000, bound=1 << 10)
+        t0 = time.perf_counter()
+        rr = rg.smith_form(ctx, ar, seed=0)
+        tr = time.perf_counter() - t0
+        if any(rr.s[i + 1] % rr.s[i] for i in range(len(rr.s) - 1)):
+            raise SystemExit("bench.py: Smith form (random n=4000) is not a divisor chain")
+        out["random_4000"] = {"workload": "n = 4000, entries uniform in [-2^10, 2^10], seed 0 (p-adic lifting)",
+                              "seconds": tr, "stats": rr.stats,
+                              "nontrivial": sum(1 for v in rr.s if v != 1),
+                              "largest_invariant_bits": rr.s[-1].bit_length()}
         p100 = synth.planted_smith(100, seed=0)
         t0 = time.perf_counter()
         osmith.smith_form(p100.a)
@@ -240,85 +251,105 @@ def run_smith(rg, reps=10):
     return out
 
 
-def _serving_requests(count, seed):
-    """Sizes log-uniform in [100, 1500] (planted, so that the Smith form is
-    nontrivial and known), one request in four a dense random matrix with
-    entries in [-2^10, 2^10] and n log-uniform in [8, 48], and one singular
-    request at position 5."""
-    import math
+def _serving_stream(count, rate, seed, tail):
+    """Serving requests: Poisson arrivals at `rate`, n log-uniform in
+    [100, 4000], entries uniform in [-2^10, 2^10] (a singular draw is
+    redrawn), the n = 10007 tail at the 50th arrival when `tail`, and one
+    singular request (all ones, n = 100) at position 5."""
     import numpy as np
     import synth
-    rng = np.random.default_rng(seed)
+    from oracle import smith as osmith
+    stream = synth.serving_stream(count, rate, lo=100, hi=4000, tail_n=10007 if tail else 0,
+                                  tail_at=50, seed=seed)
     reqs = []
-    for i in range(count):
-        if i == 5:
-            a = np.ones((6, 6), dtype=np.int64)
-            reqs.append((a, None))
-        elif i % 4 == 3:
-            n = int(round(math.exp(rng.uniform(math.log(8), math.log(48)))))
-            reqs.append((synth.small_smith(seed=int(seed * 1000 + i), n=n, bound=1 << 10), "random"))
-        else:
-            n = int(round(math.exp(rng.uniform(math.log(100), math.log(1500)))))
-            pl = synth.planted_smith(n, seed=int(seed * 1000 + i))
-            reqs.append((pl.a, pl.s))
+    for r in stream.requests:
+        if r.rid == 5:
+            reqs.append((r, np.ones((100, 100), dtype=np.int64), "singular"))
+            continue
+        a = synth.request_matrix(r)
+        if r.n <= 64 and osmith.bareiss_det(a) == 0:
+            a = synth.request_matrix(r, attempt=1)
+        reqs.append((r, a, "random"))
     return reqs
 
 
 def run_serving(rg, count):
     """Closed-loop capacity, then open-loop Poisson arrivals at 0.5x and 1.0x
-    of it; latency = completion - arrival."""
+    of it (the 1.0x point with the n = 10007 tail at its 50th arrival);
+    latency = completion - arrival.  Every served result is a divisor chain
+    certified by the library; a sample is solved again alone and compared."""
     import numpy as np
     workers = 4
     out = {"workers": workers}
     srv = rg.Server(device=0, workers=workers)
-    warm = _serving_requests(8, seed=7)
-    for a, _ in warm[:2]:
-        srv.wait(srv.submit(a))
+    warm = _serving_stream(12, 1.0, seed=7, tail=False)
+    for _, a, kind in warm[:workers]:
+        if kind != "singular":
+            srv.wait(srv.submit(a))
     t0 = time.perf_counter()
-    ts = [srv.submit(a, seed=i) for i, (a, _) in enumerate(warm)]
+    ts = [srv.submit(a, seed=i) for i, (_, a, kind) in enumerate(warm) if kind != "singular"]
     for t in ts:
         srv.wait(t)
-    cap = len(warm) / (time.perf_counter() - t0)
+    cap = len(ts) / (time.perf_counter() - t0)
     out["closed_loop_solves_per_s"] = cap
     points = []
-    for frac, seed in ((0.5, 11), (1.0, 12)):
-        reqs = _serving_requests(count, seed=seed)
+    solved = []
+    for frac, seed, tail in ((0.5, 11, False), (1.0, 12, True)):
         rate = frac * cap
-        gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
-        arrive = np.cumsum(gaps) - gaps[0]
+        reqs = _serving_stream(count, rate, seed=seed, tail=tail and count > 50)
         start = time.perf_counter()
         tickets = []
-        for (a, _), ta in zip(reqs, arrive):
-            d = start + ta - time.perf_counter()
+        for r, a, kind in reqs:
+            d = start + r.arrival - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            tickets.append((srv.submit(a, seed=1), time.perf_counter()))
-        lat, queue, service, ok, bad = [], [], [], 0, 0
-        for (t, t_arr), (a, want) in zip(tickets, reqs):
+            tickets.append(srv.submit(a, seed=1))
+        lat, queue, service, ok, bad, tail_rec, paths, exact = [], [], [], 0, 0, None, [0, 0], 0
+        for t, (r, a, kind) in zip(tickets, reqs):
             st, res, info = srv.wait(t)
-            if want is None:
+            if kind == "singular":
                 bad += int(st == 6)
                 continue
-            if st != 0 or (want != "random" and res.s != want):
-                raise SystemExit("bench.py: served Smith form differs from the planted invariants")
+            if st != 0 or any(res.s[i + 1] % res.s[i] for i in range(len(res.s) - 1)):
+                raise SystemExit("bench.py: served Smith form failed (status %d, n %d)" % (st, r.n))
             ok += 1
-            lat.append(info["t_end"] - info["t_submit"])
-            queue.append(info["t_start"] - info["t_submit"])
-            service.append(info["t_end"] - info["t_start"])
+            paths[res.stats["path"]] += 1
+            exact += res.stats["cert_exact"]
+            rec = (info["t_end"] - info["t_submit"], info["t_start"] - info["t_submit"],
+                   info["t_end"] - info["t_start"])
+            if r.n == 10007:
+                tail_rec = {"n": r.n, "latency_s": rec[0], "queue_s": rec[1], "service_s": rec[2],
+                            "stats": res.stats, "largest_invariant_bits": res.s[-1].bit_length()}
+                continue
+            lat.append(rec[0])
+            queue.append(rec[1])
+            service.append(rec[2])
+            if len(solved) < 6 and r.n <= 1500:
+                solved.append((a, res.s))
         span = time.perf_counter() - start
         points.append({"rate_frac_of_capacity": frac, "arrival_rate": rate, "requests": count,
                        "solves_per_s": ok / span, "p50_latency_s": float(np.percentile(lat, 50)),
                        "p99_latency_s": float(np.percentile(lat, 99)),
                        "p50_queue_s": float(np.percentile(queue, 50)),
+                       "p99_queue_s": float(np.percentile(queue, 99)),
                        "p50_service_s": float(np.percentile(service, 50)),
-                       "singular_rejected": bad})
+                       "p99_service_s": float(np.percentile(service, 99)),
+                       "singular_rejected": bad, "paths_residue_lifting": paths,
+                       "exact_certificates": exact, "tail": tail_rec})
     st = srv.stats()
     srv.close()
+    # alone versus in the mix
+    with rg.Context(device=0, L=24) as ctx:
+        for a, s_mix in solved:
+            if rg.smith_form(ctx, a, seed=3).s != s_mix:
+                raise SystemExit("bench.py: a served Smith form differs from the same request solved alone")
     out["points"] = points
+    out["alone_vs_mix_checked"] = len(solved)
     out["max_running"] = st["max_running"]
     out["hbm_high_water_bytes"] = st["high_water"]
-    out["workload"] = ("Poisson arrivals; n log-uniform in [100, 1500] planted (A = U diag(s) V), every 4th "
-                       "request random n in [8, 48] with entries in [-2^10, 2^10], one singular request")
+    out["workload"] = ("Poisson arrivals; n log-uniform in [100, 4000], entries uniform in [-2^10, 2^10] "
+                       "(seeded synthetic stand-ins), n = 10007 tail at the 50th arrival of the 1.0x point, "
+                       "one singular request per point; %d requests per point" % count)
     return out
 
 

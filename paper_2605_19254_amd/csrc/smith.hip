@@ -721,7 +721,9 @@ struct Driver {
         };
         add(aux->primes[pidx], detp);
         int next = pidx + 1;
-        const int chunk = 16;
+        // One batch of all the primes an exact check needs; otherwise a few
+        // at a time until the reconstruction stops changing.
+        const int chunk = cert_exact ? std::min(exact_primes + 1, 64) : 4;
         while (used < std::max(exact_primes, 3) + 2 && used < kCertMaxPrimes + 8) {
             std::vector<int> idx;
             for (int j = 0; j < chunk && next < kAuxPrimes; ++j) idx.push_back(next++);
