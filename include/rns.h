@@ -345,6 +345,18 @@ int rns_ctx_set_smith_path(rns_ctx *ctx, int path);
 int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
                rns_smith_result **out);
 
+/*
+ * rns_largest_invariant -- Phase 1 alone (Section 2.2): the largest
+ * invariant factor s_n of a nonsingular A by p-adic lifting of A^-1 J for a
+ * random n x 4 matrix J and rational reconstruction of random combinations of
+ * the solution (the path-1 machinery of smith_form).  Monte Carlo: the value
+ * returned divides s_n and equals it with high probability.  Requires n >= 16
+ * and n max|a_ij| < 2^36 (RNS_ENOTSUP otherwise).  The result holds one
+ * entry (read it with rns_smith_get(r, 0, ...)); free with rns_smith_free.
+ */
+int rns_largest_invariant(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
+                          rns_smith_result **out);
+
 /* Invariant factor i (0-based) as little-endian 64-bit magnitude words. */
 int rns_smith_get(const rns_smith_result *r, int64_t i, const uint64_t **words,
                   int *nwords);

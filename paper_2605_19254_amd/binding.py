@@ -107,6 +107,7 @@ _lib_status = _sig("rns_ctx_status", _I32, [_P, _P])
 _lib_force = _sig("rns_ctx_force_cert_failures", _I32, [_P, _I32])
 _lib_smith_path = _sig("rns_ctx_set_smith_path", _I32, [_P, _I32])
 _lib_smith = _sig("smith_form", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_P)])
+_lib_lif = _sig("rns_largest_invariant", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_P)])
 _lib_smith_get = _sig("rns_smith_get", _I32, [_P, _I64, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64)),
                                               ctypes.POINTER(_I32)])
 _lib_smith_size = _sig("rns_smith_size", _I64, [_P])
@@ -174,7 +175,7 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy",
            "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
            "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate",
-           "rns_ctx_set_smith_path"]
+           "rns_ctx_set_smith_path", "rns_largest_invariant"]
 
 
 class RnsError(RuntimeError):
@@ -563,6 +564,16 @@ def smith_form(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
     assert a.shape == (n, n)
     h = _P()
     _check(_lib_smith(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "smith_form")
+    return _smith_result(h)
+
+
+def largest_invariant(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
+    """Phase 1 alone: s_n by p-adic lifting (Monte Carlo); result.s == [s_n]."""
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    h = _P()
+    _check(_lib_lif(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "rns_largest_invariant")
     return _smith_result(h)
 
 

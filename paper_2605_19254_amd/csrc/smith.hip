@@ -816,6 +816,38 @@ struct Driver {
         return RNS_ERETRY;
     }
 
+    // Phase 1 alone: the largest invariant factor s_n (Monte Carlo: the lcm of
+    // the denominators found divides s_n and equals it with high probability).
+    int run_lif(rns_smith_result *res) {
+        const double t0 = now_s();
+        st.path = 1;
+        std::vector<int32_t> a32((size_t)n * n);
+        for (size_t e = 0; e < a32.size(); ++e) a32[e] = (int32_t)A[e];
+        DRV_ST(dA32.alloc(a32.size()));
+        DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice, stream));
+        SplitMix rng{seed ^ 0x2545F4914F6CDD1Dull};
+        int pidx = 0;
+        uint32_t detp = 0;
+        DRV_ST(lift_prime(&pidx, &detp));
+        for (int attempt = 0; attempt <= kMaxRestarts; ++attempt) {
+            BigInt s;
+            std::vector<BigInt> X;
+            const int stl = lift_solve(pidx, 4, rng, s, X);
+            if (stl == RNS_EBOUND) {
+                st.restarts += 1;
+                continue;
+            }
+            DRV_ST(stl);
+            res->s.assign(1, s.mag_words());
+            st.columns = 4;
+            st.cert_exact = 0;
+            st.t_lif = st.t_total = now_s() - t0;
+            res->st = st;
+            return RNS_OK;
+        }
+        return RNS_ERETRY;
+    }
+
     // Hadamard's bound (log2) and the largest entry, from the host matrix.
     int bounds() {
         double rows = 0, cols = 0;
@@ -837,6 +869,16 @@ struct Driver {
 
     bool lifting_applies() const {
         return n >= 16 && amax * (double)n < 68719476736.0;   // n max|a| < 2^36
+    }
+
+    int solve_lif(rns_smith_result *res) {
+        DRV_HIP(hipSetDevice(ctx->device));
+        DRV_HIP(hipStreamCreate(&stream));
+        DRV_ST(bounds());
+        if (!lifting_applies()) return RNS_ENOTSUP;
+        DRV_ST(dA.alloc((size_t)n * n));
+        DRV_HIP(hipMemcpyAsync(dA.p, A, sizeof(int64_t) * n * n, hipMemcpyHostToDevice, stream));
+        return run_lif(res);
     }
 
     // Chooses the path: residues of s A^-1 while its sizes fit the CRT of 64
@@ -901,6 +943,29 @@ extern "C" int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64
     d.seed = seed;
     int st = aux_ctx(ctx, &d.aux);
     if (st == RNS_OK) st = d.solve(res);
+    if (st != RNS_OK) {
+        delete res;
+        return st;
+    }
+    *out = res;
+    return RNS_OK;
+}
+
+extern "C" int rns_largest_invariant(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
+                                     rns_smith_result **out) {
+    if (!ctx || !out || n < 0 || (n > 0 && !A_host)) return RNS_EINVAL;
+    *out = nullptr;
+    for (int64_t e = 0; e < n * n; ++e)
+        if (A_host[e] == INT64_MIN) return RNS_EINVAL;
+    rns_smith_result *res = new (std::nothrow) rns_smith_result;
+    if (!res) return RNS_ENOMEM;
+    Driver d;
+    d.ctx = ctx;
+    d.n = n;
+    d.A = A_host;
+    d.seed = seed;
+    int st = aux_ctx(ctx, &d.aux);
+    if (st == RNS_OK) st = d.solve_lif(res);
     if (st != RNS_OK) {
         delete res;
         return st;

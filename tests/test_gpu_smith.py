@@ -199,3 +199,22 @@ def test_lifting_restart_seed_and_errors(lifting_ctx, rg):
     with pytest.raises(rg.RnsError) as e:
         rg.smith_form(ctx, big)
     assert e.value.status == 8
+
+
+def test_largest_invariant_paper_fact(ctx, rg):
+    """Section 4.1 prints the size of s_n for A_ij = i^j mod n at n = 1009:
+    4083 bits.  Phase 1 on the GPU (p-adic lifting, reconstruction of the
+    common denominator) must reproduce it."""
+    facts = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
+    fact = facts["vandermonde_mod_sn_bits"]
+    _say("largest invariant, vandermonde n =", fact["n"])
+    res = rg.largest_invariant(ctx, synth.vandermonde_mod(fact["n"]), seed=1)
+    assert len(res.s) == 1
+    assert res.s[0].bit_length() == fact["bits"]
+
+
+@pytest.mark.parametrize("n", [17, 29, 41, 53])
+def test_largest_invariant_matches_oracle(ctx, rg, n):
+    _say("largest invariant vs oracle, vandermonde", n)
+    a = synth.vandermonde_mod(n)
+    assert rg.largest_invariant(ctx, a, seed=n).s == [osmith.smith_form(a)[-1]]
