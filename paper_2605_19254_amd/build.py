@@ -70,7 +70,9 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
     rt = _runtime_dir()
     if rt:
-        cmd = ["g++", "-shared", "-fPIC", "-o", tmp] + objs + [
+        # -z defs: a symbol missing from the objects fails the link here
+        # instead of the library load on the GPU machine.
+        cmd = ["g++", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs + [
             "-L" + rt, "-l:libamdhip64.so", "-Wl,-rpath," + rt, "-lpthread"]
     else:
         cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]

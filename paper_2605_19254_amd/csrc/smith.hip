@@ -496,8 +496,10 @@ struct Driver {
     }
 
     // --------------------------------------------------- p-adic lifting --
-    DevBuf<int32_t> dA32;       // A as int32 (the lifting path requires |a| < 2^31)
+    int64_t ldl = 0;            // padded row stride of the lifting operands (multiple of 4)
+    DevBuf<int32_t> dA32;       // A as int32, [n][ldl], zero beyond column n
     DevBuf<uint32_t> dG;        // [n][2n] Gauss-Jordan of the lifting prime; right half = C
+    DevBuf<uint32_t> dC;        // C = A^-1 mod p, [n][ldl], zero beyond column n
     DevBuf<uint32_t> dXh;       // lifted digits [K][t][n]
     DevBuf<int64_t> dR0, dR1;   // residuals [t][n]
     DevBuf<uint32_t> dRm0, dRm1;
@@ -506,6 +508,18 @@ struct Driver {
     DevBuf<int32_t> derr;
     DevBuf<uint32_t> ddet;
     bool cert_exact = true;
+
+    // A as int32 rows of stride ldl (zero padded) for the lifting kernels.
+    int upload_a32() {
+        ldl = (n + 3) / 4 * 4;
+        std::vector<int32_t> a32((size_t)n * ldl, 0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) a32[(size_t)i * ldl + j] = (int32_t)A[i * n + j];
+        DRV_ST(dA32.alloc(a32.size()));
+        DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice, stream));
+        DRV_ST(sync());                                  // the host vector goes out of scope
+        return RNS_OK;
+    }
 
     // det A mod aux primes idx[0..count) by forward elimination, all at once.
     int det_mod_primes(const std::vector<int> &idx, std::vector<uint32_t> &det) {
@@ -556,7 +570,13 @@ struct Driver {
             DRV_HIP(hipMemcpyAsync(&sing, dsing.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
             DRV_HIP(hipMemcpyAsync(detp, ddet.p, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
             DRV_ST(sync());
-            if (!sing) return RNS_OK;
+            if (!sing) {
+                DRV_ST(dC.alloc((size_t)n * ldl));
+                DRV_HIP(hipMemsetAsync(dC.p, 0, sizeof(uint32_t) * n * ldl, stream));
+                DRV_HIP(hipMemcpy2DAsync(dC.p, sizeof(uint32_t) * ldl, dG.p + n, sizeof(uint32_t) * 2 * n,
+                                         sizeof(uint32_t) * n, n, hipMemcpyDeviceToDevice, stream));
+                return RNS_OK;
+            }
             // A prime divides det A.  Enough such primes prove det A = 0.
             singular += 1;
             if (singular * 25.9 > abits + 1.0) return RNS_ESINGULAR;
@@ -575,12 +595,14 @@ struct Driver {
         // Guaranteed step count: the combinations' numerators stay below
         // H n 2^30 t, their denominators below H; |s R A^-1 J| < H n^2 2^14.
         const int64_t Kmax = (int64_t)std::ceil((2.0 * abits + 4.0 * ln + 64.0) / lp) + 1;
-        std::vector<int64_t> J((size_t)t * n);
-        std::vector<uint32_t> Jm((size_t)t * n);
-        for (size_t e = 0; e < J.size(); ++e) {
-            J[e] = (int64_t)(rng.next() % 257) - 128;
-            Jm[e] = (uint32_t)(J[e] < 0 ? J[e] + (int64_t)p : J[e]);
-        }
+        std::vector<int64_t> J((size_t)t * ldl, 0);
+        std::vector<uint32_t> Jm((size_t)t * ldl, 0u);
+        for (int c = 0; c < t; ++c)
+            for (int64_t r = 0; r < n; ++r) {
+                const int64_t v = (int64_t)(rng.next() % 257) - 128;
+                J[(size_t)c * ldl + r] = v;
+                Jm[(size_t)c * ldl + r] = (uint32_t)(v < 0 ? v + (int64_t)p : v);
+            }
         std::vector<int32_t> Rp((size_t)tp * n);
         for (auto &v : Rp) v = (int32_t)(rng.next() % 257) - 128;
         std::vector<uint32_t> w1(t), w2(t);
@@ -588,11 +610,11 @@ struct Driver {
             w1[c] = 1 + (uint32_t)(rng.next() % 65535);
             w2[c] = 1 + (uint32_t)(rng.next() % 65535);
         }
-        DRV_ST(dXh.alloc((size_t)Kmax * t * n));
-        DRV_ST(dR0.alloc((size_t)t * n));
-        DRV_ST(dR1.alloc((size_t)t * n));
-        DRV_ST(dRm0.alloc((size_t)t * n));
-        DRV_ST(dRm1.alloc((size_t)t * n));
+        DRV_ST(dXh.alloc((size_t)Kmax * t * ldl));
+        DRV_ST(dR0.alloc((size_t)t * ldl));
+        DRV_ST(dR1.alloc((size_t)t * ldl));
+        DRV_ST(dRm0.alloc((size_t)t * ldl));
+        DRV_ST(dRm1.alloc((size_t)t * ldl));
         DRV_ST(dRp.alloc((size_t)tp * n));
         DRV_ST(derr.alloc(1));
         DRV_HIP(hipMemcpyAsync(dR0.p, J.data(), sizeof(int64_t) * J.size(), hipMemcpyHostToDevice, stream));
@@ -613,13 +635,13 @@ struct Driver {
         for (;;) {
             K_chk = std::min(K_chk, Kmax);
             for (int64_t i = K_done; i < K_chk; ++i) {
-                launch_lift_step(dG.p + n, 2 * n, dA32.p, n, t, p, Rm[cur], R[cur], dXh.p + i * t * n,
+                launch_lift_step(dC.p, dA32.p, n, ldl, t, p, Rm[cur], R[cur], dXh.p + i * t * ldl,
                                  R[1 - cur], Rm[1 - cur], derr.p, stream);
                 cur ^= 1;
             }
             const int64_t nb = K_chk - K_done;
             DRV_ST(dZ.alloc((size_t)nb * ne));
-            launch_lift_proj(dXh.p, n, t, dRp.p, tp, K_done, K_chk, dZ.p, stream);
+            launch_lift_proj(dXh.p, n, ldl, t, dRp.p, tp, K_done, K_chk, dZ.p, stream);
             DRV_HIP(hipGetLastError());
             hz.resize((size_t)nb * ne);
             int32_t err = 0;
@@ -755,10 +777,7 @@ struct Driver {
     int run_lifting(rns_smith_result *res) {
         const double t0 = now_s();
         st.path = 1;
-        std::vector<int32_t> a32((size_t)n * n);
-        for (size_t e = 0; e < a32.size(); ++e) a32[e] = (int32_t)A[e];
-        DRV_ST(dA32.alloc(a32.size()));
-        DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice, stream));
+        DRV_ST(upload_a32());
         SplitMix rng{seed ^ 0xA0761D6478BD642Full};
         int pidx = 0;
         uint32_t detp = 0;
@@ -821,10 +840,7 @@ struct Driver {
     int run_lif(rns_smith_result *res) {
         const double t0 = now_s();
         st.path = 1;
-        std::vector<int32_t> a32((size_t)n * n);
-        for (size_t e = 0; e < a32.size(); ++e) a32[e] = (int32_t)A[e];
-        DRV_ST(dA32.alloc(a32.size()));
-        DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice, stream));
+        DRV_ST(upload_a32());
         SplitMix rng{seed ^ 0x2545F4914F6CDD1Dull};
         int pidx = 0;
         uint32_t detp = 0;

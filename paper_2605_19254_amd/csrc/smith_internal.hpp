@@ -27,14 +27,16 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
                     hipStream_t s);
 void launch_gj_step(uint32_t *M, int64_t n, int64_t ld, int k, const GjPrime *pr, int P,
                     int32_t *singular, uint32_t *det, hipStream_t s);
-// One step of p-adic lifting for t <= 16 right-hand sides (columns of R, X
-// stored [t][n]) and the projections of stored digits.
+// One step of p-adic lifting for t <= 16 right-hand sides and the
+// projections of stored digits.  C (n x n mod p) and A (n x n int32) have
+// row stride ld, a multiple of 4, and are zero in columns n..ld-1; R, Rm and
+// X hold t vectors of stride ld ([t][ld]).
 constexpr int kLiftMaxCols = 16;
-void launch_lift_step(const uint32_t *C, int64_t ldc, const int32_t *A, int64_t n, int t, uint32_t p,
+void launch_lift_step(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
                       const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                       int32_t *err, hipStream_t s);
-void launch_lift_proj(const uint32_t *Xh, int64_t n, int t, const int32_t *Rp, int tp, int64_t i0,
-                      int64_t i1, int64_t *Z, hipStream_t s);
+void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,
+                      int64_t i0, int64_t i1, int64_t *Z, hipStream_t s);
 void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t plane_stride,
                   const GjPrime *pr, const uint32_t *c, int P, hipStream_t s);
 void launch_words_mod(const uint64_t *x, int64_t count, int W, const GjPrime *pr, int L,

@@ -131,25 +131,34 @@ __global__ __launch_bounds__(256) void k_gj_load(const int64_t *__restrict__ A, 
 
 constexpr int kLiftMaxT = 16;
 
-// X[c][r] = sum_k C[r][k] Rm[c][k] mod p.  Each lane sums at most
-// ceil(n/64) products below 2^52 (n <= 65536 keeps that below 2^62), reduces
-// its sum mod p, and the wave adds the 64 reduced sums.
+// Rows of C and A, and the vectors R, Rm, X, have a padded stride ld (a
+// multiple of 4); C and A are zero beyond column n, so every row is read with
+// 16-byte loads and the padding contributes nothing.
+
+// X[c][r] = sum_k C[r][k] Rm[c][k] mod p.  Each lane sums at most ld/64
+// products below 2^52 (ld <= 65536 keeps that below 2^62), reduces its sum
+// mod p, and the wave adds the 64 reduced sums.
 template <int T>
-__global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, int64_t ldc, int64_t n,
+__global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, int64_t n, int64_t ld,
                                                 const uint32_t *__restrict__ Rm, int t, uint32_t p,
                                                 uint32_t *__restrict__ X) {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= n) return;                                  // whole waves only
-    const uint32_t *Cr = C + r * ldc;
+    const uint4 *Cr = reinterpret_cast<const uint4 *>(C + r * ld);
+    const int64_t q = ld / 4;
     uint64_t acc[T];
 #pragma unroll
     for (int c = 0; c < T; ++c) acc[c] = 0;
-    for (int64_t k = lane; k < n; k += 64) {
-        const uint64_t cv = Cr[k];
+    for (int64_t k = lane; k < q; k += 64) {
+        const uint4 cv = Cr[k];
 #pragma unroll
         for (int c = 0; c < T; ++c)
-            if (c < t) acc[c] += cv * Rm[(int64_t)c * n + k];
+            if (c < t) {
+                const uint4 rv = reinterpret_cast<const uint4 *>(Rm + (int64_t)c * ld)[k];
+                acc[c] += (uint64_t)cv.x * rv.x + (uint64_t)cv.y * rv.y + (uint64_t)cv.z * rv.z +
+                          (uint64_t)cv.w * rv.w;
+            }
     }
 #pragma unroll
     for (int c = 0; c < T; ++c) {
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
             uint64_t v = acc[c] % p;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            if (lane == 0) X[(int64_t)c * n + r] = (uint32_t)(v % p);
+            if (lane == 0) X[(int64_t)c * ld + r] = (uint32_t)(v % p);
         }
     }
 }
@@ -165,9 +174,10 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
 // R'[c][r] = (R[c][r] - sum_k A[r][k] X[c][k]) / p and Rm'[c][r] = R' mod p.
 // The host admits this form only when n max|a| p < 2^62, so every sum fits in
 // an int64.  A division that is not exact (impossible for a correct C) sets
-// *err instead of producing a wrong residual silently.
+// *err instead of producing a wrong residual silently.  X beyond row n is
+// never written; A's zero columns make its value irrelevant.
 template <int T>
-__global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, int64_t n,
+__global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, int64_t n, int64_t ld,
                                                 const uint32_t *__restrict__ X,
                                                 const int64_t *__restrict__ R, int t, uint32_t p,
                                                 int64_t *__restrict__ Rn, uint32_t *__restrict__ Rmn,
@@ -175,15 +185,20 @@ __global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, i
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= n) return;
-    const int32_t *Ar = A + r * n;
+    const int4 *Ar = reinterpret_cast<const int4 *>(A + r * ld);
+    const int64_t q = ld / 4;
     int64_t acc[T];
 #pragma unroll
     for (int c = 0; c < T; ++c) acc[c] = 0;
-    for (int64_t k = lane; k < n; k += 64) {
-        const int64_t av = Ar[k];
+    for (int64_t k = lane; k < q; k += 64) {
+        const int4 av = Ar[k];
 #pragma unroll
         for (int c = 0; c < T; ++c)
-            if (c < t) acc[c] += av * (int64_t)X[(int64_t)c * n + k];
+            if (c < t) {
+                const uint4 xv = reinterpret_cast<const uint4 *>(X + (int64_t)c * ld)[k];
+                acc[c] += (int64_t)av.x * xv.x + (int64_t)av.y * xv.y + (int64_t)av.z * xv.z +
+                          (int64_t)av.w * xv.w;
+            }
     }
 #pragma unroll
     for (int c = 0; c < T; ++c) {
@@ -192,26 +207,27 @@ __global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, i
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
         if (lane == 0) {
-            const int64_t num = R[(int64_t)c * n + r] - v;
-            const int64_t q = num / (int64_t)p;
-            if (q * (int64_t)p != num) atomicOr(err, 1);
-            Rn[(int64_t)c * n + r] = q;
-            const int64_t m = q % (int64_t)p;
-            Rmn[(int64_t)c * n + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+            const int64_t num = R[(int64_t)c * ld + r] - v;
+            const int64_t qq = num / (int64_t)p;
+            if (qq * (int64_t)p != num) atomicOr(err, 1);
+            Rn[(int64_t)c * ld + r] = qq;
+            const int64_t m = qq % (int64_t)p;
+            Rmn[(int64_t)c * ld + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
         }
     }
 }
 
 // Projections of stored digits: Z[i][a][c] = sum_r Rp[a][r] Xh[i][c][r] for
-// steps i in [i0, i1), a < tp, c < t.  One block per (step, column); each
-// thread sums a strided share of the rows, then the block adds the shares.
-// |Rp| <= 2^8 and X < 2^26, so the sums stay far inside int64.
-__global__ __launch_bounds__(256) void k_lift_proj(const uint32_t *__restrict__ Xh, int64_t n, int t,
-                                                   const int32_t *__restrict__ Rp, int tp, int64_t i0,
-                                                   int64_t *__restrict__ Z) {
+// steps i in [i0, i1), a < tp, c < t, r < n (digit vectors have stride ld).
+// One block per (step, column); each thread sums a strided share of the rows,
+// then the block adds the shares.  |Rp| <= 2^8 and X < 2^26, so the sums
+// stay far inside int64.
+__global__ __launch_bounds__(256) void k_lift_proj(const uint32_t *__restrict__ Xh, int64_t n, int64_t ld,
+                                                   int t, const int32_t *__restrict__ Rp, int tp,
+                                                   int64_t i0, int64_t *__restrict__ Z) {
     const int64_t i = i0 + blockIdx.x / t;
     const int c = blockIdx.x % t;
-    const uint32_t *x = Xh + (i * t + c) * n;
+    const uint32_t *x = Xh + (i * t + c) * ld;
     int64_t acc[kLiftMaxT + 2];
     for (int a = 0; a < tp; ++a) acc[a] = 0;
     for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
@@ -460,26 +476,26 @@ void launch_gj_step(uint32_t *M, int64_t n, int64_t ld, int k, const GjPrime *pr
 }
 
 template <int T>
-static void lift_step_t(const uint32_t *C, int64_t ldc, const int32_t *A, int64_t n, int t, uint32_t p,
+static void lift_step_t(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
                         const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                         int32_t *err, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + 3) / 4);
-    hipLaunchKernelGGL(k_lift_x<T>, dim3(blocks), dim3(256), 0, s, C, ldc, n, Rm, t, p, X);
-    hipLaunchKernelGGL(k_lift_r<T>, dim3(blocks), dim3(256), 0, s, A, n, X, R, t, p, Rn, Rmn, err);
+    hipLaunchKernelGGL(k_lift_x<T>, dim3(blocks), dim3(256), 0, s, C, n, ld, Rm, t, p, X);
+    hipLaunchKernelGGL(k_lift_r<T>, dim3(blocks), dim3(256), 0, s, A, n, ld, X, R, t, p, Rn, Rmn, err);
 }
 
-void launch_lift_step(const uint32_t *C, int64_t ldc, const int32_t *A, int64_t n, int t, uint32_t p,
+void launch_lift_step(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
                       const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                       int32_t *err, hipStream_t s) {
-    if (t <= 4) lift_step_t<4>(C, ldc, A, n, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else if (t <= 8) lift_step_t<8>(C, ldc, A, n, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else lift_step_t<kLiftMaxT>(C, ldc, A, n, t, p, Rm, R, X, Rn, Rmn, err, s);
+    if (t <= 4) lift_step_t<4>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else if (t <= 8) lift_step_t<8>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else lift_step_t<kLiftMaxT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
 }
 
-void launch_lift_proj(const uint32_t *Xh, int64_t n, int t, const int32_t *Rp, int tp, int64_t i0,
-                      int64_t i1, int64_t *Z, hipStream_t s) {
+void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,
+                      int64_t i0, int64_t i1, int64_t *Z, hipStream_t s) {
     if (i1 <= i0) return;
-    hipLaunchKernelGGL(k_lift_proj, dim3((unsigned)((i1 - i0) * t)), dim3(256), 0, s, Xh, n, t, Rp, tp,
+    hipLaunchKernelGGL(k_lift_proj, dim3((unsigned)((i1 - i0) * t)), dim3(256), 0, s, Xh, n, ld, t, Rp, tp,
                        i0, Z);
 }
 
