@@ -142,7 +142,13 @@ typedef struct rns_gemm_desc {
     int64_t ldc, c_plane_stride;
     int32_t prime_begin;
     int32_t L;
+    int32_t flags;         /* 0, or RNS_GEMM_SUBTRACT */
+    int32_t reserved;      /* 0 */
 } rns_gemm_desc;
+
+/* rns_gemm_desc.flags: C := (C - A B) mod p instead of C := A B mod p (C must
+ * then hold residues in [0, p) on entry). */
+#define RNS_GEMM_SUBTRACT 1
 
 /* Workspace bytes modmatmul_batched needs for these problems on this path. */
 int rns_workspace_bytes(rns_ctx *ctx, const rns_gemm_desc *descs, int count,

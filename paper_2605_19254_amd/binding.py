@@ -71,7 +71,8 @@ class RnsGemmDesc(ctypes.Structure):
                 ("A", _P), ("lda", _I64), ("a_plane_stride", _I64),
                 ("B", _P), ("ldb", _I64), ("b_plane_stride", _I64),
                 ("C", _P), ("ldc", _I64), ("c_plane_stride", _I64),
-                ("prime_begin", ctypes.c_int32), ("L", ctypes.c_int32)]
+                ("prime_begin", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RnsSmithStats(ctypes.Structure):
@@ -328,12 +329,14 @@ def rns_reduce(ctx: Context, x, prime_begin: int = 0, L: Optional[int] = None, o
 
 @dataclass
 class GemmProblem:
-    """C[j] = A[j] @ B[j] mod p_{prime_begin+j}; A [L, m, k], B [L, k, n],
-    C [L, m, n], int32 device tensors with unit column stride."""
+    """C[j] = A[j] @ B[j] mod p_{prime_begin+j} (or, with subtract,
+    C[j] = C[j] - A[j] @ B[j] mod p); A [L, m, k], B [L, k, n], C [L, m, n],
+    int32 device tensors with unit column stride."""
     A: object
     B: object
     C: object
     prime_begin: int = 0
+    subtract: bool = False
 
     def desc(self) -> RnsGemmDesc:
         L, m, k = self.A.shape
@@ -347,6 +350,7 @@ class GemmProblem:
         d.B, d.ldb, d.b_plane_stride = _dev_ptr(self.B), self.B.stride(1), self.B.stride(0)
         d.C, d.ldc, d.c_plane_stride = _dev_ptr(self.C), self.C.stride(1), self.C.stride(0)
         d.prime_begin, d.L = self.prime_begin, L
+        d.flags = 1 if self.subtract else 0
         return d
 
 

@@ -32,6 +32,7 @@ struct Plan {
 
 int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x) {
     if (x.m < 0 || x.n < 0 || x.k < 0 || x.L < 0) return RNS_EINVAL;
+    if ((x.flags & ~RNS_GEMM_SUBTRACT) != 0 || x.reserved != 0) return RNS_EINVAL;
     if (x.prime_begin < 0 || x.prime_begin + x.L > ctx->L) return RNS_EINVAL;
     if (x.m > INT32_MAX / 2 || x.n > INT32_MAX / 2 || x.k > INT32_MAX / 2) return RNS_EINVAL;
     if (x.m == 0 || x.n == 0 || x.L == 0) return RNS_OK;
@@ -75,6 +76,7 @@ int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &
         g.ldc = x.ldc; g.cps = x.c_plane_stride;
         g.m = (int32_t)x.m; g.n = (int32_t)x.n; g.k = (int32_t)x.k;
         g.L = x.L; g.prime_begin = x.prime_begin;
+        g.sub = (x.flags & RNS_GEMM_SUBTRACT) ? 1 : 0;
         const int64_t Mp = round_up(x.m, TM), Np = round_up(x.n, TN);
         const int64_t Kp = round_up(std::max<int64_t>(x.k, 1), kKTile);
         g.RB = (int32_t)(Mp / 16); g.CB = (int32_t)(Np / 16); g.KT = (int32_t)(Kp / kKTile);

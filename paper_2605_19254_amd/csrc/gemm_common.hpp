@@ -25,6 +25,7 @@ struct GemmProblem {
     int64_t lda, aps, ldb, bps, ldc, cps;
     int32_t m, n, k;
     int32_t L, prime_begin;
+    int32_t sub;                 // 1: C := C - A B mod p
     int32_t RB, CB, KT;          // padded 16-row blocks of A, 16-col blocks of B, 64-k tiles
     int32_t tm, tn;              // work-group tiles along m and n
     char *At, *Bt;               // tiled operands in the workspace
@@ -88,6 +89,15 @@ __device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, i
 }
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Stores one reduced product r in [0, p) at C, or C - r mod p when sub is set.
+__device__ __forceinline__ void store_residue(uint32_t *C, uint32_t r, uint32_t p, int32_t sub) {
+    if (sub) {
+        const uint32_t c0 = *C;
+        r = c0 >= r ? c0 - r : c0 + p - r;
+    }
+    *C = r;
+}
 
 // Launchers (one per kernel family), all asynchronous on `s`.
 // INT8 GEMM variants (the autotuner chooses among them per shape class).

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmProblem *__restrict_
                 // register v of lane `lane` (the INT8 form uses 4*(lane/16) + v).
                 const int row = (rb0 + i) * 16 + 4 * v + (lane >> 4);
                 const int col = (cb0 + j) * 16 + (lane & 15);
-                if (row < g.m && col < g.n) C[(int64_t)row * g.ldc + col] = (uint32_t)r;
+                if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, (uint32_t)r, pr.p, g.sub);
             }
 }
 

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const GemmProblem *__restrict__
                 r = r < 0.0 ? r + pr.pf : r;
                 const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + v;
                 const int col = (cb0 + j) * 16 + (lane & 15);
-                if (row < g.m && col < g.n) C[(int64_t)row * g.ldc + col] = (uint32_t)r;
+                if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, (uint32_t)r, pr.p, g.sub);
             }
 }
 
@@ -249,7 +249,7 @@ __device__ __forceinline__ void i8_lds_tile(const GemmProblem &g, int plane, int
                 r = r < 0.0 ? r + pr.pf : r;
                 const int row = (rblk0 + wy * S::kRB + i) * 16 + 4 * (lane >> 4) + v;
                 const int col = (cblk0 + wx * S::kCB + j) * 16 + (lane & 15);
-                if (row < g.m && col < g.n) C[(int64_t)row * g.ldc + col] = (uint32_t)r;
+                if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, (uint32_t)r, pr.p, g.sub);
             }
 }
 

@@ -219,6 +219,72 @@ struct Driver {
         return RNS_OK;
     }
 
+    DevBuf<uint32_t> dS, dW;    // blocked elimination: panel copies, pivot-block inverses
+    DevBuf<int32_t> dpiv, dneed;
+
+    // Eliminates the P planes of M ([P][n][ld], residues mod the aux primes
+    // pbeg .. pbeg+P-1, prime table dpr): Gauss-Jordan when ld = 2n (the right
+    // halves become A^-1 mod p), forward elimination when ld = n (det only).
+    // Blocks of kGjBlock columns: panel, swaps and pivot-block inverse on the
+    // GPU (launch_gj_block), then two residue products per block through
+    // modmatmul_batched: pivot rows <- P11^-1 (pivot rows), and every other
+    // row (rows below only for ld = n) minus its panel times the pivot rows.
+    // Both products read their operands from the tiled workspace, which the
+    // product's own conversion kernel fills before the product writes C, so
+    // the update in place is safe.
+    int eliminate(uint32_t *M, int64_t ld, int P, int pbeg, uint32_t *det) {
+        const bool full = ld == 2 * n;
+        DRV_ST(dS.alloc((size_t)P * n * kGjBlock));
+        DRV_ST(dpiv.alloc((size_t)P * kGjBlock));
+        DRV_ST(dW.alloc((size_t)P * kGjBlock * kGjBlock));
+        DRV_ST(dneed.alloc((size_t)P));
+        std::vector<int32_t> need(P);
+        const int64_t ps = n * ld;
+        for (int64_t r0 = 0; r0 < n; r0 += kGjBlock) {
+            const int bw = (int)std::min<int64_t>(kGjBlock, n - r0);
+            launch_gj_blockinv(M, n, ld, r0, bw, dpr.p, P, dW.p, dsing.p, dneed.p, det, stream);
+            DRV_HIP(hipGetLastError());
+            DRV_HIP(hipMemcpyAsync(need.data(), dneed.p, sizeof(int32_t) * P, hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+            bool any = false;
+            for (int q = 0; q < P; ++q) any |= need[q] != 0;
+            if (any) {                               // rows must be exchanged for some planes
+                launch_gj_pivoted(M, n, ld, r0, bw, dpr.p, P, dS.p, dpiv.p, dsing.p, dneed.p, det, dW.p, stream);
+                DRV_HIP(hipGetLastError());
+            }
+            rns_gemm_desc d{};
+            d.m = bw; d.n = ld - r0; d.k = bw;
+            d.A = dW.p; d.lda = kGjBlock; d.a_plane_stride = (int64_t)kGjBlock * kGjBlock;
+            d.B = M + r0 * ld + r0; d.ldb = ld; d.b_plane_stride = ps;
+            d.C = M + r0 * ld + r0; d.ldc = ld; d.c_plane_stride = ps;
+            d.prime_begin = pbeg; d.L = P;
+            DRV_ST(modmatmul_batched(aux, &d, 1, RNS_PATH_AUTO, stream));
+            st.products += 1;
+            st.residue_ops += 2.0 * d.m * d.n * d.k * P;
+            const int64_t cols = ld - r0 - bw;
+            if (cols <= 0) continue;
+            rns_gemm_desc u[2]{};
+            int cnt = 0;
+            auto add = [&](int64_t row0, int64_t rows) {
+                rns_gemm_desc &e = u[cnt++];
+                e.m = rows; e.n = cols; e.k = bw;
+                e.A = M + row0 * ld + r0; e.lda = ld; e.a_plane_stride = ps;
+                e.B = M + r0 * ld + r0 + bw; e.ldb = ld; e.b_plane_stride = ps;
+                e.C = M + row0 * ld + r0 + bw; e.ldc = ld; e.c_plane_stride = ps;
+                e.prime_begin = pbeg; e.L = P;
+                e.flags = RNS_GEMM_SUBTRACT;
+                st.residue_ops += 2.0 * rows * cols * bw * P;
+            };
+            if (full && r0 > 0) add(0, r0);
+            if (n - r0 - bw > 0) add(r0 + bw, n - r0 - bw);
+            if (cnt) {
+                DRV_ST(modmatmul_batched(aux, u, cnt, RNS_PATH_AUTO, stream));
+                st.products += 1;
+            }
+        }
+        return RNS_OK;
+    }
+
     // A^-1 mod q for the P primes aux[base .. base+P); returns the index of a
     // singular prime through *bad (-1 if none).
     int invert(int P_, int *bad) {
@@ -232,8 +298,8 @@ struct Driver {
         DRV_HIP(hipMemcpyAsync(dpr.p, h.data(), sizeof(GjPrime) * P, hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemsetAsync(dsing.p, 0, sizeof(int32_t) * P, stream));
         launch_gj_load(dA.p, n, 2 * n, dM.p, dpr.p, P, stream);
-        for (int k = 0; k < n; ++k) launch_gj_step(dM.p, n, 2 * n, k, dpr.p, P, dsing.p, nullptr, stream);
         DRV_HIP(hipGetLastError());
+        DRV_ST(eliminate(dM.p, 2 * n, P, base, nullptr));
         std::vector<int32_t> sing(P);
         DRV_HIP(hipMemcpyAsync(sing.data(), dsing.p, sizeof(int32_t) * P, hipMemcpyDeviceToHost, stream));
         DRV_ST(sync());
@@ -536,9 +602,11 @@ struct Driver {
         DRV_HIP(hipMemcpyAsync(dpr.p, h.data(), sizeof(GjPrime) * Pd, hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemcpyAsync(ddet.p, ones.data(), sizeof(uint32_t) * Pd, hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemsetAsync(dsing.p, 0, sizeof(int32_t) * Pd, stream));
+        for (int q = 1; q < Pd; ++q)
+            if (idx[q] != idx[0] + q) return RNS_EINVAL;   // the products need consecutive primes
         launch_gj_load(dA.p, n, n, dM.p, dpr.p, Pd, stream);
-        for (int k = 0; k < n; ++k) launch_gj_step(dM.p, n, n, k, dpr.p, Pd, dsing.p, ddet.p, stream);
         DRV_HIP(hipGetLastError());
+        DRV_ST(eliminate(dM.p, n, Pd, idx[0], ddet.p));
         std::vector<int32_t> sing(Pd);
         DRV_HIP(hipMemcpyAsync(det.data(), ddet.p, sizeof(uint32_t) * Pd, hipMemcpyDeviceToHost, stream));
         DRV_HIP(hipMemcpyAsync(sing.data(), dsing.p, sizeof(int32_t) * Pd, hipMemcpyDeviceToHost, stream));
@@ -564,8 +632,8 @@ struct Driver {
             DRV_HIP(hipMemcpyAsync(ddet.p, &one, sizeof(uint32_t), hipMemcpyHostToDevice, stream));
             DRV_HIP(hipMemsetAsync(dsing.p, 0, sizeof(int32_t), stream));
             launch_gj_load(dA.p, n, 2 * n, dG.p, dpr.p, 1, stream);
-            for (int k = 0; k < n; ++k) launch_gj_step(dG.p, n, 2 * n, k, dpr.p, 1, dsing.p, ddet.p, stream);
             DRV_HIP(hipGetLastError());
+            DRV_ST(eliminate(dG.p, 2 * n, 1, *pidx, ddet.p));
             int32_t sing = 0;
             DRV_HIP(hipMemcpyAsync(&sing, dsing.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
             DRV_HIP(hipMemcpyAsync(detp, ddet.p, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));

@@ -27,6 +27,18 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
                     hipStream_t s);
 void launch_gj_step(uint32_t *M, int64_t n, int64_t ld, int k, const GjPrime *pr, int P,
                     int32_t *singular, uint32_t *det, hipStream_t s);
+// Blocked elimination of P planes, block at row/column r0 of width
+// bw <= kGjBlock: launch_gj_blockinv inverts the unexchanged pivot block of
+// every plane (need[q] = 1 where that fails); launch_gj_pivoted then handles
+// the planes with need[q] = 1 (panel pivot search, row exchanges, inverse).
+// The driver finishes each block with two residue products.  S: [P][n][kGjBlock]
+// scratch; piv: [P][kGjBlock]; W: [P][kGjBlock][kGjBlock]; det optional.
+constexpr int kGjBlock = 128;
+void launch_gj_blockinv(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, const GjPrime *pr, int P,
+                        uint32_t *W, int32_t *singular, int32_t *need, uint32_t *det, hipStream_t s);
+void launch_gj_pivoted(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, const GjPrime *pr, int P,
+                       uint32_t *S, int32_t *piv, int32_t *singular, int32_t *need, uint32_t *det, uint32_t *W,
+                       hipStream_t s);
 // One step of p-adic lifting for t <= 16 right-hand sides and the
 // projections of stored digits.  C (n x n mod p) and A (n x n int32) have
 // row stride ld, a multiple of 4, and are zero in columns n..ld-1; R, Rm and

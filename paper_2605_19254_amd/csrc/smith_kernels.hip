@@ -123,6 +123,181 @@ __global__ __launch_bounds__(256) void k_gj_load(const int64_t *__restrict__ A, 
     M[((int64_t)q * n + i) * ld + j] = v;
 }
 
+// ------------------------------------------ blocked elimination mod p --
+// Elimination of P planes M [P][n][ld] in blocks of bw <= kGjBlock columns
+// (ld = 2n: Gauss-Jordan on [A | I]; ld = n: forward elimination for the
+// determinant).  Per block starting at row and column r0:
+//   k_gj_blockinv (mode 0) inverts the block P11 = M[r0.., r0..] without row
+//                 exchanges; it succeeds when the leading minors of P11 are
+//                 nonzero mod p, which for a 26-bit prime fails only rarely,
+//                 and then multiplies det[q] by its pivots; on a zero pivot
+//                 it marks the plane in need[q] instead.
+//   For the marked planes only:
+//   k_gj_panel    eliminates a copy of the block's columns below row r0 with
+//                 the first nonzero entry as pivot, recording the row swaps
+//                 and multiplying det[q] by the pivots (no pivot: singular);
+//   k_gj_swap     applies those swaps to the whole rows of M;
+//   k_gj_blockinv (mode 1) inverts the new P11 (its leading minors are the
+//                 pivots just found, so no pivoting is needed).
+// The driver completes the block with two residue products:
+//   pivot rows <- P11^-1 (pivot rows),   other rows -= (their panel) (pivot rows),
+// which is Gauss-Jordan (or LU's Schur complement) for bw columns at once.
+
+constexpr int kGjBlockMax = kGjBlock;
+
+__global__ __launch_bounds__(1024) void k_gj_panel(const uint32_t *__restrict__ M, int64_t n, int64_t ld,
+                                                   int64_t r0, int bw, const GjPrime *__restrict__ pr,
+                                                   uint32_t *__restrict__ S, int32_t *__restrict__ piv,
+                                                   int32_t *__restrict__ singular,
+                                                   const int32_t *__restrict__ need,
+                                                   uint32_t *__restrict__ det) {
+    const int q = blockIdx.x;
+    if (singular[q] || !need[q]) return;
+    const uint32_t *Mq = M + (int64_t)q * n * ld;
+    const int64_t rows = n - r0;
+    uint32_t *Sq = S + (int64_t)q * n * kGjBlockMax;           // [rows][bw]
+    for (int64_t e = threadIdx.x; e < rows * bw; e += blockDim.x) {
+        const int64_t i = e / bw;
+        const int c = (int)(e - i * bw);
+        Sq[e] = Mq[(r0 + i) * ld + r0 + c];
+    }
+    __syncthreads();
+    const double pf = pr[q].pf, pinv = pr[q].pinv;
+    const uint32_t p = pr[q].p;
+    __shared__ int best;
+    __shared__ uint32_t inv;
+    for (int j = 0; j < bw; ++j) {
+        if (threadIdx.x == 0) best = (int)rows;
+        __syncthreads();
+        for (int64_t i = j + threadIdx.x; i < rows; i += blockDim.x)
+            if (Sq[i * bw + j] != 0) atomicMin(&best, (int)i);
+        __syncthreads();
+        const int r = best;                                    // the same on every thread
+        if (r >= rows) {
+            if (threadIdx.x == 0) singular[q] = 1;
+            return;
+        }
+        if (r != j)
+            for (int c = threadIdx.x; c < bw; c += blockDim.x) {
+                const uint32_t t = Sq[(int64_t)j * bw + c];
+                Sq[(int64_t)j * bw + c] = Sq[(int64_t)r * bw + c];
+                Sq[(int64_t)r * bw + c] = t;
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            piv[q * kGjBlockMax + j] = (int)(r0 + r);
+            const uint32_t pv = Sq[(int64_t)j * bw + j];
+            if (det) {
+                const uint32_t d = mulmod_p(det[q], pv, pf, pinv);
+                det[q] = (r != j && d != 0) ? p - d : d;
+            }
+            inv = powmod_p(pv, p - 2, pf, pinv);
+        }
+        __syncthreads();
+        const int w = bw - j - 1;                              // columns right of the pivot
+        if (w > 0)
+            for (int64_t e = threadIdx.x; e < (rows - j - 1) * (int64_t)w; e += blockDim.x) {
+                const int64_t i = j + 1 + e / w;
+                const int c = j + 1 + (int)(e % w);
+                const uint32_t f = Sq[i * bw + j];
+                if (f == 0) continue;
+                const uint32_t t = mulmod_p(mulmod_p(f, inv, pf, pinv), Sq[(int64_t)j * bw + c], pf, pinv);
+                const uint32_t a = Sq[i * bw + c];
+                Sq[i * bw + c] = a >= t ? a - t : a + p - t;
+            }
+        __syncthreads();
+    }
+}
+
+// Applies the recorded swaps (row r0+j <-> row piv[j], j = 0..bw-1, in order)
+// to every column; one thread per column.
+__global__ __launch_bounds__(256) void k_gj_swap(uint32_t *__restrict__ M, int64_t n, int64_t ld, int64_t r0,
+                                                 int bw, const int32_t *__restrict__ piv,
+                                                 const int32_t *__restrict__ singular,
+                                                 const int32_t *__restrict__ need) {
+    const int q = blockIdx.y;
+    if (singular[q] || !need[q]) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ld) return;
+    uint32_t *Mq = M + (int64_t)q * n * ld;
+    for (int j = 0; j < bw; ++j) {
+        const int64_t r = piv[q * kGjBlockMax + j];
+        if (r != r0 + j) {
+            const uint32_t t = Mq[(r0 + j) * ld + c];
+            Mq[(r0 + j) * ld + c] = Mq[r * ld + c];
+            Mq[r * ld + c] = t;
+        }
+    }
+}
+
+// W[q] = P11^-1 for the pivot block M[r0.., r0..] (bw x bw), Gauss-Jordan on
+// [P11 | I] in LDS without row exchanges.  Mode 0 runs on every plane, sets
+// need[q] = 0 and multiplies det[q] by the pivots on success, or sets
+// need[q] = 1 on a zero pivot (W is then not used); mode 1 runs on the planes
+// with need[q] = 1 after their rows were exchanged (a zero pivot then means
+// a singular plane).
+__global__ __launch_bounds__(1024) void k_gj_blockinv(const uint32_t *__restrict__ M, int64_t n, int64_t ld,
+                                                      int64_t r0, int bw, const GjPrime *__restrict__ pr,
+                                                      uint32_t *__restrict__ W, int32_t *__restrict__ singular,
+                                                      int32_t *__restrict__ need, uint32_t *__restrict__ det,
+                                                      int mode) {
+    __shared__ uint32_t T[kGjBlockMax][2 * kGjBlockMax];
+    __shared__ uint32_t F[kGjBlockMax];
+    __shared__ uint32_t inv, dprod;
+    __shared__ int failed;
+    const int q = blockIdx.x;
+    if (singular[q] || (mode == 1 && !need[q])) return;
+    const uint32_t *Mq = M + (int64_t)q * n * ld;
+    const int w2 = 2 * bw;
+    for (int e = threadIdx.x; e < bw * w2; e += blockDim.x) {
+        const int i = e / w2, c = e % w2;
+        T[i][c] = c < bw ? Mq[(r0 + i) * ld + r0 + c] : (uint32_t)(c - bw == i);
+    }
+    if (threadIdx.x == 0) {
+        failed = 0;
+        dprod = 1;
+    }
+    __syncthreads();
+    const double pf = pr[q].pf, pinv = pr[q].pinv;
+    const uint32_t p = pr[q].p;
+    for (int j = 0; j < bw; ++j) {
+        if (threadIdx.x == 0) {
+            const uint32_t pv = T[j][j];
+            if (pv == 0) failed = 1;
+            dprod = mulmod_p(dprod, pv, pf, pinv);
+            inv = powmod_p(pv, p - 2, pf, pinv);
+        }
+        __syncthreads();
+        if (failed) break;                                    // the same on every thread
+        for (int c = threadIdx.x; c < w2; c += blockDim.x) T[j][c] = mulmod_p(T[j][c], inv, pf, pinv);
+        __syncthreads();
+        for (int i = threadIdx.x; i < bw; i += blockDim.x) F[i] = i == j ? 0u : T[i][j];
+        __syncthreads();
+        for (int e = threadIdx.x; e < bw * w2; e += blockDim.x) {
+            const int i = e / w2, c = e % w2;
+            if (F[i] == 0) continue;
+            const uint32_t t = mulmod_p(F[i], T[j][c], pf, pinv);
+            const uint32_t a = T[i][c];
+            T[i][c] = a >= t ? a - t : a + p - t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            need[q] = failed;
+            if (!failed && det) det[q] = mulmod_p(det[q], dprod, pf, pinv);
+        } else if (failed) {
+            singular[q] = 1;                                  // cannot happen after k_gj_panel
+        }
+    }
+    if (failed) return;
+    uint32_t *Wq = W + (int64_t)q * kGjBlockMax * kGjBlockMax;   // [bw][bw], stride kGjBlockMax
+    for (int e = threadIdx.x; e < bw * bw; e += blockDim.x) {
+        const int i = e / bw, c = e % bw;
+        Wq[i * kGjBlockMax + c] = T[i][bw + c];
+    }
+}
+
 // ----------------------------------------------------- p-adic lifting --
 // Dixon's iteration for A Y = J with C = A^-1 mod p resident: with R_0 = J,
 //   X_i = C R_i mod p,   R_{i+1} = (R_i - A X_i) / p   (an exact division),
@@ -150,6 +325,7 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
     uint64_t acc[T];
 #pragma unroll
     for (int c = 0; c < T; ++c) acc[c] = 0;
+#pragma unroll 4
     for (int64_t k = lane; k < q; k += 64) {
         const uint4 cv = Cr[k];
 #pragma unroll
@@ -190,6 +366,7 @@ __global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, i
     int64_t acc[T];
 #pragma unroll
     for (int c = 0; c < T; ++c) acc[c] = 0;
+#pragma unroll 4
     for (int64_t k = lane; k < q; k += 64) {
         const int4 av = Ar[k];
 #pragma unroll
@@ -497,6 +674,23 @@ void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const in
     if (i1 <= i0) return;
     hipLaunchKernelGGL(k_lift_proj, dim3((unsigned)((i1 - i0) * t)), dim3(256), 0, s, Xh, n, ld, t, Rp, tp,
                        i0, Z);
+}
+
+void launch_gj_blockinv(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, const GjPrime *pr, int P,
+                        uint32_t *W, int32_t *singular, int32_t *need, uint32_t *det, hipStream_t s) {
+    hipLaunchKernelGGL(k_gj_blockinv, dim3((unsigned)P), dim3(1024), 0, s, M, n, ld, r0, bw, pr, W, singular, need,
+                       det, 0);
+}
+
+void launch_gj_pivoted(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, const GjPrime *pr, int P,
+                       uint32_t *S, int32_t *piv, int32_t *singular, int32_t *need, uint32_t *det, uint32_t *W,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_gj_panel, dim3((unsigned)P), dim3(1024), 0, s, M, n, ld, r0, bw, pr, S, piv, singular,
+                       need, det);
+    hipLaunchKernelGGL(k_gj_swap, dim3((unsigned)((ld + 255) / 256), (unsigned)P), dim3(256), 0, s, M, n, ld, r0,
+                       bw, piv, singular, need);
+    hipLaunchKernelGGL(k_gj_blockinv, dim3((unsigned)P), dim3(1024), 0, s, M, n, ld, r0, bw, pr, W, singular, need,
+                       det, 1);
 }
 
 void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t plane_stride,

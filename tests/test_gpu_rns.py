@@ -113,6 +113,29 @@ def test_modmatmul_matches_oracle(ctx, rg, torch_dev, path, m, n, k):
 
 
 @pytest.mark.parametrize("path", ["int8", "fp64"])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (65, 129, 130), (130, 300, 128), (40, 70, 0)])
+def test_modmatmul_subtract(ctx, rg, torch_dev, path, m, n, k):
+    """C := C - A B mod p (RNS_GEMM_SUBTRACT) against the oracle's product."""
+    torch, dev = torch_dev
+    _say("modmatmul subtract", path, m, n, k)
+    rng = np.random.default_rng(m + 3 * n + 5 * k)
+    begin, L = 4, 5
+    ps = PRIMES[begin:begin + L]
+    a = _res(rng, ps, m, k, edge=True)
+    b = _res(rng, ps, k, n, edge=True)
+    c0 = _res(rng, ps, m, n, edge=True)
+    c = torch.from_numpy(c0.copy()).to(dev)
+    ta = torch.from_numpy(a).to(dev) if k else torch.empty((L, m, 0), dtype=torch.int32, device=dev)
+    tb = torch.from_numpy(b).to(dev) if k else torch.empty((L, 0, n), dtype=torch.int32, device=dev)
+    rg.modmatmul_batched(ctx, [rg.GemmProblem(ta, tb, c, begin, subtract=True)], path=path)
+    got = c.cpu().numpy()
+    for j, p in enumerate(ps):
+        prod = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int64) if k else 0
+        want = ((c0[j].astype(np.int64) - prod) % p).astype(np.int32)
+        assert np.array_equal(got[j], want), (path, j)
+
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
 def test_modmatmul_worst_case_values(ctx, rg, torch_dev, path):
     """All residues at the balanced extremes: every digit product and every
     8-term block sits at its bound."""
