@@ -48,9 +48,11 @@
 #include "smith_internal.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <new>
+#include <thread>
 #include <vector>
 
 using namespace rns;
@@ -81,6 +83,25 @@ struct SplitMix {
         return z ^ (z >> 31);
     }
 };
+
+// f(i) for i = 0..count-1 on up to 16 host threads (independent big-integer
+// work items of the lifting path).
+template <typename F>
+void parallel_for(int count, F f) {
+    const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int nt = std::min(count, hw);
+    if (nt <= 1) {
+        for (int i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+            for (int i = next++; i < count; i = next++) f(i);
+        });
+    for (auto &x : th) x.join();
+}
 
 #define DRV_HIP(call)                                                             \
     do {                                                                          \
@@ -721,11 +742,11 @@ struct Driver {
             // inner sum by Horner's rule from the top digit.
             BigInt pnb(1);
             for (int64_t i = 0; i < nb; ++i) pnb = pnb.mul_small(p);
-            for (int e = 0; e < ne; ++e) {
+            parallel_for(ne, [&](int e) {
                 BigInt v(0);
                 for (int64_t i = nb - 1; i >= 0; --i) v = v.mul_small(p) + BigInt(hz[(size_t)i * ne + e]);
                 Y[e] = Y[e] + v * pw;
-            }
+            });
             pw = pw * pnb;
             K_done = K_chk;
             st.lift_steps = (int)K_done;
@@ -739,23 +760,28 @@ struct Driver {
                     W1 = W1 + Y[c].mul_small(w1[c]);
                     W2 = W2 + Y[t + c].mul_small(w2[c]);
                 }
-                BigInt n1, d1, n2, d2;
-                ok = BigInt::rat_recon(mod(W1, pw), pw, n1, d1) && BigInt::rat_recon(mod(W2, pw), pw, n2, d2) &&
-                     d1.mod_small(p) != 0 && d2.mod_small(p) != 0;
-                if (ok) s = BigInt::lcm(d1, d2);
+                BigInt nu[2], de[2];
+                bool rr[2] = {false, false};
+                const BigInt *Wc[2] = {&W1, &W2};
+                parallel_for(2, [&](int i) { rr[i] = BigInt::rat_recon(mod(*Wc[i], pw), pw, nu[i], de[i]); });
+                ok = rr[0] && rr[1] && de[0].mod_small(p) != 0 && de[1].mod_small(p) != 0;
+                if (ok) s = BigInt::lcm(de[0], de[1]);
             }
             // Phase 2: X' = s Y' must be small; an entry that is not shows a
             // factor missing from s (its own denominator is then added).
             const size_t bb = (pw.bit_length() - 2) / 2;
             const BigInt Bnd = BigInt(1).shl(bb);
             for (int pass = 0; ok && pass <= ne; ++pass) {
-                int bad = -1;
-                for (int e = 0; e < ne && bad < 0; ++e) {
+                std::vector<char> big(ne, 0);
+                parallel_for(ne, [&](int e) {
                     BigInt x = mod(s * Y[e], pw);
                     if (BigInt::cmp(x.shl(1), pw) > 0) x = x - pw;
-                    if (BigInt::cmp(BigInt::abs(x), Bnd) >= 0) bad = e;
+                    big[e] = BigInt::cmp(BigInt::abs(x), Bnd) >= 0;
                     X[e] = std::move(x);
-                }
+                });
+                int bad = -1;
+                for (int e = 0; e < ne && bad < 0; ++e)
+                    if (big[e]) bad = e;
                 if (bad < 0) break;
                 BigInt nu, de;
                 if (!BigInt::rat_recon(mod(Y[bad], pw), pw, nu, de) || de.mod_small(p) == 0) {

@@ -21,12 +21,9 @@ struct LocalMod {
     uint64_t pow64w;   // 2^(64W) mod m
 };
 
-// Gauss-Jordan ([A | I], ld = 2n) or forward elimination (A, ld = n) modulo P
-// primes at once; det (optional) accumulates the determinant mod each prime.
+// [A mod p | I] (ld = 2n) or A mod p (ld = n) for P primes at once.
 void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const GjPrime *pr, int P,
                     hipStream_t s);
-void launch_gj_step(uint32_t *M, int64_t n, int64_t ld, int k, const GjPrime *pr, int P,
-                    int32_t *singular, uint32_t *det, hipStream_t s);
 // Blocked elimination of P planes, block at row/column r0 of width
 // bw <= kGjBlock: launch_gj_blockinv inverts the unexchanged pivot block of
 // every plane (need[q] = 1 where that fails); launch_gj_pivoted then handles

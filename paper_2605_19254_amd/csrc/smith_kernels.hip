@@ -1,8 +1,9 @@
 // GPU kernels of the Smith-form driver.
 //
-//   Gauss-Jordan inversion modulo many primes at once ([A | I] -> [I | A^-1]
-//   per prime), used to obtain A^-1 mod q for the residue-number reconstruction
-//   of A^-1 b and s A^-1.
+//   Blocked Gauss-Jordan inversion and forward elimination modulo many primes
+//   at once (pivot blocks, row exchanges; the block updates are residue
+//   products), for A^-1 mod q and det A mod q.
+//   p-adic lifting steps and projections of the lifted digits.
 //   Residues of multiword integers, scaling of residue planes, and an exact
 //   comparison of a residue product with s I (the integrality check).
 //   Elimination over Z/q^e with minimal-valuation pivoting, which gives the
@@ -31,75 +32,6 @@ __device__ __forceinline__ uint32_t powmod_p(uint32_t a, uint32_t e, double pf, 
         e >>= 1;
     }
     return r;
-}
-
-// --------------------------------------------------- Gauss-Jordan mod p --
-// M: [P][n][ld] uint32; plane q uses prime pr[q].  With ld = 2n the planes hold
-// [A | I] and the elimination is Gauss-Jordan (every row i != k), which leaves
-// A^-1 in the right halves; with ld = n they hold A and only rows below the
-// pivot are eliminated (enough for the determinant).
-// Step k: choose the first row r >= k with a nonzero entry in column k, swap
-// it into row k (columns k..ld-1: columns < k of rows >= k are already zero),
-// multiply det[q] by the pivot (negated for a swap), and scale row k so that
-// the pivot is 1.  A prime with no pivot is marked singular.
-__global__ __launch_bounds__(256) void k_gj_pivot(uint32_t *__restrict__ M, int64_t n, int64_t ld,
-                                                  int k, const GjPrime *__restrict__ pr,
-                                                  int32_t *__restrict__ singular,
-                                                  uint32_t *__restrict__ det) {
-    const int q = blockIdx.x;
-    if (singular[q]) return;
-    uint32_t *A = M + (int64_t)q * n * ld;
-    __shared__ int best;
-    if (threadIdx.x == 0) best = (int)n;
-    __syncthreads();
-    for (int64_t r = k + threadIdx.x; r < n; r += blockDim.x)
-        if (A[r * ld + k] != 0) atomicMin(&best, (int)r);
-    __syncthreads();
-    const int r = best;
-    if (r >= n) {
-        if (threadIdx.x == 0) singular[q] = 1;
-        return;
-    }
-    const double pf = pr[q].pf, pinv = pr[q].pinv;
-    if (r != k)
-        for (int64_t j = k + threadIdx.x; j < ld; j += blockDim.x) {
-            const uint32_t t = A[(int64_t)k * ld + j];
-            A[(int64_t)k * ld + j] = A[(int64_t)r * ld + j];
-            A[(int64_t)r * ld + j] = t;
-        }
-    __syncthreads();
-    __shared__ uint32_t inv;
-    if (threadIdx.x == 0) {
-        const uint32_t piv = A[(int64_t)k * ld + k];
-        if (det) {
-            const uint32_t d = mulmod_p(det[q], piv, pf, pinv);
-            det[q] = (r != k && d != 0) ? pr[q].p - d : d;
-        }
-        inv = powmod_p(piv, pr[q].p - 2, pf, pinv);
-    }
-    __syncthreads();
-    for (int64_t j = k + threadIdx.x; j < ld; j += blockDim.x)
-        A[(int64_t)k * ld + j] = mulmod_p(A[(int64_t)k * ld + j], inv, pf, pinv);
-}
-
-// row_i -= M[i][k] * row_k on columns k+1..ld-1 for the rows i = row0 +
-// blockIdx.y (skipping k).  Column k is not written (it is never read again).
-// Grid: x = column chunk, y = row, z = prime.
-__global__ __launch_bounds__(256) void k_gj_elim(uint32_t *__restrict__ M, int64_t n, int64_t ld,
-                                                 int k, int64_t row0, const GjPrime *__restrict__ pr,
-                                                 const int32_t *__restrict__ singular) {
-    const int q = blockIdx.z;
-    const int64_t i = row0 + blockIdx.y;
-    if (singular[q] || i == k) return;
-    uint32_t *A = M + (int64_t)q * n * ld;
-    const uint32_t f = A[i * ld + k];
-    if (f == 0) return;
-    const int64_t j = (int64_t)k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= ld) return;
-    const uint32_t p = pr[q].p;
-    const uint32_t t = mulmod_p(f, A[(int64_t)k * ld + j], pr[q].pf, pr[q].pinv);
-    const uint32_t a = A[i * ld + j];
-    A[i * ld + j] = a >= t ? a - t : a + p - t;
 }
 
 // Loads A (int64) reduced mod each prime into [A mod p | I] (ld = 2n) or
@@ -310,41 +242,57 @@ constexpr int kLiftMaxT = 16;
 // multiple of 4); C and A are zero beyond column n, so every row is read with
 // 16-byte loads and the padding contributes nothing.
 
+// Each wave handles RW consecutive rows, so every load of the right-hand
+// sides (read from L2 by every wave) serves RW rows; the launcher takes RW = 1
+// for small n (more waves to hide memory latency) and up to 4 for large n.
+
 // X[c][r] = sum_k C[r][k] Rm[c][k] mod p.  Each lane sums at most ld/64
-// products below 2^52 (ld <= 65536 keeps that below 2^62), reduces its sum
-// mod p, and the wave adds the 64 reduced sums.
-template <int T>
+// products below 2^52 per row (ld <= 65536 keeps that below 2^62), reduces
+// its sums mod p, and the wave adds the 64 reduced sums.
+template <int T, int kLiftRows>
 __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, int64_t n, int64_t ld,
                                                 const uint32_t *__restrict__ Rm, int t, uint32_t p,
                                                 uint32_t *__restrict__ X) {
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= n) return;                                  // whole waves only
-    const uint4 *Cr = reinterpret_cast<const uint4 *>(C + r * ld);
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
+    if (r0 >= n) return;                                 // whole waves only
     const int64_t q = ld / 4;
-    uint64_t acc[T];
+    const uint4 *Cr[kLiftRows];
 #pragma unroll
-    for (int c = 0; c < T; ++c) acc[c] = 0;
-#pragma unroll 4
+    for (int rr = 0; rr < kLiftRows; ++rr)               // rows past n re-read row r0 and store nothing
+        Cr[rr] = reinterpret_cast<const uint4 *>(C + (r0 + rr < n ? r0 + rr : r0) * ld);
+    uint64_t acc[kLiftRows][T];
+#pragma unroll
+    for (int rr = 0; rr < kLiftRows; ++rr)
+#pragma unroll
+        for (int c = 0; c < T; ++c) acc[rr][c] = 0;
+#pragma unroll 2
     for (int64_t k = lane; k < q; k += 64) {
-        const uint4 cv = Cr[k];
+        uint4 rv[T];
 #pragma unroll
         for (int c = 0; c < T; ++c)
-            if (c < t) {
-                const uint4 rv = reinterpret_cast<const uint4 *>(Rm + (int64_t)c * ld)[k];
-                acc[c] += (uint64_t)cv.x * rv.x + (uint64_t)cv.y * rv.y + (uint64_t)cv.z * rv.z +
-                          (uint64_t)cv.w * rv.w;
-            }
-    }
+            if (c < t) rv[c] = reinterpret_cast<const uint4 *>(Rm + (int64_t)c * ld)[k];
 #pragma unroll
-    for (int c = 0; c < T; ++c) {
-        if (c < t) {
-            uint64_t v = acc[c] % p;
+        for (int rr = 0; rr < kLiftRows; ++rr) {
+            const uint4 cv = Cr[rr][k];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            if (lane == 0) X[(int64_t)c * ld + r] = (uint32_t)(v % p);
+            for (int c = 0; c < T; ++c)
+                if (c < t)
+                    acc[rr][c] += (uint64_t)cv.x * rv[c].x + (uint64_t)cv.y * rv[c].y +
+                                  (uint64_t)cv.z * rv[c].z + (uint64_t)cv.w * rv[c].w;
         }
     }
+#pragma unroll
+    for (int rr = 0; rr < kLiftRows; ++rr)
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+            if (c < t) {
+                uint64_t v = acc[rr][c] % p;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                if (lane == 0 && r0 + rr < n) X[(int64_t)c * ld + r0 + rr] = (uint32_t)(v % p);
+            }
+        }
 }
 
 // R'[c][r] = (R[c][r] - sum_k A[r][k] X[c][k]) / p and Rm'[c][r] = R' mod p.
@@ -352,46 +300,59 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
 // an int64.  A division that is not exact (impossible for a correct C) sets
 // *err instead of producing a wrong residual silently.  X beyond row n is
 // never written; A's zero columns make its value irrelevant.
-template <int T>
+template <int T, int kLiftRows>
 __global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, int64_t n, int64_t ld,
                                                 const uint32_t *__restrict__ X,
                                                 const int64_t *__restrict__ R, int t, uint32_t p,
                                                 int64_t *__restrict__ Rn, uint32_t *__restrict__ Rmn,
                                                 int32_t *__restrict__ err) {
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= n) return;
-    const int4 *Ar = reinterpret_cast<const int4 *>(A + r * ld);
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
+    if (r0 >= n) return;
     const int64_t q = ld / 4;
-    int64_t acc[T];
+    const int4 *Ar[kLiftRows];
 #pragma unroll
-    for (int c = 0; c < T; ++c) acc[c] = 0;
-#pragma unroll 4
+    for (int rr = 0; rr < kLiftRows; ++rr)
+        Ar[rr] = reinterpret_cast<const int4 *>(A + (r0 + rr < n ? r0 + rr : r0) * ld);
+    int64_t acc[kLiftRows][T];
+#pragma unroll
+    for (int rr = 0; rr < kLiftRows; ++rr)
+#pragma unroll
+        for (int c = 0; c < T; ++c) acc[rr][c] = 0;
+#pragma unroll 2
     for (int64_t k = lane; k < q; k += 64) {
-        const int4 av = Ar[k];
+        uint4 xv[T];
 #pragma unroll
         for (int c = 0; c < T; ++c)
-            if (c < t) {
-                const uint4 xv = reinterpret_cast<const uint4 *>(X + (int64_t)c * ld)[k];
-                acc[c] += (int64_t)av.x * xv.x + (int64_t)av.y * xv.y + (int64_t)av.z * xv.z +
-                          (int64_t)av.w * xv.w;
-            }
-    }
+            if (c < t) xv[c] = reinterpret_cast<const uint4 *>(X + (int64_t)c * ld)[k];
 #pragma unroll
-    for (int c = 0; c < T; ++c) {
-        if (c >= t) continue;
-        int64_t v = acc[c];
+        for (int rr = 0; rr < kLiftRows; ++rr) {
+            const int4 av = Ar[rr][k];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) {
-            const int64_t num = R[(int64_t)c * ld + r] - v;
-            const int64_t qq = num / (int64_t)p;
-            if (qq * (int64_t)p != num) atomicOr(err, 1);
-            Rn[(int64_t)c * ld + r] = qq;
-            const int64_t m = qq % (int64_t)p;
-            Rmn[(int64_t)c * ld + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+            for (int c = 0; c < T; ++c)
+                if (c < t)
+                    acc[rr][c] += (int64_t)av.x * xv[c].x + (int64_t)av.y * xv[c].y + (int64_t)av.z * xv[c].z +
+                                  (int64_t)av.w * xv[c].w;
         }
     }
+#pragma unroll
+    for (int rr = 0; rr < kLiftRows; ++rr)
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+            if (c >= t) continue;
+            int64_t v = acc[rr][c];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            const int64_t r = r0 + rr;
+            if (lane == 0 && r < n) {
+                const int64_t num = R[(int64_t)c * ld + r] - v;
+                const int64_t qq = num / (int64_t)p;
+                if (qq * (int64_t)p != num) atomicOr(err, 1);
+                Rn[(int64_t)c * ld + r] = qq;
+                const int64_t m = qq % (int64_t)p;
+                Rmn[(int64_t)c * ld + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+            }
+        }
 }
 
 // Projections of stored digits: Z[i][a][c] = sum_r Rp[a][r] Xh[i][c][r] for
@@ -640,33 +601,31 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
     hipLaunchKernelGGL(k_gj_load, grid, dim3(256), 0, s, A, n, ld, M, pr);
 }
 
-void launch_gj_step(uint32_t *M, int64_t n, int64_t ld, int k, const GjPrime *pr, int P,
-                    int32_t *singular, uint32_t *det, hipStream_t s) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)P), dim3(256), 0, s, M, n, ld, k, pr, singular, det);
-    const int64_t cols = ld - k - 1;
-    const bool full = ld == 2 * n;                      // Gauss-Jordan: every row; else below k
-    const int64_t row0 = full ? 0 : k + 1;
-    const int64_t rows = n - row0;
-    if (cols <= 0 || rows <= 0) return;
-    dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows, (unsigned)P);
-    hipLaunchKernelGGL(k_gj_elim, grid, dim3(256), 0, s, M, n, ld, k, row0, pr, singular);
-}
-
-template <int T>
+template <int T, int RW>
 static void lift_step_t(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
                         const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                         int32_t *err, hipStream_t s) {
-    const unsigned blocks = (unsigned)((n + 3) / 4);
-    hipLaunchKernelGGL(k_lift_x<T>, dim3(blocks), dim3(256), 0, s, C, n, ld, Rm, t, p, X);
-    hipLaunchKernelGGL(k_lift_r<T>, dim3(blocks), dim3(256), 0, s, A, n, ld, X, R, t, p, Rn, Rmn, err);
+    const unsigned blocks = (unsigned)((n + 4 * RW - 1) / (4 * RW));
+    hipLaunchKernelGGL((k_lift_x<T, RW>), dim3(blocks), dim3(256), 0, s, C, n, ld, Rm, t, p, X);
+    hipLaunchKernelGGL((k_lift_r<T, RW>), dim3(blocks), dim3(256), 0, s, A, n, ld, X, R, t, p, Rn, Rmn, err);
+}
+
+template <int T>
+static void lift_step_rw(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
+                         const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
+                         int32_t *err, hipStream_t s) {
+    // About 2048 waves or more: 8 per CU.
+    if (n >= 4 * 2048) lift_step_t<T, 4>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else if (n >= 2 * 2048) lift_step_t<T, 2>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else lift_step_t<T, 1>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
 }
 
 void launch_lift_step(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
                       const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                       int32_t *err, hipStream_t s) {
-    if (t <= 4) lift_step_t<4>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else if (t <= 8) lift_step_t<8>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else lift_step_t<kLiftMaxT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    if (t <= 4) lift_step_rw<4>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else if (t <= 8) lift_step_rw<8>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else lift_step_rw<kLiftMaxT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
 }
 
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,
