@@ -32,6 +32,7 @@ using namespace rns;
 namespace {
 
 constexpr int kBlock = 128;
+constexpr int kLagEntries = 4;
 
 struct PC2 {
     double pf, pinv;
@@ -184,7 +185,85 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
     }
 }
 
+// One entry of the Lagrange form: column c_lane of a row whose residues start
+// at res_row (planes ps apart) and whose output words start at out_row.  The
+// job's fields come in as values, which keeps them uniform (scalar) after
+// inlining.
 template <int WT>
+__device__ __forceinline__ void lagrange_entry(const uint32_t *res_row, uint64_t *out_row, int64_t cols,
+                                               int64_t ps, int L, const PrimeConst *pc_job,
+                                               const double *lag_c, const uint64_t *lag_mj,
+                                               const uint64_t *lag_m, int W, int64_t c_lane) {
+    // Lanes past the last column work on the last column and store nothing,
+    // so control flow stays uniform (uniform loads stay scalar).
+    const bool valid = c_lane < cols;
+    const int64_t c = valid ? c_lane : cols - 1;
+    const auto src = gptr(res_row + c);
+    const auto pc = cptr(pc_job);
+    const auto cinv = cptr(lag_c);
+    const auto mj = cptr(lag_mj);
+    const auto mw = cptr(lag_m);
+    uint64_t x[WT];
+#pragma unroll
+    for (int k = 0; k < WT; ++k) x[k] = 0;
+    double alpha = 0.0;
+    for (int j0 = 0; j0 < L; j0 += 8) {
+        uint32_t r[8];                        // eight loads in flight at a time
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = src[(int64_t)min(j0 + q, L - 1) * ps];   // in bounds
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = j0 + q;
+            if (j >= L) break;
+            const PC2 P{pc[j].pf, pc[j].pinv};
+            double y = modp((double)r[q] * cinv[j], P);
+            y = y < 0.0 ? y + P.pf : y;
+            alpha = fma(y, P.pinv, alpha);
+            const uint64_t yi = (uint64_t)y;
+            const auto m = mj + (int64_t)j * W;
+            uint64_t carry = 0;
+#pragma unroll
+            for (int k = 0; k < WT; ++k) {
+                if (k < W) {
+                    const uint64_t lo = m[k] * yi;
+                    const uint64_t hi = __umul64hi(m[k], yi);
+                    const uint64_t s1 = lo + carry;
+                    const uint64_t c1 = s1 < lo ? 1 : 0;
+                    const uint64_t s2 = x[k] + s1;
+                    const uint64_t c2 = s2 < x[k] ? 1 : 0;
+                    x[k] = s2;
+                    carry = hi + c1 + c2;
+                }
+            }
+        }
+    }
+    const uint64_t a = (uint64_t)rint(alpha);
+    uint64_t borrow = 0;
+    uint64_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+        if (k < W) {
+            const uint64_t lo = mw[k] * a;
+            const uint64_t hi = __umul64hi(mw[k], a);
+            const uint64_t s1 = lo + carry;
+            carry = hi + (s1 < lo ? 1 : 0);
+            const uint64_t d1 = x[k] - s1;
+            const uint64_t b1 = x[k] < s1 ? 1 : 0;
+            const uint64_t d2 = d1 - borrow;
+            const uint64_t b2 = d1 < borrow ? 1 : 0;
+            x[k] = d2;
+            borrow = b1 + b2;
+        }
+    }
+    if (!valid) return;
+    const auto dst = gptr_w(out_row + c * W);
+#pragma unroll
+    for (int k = 0; k < WT; ++k)
+        if (k < W) dst[k] = x[k];
+}
+
+// E entries per thread: a tile covers E * kBlock columns of one row.
+template <int WT, int E>
 __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJob *__restrict__ jobs,
                                                         int njobs, int64_t total_tiles,
                                                         const PrimeConst *__restrict__ pc_all, int W,
@@ -203,75 +282,13 @@ __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJ
         const CrtJob J = njobs > 0 ? jobs[qj] : job0;
         const int64_t u = t - J.tile_begin;
         const int64_t i = u / J.col_tiles;
-        // Lanes past the last column work on the last column and store
-        // nothing, so control flow stays uniform (uniform loads stay scalar).
-        const int64_t c_lane = (u - i * J.col_tiles) * kBlock + threadIdx.x;
-        const bool valid = c_lane < J.cols;
-        const int64_t c = valid ? c_lane : J.cols - 1;
-        const auto src = gptr(J.res + i * J.ldr + c);
-        const auto pc = cptr(pc_all + J.prime_begin);
-        const auto cinv = cptr(J.lag_c);
-        const auto mj = cptr(J.lag_mj);
-        const auto mw = cptr(J.lag_m);
-        const int L = J.L;
-        const int64_t ps = J.ps;
-        uint64_t x[WT];
+        const int64_t base = (u - i * J.col_tiles) * kBlock * E + threadIdx.x;
+        const uint32_t *res_row = J.res + i * J.ldr;
+        uint64_t *out_row = J.out + i * J.ldo * W;
 #pragma unroll
-        for (int k = 0; k < WT; ++k) x[k] = 0;
-        double alpha = 0.0;
-        for (int j0 = 0; j0 < L; j0 += 8) {
-            uint32_t r[8];                        // eight loads in flight at a time
-#pragma unroll
-            for (int q = 0; q < 8; ++q) r[q] = src[(int64_t)min(j0 + q, L - 1) * ps];   // in bounds
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int j = j0 + q;
-                if (j >= L) break;
-                const PC2 P{pc[j].pf, pc[j].pinv};
-                double y = modp((double)r[q] * cinv[j], P);
-                y = y < 0.0 ? y + P.pf : y;
-                alpha = fma(y, P.pinv, alpha);
-                const uint64_t yi = (uint64_t)y;
-                const auto m = mj + (int64_t)j * W;
-                uint64_t carry = 0;
-#pragma unroll
-                for (int k = 0; k < WT; ++k) {
-                    if (k < W) {
-                        const uint64_t lo = m[k] * yi;
-                        const uint64_t hi = __umul64hi(m[k], yi);
-                        const uint64_t s1 = lo + carry;
-                        const uint64_t c1 = s1 < lo ? 1 : 0;
-                        const uint64_t s2 = x[k] + s1;
-                        const uint64_t c2 = s2 < x[k] ? 1 : 0;
-                        x[k] = s2;
-                        carry = hi + c1 + c2;
-                    }
-                }
-            }
-        }
-        const uint64_t a = (uint64_t)rint(alpha);
-        uint64_t borrow = 0;
-        uint64_t carry = 0;
-#pragma unroll
-        for (int k = 0; k < WT; ++k) {
-            if (k < W) {
-                const uint64_t lo = mw[k] * a;
-                const uint64_t hi = __umul64hi(mw[k], a);
-                const uint64_t s1 = lo + carry;
-                carry = hi + (s1 < lo ? 1 : 0);
-                const uint64_t d1 = x[k] - s1;
-                const uint64_t b1 = x[k] < s1 ? 1 : 0;
-                const uint64_t d2 = d1 - borrow;
-                const uint64_t b2 = d1 < borrow ? 1 : 0;
-                x[k] = d2;
-                borrow = b1 + b2;
-            }
-        }
-        if (!valid) continue;
-        const auto dst = gptr_w(J.out + (i * J.ldo + c) * W);
-#pragma unroll
-        for (int k = 0; k < WT; ++k)
-            if (k < W) dst[k] = x[k];
+        for (int e = 0; e < E; ++e)
+            lagrange_entry<WT>(res_row, out_row, J.cols, J.ps, J.L, pc_all + J.prime_begin, J.lag_c, J.lag_mj,
+                               J.lag_m, W, base + e * kBlock);
       }
     }
 }
@@ -331,8 +348,12 @@ Limbs limbs_shr(const Limbs &a, int bits, bool round_up) {
 
 namespace rns {
 
-int64_t crt_col_tiles(int64_t cols) { return (cols + kBlock - 1) / kBlock; }
-int64_t crt_tiles(int64_t rows, int64_t cols) { return rows * crt_col_tiles(cols); }
+// Entries per thread: 4 for the Lagrange form with at most two output words
+// and at most 4 primes (little work per entry, so a tile's job lookup is
+// shared by more entries), otherwise 1 (more threads in flight).
+int crt_entries(bool fast, int W, int L) { return fast && W <= 2 && L <= 4 ? kLagEntries : 1; }
+int64_t crt_col_tiles(int64_t cols, int entries) { return (cols + kBlock * entries - 1) / (kBlock * entries); }
+int64_t crt_tiles(int64_t rows, int64_t cols, int entries) { return rows * crt_col_tiles(cols, entries); }
 
 bool crt_fast_ok(const rns_ctx *ctx, int begin, int L, const uint64_t *bound_words, int Wb, int W) {
     if (!bound_words || Wb <= 0) return false;
@@ -349,19 +370,21 @@ bool crt_fast_ok(const rns_ctx *ctx, int begin, int L, const uint64_t *bound_wor
     return limbs_cmp(D, T) >= 0;
 }
 
-void launch_crt(bool fast, int W, const CrtJob &job0, const CrtJob *jobs, int njobs,
+void launch_crt(bool fast, int W, int E, const CrtJob &job0, const CrtJob *jobs, int njobs,
                 int64_t total_tiles, const PrimeConst *pc, const double *garner, hipStream_t s) {
     const int chunk = njobs > 1 ? kChunk : 1;
     const unsigned grid = (unsigned)std::min<int64_t>((total_tiles + chunk - 1) / chunk, 1 << 20);
     if (fast) {
-#define RNS_LAG(WT_) \
-    hipLaunchKernelGGL(k_crt_lagrange<WT_>, dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, W, chunk)
-        if (W <= 1) RNS_LAG(1);
-        else if (W <= 2) RNS_LAG(2);
-        else if (W <= 4) RNS_LAG(4);
-        else if (W <= 8) RNS_LAG(8);
-        else if (W <= 16) RNS_LAG(16);
-        else RNS_LAG(32);
+#define RNS_LAG(WT_, E_) \
+    hipLaunchKernelGGL((k_crt_lagrange<WT_, E_>), dim3(grid), dim3(kBlock), 0, s, job0, jobs, njobs, total_tiles, pc, W, chunk)
+        if (W <= 1 && E > 1) RNS_LAG(1, kLagEntries);
+        else if (W <= 1) RNS_LAG(1, 1);
+        else if (W <= 2 && E > 1) RNS_LAG(2, kLagEntries);
+        else if (W <= 2) RNS_LAG(2, 1);
+        else if (W <= 4) RNS_LAG(4, 1);
+        else if (W <= 8) RNS_LAG(8, 1);
+        else if (W <= 16) RNS_LAG(16, 1);
+        else RNS_LAG(32, 1);
 #undef RNS_LAG
     } else {
 #define RNS_GAR(WT_) \
@@ -396,9 +419,10 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
     j.res = res; j.rows = rows; j.cols = cols; j.ldr = ldr; j.ps = plane_stride;
     j.prime_begin = prime_begin; j.L = L; j.out = out; j.ldo = ldo;
     j.status = d_status ? d_status : ctx->d_status;
-    j.col_tiles = crt_col_tiles(cols);
     j.tile_begin = 0;
     const bool fast = crt_fast_ok(ctx, prime_begin, L, bound_words, Wb, W);
+    const int E = crt_entries(fast, W, L);
+    j.col_tiles = crt_col_tiles(cols, E);
     if (fast) {
         const LagrangeTable *lt = nullptr;
         int st = lagrange_table(ctx, prime_begin, L, W, &lt);
@@ -409,7 +433,7 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
         if (st != RNS_OK) return st;
     }
     ProfScope ps(ctx, fast ? "k_crt_lagrange" : "k_crt_garner", s);
-    launch_crt(fast, W, j, nullptr, 0, crt_tiles(rows, cols), ctx->d_prime, ctx->d_garner, s);
+    launch_crt(fast, W, E, j, nullptr, 0, crt_tiles(rows, cols, E), ctx->d_prime, ctx->d_garner, s);
     RNS_HIP(hipGetLastError());
     return RNS_OK;
 }

@@ -12,6 +12,7 @@ using namespace rns;
 struct rns_matmul_plan {
     rns_ctx *ctx = nullptr;
     int W = 1;
+    int crt_E = 1;              // CRT entries per thread (the same for every job)
     bool fast_crt = false;
     void *d_planes = nullptr;
     ReduceJob *d_rjobs = nullptr;
@@ -43,6 +44,7 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
     std::vector<size_t> offA(count), offB(count), offC(count);
     size_t off = 0;
     bool all_fast = count > 0;
+    int max_L = 1;
     for (int i = 0; i < count; ++i) {
         const rns_matmul_desc &x = d[i];
         if (x.m < 0 || x.n < 0 || x.k < 0) return RNS_EINVAL;
@@ -61,12 +63,14 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
         offB[i] = take(x.k, x.n);
         offC[i] = take(x.m, x.n);
         if (!(x.bound > 0 && crt_fast_ok(ctx, x.prime_begin, x.L, &x.bound, 1, W))) all_fast = false;
+        max_L = std::max(max_L, x.L);
     }
     rns_matmul_plan *p = new (std::nothrow) rns_matmul_plan;
     if (!p) return RNS_ENOMEM;
     p->ctx = ctx;
     p->W = W;
     p->fast_crt = all_fast;
+    p->crt_E = crt_entries(all_fast, W, max_L);
     auto fail = [&](int s) { rns_matmul_plan_destroy(p); return s; };
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(RNS_EDEVICE);
     if (hipMalloc(&p->d_planes, std::max<size_t>(off, 256)) != hipSuccess) return fail(RNS_ENOMEM);
@@ -82,13 +86,18 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
         uint32_t *A = reinterpret_cast<uint32_t *>(base + offA[i]);
         uint32_t *B = reinterpret_cast<uint32_t *>(base + offB[i]);
         uint32_t *C = reinterpret_cast<uint32_t *>(base + offC[i]);
+        // A contiguous matrix is one row of rows*cols entries for the reduce
+        // and CRT jobs, so that small problems fill whole tiles.
+        auto reduce_job = [&](const int64_t *src, int64_t rows, int64_t cols, int64_t ld, uint32_t *dst) {
+            const bool flat = ld == cols;
+            ReduceJob j = make_reduce_job(src, flat ? 1 : rows, flat ? rows * cols : cols, flat ? rows * cols : ld,
+                                          x.prime_begin, x.L, dst, flat ? rows * cols : cols, rows * cols, rt);
+            rt += reduce_tiles(j);
+            rj.push_back(j);
+        };
         if (x.k > 0) {
-            ReduceJob a = make_reduce_job(x.A, x.m, x.k, x.lda, x.prime_begin, x.L, A, x.k, x.m * x.k, rt);
-            rt += reduce_tiles(a);
-            rj.push_back(a);
-            ReduceJob b = make_reduce_job(x.B, x.k, x.n, x.ldb, x.prime_begin, x.L, B, x.n, x.k * x.n, rt);
-            rt += reduce_tiles(b);
-            rj.push_back(b);
+            reduce_job(x.A, x.m, x.k, x.lda, A);
+            reduce_job(x.B, x.k, x.n, x.ldb, B);
         }
         rns_gemm_desc g{};
         g.m = x.m; g.n = x.n; g.k = x.k;
@@ -98,12 +107,15 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
         g.prime_begin = x.prime_begin; g.L = x.L;
         gd.push_back(g);
         CrtJob c{};
-        c.res = C; c.rows = x.m; c.cols = x.n; c.ldr = x.n; c.ps = x.m * x.n;
-        c.prime_begin = x.prime_begin; c.L = x.L; c.out = x.C; c.ldo = x.ldc;
+        const bool cflat = x.ldc == x.n;
+        c.res = C; c.rows = cflat ? 1 : x.m; c.cols = cflat ? x.m * x.n : x.n;
+        c.ldr = c.cols; c.ps = x.m * x.n;
+        c.prime_begin = x.prime_begin; c.L = x.L; c.out = x.C; c.ldo = cflat ? c.cols : x.ldc;
         c.status = ctx->d_status;
-        c.col_tiles = crt_col_tiles(x.n);
+        const int E = p->crt_E;
+        c.col_tiles = crt_col_tiles(c.cols, E);
         c.tile_begin = ct;
-        ct += crt_tiles(x.m, x.n);
+        ct += crt_tiles(c.rows, c.cols, E);
         {
             std::lock_guard<std::mutex> guard(ctx->mu);
             if (all_fast) {
@@ -152,7 +164,7 @@ extern "C" int rns_matmul_plan_execute(rns_matmul_plan *p, void *stream) {
     if (st != RNS_OK) return st;
     if (p->nc) {
         ProfScope ps(ctx, p->fast_crt ? "k_crt_lagrange" : "k_crt_garner", s);
-        launch_crt(p->fast_crt, p->W, CrtJob{}, p->d_cjobs, p->nc, p->ctiles, ctx->d_prime,
+        launch_crt(p->fast_crt, p->W, p->crt_E, CrtJob{}, p->d_cjobs, p->nc, p->ctiles, ctx->d_prime,
                    ctx->d_garner, s);
     }
     RNS_HIP(hipGetLastError());

@@ -20,13 +20,33 @@ using namespace rns;
 
 namespace {
 
-constexpr int kTile = 256;
+typedef long long v2ll __attribute__((ext_vector_type(2)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 256;                // threads per block
+constexpr int kPer = 4;                   // consecutive entries per thread
+constexpr int kTileCols = kTile * kPer;   // columns of one tile
 
 // With a job table, each block takes runs of `chunk` consecutive tiles (tile =
-// up to 256 entries of one row of one job); the job of the first tile is found
-// by binary search and later tiles advance the job index linearly.  A single
-// job uses runs of one tile.
+// up to 1024 entries of one row of one job); the job of the first tile is
+// found by binary search and later tiles advance the job index linearly.  A
+// single job uses runs of one tile.  Each thread reduces 4 consecutive entries,
+// with 16-byte loads and stores when the job's layout allows; control flow is
+// uniform except at the end of a row, so the prime constants come through
+// scalar loads.
 constexpr int kChunk = 8;
+
+struct RedConst {
+    double pf, pinv, c21, c42;
+};
+
+__device__ __forceinline__ uint32_t reduce_one(double a2, double a1, double a0, const RedConst &P) {
+    const double s = fma(a2, P.c42, fma(a1, P.c21, a0));
+    const double q2 = rint(s * P.pinv);
+    double r = fma(-q2, P.pf, s);
+    r = r < 0.0 ? r + P.pf : r;
+    return (uint32_t)r;
+}
 
 __global__ __launch_bounds__(kTile) void k_reduce(ReduceJob job0, const ReduceJob *__restrict__ jobs,
                                                   int njobs, int64_t total_tiles,
@@ -51,21 +71,40 @@ __global__ __launch_bounds__(kTile) void k_reduce(ReduceJob job0, const ReduceJo
             const ReduceJob J = njobs > 0 ? jobs[q] : job0;
             const int64_t u = t - J.tile_begin;
             const int64_t i = u / J.col_tiles;
-            const int64_t c = (u - i * J.col_tiles) * kTile + threadIdx.x;
-            if (c >= J.cols) continue;
-            const int64_t v = *gptr(J.x + i * J.ldx + c);
-            const double a0 = (double)(int32_t)(v & 0x1FFFFF);
-            const double a1 = (double)(int32_t)((v >> 21) & 0x1FFFFF);
-            const double a2 = (double)(int32_t)(v >> 42);
-            const auto dst = gptr_w(J.res + i * J.ldr + c);
-            const auto pc = gptr(pc_all + J.prime_begin);
+            const int64_t c0 = (u - i * J.col_tiles) * kTileCols + kPer * threadIdx.x;
+            const bool vec = J.vec && c0 + kPer <= J.cols;
+            const auto src = gptr(J.x + i * J.ldx + c0);
+            int64_t v[kPer];
+            if (vec) {
+                const auto s2 = reinterpret_cast<const __attribute__((address_space(1))) v2ll *>(src);
+                const v2ll x01 = s2[0], x23 = s2[1];
+                v[0] = x01.x; v[1] = x01.y; v[2] = x23.x; v[3] = x23.y;
+            } else {
+#pragma unroll
+                for (int e = 0; e < kPer; ++e) v[e] = c0 + e < J.cols ? src[e] : 0;
+            }
+            double a0[kPer], a1[kPer], a2[kPer];
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+                a0[e] = (double)(int32_t)(v[e] & 0x1FFFFF);
+                a1[e] = (double)(int32_t)((v[e] >> 21) & 0x1FFFFF);
+                a2[e] = (double)(int32_t)(v[e] >> 42);
+            }
+            const auto dst = gptr_w(J.res + i * J.ldr + c0);
+            const auto pc = cptr(pc_all + J.prime_begin);
             for (int j = 0; j < J.L; ++j) {
-                const auto &P = pc[j];
-                const double s = fma(a2, P.c42, fma(a1, P.c21, a0));
-                const double q2 = rint(s * P.pinv);
-                double r = fma(-q2, P.pf, s);
-                r = r < 0.0 ? r + P.pf : r;
-                dst[(int64_t)j * J.ps] = (uint32_t)r;
+                const RedConst P{pc[j].pf, pc[j].pinv, pc[j].c21, pc[j].c42};
+                uint32_t r[kPer];
+#pragma unroll
+                for (int e = 0; e < kPer; ++e) r[e] = reduce_one(a2[e], a1[e], a0[e], P);
+                const auto d = dst + (int64_t)j * J.ps;
+                if (vec) {
+                    *reinterpret_cast<__attribute__((address_space(1))) v4u *>(d) = v4u{r[0], r[1], r[2], r[3]};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < kPer; ++e)
+                        if (c0 + e < J.cols) d[e] = r[e];
+                }
             }
         }
     }
@@ -92,7 +131,11 @@ ReduceJob make_reduce_job(const int64_t *x, int64_t rows, int64_t cols, int64_t 
     j.x = x; j.rows = rows; j.cols = cols; j.ldx = ldx;
     j.res = res; j.ldr = ldr; j.ps = plane_stride;
     j.prime_begin = prime_begin; j.L = L;
-    j.col_tiles = (cols + kTile - 1) / kTile;
+    // 4-entry vectors from a column that is a multiple of 4: 16-byte aligned
+    // when the bases are and the strides are even (x) or multiples of 4 (res).
+    j.vec = ((uintptr_t)x % 16 == 0) && ldx % 2 == 0 && ((uintptr_t)res % 16 == 0) && ldr % 4 == 0 &&
+            (L <= 1 || plane_stride % 4 == 0);
+    j.col_tiles = (cols + kTileCols - 1) / kTileCols;
     j.tile_begin = tile_begin;
     return j;
 }

@@ -13,6 +13,7 @@ struct ReduceJob {
     uint32_t *res;
     int64_t ldr, ps;
     int32_t prime_begin, L;
+    int32_t vec;             // rows and planes allow 16-byte accesses of 4 entries
     int64_t col_tiles;
     int64_t tile_begin;      // prefix over jobs of rows * col_tiles
 };
@@ -44,9 +45,12 @@ void launch_reduce(const ReduceJob &job0, const ReduceJob *jobs, int njobs, int6
                    const PrimeConst *pc, hipStream_t s);
 
 // CRT: `fast` selects the Lagrange form (every job must have its tables).
-int64_t crt_tiles(int64_t rows, int64_t cols);
-int64_t crt_col_tiles(int64_t cols);
-void launch_crt(bool fast, int W, const CrtJob &job0, const CrtJob *jobs, int njobs,
+// A tile covers crt_entries(fast, W, L) x 128 columns of one row; the same
+// count goes to launch_crt.
+int crt_entries(bool fast, int W, int L);
+int64_t crt_tiles(int64_t rows, int64_t cols, int entries);
+int64_t crt_col_tiles(int64_t cols, int entries);
+void launch_crt(bool fast, int W, int E, const CrtJob &job0, const CrtJob *jobs, int njobs,
                 int64_t total_tiles, const PrimeConst *pc, const double *garner, hipStream_t s);
 // Whether a promise |x| <= B (words) lets the Lagrange form be exact for the
 // primes range, and fits W output words.
