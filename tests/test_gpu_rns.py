@@ -56,6 +56,18 @@ def _res(rng, ps, rows, cols, edge=False):
     return out.astype(np.int32)
 
 
+def _modmatmul(ctx, rg, probs, path):
+    """modmatmul_batched on a path, or a plan with a forced INT8 kernel
+    variant for paths named int8-v<variant>."""
+    if path.startswith("int8-v"):
+        plan = rg.GemmPlan(ctx, probs, path="int8")
+        plan.set_variant(int(path[len("int8-v"):]))
+        plan.execute()
+        plan.close()
+    else:
+        rg.modmatmul_batched(ctx, probs, path=path)
+
+
 # ------------------------------------------------------------------ reduce --
 
 @pytest.mark.parametrize("rows,cols,begin,L", [(1, 1, 0, 1), (3, 300, 0, 24), (257, 129, 2, 24),
@@ -104,8 +116,7 @@ def test_modmatmul_matches_oracle(ctx, rg, torch_dev, path, m, n, k):
     a = _res(rng, ps, m, k, edge=True)
     b = _res(rng, ps, k, n, edge=True)
     c = torch.full((L, m, n), -1, dtype=torch.int32, device=dev)
-    rg.modmatmul_batched(ctx, [rg.GemmProblem(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev),
-                                              c, begin)], path=path)
+    _modmatmul(ctx, rg, [rg.GemmProblem(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), c, begin)], path)
     got = c.cpu().numpy()
     for j, p in enumerate(ps):
         want = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int32)
@@ -127,7 +138,7 @@ def test_modmatmul_subtract(ctx, rg, torch_dev, path, m, n, k):
     c = torch.from_numpy(c0.copy()).to(dev)
     ta = torch.from_numpy(a).to(dev) if k else torch.empty((L, m, 0), dtype=torch.int32, device=dev)
     tb = torch.from_numpy(b).to(dev) if k else torch.empty((L, 0, n), dtype=torch.int32, device=dev)
-    rg.modmatmul_batched(ctx, [rg.GemmProblem(ta, tb, c, begin, subtract=True)], path=path)
+    _modmatmul(ctx, rg, [rg.GemmProblem(ta, tb, c, begin, subtract=True)], path)
     got = c.cpu().numpy()
     for j, p in enumerate(ps):
         prod = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int64) if k else 0
@@ -153,13 +164,51 @@ def test_modmatmul_worst_case_values(ctx, rg, torch_dev, path):
     c = torch.empty((L, m, n), dtype=torch.int32, device=dev)
     pb = [0, 1, 23]
     for j in range(L):
-        rg.modmatmul_batched(ctx, [rg.GemmProblem(torch.from_numpy(a[j:j + 1]).to(dev),
-                                                  torch.from_numpy(b[j:j + 1]).to(dev),
-                                                  c[j:j + 1], pb[j])], path=path)
+        _modmatmul(ctx, rg, [rg.GemmProblem(torch.from_numpy(a[j:j + 1]).to(dev),
+                                            torch.from_numpy(b[j:j + 1]).to(dev),
+                                            c[j:j + 1], pb[j])], path)
     got = c.cpu().numpy()
     for j, p in enumerate(ps):
         want = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int32)
         assert np.array_equal(got[j], want)
+
+
+def _digit_extremes(p):
+    """Residues mod p whose balanced base-256 digits sit at their bounds, and
+    the residue whose three low digits are all -128 (top digit as large as the
+    balanced range allows)."""
+    vals = []
+    for d in (-128, 127):
+        v = d * (1 + 256 + 256 * 256)
+        top = ((p - 1) // 2 - abs(v)) // 256 ** 3
+        w = v + top * 256 ** 3 if v > 0 else v - top * 256 ** 3
+        vals += [v, w]
+    low = (-128 * (1 + 256 + 256 * 256)) % p
+    return np.array(sorted({v % p for v in vals}), dtype=np.int64), low
+
+
+@pytest.mark.parametrize("variant", [None, 0, 3])
+def test_modmatmul_digit_extremes_at_max_k(ctx, rg, torch_dev, variant):
+    """k at the INT8 path's exactness bound, 90% of the entries the residue
+    whose low digits are all -128 (every product term of shift group 2 then
+    has the same sign): that group's int32 sum reaches 43690 * 3 * 2^14,
+    within 2^15 of 2^31; the other entries are drawn from the other extremal
+    residues."""
+    torch, dev = torch_dev
+    path = "int8" if variant is None else "int8-v%d" % variant
+    _say("modmatmul digit extremes, k = max", path)
+    k = 43690
+    m, n = 40, 70
+    begin = 9
+    p = PRIMES[begin]
+    ext, low = _digit_extremes(p)
+    rng = np.random.default_rng(17)
+    a = np.where(rng.random((1, m, k)) < 0.9, low, rng.choice(ext, size=(1, m, k))).astype(np.int32)
+    b = np.where(rng.random((1, k, n)) < 0.9, low, rng.choice(ext, size=(1, k, n))).astype(np.int32)
+    c = torch.empty((1, m, n), dtype=torch.int32, device=dev)
+    _modmatmul(ctx, rg, [rg.GemmProblem(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), c, begin)], path)
+    want = native.modmatmul(a[0].astype(np.uint32), b[0].astype(np.uint32), p).astype(np.int32)
+    assert np.array_equal(c.cpu().numpy()[0], want)
 
 
 def test_modmatmul_batch_equals_single_and_paths_agree(ctx, rg, torch_dev):
@@ -300,12 +349,7 @@ def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
     ra = rg.rns_reduce(ctx, ta, L=L)
     rb = rg.rns_reduce(ctx, tb, L=L)
     rc = torch.empty((L, n, n), dtype=torch.int32, device=dev)
-    if path.startswith("int8-v"):
-        plan = rg.GemmPlan(ctx, [rg.GemmProblem(ra, rb, rc)], path="int8")
-        plan.set_variant(int(path[len("int8-v"):]))
-        plan.execute()
-    else:
-        rg.modmatmul_batched(ctx, [rg.GemmProblem(ra, rb, rc)], path=path)
+    _modmatmul(ctx, rg, [rg.GemmProblem(ra, rb, rc)], path)
     out = rg.crt_reconstruct(ctx, rc, L=L, W=1, bound=n << 40)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
