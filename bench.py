@@ -86,6 +86,8 @@ def parse():
                     help="also time the batched workload with this many uneven products (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--smith", type=int, default=1, help="time the Smith-form workloads (0 = skip)")
+    ap.add_argument("--stress", type=int, default=1,
+                    help="time the full-range residue product with 10-word CRT (0 = skip)")
     ap.add_argument("--serving", type=int, default=60,
                     help="requests per open-loop serving point (0 = skip)")
     ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving"],
@@ -222,6 +224,16 @@ def run_smith(rg, reps=10):
                            "ms_per_solve": 1000 * t, "stats": res.stats,
                            "cpu_baseline": {"value": 1.0 / to, "unit": "solves/s", "cores": 1, "kind": "oracle",
                                             "sample": "the same matrix"}}
+        # the same solve with every residue product on the FP64 MFMA path
+        with rg.Context(device=0, L=24, path="fp64") as c64:
+            rg.smith_form(c64, a)
+            t0 = time.perf_counter()
+            for r in range(reps):
+                res64 = rg.smith_form(c64, a, seed=r)
+            t64 = (time.perf_counter() - t0) / reps
+        if res64.s != want:
+            raise SystemExit("bench.py: Smith form (64x64, FP64 products) differs from the oracle")
+        out["small_64"]["fp64_path"] = {"solves_per_s": 1.0 / t64, "ms_per_solve": 1000 * t64}
         pl = synth.planted_smith(2000, seed=0)
         t0 = time.perf_counter()
         res = rg.smith_form(ctx, pl.a, seed=0)
@@ -273,9 +285,70 @@ def _serving_stream(count, rate, seed, tail):
     return reqs
 
 
-def run_serving(rg, count):
-    """Closed-loop capacity, then open-loop Poisson arrivals at 0.5x and 1.0x
-    of it (the 1.0x point with the n = 10007 tail at its 50th arrival);
+def run_stress(rg, torch, dev, ctx, n, L, steps=3):
+    """Full-range residues: every plane uniform in [0, p_j) (seeded on the
+    device), the INT8 product of the n x n planes over L primes and the exact
+    (Garner) CRT into 10-word outputs; sampled entries against the oracle."""
+    import numpy as np
+    from oracle import rns as orns
+    W = 10
+    g = torch.Generator(device=dev)
+    ra = torch.empty((L, n, n), dtype=torch.int32, device=dev)
+    rb = torch.empty_like(ra)
+    for j, p in enumerate(ctx.primes[:L]):
+        g.manual_seed(1000 + j)
+        ra[j].random_(0, p, generator=g)
+        g.manual_seed(2000 + j)
+        rb[j].random_(0, p, generator=g)
+    rc = torch.empty_like(ra)
+    out = torch.empty((n, n, W), dtype=torch.int64, device=dev)
+    prob = [rg.GemmProblem(ra, rb, rc)]
+
+    def step():
+        rg.modmatmul_batched(ctx, prob, path="int8")
+        rg.crt_reconstruct(ctx, rc, L=L, W=W, out=out)
+
+    step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read("")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    ctx.profile(False)
+    kern = {}
+    for name in ("k_prep", "k_gemm", "k_crt"):
+        ms, cnt = ctx.profile_read(name)
+        if cnt:
+            kern[name] = {"avg_ms": ms / cnt, "launches": cnt}
+    primes = ctx.primes[:L]
+    for (i, j) in ((0, 0), (n // 2, n // 3), (n - 1, n - 1), (17, n - 5)):
+        arow = ra[:, i, :].cpu().numpy().astype(np.int64)
+        bcol = rb[:, :, j].cpu().numpy().astype(np.int64)
+        r = [orns.modmatmul_entry(arow[q], bcol[q], p) for q, p in enumerate(primes)]
+        want = orns.to_words(orns.crt(r, primes), W)
+        got = [int(v) & ((1 << 64) - 1) for v in out[i, j].cpu().numpy()]
+        if got != want:
+            print("bench.py: full-range residue product differs from the oracle at", (i, j), file=sys.stderr)
+            sys.exit(1)
+    if ctx.status() != 0:
+        print("bench.py: CRT reported an error on full-range residues", file=sys.stderr)
+        sys.exit(1)
+    ops = 2.0 * n ** 3 * L
+    return {"workload": "full-range residues uniform in [0, p_j) per plane (seeded), %dx%d, %d primes, INT8 path, "
+                        "exact Garner CRT into %d words" % (n, n, L, W),
+            "ms_per_step": 1000 * t, "value": ops / t, "unit": "int-ops/s", "kernels": kern,
+            "gemm_mfma_tops": 16.0 * ops / (kern["k_gemm"]["avg_ms"] * 1e-3) / 1e12, "sampled_entries_checked": 4}
+
+
+SERVING_FRACS = (0.25, 0.5, 0.75, 1.0, 1.25)
+
+
+def run_serving(rg, count, fracs=SERVING_FRACS):
+    """Closed-loop capacity, then open-loop Poisson arrivals at each fraction
+    of it, each point with the n = 10007 tail at its 50th arrival;
     latency = completion - arrival.  Every served result is a divisor chain
     certified by the library; a sample is solved again alone and compared."""
     import numpy as np
@@ -294,9 +367,9 @@ def run_serving(rg, count):
     out["closed_loop_solves_per_s"] = cap
     points = []
     solved = []
-    for frac, seed, tail in ((0.5, 11, False), (1.0, 12, True)):
+    for i, frac in enumerate(fracs):
         rate = frac * cap
-        reqs = _serving_stream(count, rate, seed=seed, tail=tail and count > 50)
+        reqs = _serving_stream(count, rate, seed=11 + i, tail=count > 50)
         start = time.perf_counter()
         tickets = []
         for r, a, kind in reqs:
@@ -348,7 +421,7 @@ def run_serving(rg, count):
     out["max_running"] = st["max_running"]
     out["hbm_high_water_bytes"] = st["high_water"]
     out["workload"] = ("Poisson arrivals; n log-uniform in [100, 4000], entries uniform in [-2^10, 2^10] "
-                       "(seeded synthetic stand-ins), n = 10007 tail at the 50th arrival of the 1.0x point, "
+                       "(seeded synthetic stand-ins), n = 10007 tail at the 50th arrival of each point, "
                        "one singular request per point; %d requests per point" % count)
     return out
 
@@ -407,9 +480,14 @@ def main():
         ctx.profile(True)
         ctx.profile_read("")          # drop warm-up records
         torch.cuda.synchronize()
+        # Events on the stream the library launches on (torch's current
+        # stream) bracket every step; the wall clock brackets all of them.
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(steps):
+        ev[0].record()
+        for i in range(steps):
             step(path)
+            ev[i + 1].record()
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         ctx.profile(False)
@@ -418,6 +496,8 @@ def main():
             ms, cnt = ctx.profile_read(name)
             if cnt:
                 kern[name] = {"avg_ms": ms / cnt, "launches": cnt}
+        per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+        kern["step_ms"] = {"median": per[len(per) // 2], "min": per[0], "max": per[-1]}
         return t, kern
 
     res_ops = 2.0 * n * n * n * L
@@ -486,6 +566,7 @@ def main():
                      "kernel": kernel, "avg_launch_ms": gemm_ms,
                      "ops_per_launch": mfma_ops, "measured_ceiling": ceiling},
         "kernels": k8,
+        "device": {"name": torch.cuda.get_device_name(0), "host_cores": os.cpu_count()},
         "hbm_passes": {
             "reduce_GBps": red_bytes / 2 / (k8["k_reduce"]["avg_ms"] * 1e-3) / 1e9,
             "crt_GBps": crt_bytes / (k8["k_crt"]["avg_ms"] * 1e-3) / 1e9,
@@ -493,6 +574,7 @@ def main():
         "fp64_path": fp64,
         "int8_vs_fp64_speedup": (fp64["ms_per_step"] / ms8) if fp64 else None,
     }
+    rec["stress"] = run_stress(rg, torch, dev, ctx, n, L) if args.stress else None
     rec["batched"] = run_batched(rg, torch, dev, args.batched, args.batched_steps) if args.batched > 0 else None
     rec["smith"] = run_smith(rg) if args.smith else None
     rec["serving"] = run_serving(rg, args.serving) if args.serving > 0 else None

@@ -80,11 +80,18 @@ int rns_primes_below(uint64_t bound, int count, uint32_t *out);
  *   primes: host array of L distinct odd primes, each < 2^26; NULL selects the
  *           L largest primes below 2^26.
  *   L:      1 <= L <= 4096.
- *   flags:  reserved, pass 0.
+ *   flags:  0, or RNS_CTX_PATH_FP64 / RNS_CTX_PATH_INT8: the path that
+ *           RNS_PATH_AUTO resolves to in every product of this context (and
+ *           of the Smith-form driver working on it); other bits are
+ *           reserved and rejected with RNS_EINVAL.
  * The context owns its device tables and a growable workspace; free it with
  * rns_ctx_destroy.  Returns RNS_EINVAL for a bad basis, RNS_EDEVICE or
  * RNS_ENOMEM on HIP failures.
  */
+/* rns_ctx_create flags (low two bits: the default product path). */
+#define RNS_CTX_PATH_FP64 1u
+#define RNS_CTX_PATH_INT8 2u
+
 int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes, int L,
                    uint64_t flags);
 void rns_ctx_destroy(rns_ctx *ctx);

@@ -226,14 +226,18 @@ def _dev_ptr(t) -> int:
 class Context:
     """An RNS basis on one GPU (rns_ctx)."""
 
-    def __init__(self, device: int = 0, primes: Optional[Sequence[int]] = None, L: int = 24):
+    def __init__(self, device: int = 0, primes: Optional[Sequence[int]] = None, L: int = 24,
+                 path: Optional[str] = None):
+        """path: None (the library chooses), "fp64" or "int8": what the "auto"
+        path resolves to in this context's products (RNS_CTX_PATH_*)."""
+        flags = {None: 0, "auto": 0, "fp64": 1, "int8": 2}[path]
         h = _P()
         if primes is not None:
             arr = (ctypes.c_uint32 * len(primes))(*[int(p) for p in primes])
-            _check(_lib_ctx_create(ctypes.byref(h), device, ctypes.cast(arr, _P), len(primes), 0),
+            _check(_lib_ctx_create(ctypes.byref(h), device, ctypes.cast(arr, _P), len(primes), flags),
                    "rns_ctx_create")
         else:
-            _check(_lib_ctx_create(ctypes.byref(h), device, None, L, 0), "rns_ctx_create")
+            _check(_lib_ctx_create(ctypes.byref(h), device, None, L, flags), "rns_ctx_create")
         self.handle = h
         self.device = device
         n = _lib_ctx_num_primes(h)

@@ -103,6 +103,7 @@ int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &
 
 // Plans for a path; AUTO takes INT8 unless k exceeds its exactness bound.
 int make_plan_path(rns_ctx *ctx, const rns_gemm_desc *d, int count, int path, bool &int8, Plan &plan) {
+    if (path == RNS_PATH_AUTO) path = ctx->auto_path;
     int8 = path != RNS_PATH_FP64;
     int st = make_plan(ctx, d, count, int8, plan);
     if (st == RNS_EBOUND && path == RNS_PATH_AUTO) {

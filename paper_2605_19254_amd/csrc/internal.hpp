@@ -84,6 +84,8 @@ struct rns_ctx {
     int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
     rns_ctx *aux = nullptr;            // wide-basis context of the Smith-form driver
     int int8_kernel = -1;              // forced INT8 GEMM variant (RNS_INT8_KERNEL), -1 = tuned
+    uint64_t flags = 0;                // creation flags (RNS_CTX_PATH_*)
+    int auto_path = 0;                 // what RNS_PATH_AUTO resolves to: 0 library choice, else a path
     int num_cus = 256;
     unsigned *d_counter = nullptr;     // work counter of persistent launches of modmatmul_batched
     std::map<std::string, int> tune;   // autotuned INT8 variant per shape class

@@ -1012,7 +1012,7 @@ struct Driver {
 int aux_ctx(rns_ctx *ctx, rns_ctx **out) {
     std::lock_guard<std::mutex> g(ctx->mu);
     if (!ctx->aux) {
-        int st = rns_ctx_create(&ctx->aux, ctx->device, nullptr, kAuxPrimes, 0);
+        int st = rns_ctx_create(&ctx->aux, ctx->device, nullptr, kAuxPrimes, ctx->flags);
         if (st != RNS_OK) return st;
     }
     *out = ctx->aux;

@@ -211,6 +211,34 @@ def test_modmatmul_digit_extremes_at_max_k(ctx, rg, torch_dev, variant):
     assert np.array_equal(c.cpu().numpy()[0], want)
 
 
+def test_context_path_flag(rg, torch_dev):
+    """rns_ctx_create flags: RNS_CTX_PATH_FP64 / _INT8 fix what the auto path
+    resolves to; other flag bits are rejected."""
+    import ctypes
+    from paper_2605_19254_amd import binding
+    torch, dev = torch_dev
+    _say("context path flag")
+    rng = np.random.default_rng(77)
+    ps = PRIMES[:3]
+    a = _res(rng, ps, 70, 90, edge=True)
+    b = _res(rng, ps, 90, 50, edge=True)
+    for path in ("fp64", "int8"):
+        with rg.Context(device=0, L=3, path=path) as c:
+            out = torch.empty((3, 70, 50), dtype=torch.int32, device=dev)
+            prob = rg.GemmProblem(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), out)
+            plan = rg.GemmPlan(c, [prob], path="auto")
+            assert plan.info()["path"] == path
+            plan.execute()
+            plan.close()
+            got = out.cpu().numpy()
+            for j, p in enumerate(ps):
+                want = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int32)
+                assert np.array_equal(got[j], want)
+    h = ctypes.c_void_p()
+    for flags in (3, 4, 1 << 40):
+        assert binding._lib_ctx_create(ctypes.byref(h), 0, None, 3, flags) == binding.EINVAL
+
+
 def test_modmatmul_batch_equals_single_and_paths_agree(ctx, rg, torch_dev):
     torch, dev = torch_dev
     _say("modmatmul batch")

@@ -44,6 +44,30 @@ def test_small_smith_workload(ctx, rg):
     assert res.stats["products"] >= 2
 
 
+@pytest.mark.parametrize("gen,n", [("small", 64), ("planted", 200), ("random", 300)])
+def test_smith_on_fp64_product_path(rg, gen, n):
+    """A context created with RNS_CTX_PATH_FP64 runs every product of the
+    driver (elimination updates, certificates) on the FP64 path; the Smith
+    form is the same."""
+    _say("smith on the fp64 product path", gen, n)
+    if gen == "small":
+        a = synth.small_smith(seed=0)
+        want = osmith.smith_form(a)
+    elif gen == "planted":
+        pl = synth.planted_smith(n, seed=3)
+        a, want = pl.a, pl.s
+    else:
+        a = synth.small_smith(seed=5, n=n, bound=1 << 10)
+        want = None
+    with rg.Context(device=0, L=24, path="fp64") as c64, rg.Context(device=0, L=24, path="int8") as c8:
+        r64 = rg.smith_form(c64, a, seed=1)
+        r8 = rg.smith_form(c8, a, seed=1)
+    assert r64.s == r8.s
+    assert osmith.is_divisor_chain(r64.s)
+    if want is not None:
+        assert r64.s == want
+
+
 @pytest.mark.parametrize("n", [3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53])
 def test_vandermonde_mod_family(ctx, rg, n):
     # Section 4.1 family; Section 4.2 checks primes 3..53.
