@@ -377,6 +377,8 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
             if d > 0:
                 time.sleep(d)
             tickets.append(srv.submit(a, seed=1))
+            if len(tickets) % 50 == 0:
+                print("[serving] %.2fx capacity: %d submitted" % (frac, len(tickets)), file=sys.stderr, flush=True)
         lat, queue, service, ok, bad, tail_rec, paths, exact = [], [], [], 0, 0, None, [0, 0], 0
         for t, (r, a, kind) in zip(tickets, reqs):
             st, res, info = srv.wait(t)
@@ -400,6 +402,7 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
             if len(solved) < 6 and r.n <= 1500:
                 solved.append((a, res.s))
         span = time.perf_counter() - start
+        print("[serving] %.2fx capacity: %d requests in %.1f s" % (frac, count, span), file=sys.stderr, flush=True)
         points.append({"rate_frac_of_capacity": frac, "arrival_rate": rate, "requests": count,
                        "solves_per_s": ok / span, "p50_latency_s": float(np.percentile(lat, 50)),
                        "p99_latency_s": float(np.percentile(lat, 99)),
