@@ -131,6 +131,21 @@ int rns_reduce(rns_ctx *ctx, const int64_t *x, int64_t rows, int64_t cols,
                int64_t ldr, int64_t plane_stride, void *stream);
 
 /*
+ * rns_reduce_mw -- the same reduction (Section 3.1) for multiword integers:
+ * entry (i, c) is the W-word two's-complement integer whose 64-bit words,
+ * least significant first, are x[(i*ldx + c)*W + w], w = 0 .. W-1 (the
+ * layout crt_reconstruct writes), so crt_reconstruct(rns_reduce_mw(x)) = x
+ * whenever |x| < M/2 for the product M of the primes.
+ *   x:   device uint64, 1 <= W <= 32, ldx >= cols (in entries).
+ *   res: as for rns_reduce.
+ * Each residue is formed by Horner's rule over the 32-bit halves of |x| in
+ * exact double arithmetic, then negated mod p for negative x.
+ */
+int rns_reduce_mw(rns_ctx *ctx, const uint64_t *x, int W, int64_t rows, int64_t cols,
+                  int64_t ldx, int prime_begin, int L, uint32_t *res,
+                  int64_t ldr, int64_t plane_stride, void *stream);
+
+/*
  * One residue product problem of modmatmul_batched:
  *   for j in [0, L):  C_j = A_j * B_j mod p_{prime_begin+j}
  * with A_j = A + j*a_plane_stride (m x k, leading dimension lda),
@@ -228,10 +243,12 @@ int rns_gemm_plan_autotune(rns_gemm_plan *plan, void *stream, int *variant_out);
 
 /*
  * Whole-product plans (Section 3.1 end to end): C = A B over the integers for
- * `count` independent problems.  The plan owns the residue planes of A, B and
- * C for every problem (they stay resident in HBM between executions), and one
- * execution runs one reduction launch over all A and B, the operand
- * conversion and GEMM launches of a gemm plan, and one CRT launch over all C.
+ * `count` independent problems.  One execution runs three launches: one
+ * conversion launch that reduces every A and B modulo each of its primes
+ * straight into the GEMM's tiled operand layouts (no residue planes of A and
+ * B are written), one GEMM launch over all primes and problems, and one CRT
+ * launch over all C.  The plan owns the tiled operands and the residue planes
+ * of every C; they stay resident in HBM between executions.
  *   A, B: device int64, row-major (m x k, k x n), leading dimensions lda, ldb.
  *   C:    device uint64, W words per entry (entry (i, j) at
  *         C[(i*ldc + j)*W + w]), two's complement; W == 1 is an int64 matrix.

@@ -101,6 +101,7 @@ _lib_workspace_bytes = _sig("rns_workspace_bytes", _I32,
                             [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32, ctypes.POINTER(ctypes.c_size_t)])
 _lib_primes_for_bound = _sig("rns_primes_for_bound", _I32, [_P, _P, _I32, ctypes.POINTER(_I32)])
 _lib_reduce = _sig("rns_reduce", _I32, [_P, _P, _I64, _I64, _I64, _I32, _I32, _P, _I64, _I64, _P])
+_lib_reduce_mw = _sig("rns_reduce_mw", _I32, [_P, _P, _I32, _I64, _I64, _I64, _I32, _I32, _P, _I64, _I64, _P])
 _lib_modmatmul = _sig("modmatmul_batched", _I32, [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32, _P])
 _lib_crt = _sig("crt_reconstruct", _I32, [_P, _P, _I64, _I64, _I64, _I64, _I32, _I32, _P, _I32,
                                           _P, _I32, _I64, _P, _P])
@@ -167,7 +168,7 @@ _lib_profile_read = _sig("rns_ctx_profile_read", _I32, [_P, ctypes.c_char_p, cty
 
 EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destroy",
            "rns_ctx_num_primes", "rns_ctx_primes", "rns_ctx_reserve", "rns_workspace_bytes",
-           "rns_primes_for_bound", "rns_reduce", "modmatmul_batched", "crt_reconstruct",
+           "rns_primes_for_bound", "rns_reduce", "rns_reduce_mw", "modmatmul_batched", "crt_reconstruct",
            "rns_ctx_status", "smith_form", "rns_smith_get", "rns_smith_size",
            "rns_smith_stats_get", "rns_smith_free", "rns_ctx_force_cert_failures",
            "rns_ctx_profile", "rns_ctx_profile_read", "rns_gemm_plan_create", "rns_gemm_plan_execute",
@@ -331,6 +332,22 @@ def rns_reduce(ctx: Context, x, prime_begin: int = 0, L: Optional[int] = None, o
     return out
 
 
+def rns_reduce_mw(ctx: Context, x, prime_begin: int = 0, L: Optional[int] = None, out=None, stream=None):
+    """x: int64 device tensor (rows, cols, W) of two's-complement words, least
+    significant first (the layout crt_reconstruct returns), unit stride over
+    the last two dimensions.  Returns int32 residue planes [L, rows, cols]."""
+    import torch
+    L = ctx.L - prime_begin if L is None else L
+    assert x.dtype == torch.int64 and x.dim() == 3 and x.stride(2) == 1 and x.stride(1) == x.shape[2]
+    rows, cols, W = x.shape
+    if out is None:
+        out = torch.empty((L, rows, cols), dtype=torch.int32, device=x.device)
+    assert out.dtype == torch.int32 and out.stride(2) == 1
+    _check(_lib_reduce_mw(ctx.handle, _dev_ptr(x), W, rows, cols, x.stride(0) // W, prime_begin, L,
+                          _dev_ptr(out), out.stride(1), out.stride(0), _stream(stream)), "rns_reduce_mw")
+    return out
+
+
 @dataclass
 class GemmProblem:
     """C[j] = A[j] @ B[j] mod p_{prime_begin+j} (or, with subtract,
@@ -452,7 +469,8 @@ class MatmulProblem:
 
 class MatmulPlan:
     """rns_matmul_plan: reduce -> products -> CRT for a batch, with resident
-    residue planes; execute() is four kernel launches."""
+    tiled operands and C residue planes; execute() is three kernel launches
+    (conversion of the int64 operands, GEMM, CRT)."""
 
     def __init__(self, ctx: Context, problems: Sequence[MatmulProblem], path="auto", W: int = 1):
         self.ctx = ctx

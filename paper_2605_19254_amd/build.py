@@ -71,7 +71,7 @@ def build(verbose: bool = False) -> str:
     rt = _runtime_dir()
     if rt:
         # -z defs: a symbol missing from the objects fails the link here
-        # instead of the library load on the GPU machine.
+        # instead of a later library load.
         cmd = ["g++", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs + [
             "-L" + rt, "-l:libamdhip64.so", "-Wl,-rpath," + rt, "-lpthread"]
     else:

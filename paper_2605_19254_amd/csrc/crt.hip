@@ -42,19 +42,9 @@ __device__ __forceinline__ double modp(double x, const PC2 &P) {
     return fma(-rint(x * P.pinv), P.pf, x);                 // |result| <= (p+1)/2
 }
 
-// With a job table, blocks take runs of `chunk` consecutive tiles; the job of a
-// run's first tile is found by binary search and later tiles advance the job
-// index linearly.  A single job uses runs of one tile.
+// With a job table, blocks take runs of `chunk` consecutive tiles, job by job
+// (for_job_tiles).  A single job uses runs of one tile.
 constexpr int kChunk = 8;
-
-__device__ __forceinline__ int find_job(const CrtJob *jobs, int njobs, int64_t t) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 template <int WT>
 __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob *__restrict__ jobs,
@@ -68,14 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
       const int64_t t0 = ch * chunk;
       const int64_t t1 = t0 + chunk < total_tiles ? t0 + chunk : total_tiles;
-      int qj = njobs > 0 ? find_job(jobs, njobs, t0) : 0;
-      for (int64_t t = t0; t < t1; ++t) {
-        if (njobs > 0)
-            while (qj + 1 < njobs && jobs[qj + 1].tile_begin <= t) ++qj;
-        // The job index is the same on every lane; saying so lets the job and
-        // the per-prime constants come through scalar loads.
-        qj = __builtin_amdgcn_readfirstlane(qj);
-        const CrtJob J = njobs > 0 ? jobs[qj] : job0;
+      for_job_tiles(job0, jobs, njobs, total_tiles, t0, t1, [&](const CrtJob &J, int64_t t) {
         const int64_t u = t - J.tile_begin;
         const int64_t i = u / J.col_tiles;
         // Lanes past the last column work on the last column and store
@@ -164,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
         bool fits;
         if (!neg) fits = high_zero && (top >> 63) == 0;
         else fits = high_zero && ((top >> 63) == 0 || (top == (1ull << 63) && low_zero));
-        if (!valid) continue;
+        if (!valid) return;
         if (!fits) atomicOr(J.status, 1);
         // Two's complement of the signed value, low W words.
         const auto dst = gptr_w(J.out + (i * J.ldo + c) * W);
@@ -181,7 +164,60 @@ __global__ __launch_bounds__(kBlock) void k_crt_garner(CrtJob job0, const CrtJob
                 dst[k] = v;
             }
         }
-      }
+      });
+    }
+}
+
+// Lagrange form, one prime's term for one entry: y = r (M/p_j)^-1 mod p_j in
+// [0, p_j), alpha += y / p_j, x += y (M/p_j) over the low WT words.
+template <int WT>
+__device__ __forceinline__ void lag_term(uint64_t (&x)[WT], double &alpha, uint32_t r, int j,
+                                         const __attribute__((address_space(4))) PrimeConst *pc,
+                                         const __attribute__((address_space(4))) double *cinv,
+                                         const __attribute__((address_space(4))) uint64_t *mj, int W) {
+    const PC2 P{pc[j].pf, pc[j].pinv};
+    double y = modp((double)r * cinv[j], P);
+    y = y < 0.0 ? y + P.pf : y;
+    alpha = fma(y, P.pinv, alpha);
+    const uint64_t yi = (uint64_t)y;
+    const auto m = mj + (int64_t)j * W;
+    uint64_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+        if (k < W) {
+            const uint64_t lo = m[k] * yi;
+            const uint64_t hi = __umul64hi(m[k], yi);
+            const uint64_t s1 = lo + carry;
+            const uint64_t c1 = s1 < lo ? 1 : 0;
+            const uint64_t s2 = x[k] + s1;
+            const uint64_t c2 = s2 < x[k] ? 1 : 0;
+            x[k] = s2;
+            carry = hi + c1 + c2;
+        }
+    }
+}
+
+// x -= round(alpha) M over the low WT words: the symmetric representative.
+template <int WT>
+__device__ __forceinline__ void lag_finish(uint64_t (&x)[WT], double alpha,
+                                           const __attribute__((address_space(4))) uint64_t *mw, int W) {
+    const uint64_t a = (uint64_t)rint(alpha);
+    uint64_t borrow = 0;
+    uint64_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < WT; ++k) {
+        if (k < W) {
+            const uint64_t lo = mw[k] * a;
+            const uint64_t hi = __umul64hi(mw[k], a);
+            const uint64_t s1 = lo + carry;
+            carry = hi + (s1 < lo ? 1 : 0);
+            const uint64_t d1 = x[k] - s1;
+            const uint64_t b1 = x[k] < s1 ? 1 : 0;
+            const uint64_t d2 = d1 - borrow;
+            const uint64_t b2 = d1 < borrow ? 1 : 0;
+            x[k] = d2;
+            borrow = b1 + b2;
+        }
     }
 }
 
@@ -202,7 +238,6 @@ __device__ __forceinline__ void lagrange_entry(const uint32_t *res_row, uint64_t
     const auto pc = cptr(pc_job);
     const auto cinv = cptr(lag_c);
     const auto mj = cptr(lag_mj);
-    const auto mw = cptr(lag_m);
     uint64_t x[WT];
 #pragma unroll
     for (int k = 0; k < WT; ++k) x[k] = 0;
@@ -213,53 +248,58 @@ __device__ __forceinline__ void lagrange_entry(const uint32_t *res_row, uint64_t
         for (int q = 0; q < 8; ++q) r[q] = src[(int64_t)min(j0 + q, L - 1) * ps];   // in bounds
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int j = j0 + q;
-            if (j >= L) break;
-            const PC2 P{pc[j].pf, pc[j].pinv};
-            double y = modp((double)r[q] * cinv[j], P);
-            y = y < 0.0 ? y + P.pf : y;
-            alpha = fma(y, P.pinv, alpha);
-            const uint64_t yi = (uint64_t)y;
-            const auto m = mj + (int64_t)j * W;
-            uint64_t carry = 0;
-#pragma unroll
-            for (int k = 0; k < WT; ++k) {
-                if (k < W) {
-                    const uint64_t lo = m[k] * yi;
-                    const uint64_t hi = __umul64hi(m[k], yi);
-                    const uint64_t s1 = lo + carry;
-                    const uint64_t c1 = s1 < lo ? 1 : 0;
-                    const uint64_t s2 = x[k] + s1;
-                    const uint64_t c2 = s2 < x[k] ? 1 : 0;
-                    x[k] = s2;
-                    carry = hi + c1 + c2;
-                }
-            }
+            if (j0 + q >= L) break;
+            lag_term<WT>(x, alpha, r[q], j0 + q, pc, cinv, mj, W);
         }
     }
-    const uint64_t a = (uint64_t)rint(alpha);
-    uint64_t borrow = 0;
-    uint64_t carry = 0;
-#pragma unroll
-    for (int k = 0; k < WT; ++k) {
-        if (k < W) {
-            const uint64_t lo = mw[k] * a;
-            const uint64_t hi = __umul64hi(mw[k], a);
-            const uint64_t s1 = lo + carry;
-            carry = hi + (s1 < lo ? 1 : 0);
-            const uint64_t d1 = x[k] - s1;
-            const uint64_t b1 = x[k] < s1 ? 1 : 0;
-            const uint64_t d2 = d1 - borrow;
-            const uint64_t b2 = d1 < borrow ? 1 : 0;
-            x[k] = d2;
-            borrow = b1 + b2;
-        }
-    }
+    lag_finish<WT>(x, alpha, cptr(lag_m), W);
     if (!valid) return;
     const auto dst = gptr_w(out_row + c * W);
 #pragma unroll
     for (int k = 0; k < WT; ++k)
         if (k < W) dst[k] = x[k];
+}
+
+// Short bases (L <= kShortL): E entries per thread, kBlock apart, whose
+// residues are all loaded (E*kShortL loads in flight; planes past L repeat
+// the last one) before any is combined.
+constexpr int kShortL = 4;
+
+template <int WT, int E>
+__device__ __forceinline__ void lagrange_short(const uint32_t *res_row, uint64_t *out_row, int64_t cols,
+                                               int64_t ps, int L, const PrimeConst *pc_job,
+                                               const double *lag_c, const uint64_t *lag_mj,
+                                               const uint64_t *lag_m, int W, int64_t base) {
+    const auto pc = cptr(pc_job);
+    const auto cinv = cptr(lag_c);
+    const auto mj = cptr(lag_mj);
+    uint32_t r[E][kShortL];
+    int64_t c[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t c_lane = base + (int64_t)e * kBlock;
+        c[e] = c_lane < cols ? c_lane : cols - 1;        // in bounds; stores are skipped below
+        const auto src = gptr(res_row + c[e]);
+#pragma unroll
+        for (int q = 0; q < kShortL; ++q) r[e][q] = src[(int64_t)min(q, L - 1) * ps];   // no branch per load
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        uint64_t x[WT];
+#pragma unroll
+        for (int k = 0; k < WT; ++k) x[k] = 0;
+        double alpha = 0.0;
+#pragma unroll
+        for (int q = 0; q < kShortL; ++q)
+            if (q < L) lag_term<WT>(x, alpha, r[e][q], q, pc, cinv, mj, W);
+        lag_finish<WT>(x, alpha, cptr(lag_m), W);
+        if (base + (int64_t)e * kBlock < cols) {
+            const auto dst = gptr_w(out_row + c[e] * W);
+#pragma unroll
+            for (int k = 0; k < WT; ++k)
+                if (k < W) dst[k] = x[k];
+        }
+    }
 }
 
 // E entries per thread: a tile covers E * kBlock columns of one row.
@@ -272,24 +312,20 @@ __global__ __launch_bounds__(kBlock) void k_crt_lagrange(CrtJob job0, const CrtJ
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
       const int64_t t0 = ch * chunk;
       const int64_t t1 = t0 + chunk < total_tiles ? t0 + chunk : total_tiles;
-      int qj = njobs > 0 ? find_job(jobs, njobs, t0) : 0;
-      for (int64_t t = t0; t < t1; ++t) {
-        if (njobs > 0)
-            while (qj + 1 < njobs && jobs[qj + 1].tile_begin <= t) ++qj;
-        // The job index is the same on every lane; saying so lets the job and
-        // the per-prime constants come through scalar loads.
-        qj = __builtin_amdgcn_readfirstlane(qj);
-        const CrtJob J = njobs > 0 ? jobs[qj] : job0;
+      for_job_tiles(job0, jobs, njobs, total_tiles, t0, t1, [&](const CrtJob &J, int64_t t) {
         const int64_t u = t - J.tile_begin;
         const int64_t i = u / J.col_tiles;
         const int64_t base = (u - i * J.col_tiles) * kBlock * E + threadIdx.x;
         const uint32_t *res_row = J.res + i * J.ldr;
         uint64_t *out_row = J.out + i * J.ldo * W;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
+        if constexpr (E > 1) {
+            lagrange_short<WT, E>(res_row, out_row, J.cols, J.ps, J.L, pc_all + J.prime_begin, J.lag_c,
+                                  J.lag_mj, J.lag_m, W, base);
+        } else {
             lagrange_entry<WT>(res_row, out_row, J.cols, J.ps, J.L, pc_all + J.prime_begin, J.lag_c, J.lag_mj,
-                               J.lag_m, W, base + e * kBlock);
-      }
+                               J.lag_m, W, base);
+        }
+      });
     }
 }
 
@@ -351,7 +387,7 @@ namespace rns {
 // Entries per thread: 4 for the Lagrange form with at most two output words
 // and at most 4 primes (little work per entry, so a tile's job lookup is
 // shared by more entries), otherwise 1 (more threads in flight).
-int crt_entries(bool fast, int W, int L) { return fast && W <= 2 && L <= 4 ? kLagEntries : 1; }
+int crt_entries(bool fast, int W, int L) { return fast && W <= 2 && L <= kShortL ? kLagEntries : 1; }
 int64_t crt_col_tiles(int64_t cols, int entries) { return (cols + kBlock * entries - 1) / (kBlock * entries); }
 int64_t crt_tiles(int64_t rows, int64_t cols, int entries) { return rows * crt_col_tiles(cols, entries); }
 

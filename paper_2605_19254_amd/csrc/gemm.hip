@@ -26,11 +26,13 @@ struct Plan {
     size_t work_bytes = 0;
     int64_t total_tiles = 0;
     int64_t total_units = 0;
+    bool from_int64 = false;
+    int64_t total_units64 = 0;
     double residue_ops = 0;
     int64_t max_dim = 0;
 };
 
-int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x) {
+int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x, const GemmInt64Src *src) {
     if (x.m < 0 || x.n < 0 || x.k < 0 || x.L < 0) return RNS_EINVAL;
     if ((x.flags & ~RNS_GEMM_SUBTRACT) != 0 || x.reserved != 0) return RNS_EINVAL;
     if (x.prime_begin < 0 || x.prime_begin + x.L > ctx->L) return RNS_EINVAL;
@@ -38,7 +40,9 @@ int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x) {
     if (x.m == 0 || x.n == 0 || x.L == 0) return RNS_OK;
     if (!x.C || x.ldc < x.n) return RNS_EINVAL;
     if (x.L > 1 && x.c_plane_stride < (x.m - 1) * x.ldc + x.n) return RNS_EINVAL;
-    if (x.k > 0) {
+    if (x.k > 0 && src) {
+        if (!src->A || !src->B || src->lda < x.k || src->ldb < x.n) return RNS_EINVAL;
+    } else if (x.k > 0) {
         if (!x.A || !x.B || x.lda < x.k || x.ldb < x.n) return RNS_EINVAL;
         if (x.L > 1 && (x.a_plane_stride < (x.m - 1) * x.lda + x.k ||
                         x.b_plane_stride < (x.k - 1) * x.ldb + x.n))
@@ -50,13 +54,14 @@ int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x) {
 // Builds the problem table.  Problems are ordered by decreasing tile cost
 // (k, then m*n), so that a persistent launch hands out the longest tiles
 // first; workspace offsets are relative (the caller adds the base).
-int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &plan) {
+int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &plan,
+              const GemmInt64Src *src = nullptr) {
     const int TM = int8 ? kI8TileM : kF64TileM;
     const int TN = int8 ? kI8TileN : kF64TileN;
     const int64_t elem = int8 ? 4 : 8;   // bytes per operand entry in the tiled layout
     std::vector<int> order;
     for (int i = 0; i < count; ++i) {
-        int st = check_desc(ctx, d[i]);
+        int st = check_desc(ctx, d[i], src ? &src[i] : nullptr);
         if (st != RNS_OK) return st;
         if (d[i].m == 0 || d[i].n == 0 || d[i].L == 0) continue;
         if (int8 && d[i].k > kInt8MaxK) return RNS_EBOUND;
@@ -81,6 +86,10 @@ int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &
         const int64_t Kp = round_up(std::max<int64_t>(x.k, 1), kKTile);
         g.RB = (int32_t)(Mp / 16); g.CB = (int32_t)(Np / 16); g.KT = (int32_t)(Kp / kKTile);
         g.tm = (int32_t)(Mp / TM); g.tn = (int32_t)(Np / TN);
+        // 32-bit tile and conversion-unit indices inside a problem
+        if ((int64_t)g.L * g.tm * g.tn >= ((int64_t)1 << 31) ||
+            (int64_t)g.L * (g.RB + g.CB) * g.KT >= ((int64_t)1 << 31))
+            return RNS_EINVAL;
         g.a_plane_bytes = Mp * Kp * elem;
         g.b_plane_bytes = Np * Kp * elem;
         g.At = reinterpret_cast<char *>(off);
@@ -93,23 +102,32 @@ int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &
         g.unitA_begin = plan.total_units;
         g.unitB_begin = g.unitA_begin + (int64_t)g.L * g.RB * g.KT;
         plan.total_units = g.unitB_begin + (int64_t)g.L * g.CB * g.KT;
+        if (src) {
+            g.A64 = src[i].A; g.lda64 = src[i].lda;
+            g.B64 = src[i].B; g.ldb64 = src[i].ldb;
+            g.u64A_begin = plan.total_units64;
+            g.u64B_begin = g.u64A_begin + (int64_t)g.RB * g.KT;
+            plan.total_units64 = g.u64B_begin + (int64_t)g.CB * g.KT;
+        }
         plan.residue_ops += 2.0 * x.m * x.n * x.k * x.L;
         plan.max_dim = std::max<int64_t>(plan.max_dim, std::max(x.m, std::max(x.n, x.k)));
         plan.probs.push_back(g);
     }
     plan.work_bytes = off;
+    plan.from_int64 = src != nullptr;
     return RNS_OK;
 }
 
 // Plans for a path; AUTO takes INT8 unless k exceeds its exactness bound.
-int make_plan_path(rns_ctx *ctx, const rns_gemm_desc *d, int count, int path, bool &int8, Plan &plan) {
+int make_plan_path(rns_ctx *ctx, const rns_gemm_desc *d, int count, int path, bool &int8, Plan &plan,
+                   const GemmInt64Src *src = nullptr) {
     if (path == RNS_PATH_AUTO) path = ctx->auto_path;
     int8 = path != RNS_PATH_FP64;
-    int st = make_plan(ctx, d, count, int8, plan);
+    int st = make_plan(ctx, d, count, int8, plan, src);
     if (st == RNS_EBOUND && path == RNS_PATH_AUTO) {
         int8 = false;
         plan = Plan();
-        st = make_plan(ctx, d, count, int8, plan);
+        st = make_plan(ctx, d, count, int8, plan, src);
     }
     return st;
 }
@@ -137,10 +155,16 @@ int choose_variant(rns_ctx *ctx, bool int8, const Plan &plan) {
     return it != ctx->tune.end() ? it->second : kI8Default;
 }
 
+// units: conversion units (per prime and tile, or per tile for int64 operands).
 int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np, int64_t tiles,
-             int64_t units, const int32_t *tile_prob, unsigned *counter, hipStream_t s) {
+             int64_t units, const int32_t *tile_prob, unsigned *counter, hipStream_t s,
+             bool from_int64 = false) {
     const bool persistent = int8 && variant == kI8HalfPersistent;
-    {
+    if (from_int64) {
+        ProfScope ps(ctx, int8 ? "k_prep_i64_i8" : "k_prep_i64_f64", s);
+        launch_prep_i64(int8, dP, np, units, (const PrimeConst *)ctx->d_prime,
+                        persistent ? counter : nullptr, s);
+    } else {
         ProfScope ps(ctx, int8 ? "k_prep_i8" : "k_prep_f64", s);
         launch_prep(int8, dP, np, units, (const PrimeConst *)ctx->d_prime,
                     persistent ? counter : nullptr, s);
@@ -165,6 +189,7 @@ int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np
 struct rns_gemm_plan {
     rns_ctx *ctx = nullptr;
     bool int8 = true;
+    bool from_int64 = false;        // operands are int64 matrices (conversion reduces them)
     int variant = 0;
     int nprob = 0;
     int64_t total_tiles = 0, total_units = 0;
@@ -188,22 +213,25 @@ extern "C" void rns_gemm_plan_destroy(rns_gemm_plan *p) {
     delete p;
 }
 
-extern "C" int rns_gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, int count, int path,
-                                    rns_gemm_plan **out) {
+namespace {
+
+int gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, const GemmInt64Src *src, int count, int path,
+                     rns_gemm_plan **out) {
     if (!ctx || !out || count < 0 || (count > 0 && !descs)) return RNS_EINVAL;
     if (path != RNS_PATH_AUTO && path != RNS_PATH_FP64 && path != RNS_PATH_INT8) return RNS_EINVAL;
     *out = nullptr;
     bool int8 = true;
     Plan plan;
-    int st = make_plan_path(ctx, descs, count, path, int8, plan);
+    int st = make_plan_path(ctx, descs, count, path, int8, plan, src);
     if (st != RNS_OK) return st;
     rns_gemm_plan *p = new (std::nothrow) rns_gemm_plan;
     if (!p) return RNS_ENOMEM;
     p->ctx = ctx;
     p->int8 = int8;
+    p->from_int64 = plan.from_int64;
     p->nprob = (int)plan.probs.size();
     p->total_tiles = plan.total_tiles;
-    p->total_units = plan.total_units;
+    p->total_units = plan.from_int64 ? plan.total_units64 : plan.total_units;
     p->work_bytes = plan.work_bytes;
     p->residue_ops = plan.residue_ops;
     p->key = tune_key(int8, plan);
@@ -241,12 +269,27 @@ extern "C" int rns_gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, in
     return RNS_OK;
 }
 
+}  // namespace
+
+extern "C" int rns_gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, int count, int path,
+                                    rns_gemm_plan **out) {
+    return gemm_plan_create(ctx, descs, nullptr, count, path, out);
+}
+
+namespace rns {
+int gemm_plan_create_int64(rns_ctx *ctx, const rns_gemm_desc *descs, const GemmInt64Src *src, int count,
+                           int path, rns_gemm_plan **out) {
+    if (count > 0 && !src) return RNS_EINVAL;
+    return gemm_plan_create(ctx, descs, src, count, path, out);
+}
+}  // namespace rns
+
 extern "C" int rns_gemm_plan_execute(rns_gemm_plan *p, void *stream) {
     if (!p) return RNS_EINVAL;
     if (p->nprob == 0) return RNS_OK;
     RNS_HIP(hipSetDevice(p->ctx->device));
     return run_plan(p->ctx, p->int8, p->variant, p->d_probs, p->nprob, p->total_tiles,
-                    p->total_units, p->d_tile_prob, p->d_counter, (hipStream_t)stream);
+                    p->total_units, p->d_tile_prob, p->d_counter, (hipStream_t)stream, p->from_int64);
 }
 
 extern "C" int rns_gemm_plan_info(const rns_gemm_plan *p, rns_plan_info *info) {

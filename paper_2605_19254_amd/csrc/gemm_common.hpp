@@ -33,6 +33,11 @@ struct GemmProblem {
     int64_t tile_begin;          // prefix over problems of L*tm*tn
     int64_t unitA_begin;         // prefix over problems of prep units (A then B)
     int64_t unitB_begin;
+    // int64 operands (whole-product plans): the conversion kernel reduces them
+    // straight into the tiled layouts, one unit per tile for all primes.
+    const int64_t *A64, *B64;
+    int64_t lda64, ldb64;
+    int64_t u64A_begin, u64B_begin;   // prefix over problems of those units (A then B)
 };
 
 __device__ __forceinline__ int find_problem(const GemmProblem *P, int nprob, int64_t t,
@@ -71,19 +76,21 @@ __device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, i
     TileCoord c;
     c.q = tile_prob ? tile_prob[t] : find_problem(P, nprob, t, &GemmProblem::tile_begin);
     const GemmProblem &g = P[c.q];
-    int64_t u = t - g.tile_begin;
-    const int64_t per_plane = (int64_t)g.tm * g.tn;
+    // A problem has fewer than 2^31 tiles (the host checks), so the index
+    // arithmetic inside it is 32-bit.
+    uint32_t u = (uint32_t)(t - g.tile_begin);
+    const uint32_t per_plane = (uint32_t)g.tm * (uint32_t)g.tn;
     c.plane = (int)(u / per_plane);
-    u -= (int64_t)c.plane * per_plane;
+    u -= (uint32_t)c.plane * per_plane;
     // Grouped raster inside a plane: 8 tile-rows at a time, column-major
     // within the group, so neighbouring work-groups share A and B panels.
-    const int group = 8;
-    const int64_t gsize = (int64_t)group * g.tn;
-    const int gi = (int)(u / gsize);
-    const int first = gi * group;
-    const int rows_in = min(group, g.tm - first);
-    const int64_t v = u - (int64_t)gi * gsize;
-    c.tm = first + (int)(v % rows_in);
+    const uint32_t group = 8;
+    const uint32_t gsize = group * (uint32_t)g.tn;
+    const uint32_t gi = u / gsize;
+    const uint32_t first = gi * group;
+    const uint32_t rows_in = min(group, (uint32_t)g.tm - first);
+    const uint32_t v = u - gi * gsize;
+    c.tm = (int)(first + v % rows_in);
     c.tn = (int)(v / rows_in);
     return c;
 }
@@ -106,6 +113,8 @@ constexpr int kI8Default = kI8Half;
 
 void launch_prep(bool int8, const GemmProblem *P, int nprob, int64_t units,
                  const PrimeConst *pc, unsigned *counter, hipStream_t s);
+void launch_prep_i64(bool int8, const GemmProblem *P, int nprob, int64_t units,
+                     const PrimeConst *pc, unsigned *counter, hipStream_t s);
 void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
                     const PrimeConst *pc, const int32_t *tile_prob, unsigned *counter,
                     int num_cus, hipStream_t s);

@@ -5,10 +5,9 @@
 // |d3| <= 2 (the prep kernel does the split).  The 16 digit-pair products are
 // computed with v_mfma_i32_16x16x64_i8 and summed in int32 per shift group
 // s = i+j (7 groups).  The largest group sum per term is 3*2^14, so the int32
-// sums are exact for k <= 43690.  The epilogue reduces each group mod p and
-// recombines C = sum_s (C_s mod p)(2^(8s) mod p) mod p in exact doubles:
-// every product of two balanced residues is below 2^50 and seven of them
-// stay below 2^53.
+// sums are exact for k <= 43690.  The epilogue (recombine) forms
+// C = sum_s C_s 2^(8s) mod p in exact doubles with one intermediate
+// reduction.
 //
 // Every variant covers the same 64 x 128 output tiles (the host's tiling):
 //   direct   four waves in 2 x 2, each 32 x 64 outputs, operands straight from
@@ -28,6 +27,29 @@
 namespace rns {
 namespace gemm {
 namespace {
+
+// Epilogue of one output: (sum_s C_s 2^(8s)) mod p in [0, p), every step an
+// exact double operation.  With |C_s| < 2^31:
+//   lo  = C_0 + 2^8 C_1 + 2^16 C_2 and mid = C_3 + 2^8 C_4 + 2^16 C_5 are
+//         below 2^48 (exact);
+//   rm  = mid mod p, balanced (quotient below 2^22, so the rounded
+//         reciprocal gives it exactly);
+//   C_6 = sum of e3 f3 with |e3|, |f3| <= 2 is below 4k < 2^18;
+//   s   = lo + rm (2^24 mod p) + C_6 (2^48 mod p), the weights balanced:
+//         |s| < 2^48 + 2^50 + 2^43 < 2^53 (exact);
+//   r   = s - rint(s/p) p: the quotient can be off by one only when s mod p
+//         lies next to +-p/2, and then r lands in (-p, 0) or (0, p) so that
+//         adding p to a negative r still gives s mod p in [0, p).
+__device__ __forceinline__ uint32_t recombine(int c0, int c1, int c2, int c3, int c4, int c5, int c6,
+                                              const PrimeConst &pr) {
+    const double lo = fma((double)c2, 65536.0, fma((double)c1, 256.0, (double)c0));
+    const double mid = fma((double)c5, 65536.0, fma((double)c4, 256.0, (double)c3));
+    const double rm = fma(-rint(mid * pr.pinv), pr.pf, mid);
+    const double sum = fma((double)c6, pr.w[6], fma(rm, pr.w[3], lo));
+    double r = fma(-rint(sum * pr.pinv), pr.pf, sum);
+    r = r < 0.0 ? r + pr.pf : r;
+    return (uint32_t)r;
+}
 
 // ------------------------------------------------------------- INT8 GEMM --
 
@@ -96,7 +118,6 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const GemmProblem *__restrict__
         }
     }
 
-    // Epilogue: C = sum_s (C_s mod p) * w_s mod p, all in exact doubles.
     const PrimeConst pr = pc[g.prime_begin + tc.plane];
     uint32_t *C = g.C + (int64_t)tc.plane * g.cps;
 #pragma unroll
@@ -105,18 +126,11 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const GemmProblem *__restrict__
         for (int j = 0; j < kI8WaveCB; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double sum = 0.0;
-#pragma unroll
-                for (int s = 0; s < 7; ++s) {
-                    const double cs = (double)acc[s][i][j][v];
-                    const double r = fma(-rint(cs * pr.pinv), pr.pf, cs);   // |r| <= p/2
-                    sum = fma(r, pr.w[s], sum);                              // |sum| < 7*2^50
-                }
-                double r = fma(-rint(sum * pr.pinv), pr.pf, sum);
-                r = r < 0.0 ? r + pr.pf : r;
+                const uint32_t r = recombine(acc[0][i][j][v], acc[1][i][j][v], acc[2][i][j][v], acc[3][i][j][v],
+                                             acc[4][i][j][v], acc[5][i][j][v], acc[6][i][j][v], pr);
                 const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + v;
                 const int col = (cb0 + j) * 16 + (lane & 15);
-                if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, (uint32_t)r, pr.p, g.sub);
+                if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, r, pr.p, g.sub);
             }
 }
 
@@ -238,18 +252,11 @@ __device__ __forceinline__ void i8_lds_tile(const GemmProblem &g, int plane, int
         for (int j = 0; j < S::kCB; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double sum = 0.0;
-#pragma unroll
-                for (int s = 0; s < 7; ++s) {
-                    const double cs = (double)acc[s][i][j][v];
-                    const double r = fma(-rint(cs * pr.pinv), pr.pf, cs);   // |r| <= p/2
-                    sum = fma(r, pr.w[s], sum);                              // |sum| < 7*2^50
-                }
-                double r = fma(-rint(sum * pr.pinv), pr.pf, sum);
-                r = r < 0.0 ? r + pr.pf : r;
+                const uint32_t r = recombine(acc[0][i][j][v], acc[1][i][j][v], acc[2][i][j][v], acc[3][i][j][v],
+                                             acc[4][i][j][v], acc[5][i][j][v], acc[6][i][j][v], pr);
                 const int row = (rblk0 + wy * S::kRB + i) * 16 + 4 * (lane >> 4) + v;
                 const int col = (cblk0 + wx * S::kCB + j) * 16 + (lane & 15);
-                if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, (uint32_t)r, pr.p, g.sub);
+                if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, r, pr.p, g.sub);
             }
 }
 

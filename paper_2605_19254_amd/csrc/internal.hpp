@@ -135,6 +135,19 @@ struct ProfScope {
 };
 
 int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **out);
+
+// A gemm plan whose operands are int64 matrices (row-major A m x k, B k x n,
+// one per descriptor; the descriptors' A and B residue pointers are unused):
+// its conversion kernel reduces them mod every prime of the problem straight
+// into the tiled operand layouts.
+struct GemmInt64Src {
+    const int64_t *A;
+    int64_t lda;
+    const int64_t *B;
+    int64_t ldb;
+};
+int gemm_plan_create_int64(rns_ctx *ctx, const rns_gemm_desc *descs, const GemmInt64Src *src, int count,
+                           int path, rns_gemm_plan **out);
 int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out);
 
 }  // namespace rns

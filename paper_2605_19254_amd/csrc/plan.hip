@@ -1,6 +1,8 @@
-// Whole-product plans: reduce -> per-prime products -> CRT for a batch of
-// independent integer products (Section 3.1 end to end), with the residue
-// planes of every operand and result resident in a plan-owned buffer.
+// Whole-product plans: int64 A and B -> per-prime products -> CRT for a batch
+// of independent integer products (Section 3.1 end to end).  The conversion
+// kernel of the plan's gemm plan reduces A and B straight into the tiled
+// operand layouts (no residue planes of A and B are written); the residue
+// planes of every C stay resident in a plan-owned buffer for the CRT.
 #include "reduce_crt.hpp"
 
 #include <algorithm>
@@ -15,9 +17,6 @@ struct rns_matmul_plan {
     int crt_E = 1;              // CRT entries per thread (the same for every job)
     bool fast_crt = false;
     void *d_planes = nullptr;
-    ReduceJob *d_rjobs = nullptr;
-    int nr = 0;
-    int64_t rtiles = 0;
     CrtJob *d_cjobs = nullptr;
     int nc = 0;
     int64_t ctiles = 0;
@@ -30,7 +29,6 @@ extern "C" void rns_matmul_plan_destroy(rns_matmul_plan *p) {
     (void)hipDeviceSynchronize();
     if (p->gemm) rns_gemm_plan_destroy(p->gemm);
     if (p->d_planes) (void)hipFree(p->d_planes);
-    if (p->d_rjobs) (void)hipFree(p->d_rjobs);
     if (p->d_cjobs) (void)hipFree(p->d_cjobs);
     delete p;
 }
@@ -40,8 +38,8 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
     if (!ctx || !out || count < 0 || (count > 0 && !d)) return RNS_EINVAL;
     if (W < 1 || W > kCrtMaxW) return RNS_EINVAL;
     *out = nullptr;
-    // Validate and lay out the resident planes.
-    std::vector<size_t> offA(count), offB(count), offC(count);
+    // Validate and lay out the resident C planes.
+    std::vector<size_t> offC(count);
     size_t off = 0;
     bool all_fast = count > 0;
     int max_L = 1;
@@ -54,14 +52,8 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
             if (!x.C || x.ldc < x.n) return RNS_EINVAL;
             if (x.k > 0 && (!x.A || !x.B || x.lda < x.k || x.ldb < x.n)) return RNS_EINVAL;
         }
-        auto take = [&](int64_t r, int64_t c) {
-            const size_t at = off;
-            off += ((size_t)x.L * r * c * sizeof(uint32_t) + 255) & ~(size_t)255;
-            return at;
-        };
-        offA[i] = take(x.m, x.k);
-        offB[i] = take(x.k, x.n);
-        offC[i] = take(x.m, x.n);
+        offC[i] = off;
+        off += ((size_t)x.L * x.m * x.n * sizeof(uint32_t) + 255) & ~(size_t)255;
         if (!(x.bound > 0 && crt_fast_ok(ctx, x.prime_begin, x.L, &x.bound, 1, W))) all_fast = false;
         max_L = std::max(max_L, x.L);
     }
@@ -76,36 +68,22 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
     if (hipMalloc(&p->d_planes, std::max<size_t>(off, 256)) != hipSuccess) return fail(RNS_ENOMEM);
     char *base = static_cast<char *>(p->d_planes);
 
-    std::vector<ReduceJob> rj;
     std::vector<rns_gemm_desc> gd;
+    std::vector<GemmInt64Src> src;
     std::vector<CrtJob> cj;
-    int64_t rt = 0, ct = 0;
+    int64_t ct = 0;
     for (int i = 0; i < count; ++i) {
         const rns_matmul_desc &x = d[i];
         if (x.m == 0 || x.n == 0) continue;
-        uint32_t *A = reinterpret_cast<uint32_t *>(base + offA[i]);
-        uint32_t *B = reinterpret_cast<uint32_t *>(base + offB[i]);
         uint32_t *C = reinterpret_cast<uint32_t *>(base + offC[i]);
-        // A contiguous matrix is one row of rows*cols entries for the reduce
-        // and CRT jobs, so that small problems fill whole tiles.
-        auto reduce_job = [&](const int64_t *src, int64_t rows, int64_t cols, int64_t ld, uint32_t *dst) {
-            const bool flat = ld == cols;
-            ReduceJob j = make_reduce_job(src, flat ? 1 : rows, flat ? rows * cols : cols, flat ? rows * cols : ld,
-                                          x.prime_begin, x.L, dst, flat ? rows * cols : cols, rows * cols, rt);
-            rt += reduce_tiles(j);
-            rj.push_back(j);
-        };
-        if (x.k > 0) {
-            reduce_job(x.A, x.m, x.k, x.lda, A);
-            reduce_job(x.B, x.k, x.n, x.ldb, B);
-        }
         rns_gemm_desc g{};
         g.m = x.m; g.n = x.n; g.k = x.k;
-        g.A = A; g.lda = std::max<int64_t>(x.k, 1); g.a_plane_stride = x.m * x.k;
-        g.B = B; g.ldb = x.n; g.b_plane_stride = x.k * x.n;
         g.C = C; g.ldc = x.n; g.c_plane_stride = x.m * x.n;
         g.prime_begin = x.prime_begin; g.L = x.L;
         gd.push_back(g);
+        src.push_back(GemmInt64Src{x.A, x.lda, x.B, x.ldb});
+        // A contiguous C is one row of m*n entries for the CRT, so that
+        // small problems fill whole tiles.
         CrtJob c{};
         const bool cflat = x.ldc == x.n;
         c.res = C; c.rows = cflat ? 1 : x.m; c.cols = cflat ? x.m * x.n : x.n;
@@ -130,17 +108,10 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
         }
         cj.push_back(c);
     }
-    int st = rns_gemm_plan_create(ctx, gd.data(), (int)gd.size(), path, &p->gemm);
+    int st = gemm_plan_create_int64(ctx, gd.data(), src.data(), (int)gd.size(), path, &p->gemm);
     if (st != RNS_OK) return fail(st);
-    p->nr = (int)rj.size();
-    p->rtiles = rt;
     p->nc = (int)cj.size();
     p->ctiles = ct;
-    if (p->nr) {
-        if (hipMalloc(&p->d_rjobs, sizeof(ReduceJob) * p->nr) != hipSuccess) return fail(RNS_ENOMEM);
-        if (hipMemcpy(p->d_rjobs, rj.data(), sizeof(ReduceJob) * p->nr, hipMemcpyHostToDevice) != hipSuccess)
-            return fail(RNS_EDEVICE);
-    }
     if (p->nc) {
         if (hipMalloc(&p->d_cjobs, sizeof(CrtJob) * p->nc) != hipSuccess) return fail(RNS_ENOMEM);
         if (hipMemcpy(p->d_cjobs, cj.data(), sizeof(CrtJob) * p->nc, hipMemcpyHostToDevice) != hipSuccess)
@@ -155,11 +126,6 @@ extern "C" int rns_matmul_plan_execute(rns_matmul_plan *p, void *stream) {
     rns_ctx *ctx = p->ctx;
     hipStream_t s = (hipStream_t)stream;
     RNS_HIP(hipSetDevice(ctx->device));
-    if (p->nr) {
-        ProfScope ps(ctx, "k_reduce", s);
-        launch_reduce(ReduceJob{}, p->d_rjobs, p->nr, p->rtiles, ctx->d_prime, s);
-    }
-    RNS_HIP(hipGetLastError());
     int st = rns_gemm_plan_execute(p->gemm, stream);
     if (st != RNS_OK) return st;
     if (p->nc) {

@@ -35,6 +35,34 @@ struct CrtJob {
     int64_t tile_begin;
 };
 
+// Tiles [t0, t1) of a launch, job by job: body(J, t) for every tile t, with J
+// the job that holds t (job0 when there is no table).  The job index is the
+// same on every lane, so the job's fields come through scalar loads, once per
+// job that the range touches.
+template <class Job, class Body>
+__device__ __forceinline__ void for_job_tiles(const Job &job0, const Job *__restrict__ jobs, int njobs,
+                                              int64_t total_tiles, int64_t t0, int64_t t1, Body &&body) {
+    if (njobs <= 0) {
+        for (int64_t t = t0; t < t1; ++t) body(job0, t);
+        return;
+    }
+    int lo = 0, hi = njobs - 1;                     // last job starting at or before t0
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_begin <= t0) lo = mid; else hi = mid - 1;
+    }
+    int q = lo;
+    int64_t t = t0;
+    while (t < t1 && q < njobs) {
+        q = __builtin_amdgcn_readfirstlane(q);
+        const Job J = jobs[q];
+        const int64_t end = q + 1 < njobs ? jobs[q + 1].tile_begin : total_tiles;
+        const int64_t te = end < t1 ? end : t1;
+        for (; t < te; ++t) body(J, t);
+        ++q;
+    }
+}
+
 int reduce_check(const rns_ctx *ctx, const int64_t *x, int64_t rows, int64_t cols, int64_t ldx,
                  int prime_begin, int L, const uint32_t *res, int64_t ldr, int64_t plane_stride);
 ReduceJob make_reduce_job(const int64_t *x, int64_t rows, int64_t cols, int64_t ldx,

@@ -142,6 +142,45 @@ def test_matmul_plan_uneven_batch(ctx, rg, torch_dev, with_bound):
     p1.close()
 
 
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_matmul_plan_full_range_int64(ctx, rg, torch_dev, path):
+    """Whole-product plans convert int64 operands straight into the tiled
+    layouts: entries across the whole int64 range (the extremes included),
+    strided A and B, tiles cut by the matrix edges, exact CRT into 3 words;
+    every entry against the oracle's Python-integer product."""
+    torch, dev = torch_dev
+    _say("matmul plan full-range int64", path)
+    rng = np.random.default_rng(97)
+    lim = np.iinfo(np.int64)
+    special = np.array([lim.min, lim.max, 0, -1, 1, lim.min + 1, lim.max - 1, 1 << 42, -(1 << 42),
+                        (1 << 21) - 1, -(1 << 21)], dtype=np.int64)
+    probs, hosts = [], []
+    for i, (m, k, n) in enumerate([(40, 70, 30), (17, 130, 65), (64, 64, 128), (1, 3, 1)]):
+        a = rng.integers(lim.min, lim.max, size=(m, k), dtype=np.int64, endpoint=True)
+        b = rng.integers(lim.min, lim.max, size=(k, n), dtype=np.int64, endpoint=True)
+        ma = rng.random((m, k)) < 0.2
+        a[ma] = rng.choice(special, size=int(ma.sum()))
+        mb = rng.random((k, n)) < 0.2
+        b[mb] = rng.choice(special, size=int(mb.sum()))
+        Abig = torch.zeros((m, k + 3), dtype=torch.int64, device=dev)
+        Bbig = torch.zeros((k, n + 5), dtype=torch.int64, device=dev)
+        Abig[:, :k] = torch.from_numpy(a).to(dev)
+        Bbig[:, :n] = torch.from_numpy(b).to(dev)
+        C = torch.empty((m, n, 3), dtype=torch.int64, device=dev)
+        # |C| <= k 2^126 < 2^134: 6 primes below 2^26 give 155 bits
+        probs.append(rg.MatmulProblem(Abig[:, :k], Bbig[:, :n], C, prime_begin=2 * i, L=6))
+        hosts.append((a, b))
+    plan = rg.MatmulPlan(ctx, probs, path=path, W=3)
+    plan.execute()
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for (a, b), p in zip(hosts, probs):
+        got = rg.words_to_ints(p.C.cpu().numpy())
+        want = a.astype(object).dot(b.astype(object))
+        assert np.array_equal(got, want)
+    plan.close()
+
+
 def test_matmul_plan_graph_replay(ctx, rg, torch_dev):
     """Capture the whole product (reduce, prep, GEMM, CRT) into a HIP graph and
     replay it several times with eager work in between; every replay must equal

@@ -99,6 +99,55 @@ def test_reduce_strided_and_empty(ctx, rg, torch_dev):
     assert rg.rns_reduce(ctx, e, L=3).shape == (3, 0, 5)
 
 
+@pytest.mark.parametrize("W", [1, 2, 5, 10, 32])
+def test_reduce_multiword(ctx, rg, torch_dev, W):
+    """rns_reduce_mw against the oracle's residues of the Python integers
+    (random words plus the extremes of the W-word range), a strided view,
+    and the round trip through crt_reconstruct where the 26 primes cover the
+    W-word range (W <= 10); W = 1 agrees with rns_reduce."""
+    torch, dev = torch_dev
+    _say("reduce multiword", W)
+    rng = np.random.default_rng(100 + W)
+    rows, cols, extra = 19, 70, 3
+    words = rng.integers(0, 1 << 64, size=(rows, cols + extra, W), dtype=np.uint64)
+    lim = 1 << (64 * W - 1)
+    special = [v for v in (-lim, lim - 1, 0, -1, 1, -(lim // 2), (1 << 64) - 1, -(1 << 64)) if -lim <= v < lim]
+    for idx, v in enumerate(special):
+        words[idx % rows, idx, :] = np.array(orns.to_words(v, W), dtype=np.uint64)
+    words[rows - 1, cols - 1, :] = np.array(orns.to_words(-lim, W), dtype=np.uint64)   # last entry of the view
+    x = torch.from_numpy(words.view(np.int64)).to(dev)[:, :cols, :]
+    res = rg.rns_reduce_mw(ctx, x, L=26)
+    torch.cuda.synchronize()
+    got = res.cpu().numpy()
+    ints = [[orns.from_words([int(w) for w in words[i, c]]) for c in range(cols)] for i in range(rows)]
+    for j, p in enumerate(PRIMES):
+        want = np.array([[v % p for v in row] for row in ints], dtype=np.int64)
+        assert np.array_equal(got[j].astype(np.int64), want), j
+    if W <= 10:
+        back = rg.crt_reconstruct(ctx, res, L=26, W=W)
+        assert np.array_equal(back.cpu().numpy().reshape(rows, cols, W).view(np.uint64), words[:, :cols, :])
+    if W == 1:
+        x1 = x[:, :, 0]
+        assert torch.equal(rg.rns_reduce(ctx, x1, L=26), res)
+    assert ctx.status() == 0
+
+
+def test_reduce_multiword_errors(ctx, rg, torch_dev):
+    import ctypes
+    from paper_2605_19254_amd import binding
+    torch, dev = torch_dev
+    _say("reduce multiword errors")
+    x = torch.zeros((2, 3, 33), dtype=torch.int64, device=dev)
+    out = torch.empty((1, 2, 3), dtype=torch.int32, device=dev)
+    for W in (0, 33):
+        assert binding._lib_reduce_mw(ctx.handle, x.data_ptr(), W, 2, 3, 3, 0, 1, out.data_ptr(), 3, 6,
+                                      None) == binding.EINVAL
+    assert binding._lib_reduce_mw(ctx.handle, x.data_ptr(), 2, 2, 3, 3, 25, 2, out.data_ptr(), 3, 6,
+                                  None) == binding.EINVAL          # primes past the basis
+    assert binding._lib_reduce_mw(ctx.handle, x.data_ptr(), 2, 0, 3, 3, 0, 1, out.data_ptr(), 3, 6,
+                                  None) == binding.OK              # empty is a no-op
+
+
 # --------------------------------------------------------------- modmatmul --
 
 SHAPES = [(1, 1, 1), (1, 5, 1), (16, 16, 64), (17, 33, 70), (64, 128, 64), (65, 129, 65),
