@@ -473,37 +473,46 @@ struct Driver {
             if (m >= 17179869184.0) gpu = false;   // 2^34
         }
         g.assign(n, BigInt(1));
-        if (gpu) {
-            DevBuf<uint64_t> dm, part;
+        if (gpu && !fac.empty()) {
+            // Every prime power of s in one elimination: plane f is X mod q_f^e_f.
+            const int F = (int)fac.size();
+            DevBuf<uint64_t> dm, dkey;
             DevBuf<int32_t> dval;
-            DRV_ST(dm.alloc((size_t)n * n));
-            const int nparts = 512;
-            DRV_ST(part.alloc(nparts));
-            DRV_ST(dval.alloc(n));
-            std::vector<int32_t> val(n);
-            for (auto &f : fac) {
-                LocalMod lm;
-                lm.q = f.first;
-                lm.e = f.second;
+            DevBuf<LocalMod> dlm;
+            DRV_ST(dm.alloc((size_t)F * n * n));
+            DRV_ST(dkey.alloc((size_t)F * (n + 1)));
+            DRV_ST(dval.alloc((size_t)F * n));
+            DRV_ST(dlm.alloc((size_t)F));
+            std::vector<LocalMod> lms(F);
+            for (int f = 0; f < F; ++f) {
+                LocalMod &lm = lms[f];
+                lm.q = fac[f].first;
+                lm.e = fac[f].second;
                 lm.m = 1;
-                for (int t = 0; t < f.second; ++t) lm.m *= f.first;
+                for (int t = 0; t < lm.e; ++t) lm.m *= lm.q;
                 lm.mf = (double)lm.m;
                 lm.minv = 1.0 / lm.mf;
                 lm.pow64w = powmod_u64(2, 64ull * Wx, lm.m);
-                launch_words_mod_m(dX.p, n * n, Wx, lm, dm.p, stream);
-                for (int k = 0; k < n; ++k) launch_loc_step(dm.p, n, k, lm, part.p, nparts, dval.p, stream);
-                DRV_HIP(hipGetLastError());
-                DRV_HIP(hipMemcpyAsync(val.data(), dval.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream));
-                DRV_ST(sync());
+                launch_words_mod_m(dX.p, n * n, Wx, lm, dm.p + (size_t)f * n * n, stream);
+            }
+            DRV_HIP(hipMemcpyAsync(dlm.p, lms.data(), sizeof(LocalMod) * F, hipMemcpyHostToDevice, stream));
+            DRV_HIP(hipMemsetAsync(dkey.p, 0xFF, sizeof(uint64_t) * F * (n + 1), stream));
+            launch_loc_init(dm.p, n, dlm.p, F, dkey.p, stream);
+            for (int k = 0; k < n; ++k) launch_loc_step(dm.p, n, k, dlm.p, F, dkey.p, dval.p, stream);
+            DRV_HIP(hipGetLastError());
+            std::vector<int32_t> val((size_t)F * n);
+            DRV_HIP(hipMemcpyAsync(val.data(), dval.p, sizeof(int32_t) * val.size(), hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+            for (int f = 0; f < F; ++f) {
                 // Once the remainder is zero mod q^e the later steps record e.
                 bool zero = false;
                 for (int64_t i = 0; i < n; ++i) {
-                    int v = zero ? f.second : std::min(val[i], f.second);
-                    if (v >= f.second) zero = true;
-                    for (int t = 0; t < v; ++t) g[i] = g[i].mul_small(f.first);
+                    int v = zero ? lms[f].e : std::min(val[(size_t)f * n + i], lms[f].e);
+                    if (v >= lms[f].e) zero = true;
+                    for (int t = 0; t < v; ++t) g[i] = g[i].mul_small(lms[f].q);
                 }
             }
-        } else {
+        } else if (!gpu) {
             std::vector<uint64_t> hx((size_t)n * n * Wx);
             DRV_HIP(hipMemcpyAsync(hx.data(), dX.p, sizeof(uint64_t) * hx.size(), hipMemcpyDeviceToHost, stream));
             DRV_ST(sync());

@@ -489,28 +489,44 @@ __global__ __launch_bounds__(256) void k_words_mod_m(const uint64_t *__restrict_
     out[e] = r;
 }
 
-// Step k, pass 1: minimal valuation over rows k..n-1, columns k..n-1.  Each
-// block reduces its share into part[block] = (valuation << 40) | flat index.
-__global__ __launch_bounds__(256) void k_loc_min(const uint64_t *__restrict__ M, int64_t n, int k,
-                                                 LocalMod lm, uint64_t *__restrict__ part) {
-    const int64_t w = n - k;
-    const int64_t total = w * w;
-    uint64_t best = ~0ull;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = k + t / w, j = k + t % w;
-        const int v = valuation(M[i * n + j], lm.q, lm.e);
-        const uint64_t key = ((uint64_t)v << 40) | (uint64_t)(i * n + j);
-        best = key < best ? key : best;
-    }
+// The F prime powers q^e of s are eliminated together: plane f of M
+// ([F][n][n]) holds X mod lms[f].m, and step k of every plane runs in the
+// same two launches.  The pivot of step k is the entry of least valuation in
+// rows and columns k..n-1 (the smallest key (valuation << 40) | flat index);
+// the keys of step k+1 are gathered by step k's elimination, which visits
+// exactly that region, with one 64-bit atomicMin per block into key[f][k+1]
+// (every key starts at ~0).
+
+__device__ __forceinline__ uint64_t loc_key(uint64_t x, const LocalMod &lm, int64_t flat) {
+    return ((uint64_t)valuation(x, lm.q, lm.e) << 40) | (uint64_t)flat;
+}
+
+// Block minimum of one key per thread (every thread of the block calls it),
+// then one atomicMin into *dst.
+__device__ __forceinline__ void block_min_to(uint64_t key, uint64_t *dst) {
     __shared__ uint64_t red[256];
-    red[threadIdx.x] = best;
+    red[threadIdx.x] = key;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s && red[threadIdx.x + s] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0 && red[0] != ~0ull)
+        atomicMin(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)red[0]);
+}
+
+// Keys of step 0: the whole of every plane.  Grid (blocks, F).
+__global__ __launch_bounds__(256) void k_loc_init(const uint64_t *__restrict__ M, int64_t n,
+                                                  const LocalMod *__restrict__ lms, uint64_t *__restrict__ key) {
+    const int f = blockIdx.y;
+    const LocalMod lm = lms[f];
+    const uint64_t *Mf = M + (int64_t)f * n * n;
+    uint64_t best = ~0ull;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * n; t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t kk = loc_key(Mf[t], lm, t);
+        best = kk < best ? kk : best;
+    }
+    block_min_to(best, key + (int64_t)f * (n + 1));
 }
 
 __device__ uint64_t inv_unit(uint64_t u, uint64_t m) {   // u a unit mod m (m < 2^34)
@@ -528,67 +544,78 @@ __device__ uint64_t inv_unit(uint64_t u, uint64_t m) {   // u a unit mod m (m < 
     return (uint64_t)(t0 < 0 ? t0 + (int64_t)m : t0);
 }
 
-// Step k, pass 2 (one block): reduce the partial minima, record the
-// valuation, swap the pivot into (k, k), and scale row k by the inverse of
-// the pivot's unit part so that the pivot becomes q^v.
+// Step k, pivot (one block per plane): record the valuation, swap the pivot
+// into (k, k), and scale row k by the inverse of the pivot's unit part so that
+// the pivot becomes q^v.  Grid (1, F).
 __global__ __launch_bounds__(256) void k_loc_pivot(uint64_t *__restrict__ M, int64_t n, int k,
-                                                   LocalMod lm, const uint64_t *__restrict__ part,
-                                                   int nparts, int32_t *__restrict__ val) {
-    __shared__ uint64_t red[256];
-    uint64_t best = ~0ull;
-    for (int t = threadIdx.x; t < nparts; t += blockDim.x) best = part[t] < best ? part[t] : best;
-    red[threadIdx.x] = best;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s && red[threadIdx.x + s] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
-        __syncthreads();
-    }
-    const uint64_t key = red[0];
-    const int v = (int)(key >> 40);
+                                                   const LocalMod *__restrict__ lms,
+                                                   const uint64_t *__restrict__ keys, int32_t *__restrict__ val) {
+    const int f = blockIdx.y;
+    const LocalMod lm = lms[f];
+    uint64_t *Mf = M + (int64_t)f * n * n;
+    const uint64_t key = keys[(int64_t)f * (n + 1) + k];
+    const int v = key == ~0ull ? lm.e : (int)(key >> 40);
+    if (threadIdx.x == 0) val[(int64_t)f * n + k] = v;
+    if (v >= lm.e) return;                  // the rest is 0 mod m
     const int64_t flat = (int64_t)(key & ((1ull << 40) - 1));
     const int64_t r = flat / n, c = flat % n;
-    if (threadIdx.x == 0) val[k] = v;
-    if (v >= lm.e) return;                  // the rest is 0 mod m
-    // swap rows k, r and columns k, c
     if (r != k)
         for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-            const uint64_t t = M[(int64_t)k * n + j];
-            M[(int64_t)k * n + j] = M[r * n + j];
-            M[r * n + j] = t;
+            const uint64_t t = Mf[(int64_t)k * n + j];
+            Mf[(int64_t)k * n + j] = Mf[r * n + j];
+            Mf[r * n + j] = t;
         }
     __syncthreads();
     if (c != k)
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint64_t t = M[i * n + k];
-            M[i * n + k] = M[i * n + c];
-            M[i * n + c] = t;
+            const uint64_t t = Mf[i * n + k];
+            Mf[i * n + k] = Mf[i * n + c];
+            Mf[i * n + c] = t;
         }
     __syncthreads();
     __shared__ uint64_t uinv;
     if (threadIdx.x == 0) {
-        uint64_t piv = M[(int64_t)k * n + k];
+        uint64_t piv = Mf[(int64_t)k * n + k];
         for (int t = 0; t < v; ++t) piv /= lm.q;
         uinv = inv_unit(piv % lm.m, lm.m);
     }
     __syncthreads();
     for (int64_t j = k + threadIdx.x; j < n; j += blockDim.x)
-        M[(int64_t)k * n + j] = mulmod_m(M[(int64_t)k * n + j], uinv, lm.mf, lm.minv);
+        Mf[(int64_t)k * n + j] = mulmod_m(Mf[(int64_t)k * n + j], uinv, lm.mf, lm.minv);
 }
 
-// Step k, pass 3: rows i > k: row_i -= (M[i][k] / q^v) row_k on columns > k.
+// Step k, elimination: rows i > k, row_i -= (M[i][k] / q^v) row_k on columns
+// > k, and the keys of the updated region into key[f][k+1].  A block covers
+// 256 columns of kLocRows rows.  Grid (column blocks, row groups, F).
+constexpr int kLocRows = 8;
+
 __global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int64_t n, int k,
-                                                  LocalMod lm, const int32_t *__restrict__ val) {
-    const int v = val[k];
-    if (v >= lm.e) return;
-    const int64_t i = k + 1 + (int64_t)blockIdx.y;
+                                                  const LocalMod *__restrict__ lms, const int32_t *__restrict__ val,
+                                                  uint64_t *__restrict__ keys) {
+    const int f = blockIdx.z;
+    const LocalMod lm = lms[f];
+    const int v = val[(int64_t)f * n + k];
+    if (v >= lm.e) return;                  // uniform over the block
+    uint64_t *Mf = M + (int64_t)f * n * n;
     const int64_t j = k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || j >= n) return;
-    uint64_t f = M[i * n + k];
-    if (f == 0) return;
-    for (int t = 0; t < v; ++t) f /= lm.q;
-    const uint64_t d = mulmod_m(f % lm.m, M[(int64_t)k * n + j], lm.mf, lm.minv);
-    const uint64_t a = M[i * n + j];
-    M[i * n + j] = a >= d ? a - d : a + lm.m - d;
+    const bool colv = j < n;
+    const uint64_t pk = colv ? Mf[(int64_t)k * n + j] : 0;
+    uint64_t best = ~0ull;
+    for (int rr = 0; rr < kLocRows; ++rr) {
+        const int64_t i = k + 1 + (int64_t)blockIdx.y * kLocRows + rr;
+        if (i >= n || !colv) continue;
+        uint64_t fct = Mf[i * n + k];
+        uint64_t a = Mf[i * n + j];
+        if (fct != 0) {
+            for (int t = 0; t < v; ++t) fct /= lm.q;
+            const uint64_t d = mulmod_m(fct % lm.m, pk, lm.mf, lm.minv);
+            a = a >= d ? a - d : a + lm.m - d;
+            Mf[i * n + j] = a;
+        }
+        const uint64_t kk = loc_key(a, lm, i * n + j);
+        best = kk < best ? kk : best;
+    }
+    block_min_to(best, keys + (int64_t)f * (n + 1) + k + 1);
 }
 
 }  // namespace
@@ -676,14 +703,18 @@ void launch_words_mod_m(const uint64_t *x, int64_t count, int W, const LocalMod 
                        W, lm, out);
 }
 
-void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod &lm, uint64_t *part, int nparts,
-                     int32_t *val, hipStream_t s) {
-    hipLaunchKernelGGL(k_loc_min, dim3((unsigned)nparts), dim3(256), 0, s, M, n, k, lm, part);
-    hipLaunchKernelGGL(k_loc_pivot, dim3(1), dim3(256), 0, s, M, n, k, lm, part, nparts, val);
+void launch_loc_init(const uint64_t *M, int64_t n, const LocalMod *lms, int F, uint64_t *keys, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>((n * n + 255) / 256, 512);
+    hipLaunchKernelGGL(k_loc_init, dim3((unsigned)blocks, (unsigned)F), dim3(256), 0, s, M, n, lms, keys);
+}
+
+void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod *lms, int F, uint64_t *keys, int32_t *val,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_loc_pivot, dim3(1, (unsigned)F), dim3(256), 0, s, M, n, k, lms, keys, val);
     const int64_t w = n - k - 1;
     if (w <= 0) return;
-    dim3 grid((unsigned)((w + 255) / 256), (unsigned)w);
-    hipLaunchKernelGGL(k_loc_elim, grid, dim3(256), 0, s, M, n, k, lm, val);
+    dim3 grid((unsigned)((w + 255) / 256), (unsigned)((w + kLocRows - 1) / kLocRows), (unsigned)F);
+    hipLaunchKernelGGL(k_loc_elim, grid, dim3(256), 0, s, M, n, k, lms, val, keys);
 }
 
 }  // namespace rns
