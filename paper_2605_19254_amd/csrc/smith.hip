@@ -592,8 +592,10 @@ struct Driver {
     }
 
     // --------------------------------------------------- p-adic lifting --
-    int64_t ldl = 0;            // padded row stride of the lifting operands (multiple of 4)
+    int64_t ldl = 0;            // padded row stride of the lifting operands (multiple of 8)
     DevBuf<int32_t> dA32;       // A as int32, [n][ldl], zero beyond column n
+    DevBuf<int16_t> dA16;       // the same as int16 when every |a| < 2^15 (then dA32 is unused)
+    int a_bytes = 4;
     DevBuf<uint32_t> dG;        // [n][2n] Gauss-Jordan of the lifting prime; right half = C
     DevBuf<uint32_t> dC;        // C = A^-1 mod p, [n][ldl], zero beyond column n
     DevBuf<uint32_t> dXh;       // lifted digits [K][t][n]
@@ -605,15 +607,30 @@ struct Driver {
     DevBuf<uint32_t> ddet;
     bool cert_exact = true;
 
-    // A as int32 rows of stride ldl (zero padded) for the lifting kernels.
+    // A as int16 (every |a| < 2^15) or int32 rows of stride ldl (zero padded)
+    // for the lifting kernels.
     int upload_a32() {
-        ldl = (n + 3) / 4 * 4;
-        std::vector<int32_t> a32((size_t)n * ldl, 0);
-        for (int64_t i = 0; i < n; ++i)
-            for (int64_t j = 0; j < n; ++j) a32[(size_t)i * ldl + j] = (int32_t)A[i * n + j];
-        DRV_ST(dA32.alloc(a32.size()));
-        DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice, stream));
-        DRV_ST(sync());                                  // the host vector goes out of scope
+        ldl = (n + 7) / 8 * 8;
+        bool narrow = true;
+        for (int64_t e = 0; e < n * n && narrow; ++e) narrow = A[e] > -(1 << 15) && A[e] < (1 << 15);
+        a_bytes = narrow ? 2 : 4;
+        if (a_bytes == 2) {
+            std::vector<int16_t> a16((size_t)n * ldl, 0);
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t j = 0; j < n; ++j) a16[(size_t)i * ldl + j] = (int16_t)A[i * n + j];
+            DRV_ST(dA16.alloc(a16.size()));
+            DRV_HIP(hipMemcpyAsync(dA16.p, a16.data(), sizeof(int16_t) * a16.size(), hipMemcpyHostToDevice,
+                                   stream));
+            DRV_ST(sync());                              // the host vector goes out of scope
+        } else {
+            std::vector<int32_t> a32((size_t)n * ldl, 0);
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t j = 0; j < n; ++j) a32[(size_t)i * ldl + j] = (int32_t)A[i * n + j];
+            DRV_ST(dA32.alloc(a32.size()));
+            DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice,
+                                   stream));
+            DRV_ST(sync());
+        }
         return RNS_OK;
     }
 
@@ -733,7 +750,8 @@ struct Driver {
         for (;;) {
             K_chk = std::min(K_chk, Kmax);
             for (int64_t i = K_done; i < K_chk; ++i) {
-                launch_lift_step(dC.p, dA32.p, n, ldl, t, p, Rm[cur], R[cur], dXh.p + i * t * ldl,
+                launch_lift_step(dC.p, a_bytes == 2 ? (const void *)dA16.p : (const void *)dA32.p, a_bytes, n, ldl,
+                                 t, p, Rm[cur], R[cur], dXh.p + i * t * ldl,
                                  R[1 - cur], Rm[1 - cur], derr.p, stream);
                 cur ^= 1;
             }

@@ -37,11 +37,11 @@ void launch_gj_pivoted(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, c
                        uint32_t *S, int32_t *piv, int32_t *singular, int32_t *need, uint32_t *det, uint32_t *W,
                        hipStream_t s);
 // One step of p-adic lifting for t <= 16 right-hand sides and the
-// projections of stored digits.  C (n x n mod p) and A (n x n int32) have
-// row stride ld, a multiple of 4, and are zero in columns n..ld-1; R, Rm and
-// X hold t vectors of stride ld ([t][ld]).
+// projections of stored digits.  C (n x n mod p) and A (n x n, int32 or,
+// with a_bytes = 2, int16) have row stride ld, a multiple of 8, and are zero
+// in columns n..ld-1; R, Rm and X hold t vectors of stride ld ([t][ld]).
 constexpr int kLiftMaxCols = 16;
-void launch_lift_step(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
+void launch_lift_step(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
                       const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                       int32_t *err, hipStream_t s);
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,

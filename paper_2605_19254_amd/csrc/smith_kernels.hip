@@ -299,17 +299,34 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
 // The host admits this form only when n max|a| p < 2^62, so every sum fits in
 // an int64.  A division that is not exact (impossible for a correct C) sets
 // *err instead of producing a wrong residual silently.  X beyond row n is
-// never written; A's zero columns make its value irrelevant.
-template <int T, int kLiftRows>
-__global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, int64_t n, int64_t ld,
+// never written; A's zero columns make its value irrelevant.  A is int32, or
+// int16 when every |a| < 2^15 (a quarter less traffic per step); either way
+// one 16-byte load per lane and step of the loop.
+template <typename AT>
+__device__ __forceinline__ void unpack_a(const int4 raw, int32_t (&a)[16 / sizeof(AT)]) {
+    if constexpr (sizeof(AT) == 4) {
+        a[0] = raw.x; a[1] = raw.y; a[2] = raw.z; a[3] = raw.w;
+    } else {
+        const int32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            a[2 * h] = (int32_t)(int16_t)(w[h] & 0xFFFF);
+            a[2 * h + 1] = w[h] >> 16;
+        }
+    }
+}
+
+template <int T, int kLiftRows, typename AT>
+__global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_t n, int64_t ld,
                                                 const uint32_t *__restrict__ X,
                                                 const int64_t *__restrict__ R, int t, uint32_t p,
                                                 int64_t *__restrict__ Rn, uint32_t *__restrict__ Rmn,
                                                 int32_t *__restrict__ err) {
+    constexpr int kPer = 16 / (int)sizeof(AT);   // entries of A per 16-byte load
     const int lane = threadIdx.x & 63;
     const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
     if (r0 >= n) return;
-    const int64_t q = ld / 4;
+    const int64_t q = ld / kPer;
     const int4 *Ar[kLiftRows];
 #pragma unroll
     for (int rr = 0; rr < kLiftRows; ++rr)
@@ -321,18 +338,28 @@ __global__ __launch_bounds__(256) void k_lift_r(const int32_t *__restrict__ A, i
         for (int c = 0; c < T; ++c) acc[rr][c] = 0;
 #pragma unroll 2
     for (int64_t k = lane; k < q; k += 64) {
-        uint4 xv[T];
+        uint32_t xv[T][kPer];
 #pragma unroll
         for (int c = 0; c < T; ++c)
-            if (c < t) xv[c] = reinterpret_cast<const uint4 *>(X + (int64_t)c * ld)[k];
+            if (c < t) {
+#pragma unroll
+                for (int h = 0; h < kPer / 4; ++h) {
+                    const uint4 v = reinterpret_cast<const uint4 *>(X + (int64_t)c * ld)[k * (kPer / 4) + h];
+                    xv[c][4 * h] = v.x; xv[c][4 * h + 1] = v.y; xv[c][4 * h + 2] = v.z; xv[c][4 * h + 3] = v.w;
+                }
+            }
 #pragma unroll
         for (int rr = 0; rr < kLiftRows; ++rr) {
-            const int4 av = Ar[rr][k];
+            int32_t av[kPer];
+            unpack_a<AT>(Ar[rr][k], av);
 #pragma unroll
             for (int c = 0; c < T; ++c)
-                if (c < t)
-                    acc[rr][c] += (int64_t)av.x * xv[c].x + (int64_t)av.y * xv[c].y + (int64_t)av.z * xv[c].z +
-                                  (int64_t)av.w * xv[c].w;
+                if (c < t) {
+                    int64_t sum = 0;
+#pragma unroll
+                    for (int e = 0; e < kPer; ++e) sum += (int64_t)av[e] * xv[c][e];
+                    acc[rr][c] += sum;
+                }
         }
     }
 #pragma unroll
@@ -628,31 +655,41 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
     hipLaunchKernelGGL(k_gj_load, grid, dim3(256), 0, s, A, n, ld, M, pr);
 }
 
-template <int T, int RW>
-static void lift_step_t(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
+template <int T, int RW, typename AT>
+static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
                         const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                         int32_t *err, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + 4 * RW - 1) / (4 * RW));
     hipLaunchKernelGGL((k_lift_x<T, RW>), dim3(blocks), dim3(256), 0, s, C, n, ld, Rm, t, p, X);
-    hipLaunchKernelGGL((k_lift_r<T, RW>), dim3(blocks), dim3(256), 0, s, A, n, ld, X, R, t, p, Rn, Rmn, err);
+    hipLaunchKernelGGL((k_lift_r<T, RW, AT>), dim3(blocks), dim3(256), 0, s, A, n, ld, X, R, t, p, Rn, Rmn, err);
 }
 
-template <int T>
-static void lift_step_rw(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
+template <int T, typename AT>
+static void lift_step_rw(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
                          const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                          int32_t *err, hipStream_t s) {
     // About 2048 waves or more: 8 per CU.
-    if (n >= 4 * 2048) lift_step_t<T, 4>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else if (n >= 2 * 2048) lift_step_t<T, 2>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else lift_step_t<T, 1>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    if (n >= 4 * 2048) lift_step_t<T, 4, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else if (n >= 2 * 2048) lift_step_t<T, 2, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else lift_step_t<T, 1, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
 }
 
-void launch_lift_step(const uint32_t *C, const int32_t *A, int64_t n, int64_t ld, int t, uint32_t p,
+template <typename AT>
+static void lift_step_at(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
+                         const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
+                         int32_t *err, hipStream_t s) {
+    if (t <= 4) lift_step_rw<4, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else if (t <= 8) lift_step_rw<8, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else lift_step_rw<kLiftMaxT, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+}
+
+void launch_lift_step(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
                       const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
                       int32_t *err, hipStream_t s) {
-    if (t <= 4) lift_step_rw<4>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else if (t <= 8) lift_step_rw<8>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else lift_step_rw<kLiftMaxT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    if (a_bytes == 2)
+        lift_step_at(C, static_cast<const int16_t *>(A), n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    else
+        lift_step_at(C, static_cast<const int32_t *>(A), n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
 }
 
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,

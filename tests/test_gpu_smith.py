@@ -185,13 +185,19 @@ def test_lifting_golden(lifting_ctx, rg, case):
     print("stats", res.stats, flush=True)
 
 
-@pytest.mark.parametrize("n,seed", [(16, 0), (24, 1), (40, 2), (64, 3)])
-def test_lifting_forced_matches_oracle(lifting_ctx, rg, n, seed):
+@pytest.mark.parametrize("n,seed,bound", [(16, 0, 100), (24, 1, 100), (40, 2, 100), (64, 3, 100),
+                                          (17, 4, 1 << 15), (33, 5, 1 << 20)])
+def test_lifting_forced_matches_oracle(lifting_ctx, rg, n, seed, bound):
+    """Forced p-adic lifting against the oracle; entries below 2^15 in
+    magnitude take the int16 form of A in the lifting kernels, the larger ones
+    (|a| up to 2^15 and 2^20) the int32 form."""
     ctx = lifting_ctx
-    _say("smith lifting forced", n, seed)
+    _say("smith lifting forced", n, seed, bound)
     rng = np.random.default_rng(500 + seed)
     while True:
-        a = rng.integers(-99, 100, size=(n, n), dtype=np.int64)
+        a = rng.integers(-bound + 1, bound, size=(n, n), dtype=np.int64)
+        if bound > 100:
+            a[0, 0] = bound if seed % 2 == 0 else -bound        # one entry just outside int16
         if osmith.bareiss_det(a) != 0:
             break
     ctx.set_smith_path("lifting")
