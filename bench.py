@@ -380,8 +380,11 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
             if len(tickets) % 50 == 0:
                 print("[serving] %.2fx capacity: %d submitted" % (frac, len(tickets)), file=sys.stderr, flush=True)
         lat, queue, service, ok, bad, tail_rec, paths, exact = [], [], [], 0, 0, None, [0, 0], 0
+        intervals = []
         for t, (r, a, kind) in zip(tickets, reqs):
             st, res, info = srv.wait(t)
+            if info["t_start"] > 0 and info["t_end"] >= info["t_start"]:
+                intervals.append((info["t_start"], info["t_end"]))
             if kind == "singular":
                 bad += int(st == 6)
                 continue
@@ -402,6 +405,18 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
             if len(solved) < 6 and r.n <= 1500:
                 solved.append((a, res.s))
         span = time.perf_counter() - start
+        # Share of the point's span with at least one request running on the
+        # device (union of the [start, end] intervals of every request).
+        busy, cur_a, cur_b = 0.0, None, None
+        for a_, b_ in sorted(intervals):
+            if cur_b is None or a_ > cur_b:
+                if cur_b is not None:
+                    busy += cur_b - cur_a
+                cur_a, cur_b = a_, b_
+            else:
+                cur_b = max(cur_b, b_)
+        if cur_b is not None:
+            busy += cur_b - cur_a
         print("[serving] %.2fx capacity: %d requests in %.1f s" % (frac, count, span), file=sys.stderr, flush=True)
         points.append({"rate_frac_of_capacity": frac, "arrival_rate": rate, "requests": count,
                        "solves_per_s": ok / span, "p50_latency_s": float(np.percentile(lat, 50)),
@@ -411,6 +426,7 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
                        "p50_service_s": float(np.percentile(service, 50)),
                        "p99_service_s": float(np.percentile(service, 99)),
                        "singular_rejected": bad, "paths_residue_lifting": paths,
+                       "busy_frac": busy / span if span > 0 else None,
                        "exact_certificates": exact, "tail": tail_rec})
     st = srv.stats()
     srv.close()
