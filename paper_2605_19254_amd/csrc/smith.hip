@@ -114,6 +114,18 @@ void parallel_for(int count, F f) {
         if (s_ != RNS_OK) return s_;     \
     } while (0)
 
+// A captured run of lifting steps; destroyed with the run.
+constexpr int kLiftGraphSteps = 16;
+struct StepGraph {
+    bool tried = false;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~StepGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
@@ -604,6 +616,7 @@ struct Driver {
     DevBuf<int32_t> dRp;        // projection [tp][n]
     DevBuf<int64_t> dZ;         // projected digits of one checkpoint interval
     DevBuf<int32_t> derr;
+    DevBuf<int64_t> dstep;      // device-side index of the next lifting step
     DevBuf<uint32_t> ddet;
     bool cert_exact = true;
 
@@ -732,29 +745,48 @@ struct Driver {
         DRV_ST(dRm1.alloc((size_t)t * ldl));
         DRV_ST(dRp.alloc((size_t)tp * n));
         DRV_ST(derr.alloc(1));
+        DRV_ST(dstep.alloc(1));
         DRV_HIP(hipMemcpyAsync(dR0.p, J.data(), sizeof(int64_t) * J.size(), hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemcpyAsync(dRm0.p, Jm.data(), sizeof(uint32_t) * Jm.size(), hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemcpyAsync(dRp.p, Rp.data(), sizeof(int32_t) * Rp.size(), hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), stream));
+        DRV_HIP(hipMemsetAsync(dstep.p, 0, sizeof(int64_t), stream));
+        const LiftBufs lb{dR0.p, dR1.p, dRm0.p, dRm1.p, dXh.p, derr.p, dstep.p};
+        const void *Adev = a_bytes == 2 ? (const void *)dA16.p : (const void *)dA32.p;
+        // Runs of kLiftGraphSteps steps replay one captured graph (the step
+        // launches take the same arguments every time); the rest, and every
+        // step if capture is not available, are launched directly.
+        StepGraph graph;
+        auto capture = [&]() {
+            graph.tried = true;
+            if (hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) != hipSuccess) return;
+            launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, t, p, lb, kLiftGraphSteps, stream);
+            hipGraph_t gr = nullptr;
+            if (hipStreamEndCapture(stream, &gr) != hipSuccess || !gr) {
+                (void)hipGetLastError();
+                return;
+            }
+            graph.g = gr;
+            if (hipGraphInstantiate(&graph.exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+                graph.exec = nullptr;
+                (void)hipGetLastError();
+            }
+        };
         const int ne = tp * t;
         std::vector<BigInt> Y(ne, BigInt(0));
         BigInt pw(1);                                    // p^K_done
         int64_t K_done = 0, K_chk = 32;
-        int64_t *R[2] = {dR0.p, dR1.p};
-        uint32_t *Rm[2] = {dRm0.p, dRm1.p};
-        int cur = 0;
         bool have_prev = false;
         BigInt prev_s;
         std::vector<BigInt> prev_X;
         std::vector<int64_t> hz;
         for (;;) {
             K_chk = std::min(K_chk, Kmax);
-            for (int64_t i = K_done; i < K_chk; ++i) {
-                launch_lift_step(dC.p, a_bytes == 2 ? (const void *)dA16.p : (const void *)dA32.p, a_bytes, n, ldl,
-                                 t, p, Rm[cur], R[cur], dXh.p + i * t * ldl,
-                                 R[1 - cur], Rm[1 - cur], derr.p, stream);
-                cur ^= 1;
-            }
+            int64_t i = K_done;
+            if (K_chk - i >= kLiftGraphSteps && !graph.tried) capture();
+            for (; graph.exec && K_chk - i >= kLiftGraphSteps; i += kLiftGraphSteps)
+                DRV_HIP(hipGraphLaunch(graph.exec, stream));
+            if (i < K_chk) launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, t, p, lb, (int)(K_chk - i), stream);
             const int64_t nb = K_chk - K_done;
             DRV_ST(dZ.alloc((size_t)nb * ne));
             launch_lift_proj(dXh.p, n, ldl, t, dRp.p, tp, K_done, K_chk, dZ.p, stream);

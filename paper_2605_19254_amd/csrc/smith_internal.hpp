@@ -41,9 +41,20 @@ void launch_gj_pivoted(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, c
 // with a_bytes = 2, int16) have row stride ld, a multiple of 8, and are zero
 // in columns n..ld-1; R, Rm and X hold t vectors of stride ld ([t][ld]).
 constexpr int kLiftMaxCols = 16;
-void launch_lift_step(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
-                      const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
-                      int32_t *err, hipStream_t s);
+// Device state of a lifting run: residuals R[2] (int64) and Rm[2] (mod p),
+// every step's digits Xh ([K][t][ld]), the inexact-division flag and the
+// index of the next step (*base).
+struct LiftBufs {
+    int64_t *R0, *R1;
+    uint32_t *Rm0, *Rm1;
+    uint32_t *Xh;
+    int32_t *err;
+    int64_t *base;
+};
+// `steps` lifting steps (two launches each) and one launch advancing *base;
+// the launches take the same arguments for every run of the same length.
+void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
+                       const LiftBufs &b, int steps, hipStream_t s);
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,
                       int64_t i0, int64_t i1, int64_t *Z, hipStream_t s);
 void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t plane_stride,

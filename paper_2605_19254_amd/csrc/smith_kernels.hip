@@ -201,16 +201,25 @@ __global__ __launch_bounds__(1024) void k_gj_blockinv(const uint32_t *__restrict
         }
         __syncthreads();
         if (failed) break;                                    // the same on every thread
-        for (int c = threadIdx.x; c < w2; c += blockDim.x) T[j][c] = mulmod_p(T[j][c], inv, pf, pinv);
-        __syncthreads();
+        // Without row exchanges only bw columns can change at step j: the
+        // left columns j+1 .. bw-1 (those before are reduced to unit
+        // columns) and the right columns bw .. bw+j (row j's right part is
+        // zero beyond column bw+j).  Active column a < bw maps to
+        // j+1+a (a < bw-j-1) or to bw+a-(bw-j-1).
+        const int nleft = bw - j - 1;
+        for (int a = threadIdx.x; a < bw; a += blockDim.x) {
+            const int c = a < nleft ? j + 1 + a : bw + a - nleft;
+            T[j][c] = mulmod_p(T[j][c], inv, pf, pinv);
+        }
         for (int i = threadIdx.x; i < bw; i += blockDim.x) F[i] = i == j ? 0u : T[i][j];
         __syncthreads();
-        for (int e = threadIdx.x; e < bw * w2; e += blockDim.x) {
-            const int i = e / w2, c = e % w2;
+        for (int e = threadIdx.x; e < bw * bw; e += blockDim.x) {
+            const int i = e / bw, a = e % bw;
             if (F[i] == 0) continue;
+            const int c = a < nleft ? j + 1 + a : bw + a - nleft;
             const uint32_t t = mulmod_p(F[i], T[j][c], pf, pinv);
-            const uint32_t a = T[i][c];
-            T[i][c] = a >= t ? a - t : a + p - t;
+            const uint32_t v = T[i][c];
+            T[i][c] = v >= t ? v - t : v + p - t;
         }
         __syncthreads();
     }
@@ -249,10 +258,19 @@ constexpr int kLiftMaxT = 16;
 // X[c][r] = sum_k C[r][k] Rm[c][k] mod p.  Each lane sums at most ld/64
 // products below 2^52 per row (ld <= 65536 keeps that below 2^62), reduces
 // its sums mod p, and the wave adds the 64 reduced sums.
+// Step i = *base + off: it reads Rm[i & 1] and R[i & 1], writes its digits to
+// Xh + i t ld and the next residuals to the other buffers.  *base lives in
+// device memory and is advanced by k_lift_advance after a run of steps, so a
+// run of steps (offsets 0, 1, ...) takes the same arguments every time and
+// can be replayed from a captured graph.
 template <int T, int kLiftRows>
 __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, int64_t n, int64_t ld,
-                                                const uint32_t *__restrict__ Rm, int t, uint32_t p,
-                                                uint32_t *__restrict__ X) {
+                                                const uint32_t *__restrict__ Rm0, const uint32_t *__restrict__ Rm1,
+                                                int t, uint32_t p, uint32_t *__restrict__ Xh,
+                                                const int64_t *__restrict__ base, int off) {
+    const int64_t i_step = *base + off;
+    const uint32_t *__restrict__ Rm = (i_step & 1) ? Rm1 : Rm0;
+    uint32_t *__restrict__ X = Xh + i_step * t * ld;
     const int lane = threadIdx.x & 63;
     const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
     if (r0 >= n) return;                                 // whole waves only
@@ -316,16 +334,15 @@ __device__ __forceinline__ void unpack_a(const int4 raw, int32_t (&a)[16 / sizeo
     }
 }
 
+// The rows r0 .. r0+kLiftRows-1 of one step of k_lift_r (one wave).
 template <int T, int kLiftRows, typename AT>
-__global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_t n, int64_t ld,
-                                                const uint32_t *__restrict__ X,
-                                                const int64_t *__restrict__ R, int t, uint32_t p,
-                                                int64_t *__restrict__ Rn, uint32_t *__restrict__ Rmn,
-                                                int32_t *__restrict__ err) {
+__device__ __forceinline__ void lift_r_rows(const AT *__restrict__ A, int64_t n, int64_t ld,
+                                            const uint32_t *__restrict__ X,
+                                            const int64_t *__restrict__ R, int t, uint32_t p,
+                                            int64_t *__restrict__ Rn, uint32_t *__restrict__ Rmn,
+                                            int32_t *__restrict__ err, int64_t r0) {
     constexpr int kPer = 16 / (int)sizeof(AT);   // entries of A per 16-byte load
     const int lane = threadIdx.x & 63;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
-    if (r0 >= n) return;
     const int64_t q = ld / kPer;
     const int4 *Ar[kLiftRows];
 #pragma unroll
@@ -380,6 +397,27 @@ __global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_
                 Rmn[(int64_t)c * ld + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
             }
         }
+}
+
+template <int T, int kLiftRows, typename AT>
+__global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_t n, int64_t ld,
+                                                const uint32_t *__restrict__ Xh,
+                                                int64_t *__restrict__ R0, int64_t *__restrict__ R1,
+                                                uint32_t *__restrict__ Rm0, uint32_t *__restrict__ Rm1,
+                                                int t, uint32_t p, int32_t *__restrict__ err,
+                                                const int64_t *__restrict__ base, int off) {
+    const int64_t i_step = *base + off;
+    const uint32_t *__restrict__ X = Xh + i_step * t * ld;
+    const int64_t *__restrict__ R = (i_step & 1) ? R1 : R0;
+    int64_t *__restrict__ Rn = (i_step & 1) ? R0 : R1;
+    uint32_t *__restrict__ Rmn = (i_step & 1) ? Rm0 : Rm1;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
+    if (r0 < n) lift_r_rows<T, kLiftRows, AT>(A, n, ld, X, R, t, p, Rn, Rmn, err, r0);
+}
+
+// *base += steps (one thread), after a run of steps.
+__global__ void k_lift_advance(int64_t *__restrict__ base, int steps) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *base += steps;
 }
 
 // Projections of stored digits: Z[i][a][c] = sum_r Rp[a][r] Xh[i][c][r] for
@@ -657,39 +695,40 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
 
 template <int T, int RW, typename AT>
 static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
-                        const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
-                        int32_t *err, hipStream_t s) {
+                        const LiftBufs &b, int off, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + 4 * RW - 1) / (4 * RW));
-    hipLaunchKernelGGL((k_lift_x<T, RW>), dim3(blocks), dim3(256), 0, s, C, n, ld, Rm, t, p, X);
-    hipLaunchKernelGGL((k_lift_r<T, RW, AT>), dim3(blocks), dim3(256), 0, s, A, n, ld, X, R, t, p, Rn, Rmn, err);
+    hipLaunchKernelGGL((k_lift_x<T, RW>), dim3(blocks), dim3(256), 0, s, C, n, ld, b.Rm0, b.Rm1, t, p, b.Xh,
+                       b.base, off);
+    hipLaunchKernelGGL((k_lift_r<T, RW, AT>), dim3(blocks), dim3(256), 0, s, A, n, ld, b.Xh, b.R0, b.R1, b.Rm0,
+                       b.Rm1, t, p, b.err, b.base, off);
 }
 
 template <int T, typename AT>
 static void lift_step_rw(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
-                         const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
-                         int32_t *err, hipStream_t s) {
+                         const LiftBufs &b, int off, hipStream_t s) {
     // About 2048 waves or more: 8 per CU.
-    if (n >= 4 * 2048) lift_step_t<T, 4, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else if (n >= 2 * 2048) lift_step_t<T, 2, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else lift_step_t<T, 1, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+    if (n >= 4 * 2048) lift_step_t<T, 4, AT>(C, A, n, ld, t, p, b, off, s);
+    else if (n >= 2 * 2048) lift_step_t<T, 2, AT>(C, A, n, ld, t, p, b, off, s);
+    else lift_step_t<T, 1, AT>(C, A, n, ld, t, p, b, off, s);
 }
 
 template <typename AT>
 static void lift_step_at(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
-                         const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
-                         int32_t *err, hipStream_t s) {
-    if (t <= 4) lift_step_rw<4, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else if (t <= 8) lift_step_rw<8, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else lift_step_rw<kLiftMaxT, AT>(C, A, n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+                         const LiftBufs &b, int off, hipStream_t s) {
+    if (t <= 4) lift_step_rw<4, AT>(C, A, n, ld, t, p, b, off, s);
+    else if (t <= 8) lift_step_rw<8, AT>(C, A, n, ld, t, p, b, off, s);
+    else lift_step_rw<kLiftMaxT, AT>(C, A, n, ld, t, p, b, off, s);
 }
 
-void launch_lift_step(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
-                      const uint32_t *Rm, const int64_t *R, uint32_t *X, int64_t *Rn, uint32_t *Rmn,
-                      int32_t *err, hipStream_t s) {
-    if (a_bytes == 2)
-        lift_step_at(C, static_cast<const int16_t *>(A), n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
-    else
-        lift_step_at(C, static_cast<const int32_t *>(A), n, ld, t, p, Rm, R, X, Rn, Rmn, err, s);
+void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
+                       const LiftBufs &b, int steps, hipStream_t s) {
+    for (int off = 0; off < steps; ++off) {
+        if (a_bytes == 2)
+            lift_step_at(C, static_cast<const int16_t *>(A), n, ld, t, p, b, off, s);
+        else
+            lift_step_at(C, static_cast<const int32_t *>(A), n, ld, t, p, b, off, s);
+    }
+    hipLaunchKernelGGL(k_lift_advance, dim3(1), dim3(64), 0, s, b.base, steps);
 }
 
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,
