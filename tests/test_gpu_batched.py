@@ -181,6 +181,33 @@ def test_matmul_plan_full_range_int64(ctx, rg, torch_dev, path):
     plan.close()
 
 
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_matmul_plan_degenerate_shapes(ctx, rg, torch_dev, path):
+    """Whole-product plans with k = 0 (C = 0), empty problems (m = 0 or n = 0)
+    and 1 x 1 products in one batch, beside an ordinary product."""
+    torch, dev = torch_dev
+    _say("matmul plan degenerate shapes", path)
+    rng = np.random.default_rng(7)
+    shapes = [(5, 0, 7), (0, 4, 3), (6, 4, 0), (1, 1, 1), (33, 65, 17)]
+    probs, hosts = [], []
+    for m, k, n in shapes:
+        a = rng.integers(-(1 << 25), 1 << 25, size=(m, k), dtype=np.int64)
+        b = rng.integers(-(1 << 25), 1 << 25, size=(k, n), dtype=np.int64)
+        A = torch.from_numpy(a).to(dev) if a.size else torch.zeros((m, k), dtype=torch.int64, device=dev)
+        B = torch.from_numpy(b).to(dev) if b.size else torch.zeros((k, n), dtype=torch.int64, device=dev)
+        C = torch.full((m, n), 123, dtype=torch.int64, device=dev)
+        probs.append(rg.MatmulProblem(A, B, C, prime_begin=0, L=4, bound=max(k, 1) << 50))
+        hosts.append((a, b))
+    plan = rg.MatmulPlan(ctx, probs, path=path)
+    plan.execute()
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for (a, b), p in zip(hosts, probs):
+        want = a.astype(object).dot(b.astype(object)) if a.shape[1] else np.zeros((a.shape[0], b.shape[1]), dtype=object)
+        assert np.array_equal(p.C.cpu().numpy().astype(object), want)
+    plan.close()
+
+
 def test_matmul_plan_graph_replay(ctx, rg, torch_dev):
     """Capture the whole product (reduce, prep, GEMM, CRT) into a HIP graph and
     replay it several times with eager work in between; every replay must equal
