@@ -444,3 +444,30 @@ def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
     for i, c in idx:
         assert int(o[i, c]) == orns.exact_entry(a[i], b[:, c])
     assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_matmul_plan_n4096_sampled(ctx, rg, torch_dev, path):
+    """The benchmark's step: one whole-product plan over the n = 4096, 24-prime
+    product (int64 A and B straight into the tiled operands, GEMM, Lagrange
+    CRT), executed twice; sampled rows and entries against the oracle."""
+    torch, dev = torch_dev
+    _say("whole-product plan n=4096", path)
+    n, L = 4096, 24
+    a, b = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    out = torch.empty((n, n), dtype=torch.int64, device=dev)
+    plan = rg.MatmulPlan(ctx, [rg.MatmulProblem(ta, tb, out, prime_begin=0, L=L, bound=n << 40)], path=path)
+    plan.execute()
+    out.fill_(0)
+    plan.execute()                      # a second execution on the resident workspace
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    rng = np.random.default_rng(9)
+    rows = np.concatenate([[0, n - 1], rng.integers(0, n, size=2)])
+    got = out[torch.from_numpy(rows).to(dev)].cpu().numpy()
+    assert np.array_equal(got, native.exact_matmul(a[rows], b))
+    o = out.cpu().numpy()
+    for i, c in rng.integers(0, n, size=(64, 2)):
+        assert int(o[i, c]) == orns.exact_entry(a[i], b[:, c])
+    plan.close()
