@@ -14,7 +14,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerCU = 8;
+constexpr int kBlocksPerCU = kWavesPerCU * 64 / kBlock;
 constexpr int kChains = 8;
+// The launch bounds state the two work-groups per CU that the grid places.
+// With a bound of one work-group the compiler keeps the accumulators in the
+// accumulation registers (AGPRs), and 16x16x64 INT8 MFMAs with AGPR
+// accumulators were measured about 20% slower on MI355X than with ordinary
+// VGPR accumulators, which is where the GEMM kernels keep them.
 
 __device__ __forceinline__ unsigned mix32(unsigned x) {
     // Integer finaliser (xor-shift / multiply rounds) for operand bits.
@@ -41,7 +47,7 @@ __device__ __forceinline__ void fill_int(V (&a)[kChains], V (&b)[kChains], int w
 }
 
 // One iteration = 2 * kChains instructions (two pairings of the operands).
-__global__ __launch_bounds__(kBlock) void k_cal_i8_16(int iters, int random, unsigned seed, int *out) {
+__global__ __launch_bounds__(kBlock, kBlocksPerCU) void k_cal_i8_16(int iters, int random, unsigned seed, int *out) {
     v4i a[kChains], b[kChains], acc[kChains];
     fill_int(a, b, 4, random != 0, seed);
 #pragma unroll
@@ -59,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_cal_i8_16(int iters, int random, uns
     out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cal_i8_32(int iters, int random, unsigned seed, int *out) {
+__global__ __launch_bounds__(kBlock, kBlocksPerCU) void k_cal_i8_32(int iters, int random, unsigned seed, int *out) {
     v4i a[kChains], b[kChains];
     v16i acc[kChains];
     fill_int(a, b, 4, random != 0, seed);
@@ -83,7 +89,7 @@ __device__ __forceinline__ double unit_double(unsigned bits) {
     return 1.0 + (double)(bits >> 8) * (1.0 / 16777216.0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cal_f64_mfma(int iters, int random, unsigned seed, int *out) {
+__global__ __launch_bounds__(kBlock, kBlocksPerCU) void k_cal_f64_mfma(int iters, int random, unsigned seed, int *out) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     double a[kChains], b[kChains];
     v4d acc[kChains];
@@ -106,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_cal_f64_mfma(int iters, int random, 
     out[blockIdx.x * blockDim.x + threadIdx.x] = s != 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cal_f64_fma(int iters, int random, unsigned seed, int *out) {
+__global__ __launch_bounds__(kBlock, kBlocksPerCU) void k_cal_f64_fma(int iters, int random, unsigned seed, int *out) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     double x[kChains], y[kChains];
 #pragma unroll

@@ -11,7 +11,12 @@
 // on the order of summation.  The paper bounds the whole dot product instead
 // (n(p-1)^2 + (p-1) < 2^53); blocking by 8 lets 26-bit primes be used at any k.
 //
-// Work-group tile 128 x 128: four waves in 2 x 2, each 64 x 64.
+// Work-group tile 128 x 128: four waves in 2 x 2, each 64 x 64.  Two
+// work-groups per CU (the launch bound), so that the compiler keeps the 64
+// accumulators per lane in ordinary VGPRs (220 registers in all) and one
+// wave's reduction overlaps the other wave's MFMAs; with one work-group per
+// CU the accumulators went to the accumulation registers (AGPRs), where
+// FP64 MFMAs ran at half rate on MI355X.
 #include "gemm_common.hpp"
 
 namespace rns {
@@ -20,7 +25,7 @@ namespace {
 
 // ------------------------------------------------------------- FP64 GEMM --
 
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmProblem *__restrict__ P, int nprob,
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmProblem *__restrict__ P, int nprob,
                                                   int64_t total_tiles,
                                                   const PrimeConst *__restrict__ pc,
         const int32_t *__restrict__ tile_prob) {
