@@ -2,13 +2,15 @@
 """Benchmark of the exact multi-modular integer matrix product on one MI355X.
 
 One step = the whole hot path over one batch of synthetic input that is
-already resident in HBM:
-    rns_reduce(A), rns_reduce(B)            int64 -> 24 residue planes each
-    modmatmul_batched(..., path)            24 exact products mod p
-    crt_reconstruct(..., bound)             24 planes -> int64 result
-Workload: A, B 4096 x 4096, entries uniform in [-2^20, 2^20] (seeds 0 and 1),
-the 24 largest primes below 2^26.  The headline runs the INT8-limb path; the
-FP64-MFMA path is timed beside it on the same inputs.
+already resident in HBM, as one execution of a whole-product plan:
+    int64 A and B -> tiled residue digits   all 24 primes, one launch
+    24 exact products mod p                 one GEMM launch
+    CRT of the 24 planes -> int64 result    one launch
+The same product through the four boundary calls (rns_reduce(A),
+rns_reduce(B), modmatmul_batched, crt_reconstruct) is timed beside it
+(`boundary_calls`).  Workload: A, B 4096 x 4096, entries uniform in
+[-2^20, 2^20] (seeds 0 and 1), the 24 largest primes below 2^26.  The headline
+runs the INT8-limb path; the FP64-MFMA path is timed on the same inputs.
 
 Prints one JSON line.  `value` is residue int-ops per second of the whole step,
 2*m*n*k*L per step.  The roofline entry is for the dominant kernel (the GEMM):
@@ -79,7 +81,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--primes", type=int, default=24)
     ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-rows", type=int, default=96,
+    ap.add_argument("--cpu-rows", type=int, default=288,
                     help="rows of C the oracle computes for the CPU baseline (0 = skip)")
     ap.add_argument("--out", default="")
     ap.add_argument("--batched", type=int, default=512,
