@@ -59,6 +59,27 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Windowed XCD remap, used by the GEMM kernels: XCD x (work-groups b with
+// b % 8 == x) takes windows x, x+8, x+16, ... of W consecutive logical
+// indices, W = the work-groups one XCD holds at a time.  The eight XCDs then
+// work on neighbouring windows at the same time, inside one prime's operand
+// planes (128 MB at n = 4096, which the 256 MB Infinity Cache holds), while
+// each XCD's L2 still sees W neighbouring tiles.  Giving each XCD one
+// contiguous range instead (xcd_remap) puts the XCDs on eight different
+// primes at once; on MI355X the INT8 GEMM at n = 4096 with 24 primes ran 4 %
+// slower that way.  The indices past the last full round of 8 W use
+// xcd_remap.
+// Work-groups one XCD of MI355X holds at a time (32 CUs) for kernels with one
+// and with two work-groups per CU.
+constexpr int64_t kXcdWindow1 = 32, kXcdWindow2 = 64;
+
+__device__ __forceinline__ int64_t xcd_window_remap(int64_t b, int64_t G, int64_t W) {
+    const int64_t full = G / (8 * W) * (8 * W);
+    if (b >= full) return full + xcd_remap(b - full, G - full);
+    const int64_t x = b % 8, i = b / 8;
+    return ((i / W) * 8 + x) * W + i % W;
+}
+
 __device__ __forceinline__ int32_t balanced(uint32_t r, uint32_t p, uint32_t half) {
     return r > half ? (int32_t)r - (int32_t)p : (int32_t)r;
 }

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const GemmProblem *__restri
                                                   int64_t total_tiles,
                                                   const PrimeConst *__restrict__ pc,
         const int32_t *__restrict__ tile_prob) {
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t = xcd_window_remap(blockIdx.x, gridDim.x, kXcdWindow2);
     if (t >= total_tiles) return;
     const TileCoord tc = map_tile(P, nprob, t, tile_prob);
     const GemmProblem &g = P[tc.q];

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const GemmProblem *__restrict__
                                                  int64_t total_tiles,
                                                  const PrimeConst *__restrict__ pc,
         const int32_t *__restrict__ tile_prob) {
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t = xcd_window_remap(blockIdx.x, gridDim.x, kXcdWindow1);
     if (t >= total_tiles) return;
     const TileCoord tc = map_tile(P, nprob, t, tile_prob);
     const GemmProblem &g = P[tc.q];
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restri
                                                      const PrimeConst *__restrict__ pc,
                                                      const int32_t *__restrict__ tile_prob) {
     __shared__ v4i sbuf[2][ShapeLds::kFrag * 64];
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t = xcd_window_remap(blockIdx.x, gridDim.x, kXcdWindow1);
     if (t >= total_tiles) return;
     const TileCoord tc = map_tile(P, nprob, t, tile_prob);
     i8_lds_tile<ShapeLds>(P[tc.q], tc.plane, tc.tm * 4, tc.tn * 8, pc, sbuf);
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(512) void k_gemm_i8_w8(const GemmProblem *__restric
                                                     const PrimeConst *__restrict__ pc,
                                                     const int32_t *__restrict__ tile_prob) {
     __shared__ v4i sbuf[2][ShapeW8::kFrag * 64];
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t = xcd_window_remap(blockIdx.x, gridDim.x, kXcdWindow1);
     if (t >= total_tiles) return;
     const TileCoord tc = map_tile(P, nprob, t, tile_prob);
     i8_lds_tile<ShapeW8>(P[tc.q], tc.plane, tc.tm * 4, tc.tn * 8, pc, sbuf);
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_i8_half(const GemmProblem *__re
                                                          const PrimeConst *__restrict__ pc,
                                                          const int32_t *__restrict__ tile_prob) {
     __shared__ v4i sbuf[2][ShapeHalf::kFrag * 64];
-    const int64_t h2 = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t h2 = xcd_window_remap(blockIdx.x, gridDim.x, kXcdWindow2);
     if (h2 >= 2 * total_tiles) return;
     const TileCoord tc = map_tile(P, nprob, h2 >> 1, tile_prob);
     i8_lds_tile<ShapeHalf>(P[tc.q], tc.plane, tc.tm * 4, tc.tn * 8 + (int)(h2 & 1) * 4, pc, sbuf);
