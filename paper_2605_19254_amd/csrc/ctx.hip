@@ -200,6 +200,8 @@ extern "C" void rns_ctx_destroy(rns_ctx *ctx) {
     // Teardown is best effort: errors cannot be reported from here.
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->solve_stream) (void)hipStreamDestroy(ctx->solve_stream);
+    for (auto &kv : ctx->solve_pool) (void)hipFree(kv.second);
     if (ctx->d_prime) (void)hipFree(ctx->d_prime);
     if (ctx->d_garner) (void)hipFree(ctx->d_garner);
     if (ctx->d_status) (void)hipFree(ctx->d_status);

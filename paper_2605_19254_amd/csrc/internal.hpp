@@ -83,6 +83,12 @@ struct rns_ctx {
     int force_cert_failures = 0;
     int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
     rns_ctx *aux = nullptr;            // wide-basis context of the Smith-form driver
+    // Smith-form solves on this context run on one stream, created by the
+    // first, and return their device blocks of up to 64 MiB to a pool (at
+    // most 512 MiB kept) that later solves allocate from.
+    hipStream_t solve_stream = nullptr;
+    std::multimap<size_t, void *> solve_pool;
+    size_t solve_pool_bytes = 0;
     int int8_kernel = -1;              // forced INT8 GEMM variant (RNS_INT8_KERNEL), -1 = tuned
     uint64_t flags = 0;                // creation flags (RNS_CTX_PATH_*)
     int auto_path = 0;                 // what RNS_PATH_AUTO resolves to: 0 library choice, else a path

@@ -126,23 +126,83 @@ struct StepGraph {
     }
 };
 
+// The context of the Smith-form solve running on this thread (set for the
+// duration of a solve): device buffers come from its pool and go back to it.
+thread_local rns_ctx *t_solve_ctx = nullptr;
+
+struct SolveScope {
+    rns_ctx *prev;
+    explicit SolveScope(rns_ctx *c) : prev(t_solve_ctx) { t_solve_ctx = c; }
+    ~SolveScope() { t_solve_ctx = prev; }
+};
+
+constexpr size_t kPoolMaxBlock = size_t(64) << 20, kPoolMaxBytes = size_t(512) << 20;
+
+// A device block of at least `bytes` (its size in `got`): the smallest pooled
+// block that is not more than twice as large, else a new allocation.
+void *pool_get(size_t bytes, size_t &got) {
+    rns_ctx *c = t_solve_ctx;
+    if (c && bytes <= kPoolMaxBlock) {
+        auto it = c->solve_pool.lower_bound(bytes);
+        if (it != c->solve_pool.end() && it->first <= 2 * bytes) {
+            got = it->first;
+            void *q = it->second;
+            c->solve_pool_bytes -= it->first;
+            c->solve_pool.erase(it);
+            return q;
+        }
+    }
+    bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+    got = bytes;
+    return q;
+}
+
+// Returns a block: to the pool once the solve stream has finished with it
+// (the synchronisation hipFree would do), or to the device when the pool is
+// full, the block is large, or no solve is running.
+void pool_put(void *q, size_t bytes) {
+    rns_ctx *c = t_solve_ctx;
+    if (c && c->solve_stream && bytes <= kPoolMaxBlock && c->solve_pool_bytes + bytes <= kPoolMaxBytes &&
+        hipStreamSynchronize(c->solve_stream) == hipSuccess) {
+        c->solve_pool.emplace(bytes, q);
+        c->solve_pool_bytes += bytes;
+        return;
+    }
+    (void)hipFree(q);
+}
+
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
-    size_t n = 0;
+    size_t n = 0;               // elements asked for
+    size_t bytes = 0;           // size of the block held
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (p) pool_put(p, bytes);
     }
     int alloc(size_t count) {
         if (count <= n) return RNS_OK;
-        if (p) (void)hipFree(p);
+        if (p) pool_put(p, bytes);
         p = nullptr;
         n = 0;
-        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return RNS_ENOMEM;
+        bytes = 0;
+        size_t got = 0;
+        void *q = pool_get(std::max<size_t>(count, 1) * sizeof(T), got);
+        if (!q) return RNS_ENOMEM;
+        p = static_cast<T *>(q);
         n = count;
+        bytes = got;
         return RNS_OK;
     }
 };
+
+// The stream of the context's solves (created by the first).
+int solve_stream(rns_ctx *ctx, hipStream_t *s) {
+    if (!ctx->solve_stream) RNS_HIP(hipStreamCreate(&ctx->solve_stream));
+    *s = ctx->solve_stream;
+    return RNS_OK;
+}
 
 // Rational reconstruction with the coprimality check: y mod m -> num / den
 // (BigInt::rat_recon gives the bounds; Lehmer's method).
@@ -235,7 +295,8 @@ struct Driver {
     int Wx = 1;
 
     ~Driver() {
-        if (stream) (void)hipStreamDestroy(stream);
+        // The stream belongs to the context; the buffers (destroyed after
+        // this) wait for it before they return to the pool.
     }
 
     GjPrime gjp(int idx, int W) const {
@@ -1042,7 +1103,7 @@ struct Driver {
 
     int solve_lif(rns_smith_result *res) {
         DRV_HIP(hipSetDevice(ctx->device));
-        DRV_HIP(hipStreamCreate(&stream));
+        DRV_ST(solve_stream(ctx, &stream));
         DRV_ST(bounds());
         if (!lifting_applies()) return RNS_ENOTSUP;
         DRV_ST(dA.alloc((size_t)n * n));
@@ -1054,7 +1115,7 @@ struct Driver {
     // primes, p-adic lifting beyond when the entries are small enough.
     int solve(rns_smith_result *res) {
         DRV_HIP(hipSetDevice(ctx->device));
-        DRV_HIP(hipStreamCreate(&stream));
+        DRV_ST(solve_stream(ctx, &stream));
         DRV_ST(bounds());
         DRV_ST(dA.alloc((size_t)n * n));
         DRV_HIP(hipMemcpyAsync(dA.p, A, sizeof(int64_t) * n * n, hipMemcpyHostToDevice, stream));
@@ -1105,6 +1166,7 @@ extern "C" int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64
             delete res;
             return RNS_EINVAL;
         }
+    SolveScope scope(ctx);   // outlives the driver and its buffers
     Driver d;
     d.ctx = ctx;
     d.n = n;
@@ -1128,6 +1190,7 @@ extern "C" int rns_largest_invariant(rns_ctx *ctx, const int64_t *A_host, int64_
         if (A_host[e] == INT64_MIN) return RNS_EINVAL;
     rns_smith_result *res = new (std::nothrow) rns_smith_result;
     if (!res) return RNS_ENOMEM;
+    SolveScope scope(ctx);
     Driver d;
     d.ctx = ctx;
     d.n = n;
