@@ -467,14 +467,16 @@ __global__ __launch_bounds__(256) void k_scale(uint32_t *__restrict__ R, int64_t
 // Residues of W-word two's-complement integers modulo L primes:
 // out[j*count + e] = x_e mod p_j.  x = sum_w u_w 2^(64w) - [neg] 2^(64W);
 // the value is accumulated word by word with Horner's rule in exact doubles.
+// One thread per entry and prime (grid.y = prime).
 __global__ __launch_bounds__(256) void k_words_mod(const uint64_t *__restrict__ x, int64_t count,
-                                                   int W, const GjPrime *__restrict__ pr, int L,
+                                                   int W, const GjPrime *__restrict__ pr,
                                                    uint32_t *__restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
     const uint64_t *xe = x + e * W;
     const bool neg = (xe[W - 1] >> 63) != 0;
-    for (int j = 0; j < L; ++j) {
+    {
+        const int j = blockIdx.y;
         const double pf = pr[j].pf, pinv = pr[j].pinv;
         double r = 0.0;
         for (int w = W - 1; w >= 0; --w) {
@@ -763,8 +765,9 @@ void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t p
 
 void launch_words_mod(const uint64_t *x, int64_t count, int W, const GjPrime *pr, int L,
                       uint32_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_words_mod, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, x, count,
-                       W, pr, L, out);
+    if (count <= 0 || L <= 0) return;
+    hipLaunchKernelGGL(k_words_mod, dim3((unsigned)((count + 255) / 256), (unsigned)L), dim3(256), 0, s, x,
+                       count, W, pr, out);
 }
 
 void launch_check_sI(const uint32_t *P, int64_t n, const uint32_t *s_mod, int L, unsigned *mism,
