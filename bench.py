@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--primes", type=int, default=24)
     ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-rows", type=int, default=288,
+    ap.add_argument("--cpu-rows", type=int, default=384,
                     help="rows of C the oracle computes for the CPU baseline (0 = skip)")
     ap.add_argument("--out", default="")
     ap.add_argument("--batched", type=int, default=512,
