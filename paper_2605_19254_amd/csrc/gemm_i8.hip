@@ -17,9 +17,11 @@
 //   half     two independent work-groups per tile (one per 64-column half),
 //            four waves of 32 x 32 each, two work-groups per CU;
 //   half, persistent  the half kernel taking half-tiles from a work counter.
-// Measured on MI355X: a single wave per SIMD cannot keep the matrix unit busy
-// with 16x16x64 INT8 MFMAs, so the two-waves-per-SIMD forms are faster; the
-// half form, whose work-groups do not share a barrier, is the default.
+// Measured on MI355X: the two-waves-per-SIMD forms are faster than the
+// one-wave forms (whose 224 accumulators also sit in AGPRs, where 16x16x64
+// INT8 MFMAs run about a fifth slower than with VGPR accumulators); the half
+// form, whose work-groups do not share a barrier, is the default.  Every form
+// places its work-groups with xcd_window_remap.
 #include "gemm_common.hpp"
 
 #include <algorithm>
