@@ -40,7 +40,7 @@ struct GemmProblem {
     int64_t u64A_begin, u64B_begin;   // prefix over problems of those units (A then B)
 };
 
-__device__ __forceinline__ int find_problem(const GemmProblem *P, int nprob, int64_t t,
+__host__ __device__ __forceinline__ int find_problem(const GemmProblem *P, int nprob, int64_t t,
                                             int64_t GemmProblem::*field) {
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
@@ -53,12 +53,15 @@ __device__ __forceinline__ int find_problem(const GemmProblem *P, int nprob, int
 // XCD-aware remap: work-group b runs on XCD b % 8.  Give each XCD one
 // contiguous range of logical tiles so that the tiles sharing operand panels
 // share that XCD's L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+__host__ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
     const int64_t q = G / 8, r = G % 8;
     const int64_t x = b % 8, i = b / 8;
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// The tile-order functions are also built for the host, where a test checks
+// that they cover every tile exactly once.
+//
 // Windowed XCD remap, used by the GEMM kernels: XCD x (work-groups b with
 // b % 8 == x) takes windows x, x+8, x+16, ... of W consecutive logical
 // indices, W = the work-groups one XCD holds at a time.  The eight XCDs then
@@ -73,7 +76,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
 // and with two work-groups per CU.
 constexpr int64_t kXcdWindow1 = 32, kXcdWindow2 = 64;
 
-__device__ __forceinline__ int64_t xcd_window_remap(int64_t b, int64_t G, int64_t W) {
+__host__ __device__ __forceinline__ int64_t xcd_window_remap(int64_t b, int64_t G, int64_t W) {
     const int64_t full = G / (8 * W) * (8 * W);
     if (b >= full) return full + xcd_remap(b - full, G - full);
     const int64_t x = b % 8, i = b / 8;
@@ -92,7 +95,7 @@ struct TileCoord {
 
 // tile_prob (optional): the problem index of every tile, built by plans so
 // that a batch of many problems needs one load instead of a search per tile.
-__device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, int64_t t,
+__host__ __device__ __forceinline__ TileCoord map_tile(const GemmProblem *P, int nprob, int64_t t,
                                               const int32_t *tile_prob) {
     TileCoord c;
     c.q = tile_prob ? tile_prob[t] : find_problem(P, nprob, t, &GemmProblem::tile_begin);
