@@ -162,9 +162,28 @@ __global__ __launch_bounds__(256) void k_gj_swap(uint32_t *__restrict__ M, int64
     }
 }
 
-// W[q] = P11^-1 for the pivot block M[r0.., r0..] (bw x bw), Gauss-Jordan on
-// [P11 | I] in LDS without row exchanges.  Mode 0 runs on every plane, sets
-// need[q] = 0 and multiplies det[q] by the pivots on success, or sets
+// (a b - f c) mod p for a, b, f, c in [0, p), p < 2^26: both products are
+// below 2^52, so the difference is an exact double and one reduction finishes.
+__device__ __forceinline__ uint32_t mulsub_p(uint32_t a, uint32_t b, uint32_t f, uint32_t c, double pf,
+                                             double pinv) {
+    const double x = fma((double)a, (double)b, -((double)f * (double)c));
+    double r = fma(-rint(x * pinv), pf, x);
+    r = r < 0.0 ? r + pf : r;
+    return (uint32_t)r;
+}
+
+// W[q] = P11^-1 for the pivot block M[r0.., r0..] (bw x bw) by fraction-free
+// Gauss-Jordan on [P11 | I] in LDS without row exchanges: step j leaves the
+// pivot row alone and replaces every other row i by pv_j row_i - T[i][j]
+// row_j (pv_j = T[j][j]), so no step waits for a modular inverse.  Row i then
+// changes only in columns j+1 .. bw+j (beyond them row j is zero) and in its
+// own column (its diagonal, i < j, or its unit column bw+i, i > j), which is
+// only scaled; column j becomes zero.  At the end the left block is diag(d)
+// and the right block R = E (the product of the steps), so P11^-1 = D^-1 R,
+// with the bw inverses taken in parallel.  Each step scales bw-1 rows by
+// pv_j, so det(P11) = prod d_i / prod_j pv_j^(bw-1).  A zero pivot means a
+// zero leading minor, as in the scaled form.  Mode 0 runs on every plane,
+// sets need[q] = 0 and multiplies det[q] by det(P11) on success, or sets
 // need[q] = 1 on a zero pivot (W is then not used); mode 1 runs on the planes
 // with need[q] = 1 after their rows were exchanged (a zero pivot then means
 // a singular plane).
@@ -175,8 +194,9 @@ __global__ __launch_bounds__(1024) void k_gj_blockinv(const uint32_t *__restrict
                                                       int mode) {
     __shared__ uint32_t T[kGjBlockMax][2 * kGjBlockMax];
     __shared__ uint32_t F[kGjBlockMax];
-    __shared__ uint32_t inv, dprod;
-    __shared__ int failed;
+    __shared__ uint32_t PV[kGjBlockMax];
+    __shared__ uint32_t Dinv[kGjBlockMax];
+    __shared__ uint32_t red[kGjBlockMax];
     const int q = blockIdx.x;
     if (singular[q] || (mode == 1 && !need[q])) return;
     const uint32_t *Mq = M + (int64_t)q * n * ld;
@@ -185,57 +205,67 @@ __global__ __launch_bounds__(1024) void k_gj_blockinv(const uint32_t *__restrict
         const int i = e / w2, c = e % w2;
         T[i][c] = c < bw ? Mq[(r0 + i) * ld + r0 + c] : (uint32_t)(c - bw == i);
     }
-    if (threadIdx.x == 0) {
-        failed = 0;
-        dprod = 1;
-    }
     __syncthreads();
     const double pf = pr[q].pf, pinv = pr[q].pinv;
     const uint32_t p = pr[q].p;
+    // Thread t updates window column a0 = t % bw of rows i0, i0 + rstep, ...
+    // (rstep = threads / bw; the threads beyond rstep * bw stay idle).
+    const int rstep = (int)blockDim.x / bw;
+    const int a0 = (int)threadIdx.x % bw, i0 = (int)threadIdx.x / bw;
+    bool failed = false;
     for (int j = 0; j < bw; ++j) {
-        if (threadIdx.x == 0) {
-            const uint32_t pv = T[j][j];
-            if (pv == 0) failed = 1;
-            dprod = mulmod_p(dprod, pv, pf, pinv);
-            inv = powmod_p(pv, p - 2, pf, pinv);
+        const uint32_t pv = T[j][j];                          // the same on every thread
+        if (pv == 0) {
+            failed = true;
+            break;
         }
+        for (int i = threadIdx.x; i < bw; i += blockDim.x) F[i] = T[i][j];
+        if (threadIdx.x == 0) PV[j] = pv;
         __syncthreads();
-        if (failed) break;                                    // the same on every thread
-        // Without row exchanges only bw columns can change at step j: the
-        // left columns j+1 .. bw-1 (those before are reduced to unit
-        // columns) and the right columns bw .. bw+j (row j's right part is
-        // zero beyond column bw+j).  Active column a < bw maps to
-        // j+1+a (a < bw-j-1) or to bw+a-(bw-j-1).
-        const int nleft = bw - j - 1;
-        for (int a = threadIdx.x; a < bw; a += blockDim.x) {
-            const int c = a < nleft ? j + 1 + a : bw + a - nleft;
-            T[j][c] = mulmod_p(T[j][c], inv, pf, pinv);
+        if (i0 < rstep) {
+            const int c = j + 1 + a0;                         // window column, j+1 .. bw+j
+            const uint32_t tj = T[j][c];
+            for (int i = i0; i < bw; i += rstep)
+                if (i != j) T[i][c] = mulsub_p(pv, T[i][c], F[i], tj, pf, pinv);
         }
-        for (int i = threadIdx.x; i < bw; i += blockDim.x) F[i] = i == j ? 0u : T[i][j];
-        __syncthreads();
-        for (int e = threadIdx.x; e < bw * bw; e += blockDim.x) {
-            const int i = e / bw, a = e % bw;
-            if (F[i] == 0) continue;
-            const int c = a < nleft ? j + 1 + a : bw + a - nleft;
-            const uint32_t t = mulmod_p(F[i], T[j][c], pf, pinv);
-            const uint32_t v = T[i][c];
-            T[i][c] = v >= t ? v - t : v + p - t;
+        for (int i = threadIdx.x; i < bw; i += blockDim.x) {
+            if (i == j) continue;
+            const int own = i < j ? i : bw + i;               // outside the window above
+            T[i][own] = mulmod_p(pv, T[i][own], pf, pinv);
+            T[i][j] = 0;
         }
         __syncthreads();
     }
+    if (failed) {
+        if (threadIdx.x == 0) {
+            if (mode == 0) need[q] = 1;
+            else singular[q] = 1;                             // cannot happen after k_gj_panel
+        }
+        return;
+    }
+    const bool want_det = mode == 0 && det != nullptr;
+    for (int i = threadIdx.x; i < bw; i += blockDim.x) {
+        const uint32_t d = T[i][i];
+        Dinv[i] = powmod_p(d, p - 2, pf, pinv);
+        if (want_det) red[i] = mulmod_p(d, powmod_p(PV[i], p - (uint32_t)bw, pf, pinv), pf, pinv);   // d_i pv_i^-(bw-1)
+    }
+    __syncthreads();
+    if (want_det)
+        for (int h = 1; h < bw; h *= 2) {                     // product of red[0 .. bw-1] into red[0]
+            for (int i = threadIdx.x; i < bw; i += blockDim.x)
+                if (i % (2 * h) == 0 && i + h < bw) red[i] = mulmod_p(red[i], red[i + h], pf, pinv);
+            __syncthreads();
+        }
     if (threadIdx.x == 0) {
         if (mode == 0) {
-            need[q] = failed;
-            if (!failed && det) det[q] = mulmod_p(det[q], dprod, pf, pinv);
-        } else if (failed) {
-            singular[q] = 1;                                  // cannot happen after k_gj_panel
+            need[q] = 0;
+            if (want_det) det[q] = mulmod_p(det[q], red[0], pf, pinv);
         }
     }
-    if (failed) return;
     uint32_t *Wq = W + (int64_t)q * kGjBlockMax * kGjBlockMax;   // [bw][bw], stride kGjBlockMax
     for (int e = threadIdx.x; e < bw * bw; e += blockDim.x) {
         const int i = e / bw, c = e % bw;
-        Wq[i * kGjBlockMax + c] = T[i][bw + c];
+        Wq[i * kGjBlockMax + c] = mulmod_p(Dinv[i], T[i][bw + c], pf, pinv);
     }
 }
 
