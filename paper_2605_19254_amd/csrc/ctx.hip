@@ -162,6 +162,7 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
     ctx->auto_path = (flags & 3) == RNS_CTX_PATH_FP64 ? RNS_PATH_FP64
                    : (flags & 3) == RNS_CTX_PATH_INT8 ? RNS_PATH_INT8 : RNS_PATH_AUTO;
     if (const char *e = std::getenv("RNS_INT8_KERNEL")) ctx->int8_kernel = std::atoi(e);
+    if (const char *e = std::getenv("RNS_LIFT_VECTOR")) ctx->lift_vector_only = std::atoi(e) != 0;
     ctx->primes = ps;
 
     std::vector<PrimeConst> pc(L);

@@ -82,6 +82,7 @@ struct rns_ctx {
     std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
     int force_cert_failures = 0;
     int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
+    bool lift_vector_only = false;    // lifting products on the vector units only (RNS_LIFT_VECTOR)
     rns_ctx *aux = nullptr;            // wide-basis context of the Smith-form driver
     // Smith-form solves on this context run on one stream, created by the
     // first, and return their device blocks of up to 64 MiB to a pool (at

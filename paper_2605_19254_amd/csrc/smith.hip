@@ -671,6 +671,9 @@ struct Driver {
     int a_bytes = 4;
     DevBuf<uint32_t> dG;        // [n][2n] Gauss-Jordan of the lifting prime; right half = C
     DevBuf<uint32_t> dC;        // C = A^-1 mod p, [n][ldl], zero beyond column n
+    DevBuf<char> dCt;           // C as tiled digits for the matrix-core lifting products
+    DevBuf<char> dAt;           // int16 A as tiled digits, the same
+    DevBuf<char> dXd, dRmd;     // digit fragments passed between the two lifting products
     DevBuf<uint32_t> dXh;       // lifted digits [K][t][n]
     DevBuf<int64_t> dR0, dR1;   // residuals [t][n]
     DevBuf<uint32_t> dRm0, dRm1;
@@ -812,7 +815,25 @@ struct Driver {
         DRV_HIP(hipMemcpyAsync(dRp.p, Rp.data(), sizeof(int32_t) * Rp.size(), hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), stream));
         DRV_HIP(hipMemsetAsync(dstep.p, 0, sizeof(int64_t), stream));
-        const LiftBufs lb{dR0.p, dR1.p, dRm0.p, dRm1.p, dXh.p, derr.p, dstep.p};
+        LiftBufs lb{dR0.p, dR1.p, dRm0.p, dRm1.p, dXh.p, derr.p, dstep.p};
+        if (n <= kLiftMfmaMaxN && !ctx->lift_vector_only) {   // C's digits, once per lifting
+            DRV_ST(dCt.alloc(lift_tile_c_bytes(n)));
+            launch_lift_tile_c(dC.p, n, ldl, p, dCt.p, stream);
+            DRV_HIP(hipGetLastError());
+            lb.Ct = dCt.p;
+            if (a_bytes == 2) {
+                DRV_ST(dAt.alloc(lift_tile_a_bytes(n)));
+                launch_lift_tile_a(dA16.p, n, ldl, dAt.p, stream);
+                DRV_HIP(hipGetLastError());
+                lb.At = dAt.p;
+                DRV_ST(dXd.alloc(lift_frag_bytes(n)));
+                DRV_ST(dRmd.alloc(lift_frag_bytes(n)));
+                launch_lift_frag(dRm0.p, n, ldl, t, dRmd.p, stream);   // the first step's Rm
+                DRV_HIP(hipGetLastError());
+                lb.Xd = dXd.p;
+                lb.Rmd = dRmd.p;
+            }
+        }
         const void *Adev = a_bytes == 2 ? (const void *)dA16.p : (const void *)dA32.p;
         // Runs of kLiftGraphSteps steps replay one captured graph (the step
         // launches take the same arguments every time); the rest, and every

@@ -50,7 +50,26 @@ struct LiftBufs {
     uint32_t *Xh;
     int32_t *err;
     int64_t *base;
+    const char *Ct = nullptr;   // C as tiled digits (launch_lift_tile_c), or null: products on the vector units
+    const char *At = nullptr;   // int16 A as tiled digits (launch_lift_tile_a), or null
+    char *Xd = nullptr;         // digit fragments of the step's X and of the next Rm (each
+    char *Rmd = nullptr;        // lift_frag_bytes(n)); used when Ct and At are both set
 };
+// Largest n whose lifting products run on the matrix cores (int32 sums of
+// the digit products stay exact for k <= 43690).
+constexpr int64_t kLiftMfmaMaxN = 43690;
+// Bytes of the tiled digits of an n x n residue matrix, and their build
+// (balanced digits of C mod p, 16-row blocks x 64-column steps, the matrix-
+// core operand layout).
+size_t lift_tile_c_bytes(int64_t n);
+void launch_lift_tile_c(const uint32_t *C, int64_t n, int64_t ld, uint32_t p, char *Ct, hipStream_t s);
+// Digit fragments of t <= 16 vectors [t][ld] (the right operand of the
+// lifting products), for the first step's Rm.
+size_t lift_frag_bytes(int64_t n);
+void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, char *frag, hipStream_t s);
+// The same for an int16 A (two exact signed byte digits per entry).
+size_t lift_tile_a_bytes(int64_t n);
+void launch_lift_tile_a(const int16_t *A, int64_t n, int64_t ld, char *At, hipStream_t s);
 // `steps` lifting steps (two launches each) and one launch advancing *base;
 // the launches take the same arguments for every run of the same length.
 void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,

@@ -281,9 +281,11 @@ constexpr int kLiftMaxT = 16;
 // multiple of 4); C and A are zero beyond column n, so every row is read with
 // 16-byte loads and the padding contributes nothing.
 
-// Each wave handles RW consecutive rows, so every load of the right-hand
-// sides (read from L2 by every wave) serves RW rows; the launcher takes RW = 1
-// for small n (more waves to hide memory latency) and up to 4 for large n.
+// Each work-group handles RW consecutive rows; its four waves take one
+// quarter of the columns k each and add their sums through LDS at the end.
+// Every load of the right-hand sides (from L2) serves RW rows, and splitting
+// the columns gives four times as many independent waves as one wave per row
+// block would (the launcher takes RW = 1 for small n and up to 4 for large n).
 
 // X[c][r] = sum_k C[r][k] Rm[c][k] mod p.  Each lane sums at most ld/64
 // products below 2^52 per row (ld <= 65536 keeps that below 2^62), reduces
@@ -298,13 +300,17 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
                                                 const uint32_t *__restrict__ Rm0, const uint32_t *__restrict__ Rm1,
                                                 int t, uint32_t p, uint32_t *__restrict__ Xh,
                                                 const int64_t *__restrict__ base, int off) {
+    static_assert(kLiftRows * T <= 64, "one lane of wave 0 per (row, column) in the final sum");
+    __shared__ uint64_t part[4][kLiftRows][T];
     const int64_t i_step = *base + off;
     const uint32_t *__restrict__ Rm = (i_step & 1) ? Rm1 : Rm0;
     uint32_t *__restrict__ X = Xh + i_step * t * ld;
     const int lane = threadIdx.x & 63;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
-    if (r0 >= n) return;                                 // whole waves only
+    const int wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kLiftRows;
+    if (r0 >= n) return;                                 // whole work-groups only
     const int64_t q = ld / 4;
+    const int64_t kb = q * wave / 4, ke = q * (wave + 1) / 4;
     const uint4 *Cr[kLiftRows];
 #pragma unroll
     for (int rr = 0; rr < kLiftRows; ++rr)               // rows past n re-read row r0 and store nothing
@@ -315,7 +321,7 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
 #pragma unroll
         for (int c = 0; c < T; ++c) acc[rr][c] = 0;
 #pragma unroll 2
-    for (int64_t k = lane; k < q; k += 64) {
+    for (int64_t k = kb + lane; k < ke; k += 64) {
         uint4 rv[T];
 #pragma unroll
         for (int c = 0; c < T; ++c)
@@ -337,10 +343,362 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
             if (c < t) {
                 uint64_t v = acc[rr][c] % p;
 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-                if (lane == 0 && r0 + rr < n) X[(int64_t)c * ld + r0 + rr] = (uint32_t)(v % p);
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                if (lane == 0) part[wave][rr][c] = v;    // below 64 p < 2^32
             }
         }
+    __syncthreads();
+    if (wave == 0) {
+        const int rr = lane / T, c = lane % T;
+        if (rr < kLiftRows && c < t && r0 + rr < n) {
+            const uint64_t v = part[0][rr][c] + part[1][rr][c] + part[2][rr][c] + part[3][rr][c];
+            X[(int64_t)c * ld + r0 + rr] = (uint32_t)(v % p);
+        }
+    }
+}
+
+// --------------------------------------- lifting products on the matrix cores
+// X = C Rm mod p is a residue product with at most 16 columns.  C is fixed
+// for a whole lifting, so its balanced residues are split once into four
+// signed base-256 digits and tiled in the INT8 MFMA operand layout (per
+// 16-row block and 64-column step, four 1 KiB fragments, lane l holding row
+// l%16 and the 16 columns 16(l/16) .. +15).  Each step splits Rm the same way
+// in registers (lane l: right-hand side l%16) and runs the 16 digit-pair
+// products v_mfma_i32_16x16x64_i8 per block and step, summed in int32 per
+// shift group s = i+j; the sums of one group over k <= 43690 columns stay
+// below 2^31 (at most 4 pairs of |d| <= 128 per column, |d3| <= 2).
+
+typedef int v4i_l __attribute__((ext_vector_type(4)));
+
+// Balanced signed base-256 digits of a balanced residue |r| <= (p-1)/2 < 2^25:
+// r = d0 + 2^8 d1 + 2^16 d2 + 2^24 d3, d0..d2 in [-128, 127], |d3| <= 2.
+__device__ __forceinline__ void lift_digits(int32_t r, int32_t (&d)[4]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d[i] = (int32_t)(int8_t)(r & 0xFF);
+        r = (r - d[i]) >> 8;
+    }
+    d[3] = r;
+}
+
+// Digit fragments of 16 residues x[0..15] in [0, p): byte j of word w of
+// fragment i is digit i of x[4w + j].
+__device__ __forceinline__ void lift_pack(const uint32_t (&x)[16], uint32_t p, v4i_l (&f)[4]) {
+    uint32_t w[4][4] = {};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int32_t r = x[e] > (p >> 1) ? (int32_t)x[e] - (int32_t)p : (int32_t)x[e];
+        int32_t d[4];
+        lift_digits(r, d);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i][e >> 2] |= ((uint32_t)d[i] & 0xFFu) << (8 * (e & 3));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = v4i_l{(int)w[i][0], (int)w[i][1], (int)w[i][2], (int)w[i][3]};
+}
+
+// 16 consecutive entries v[k0 .. k0+15] of a padded row (stride ld, a
+// multiple of 4): whole 4-entry chunks at or past ld read as zero.
+__device__ __forceinline__ void lift_load16(const uint32_t *v, int64_t k0, int64_t ld, bool valid,
+                                            uint32_t (&x)[16]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint4 u = {0u, 0u, 0u, 0u};
+        if (valid && k0 + 4 * q < ld) u = *reinterpret_cast<const uint4 *>(v + k0 + 4 * q);
+        x[4 * q] = u.x; x[4 * q + 1] = u.y; x[4 * q + 2] = u.z; x[4 * q + 3] = u.w;
+    }
+}
+
+// One wave per (64-column step kt, 16-row block rb).
+__global__ __launch_bounds__(64) void k_lift_tile_c(const uint32_t *__restrict__ C, int64_t n, int64_t ld,
+                                                    uint32_t p, int KT, v4i_l *__restrict__ Ct) {
+    const int kt = blockIdx.x;
+    const int64_t rb = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int64_t row = rb * 16 + (lane & 15);
+    uint32_t x[16];
+    lift_load16(C + row * ld, (int64_t)kt * 64 + 16 * (lane >> 4), ld, row < n, x);
+    v4i_l f[4];
+    lift_pack(x, p, f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Ct[((rb * KT + kt) * 4 + i) * 64 + lane] = f[i];
+}
+
+// (sum_s C_s 2^(8s)) mod p in [0, p) for the seven shift-group sums, every
+// step an exact double operation (|C_s| < 2^31): lo and mid below 2^48,
+// mid reduced to a balanced residue, then lo + rm (2^24 mod p) + C_6 (2^48
+// mod p) below 2^53 with balanced weights, and a final reduction whose
+// quotient can be off by one only next to +-p/2 (then one +p fixes it).
+__device__ __forceinline__ uint32_t lift_recombine(const int32_t (&c)[7], double pf, double pinv, double w24,
+                                                   double w48) {
+    const double lo = fma((double)c[2], 65536.0, fma((double)c[1], 256.0, (double)c[0]));
+    const double mid = fma((double)c[5], 65536.0, fma((double)c[4], 256.0, (double)c[3]));
+    const double rm = fma(-rint(mid * pinv), pf, mid);
+    const double sum = fma((double)c[6], w48, fma(rm, w24, lo));
+    double r = fma(-rint(sum * pinv), pf, sum);
+    r = r < 0.0 ? r + pf : r;
+    return (uint32_t)r;
+}
+
+// Exact base-256 digits of 16 values x in [0, 2^26): digit fragments as in
+// lift_pack, without the reduction to balanced residues.
+__device__ __forceinline__ void lift_pack_exact(const uint32_t (&x)[16], v4i_l (&f)[4]) {
+    uint32_t w[4][4] = {};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        int32_t d[4];
+        lift_digits((int32_t)x[e], d);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i][e >> 2] |= ((uint32_t)d[i] & 0xFFu) << (8 * (e & 3));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = v4i_l{(int)w[i][0], (int)w[i][1], (int)w[i][2], (int)w[i][3]};
+}
+
+// The right-hand sides of the next product as ready digit fragments: the
+// 16 x 16 block of a work-group (tile[c][j] = value of column c at row
+// 16 rb + j, rows past n zero) becomes lanes 16 (rb % 4) .. +15 of the four
+// digit fragments of 64-row step rb / 4 (exact base-256 digits, as the
+// product's right operand takes them).  One wave; its LDS writes precede
+// these reads in program order.
+__device__ __forceinline__ void lift_emit_frag(const uint32_t (&tile)[16][17], int64_t rb, int lane,
+                                               v4i_l *__restrict__ frag) {
+    if (lane >= 16) return;
+    uint32_t x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = tile[lane][j];
+    v4i_l f[4];
+    lift_pack_exact(x, f);
+    const int64_t kt = rb >> 2;
+    const int slot = (int)(rb & 3) * 16 + lane;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) frag[(kt * 4 + i) * 64 + slot] = f[i];
+}
+
+// Digit fragments of t <= 16 vectors v [t][ld] (entries in [0, p), rows past
+// n zero): one wave per 64-row step, lane l taking vector l%16 and rows
+// 16 (l/16) .. +15.
+__global__ __launch_bounds__(64) void k_lift_frag(const uint32_t *__restrict__ v, int64_t n, int64_t ld, int t,
+                                                  v4i_l *__restrict__ frag) {
+    const int kt = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c = lane & 15;
+    const int64_t k0 = (int64_t)kt * 64 + 16 * (lane >> 4);
+    uint32_t x[16];
+    lift_load16(v + (int64_t)(c < t ? c : 0) * ld, k0, ld, c < t, x);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (k0 + j >= n) x[j] = 0;
+    v4i_l f[4];
+    lift_pack_exact(x, f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) frag[((int64_t)kt * 4 + i) * 64 + lane] = f[i];
+}
+
+// X[c][r] = sum_k C[r][k] Rm[c][k] mod p for one 16-row block per work-group;
+// its KS waves take KS slices of the 64-column steps and add their int32
+// sums in LDS.  Same step indexing as k_lift_x.
+template <int KS, bool FRAG>
+__global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_x_mfma(const v4i_l *__restrict__ Ct, int64_t n, int64_t ld,
+                                                         int KT, const uint32_t *__restrict__ Rm0,
+                                                         const uint32_t *__restrict__ Rm1, int t, uint32_t p,
+                                                         uint32_t *__restrict__ Xh,
+                                                         const int64_t *__restrict__ base, int off,
+                                                         const v4i_l *__restrict__ Rmd, v4i_l *__restrict__ Xd) {
+    __shared__ v4i_l part[KS][7][64];
+    const int64_t i_step = *base + off;
+    const uint32_t *__restrict__ Rm = (i_step & 1) ? Rm1 : Rm0;
+    uint32_t *__restrict__ X = Xh + i_step * t * ld;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t rb = blockIdx.x;
+    const int kt0 = (int)((int64_t)KT * wave / KS), kt1 = (int)((int64_t)KT * (wave + 1) / KS);
+    const int c = lane & 15;
+    const bool cvalid = c < t;
+    const uint32_t *rmc = Rm + (int64_t)(cvalid ? c : 0) * ld;
+    const v4i_l *cf = Ct + rb * KT * 256 + lane;
+    v4i_l acc[7];
+#pragma unroll
+    for (int g = 0; g < 7; ++g) acc[g] = v4i_l{0, 0, 0, 0};
+    // Fragments of step kt+1 are loaded before the products of step kt.
+    v4i_l a[4], b[4], an[4], bn[4];
+    auto load = [&](int kt, v4i_l (&ar)[4], v4i_l (&br)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ar[i] = cf[(int64_t)kt * 256 + i * 64];
+        if constexpr (FRAG) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) br[i] = Rmd[((int64_t)kt * 4 + i) * 64 + lane];
+        } else {
+            uint32_t x[16];
+            lift_load16(rmc, (int64_t)kt * 64 + 16 * (lane >> 4), ld, cvalid, x);
+            lift_pack(x, p, br);
+        }
+    };
+    if (kt0 < kt1) load(kt0, a, b);
+    for (int kt = kt0; kt < kt1; ++kt) {
+        if (kt + 1 < kt1) load(kt + 1, an, bn);
+#pragma unroll
+        for (int da = 0; da < 4; ++da)
+#pragma unroll
+            for (int db = 0; db < 4; ++db)
+                acc[da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[db], acc[da + db], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a[i] = an[i];
+            b[i] = bn[i];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 7; ++g) part[wave][g][lane] = acc[g];
+    __syncthreads();
+    if (wave != 0) return;
+    __shared__ uint32_t tile16[16][17];
+    const double pf = (double)p, pinv = 1.0 / pf;
+    const double w24 = fma(-rint(16777216.0 * pinv), pf, 16777216.0);            // 2^24 mod p, balanced
+    const double w48 = fma(-rint(281474976710656.0 * pinv), pf, 281474976710656.0);   // 2^48 mod p, balanced
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int32_t cs[7];
+#pragma unroll
+        for (int g = 0; g < 7; ++g) {
+            int32_t sum = 0;
+#pragma unroll
+            for (int w = 0; w < KS; ++w) sum += part[w][g][lane][v];
+            cs[g] = sum;
+        }
+        // 16x16x64 INT8 output layout: register v of lane l is row 4(l/16) + v, column l%16.
+        const int64_t row = rb * 16 + 4 * (lane >> 4) + v;
+        const uint32_t xr = lift_recombine(cs, pf, pinv, w24, w48);
+        if (cvalid && row < n) X[(int64_t)c * ld + row] = xr;
+        if constexpr (FRAG) tile16[c][4 * (lane >> 4) + v] = (cvalid && row < n) ? xr : 0u;
+    }
+    if constexpr (FRAG) lift_emit_frag(tile16, rb, lane, Xd);
+}
+
+// The residual update on the matrix cores, for A held as int16: A splits
+// exactly into two signed bytes (a = a0 + 2^8 a1, |a| < 2^15), X in [0, p)
+// into four base-256 digits (the top one in [0, 4]); the 8 digit pairs fall
+// into 5 shift groups with at most 2 pairs each, so an int32 group sum over
+// k <= 43690 columns stays below 2^31, and sum_s S_s 2^(8s) is the exact
+// product sum in int64.  A's digits are tiled once per lifting (two 1 KiB
+// fragments per 16-row block and 64-column step).
+
+// One wave per (64-column step kt, 16-row block rb).
+__global__ __launch_bounds__(64) void k_lift_tile_a(const int16_t *__restrict__ A, int64_t n, int64_t ld, int KT,
+                                                    v4i_l *__restrict__ At) {
+    const int kt = blockIdx.x;
+    const int64_t rb = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int64_t row = rb * 16 + (lane & 15);
+    const int64_t k0 = (int64_t)kt * 64 + 16 * (lane >> 4);
+    uint32_t w[2][4] = {};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {                        // 8 entries per 16-byte chunk; ld is a multiple of 8
+        int4 u = {0, 0, 0, 0};
+        if (row < n && k0 + 8 * h < ld) u = *reinterpret_cast<const int4 *>(A + row * ld + k0 + 8 * h);
+        const int32_t q[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int32_t a = (int32_t)(int16_t)((q[e >> 1] >> (16 * (e & 1))) & 0xFFFF);
+            const int32_t a0 = (int32_t)(int8_t)(a & 0xFF), a1 = (a - a0) >> 8;
+            const int idx = 8 * h + e;                   // entry k0 + idx
+            w[0][idx >> 2] |= ((uint32_t)a0 & 0xFFu) << (8 * (idx & 3));
+            w[1][idx >> 2] |= ((uint32_t)a1 & 0xFFu) << (8 * (idx & 3));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        At[((rb * KT + kt) * 2 + i) * 64 + lane] = v4i_l{(int)w[i][0], (int)w[i][1], (int)w[i][2], (int)w[i][3]};
+}
+
+// R'[c][r] = (R[c][r] - sum_k A[r][k] X[c][k]) / p, Rm'[c][r] = R' mod p, for
+// one 16-row block per work-group (KS waves over slices of the steps, sums
+// added in LDS).  Same step indexing and error flag as k_lift_r.
+template <int KS, bool FRAG>
+__global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__restrict__ At, int64_t n,
+                                                                 int64_t ld, int KT,
+                                                                 const uint32_t *__restrict__ Xh,
+                                                                 int64_t *__restrict__ R0, int64_t *__restrict__ R1,
+                                                                 uint32_t *__restrict__ Rm0,
+                                                                 uint32_t *__restrict__ Rm1, int t, uint32_t p,
+                                                                 int32_t *__restrict__ err,
+                                                                 const int64_t *__restrict__ base, int off,
+                                                                 const v4i_l *__restrict__ Xd,
+                                                                 v4i_l *__restrict__ Rmd) {
+    __shared__ v4i_l part[KS][5][64];
+    const int64_t i_step = *base + off;
+    const uint32_t *__restrict__ X = Xh + i_step * t * ld;
+    const int64_t *__restrict__ R = (i_step & 1) ? R1 : R0;
+    int64_t *__restrict__ Rn = (i_step & 1) ? R0 : R1;
+    uint32_t *__restrict__ Rmn = (i_step & 1) ? Rm0 : Rm1;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t rb = blockIdx.x;
+    const int kt0 = (int)((int64_t)KT * wave / KS), kt1 = (int)((int64_t)KT * (wave + 1) / KS);
+    const int c = lane & 15;
+    const bool cvalid = c < t;
+    const uint32_t *xc = X + (int64_t)(cvalid ? c : 0) * ld;
+    const v4i_l *af = At + rb * KT * 128 + lane;
+    v4i_l acc[5];
+#pragma unroll
+    for (int g = 0; g < 5; ++g) acc[g] = v4i_l{0, 0, 0, 0};
+    // Fragments of step kt+1 are loaded before the products of step kt.
+    v4i_l a[2], b[4], an[2], bn[4];
+    auto load = [&](int kt, v4i_l (&ar)[2], v4i_l (&br)[4]) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) ar[i] = af[(int64_t)kt * 128 + i * 64];
+        if constexpr (FRAG) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) br[i] = Xd[((int64_t)kt * 4 + i) * 64 + lane];
+        } else {
+            uint32_t x[16];
+            lift_load16(xc, (int64_t)kt * 64 + 16 * (lane >> 4), ld, cvalid, x);
+            lift_pack_exact(x, br);
+        }
+    };
+    if (kt0 < kt1) load(kt0, a, b);
+    for (int kt = kt0; kt < kt1; ++kt) {
+        if (kt + 1 < kt1) load(kt + 1, an, bn);
+#pragma unroll
+        for (int da = 0; da < 2; ++da)
+#pragma unroll
+            for (int db = 0; db < 4; ++db)
+                acc[da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[db], acc[da + db], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i < 2) a[i] = an[i];
+            b[i] = bn[i];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 5; ++g) part[wave][g][lane] = acc[g];
+    __syncthreads();
+    if (wave != 0) return;
+    __shared__ uint32_t tile16[16][17];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int64_t sum = 0;
+#pragma unroll
+        for (int g = 0; g < 5; ++g) {
+            int32_t sg = 0;
+#pragma unroll
+            for (int w = 0; w < KS; ++w) sg += part[w][g][lane][v];
+            sum += (int64_t)sg << (8 * g);
+        }
+        const int64_t r = rb * 16 + 4 * (lane >> 4) + v;
+        uint32_t rm = 0;
+        if (cvalid && r < n) {
+            const int64_t num = R[(int64_t)c * ld + r] - sum;
+            const int64_t qq = num / (int64_t)p;
+            if (qq * (int64_t)p != num) atomicOr(err, 1);
+            Rn[(int64_t)c * ld + r] = qq;
+            const int64_t m = qq % (int64_t)p;
+            rm = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+            Rmn[(int64_t)c * ld + r] = rm;
+        }
+        if constexpr (FRAG) tile16[c][4 * (lane >> 4) + v] = rm;
+    }
+    if constexpr (FRAG) lift_emit_frag(tile16, rb, lane, Rmd);
 }
 
 // R'[c][r] = (R[c][r] - sum_k A[r][k] X[c][k]) / p and Rm'[c][r] = R' mod p.
@@ -364,16 +722,29 @@ __device__ __forceinline__ void unpack_a(const int4 raw, int32_t (&a)[16 / sizeo
     }
 }
 
-// The rows r0 .. r0+kLiftRows-1 of one step of k_lift_r (one wave).
+// One step of k_lift_r for the rows r0 .. r0+kLiftRows-1 of one work-group:
+// wave w sums the columns of its quarter, the four sums meet in LDS.
 template <int T, int kLiftRows, typename AT>
-__device__ __forceinline__ void lift_r_rows(const AT *__restrict__ A, int64_t n, int64_t ld,
-                                            const uint32_t *__restrict__ X,
-                                            const int64_t *__restrict__ R, int t, uint32_t p,
-                                            int64_t *__restrict__ Rn, uint32_t *__restrict__ Rmn,
-                                            int32_t *__restrict__ err, int64_t r0) {
+__global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_t n, int64_t ld,
+                                                const uint32_t *__restrict__ Xh,
+                                                int64_t *__restrict__ R0, int64_t *__restrict__ R1,
+                                                uint32_t *__restrict__ Rm0, uint32_t *__restrict__ Rm1,
+                                                int t, uint32_t p, int32_t *__restrict__ err,
+                                                const int64_t *__restrict__ base, int off) {
+    static_assert(kLiftRows * T <= 64, "one lane of wave 0 per (row, column) in the final sum");
     constexpr int kPer = 16 / (int)sizeof(AT);   // entries of A per 16-byte load
+    __shared__ int64_t part[4][kLiftRows][T];
+    const int64_t i_step = *base + off;
+    const uint32_t *__restrict__ X = Xh + i_step * t * ld;
+    const int64_t *__restrict__ R = (i_step & 1) ? R1 : R0;
+    int64_t *__restrict__ Rn = (i_step & 1) ? R0 : R1;
+    uint32_t *__restrict__ Rmn = (i_step & 1) ? Rm0 : Rm1;
     const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kLiftRows;
+    if (r0 >= n) return;                                 // whole work-groups only
     const int64_t q = ld / kPer;
+    const int64_t kb = q * wave / 4, ke = q * (wave + 1) / 4;
     const int4 *Ar[kLiftRows];
 #pragma unroll
     for (int rr = 0; rr < kLiftRows; ++rr)
@@ -384,7 +755,7 @@ __device__ __forceinline__ void lift_r_rows(const AT *__restrict__ A, int64_t n,
 #pragma unroll
         for (int c = 0; c < T; ++c) acc[rr][c] = 0;
 #pragma unroll 2
-    for (int64_t k = lane; k < q; k += 64) {
+    for (int64_t k = kb + lane; k < ke; k += 64) {
         uint32_t xv[T][kPer];
 #pragma unroll
         for (int c = 0; c < T; ++c)
@@ -416,33 +787,23 @@ __device__ __forceinline__ void lift_r_rows(const AT *__restrict__ A, int64_t n,
             if (c >= t) continue;
             int64_t v = acc[rr][c];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            const int64_t r = r0 + rr;
-            if (lane == 0 && r < n) {
-                const int64_t num = R[(int64_t)c * ld + r] - v;
-                const int64_t qq = num / (int64_t)p;
-                if (qq * (int64_t)p != num) atomicOr(err, 1);
-                Rn[(int64_t)c * ld + r] = qq;
-                const int64_t m = qq % (int64_t)p;
-                Rmn[(int64_t)c * ld + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
-            }
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) part[wave][rr][c] = v;
         }
-}
-
-template <int T, int kLiftRows, typename AT>
-__global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_t n, int64_t ld,
-                                                const uint32_t *__restrict__ Xh,
-                                                int64_t *__restrict__ R0, int64_t *__restrict__ R1,
-                                                uint32_t *__restrict__ Rm0, uint32_t *__restrict__ Rm1,
-                                                int t, uint32_t p, int32_t *__restrict__ err,
-                                                const int64_t *__restrict__ base, int off) {
-    const int64_t i_step = *base + off;
-    const uint32_t *__restrict__ X = Xh + i_step * t * ld;
-    const int64_t *__restrict__ R = (i_step & 1) ? R1 : R0;
-    int64_t *__restrict__ Rn = (i_step & 1) ? R0 : R1;
-    uint32_t *__restrict__ Rmn = (i_step & 1) ? Rm0 : Rm1;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kLiftRows;
-    if (r0 < n) lift_r_rows<T, kLiftRows, AT>(A, n, ld, X, R, t, p, Rn, Rmn, err, r0);
+    __syncthreads();
+    if (wave == 0) {
+        const int rr = lane / T, c = lane % T;
+        const int64_t r = r0 + rr;
+        if (rr < kLiftRows && c < t && r < n) {
+            const int64_t v = part[0][rr][c] + part[1][rr][c] + part[2][rr][c] + part[3][rr][c];
+            const int64_t num = R[(int64_t)c * ld + r] - v;
+            const int64_t qq = num / (int64_t)p;
+            if (qq * (int64_t)p != num) atomicOr(err, 1);
+            Rn[(int64_t)c * ld + r] = qq;
+            const int64_t m = qq % (int64_t)p;
+            Rmn[(int64_t)c * ld + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+        }
+    }
 }
 
 // *base += steps (one thread), after a run of steps.
@@ -728,17 +1089,51 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
 template <int T, int RW, typename AT>
 static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
                         const LiftBufs &b, int off, hipStream_t s) {
-    const unsigned blocks = (unsigned)((n + 4 * RW - 1) / (4 * RW));
-    hipLaunchKernelGGL((k_lift_x<T, RW>), dim3(blocks), dim3(256), 0, s, C, n, ld, b.Rm0, b.Rm1, t, p, b.Xh,
-                       b.base, off);
-    hipLaunchKernelGGL((k_lift_r<T, RW, AT>), dim3(blocks), dim3(256), 0, s, A, n, ld, b.Xh, b.R0, b.R1, b.Rm0,
-                       b.Rm1, t, p, b.err, b.base, off);
+    const unsigned blocks = (unsigned)((n + RW - 1) / RW);   // one work-group per RW rows
+    // With both operands tiled the two products pass each other their right
+    // operands as digit fragments (Xd, Rmd); with C alone the first product
+    // splits Rm itself.
+    const bool frag = b.Ct && b.At && sizeof(AT) == 2 && b.Xd && b.Rmd;
+    const v4i_l *rmd = reinterpret_cast<const v4i_l *>(b.Rmd);
+    v4i_l *xd = reinterpret_cast<v4i_l *>(b.Xd);
+    if (b.Ct) {
+        const int KT = (int)((n + 63) / 64);
+        const unsigned rbs = (unsigned)((n + 15) / 16);
+        const v4i_l *ct = reinterpret_cast<const v4i_l *>(b.Ct);
+        // Eight waves per 16-row block, two work-groups per CU.
+        if (frag)
+            hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(rbs), dim3(512), 0, s, ct, n, ld, KT, b.Rm0, b.Rm1, t, p,
+                               b.Xh, b.base, off, rmd, xd);
+        else
+            hipLaunchKernelGGL((k_lift_x_mfma<8, false>), dim3(rbs), dim3(512), 0, s, ct, n, ld, KT, b.Rm0, b.Rm1, t,
+                               p, b.Xh, b.base, off, rmd, xd);
+    } else {
+        hipLaunchKernelGGL((k_lift_x<T, RW>), dim3(blocks), dim3(256), 0, s, C, n, ld, b.Rm0, b.Rm1, t, p, b.Xh,
+                           b.base, off);
+    }
+    if (b.At && sizeof(AT) == 2) {
+        const int KT = (int)((n + 63) / 64);
+        const unsigned rbs = (unsigned)((n + 15) / 16);
+        const v4i_l *at = reinterpret_cast<const v4i_l *>(b.At);
+        const v4i_l *xdc = reinterpret_cast<const v4i_l *>(b.Xd);
+        v4i_l *rmdw = reinterpret_cast<v4i_l *>(b.Rmd);
+        if (frag)
+            hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(rbs), dim3(512), 0, s, at, n, ld, KT, b.Xh, b.R0, b.R1,
+                               b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw);
+        else
+            hipLaunchKernelGGL((k_lift_r_mfma<8, false>), dim3(rbs), dim3(512), 0, s, at, n, ld, KT, b.Xh, b.R0,
+                               b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw);
+    } else {
+        hipLaunchKernelGGL((k_lift_r<T, RW, AT>), dim3(blocks), dim3(256), 0, s, A, n, ld, b.Xh, b.R0, b.R1,
+                           b.Rm0, b.Rm1, t, p, b.err, b.base, off);
+    }
 }
 
 template <int T, typename AT>
 static void lift_step_rw(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
                          const LiftBufs &b, int off, hipStream_t s) {
-    // About 2048 waves or more: 8 per CU.
+    // Rows per work-group: more for large n, where the work-groups are many
+    // anyway and each right-hand-side load then serves more rows.
     if (n >= 4 * 2048) lift_step_t<T, 4, AT>(C, A, n, ld, t, p, b, off, s);
     else if (n >= 2 * 2048) lift_step_t<T, 2, AT>(C, A, n, ld, t, p, b, off, s);
     else lift_step_t<T, 1, AT>(C, A, n, ld, t, p, b, off, s);
@@ -750,6 +1145,32 @@ static void lift_step_at(const uint32_t *C, const AT *A, int64_t n, int64_t ld, 
     if (t <= 4) lift_step_rw<4, AT>(C, A, n, ld, t, p, b, off, s);
     else if (t <= 8) lift_step_rw<8, AT>(C, A, n, ld, t, p, b, off, s);
     else lift_step_rw<kLiftMaxT, AT>(C, A, n, ld, t, p, b, off, s);
+}
+
+size_t lift_tile_c_bytes(int64_t n) { return (size_t)((n + 15) / 16) * (size_t)((n + 63) / 64) * 4096; }
+
+void launch_lift_tile_c(const uint32_t *C, int64_t n, int64_t ld, uint32_t p, char *Ct, hipStream_t s) {
+    if (n <= 0) return;
+    const int KT = (int)((n + 63) / 64);
+    hipLaunchKernelGGL(k_lift_tile_c, dim3((unsigned)KT, (unsigned)((n + 15) / 16)), dim3(64), 0, s, C, n, ld, p,
+                       KT, reinterpret_cast<v4i_l *>(Ct));
+}
+
+size_t lift_frag_bytes(int64_t n) { return (size_t)((n + 63) / 64) * 4096; }
+
+void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, char *frag, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_lift_frag, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, v, n, ld, t,
+                       reinterpret_cast<v4i_l *>(frag));
+}
+
+size_t lift_tile_a_bytes(int64_t n) { return (size_t)((n + 15) / 16) * (size_t)((n + 63) / 64) * 2048; }
+
+void launch_lift_tile_a(const int16_t *A, int64_t n, int64_t ld, char *At, hipStream_t s) {
+    if (n <= 0) return;
+    const int KT = (int)((n + 63) / 64);
+    hipLaunchKernelGGL(k_lift_tile_a, dim3((unsigned)KT, (unsigned)((n + 15) / 16)), dim3(64), 0, s, A, n, ld, KT,
+                       reinterpret_cast<v4i_l *>(At));
 }
 
 void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
