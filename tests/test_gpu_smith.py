@@ -206,6 +206,23 @@ def test_lifting_forced_matches_oracle(lifting_ctx, rg, n, seed, bound):
     assert res.stats["path"] == 1 and res.stats["cert_exact"] == 1
 
 
+def test_lifting_vector_kernels_match(rg, monkeypatch):
+    """The lifting products on the vector units (RNS_LIFT_VECTOR=1, read when
+    a context is created) give the same invariants as the default matrix-core
+    products; both are checked against the stored golden values."""
+    case = _GOLDEN["cases"][0]
+    _say("smith lifting, vector kernels", case)
+    a = _golden_matrix(case)
+    monkeypatch.setenv("RNS_LIFT_VECTOR", "1")
+    vctx = rg.Context(device=0, L=24)
+    monkeypatch.delenv("RNS_LIFT_VECTOR")
+    try:
+        res = rg.smith_form(vctx, a, seed=case["seed"])
+    finally:
+        vctx.close()
+    assert res.s == _golden_s(case) and res.stats["path"] == 1 and res.stats["lift_steps"] > 0
+
+
 def test_lifting_restart_seed_and_errors(lifting_ctx, rg):
     ctx = lifting_ctx
     _say("smith lifting restart / seed / singular / not applicable")
