@@ -1,8 +1,8 @@
 // Host-side arbitrary-precision signed integers for the Smith-form driver
 // (the big numbers of Section 2: the largest invariant factor s, p-adic
 // lifting sums, rational reconstruction).  Sign and magnitude, 32-bit limbs,
-// schoolbook multiplication and Knuth's long division; sizes here stay at a
-// few thousand limbs.
+// Karatsuba products, Knuth's long division and Barrett reduction for a fixed
+// modulus; sizes here reach some ten thousand limbs.
 #pragma once
 
 #include <algorithm>
@@ -130,26 +130,114 @@ public:
         while (!r.empty() && r.back() == 0) r.pop_back();
         return r;
     }
+    // ---- products: schoolbook below kKaraLimbs limbs, Karatsuba above.
+    static constexpr size_t kKaraLimbs = 40;
+
+    // r[0 .. na+nb) = a b (r is overwritten).
+    static void mul_school(const uint32_t *a, size_t na, const uint32_t *b, size_t nb, uint32_t *r) {
+        std::fill(r, r + na + nb, 0u);
+        for (size_t j = 0; j < nb; ++j) {
+            const uint64_t bj = b[j];
+            uint64_t c = 0;
+            if (bj)
+                for (size_t i = 0; i < na; ++i) {
+                    c += a[i] * bj + r[i + j];
+                    r[i + j] = (uint32_t)c;
+                    c >>= 32;
+                }
+            r[j + na] = (uint32_t)c;
+        }
+    }
+    // r[0 .. n) += a[0 .. na), na <= n; returns the carry out of r[n-1].
+    static uint32_t add_into(uint32_t *r, size_t n, const uint32_t *a, size_t na) {
+        uint64_t c = 0;
+        size_t i = 0;
+        for (; i < na; ++i) {
+            c += (uint64_t)r[i] + a[i];
+            r[i] = (uint32_t)c;
+            c >>= 32;
+        }
+        for (; c && i < n; ++i) {
+            c += r[i];
+            r[i] = (uint32_t)c;
+            c >>= 32;
+        }
+        return (uint32_t)c;
+    }
+    // r[0 .. n) -= a[0 .. na), na <= n; returns the borrow out of r[n-1].
+    static uint32_t sub_into(uint32_t *r, size_t n, const uint32_t *a, size_t na) {
+        int64_t br = 0;
+        size_t i = 0;
+        for (; i < na; ++i) {
+            const int64_t t = (int64_t)r[i] - a[i] - br;
+            br = t < 0;
+            r[i] = (uint32_t)t;
+        }
+        for (; br && i < n; ++i) {
+            const int64_t t = (int64_t)r[i] - br;
+            br = t < 0;
+            r[i] = (uint32_t)t;
+        }
+        return (uint32_t)br;
+    }
+    // Scratch limbs that kara needs for n-limb operands.
+    static size_t kara_scratch(size_t n) {
+        return n < kKaraLimbs ? 0 : 4 * (n - n / 2 + 1) + kara_scratch(n - n / 2 + 1);
+    }
+    // r[0 .. 2n) = a b for two n-limb operands (Karatsuba: with a = a0 + a1 B^h,
+    // b likewise, a b = z0 + (z1 - z0 - z2) B^h + z2 B^2h for z0 = a0 b0,
+    // z2 = a1 b1, z1 = (a0 + a1)(b0 + b1)).  w: kara_scratch(n) limbs.
+    static void kara(const uint32_t *a, const uint32_t *b, size_t n, uint32_t *r, uint32_t *w) {
+        if (n < kKaraLimbs) {
+            mul_school(a, n, b, n, r);
+            return;
+        }
+        const size_t lo = n / 2, hi = n - lo;
+        kara(a, b, lo, r, w);                            // z0 -> r[0, 2 lo)
+        kara(a + lo, b + lo, hi, r + 2 * lo, w);         // z2 -> r[2 lo, 2 n)
+        uint32_t *sa = w, *sb = w + hi + 1, *z1 = w + 2 * (hi + 1);
+        std::copy(a + lo, a + n, sa);
+        sa[hi] = add_into(sa, hi, a, lo);
+        std::copy(b + lo, b + n, sb);
+        sb[hi] = add_into(sb, hi, b, lo);
+        kara(sa, sb, hi + 1, z1, w + 4 * (hi + 1));
+        sub_into(z1, 2 * hi + 2, r, 2 * lo);
+        sub_into(z1, 2 * hi + 2, r + 2 * lo, 2 * hi);
+        // z1 - z0 - z2 = a0 b1 + a1 b0 < 2 B^n: its limbs above n are zero.
+        add_into(r + lo, 2 * n - lo, z1, std::min(2 * hi + 2, 2 * n - lo));
+    }
+    // r[0 .. na+nb) = a b for any sizes: Karatsuba on equal pieces of the
+    // longer operand, each the length of the shorter.
+    static void mul_into(const uint32_t *a, size_t na, const uint32_t *b, size_t nb, uint32_t *r) {
+        if (na < nb) {
+            std::swap(a, b);
+            std::swap(na, nb);
+        }
+        if (nb < kKaraLimbs) {
+            mul_school(a, na, b, nb, r);
+            return;
+        }
+        const size_t ws = kara_scratch(nb);
+        std::vector<uint32_t> w(ws + (na == nb ? 0 : 2 * nb));
+        if (na == nb) {
+            kara(a, b, nb, r, w.data());
+            return;
+        }
+        uint32_t *t = w.data() + ws;
+        std::fill(r, r + na + nb, 0u);
+        for (size_t off = 0; off < na; off += nb) {
+            const size_t len = std::min(nb, na - off);
+            if (len == nb)
+                kara(a + off, b, nb, t, w.data());
+            else
+                mul_into(a + off, len, b, nb, t);
+            add_into(r + off, na + nb - off, t, len + nb);
+        }
+    }
     static std::vector<uint32_t> mul_mag(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) {
         if (a.empty() || b.empty()) return {};
-        std::vector<uint32_t> r(a.size() + b.size(), 0);
-        for (size_t i = 0; i < a.size(); ++i) {
-            uint64_t c = 0;
-            const uint64_t ai = a[i];
-            if (!ai) continue;
-            for (size_t j = 0; j < b.size(); ++j) {
-                c += ai * b[j] + r[i + j];
-                r[i + j] = (uint32_t)c;
-                c >>= 32;
-            }
-            size_t k = i + b.size();
-            while (c) {
-                c += r[k];
-                r[k] = (uint32_t)c;
-                c >>= 32;
-                ++k;
-            }
-        }
+        std::vector<uint32_t> r(a.size() + b.size());
+        mul_into(a.data(), a.size(), b.data(), b.size(), r.data());
         while (!r.empty() && r.back() == 0) r.pop_back();
         return r;
     }
@@ -312,9 +400,10 @@ public:
     friend bool operator>(const BigInt &a, const BigInt &b) { return cmp(a, b) > 0; }
 
     // ---- Euclid's algorithm, Lehmer's way (Knuth TAOCP 4.5.2, Algorithm L):
-    // far from the end, runs of quotients are found from the leading 62 bits
-    // of the two remainders and applied to the full numbers as one 2 x 2
-    // matrix; the cofactor sequence (t0, t1) follows the same matrices.
+    // far from the end, runs of quotients are found from the leading 124 bits
+    // of the two remainders (128-bit arithmetic, so that a run goes on until
+    // its matrix entries near 2^62) and applied to the full numbers as one
+    // 2 x 2 matrix; the cofactor sequence (t0, t1) follows the same matrices.
 
     // One exact step: (r0, r1) <- (r1, r0 - q r1), (t0, t1) <- (t1, t0 - q t1).
     static void euclid_step(BigInt &r0, BigInt &r1, BigInt &t0, BigInt &t1, bool track) {
@@ -328,15 +417,17 @@ public:
             t1 = std::move(t);
         }
     }
-    // floor(|x| / 2^shift) mod 2^64.
-    static uint64_t shifted_u64(const BigInt &x, size_t shift) {
+    // floor(|x| / 2^shift) mod 2^128.
+    static unsigned __int128 shifted_u128(const BigInt &x, size_t shift) {
         const size_t w = shift / 32, b = shift % 32;
         unsigned __int128 v = 0;
-        for (int i = 2; i >= 0; --i) {
+        for (int i = 3; i >= 0; --i) {
             const size_t idx = w + (size_t)i;
             v = (v << 32) | (idx < x.mag.size() ? x.mag[idx] : 0u);
         }
-        return (uint64_t)(v >> b);
+        const size_t top = w + 4;                        // the bits above the four limbs
+        const uint32_t hi = top < x.mag.size() ? x.mag[top] : 0u;
+        return b ? (v >> b) | ((unsigned __int128)hi << (128 - b)) : v;
     }
     // a x - b y for magnitudes when the result is >= 0 (a, b < 2^63).
     static std::vector<uint32_t> lin_sub_mag(const std::vector<uint32_t> &x, uint64_t a,
@@ -373,21 +464,23 @@ public:
     // while r1 has more than stop_bits + 130 bits; the caller finishes with
     // euclid_step.
     static void lehmer_run(BigInt &r0, BigInt &r1, BigInt &t0, BigInt &t1, size_t stop_bits, bool track) {
+        // |A|, |B|, |C|, |D| < lim; the leading digits are below 2^124, so
+        // every sum, product and quotient below fits a signed 128-bit word.
         const __int128 lim = (__int128)1 << 62;
         while (!r1.is_zero() && r1.bit_length() > stop_bits + 130) {
-            const size_t shift = r0.bit_length() - 62;
-            int64_t uh = (int64_t)shifted_u64(r0, shift), vh = (int64_t)shifted_u64(r1, shift);
+            const size_t shift = r0.bit_length() - 124;
+            __int128 uh = (__int128)shifted_u128(r0, shift), vh = (__int128)shifted_u128(r1, shift);
             int64_t A = 1, B = 0, C = 0, D = 1;
             for (;;) {
-                const __int128 dc = (__int128)vh + C, dd = (__int128)vh + D;
-                if (dc == 0 || dd == 0) break;
-                const __int128 q1 = ((__int128)uh + A) / dc, q2 = ((__int128)uh + B) / dd;
-                if (q1 != q2) break;
+                const __int128 dc = vh + C, dd = vh + D;
+                if (dc <= 0 || dd <= 0) break;
+                const __int128 q1 = (uh + A) / dc, q2 = (uh + B) / dd;
+                if (q1 != q2 || q1 < 1 || q1 >= lim) break;
                 const __int128 nC = (__int128)A - q1 * C, nD = (__int128)B - q1 * D;
                 if (nC >= lim || nC <= -lim || nD >= lim || nD <= -lim) break;
                 A = C; C = (int64_t)nC;
                 B = D; D = (int64_t)nD;
-                const int64_t nv = uh - (int64_t)q1 * vh;
+                const __int128 nv = uh - q1 * vh;
                 uh = vh; vh = nv;
             }
             if (B == 0) {                                 // no run found: one exact step
@@ -492,6 +585,46 @@ public:
             x = q;
         }
     }
+};
+
+// Reduction modulo one fixed m > 0 by Barrett's method (Handbook of Applied
+// Cryptography, Algorithm 14.42): with B = 2^32, k the limbs of m and
+// mu = floor(B^2k / m) found once, x < B^2k costs two products and at most
+// two subtractions instead of a long division.  Larger x fall back to mod.
+class ModReducer {
+public:
+    explicit ModReducer(const BigInt &m) : m_(BigInt::abs(m)), k_(m_.mag.size()) {
+        if (k_ == 0) return;
+        std::vector<uint32_t> p(2 * k_ + 1, 0u), r;
+        p[2 * k_] = 1;
+        BigInt::divmod_mag(p, m_.mag, mu_, r);
+    }
+    const BigInt &modulus() const { return m_; }
+    // The non-negative residue of x.
+    BigInt reduce(const BigInt &x) const {
+        if (x.mag.size() > 2 * k_ || k_ < 2) return mod(x, m_);
+        BigInt r;
+        if (x.mag.size() < k_) {
+            r.mag = x.mag;                                   // |x| < m already
+        } else {
+            const std::vector<uint32_t> q1(x.mag.begin() + (k_ - 1), x.mag.end());
+            const std::vector<uint32_t> q2 = BigInt::mul_mag(q1, mu_);
+            if (q2.size() > k_ + 1) {
+                const std::vector<uint32_t> q3(q2.begin() + (k_ + 1), q2.end());
+                r.mag = BigInt::sub_mag(x.mag, BigInt::mul_mag(q3, m_.mag));   // q3 <= floor(|x| / m)
+            } else {
+                r.mag = x.mag;
+            }
+            while (BigInt::cmp_mag(r.mag, m_.mag) >= 0) r.mag = BigInt::sub_mag(r.mag, m_.mag);
+        }
+        if (x.neg && !r.mag.empty()) r.mag = BigInt::sub_mag(m_.mag, r.mag);
+        return r;
+    }
+
+private:
+    BigInt m_;
+    size_t k_;
+    std::vector<uint32_t> mu_;
 };
 
 }  // namespace rns

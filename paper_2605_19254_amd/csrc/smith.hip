@@ -51,6 +51,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <functional>
+#include <memory>
 #include <new>
 #include <thread>
 #include <vector>
@@ -213,9 +215,16 @@ bool rational_reconstruct(const BigInt &y, const BigInt &m, BigInt &num, BigInt 
 
 // Smith diagonal modulo s of an n x n matrix (entries reduced mod s), by
 // unimodular gcd row/column operations; returns g_i = gcd(d_i, s) in
-// divisibility order.  Host code for small n.
+// divisibility order.  Host code for small n; the entries of one operation
+// are updated in parallel when s is large.
 std::vector<BigInt> snf_mod_host(std::vector<BigInt> M, int64_t n, const BigInt &s) {
     auto at = [&](int64_t i, int64_t j) -> BigInt & { return M[i * n + j]; };
+    const ModReducer red(s);
+    const bool par = s.bit_length() > 20000;
+    auto each = [&](int64_t lo, int64_t hi, const std::function<void(int64_t)> &f) {
+        if (par) parallel_for((int)(hi - lo), [&](int q) { f(lo + q); });
+        else for (int64_t q = lo; q < hi; ++q) f(q);
+    };
     auto op = [&](const BigInt &a, const BigInt &b, BigInt &g, BigInt &x, BigInt &y) {
         if (!a.is_zero() && mod(b, BigInt::abs(a)).is_zero()) {
             g = a;
@@ -233,25 +242,25 @@ std::vector<BigInt> snf_mod_host(std::vector<BigInt> M, int64_t n, const BigInt 
                 const BigInt a = at(k, k), b = at(i, k);
                 op(a, b, g, x, y);
                 const BigInt ag = a / g, bg = b / g;
-                for (int64_t j = k; j < n; ++j) {
+                each(k, n, [&](int64_t j) {
                     const BigInt u = at(k, j), v = at(i, j);
-                    at(k, j) = mod(x * u + y * v, s);
-                    at(i, j) = mod(ag * v - bg * u, s);
-                }
+                    at(k, j) = red.reduce(x * u + y * v);
+                    at(i, j) = red.reduce(ag * v - bg * u);
+                });
             }
-            bool dirty = false;
+            std::atomic<bool> dirty{false};
             for (int64_t j = k + 1; j < n; ++j) {
                 if (at(k, j).is_zero()) continue;
                 BigInt g, x, y;
                 const BigInt a = at(k, k), b = at(k, j);
                 op(a, b, g, x, y);
                 const BigInt ag = a / g, bg = b / g;
-                for (int64_t i = k; i < n; ++i) {
+                each(k, n, [&](int64_t i) {
                     const BigInt u = at(i, k), v = at(i, j);
-                    at(i, k) = mod(x * u + y * v, s);
-                    at(i, j) = mod(ag * v - bg * u, s);
+                    at(i, k) = red.reduce(x * u + y * v);
+                    at(i, j) = red.reduce(ag * v - bg * u);
                     if (i > k && !at(i, k).is_zero()) dirty = true;
-                }
+                });
             }
             if (!dirty) break;
         }
@@ -678,7 +687,7 @@ struct Driver {
     DevBuf<int64_t> dR0, dR1;   // residuals [t][n]
     DevBuf<uint32_t> dRm0, dRm1;
     DevBuf<int32_t> dRp;        // projection [tp][n]
-    DevBuf<int64_t> dZ;         // projected digits of one checkpoint interval
+    DevBuf<int64_t> dZ, dZb;    // projected digits of a checkpoint interval (two, for overlap)
     DevBuf<int32_t> derr;
     DevBuf<int64_t> dstep;      // device-side index of the next lifting step
     DevBuf<uint32_t> ddet;
@@ -862,23 +871,46 @@ struct Driver {
         BigInt prev_s;
         std::vector<BigInt> prev_X;
         std::vector<int64_t> hz;
+        // Steps k0 .. k1-1 and the projections of their digits into z.
+        auto launch_interval = [&](int64_t k0, int64_t k1, DevBuf<int64_t> &z) -> int {
+            int64_t i = k0;
+            if (k1 - i >= kLiftGraphSteps && !graph.tried) capture();
+            for (; graph.exec && k1 - i >= kLiftGraphSteps; i += kLiftGraphSteps)
+                DRV_HIP(hipGraphLaunch(graph.exec, stream));
+            if (i < k1) launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, t, p, lb, (int)(k1 - i), stream);
+            DRV_ST(z.alloc((size_t)(k1 - k0) * ne));
+            launch_lift_proj(dXh.p, n, ldl, t, dRp.p, tp, k0, k1, z.p, stream);
+            DRV_HIP(hipGetLastError());
+            return RNS_OK;
+        };
+        // The interval after a checkpoint is launched before that checkpoint's
+        // host work whenever the checkpoint cannot end the loop (a stable
+        // result needs the previous checkpoint to have succeeded), so the
+        // GPU lifts while the host reconstructs; otherwise it is launched
+        // after.  zb[cur] holds the projections of the current interval.
+        DevBuf<int64_t> *zb[2] = {&dZ, &dZb};
+        int cur = 0;
+        int64_t launched = K_done;                       // steps queued so far
         for (;;) {
             K_chk = std::min(K_chk, Kmax);
-            int64_t i = K_done;
-            if (K_chk - i >= kLiftGraphSteps && !graph.tried) capture();
-            for (; graph.exec && K_chk - i >= kLiftGraphSteps; i += kLiftGraphSteps)
-                DRV_HIP(hipGraphLaunch(graph.exec, stream));
-            if (i < K_chk) launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, t, p, lb, (int)(K_chk - i), stream);
+            if (launched < K_chk) {
+                DRV_ST(launch_interval(K_done, K_chk, *zb[cur]));
+                launched = K_chk;
+            }
             const int64_t nb = K_chk - K_done;
-            DRV_ST(dZ.alloc((size_t)nb * ne));
-            launch_lift_proj(dXh.p, n, ldl, t, dRp.p, tp, K_done, K_chk, dZ.p, stream);
-            DRV_HIP(hipGetLastError());
             hz.resize((size_t)nb * ne);
             int32_t err = 0;
-            DRV_HIP(hipMemcpyAsync(hz.data(), dZ.p, sizeof(int64_t) * hz.size(), hipMemcpyDeviceToHost, stream));
+            DRV_HIP(hipMemcpyAsync(hz.data(), zb[cur]->p, sizeof(int64_t) * hz.size(), hipMemcpyDeviceToHost,
+                                   stream));
             DRV_HIP(hipMemcpyAsync(&err, derr.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
             DRV_ST(sync());
             if (err) return RNS_EDEVICE;                 // an inexact division: C is not A^-1 mod p
+            const int64_t K_next = std::min(2 * K_chk, Kmax);
+            if (!have_prev && K_chk < Kmax) {
+                DRV_ST(launch_interval(K_chk, K_next, *zb[cur ^ 1]));
+                launched = K_next;
+                cur ^= 1;
+            }
             // Y' += (sum over the interval of Z_i p^(i - K_done)) p^K_done, the
             // inner sum by Horner's rule from the top digit.
             BigInt pnb(1);
@@ -912,10 +944,12 @@ struct Driver {
             // factor missing from s (its own denominator is then added).
             const size_t bb = (pw.bit_length() - 2) / 2;
             const BigInt Bnd = BigInt(1).shl(bb);
+            std::unique_ptr<ModReducer> red_pw;
+            if (ok) red_pw.reset(new ModReducer(pw));
             for (int pass = 0; ok && pass <= ne; ++pass) {
                 std::vector<char> big(ne, 0);
                 parallel_for(ne, [&](int e) {
-                    BigInt x = mod(s * Y[e], pw);
+                    BigInt x = red_pw->reduce(s * Y[e]);
                     if (BigInt::cmp(x.shl(1), pw) > 0) x = x - pw;
                     big[e] = BigInt::cmp(BigInt::abs(x), Bnd) >= 0;
                     X[e] = std::move(x);
@@ -950,7 +984,7 @@ struct Driver {
                 have_prev = false;
             }
             if (K_done >= Kmax) return RNS_EBOUND;
-            K_chk = 2 * K_chk;
+            K_chk = K_next;
         }
     }
 

@@ -1,6 +1,7 @@
-// Host check of the driver's big-integer routines (Lehmer gcd, extended gcd,
-// rational reconstruction) against plain Euclid on random inputs.  Built and
-// run by tests/test_host_bigint.py.
+// Host check of the driver's big-integer routines (Karatsuba products, Barrett
+// reduction, Lehmer gcd, extended gcd, rational reconstruction) against
+// schoolbook products, long division and plain Euclid on random inputs.
+// Built and run by tests/test_host_bigint.py.
 #include "../../paper_2605_19254_amd/csrc/bigint.hpp"
 #include <chrono>
 #include <cstdio>
@@ -14,9 +15,49 @@ static BigInt rnd(std::mt19937_64 &g, int limbs, bool sgn) {
     if (sgn && (g() & 1)) x = -x;
     return x;
 }
+// Reference: schoolbook product, one limb of b at a time.
+static BigInt mul_ref(const BigInt &a, const BigInt &b) {
+    BigInt r(0);
+    for (size_t j = b.mag.size(); j-- > 0;) r = r.shl(32) + BigInt::abs(a).mul_small(b.mag[j]);
+    if (a.neg != b.neg && !r.is_zero()) r = -r;
+    return r;
+}
+// Limbs of all ones (carry paths) or random.
+static BigInt limbs(std::mt19937_64 &g, int n, bool ones) {
+    BigInt x(0);
+    for (int i = 0; i < n; ++i) x = x.shl(32) + BigInt((int64_t)(ones ? 0xFFFFFFFFu : (g() & 0xFFFFFFFFu)));
+    return x;
+}
 int main() {
     std::mt19937_64 g(5);
     int bad = 0;
+    // Products across the Karatsuba threshold: balanced, unbalanced, all-ones.
+    for (int it = 0; it < 400; ++it) {
+        const int la = 1 + g() % 300, lb = (it % 5 == 0) ? la : 1 + g() % 300;
+        const bool ones = it % 9 == 0;
+        BigInt a = limbs(g, la, ones), b = limbs(g, lb, ones);
+        if (g() & 1) a = -a;
+        if (it % 17 == 0) b = BigInt(0);
+        if (a * b != mul_ref(a, b)) { ++bad; printf("mul mismatch %d (%d x %d)\n", it, la, lb); }
+    }
+    // Barrett reduction against long division, up to the 2k-limb limit and past it.
+    for (int it = 0; it < 400; ++it) {
+        const int lm = 1 + g() % 160;
+        BigInt m = limbs(g, lm, it % 11 == 0);
+        if (m.is_zero()) m = BigInt(7);
+        const ModReducer R(m);
+        for (int j = 0; j < 4; ++j) {
+            const int lx = j == 3 ? 2 * lm + 1 + (int)(g() % 3) : (int)(g() % (2 * lm + 1));
+            BigInt x = limbs(g, lx, it % 13 == 0);
+            if (g() & 1) x = -x;
+            if (j == 0) x = m * limbs(g, 1 + g() % lm, false);       // multiples of m
+            if (R.reduce(x) != mod(x, m)) { ++bad; printf("barrett mismatch %d/%d\n", it, j); }
+        }
+    }
+    if (bad) {                 // the gcd checks below rely on the products
+        printf("bad=%d\n", bad);
+        return 1;
+    }
     for (int it = 0; it < 3000; ++it) {
         int la = 1 + g() % 40, lb = 1 + g() % 40;
         if (it % 7 == 0) lb = la;
