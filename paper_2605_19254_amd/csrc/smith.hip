@@ -689,34 +689,34 @@ struct Driver {
     DevBuf<int32_t> dRp;        // projection [tp][n]
     DevBuf<int64_t> dZ, dZb;    // projected digits of a checkpoint interval (two, for overlap)
     DevBuf<int32_t> derr;
+    DevBuf<int32_t> dflag;      // A has an entry outside the int16 range
     DevBuf<int64_t> dstep;      // device-side index of the next lifting step
     DevBuf<uint32_t> ddet;
     bool cert_exact = true;
 
     // A as int16 (every |a| < 2^15) or int32 rows of stride ldl (zero padded)
-    // for the lifting kernels.
+    // for the lifting kernels, built on the device from the int64 A there
+    // (lifting_applies keeps every |a| below 2^31).
     int upload_a32() {
         ldl = (n + 7) / 8 * 8;
-        bool narrow = true;
-        for (int64_t e = 0; e < n * n && narrow; ++e) narrow = A[e] > -(1 << 15) && A[e] < (1 << 15);
-        a_bytes = narrow ? 2 : 4;
+        DRV_ST(dflag.alloc(1));
+        DRV_HIP(hipMemsetAsync(dflag.p, 0, sizeof(int32_t), stream));
+        launch_range16(dA.p, n * n, dflag.p, stream);
+        DRV_HIP(hipGetLastError());
+        int32_t wide = 0;
+        DRV_HIP(hipMemcpyAsync(&wide, dflag.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        a_bytes = wide ? 4 : 2;
+        void *out = nullptr;
         if (a_bytes == 2) {
-            std::vector<int16_t> a16((size_t)n * ldl, 0);
-            for (int64_t i = 0; i < n; ++i)
-                for (int64_t j = 0; j < n; ++j) a16[(size_t)i * ldl + j] = (int16_t)A[i * n + j];
-            DRV_ST(dA16.alloc(a16.size()));
-            DRV_HIP(hipMemcpyAsync(dA16.p, a16.data(), sizeof(int16_t) * a16.size(), hipMemcpyHostToDevice,
-                                   stream));
-            DRV_ST(sync());                              // the host vector goes out of scope
+            DRV_ST(dA16.alloc((size_t)n * ldl));
+            out = dA16.p;
         } else {
-            std::vector<int32_t> a32((size_t)n * ldl, 0);
-            for (int64_t i = 0; i < n; ++i)
-                for (int64_t j = 0; j < n; ++j) a32[(size_t)i * ldl + j] = (int32_t)A[i * n + j];
-            DRV_ST(dA32.alloc(a32.size()));
-            DRV_HIP(hipMemcpyAsync(dA32.p, a32.data(), sizeof(int32_t) * a32.size(), hipMemcpyHostToDevice,
-                                   stream));
-            DRV_ST(sync());
+            DRV_ST(dA32.alloc((size_t)n * ldl));
+            out = dA32.p;
         }
+        launch_pack_rows(dA.p, n, ldl, a_bytes, out, stream);
+        DRV_HIP(hipGetLastError());
         return RNS_OK;
     }
 
@@ -1133,27 +1133,45 @@ struct Driver {
         return RNS_ERETRY;
     }
 
-    // Hadamard's bound (log2) and the largest entry, from the host matrix.
+    // Hadamard's bound (log2) and the largest entry, from the host matrix:
+    // 64 fixed blocks of rows on host threads, their partial sums combined in
+    // block order (the result does not depend on the thread count).
     int bounds() {
-        double rows = 0, cols = 0;
-        std::vector<double> colsq(n, 0.0);
-        for (int64_t i = 0; i < n; ++i) {
-            double r = 0;
-            for (int64_t j = 0; j < n; ++j) {
-                const double v = (double)A[i * n + j];
-                r += v * v;
-                colsq[j] += v * v;
-                amax = std::max(amax, std::fabs(v));
+        const int nb = (int)std::min<int64_t>(n, 64);
+        std::vector<double> colsq((size_t)nb * n, 0.0), rowlog(nb, 0.0), amx(nb, 0.0);
+        parallel_for(nb, [&](int b) {
+            double *cs = colsq.data() + (size_t)b * n;
+            double rl = 0, am = 0;
+            for (int64_t i = n * b / nb; i < n * (b + 1) / nb; ++i) {
+                double r = 0;
+                for (int64_t j = 0; j < n; ++j) {
+                    const double v = (double)A[i * n + j];
+                    r += v * v;
+                    cs[j] += v * v;
+                    am = std::max(am, std::fabs(v));
+                }
+                rl += r > 0 ? 0.5 * std::log2(r) : -1e300;
             }
-            rows += r > 0 ? 0.5 * std::log2(r) : -1e300;
+            rowlog[b] = rl;
+            amx[b] = am;
+        });
+        double rows = 0, cols = 0;
+        for (int b = 0; b < nb; ++b) {
+            rows += rowlog[b];
+            amax = std::max(amax, amx[b]);
         }
-        for (int64_t j = 0; j < n; ++j) cols += colsq[j] > 0 ? 0.5 * std::log2(colsq[j]) : -1e300;
+        for (int64_t j = 0; j < n; ++j) {
+            double c = 0;
+            for (int b = 0; b < nb; ++b) c += colsq[(size_t)b * n + j];
+            cols += c > 0 ? 0.5 * std::log2(c) : -1e300;
+        }
         abits = std::min(rows, cols);
         return abits > -1e299 ? RNS_OK : RNS_ESINGULAR;   // a zero row or column
     }
 
     bool lifting_applies() const {
-        return n >= 16 && amax * (double)n < 68719476736.0;   // n max|a| < 2^36
+        // n max|a| < 2^36, and max|a| < 2^31 for the int32 form of A.
+        return n >= 16 && amax * (double)n < 68719476736.0 && amax < 2147483648.0;
     }
 
     int solve_lif(rns_smith_result *res) {

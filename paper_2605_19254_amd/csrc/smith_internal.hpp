@@ -70,6 +70,12 @@ void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, char *fra
 // The same for an int16 A (two exact signed byte digits per entry).
 size_t lift_tile_a_bytes(int64_t n);
 void launch_lift_tile_a(const int16_t *A, int64_t n, int64_t ld, char *At, hipStream_t s);
+// *flag = 1 if an entry of A (count int64 values) is outside (-2^15, 2^15);
+// the caller clears *flag first.
+void launch_range16(const int64_t *A, int64_t count, int32_t *flag, hipStream_t s);
+// The n x n int64 A as int16 (a_bytes 2) or int32 rows of stride ld >= n,
+// zero padded; every entry must fit the narrower type.
+void launch_pack_rows(const int64_t *A, int64_t n, int64_t ld, int a_bytes, void *out, hipStream_t s);
 // `steps` lifting steps (two launches each) and one launch advancing *base;
 // the launches take the same arguments for every run of the same length.
 void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,

@@ -807,6 +807,30 @@ __global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_
 }
 
 // *base += steps (one thread), after a run of steps.
+// *flag = 1 if any of the count entries lies outside (-2^15, 2^15), the
+// range that the int16 form of A holds (a plain store: every writer writes 1).
+__global__ __launch_bounds__(256) void k_range16(const int64_t *__restrict__ A, int64_t count,
+                                                 int32_t *__restrict__ flag) {
+    bool out = false;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        const int64_t v = A[e];
+        out |= v <= -32768 || v >= 32768;
+    }
+    if (out) *flag = 1;
+}
+
+// The n x n int64 matrix as rows of ld entries of T (the caller has checked
+// that every entry fits T), zero in the padding columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_rows(const int64_t *__restrict__ A, int64_t n, int64_t ld,
+                                                   T *__restrict__ out) {
+    const int64_t total = n * ld;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / ld, j = e - i * ld;
+        out[e] = j < n ? (T)A[i * n + j] : (T)0;
+    }
+}
+
 __global__ void k_lift_advance(int64_t *__restrict__ base, int steps) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *base += steps;
 }
@@ -1171,6 +1195,23 @@ void launch_lift_tile_a(const int16_t *A, int64_t n, int64_t ld, char *At, hipSt
     const int KT = (int)((n + 63) / 64);
     hipLaunchKernelGGL(k_lift_tile_a, dim3((unsigned)KT, (unsigned)((n + 15) / 16)), dim3(64), 0, s, A, n, ld, KT,
                        reinterpret_cast<v4i_l *>(At));
+}
+
+void launch_range16(const int64_t *A, int64_t count, int32_t *flag, hipStream_t s) {
+    if (count <= 0) return;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_range16, dim3((unsigned)blocks), dim3(256), 0, s, A, count, flag);
+}
+
+void launch_pack_rows(const int64_t *A, int64_t n, int64_t ld, int a_bytes, void *out, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>((n * ld + 255) / 256, 8192);
+    if (a_bytes == 2)
+        hipLaunchKernelGGL(k_pack_rows<int16_t>, dim3((unsigned)blocks), dim3(256), 0, s, A, n, ld,
+                           static_cast<int16_t *>(out));
+    else
+        hipLaunchKernelGGL(k_pack_rows<int32_t>, dim3((unsigned)blocks), dim3(256), 0, s, A, n, ld,
+                           static_cast<int32_t *>(out));
 }
 
 void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
