@@ -676,7 +676,7 @@ struct Driver {
     // --------------------------------------------------- p-adic lifting --
     int64_t ldl = 0;            // padded row stride of the lifting operands (multiple of 8)
     DevBuf<int32_t> dA32;       // A as int32, [n][ldl], zero beyond column n
-    DevBuf<int16_t> dA16;       // the same as int16 when every |a| < 2^15 (then dA32 is unused)
+    DevBuf<int16_t> dA16;       // the same as int16 when every |a| < 32640 (then dA32 is unused)
     int a_bytes = 4;
     DevBuf<uint32_t> dG;        // [n][2n] Gauss-Jordan of the lifting prime; right half = C
     DevBuf<uint32_t> dC;        // C = A^-1 mod p, [n][ldl], zero beyond column n
@@ -694,7 +694,7 @@ struct Driver {
     DevBuf<uint32_t> ddet;
     bool cert_exact = true;
 
-    // A as int16 (every |a| < 2^15) or int32 rows of stride ldl (zero padded)
+    // A as int16 (every |a| < 32640, two signed bytes) or int32 rows of stride ldl (zero padded)
     // for the lifting kernels, built on the device from the int64 A there
     // (lifting_applies keeps every |a| below 2^31).
     int upload_a32() {
@@ -837,7 +837,7 @@ struct Driver {
                 lb.At = dAt.p;
                 DRV_ST(dXd.alloc(lift_frag_bytes(n)));
                 DRV_ST(dRmd.alloc(lift_frag_bytes(n)));
-                launch_lift_frag(dRm0.p, n, ldl, t, dRmd.p, stream);   // the first step's Rm
+                launch_lift_frag(dRm0.p, n, ldl, t, p, dRmd.p, stream);   // the first step's Rm
                 DRV_HIP(hipGetLastError());
                 lb.Xd = dXd.p;
                 lb.Rmd = dRmd.p;

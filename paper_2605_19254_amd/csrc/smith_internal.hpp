@@ -64,13 +64,14 @@ constexpr int64_t kLiftMfmaMaxN = 43690;
 size_t lift_tile_c_bytes(int64_t n);
 void launch_lift_tile_c(const uint32_t *C, int64_t n, int64_t ld, uint32_t p, char *Ct, hipStream_t s);
 // Digit fragments of t <= 16 vectors [t][ld] (the right operand of the
-// lifting products), for the first step's Rm.
+// lifting products); balanced digits of the first step's Rm (entries in
+// [0, p)) for C Rm mod p.
 size_t lift_frag_bytes(int64_t n);
-void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, char *frag, hipStream_t s);
+void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, uint32_t p, char *frag, hipStream_t s);
 // The same for an int16 A (two exact signed byte digits per entry).
 size_t lift_tile_a_bytes(int64_t n);
 void launch_lift_tile_a(const int16_t *A, int64_t n, int64_t ld, char *At, hipStream_t s);
-// *flag = 1 if an entry of A (count int64 values) is outside (-2^15, 2^15);
+// *flag = 1 if an entry of A (count int64 values) is outside (-32640, 32640);
 // the caller clears *flag first.
 void launch_range16(const int64_t *A, int64_t count, int32_t *flag, hipStream_t s);
 // The n x n int64 A as int16 (a_bytes 2) or int32 rows of stride ld >= n,

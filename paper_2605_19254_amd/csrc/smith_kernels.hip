@@ -363,10 +363,13 @@ __global__ __launch_bounds__(256) void k_lift_x(const uint32_t *__restrict__ C, 
 // signed base-256 digits and tiled in the INT8 MFMA operand layout (per
 // 16-row block and 64-column step, four 1 KiB fragments, lane l holding row
 // l%16 and the 16 columns 16(l/16) .. +15).  Each step splits Rm the same way
-// in registers (lane l: right-hand side l%16) and runs the 16 digit-pair
+// in registers (lane l: right-hand side l%16), or takes it as balanced digit
+// fragments written by the residual update, and runs the 16 digit-pair
 // products v_mfma_i32_16x16x64_i8 per block and step, summed in int32 per
 // shift group s = i+j; the sums of one group over k <= 43690 columns stay
-// below 2^31 (at most 4 pairs of |d| <= 128 per column, |d3| <= 2).
+// below 2^31: both operands' digits are balanced (d0..d2 in [-128, 127],
+// |d3| <= 2), so a group adds per column at most three products of two full
+// digits (3 * 2^14) or two of them and two with a top digit (2^15 + 2^9).
 
 typedef int v4i_l __attribute__((ext_vector_type(4)));
 
@@ -458,28 +461,32 @@ __device__ __forceinline__ void lift_pack_exact(const uint32_t (&x)[16], v4i_l (
 // The right-hand sides of the next product as ready digit fragments: the
 // 16 x 16 block of a work-group (tile[c][j] = value of column c at row
 // 16 rb + j, rows past n zero) becomes lanes 16 (rb % 4) .. +15 of the four
-// digit fragments of 64-row step rb / 4 (exact base-256 digits, as the
-// product's right operand takes them).  One wave; its LDS writes precede
-// these reads in program order.
-__device__ __forceinline__ void lift_emit_frag(const uint32_t (&tile)[16][17], int64_t rb, int lane,
+// digit fragments of 64-row step rb / 4: exact base-256 digits of X for the
+// residual update (BAL false), which needs the integer product, balanced
+// digits of the balanced residue for C Rm mod p (BAL true, with p), which
+// keeps that product's group sums within its bound.  One wave; its LDS
+// writes precede these reads in program order.
+template <bool BAL>
+__device__ __forceinline__ void lift_emit_frag(const uint32_t (&tile)[16][17], int64_t rb, int lane, uint32_t p,
                                                v4i_l *__restrict__ frag) {
     if (lane >= 16) return;
     uint32_t x[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) x[j] = tile[lane][j];
     v4i_l f[4];
-    lift_pack_exact(x, f);
+    if constexpr (BAL) lift_pack(x, p, f);
+    else lift_pack_exact(x, f);
     const int64_t kt = rb >> 2;
     const int slot = (int)(rb & 3) * 16 + lane;
 #pragma unroll
     for (int i = 0; i < 4; ++i) frag[(kt * 4 + i) * 64 + slot] = f[i];
 }
 
-// Digit fragments of t <= 16 vectors v [t][ld] (entries in [0, p), rows past
-// n zero): one wave per 64-row step, lane l taking vector l%16 and rows
-// 16 (l/16) .. +15.
+// Balanced digit fragments of t <= 16 vectors v [t][ld] (entries in [0, p),
+// rows past n zero; the first step's Rm for C Rm mod p): one wave per 64-row
+// step, lane l taking vector l%16 and rows 16 (l/16) .. +15.
 __global__ __launch_bounds__(64) void k_lift_frag(const uint32_t *__restrict__ v, int64_t n, int64_t ld, int t,
-                                                  v4i_l *__restrict__ frag) {
+                                                  uint32_t p, v4i_l *__restrict__ frag) {
     const int kt = blockIdx.x;
     const int lane = threadIdx.x;
     const int c = lane & 15;
@@ -490,7 +497,7 @@ __global__ __launch_bounds__(64) void k_lift_frag(const uint32_t *__restrict__ v
     for (int j = 0; j < 16; ++j)
         if (k0 + j >= n) x[j] = 0;
     v4i_l f[4];
-    lift_pack_exact(x, f);
+    lift_pack(x, p, f);
 #pragma unroll
     for (int i = 0; i < 4; ++i) frag[((int64_t)kt * 4 + i) * 64 + lane] = f[i];
 }
@@ -572,15 +579,15 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_x_mfma(const v4i_l *__
         if (cvalid && row < n) X[(int64_t)c * ld + row] = xr;
         if constexpr (FRAG) tile16[c][4 * (lane >> 4) + v] = (cvalid && row < n) ? xr : 0u;
     }
-    if constexpr (FRAG) lift_emit_frag(tile16, rb, lane, Xd);
+    if constexpr (FRAG) lift_emit_frag<false>(tile16, rb, lane, p, Xd);
 }
 
 // The residual update on the matrix cores, for A held as int16: A splits
-// exactly into two signed bytes (a = a0 + 2^8 a1, |a| < 2^15), X in [0, p)
-// into four base-256 digits (the top one in [0, 4]); the 8 digit pairs fall
-// into 5 shift groups with at most 2 pairs each, so an int32 group sum over
-// k <= 43690 columns stays below 2^31, and sum_s S_s 2^(8s) is the exact
-// product sum in int64.  A's digits are tiled once per lifting (two 1 KiB
+// exactly into two signed bytes (a = a0 + 2^8 a1, a0 and a1 in [-128, 127],
+// which holds for |a| < 32640), X in [0, p) into four base-256 digits (the
+// top one in [0, 4]); each of the 8 digit pairs has its own int32 sum, below
+// 2^31 over k <= 65793 columns (|a_i x_j| <= 128 * 255), and
+// sum S_ij 2^(8(i+j)) is the exact product sum in int64.  A's digits are tiled once per lifting (two 1 KiB
 // fragments per 16-row block and 64-column step).
 
 // One wave per (64-column step kt, 16-row block rb).
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
                                                                  const int64_t *__restrict__ base, int off,
                                                                  const v4i_l *__restrict__ Xd,
                                                                  v4i_l *__restrict__ Rmd) {
-    __shared__ v4i_l part[KS][5][64];
+    __shared__ v4i_l part[KS][8][64];
     const int64_t i_step = *base + off;
     const uint32_t *__restrict__ X = Xh + i_step * t * ld;
     const int64_t *__restrict__ R = (i_step & 1) ? R1 : R0;
@@ -639,9 +646,9 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
     const bool cvalid = c < t;
     const uint32_t *xc = X + (int64_t)(cvalid ? c : 0) * ld;
     const v4i_l *af = At + rb * KT * 128 + lane;
-    v4i_l acc[5];
+    v4i_l acc[8];                                        // acc[4 i + j]: digit pair (a_i, x_j)
 #pragma unroll
-    for (int g = 0; g < 5; ++g) acc[g] = v4i_l{0, 0, 0, 0};
+    for (int g = 0; g < 8; ++g) acc[g] = v4i_l{0, 0, 0, 0};
     // Fragments of step kt+1 are loaded before the products of step kt.
     v4i_l a[2], b[4], an[2], bn[4];
     auto load = [&](int kt, v4i_l (&ar)[2], v4i_l (&br)[4]) {
@@ -663,7 +670,7 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
         for (int da = 0; da < 2; ++da)
 #pragma unroll
             for (int db = 0; db < 4; ++db)
-                acc[da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[db], acc[da + db], 0, 0, 0);
+                acc[4 * da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[db], acc[4 * da + db], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if (i < 2) a[i] = an[i];
@@ -671,7 +678,7 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
         }
     }
 #pragma unroll
-    for (int g = 0; g < 5; ++g) part[wave][g][lane] = acc[g];
+    for (int g = 0; g < 8; ++g) part[wave][g][lane] = acc[g];
     __syncthreads();
     if (wave != 0) return;
     __shared__ uint32_t tile16[16][17];
@@ -679,11 +686,11 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
     for (int v = 0; v < 4; ++v) {
         int64_t sum = 0;
 #pragma unroll
-        for (int g = 0; g < 5; ++g) {
+        for (int g = 0; g < 8; ++g) {
             int32_t sg = 0;
 #pragma unroll
             for (int w = 0; w < KS; ++w) sg += part[w][g][lane][v];
-            sum += (int64_t)sg << (8 * g);
+            sum += (int64_t)sg << (8 * ((g >> 2) + (g & 3)));
         }
         const int64_t r = rb * 16 + 4 * (lane >> 4) + v;
         uint32_t rm = 0;
@@ -698,7 +705,7 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
         }
         if constexpr (FRAG) tile16[c][4 * (lane >> 4) + v] = rm;
     }
-    if constexpr (FRAG) lift_emit_frag(tile16, rb, lane, Rmd);
+    if constexpr (FRAG) lift_emit_frag<true>(tile16, rb, lane, p, Rmd);
 }
 
 // R'[c][r] = (R[c][r] - sum_k A[r][k] X[c][k]) / p and Rm'[c][r] = R' mod p.
@@ -706,7 +713,7 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
 // an int64.  A division that is not exact (impossible for a correct C) sets
 // *err instead of producing a wrong residual silently.  X beyond row n is
 // never written; A's zero columns make its value irrelevant.  A is int32, or
-// int16 when every |a| < 2^15 (a quarter less traffic per step); either way
+// int16 when every |a| < 32640 (a quarter less traffic per step); either way
 // one 16-byte load per lane and step of the loop.
 template <typename AT>
 __device__ __forceinline__ void unpack_a(const int4 raw, int32_t (&a)[16 / sizeof(AT)]) {
@@ -807,14 +814,15 @@ __global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_
 }
 
 // *base += steps (one thread), after a run of steps.
-// *flag = 1 if any of the count entries lies outside (-2^15, 2^15), the
-// range that the int16 form of A holds (a plain store: every writer writes 1).
+// *flag = 1 if any of the count entries lies outside (-32640, 32640), the
+// range whose entries split into two signed bytes a0 + 2^8 a1 (a plain store:
+// every writer writes 1).
 __global__ __launch_bounds__(256) void k_range16(const int64_t *__restrict__ A, int64_t count,
                                                  int32_t *__restrict__ flag) {
     bool out = false;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
         const int64_t v = A[e];
-        out |= v <= -32768 || v >= 32768;
+        out |= v <= -32640 || v >= 32640;
     }
     if (out) *flag = 1;
 }
@@ -1182,9 +1190,9 @@ void launch_lift_tile_c(const uint32_t *C, int64_t n, int64_t ld, uint32_t p, ch
 
 size_t lift_frag_bytes(int64_t n) { return (size_t)((n + 63) / 64) * 4096; }
 
-void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, char *frag, hipStream_t s) {
+void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, uint32_t p, char *frag, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_lift_frag, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, v, n, ld, t,
+    hipLaunchKernelGGL(k_lift_frag, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, v, n, ld, t, p,
                        reinterpret_cast<v4i_l *>(frag));
 }
 

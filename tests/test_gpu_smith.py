@@ -206,6 +206,29 @@ def test_lifting_forced_matches_oracle(lifting_ctx, rg, n, seed, bound):
     assert res.stats["path"] == 1 and res.stats["cert_exact"] == 1
 
 
+@pytest.mark.parametrize("edge", [32639, 32700])
+def test_lifting_int16_edge_matches_oracle(lifting_ctx, rg, edge):
+    """Entries at the edge of the int16 form of A: every |a| <= 32639 splits
+    into two signed bytes (here 127 and -127 at the extremes) and takes the
+    matrix-core residual update; an entry of 32700, whose high byte would be
+    128 in that split, must send A to the int32 form instead."""
+    ctx = lifting_ctx
+    n = 40
+    _say("smith lifting int16 edge", n, edge)
+    rng = np.random.default_rng(900 + edge)
+    while True:
+        a = rng.integers(-32639, 32640, size=(n, n), dtype=np.int64)
+        for i in range(6):
+            a[i, i] = edge if i % 2 == 0 else -32639
+            a[i, n - 1 - i] = 32639
+        if osmith.bareiss_det(a) != 0:
+            break
+    ctx.set_smith_path("lifting")
+    res = rg.smith_form(ctx, a, seed=edge)
+    assert res.s == osmith.smith_form(a)
+    assert res.stats["path"] == 1
+
+
 def test_lifting_vector_kernels_match(rg, monkeypatch):
     """The lifting products on the vector units (RNS_LIFT_VECTOR=1, read when
     a context is created) give the same invariants as the default matrix-core
