@@ -63,9 +63,12 @@ constexpr int64_t kLiftMfmaMaxN = 43690;
 // core operand layout).
 size_t lift_tile_c_bytes(int64_t n);
 void launch_lift_tile_c(const uint32_t *C, int64_t n, int64_t ld, uint32_t p, char *Ct, hipStream_t s);
+// With both operands tiled and t <= 4 the right operands use the packed
+// fragment (digit d of vector c in MFMA column 4 d + c, 1 KiB per 64 rows).
+inline bool lift_packed(int t) { return t <= 4; }
 // Digit fragments of t <= 16 vectors [t][ld] (the right operand of the
-// lifting products); balanced digits of the first step's Rm (entries in
-// [0, p)) for C Rm mod p.
+// lifting products; packed when lift_packed(t)); balanced digits of the first
+// step's Rm (entries in [0, p)) for C Rm mod p.
 size_t lift_frag_bytes(int64_t n);
 void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, uint32_t p, char *frag, hipStream_t s);
 // The same for an int16 A (two exact signed byte digits per entry).

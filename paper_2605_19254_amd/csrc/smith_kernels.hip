@@ -708,6 +708,200 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
     if constexpr (FRAG) lift_emit_frag<true>(tile16, rb, lane, p, Rmd);
 }
 
+// ------------------------------- packed right operands for t <= 4 vectors
+// With at most four right-hand sides, twelve of the sixteen columns of the
+// right operand above would be zero.  The packed fragment puts digit d of
+// vector c in column 4 d + c instead (lane l: column l%16, rows
+// 16 (l/16) .. +15 of the 64-row step, one 1 KiB fragment per step), so one
+// MFMA per digit of the left operand forms every digit pair, each in its
+// own output column: a quarter of the products and of the fragment reads.
+// Every pair sum is exact in int32 on its own (C Rm: |d_i d_j| <= 2^14 per
+// column; A X: <= 128 * 255); the epilogue adds the pairs of a shift group.
+
+// Digit d of 16 values (balanced digits of the balanced residue mod p when
+// BAL, exact base-256 digits of values in [0, 2^26) otherwise).
+template <bool BAL>
+__device__ __forceinline__ v4i_l lift_digit_frag(const uint32_t (&x)[16], uint32_t p, int d) {
+    v4i_l f[4];
+    if constexpr (BAL) lift_pack(x, p, f);
+    else lift_pack_exact(x, f);
+    return d == 0 ? f[0] : d == 1 ? f[1] : d == 2 ? f[2] : f[3];
+}
+
+// The packed fragment of the 16 x 4 block of a work-group (tile[c][j], rows
+// past n and vectors past t zero): lanes 16 (rb % 4) .. +15 of the packed
+// fragment of 64-row step rb / 4.  One wave, as lift_emit_frag.
+template <bool BAL>
+__device__ __forceinline__ void lift_emit_frag_pk(const uint32_t (&tile)[16][17], int64_t rb, int lane, uint32_t p,
+                                                  v4i_l *__restrict__ frag) {
+    if (lane >= 16) return;
+    uint32_t x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = tile[lane & 3][j];
+    frag[(rb >> 2) * 64 + (rb & 3) * 16 + lane] = lift_digit_frag<BAL>(x, p, lane >> 2);
+}
+
+// Packed balanced fragments of t <= 4 vectors v [t][ld] (entries in [0, p),
+// rows past n zero; the first step's Rm): one wave per 64-row step.
+__global__ __launch_bounds__(64) void k_lift_frag_pk(const uint32_t *__restrict__ v, int64_t n, int64_t ld, int t,
+                                                     uint32_t p, v4i_l *__restrict__ frag) {
+    const int kt = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c = lane & 3;
+    const int64_t k0 = (int64_t)kt * 64 + 16 * (lane >> 4);
+    uint32_t x[16];
+    lift_load16(v + (int64_t)(c < t ? c : 0) * ld, k0, ld, c < t, x);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (k0 + j >= n) x[j] = 0;
+    frag[(int64_t)kt * 64 + lane] = lift_digit_frag<true>(x, p, (lane & 15) >> 2);
+}
+
+// Sums over the KS waves of the per-wave MFMA results part[w][i][lane] into
+// sums[i][row][column] (16 x 16 output layout), spread over all the threads.
+template <int KS, int NI>
+__device__ __forceinline__ void lift_sum_waves(const v4i_l (&part)[KS][NI][64], int32_t (&sums)[NI][16][17]) {
+    for (int q = threadIdx.x; q < NI * 256; q += 64 * KS) {
+        const int i = q >> 8, l = (q >> 2) & 63, v = q & 3;
+        int32_t sum = 0;
+#pragma unroll
+        for (int w = 0; w < KS; ++w) sum += part[w][i][l][v];
+        sums[i][4 * (l >> 4) + v][l & 15] = sum;
+    }
+}
+
+// k_lift_x_mfma with packed fragments (t <= 4): X = C Rm mod p for one 16-row
+// block per work-group, then X's packed exact fragments for the residual
+// update.
+template <int KS>
+__global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_x_mfma_pk(const v4i_l *__restrict__ Ct, int64_t n,
+                                                            int64_t ld, int KT, int t, uint32_t p,
+                                                            uint32_t *__restrict__ Xh,
+                                                            const int64_t *__restrict__ base, int off,
+                                                            const v4i_l *__restrict__ Rmp,
+                                                            v4i_l *__restrict__ Xp) {
+    __shared__ v4i_l part[KS][4][64];
+    __shared__ int32_t sums[4][16][17];
+    __shared__ uint32_t tile16[16][17];
+    const int64_t i_step = *base + off;
+    uint32_t *__restrict__ X = Xh + i_step * t * ld;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t rb = blockIdx.x;
+    const int kt0 = (int)((int64_t)KT * wave / KS), kt1 = (int)((int64_t)KT * (wave + 1) / KS);
+    const v4i_l *cf = Ct + rb * KT * 256 + lane;
+    v4i_l acc[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[g] = v4i_l{0, 0, 0, 0};
+    v4i_l a[4], an[4], b, bn;
+    auto load = [&](int kt, v4i_l (&ar)[4], v4i_l &br) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ar[i] = cf[(int64_t)kt * 256 + i * 64];
+        br = Rmp[(int64_t)kt * 64 + lane];
+    };
+    if (kt0 < kt1) load(kt0, a, b);
+    for (int kt = kt0; kt < kt1; ++kt) {
+        if (kt + 1 < kt1) load(kt + 1, an, bn);
+#pragma unroll
+        for (int da = 0; da < 4; ++da) acc[da] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b, acc[da], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = an[i];
+        b = bn;
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) part[wave][g][lane] = acc[g];
+    __syncthreads();
+    lift_sum_waves<KS, 4>(part, sums);
+    __syncthreads();
+    if (wave != 0) return;
+    // Lane (row, c) = (lane / 4, lane % 4); column 4 d + c holds the pairs of
+    // left digit i with right digit d, shift group i + d.
+    const int row = lane >> 2, c = lane & 3;
+    int32_t cs[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) cs[i + d] += sums[i][row][4 * d + c];
+    const double pf = (double)p, pinv = 1.0 / pf;
+    const double w24 = fma(-rint(16777216.0 * pinv), pf, 16777216.0);            // 2^24 mod p, balanced
+    const double w48 = fma(-rint(281474976710656.0 * pinv), pf, 281474976710656.0);   // 2^48 mod p, balanced
+    const int64_t grow = rb * 16 + row;
+    const bool ok = c < t && grow < n;
+    const uint32_t xr = lift_recombine(cs, pf, pinv, w24, w48);
+    if (ok) X[(int64_t)c * ld + grow] = xr;
+    tile16[c][row] = ok ? xr : 0u;
+    lift_emit_frag_pk<false>(tile16, rb, lane, p, Xp);
+}
+
+// k_lift_r_mfma with packed fragments (t <= 4): R' = (R - A X) / p and
+// Rm' = R' mod p for one 16-row block per work-group, then Rm''s packed
+// balanced fragments for the next C Rm.
+template <int KS>
+__global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma_pk(const v4i_l *__restrict__ At, int64_t n,
+                                                            int64_t ld, int KT, const uint32_t *__restrict__ Xh,
+                                                            int64_t *__restrict__ R0, int64_t *__restrict__ R1,
+                                                            uint32_t *__restrict__ Rm0,
+                                                            uint32_t *__restrict__ Rm1, int t, uint32_t p,
+                                                            int32_t *__restrict__ err,
+                                                            const int64_t *__restrict__ base, int off,
+                                                            const v4i_l *__restrict__ Xp,
+                                                            v4i_l *__restrict__ Rmp) {
+    __shared__ v4i_l part[KS][2][64];
+    __shared__ int32_t sums[2][16][17];
+    __shared__ uint32_t tile16[16][17];
+    const int64_t i_step = *base + off;
+    const int64_t *__restrict__ R = (i_step & 1) ? R1 : R0;
+    int64_t *__restrict__ Rn = (i_step & 1) ? R0 : R1;
+    uint32_t *__restrict__ Rmn = (i_step & 1) ? Rm0 : Rm1;
+    (void)Xh;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t rb = blockIdx.x;
+    const int kt0 = (int)((int64_t)KT * wave / KS), kt1 = (int)((int64_t)KT * (wave + 1) / KS);
+    const v4i_l *af = At + rb * KT * 128 + lane;
+    v4i_l acc[2] = {v4i_l{0, 0, 0, 0}, v4i_l{0, 0, 0, 0}};
+    v4i_l a[2], an[2], b, bn;
+    auto load = [&](int kt, v4i_l (&ar)[2], v4i_l &br) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) ar[i] = af[(int64_t)kt * 128 + i * 64];
+        br = Xp[(int64_t)kt * 64 + lane];
+    };
+    if (kt0 < kt1) load(kt0, a, b);
+    for (int kt = kt0; kt < kt1; ++kt) {
+        if (kt + 1 < kt1) load(kt + 1, an, bn);
+#pragma unroll
+        for (int da = 0; da < 2; ++da) acc[da] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b, acc[da], 0, 0, 0);
+        a[0] = an[0];
+        a[1] = an[1];
+        b = bn;
+    }
+    part[wave][0][lane] = acc[0];
+    part[wave][1][lane] = acc[1];
+    __syncthreads();
+    lift_sum_waves<KS, 2>(part, sums);
+    __syncthreads();
+    if (wave != 0) return;
+    const int row = lane >> 2, c = lane & 3;
+    int64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) sum += (int64_t)sums[i][row][4 * d + c] << (8 * (i + d));
+    const int64_t grow = rb * 16 + row;
+    uint32_t rm = 0;
+    if (c < t && grow < n) {
+        const int64_t num = R[(int64_t)c * ld + grow] - sum;
+        const int64_t qq = num / (int64_t)p;
+        if (qq * (int64_t)p != num) atomicOr(err, 1);
+        Rn[(int64_t)c * ld + grow] = qq;
+        const int64_t m = qq % (int64_t)p;
+        rm = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+        Rmn[(int64_t)c * ld + grow] = rm;
+    }
+    tile16[c][row] = rm;
+    lift_emit_frag_pk<true>(tile16, rb, lane, p, Rmp);
+}
+
 // R'[c][r] = (R[c][r] - sum_k A[r][k] X[c][k]) / p and Rm'[c][r] = R' mod p.
 // The host admits this form only when n max|a| p < 2^62, so every sum fits in
 // an int64.  A division that is not exact (impossible for a correct C) sets
@@ -1128,6 +1322,17 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
     const bool frag = b.Ct && b.At && sizeof(AT) == 2 && b.Xd && b.Rmd;
     const v4i_l *rmd = reinterpret_cast<const v4i_l *>(b.Rmd);
     v4i_l *xd = reinterpret_cast<v4i_l *>(b.Xd);
+    if (frag && lift_packed(t)) {                          // both products with packed fragments
+        const int KT = (int)((n + 63) / 64);
+        const unsigned rbs = (unsigned)((n + 15) / 16);
+        hipLaunchKernelGGL((k_lift_x_mfma_pk<8>), dim3(rbs), dim3(512), 0, s,
+                           reinterpret_cast<const v4i_l *>(b.Ct), n, ld, KT, t, p, b.Xh, b.base, off, rmd, xd);
+        hipLaunchKernelGGL((k_lift_r_mfma_pk<8>), dim3(rbs), dim3(512), 0, s,
+                           reinterpret_cast<const v4i_l *>(b.At), n, ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p,
+                           b.err, b.base, off, reinterpret_cast<const v4i_l *>(b.Xd),
+                           reinterpret_cast<v4i_l *>(b.Rmd));
+        return;
+    }
     if (b.Ct) {
         const int KT = (int)((n + 63) / 64);
         const unsigned rbs = (unsigned)((n + 15) / 16);
@@ -1192,6 +1397,11 @@ size_t lift_frag_bytes(int64_t n) { return (size_t)((n + 63) / 64) * 4096; }
 
 void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, uint32_t p, char *frag, hipStream_t s) {
     if (n <= 0) return;
+    if (lift_packed(t)) {
+        hipLaunchKernelGGL(k_lift_frag_pk, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, v, n, ld, t, p,
+                           reinterpret_cast<v4i_l *>(frag));
+        return;
+    }
     hipLaunchKernelGGL(k_lift_frag, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, v, n, ld, t, p,
                        reinterpret_cast<v4i_l *>(frag));
 }
