@@ -92,8 +92,10 @@ def parse():
                     help="time the full-range residue product with 10-word CRT (0 = skip)")
     ap.add_argument("--serving", type=int, default=60,
                     help="requests per open-loop serving point (0 = skip)")
-    ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving"],
+    ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving", "lifting"],
                     help="run only this workload (for profiling)")
+    ap.add_argument("--lifting-n", type=int, default=10007,
+                    help="matrix order of the --only lifting workload (one random Smith-form solve)")
     ap.add_argument("--calibrate-iters", type=int, default=300000,
                     help="iterations of the random-operand INT8 MFMA ceiling probe (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -199,6 +201,24 @@ def run_batched(rg, torch, dev, count, steps):
             "per_problem_launch_loop_ms": ms_loop,
             "cpu_baseline": {"value": sops / tc, "unit": "int-ops/s", "cores": native.num_threads(),
                              "kind": "oracle", "sample": "first 24 problems of the batch, %.1f s" % tc}}
+
+
+def run_lifting(rg, n):
+    """One Smith-form solve of a random n x n matrix with entries in
+    [-2^10, 2^10] (the p-adic lifting path; n = 10007 is the serving tail)."""
+    import synth
+    ctx = rg.Context(device=0, L=24)
+    try:
+        a = synth.small_smith(seed=0, n=n, bound=1 << 10)
+        t0 = time.perf_counter()
+        r = rg.smith_form(ctx, a, seed=0)
+        t = time.perf_counter() - t0
+    finally:
+        ctx.close()
+    if any(r.s[i + 1] % r.s[i] for i in range(len(r.s) - 1)):
+        raise SystemExit("bench.py: Smith form (random n=%d) is not a divisor chain" % n)
+    return {"workload": "n = %d, entries uniform in [-2^10, 2^10], seed 0 (p-adic lifting)" % n,
+            "seconds": t, "stats": r.stats, "largest_invariant_bits": r.s[-1].bit_length()}
 
 
 def run_smith(rg, reps=10):
@@ -470,6 +490,9 @@ def main():
         return
     if args.only == "serving":
         print(json.dumps(run_serving(rg, args.serving)), flush=True)
+        return
+    if args.only == "lifting":
+        print(json.dumps(run_lifting(rg, args.lifting_n)), flush=True)
         return
     a_np, b_np = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
     A = torch.from_numpy(a_np).to(dev)
