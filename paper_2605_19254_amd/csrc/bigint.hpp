@@ -627,4 +627,36 @@ private:
     std::vector<uint32_t> mu_;
 };
 
+// The primes below 2^16 (sieve of Eratosthenes, built once).
+inline const std::vector<uint32_t> &small_primes() {
+    static const std::vector<uint32_t> primes = [] {
+        std::vector<char> comp(65536, 0);
+        std::vector<uint32_t> v;
+        for (uint32_t q = 2; q < 65536; ++q) {
+            if (comp[q]) continue;
+            v.push_back(q);
+            for (uint32_t m = q * q; m < 65536; m += q) comp[m] = 1;
+        }
+        return v;
+    }();
+    return primes;
+}
+
+// True when every prime factor of s > 0 is below 2^16: s is divided by its
+// gcd with the product of those primes (built once) until the gcd is 1.
+inline bool smooth16(const BigInt &s) {
+    static const BigInt primorial = [] {
+        BigInt q(1);
+        for (uint32_t p : small_primes()) q = q.mul_small(p);
+        return q;
+    }();
+    BigInt rest = BigInt::abs(s);
+    while (!rest.is_one() && !rest.is_zero()) {
+        const BigInt g = BigInt::gcd(primorial, rest);
+        if (g.is_one()) return false;
+        rest = rest / g;
+    }
+    return rest.is_one();
+}
+
 }  // namespace rns

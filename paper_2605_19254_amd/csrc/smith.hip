@@ -537,19 +537,27 @@ struct Driver {
         // Factor s over the primes below 2^16.
         std::vector<std::pair<uint32_t, int>> fac;
         BigInt rest = s;
-        for (uint32_t q = 2; q < 65536 && !rest.is_one(); ++q) {
-            bool prime = true;
-            for (uint32_t d = 2; d * d <= q; ++d)
-                if (q % d == 0) { prime = false; break; }
-            if (!prime) continue;
-            int e = 0;
-            while (rest.mod_small(q) == 0) {
-                rest = rest / BigInt((int64_t)q);
-                ++e;
+        // The local Smith forms on the GPU need the factors of s, all below
+        // 2^16; whether s has only such factors is one gcd with their
+        // product, so trial division runs only when its result is used.
+        const bool smooth = n > 24 && smooth16(s);
+        // Two primes per pass over rest: one remainder modulo their product
+        // (below 2^32), then each prime's own test.
+        const std::vector<uint32_t> &P = small_primes();
+        for (size_t i = 0; smooth && i < P.size() && !rest.is_one(); i += 2) {
+            const uint32_t q1 = P[i], q2 = i + 1 < P.size() ? P[i + 1] : 1u;
+            const uint32_t r = rest.mod_small(q1 * q2);
+            for (const uint32_t q : {q1, q2}) {
+                if (q == 1 || r % q != 0) continue;
+                int e = 0;
+                while (rest.mod_small(q) == 0) {
+                    rest = rest / BigInt((int64_t)q);
+                    ++e;
+                }
+                if (e) fac.push_back({q, e});
             }
-            if (e) fac.push_back({q, e});
         }
-        bool gpu = rest.is_one() && n > 24;
+        bool gpu = smooth && rest.is_one();
         for (auto &f : fac) {
             double m = std::pow((double)f.first, f.second);
             if (m >= 17179869184.0) gpu = false;   // 2^34

@@ -1,6 +1,7 @@
 // Host check of the driver's big-integer routines (Karatsuba products, Barrett
-// reduction, Lehmer gcd, extended gcd, rational reconstruction) against
-// schoolbook products, long division and plain Euclid on random inputs.
+// reduction, 2^16-smoothness, Lehmer gcd, extended gcd, rational
+// reconstruction) against schoolbook products, long division, trial division
+// and plain Euclid on random inputs.
 // Built and run by tests/test_host_bigint.py.
 #include "../../paper_2605_19254_amd/csrc/bigint.hpp"
 #include <chrono>
@@ -53,6 +54,24 @@ int main() {
             if (j == 0) x = m * limbs(g, 1 + g() % lm, false);       // multiples of m
             if (R.reduce(x) != mod(x, m)) { ++bad; printf("barrett mismatch %d/%d\n", it, j); }
         }
+    }
+    // 2^16-smoothness by the primorial gcd against trial division: products
+    // of primes around the bound (65521 is the largest below, 65537 the
+    // first above) and of random small factors.
+    for (int it = 0; it < 600; ++it) {
+        BigInt s(1);
+        const int k = 1 + g() % 10;
+        for (int j = 0; j < k; ++j) {
+            uint64_t f = (it % 3 == 0) ? small_primes()[g() % small_primes().size()]
+                                       : 2 + g() % ((it % 3 == 1) ? 70000 : 200);
+            if (it % 17 == 0 && j == 0) f = 65537;
+            if (it % 19 == 0 && j == 0) f = 65521;
+            s = s.mul_small((uint32_t)f);
+        }
+        BigInt r = s;
+        for (uint32_t q : small_primes())
+            while (r.mod_small(q) == 0) r = r / BigInt((int64_t)q);
+        if (smooth16(s) != r.is_one()) { ++bad; printf("smooth16 mismatch %d\n", it); }
     }
     if (bad) {                 // the gcd checks below rely on the products
         printf("bad=%d\n", bad);
