@@ -569,10 +569,12 @@ struct Driver {
             DevBuf<uint64_t> dm, dkey;
             DevBuf<int32_t> dval;
             DevBuf<LocalMod> dlm;
+            DevBuf<uint64_t> dinv;
             DRV_ST(dm.alloc((size_t)F * n * n));
             DRV_ST(dkey.alloc((size_t)F * (n + 1)));
             DRV_ST(dval.alloc((size_t)F * n));
             DRV_ST(dlm.alloc((size_t)F));
+            DRV_ST(dinv.alloc((size_t)F));
             std::vector<LocalMod> lms(F);
             for (int f = 0; f < F; ++f) {
                 LocalMod &lm = lms[f];
@@ -588,7 +590,7 @@ struct Driver {
             DRV_HIP(hipMemcpyAsync(dlm.p, lms.data(), sizeof(LocalMod) * F, hipMemcpyHostToDevice, stream));
             DRV_HIP(hipMemsetAsync(dkey.p, 0xFF, sizeof(uint64_t) * F * (n + 1), stream));
             launch_loc_init(dm.p, n, dlm.p, F, dkey.p, stream);
-            for (int k = 0; k < n; ++k) launch_loc_step(dm.p, n, k, dlm.p, F, dkey.p, dval.p, stream);
+            for (int k = 0; k < n; ++k) launch_loc_step(dm.p, n, k, dlm.p, F, dkey.p, dval.p, dinv.p, stream);
             DRV_HIP(hipGetLastError());
             std::vector<int32_t> val((size_t)F * n);
             DRV_HIP(hipMemcpyAsync(val.data(), dval.p, sizeof(int32_t) * val.size(), hipMemcpyDeviceToHost, stream));

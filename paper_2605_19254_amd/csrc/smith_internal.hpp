@@ -95,9 +95,10 @@ void launch_check_sI(const uint32_t *P, int64_t n, const uint32_t *s_mod, int L,
 void launch_words_mod_m(const uint64_t *x, int64_t count, int W, const LocalMod &lm, uint64_t *out,
                         hipStream_t s);
 // Local Smith form of F planes at once (plane f modulo lms[f].m): keys
-// ([F][n+1], all ~0 beforehand) of step 0, then step k of every plane.
+// ([F][n+1], all ~0 beforehand) of step 0, then step k of every plane
+// (uinv: F words of scratch for the pivots' unit inverses).
 void launch_loc_init(const uint64_t *M, int64_t n, const LocalMod *lms, int F, uint64_t *keys, hipStream_t s);
 void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod *lms, int F, uint64_t *keys, int32_t *val,
-                     hipStream_t s);
+                     uint64_t *uinv, hipStream_t s);
 
 }  // namespace rns

@@ -1228,44 +1228,51 @@ __device__ uint64_t inv_unit(uint64_t u, uint64_t m) {   // u a unit mod m (m < 
     return (uint64_t)(t0 < 0 ? t0 + (int64_t)m : t0);
 }
 
-// Step k, pivot (one block per plane): record the valuation, swap the pivot
-// into (k, k), and scale row k by the inverse of the pivot's unit part so that
-// the pivot becomes q^v.  Grid (1, F).
-__global__ __launch_bounds__(256) void k_loc_pivot(uint64_t *__restrict__ M, int64_t n, int k,
-                                                   const LocalMod *__restrict__ lms,
-                                                   const uint64_t *__restrict__ keys, int32_t *__restrict__ val) {
+// Step k, pivot: record the valuation and swap the pivot (r, c) into (k, k),
+// rows k and r and columns k and c of the whole plane, with one thread per
+// index t < n: the row pair at column t (t not k or c), the column pair at
+// row t (t not k or r), and thread k the four entries of rows {k, r} and
+// columns {k, c} (M'[i][j] = M[sigma(i)][tau(j)] there; r = k or c = k make
+// it the one swap that applies).  Each entry has one owner, which reads it
+// before writing it.  Thread k, which places the pivot, also stores the
+// inverse of its unit part in uinv[f]; the elimination scales row k by it as
+// it reads the row.  Grid (ceil(n / 256), F).
+__global__ __launch_bounds__(256) void k_loc_swap(uint64_t *__restrict__ M, int64_t n, int k,
+                                                  const LocalMod *__restrict__ lms,
+                                                  const uint64_t *__restrict__ keys, int32_t *__restrict__ val,
+                                                  uint64_t *__restrict__ uinv) {
     const int f = blockIdx.y;
     const LocalMod lm = lms[f];
-    uint64_t *Mf = M + (int64_t)f * n * n;
     const uint64_t key = keys[(int64_t)f * (n + 1) + k];
     const int v = key == ~0ull ? lm.e : (int)(key >> 40);
-    if (threadIdx.x == 0) val[(int64_t)f * n + k] = v;
-    if (v >= lm.e) return;                  // the rest is 0 mod m
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) val[(int64_t)f * n + k] = v;
+    if (v >= lm.e || t >= n) return;                    // the rest is 0 mod m
+    uint64_t *Mf = M + (int64_t)f * n * n;
     const int64_t flat = (int64_t)(key & ((1ull << 40) - 1));
     const int64_t r = flat / n, c = flat % n;
-    if (r != k)
-        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-            const uint64_t t = Mf[(int64_t)k * n + j];
-            Mf[(int64_t)k * n + j] = Mf[r * n + j];
-            Mf[r * n + j] = t;
-        }
-    __syncthreads();
-    if (c != k)
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint64_t t = Mf[i * n + k];
-            Mf[i * n + k] = Mf[i * n + c];
-            Mf[i * n + c] = t;
-        }
-    __syncthreads();
-    __shared__ uint64_t uinv;
-    if (threadIdx.x == 0) {
-        uint64_t piv = Mf[(int64_t)k * n + k];
-        for (int t = 0; t < v; ++t) piv /= lm.q;
-        uinv = inv_unit(piv % lm.m, lm.m);
+    if (t == k) {
+        const uint64_t kk = Mf[(int64_t)k * n + k], kc = Mf[(int64_t)k * n + c];
+        const uint64_t rk = Mf[r * n + k], rc = Mf[r * n + c];
+        Mf[(int64_t)k * n + k] = rc;
+        Mf[(int64_t)k * n + c] = rk;
+        Mf[r * n + k] = kc;
+        Mf[r * n + c] = kk;
+        uint64_t piv = rc;                               // the new M[k][k]
+        for (int e = 0; e < v; ++e) piv /= lm.q;
+        uinv[f] = inv_unit(piv % lm.m, lm.m);
+        return;
     }
-    __syncthreads();
-    for (int64_t j = k + threadIdx.x; j < n; j += blockDim.x)
-        Mf[(int64_t)k * n + j] = mulmod_m(Mf[(int64_t)k * n + j], uinv, lm.mf, lm.minv);
+    if (r != k && t != c) {
+        const uint64_t x = Mf[(int64_t)k * n + t];
+        Mf[(int64_t)k * n + t] = Mf[r * n + t];
+        Mf[r * n + t] = x;
+    }
+    if (c != k && t != r) {
+        const uint64_t x = Mf[t * n + k];
+        Mf[t * n + k] = Mf[t * n + c];
+        Mf[t * n + c] = x;
+    }
 }
 
 // Step k, elimination: rows i > k, row_i -= (M[i][k] / q^v) row_k on columns
@@ -1275,7 +1282,7 @@ constexpr int kLocRows = 8;
 
 __global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int64_t n, int k,
                                                   const LocalMod *__restrict__ lms, const int32_t *__restrict__ val,
-                                                  uint64_t *__restrict__ keys) {
+                                                  const uint64_t *__restrict__ uinv, uint64_t *__restrict__ keys) {
     const int f = blockIdx.z;
     const LocalMod lm = lms[f];
     const int v = val[(int64_t)f * n + k];
@@ -1283,7 +1290,8 @@ __global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int6
     uint64_t *Mf = M + (int64_t)f * n * n;
     const int64_t j = k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool colv = j < n;
-    const uint64_t pk = colv ? Mf[(int64_t)k * n + j] : 0;
+    // Row k scaled so that the pivot is q^v.
+    const uint64_t pk = colv ? mulmod_m(Mf[(int64_t)k * n + j], uinv[f], lm.mf, lm.minv) : 0;
     uint64_t best = ~0ull;
     for (int rr = 0; rr < kLocRows; ++rr) {
         const int64_t i = k + 1 + (int64_t)blockIdx.y * kLocRows + rr;
@@ -1498,12 +1506,13 @@ void launch_loc_init(const uint64_t *M, int64_t n, const LocalMod *lms, int F, u
 }
 
 void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod *lms, int F, uint64_t *keys, int32_t *val,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_loc_pivot, dim3(1, (unsigned)F), dim3(256), 0, s, M, n, k, lms, keys, val);
+                     uint64_t *uinv, hipStream_t s) {
+    hipLaunchKernelGGL(k_loc_swap, dim3((unsigned)((n + 255) / 256), (unsigned)F), dim3(256), 0, s, M, n, k, lms,
+                       keys, val, uinv);
     const int64_t w = n - k - 1;
     if (w <= 0) return;
     dim3 grid((unsigned)((w + 255) / 256), (unsigned)((w + kLocRows - 1) / kLocRows), (unsigned)F);
-    hipLaunchKernelGGL(k_loc_elim, grid, dim3(256), 0, s, M, n, k, lms, val, keys);
+    hipLaunchKernelGGL(k_loc_elim, grid, dim3(256), 0, s, M, n, k, lms, val, uinv, keys);
 }
 
 }  // namespace rns
