@@ -1146,14 +1146,41 @@ __device__ __forceinline__ uint64_t mulmod_m(uint64_t a, uint64_t b, double mf, 
     return mod_m(fma((double)hi, 131072.0, (double)(a & 0x1FFFF) * b_), mf, minv);
 }
 
-__device__ __forceinline__ int valuation(uint64_t x, uint32_t q, int e) {
+// x / q and (through r) x mod q for x < 2^53: one double product with
+// qinv = RN(1/q) is within 2^-19 of x / q for x < 2^34, so the truncated
+// quotient is off by at most one and one correction fixes it.
+__device__ __forceinline__ uint64_t divmod_q(uint64_t x, uint32_t q, double qinv, uint64_t &r) {
+    int64_t t = (int64_t)((double)x * qinv);
+    int64_t rr = (int64_t)x - t * (int64_t)q;
+    if (rr < 0) {
+        rr += q;
+        --t;
+    } else if (rr >= (int64_t)q) {
+        rr -= q;
+        ++t;
+    }
+    r = (uint64_t)rr;
+    return (uint64_t)t;
+}
+__device__ __forceinline__ int valuation(uint64_t x, uint32_t q, double qinv, int e) {
     if (x == 0) return e;
     int v = 0;
-    while (v < e && x % q == 0) {
-        x /= q;
+    while (v < e) {
+        uint64_t r;
+        const uint64_t t = divmod_q(x, q, qinv, r);
+        if (r) break;
+        x = t;
         ++v;
     }
     return v;
+}
+// x / q^v for x divisible by q^v.
+__device__ __forceinline__ uint64_t div_qpow(uint64_t x, uint32_t q, double qinv, int v) {
+    for (int t = 0; t < v; ++t) {
+        uint64_t r;
+        x = divmod_q(x, q, qinv, r);
+    }
+    return x;
 }
 
 // X (W words per entry, two's complement) -> X mod m.
@@ -1181,8 +1208,8 @@ __global__ __launch_bounds__(256) void k_words_mod_m(const uint64_t *__restrict_
 // exactly that region, with one 64-bit atomicMin per block into key[f][k+1]
 // (every key starts at ~0).
 
-__device__ __forceinline__ uint64_t loc_key(uint64_t x, const LocalMod &lm, int64_t flat) {
-    return ((uint64_t)valuation(x, lm.q, lm.e) << 40) | (uint64_t)flat;
+__device__ __forceinline__ uint64_t loc_key(uint64_t x, const LocalMod &lm, double qinv, int64_t flat) {
+    return ((uint64_t)valuation(x, lm.q, qinv, lm.e) << 40) | (uint64_t)flat;
 }
 
 // Block minimum of one key per thread (every thread of the block calls it),
@@ -1205,9 +1232,10 @@ __global__ __launch_bounds__(256) void k_loc_init(const uint64_t *__restrict__ M
     const int f = blockIdx.y;
     const LocalMod lm = lms[f];
     const uint64_t *Mf = M + (int64_t)f * n * n;
+    const double qinv = 1.0 / (double)lm.q;
     uint64_t best = ~0ull;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * n; t += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t kk = loc_key(Mf[t], lm, t);
+        const uint64_t kk = loc_key(Mf[t], lm, qinv, t);
         best = kk < best ? kk : best;
     }
     block_min_to(best, key + (int64_t)f * (n + 1));
@@ -1258,8 +1286,7 @@ __global__ __launch_bounds__(256) void k_loc_swap(uint64_t *__restrict__ M, int6
         Mf[(int64_t)k * n + c] = rk;
         Mf[r * n + k] = kc;
         Mf[r * n + c] = kk;
-        uint64_t piv = rc;                               // the new M[k][k]
-        for (int e = 0; e < v; ++e) piv /= lm.q;
+        const uint64_t piv = div_qpow(rc, lm.q, 1.0 / (double)lm.q, v);   // the new M[k][k], unit part
         uinv[f] = inv_unit(piv % lm.m, lm.m);
         return;
     }
@@ -1290,6 +1317,7 @@ __global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int6
     uint64_t *Mf = M + (int64_t)f * n * n;
     const int64_t j = k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool colv = j < n;
+    const double qinv = 1.0 / (double)lm.q;
     // Row k scaled so that the pivot is q^v.
     const uint64_t pk = colv ? mulmod_m(Mf[(int64_t)k * n + j], uinv[f], lm.mf, lm.minv) : 0;
     uint64_t best = ~0ull;
@@ -1299,12 +1327,12 @@ __global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int6
         uint64_t fct = Mf[i * n + k];
         uint64_t a = Mf[i * n + j];
         if (fct != 0) {
-            for (int t = 0; t < v; ++t) fct /= lm.q;
-            const uint64_t d = mulmod_m(fct % lm.m, pk, lm.mf, lm.minv);
+            fct = div_qpow(fct, lm.q, qinv, v);          // < m already
+            const uint64_t d = mulmod_m(fct, pk, lm.mf, lm.minv);
             a = a >= d ? a - d : a + lm.m - d;
             Mf[i * n + j] = a;
         }
-        const uint64_t kk = loc_key(a, lm, i * n + j);
+        const uint64_t kk = loc_key(a, lm, qinv, i * n + j);
         best = kk < best ? kk : best;
     }
     block_min_to(best, keys + (int64_t)f * (n + 1) + k + 1);
