@@ -234,10 +234,42 @@ std::vector<BigInt> snf_mod_host(std::vector<BigInt> M, int64_t n, const BigInt 
             g = BigInt::xgcd(a, b, x, y);
         }
     };
+    // An operation whose pivot divides the entry (x = 1, y = 0) leaves row
+    // (column) k as it is, so a run of them is independent: they are queued
+    // and applied together, on host threads when the run is large, before
+    // the next operation that changes row (column) k.
+    std::vector<int64_t> queued;
+    auto run_queued = [&](int64_t k, bool rows, std::atomic<bool> *dirty) {
+        if (queued.empty()) return;
+        const BigInt a = at(k, k);
+        auto one = [&](int64_t l) {
+            if (rows) {
+                const BigInt f = at(l, k) / a;
+                for (int64_t j = k; j < n; ++j) at(l, j) = red.reduce(at(l, j) - f * at(k, j));
+            } else {
+                const BigInt f = at(k, l) / a;
+                for (int64_t i = k; i < n; ++i) {
+                    at(i, l) = red.reduce(at(i, l) - f * at(i, k));
+                    if (i > k && !at(i, k).is_zero()) *dirty = true;
+                }
+            }
+        };
+        if (queued.size() >= 4 && (int64_t)queued.size() * (n - k) >= 256)
+            parallel_for((int)queued.size(), [&](int q) { one(queued[(size_t)q]); });
+        else
+            for (const int64_t l : queued) one(l);
+        queued.clear();
+    };
+    auto divides = [](const BigInt &a, const BigInt &b) { return !a.is_zero() && mod(b, BigInt::abs(a)).is_zero(); };
     for (int64_t k = 0; k < n; ++k) {
         for (;;) {
             for (int64_t i = k + 1; i < n; ++i) {
                 if (at(i, k).is_zero()) continue;
+                if (divides(at(k, k), at(i, k))) {
+                    queued.push_back(i);
+                    continue;
+                }
+                run_queued(k, true, nullptr);
                 BigInt g, x, y;
                 const BigInt a = at(k, k), b = at(i, k);
                 op(a, b, g, x, y);
@@ -248,9 +280,15 @@ std::vector<BigInt> snf_mod_host(std::vector<BigInt> M, int64_t n, const BigInt 
                     at(i, j) = red.reduce(ag * v - bg * u);
                 });
             }
+            run_queued(k, true, nullptr);
             std::atomic<bool> dirty{false};
             for (int64_t j = k + 1; j < n; ++j) {
                 if (at(k, j).is_zero()) continue;
+                if (divides(at(k, k), at(k, j))) {
+                    queued.push_back(j);
+                    continue;
+                }
+                run_queued(k, false, &dirty);
                 BigInt g, x, y;
                 const BigInt a = at(k, k), b = at(k, j);
                 op(a, b, g, x, y);
@@ -262,6 +300,7 @@ std::vector<BigInt> snf_mod_host(std::vector<BigInt> M, int64_t n, const BigInt 
                     if (i > k && !at(i, k).is_zero()) dirty = true;
                 });
             }
+            run_queued(k, false, &dirty);
             if (!dirty) break;
         }
     }
