@@ -105,6 +105,14 @@ void parallel_for(int count, F f) {
     for (auto &x : th) x.join();
 }
 
+// parallel_for when the items are large enough to repay starting threads,
+// else the same items in order on the calling thread.
+template <typename F>
+void parallel_for_if(bool par, int count, F f) {
+    if (par) parallel_for(count, f);
+    else for (int i = 0; i < count; ++i) f(i);
+}
+
 #define DRV_HIP(call)                                                             \
     do {                                                                          \
         hipError_t e_ = (call);                                                   \
@@ -242,22 +250,26 @@ std::vector<BigInt> snf_mod_host(std::vector<BigInt> M, int64_t n, const BigInt 
     auto run_queued = [&](int64_t k, bool rows, std::atomic<bool> *dirty) {
         if (queued.empty()) return;
         const BigInt a = at(k, k);
-        auto one = [&](int64_t l) {
-            if (rows) {
-                const BigInt f = at(l, k) / a;
-                for (int64_t j = k; j < n; ++j) at(l, j) = red.reduce(at(l, j) - f * at(k, j));
-            } else {
-                const BigInt f = at(k, l) / a;
-                for (int64_t i = k; i < n; ++i) {
-                    at(i, l) = red.reduce(at(i, l) - f * at(i, k));
-                    if (i > k && !at(i, k).is_zero()) *dirty = true;
+        // One queued operation; its entries on host threads when s is large.
+        auto one = [&](int64_t l, bool entries_par) {
+            const BigInt f = rows ? at(l, k) / a : at(k, l) / a;
+            auto entry = [&](int64_t q) {
+                if (rows) {
+                    at(l, q) = red.reduce(at(l, q) - f * at(k, q));
+                } else {
+                    at(q, l) = red.reduce(at(q, l) - f * at(q, k));
+                    if (q > k && !at(q, k).is_zero()) *dirty = true;
                 }
-            }
+            };
+            if (entries_par) each(k, n, entry);
+            else for (int64_t q = k; q < n; ++q) entry(q);
         };
-        if (queued.size() >= 4 && (int64_t)queued.size() * (n - k) >= 256)
-            parallel_for((int)queued.size(), [&](int q) { one(queued[(size_t)q]); });
+        if (par)
+            for (const int64_t l : queued) one(l, true);
+        else if (queued.size() >= 4 && (int64_t)queued.size() * (n - k) >= 256)
+            parallel_for((int)queued.size(), [&](int q) { one(queued[(size_t)q], false); });
         else
-            for (const int64_t l : queued) one(l);
+            for (const int64_t l : queued) one(l, false);
         queued.clear();
     };
     auto divides = [](const BigInt &a, const BigInt &b) { return !a.is_zero() && mod(b, BigInt::abs(a)).is_zero(); };
@@ -964,7 +976,9 @@ struct Driver {
             // inner sum by Horner's rule from the top digit.
             BigInt pnb(1);
             for (int64_t i = 0; i < nb; ++i) pnb = pnb.mul_small(p);
-            parallel_for(ne, [&](int e) {
+            // Host threads only once the numbers reach some thousand bits.
+            const bool big = (double)K_chk * lp > 16384.0;
+            parallel_for_if(big, ne, [&](int e) {
                 BigInt v(0);
                 for (int64_t i = nb - 1; i >= 0; --i) v = v.mul_small(p) + BigInt(hz[(size_t)i * ne + e]);
                 Y[e] = Y[e] + v * pw;
@@ -985,7 +999,7 @@ struct Driver {
                 BigInt nu[2], de[2];
                 bool rr[2] = {false, false};
                 const BigInt *Wc[2] = {&W1, &W2};
-                parallel_for(2, [&](int i) { rr[i] = BigInt::rat_recon(mod(*Wc[i], pw), pw, nu[i], de[i]); });
+                parallel_for_if(big, 2, [&](int i) { rr[i] = BigInt::rat_recon(mod(*Wc[i], pw), pw, nu[i], de[i]); });
                 ok = rr[0] && rr[1] && de[0].mod_small(p) != 0 && de[1].mod_small(p) != 0;
                 if (ok) s = BigInt::lcm(de[0], de[1]);
             }
@@ -996,16 +1010,16 @@ struct Driver {
             std::unique_ptr<ModReducer> red_pw;
             if (ok) red_pw.reset(new ModReducer(pw));
             for (int pass = 0; ok && pass <= ne; ++pass) {
-                std::vector<char> big(ne, 0);
-                parallel_for(ne, [&](int e) {
+                std::vector<char> large(ne, 0);
+                parallel_for_if(big, ne, [&](int e) {
                     BigInt x = red_pw->reduce(s * Y[e]);
                     if (BigInt::cmp(x.shl(1), pw) > 0) x = x - pw;
-                    big[e] = BigInt::cmp(BigInt::abs(x), Bnd) >= 0;
+                    large[e] = BigInt::cmp(BigInt::abs(x), Bnd) >= 0;
                     X[e] = std::move(x);
                 });
                 int bad = -1;
                 for (int e = 0; e < ne && bad < 0; ++e)
-                    if (big[e]) bad = e;
+                    if (large[e]) bad = e;
                 if (bad < 0) break;
                 BigInt nu, de;
                 if (!BigInt::rat_recon(mod(Y[bad], pw), pw, nu, de) || de.mod_small(p) == 0) {
@@ -1188,7 +1202,7 @@ struct Driver {
     int bounds() {
         const int nb = (int)std::min<int64_t>(n, 64);
         std::vector<double> colsq((size_t)nb * n, 0.0), rowlog(nb, 0.0), amx(nb, 0.0);
-        parallel_for(nb, [&](int b) {
+        parallel_for_if(n * n >= (1 << 20), nb, [&](int b) {
             double *cs = colsq.data() + (size_t)b * n;
             double rl = 0, am = 0;
             for (int64_t i = n * b / nb; i < n * (b + 1) / nb; ++i) {
