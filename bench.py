@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-rows", type=int, default=384,
                     help="rows of C the oracle computes for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-rows-1core", type=int, default=16,
+                    help="rows of C for the single-core oracle timing (0 = skip)")
     ap.add_argument("--out", default="")
     ap.add_argument("--batched", type=int, default=512,
                     help="also time the batched workload with this many uneven products (0 = skip)")
@@ -90,7 +92,7 @@ def parse():
     ap.add_argument("--smith", type=int, default=1, help="time the Smith-form workloads (0 = skip)")
     ap.add_argument("--stress", type=int, default=1,
                     help="time the full-range residue product with 10-word CRT (0 = skip)")
-    ap.add_argument("--serving", type=int, default=60,
+    ap.add_argument("--serving", type=int, default=200,
                     help="requests per open-loop serving point (0 = skip)")
     ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving", "lifting"],
                     help="run only this workload (for profiling)")
@@ -104,11 +106,14 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(a, b, primes, rows):
+def cpu_baseline(a, b, primes, rows, threads=0):
     """The oracle as it stands, on the first `rows` rows of C: reduce, the
-    per-prime schoolbook products (plain C loops, OpenMP), CRT in Python ints."""
+    per-prime schoolbook products (plain C loops, OpenMP on `threads` threads,
+    0 = all), CRT in Python ints."""
     import numpy as np
     from oracle import native, rns as orns
+    if threads:
+        native.set_threads(threads)
     t0 = time.perf_counter()
     ra = orns.reduce(a[:rows], primes)
     rb = orns.reduce(b, primes)
@@ -120,10 +125,38 @@ def cpu_baseline(a, b, primes, rows):
     # spot-check the sample against the exact product
     want = native.exact_matmul(a[:2], b)
     assert all(int(c[i, j]) == int(want[i, j]) for i in range(2) for j in range(0, b.shape[1], 97))
-    return {"value": ops / t, "unit": "int-ops/s", "cores": native.num_threads(), "kind": "oracle",
+    cores = native.num_threads()
+    if threads:
+        native.set_threads(os.cpu_count() or 1)
+    return {"value": ops / t, "unit": "int-ops/s", "cores": cores, "kind": "oracle",
             "sample": "rows 0..%d of C (%d x %d x %d, %d primes): reduce, per-prime schoolbook "
                       "modmatmul, CRT; %.1f s" % (rows - 1, rows, n, b.shape[1], len(primes), t),
             "seconds": t}
+
+
+def _oracle_timings(conn, n, L, rows1):
+    """Single-core oracle timings, run in a child process (forked before the
+    GPU is touched) while the parent times GPU work: the headline product's
+    oracle on `rows1` rows of C with one thread, and the oracle's Smith form of
+    the planted n = 200 matrix (the planted n = 2000 workload's generator)."""
+    out = {}
+    try:
+        import synth
+        from oracle import primes as op, smith as osmith
+        a, b = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
+        if rows1 > 0:
+            out["headline_1core"] = cpu_baseline(a, b, op.largest_primes_below(1 << 26, L), rows1, threads=1)
+        del a, b
+        pl = synth.planted_smith(200, seed=0)
+        t0 = time.perf_counter()
+        ok = osmith.smith_form(pl.a) == pl.s
+        out["planted_200"] = {"value": time.perf_counter() - t0, "unit": "s", "cores": 1, "kind": "oracle",
+                              "sample": "planted n = 200, seed 0 (Bareiss determinant + gcd elimination mod d, "
+                                        "Python)", "agrees_with_planted": ok}
+    except Exception as e:                       # reported, never fatal to the GPU measurements
+        out["error"] = repr(e)
+    conn.send(out)
+    conn.close()
 
 
 def run_batched(rg, torch, dev, count, steps):
@@ -167,6 +200,38 @@ def run_batched(rg, torch, dev, count, steps):
         g.replay()
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / steps
+    def replay_ms(pl, reps):
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        gg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gg, stream=st):
+            pl.execute()
+        torch.cuda.synchronize()
+        gg.replay()
+        torch.cuda.synchronize()
+        t0_ = time.perf_counter()
+        for _ in range(reps):
+            gg.replay()
+        torch.cuda.synchronize()
+        r = 1000.0 * (time.perf_counter() - t0_) / reps
+        del gg
+        return r
+
+    # the same batch with the persistent GEMM (two work-groups per CU take
+    # half-tiles, longest first, from a counter: one GEMM launch that stays
+    # resident for the whole batch)
+    plan.set_variant(2)
+    ms_persistent = replay_ms(plan, steps)
+    plan.set_variant(variant)
+    # ablation: every residue product on the FP64 MFMA path
+    plan64 = rg.MatmulPlan(ctx, probs, path="fp64")
+    ms_fp64 = replay_ms(plan64, max(2, steps // 2))
+    for i in (order[0], order[count // 2], order[-1]):
+        rows = np.array([0, batch[i].m - 1])
+        got = probs[i].C[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        if not np.array_equal(got, native.exact_matmul(batch[i].a[rows], batch[i].b)):
+            raise SystemExit("bench.py: batched result (FP64 path) differs from the oracle")
+    plan64.close()
     # ablation: a plan per problem, launched in a host loop, no graph
     singles = [rg.MatmulPlan(ctx, [p], path="int8") for p in probs]
     for sp in singles:
@@ -199,6 +264,8 @@ def run_batched(rg, torch, dev, count, steps):
             "residue_ops": ops, "variant": variant, "tiles": info["tiles"],
             "mfma_frac_of_int8_peak": 16.0 * ops / (ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
             "per_problem_launch_loop_ms": ms_loop,
+            "persistent_gemm_ms_per_step": ms_persistent,
+            "fp64_path_ms_per_step": ms_fp64,
             "cpu_baseline": {"value": sops / tc, "unit": "int-ops/s", "cores": native.num_threads(),
                              "kind": "oracle", "sample": "first 24 problems of the batch, %.1f s" % tc}}
 
@@ -221,11 +288,26 @@ def run_lifting(rg, n):
             "seconds": t, "stats": r.stats, "largest_invariant_bits": r.s[-1].bit_length()}
 
 
-def run_smith(rg, reps=10):
+def _traced(rg, ctx, a, seed=0):
+    """One more solve with every library kernel bracketed by HIP events:
+    (kernel milliseconds, kernel launches, wall milliseconds).  Tracing adds
+    work of its own, so the untraced timings above it are the figures."""
+    ctx.profile(True)
+    ctx.profile_read("")
+    t0 = time.perf_counter()
+    rg.smith_form(ctx, a, seed=seed)
+    wall = 1000.0 * (time.perf_counter() - t0)
+    ms, launches = ctx.profile_read("")
+    ctx.profile(False)
+    return {"kernel_ms": ms, "launches": launches, "wall_ms_traced": wall, "kernel_share": ms / wall}
+
+
+def run_smith(rg, reps=10, oracle_bg=None):
     """Smith forms: the 64 x 64 matrix with entries in [-99, 99] (seed 0) and
     the planted n = 2000 matrix (A = U diag(s) V, seed 0), each checked against
     the oracle or the planted invariants; the oracle is timed on the 64 x 64
-    matrix and on a planted n = 100 matrix."""
+    matrix and on a planted n = 200 matrix (in `oracle_bg` when the caller
+    timed it in a child process, else here)."""
     import synth
     from oracle import smith as osmith
     out = {}
@@ -243,7 +325,7 @@ def run_smith(rg, reps=10):
         osmith.smith_form(a)
         to = time.perf_counter() - t0
         out["small_64"] = {"workload": "64x64, entries uniform in [-99, 99], seed 0", "solves_per_s": 1.0 / t,
-                           "ms_per_solve": 1000 * t, "stats": res.stats,
+                           "ms_per_solve": 1000 * t, "stats": res.stats, "traced": _traced(rg, ctx, a),
                            "cpu_baseline": {"value": 1.0 / to, "unit": "solves/s", "cores": 1, "kind": "oracle",
                                             "sample": "the same matrix"}}
         # the same solve with every residue product on the FP64 MFMA path
@@ -273,15 +355,18 @@ def run_smith(rg, reps=10):
                               "seconds": tr, "stats": rr.stats,
                               "nontrivial": sum(1 for v in rr.s if v != 1),
                               "largest_invariant_bits": rr.s[-1].bit_length()}
-        p100 = synth.planted_smith(100, seed=0)
-        t0 = time.perf_counter()
-        osmith.smith_form(p100.a)
-        to = time.perf_counter() - t0
+        if oracle_bg and "planted_200" in oracle_bg:
+            cb = oracle_bg["planted_200"]
+        else:
+            p200 = synth.planted_smith(200, seed=0)
+            t0 = time.perf_counter()
+            ok = osmith.smith_form(p200.a) == p200.s
+            cb = {"value": time.perf_counter() - t0, "unit": "s", "cores": 1, "kind": "oracle",
+                  "sample": "planted n = 200, seed 0", "agrees_with_planted": ok}
         out["planted_2000"] = {"workload": "A = U diag(s) V, n = 2000, 4n random row and column operations, "
                                            "5 planted factors from the primes below 100, seed 0",
-                               "seconds": t, "stats": res.stats,
-                               "cpu_baseline": {"value": to, "unit": "s", "cores": 1, "kind": "oracle",
-                                                "sample": "planted n = 100 (the oracle is O(n^3) in Python)"}}
+                               "seconds": t, "stats": res.stats, "traced": _traced(rg, ctx, pl.a),
+                               "cpu_baseline": cb}
     return out
 
 
@@ -402,6 +487,7 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
             if len(tickets) % 50 == 0:
                 print("[serving] %.2fx capacity: %d submitted" % (frac, len(tickets)), file=sys.stderr, flush=True)
         lat, queue, service, ok, bad, tail_rec, paths, exact = [], [], [], 0, 0, None, [0, 0], 0
+        ops, cpu = [], []
         intervals = []
         for t, (r, a, kind) in zip(tickets, reqs):
             st, res, info = srv.wait(t)
@@ -417,13 +503,14 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
             exact += res.stats["cert_exact"]
             rec = (info["t_end"] - info["t_submit"], info["t_start"] - info["t_submit"],
                    info["t_end"] - info["t_start"])
-            if r.n == 10007:
+            if r.n == 10007:                     # also counted in the percentiles below
                 tail_rec = {"n": r.n, "latency_s": rec[0], "queue_s": rec[1], "service_s": rec[2],
                             "stats": res.stats, "largest_invariant_bits": res.s[-1].bit_length()}
-                continue
             lat.append(rec[0])
             queue.append(rec[1])
             service.append(rec[2])
+            ops.append(res.stats["residue_ops"])
+            cpu.append(res.stats["t_host_cpu"])
             if len(solved) < 6 and r.n <= 1500:
                 solved.append((a, res.s))
         span = time.perf_counter() - start
@@ -447,6 +534,14 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
                        "p99_queue_s": float(np.percentile(queue, 99)),
                        "p50_service_s": float(np.percentile(service, 50)),
                        "p99_service_s": float(np.percentile(service, 99)),
+                       "max_latency_s": float(np.max(lat)),
+                       "residue_int_ops_per_request": {"mean": float(np.mean(ops)),
+                                                       "p50": float(np.percentile(ops, 50)),
+                                                       "p99": float(np.percentile(ops, 99))},
+                       "residue_int_ops_per_s": float(np.sum(ops)) / span,
+                       "host_cpu_s_per_request": {"mean": float(np.mean(cpu)),
+                                                  "p50": float(np.percentile(cpu, 50)),
+                                                  "p99": float(np.percentile(cpu, 99))},
                        "singular_rejected": bad, "paths_residue_lifting": paths,
                        "busy_frac": busy / span if span > 0 else None,
                        "exact_certificates": exact, "tail": tail_rec})
@@ -462,8 +557,9 @@ def run_serving(rg, count, fracs=SERVING_FRACS):
     out["max_running"] = st["max_running"]
     out["hbm_high_water_bytes"] = st["high_water"]
     out["workload"] = ("Poisson arrivals; n log-uniform in [100, 4000], entries uniform in [-2^10, 2^10] "
-                       "(seeded synthetic stand-ins), n = 10007 tail at the 50th arrival of each point, "
-                       "one singular request per point; %d requests per point" % count)
+                       "(seeded synthetic stand-ins), n = 10007 tail at the 50th arrival of each point "
+                       "(counted in the latency percentiles; also broken out as `tail`), one singular "
+                       "request per point; %d requests per point; latency = completion - arrival" % count)
     return out
 
 
@@ -474,6 +570,16 @@ def main():
               "Smith-form requests would shard over several GPUs is designed but not built",
               file=sys.stderr)
         sys.exit(2)
+    bg = None
+    if not args.only and args.smith:
+        # single-core oracle timings in a child forked before the GPU is
+        # touched; it runs while the GPU products below are timed
+        import multiprocessing as mp
+        ctx_mp = mp.get_context("fork")
+        parent, child = ctx_mp.Pipe(duplex=False)
+        bg = (ctx_mp.Process(target=_oracle_timings, args=(child, args.n, args.primes, args.cpu_rows_1core)),
+              parent)
+        bg[0].start()
     import numpy as np
     import torch
 
@@ -647,13 +753,25 @@ def main():
         "boundary_calls": calls_rec,
         "int8_vs_fp64_speedup": (fp64["ms_per_step"] / ms8) if fp64 else None,
     }
+    print("[bench] headline and FP64 path done", file=sys.stderr, flush=True)
     rec["stress"] = run_stress(rg, torch, dev, ctx, n, L) if args.stress else None
+    print("[bench] full-range stress done", file=sys.stderr, flush=True)
     rec["batched"] = run_batched(rg, torch, dev, args.batched, args.batched_steps) if args.batched > 0 else None
-    rec["smith"] = run_smith(rg) if args.smith else None
+    print("[bench] batched done", file=sys.stderr, flush=True)
+    oracle_bg = None
+    if bg is not None:
+        print("[bench] waiting for the single-core oracle timings", file=sys.stderr, flush=True)
+        oracle_bg = bg[1].recv()
+        bg[0].join()
+    rec["smith"] = run_smith(rg, oracle_bg=oracle_bg) if args.smith else None
+    print("[bench] smith done", file=sys.stderr, flush=True)
     rec["serving"] = run_serving(rg, args.serving) if args.serving > 0 else None
+    print("[bench] serving done", file=sys.stderr, flush=True)
     if args.cpu_rows > 0:
         primes = ctx.primes[:L]
         rec["cpu_baseline"] = cpu_baseline(a_np, b_np, primes, args.cpu_rows)
+        if oracle_bg and "headline_1core" in oracle_bg:
+            rec["cpu_baseline"]["single_core"] = oracle_bg["headline_1core"]
     else:
         rec["cpu_baseline"] = None
     line = json.dumps(rec)

@@ -334,8 +334,16 @@ typedef struct rns_smith_stats {
                               path 1: primes of det A / s */
     int columns;           /* columns of the projection J (n: J = I) */
     int path;              /* 0: residues of s A^-1 (J = I); 1: p-adic lifting */
-    int cert_exact;        /* 1: the certificate is exact; 0: det A / s was
-                              taken from an early-terminated reconstruction */
+    int cert_exact;        /* 1: the result is certified (path 0: A X = s I
+                              exactly; path 1: |det A| = prod s_i with det A / s
+                              reconstructed from enough primes to be exact);
+                              0: not certified (rns_largest_invariant) */
+    int lift_a_bytes;      /* path 1: 2 when A was stored as int16 for the
+                              lifting kernels, 4 for int32; 0 on path 0 */
+    int lift_kernels;      /* path 1: the lifting kernels of the last
+                              lifting, as rns_lift_step's `kernels` bits */
+    double t_host_cpu;     /* CPU seconds of the calling thread and of the
+                              helper threads it started for this call */
 } rns_smith_stats;
 
 /*
@@ -396,7 +404,11 @@ void rns_smith_free(rns_smith_result *r);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (tracing).  When enabled, every kernel the library launches
- * is bracketed by two HIP events recorded on the caller's stream.
+ * is bracketed by two HIP events recorded on the caller's stream (for
+ * smith_form and rns_largest_invariant: on the solve's stream, including
+ * the products they run on their internal basis; a run of lifting steps is
+ * one record counting all its launches, and the lifting graphs are not
+ * captured while tracing).
  * rns_ctx_profile_read synchronises those events and returns, for kernels
  * whose name contains `name` (NULL or "" = all), the summed duration in
  * milliseconds and the number of launches, then forgets them.
@@ -466,6 +478,35 @@ int rns_server_footprint(int64_t n, size_t *bytes);
 /* Stops the workers after the requests they are running; queued requests
  * are dropped. */
 void rns_server_destroy(rns_server *s);
+
+/*
+ * rns_lift_step -- one step of Dixon's p-adic lifting (Section 3 names it as
+ * the solver of the method's linear systems), run by the same kernels and the
+ * same set-up as the Smith-form driver's lifting, on caller-given operands:
+ *     X  = C (R mod p) mod p,
+ *     R' = (R - A X) / p      (rounded toward zero; exact when C = A^-1 mod p),
+ *     Rm' = R' mod p.
+ * With C = A^-1 mod p this is the step the driver repeats; for other C the
+ * division is inexact somewhere and *inexact is set.  It exists so that the
+ * step kernels can be checked against a CPU computation at any n up to their
+ * exactness bound.
+ *   C:  device uint32, n x n row-major, residues in [0, p).
+ *   A:  device int64, n x n row-major; stored as int16 when every |a| < 32640
+ *       (the driver's rule), else int32 (entries must fit int32).
+ *   R:  device int64, t vectors of n entries ([t][n]); |R| + n max|A| p < 2^63.
+ *   X, Rm_next: device uint32 [t][n]; R_next: device int64 [t][n].
+ *   form: 0 vector units only; 1 matrix cores (C Rm on INT8 MFMA; A X on
+ *       INT8 MFMA as well when A is int16, with packed right operands when
+ *       t <= 4).  n <= 43690 for form 1 (RNS_EBOUND beyond), n <= 65536.
+ *   inexact: host int32, 1 if p does not divide some R - A X.
+ *   kernels: host int, bit 0 C Rm on the matrix cores, bit 1 A X on the matrix
+ *       cores, bit 2 packed right operands, bit 3 A stored as int16.
+ * 1 <= t <= 16, p an odd prime below 2^26.  Allocates and frees its own work
+ * buffers and synchronises `stream` before returning.
+ */
+int rns_lift_step(int device, const uint32_t *C, const int64_t *A, const int64_t *R, int64_t n, int t,
+                  uint32_t p, int form, uint32_t *X, int64_t *R_next, uint32_t *Rm_next, int32_t *inexact,
+                  int *kernels, void *stream);
 
 /* Test hook: make the next `count` certifications of this context fail, to
  * exercise the Las Vegas restart (Section 2.2, Phase 3).  0 disables. */

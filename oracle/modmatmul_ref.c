@@ -61,6 +61,16 @@ void oracle_exact_matmul(const int64_t *A, const int64_t *B, int64_t *C,
     }
 }
 
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -45,6 +45,8 @@ def _load():
             lib.oracle_modmatmul.restype = None
             lib.oracle_exact_matmul.argtypes = [P, P, P, I, I, I]
             lib.oracle_exact_matmul.restype = None
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
+            lib.oracle_set_threads.restype = None
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
@@ -61,6 +63,13 @@ def available() -> bool:
 def num_threads() -> int:
     lib = _load()
     return int(lib.oracle_num_threads()) if lib is not None else 1
+
+
+def set_threads(n: int) -> None:
+    """Threads of the OpenMP loops from now on (for single-core timings)."""
+    lib = _load()
+    if lib is not None:
+        lib.oracle_set_threads(int(n))
 
 
 def modmatmul(a: np.ndarray, b: np.ndarray, p: int) -> np.ndarray:

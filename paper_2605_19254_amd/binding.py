@@ -80,7 +80,8 @@ class RnsSmithStats(ctypes.Structure):
                 ("t_uc", ctypes.c_double), ("t_total", ctypes.c_double),
                 ("restarts", _I32), ("lift_steps", _I32), ("products", _I64),
                 ("residue_ops", ctypes.c_double), ("cert_primes", _I32),
-                ("columns", _I32), ("path", _I32), ("cert_exact", _I32)]
+                ("columns", _I32), ("path", _I32), ("cert_exact", _I32),
+                ("lift_a_bytes", _I32), ("lift_kernels", _I32), ("t_host_cpu", ctypes.c_double)]
 
 
 def _sig(name, res, args):
@@ -163,6 +164,8 @@ _lib_srv_destroy = _sig("rns_server_destroy", None, [_P])
 _lib_profile = _sig("rns_ctx_profile", _I32, [_P, _I32])
 _lib_calibrate = _sig("rns_calibrate", _I32, [_P, _I32, _I32, _I32, _P, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_double)])
+_lib_lift_step = _sig("rns_lift_step", _I32, [_I32, _P, _P, _P, _I64, _I32, ctypes.c_uint32, _I32, _P, _P, _P,
+                                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I32), _P])
 _lib_profile_read = _sig("rns_ctx_profile_read", _I32, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                                         ctypes.POINTER(_I64)])
 
@@ -177,7 +180,7 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy",
            "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
            "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate",
-           "rns_ctx_set_smith_path", "rns_largest_invariant"]
+           "rns_ctx_set_smith_path", "rns_largest_invariant", "rns_lift_step"]
 
 
 class RnsError(RuntimeError):
@@ -601,6 +604,31 @@ def largest_invariant(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult
     h = _P()
     _check(_lib_lif(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "rns_largest_invariant")
     return _smith_result(h)
+
+
+LIFT_C_MFMA, LIFT_AX_MFMA, LIFT_PACKED, LIFT_A_INT16 = 1, 2, 4, 8
+
+
+def lift_step(C, A, R, p: int, form: str = "mfma", device: int = 0, stream=None):
+    """One Dixon lifting step on the GPU (rns_lift_step).  C: uint32 residues
+    as int32 (n, n); A: int64 (n, n); R: int64 (t, n) -- device tensors.
+    Returns (X int32 (t, n), R_next int64 (t, n), Rm_next int32 (t, n),
+    inexact: bool, kernels: LIFT_* bits)."""
+    import torch
+    n = A.shape[0]
+    t = R.shape[0]
+    assert C.shape == (n, n) and A.shape == (n, n) and R.shape == (t, n)
+    assert C.dtype == torch.int32 and A.dtype == torch.int64 and R.dtype == torch.int64
+    assert C.is_contiguous() and A.is_contiguous() and R.is_contiguous()
+    X = torch.empty((t, n), dtype=torch.int32, device=A.device)
+    Rn = torch.empty((t, n), dtype=torch.int64, device=A.device)
+    Rnm = torch.empty((t, n), dtype=torch.int32, device=A.device)
+    bad = ctypes.c_int32()
+    used = _I32()
+    _check(_lib_lift_step(device, _dev_ptr(C), _dev_ptr(A), _dev_ptr(R), n, t, p,
+                          {"vector": 0, "mfma": 1}[form], _dev_ptr(X), _dev_ptr(Rn), _dev_ptr(Rnm),
+                          ctypes.byref(bad), ctypes.byref(used), _stream(stream)), "rns_lift_step")
+    return X, Rn, Rnm, bool(bad.value), used.value
 
 
 def server_footprint(n: int) -> int:

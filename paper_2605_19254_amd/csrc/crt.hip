@@ -461,11 +461,11 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
     j.col_tiles = crt_col_tiles(cols, E);
     if (fast) {
         const LagrangeTable *lt = nullptr;
-        int st = lagrange_table(ctx, prime_begin, L, W, &lt);
+        int st = lagrange_table(ctx, prime_begin, L, W, &lt, s);
         if (st != RNS_OK) return st;
         j.lag_c = lt->d_c; j.lag_mj = lt->d_mj; j.lag_m = lt->d_m;
     } else {
-        int st = mixed_radix_half(ctx, prime_begin, L, &j.half);
+        int st = mixed_radix_half(ctx, prime_begin, L, &j.half, s);
         if (st != RNS_OK) return st;
     }
     ProfScope ps(ctx, fast ? "k_crt_lagrange" : "k_crt_garner", s);

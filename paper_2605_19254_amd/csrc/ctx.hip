@@ -262,7 +262,9 @@ int ensure_desc(rns_ctx *ctx, size_t bytes) {
 }
 
 // Lagrange constants of the primes range [begin, begin+L) for W output words.
-int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **out) {
+// Built on first use with copies on the caller's stream `s` (never the null
+// stream, which would synchronise with other threads' streams).
+int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **out, hipStream_t s) {
     auto key = std::make_tuple(begin, L, W);
     auto it = ctx->lagrange.find(key);
     if (it != ctx->lagrange.end()) {
@@ -295,16 +297,17 @@ int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **
     RNS_HIP(hipMalloc(&t.d_c, sizeof(double) * L));
     RNS_HIP(hipMalloc(&t.d_mj, sizeof(uint64_t) * L * W));
     RNS_HIP(hipMalloc(&t.d_m, sizeof(uint64_t) * W));
-    RNS_HIP(hipMemcpy(t.d_c, c.data(), sizeof(double) * L, hipMemcpyHostToDevice));
-    RNS_HIP(hipMemcpy(t.d_mj, mj.data(), sizeof(uint64_t) * L * W, hipMemcpyHostToDevice));
-    RNS_HIP(hipMemcpy(t.d_m, m.data(), sizeof(uint64_t) * W, hipMemcpyHostToDevice));
+    RNS_HIP(hipMemcpyAsync(t.d_c, c.data(), sizeof(double) * L, hipMemcpyHostToDevice, s));
+    RNS_HIP(hipMemcpyAsync(t.d_mj, mj.data(), sizeof(uint64_t) * L * W, hipMemcpyHostToDevice, s));
+    RNS_HIP(hipMemcpyAsync(t.d_m, m.data(), sizeof(uint64_t) * W, hipMemcpyHostToDevice, s));
+    RNS_HIP(hipStreamSynchronize(s));                  // the host vectors end with this call
     auto res = ctx->lagrange.emplace(key, std::move(t));
     *out = &res.first->second;
     return RNS_OK;
 }
 
 // Mixed-radix digits h_j of (M-1)/2 for the range: (M-1)/2 = sum_j h_j * prod_{i<j} p_i.
-int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out) {
+int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out, hipStream_t s) {
     auto key = std::make_pair(begin, L);
     auto it = ctx->mr_half.find(key);
     if (it != ctx->mr_half.end()) {
@@ -320,8 +323,9 @@ int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out) {
     uint32_t *d = nullptr;
     RNS_HIP(hipSetDevice(ctx->device));
     RNS_HIP(hipMalloc(&d, sizeof(uint32_t) * L));
-    RNS_HIP(hipMemcpy(d, dig.data(), sizeof(uint32_t) * L, hipMemcpyHostToDevice));
     ctx->mr_half[key] = d;
+    RNS_HIP(hipMemcpyAsync(d, dig.data(), sizeof(uint32_t) * L, hipMemcpyHostToDevice, s));
+    RNS_HIP(hipStreamSynchronize(s));
     *out = d;
     return RNS_OK;
 }
@@ -388,8 +392,11 @@ extern "C" int rns_ctx_force_cert_failures(rns_ctx *ctx, int count) {
 
 namespace rns {
 
-ProfScope::ProfScope(rns_ctx *c, const char *n, hipStream_t st) : ctx(c), name(n), s(st) {
-    if (!ctx->prof) return;
+thread_local rns_ctx *tl_trace = nullptr;
+
+ProfScope::ProfScope(rns_ctx *c, const char *n, hipStream_t st, int64_t k)
+    : ctx(c), name(n), s(st), launches(k) {
+    if (!ctx || !ctx->prof) return;
     if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
     if (hipEventRecord(a, s) != hipSuccess) { (void)hipEventDestroy(a); a = nullptr; }
 }
@@ -402,8 +409,9 @@ ProfScope::~ProfScope() {
         if (b) (void)hipEventDestroy(b);
         return;
     }
-    std::lock_guard<std::mutex> g(ctx->prof_mu);
-    ctx->prof_recs.push_back({name, a, b});
+    rns_ctx *sink = ctx->prof_sink ? ctx->prof_sink : ctx;
+    std::lock_guard<std::mutex> g(sink->prof_mu);
+    sink->prof_recs.push_back({name, a, b, launches});
 }
 
 }  // namespace rns
@@ -433,7 +441,7 @@ extern "C" int rns_ctx_profile_read(rns_ctx *ctx, const char *name, double *tota
         if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
             st = RNS_EDEVICE;
         tot += ms;
-        ++cnt;
+        cnt += r.launches;
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
     }

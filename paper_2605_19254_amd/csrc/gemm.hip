@@ -439,3 +439,4 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
                     (int)plan.probs.size(), plan.total_tiles, plan.total_units, nullptr,
                     ctx->d_counter, s);
 }
+

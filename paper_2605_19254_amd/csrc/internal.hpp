@@ -100,9 +100,11 @@ struct rns_ctx {
     std::mutex mu;
     // tracing: (kernel name, start event, stop event) per launch
     bool prof = false;
+    rns_ctx *prof_sink = nullptr;      // records go here instead (the driver's basis -> its owner)
     struct ProfRec {
         const char *name;
         hipEvent_t a, b;
+        int64_t launches;              // kernel launches between the two events
     };
     std::vector<ProfRec> prof_recs;
     std::mutex prof_mu;
@@ -131,17 +133,22 @@ uint64_t mulmod_u64(uint64_t a, uint64_t b, uint64_t m);
 uint64_t powmod_u64(uint64_t a, uint64_t e, uint64_t m);
 uint64_t invmod_u64(uint64_t a, uint64_t m);            // m prime
 
-// Tracing helpers: bracket one kernel launch with events when enabled.
+// Tracing helpers: bracket one kernel launch (or `launches` launches in a
+// row) with events when the context traces; a null context traces nothing.
 struct ProfScope {
     rns_ctx *ctx;
     const char *name;
     hipStream_t s;
+    int64_t launches;
     hipEvent_t a = nullptr;
-    ProfScope(rns_ctx *c, const char *n, hipStream_t st);
+    ProfScope(rns_ctx *c, const char *n, hipStream_t st, int64_t launches = 1);
     ~ProfScope();
 };
+// The tracing context of the Smith-form solve running on this thread (null
+// when none traces): the driver's own kernel launchers record into it.
+extern thread_local rns_ctx *tl_trace;
 
-int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **out);
+int lagrange_table(rns_ctx *ctx, int begin, int L, int W, const LagrangeTable **out, hipStream_t s);
 
 // A gemm plan whose operands are int64 matrices (row-major A m x k, B k x n,
 // one per descriptor; the descriptors' A and B residue pointers are unused):
@@ -155,6 +162,6 @@ struct GemmInt64Src {
 };
 int gemm_plan_create_int64(rns_ctx *ctx, const rns_gemm_desc *descs, const GemmInt64Src *src, int count,
                            int path, rns_gemm_plan **out);
-int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out);
+int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out, hipStream_t s);
 
 }  // namespace rns

@@ -98,11 +98,11 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
             std::lock_guard<std::mutex> guard(ctx->mu);
             if (all_fast) {
                 const LagrangeTable *lt = nullptr;
-                int st = lagrange_table(ctx, x.prime_begin, x.L, W, &lt);
+                int st = lagrange_table(ctx, x.prime_begin, x.L, W, &lt, nullptr);
                 if (st != RNS_OK) return fail(st);
                 c.lag_c = lt->d_c; c.lag_mj = lt->d_mj; c.lag_m = lt->d_m;
             } else {
-                int st = mixed_radix_half(ctx, x.prime_begin, x.L, &c.half);
+                int st = mixed_radix_half(ctx, x.prime_begin, x.L, &c.half, nullptr);
                 if (st != RNS_OK) return fail(st);
             }
         }

@@ -51,6 +51,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <ctime>
 #include <functional>
 #include <memory>
 #include <new>
@@ -66,11 +67,13 @@ struct rns_smith_result {
 
 namespace {
 
-constexpr int kAuxPrimes = 256;     // basis of the driver's internal context
+constexpr int kAuxPrimes = 2048;    // basis of the driver's internal context
 constexpr int kChunk = 16;          // primes added per round
 constexpr int kMaxSolvePrimes = 64; // primes of one GPU CRT call
 constexpr int kMaxRestarts = 4;
-constexpr int kCertMaxPrimes = 48;  // lifting path: exact det certificate up to this many primes
+// Lifting path certificate: det A mod primes in chunks whose residue planes
+// take at most this many bytes (and at most 64 primes).
+constexpr double kCertChunkBytes = 16.0 * (1ull << 30);
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -88,6 +91,17 @@ struct SplitMix {
 
 // f(i) for i = 0..count-1 on up to 16 host threads (independent big-integer
 // work items of the lifting path).
+// CPU seconds used so far by the calling thread.
+double thread_cpu_s() {
+    timespec ts{};
+    clock_gettime(CLOCK_THREAD_CPUTIME_ID, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+// CPU seconds of the helper threads of the solve running on this thread
+// (added by parallel_for; null when no solve accounts for them).
+thread_local double *tl_helper_cpu = nullptr;
+
 template <typename F>
 void parallel_for(int count, F f) {
     const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -98,11 +112,15 @@ void parallel_for(int count, F f) {
     }
     std::atomic<int> next{0};
     std::vector<std::thread> th;
+    std::vector<double> cpu((size_t)nt, 0.0);
     for (int t = 0; t < nt; ++t)
-        th.emplace_back([&] {
+        th.emplace_back([&, t] {
             for (int i = next++; i < count; i = next++) f(i);
+            cpu[(size_t)t] = thread_cpu_s();             // a fresh thread: its whole CPU time
         });
     for (auto &x : th) x.join();
+    if (tl_helper_cpu)
+        for (double c : cpu) *tl_helper_cpu += c;
 }
 
 // parallel_for when the items are large enough to repay starting threads,
@@ -144,6 +162,29 @@ struct SolveScope {
     rns_ctx *prev;
     explicit SolveScope(rns_ctx *c) : prev(t_solve_ctx) { t_solve_ctx = c; }
     ~SolveScope() { t_solve_ctx = prev; }
+};
+
+// For the duration of a solve on this thread: the driver's kernel launches
+// (and the products it runs on its internal basis) are traced into ctx when
+// ctx traces, and the CPU time of the thread and of its helper threads is
+// accounted.
+struct TraceScope {
+    rns_ctx *prev_trace;
+    double *prev_cpu;
+    double helper = 0.0, t0;
+    TraceScope(rns_ctx *ctx, rns_ctx *aux) : prev_trace(tl_trace), prev_cpu(tl_helper_cpu), t0(thread_cpu_s()) {
+        tl_trace = ctx->prof ? ctx : nullptr;
+        if (aux) {
+            aux->prof = ctx->prof;
+            aux->prof_sink = ctx;
+        }
+        tl_helper_cpu = &helper;
+    }
+    double cpu_s() const { return thread_cpu_s() - t0 + helper; }
+    ~TraceScope() {
+        tl_trace = prev_trace;
+        tl_helper_cpu = prev_cpu;
+    }
 };
 
 constexpr size_t kPoolMaxBlock = size_t(64) << 20, kPoolMaxBytes = size_t(512) << 20;
@@ -209,7 +250,9 @@ struct DevBuf {
 
 // The stream of the context's solves (created by the first).
 int solve_stream(rns_ctx *ctx, hipStream_t *s) {
-    if (!ctx->solve_stream) RNS_HIP(hipStreamCreate(&ctx->solve_stream));
+    // Non-blocking: no implicit synchronisation with the null stream, so a
+    // solve never waits for (or breaks the graph capture of) another thread.
+    if (!ctx->solve_stream) RNS_HIP(hipStreamCreateWithFlags(&ctx->solve_stream, hipStreamNonBlocking));
     *s = ctx->solve_stream;
     return RNS_OK;
 }
@@ -753,7 +796,9 @@ struct Driver {
     DevBuf<int32_t> dflag;      // A has an entry outside the int16 range
     DevBuf<int64_t> dstep;      // device-side index of the next lifting step
     DevBuf<uint32_t> ddet;
-    bool cert_exact = true;
+
+    // The lifting products run on the matrix cores (else on the vector units).
+    bool mfma_lift() const { return n <= kLiftMfmaMaxN && !ctx->lift_vector_only; }
 
     // A as int16 (every |a| < 32640, two signed bytes) or int32 rows of stride ldl (zero padded)
     // for the lifting kernels, built on the device from the int64 A there
@@ -886,7 +931,7 @@ struct Driver {
         DRV_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), stream));
         DRV_HIP(hipMemsetAsync(dstep.p, 0, sizeof(int64_t), stream));
         LiftBufs lb{dR0.p, dR1.p, dRm0.p, dRm1.p, dXh.p, derr.p, dstep.p};
-        if (n <= kLiftMfmaMaxN && !ctx->lift_vector_only) {   // C's digits, once per lifting
+        if (mfma_lift()) {                               // C's digits, once per lifting
             DRV_ST(dCt.alloc(lift_tile_c_bytes(n)));
             launch_lift_tile_c(dC.p, n, ldl, p, dCt.p, stream);
             DRV_HIP(hipGetLastError());
@@ -911,6 +956,7 @@ struct Driver {
         StepGraph graph;
         auto capture = [&]() {
             graph.tried = true;
+            if (tl_trace) return;                        // traced launches are bracketed one run at a time
             if (hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) != hipSuccess) return;
             launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, t, p, lb, kLiftGraphSteps, stream);
             hipGraph_t gr = nullptr;
@@ -1052,20 +1098,28 @@ struct Driver {
     }
 
     // prod of the extracted invariants == |det A|, with det A / s rebuilt from
-    // det A mod primes (exact once the primes' product exceeds 2 H / s + 1).
+    // det A mod primes.  s divides s_n, hence det A, and |det A / s| <= H / s
+    // for Hadamard's bound H, so once the primes' product exceeds 2 H / s + 1
+    // the reconstruction is det A / s itself: the check is exact (Las Vegas),
+    // whatever the size.  prod = s * c for the candidate c = prod_{i<n} s_i;
+    // a prime at which det A / s is neither c nor -c ends the check early.
     int lift_certify(int pidx, uint32_t detp, const BigInt &s, const BigInt &prod, bool *ok) {
         *ok = false;
         const double need = abits - (double)s.bit_length() + 3.0;     // bits of 2 H / s, generously
         const int exact_primes = std::max(1, (int)std::ceil(need / 25.9));
-        cert_exact = exact_primes <= kCertMaxPrimes;
-        BigInt D(0), Q(1), prevD;
-        int used = 0, stable = 0;
+        const BigInt c = prod / s;
+        if (!(c * s == prod)) return RNS_OK;             // |det A| is a multiple of s; prod is not
+        BigInt D(0), Q(1);
+        int used = 0;
+        bool mismatch = false;
         auto add = [&](uint32_t q, uint32_t dq) {
             const uint32_t sq = s.mod_small(q);
             if (sq == 0) return;                         // q divides s, hence det A: no information
             // dq / sq mod q, then D <- the CRT combination of D mod Q and it mod q.
             const uint32_t sinv = (uint32_t)powmod_u64(sq, q - 2, q);
             const uint64_t target = (uint64_t)dq * sinv % q;
+            const uint64_t cq = c.mod_small(q);
+            if (target != cq && target != (q - cq) % q) mismatch = true;
             const uint64_t dmod = D.mod_small(q);
             const uint64_t qinv = powmod_u64(Q.mod_small(q), q - 2, q);
             const uint64_t k = (target + q - dmod) % q * qinv % q;
@@ -1075,34 +1129,23 @@ struct Driver {
         };
         add(aux->primes[pidx], detp);
         int next = pidx + 1;
-        // One batch of all the primes an exact check needs; otherwise a few
-        // at a time until the reconstruction stops changing.
-        const int chunk = cert_exact ? std::min(exact_primes + 1, 64) : 4;
-        while (used < std::max(exact_primes, 3) + 2 && used < kCertMaxPrimes + 8) {
+        const int chunk_max = (int)std::max(1.0, std::min(64.0, kCertChunkBytes / (4.0 * (double)n * (double)n)));
+        while (used < exact_primes && !mismatch) {
+            // one extra prime per chunk covers a prime that divides s
+            const int want = std::min(chunk_max, exact_primes - used + 1);
             std::vector<int> idx;
-            for (int j = 0; j < chunk && next < kAuxPrimes; ++j) idx.push_back(next++);
-            if (idx.empty()) return RNS_ENOTSUP;
+            for (int j = 0; j < want && next < kAuxPrimes; ++j) idx.push_back(next++);
+            if (idx.empty()) return RNS_ENOTSUP;        // 2 H / s exceeds the driver's basis
             std::vector<uint32_t> det;
             DRV_ST(det_mod_primes(idx, det));
-            bool done = false;
-            for (size_t j = 0; j < idx.size() && !done; ++j) {
+            for (size_t j = 0; j < idx.size() && used < exact_primes && !mismatch; ++j)
                 add(aux->primes[idx[j]], det[j]);
-                BigInt Ds = D;                           // symmetric representative
-                if (BigInt::cmp(Ds.shl(1), Q) > 0) Ds = Ds - Q;
-                if (cert_exact) {
-                    done = used >= exact_primes;
-                } else {
-                    stable = (used > 1 && Ds == prevD) ? stable + 1 : 0;
-                    done = stable >= 2;
-                }
-                prevD = Ds;
-            }
-            if (done) break;
         }
         st.cert_primes = used;
-        BigInt Ds = D;
+        if (mismatch) return RNS_OK;
+        BigInt Ds = D;                                   // symmetric representative
         if (BigInt::cmp(Ds.shl(1), Q) > 0) Ds = Ds - Q;
-        *ok = prod == s * BigInt::abs(Ds);
+        *ok = c == BigInt::abs(Ds);
         return RNS_OK;
     }
 
@@ -1159,7 +1202,10 @@ struct Driver {
             res->s.assign(n, BigInt(1).mag_words());
             for (int i = 0; i < t; ++i) res->s[n - 1 - i] = (s / g[i]).mag_words();
             st.columns = t;
-            st.cert_exact = cert_exact ? 1 : 0;
+            st.cert_exact = 1;
+            st.lift_a_bytes = a_bytes;
+            st.lift_kernels = (mfma_lift() ? 1 : 0) | (mfma_lift() && a_bytes == 2 ? 2 | (lift_packed(t) ? 4 : 0) : 0) |
+                              (a_bytes == 2 ? 8 : 0);
             st.t_total = now_s() - t0;
             res->st = st;
             return RNS_OK;
@@ -1309,7 +1355,11 @@ extern "C" int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64
     d.A = A_host;
     d.seed = seed;
     int st = aux_ctx(ctx, &d.aux);
-    if (st == RNS_OK) st = d.solve(res);
+    if (st == RNS_OK) {
+        TraceScope trace(ctx, d.aux);
+        st = d.solve(res);
+        res->st.t_host_cpu = trace.cpu_s();
+    }
     if (st != RNS_OK) {
         delete res;
         return st;
@@ -1333,7 +1383,11 @@ extern "C" int rns_largest_invariant(rns_ctx *ctx, const int64_t *A_host, int64_
     d.A = A_host;
     d.seed = seed;
     int st = aux_ctx(ctx, &d.aux);
-    if (st == RNS_OK) st = d.solve_lif(res);
+    if (st == RNS_OK) {
+        TraceScope trace(ctx, d.aux);
+        st = d.solve_lif(res);
+        res->st.t_host_cpu = trace.cpu_s();
+    }
     if (st != RNS_OK) {
         delete res;
         return st;

@@ -1344,6 +1344,7 @@ __global__ __launch_bounds__(256) void k_loc_elim(uint64_t *__restrict__ M, int6
 
 void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const GjPrime *pr, int P,
                     hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_gj_load", s);
     dim3 grid((unsigned)((ld + 255) / 256), (unsigned)n, (unsigned)P);
     hipLaunchKernelGGL(k_gj_load, grid, dim3(256), 0, s, A, n, ld, M, pr);
 }
@@ -1424,6 +1425,7 @@ size_t lift_tile_c_bytes(int64_t n) { return (size_t)((n + 15) / 16) * (size_t)(
 
 void launch_lift_tile_c(const uint32_t *C, int64_t n, int64_t ld, uint32_t p, char *Ct, hipStream_t s) {
     if (n <= 0) return;
+    ProfScope trace_(tl_trace, "k_lift_tile_c", s);
     const int KT = (int)((n + 63) / 64);
     hipLaunchKernelGGL(k_lift_tile_c, dim3((unsigned)KT, (unsigned)((n + 15) / 16)), dim3(64), 0, s, C, n, ld, p,
                        KT, reinterpret_cast<v4i_l *>(Ct));
@@ -1433,6 +1435,7 @@ size_t lift_frag_bytes(int64_t n) { return (size_t)((n + 63) / 64) * 4096; }
 
 void launch_lift_frag(const uint32_t *v, int64_t n, int64_t ld, int t, uint32_t p, char *frag, hipStream_t s) {
     if (n <= 0) return;
+    ProfScope trace_(tl_trace, "k_lift_frag", s);
     if (lift_packed(t)) {
         hipLaunchKernelGGL(k_lift_frag_pk, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, v, n, ld, t, p,
                            reinterpret_cast<v4i_l *>(frag));
@@ -1446,6 +1449,7 @@ size_t lift_tile_a_bytes(int64_t n) { return (size_t)((n + 15) / 16) * (size_t)(
 
 void launch_lift_tile_a(const int16_t *A, int64_t n, int64_t ld, char *At, hipStream_t s) {
     if (n <= 0) return;
+    ProfScope trace_(tl_trace, "k_lift_tile_a", s);
     const int KT = (int)((n + 63) / 64);
     hipLaunchKernelGGL(k_lift_tile_a, dim3((unsigned)KT, (unsigned)((n + 15) / 16)), dim3(64), 0, s, A, n, ld, KT,
                        reinterpret_cast<v4i_l *>(At));
@@ -1453,12 +1457,14 @@ void launch_lift_tile_a(const int16_t *A, int64_t n, int64_t ld, char *At, hipSt
 
 void launch_range16(const int64_t *A, int64_t count, int32_t *flag, hipStream_t s) {
     if (count <= 0) return;
+    ProfScope trace_(tl_trace, "k_range16", s);
     const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
     hipLaunchKernelGGL(k_range16, dim3((unsigned)blocks), dim3(256), 0, s, A, count, flag);
 }
 
 void launch_pack_rows(const int64_t *A, int64_t n, int64_t ld, int a_bytes, void *out, hipStream_t s) {
     if (n <= 0) return;
+    ProfScope trace_(tl_trace, "k_pack_rows", s);
     const int64_t blocks = std::min<int64_t>((n * ld + 255) / 256, 8192);
     if (a_bytes == 2)
         hipLaunchKernelGGL(k_pack_rows<int16_t>, dim3((unsigned)blocks), dim3(256), 0, s, A, n, ld,
@@ -1470,6 +1476,7 @@ void launch_pack_rows(const int64_t *A, int64_t n, int64_t ld, int a_bytes, void
 
 void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n, int64_t ld, int t, uint32_t p,
                        const LiftBufs &b, int steps, hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_lift_steps", s, 2 * (int64_t)steps + 1);
     for (int off = 0; off < steps; ++off) {
         if (a_bytes == 2)
             lift_step_at(C, static_cast<const int16_t *>(A), n, ld, t, p, b, off, s);
@@ -1482,12 +1489,14 @@ void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n,
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,
                       int64_t i0, int64_t i1, int64_t *Z, hipStream_t s) {
     if (i1 <= i0) return;
+    ProfScope trace_(tl_trace, "k_lift_proj", s);
     hipLaunchKernelGGL(k_lift_proj, dim3((unsigned)((i1 - i0) * t)), dim3(256), 0, s, Xh, n, ld, t, Rp, tp,
                        i0, Z);
 }
 
 void launch_gj_blockinv(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, const GjPrime *pr, int P,
                         uint32_t *W, int32_t *singular, int32_t *need, uint32_t *det, hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_gj_blockinv", s);
     hipLaunchKernelGGL(k_gj_blockinv, dim3((unsigned)P), dim3(1024), 0, s, M, n, ld, r0, bw, pr, W, singular, need,
                        det, 0);
 }
@@ -1495,6 +1504,7 @@ void launch_gj_blockinv(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, 
 void launch_gj_pivoted(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, const GjPrime *pr, int P,
                        uint32_t *S, int32_t *piv, int32_t *singular, int32_t *need, uint32_t *det, uint32_t *W,
                        hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_gj_pivoted", s, 3);
     hipLaunchKernelGGL(k_gj_panel, dim3((unsigned)P), dim3(1024), 0, s, M, n, ld, r0, bw, pr, S, piv, singular,
                        need, det);
     hipLaunchKernelGGL(k_gj_swap, dim3((unsigned)((ld + 255) / 256), (unsigned)P), dim3(256), 0, s, M, n, ld, r0,
@@ -1505,6 +1515,7 @@ void launch_gj_pivoted(uint32_t *M, int64_t n, int64_t ld, int64_t r0, int bw, c
 
 void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t plane_stride,
                   const GjPrime *pr, const uint32_t *c, int P, hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_scale", s);
     dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows, (unsigned)P);
     hipLaunchKernelGGL(k_scale, grid, dim3(256), 0, s, R, rows, cols, ld, plane_stride, pr, c);
 }
@@ -1512,29 +1523,34 @@ void launch_scale(uint32_t *R, int64_t rows, int64_t cols, int64_t ld, int64_t p
 void launch_words_mod(const uint64_t *x, int64_t count, int W, const GjPrime *pr, int L,
                       uint32_t *out, hipStream_t s) {
     if (count <= 0 || L <= 0) return;
+    ProfScope trace_(tl_trace, "k_words_mod", s);
     hipLaunchKernelGGL(k_words_mod, dim3((unsigned)((count + 255) / 256), (unsigned)L), dim3(256), 0, s, x,
                        count, W, pr, out);
 }
 
 void launch_check_sI(const uint32_t *P, int64_t n, const uint32_t *s_mod, int L, unsigned *mism,
                      hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_check_sI", s);
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)L);
     hipLaunchKernelGGL(k_check_sI, grid, dim3(256), 0, s, P, n, s_mod, mism);
 }
 
 void launch_words_mod_m(const uint64_t *x, int64_t count, int W, const LocalMod &lm, uint64_t *out,
                         hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_words_mod_m", s);
     hipLaunchKernelGGL(k_words_mod_m, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, x, count,
                        W, lm, out);
 }
 
 void launch_loc_init(const uint64_t *M, int64_t n, const LocalMod *lms, int F, uint64_t *keys, hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_loc_init", s);
     const int64_t blocks = std::min<int64_t>((n * n + 255) / 256, 512);
     hipLaunchKernelGGL(k_loc_init, dim3((unsigned)blocks, (unsigned)F), dim3(256), 0, s, M, n, lms, keys);
 }
 
 void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod *lms, int F, uint64_t *keys, int32_t *val,
                      uint64_t *uinv, hipStream_t s) {
+    ProfScope trace_(tl_trace, "k_loc_step", s, n - k - 1 > 0 ? 2 : 1);
     hipLaunchKernelGGL(k_loc_swap, dim3((unsigned)((n + 255) / 256), (unsigned)F), dim3(256), 0, s, M, n, k, lms,
                        keys, val, uinv);
     const int64_t w = n - k - 1;

@@ -270,3 +270,45 @@ def test_autotune_and_cache(ctx, rg, torch_dev):
         plan.close()
         c2.close()
         ctx.set_tune_cache("")
+
+
+@pytest.fixture(scope="module")
+def batch512():
+    batch = synth.uneven_batch(count=512, lo=32, hi=1024, bound=1 << 16, seed=0)
+    return batch, [native.exact_matmul(pr.a, pr.b) for pr in batch]
+
+
+@pytest.mark.parametrize("path", ["int8", "fp64"])
+def test_matmul_plan_512_uneven_full(ctx, rg, torch_dev, batch512, path):
+    """The 512-product workload exactly as the benchmark runs it (n_i
+    log-uniform in [32, 1024], seed 0, entries in [-2^16, 2^16], 2 primes
+    each, one whole-product plan, autotuned on the INT8 path, replayed from a
+    HIP graph): every entry of every product against the oracle's exact
+    product."""
+    torch, dev = torch_dev
+    _say("512 uneven products, all entries", path)
+    batch, wants = batch512
+    probs = [rg.MatmulProblem(torch.from_numpy(pr.a).to(dev), torch.from_numpy(pr.b).to(dev),
+                              torch.empty((pr.m, pr.n), dtype=torch.int64, device=dev),
+                              prime_begin=0, L=2, bound=pr.k << 32) for pr in batch]
+    plan = rg.MatmulPlan(ctx, probs, path=path)
+    if path == "int8":
+        plan.autotune()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.execute()
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for p in probs:
+            p.C.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        for i, (pr, p) in enumerate(zip(batch, probs)):
+            assert np.array_equal(p.C.cpu().numpy(), wants[i]), (rep, i, pr.n)
+        _say("  replay", rep, "agrees")
+    del g
+    plan.close()

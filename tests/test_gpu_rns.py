@@ -414,14 +414,23 @@ def test_exact_product_small(ctx, rg, torch_dev, path):
     assert ctx.status() == 0
 
 
+@pytest.fixture(scope="module")
+def n4096_product():
+    """The n = 4096 operands of the single-product workload and their exact
+    product C = A B from the oracle's plain C loop (every entry)."""
+    a, b = synth.square_pair(n=4096, bound=1 << 20, seed_a=0, seed_b=1)
+    return a, b, native.exact_matmul(a, b)
+
+
 @pytest.mark.parametrize("path", ["int8", "fp64", "int8-v0", "int8-v2", "int8-v3"])
-def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
-    """The full n = 4096, 24-prime product in the benchmark's configuration;
-    sampled outputs against the oracle, plus every residue of sampled rows."""
+def test_exact_product_n4096_full(ctx, rg, torch_dev, n4096_product, path):
+    """The full n = 4096, 24-prime product in the benchmark's configuration
+    through the boundary calls: every entry of C and every residue of every
+    prime plane against the oracle."""
     torch, dev = torch_dev
-    _say("exact product n=4096", path)
+    _say("exact product n=4096 (all entries)", path)
     n, L = 4096, 24
-    a, b = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
+    a, b, want = n4096_product
     ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
     ra = rg.rns_reduce(ctx, ta, L=L)
     rb = rg.rns_reduce(ctx, tb, L=L)
@@ -429,45 +438,66 @@ def test_exact_product_n4096_sampled(ctx, rg, torch_dev, path):
     _modmatmul(ctx, rg, [rg.GemmProblem(ra, rb, rc)], path)
     out = rg.crt_reconstruct(ctx, rc, L=L, W=1, bound=n << 40)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(5)
-    rows = rng.integers(0, n, size=3)
-    got = out[torch.from_numpy(rows).to(dev)].cpu().numpy()
-    want = native.exact_matmul(a[rows], b)
-    assert np.array_equal(got, want)
-    # residues of the sampled rows, every prime
-    rcs = rc[:, torch.from_numpy(rows).to(dev), :].cpu().numpy()
+    assert np.array_equal(out.cpu().numpy(), want)
     for j, p in enumerate(PRIMES[:L]):
-        assert np.array_equal(rcs[j], np.mod(want, p).astype(np.int32))
-    # sampled single entries anywhere
-    idx = rng.integers(0, n, size=(64, 2))
-    o = out.cpu().numpy()
-    for i, c in idx:
-        assert int(o[i, c]) == orns.exact_entry(a[i], b[:, c])
+        assert np.array_equal(rc[j].cpu().numpy(), np.mod(want, p).astype(np.int32)), j
     assert ctx.status() == 0
 
 
 @pytest.mark.parametrize("path", ["int8", "fp64"])
-def test_matmul_plan_n4096_sampled(ctx, rg, torch_dev, path):
+def test_matmul_plan_n4096_full(ctx, rg, torch_dev, n4096_product, path):
     """The benchmark's step: one whole-product plan over the n = 4096, 24-prime
     product (int64 A and B straight into the tiled operands, GEMM, Lagrange
-    CRT), executed twice; sampled rows and entries against the oracle."""
+    CRT), executed twice; every entry against the oracle both times."""
     torch, dev = torch_dev
-    _say("whole-product plan n=4096", path)
+    _say("whole-product plan n=4096 (all entries)", path)
     n, L = 4096, 24
-    a, b = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
+    a, b, want = n4096_product
     ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
     out = torch.empty((n, n), dtype=torch.int64, device=dev)
     plan = rg.MatmulPlan(ctx, [rg.MatmulProblem(ta, tb, out, prime_begin=0, L=L, bound=n << 40)], path=path)
     plan.execute()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
     out.fill_(0)
     plan.execute()                      # a second execution on the resident workspace
     torch.cuda.synchronize()
     assert ctx.status() == 0
-    rng = np.random.default_rng(9)
-    rows = np.concatenate([[0, n - 1], rng.integers(0, n, size=2)])
-    got = out[torch.from_numpy(rows).to(dev)].cpu().numpy()
-    assert np.array_equal(got, native.exact_matmul(a[rows], b))
-    o = out.cpu().numpy()
-    for i, c in rng.integers(0, n, size=(64, 2)):
-        assert int(o[i, c]) == orns.exact_entry(a[i], b[:, c])
+    assert np.array_equal(out.cpu().numpy(), want)
     plan.close()
+
+
+def test_full_range_residues_n4096_stripe(ctx, rg, torch_dev):
+    """The stress form of the n = 4096 product: every residue plane uniform in
+    [0, p_j) (seeded on the device as in the benchmark), INT8 products of all
+    24 primes and the exact mixed-radix CRT into 10 words.  Every residue and
+    every CRT output of a 256-row stripe against the oracle (schoolbook
+    modmatmul per prime, Lagrange CRT in Python integers)."""
+    torch, dev = torch_dev
+    _say("full-range residues n=4096 W=10, 256-row stripe")
+    n, L, W, rows = 4096, 24, 10, 256
+    ps = PRIMES[:L]
+    g = torch.Generator(device=dev)
+    ra = torch.empty((L, n, n), dtype=torch.int32, device=dev)
+    rb = torch.empty_like(ra)
+    for j, p in enumerate(ps):
+        g.manual_seed(1000 + j)
+        ra[j].random_(0, p, generator=g)
+        g.manual_seed(2000 + j)
+        rb[j].random_(0, p, generator=g)
+    rc = torch.empty_like(ra)
+    out = torch.empty((n, n, W), dtype=torch.int64, device=dev)
+    rg.modmatmul_batched(ctx, [rg.GemmProblem(ra, rb, rc)], path="int8")
+    rg.crt_reconstruct(ctx, rc, L=L, W=W, out=out)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    r0 = n // 2 - rows // 2                              # a stripe in the middle of C
+    a_s = ra[:, r0:r0 + rows, :].cpu().numpy().astype(np.uint32)
+    b_all = rb.cpu().numpy().astype(np.uint32)
+    want_res = np.stack([native.modmatmul(a_s[j], b_all[j], p) for j, p in enumerate(ps)])
+    got_res = rc[:, r0:r0 + rows, :].cpu().numpy().astype(np.uint32)
+    assert np.array_equal(got_res, want_res)
+    _say("  residues of the stripe agree; CRT of", rows * n, "entries")
+    want = orns.crt_planes(want_res, ps)
+    got = rg.words_to_ints(out[r0:r0 + rows].cpu().numpy())
+    assert np.array_equal(got, want)

@@ -2,6 +2,8 @@
 served in the mix equals the result of the same request alone, and equals the
 oracle or the planted invariants; a singular request fails alone; admission
 respects the device-memory budget."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -35,6 +37,14 @@ def _mix():
     for n, sd in [(12, 5), (24, 6), (31, 7)]:
         a = synth.small_smith(seed=sd, n=n, bound=1 << 10)
         reqs.append((a, osmith.smith_form(a)))
+    # requests whose invariants are too large for the residue path: the p-adic
+    # lifting path (its lifting graphs are captured while other requests run);
+    # expected values are the oracle's, stored by tests/golden/make_smith_golden.py
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "smith_lifting.json")))
+    for case in gold["cases"]:
+        if case["gen"] == "small_smith" and case["n"] in (80, 120):
+            a = synth.small_smith(seed=case["seed"], attempt=case["attempt"], n=case["n"], bound=case["bound"])
+            reqs.append((a, [1] * case["ones"] + [int(v) for v in case["tail"]]))
     sing = np.array([[1, 2, 3, 4, 5]] * 5, dtype=np.int64) + np.arange(5)[:, None]
     sing[4] = sing[0] + sing[1] - sing[2]     # dependent row
     reqs.insert(3, (sing, None))
@@ -56,11 +66,13 @@ def test_mix_equals_alone(rg):
                 continue
             assert st == 0, info
             assert res.s == want
+            assert res.stats["cert_exact"] == 1
             alone = rg.smith_form(ctx, a, seed=99)
             assert alone.s == res.s
             assert info["t_end"] >= info["t_start"] >= info["t_submit"] - 1e-6
     assert stats["max_running"] >= 2
     assert stats["high_water"] <= stats["budget"]
+    assert sum(1 for (_, w), (st, r, _) in zip(reqs, results) if r is not None and r.stats["path"] == 1) >= 2
 
 
 def test_admission_by_footprint(rg):

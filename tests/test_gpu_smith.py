@@ -227,6 +227,13 @@ def test_lifting_int16_edge_matches_oracle(lifting_ctx, rg, edge):
     res = rg.smith_form(ctx, a, seed=edge)
     assert res.s == osmith.smith_form(a)
     assert res.stats["path"] == 1
+    # which form of A and which lifting kernels ran (bit 1: A X on the matrix
+    # cores, bit 3: A stored as int16)
+    int16 = edge < 32640
+    assert res.stats["lift_a_bytes"] == (2 if int16 else 4)
+    assert bool(res.stats["lift_kernels"] & rg.binding.LIFT_A_INT16) == int16
+    assert bool(res.stats["lift_kernels"] & rg.binding.LIFT_AX_MFMA) == int16
+    assert res.stats["lift_kernels"] & rg.binding.LIFT_C_MFMA
 
 
 def test_lifting_vector_kernels_match(rg, monkeypatch):

@@ -235,3 +235,87 @@ def test_primes_needed_and_hadamard():
     for _ in range(10):
         a = rng.integers(-9, 10, size=(6, 6))
         assert abs(int(sympy.Matrix(a.tolist()).det())) <= rns.hadamard_bound(a)
+
+
+# ------------------------------------------- single entries and plane stacks --
+# modmatmul_entry and exact_entry are the expected values of sampled checks at
+# sizes where whole products are too slow; modmatmul_planes is the per-prime
+# loop of the CPU baseline.  Each is pinned here against brute force, closed
+# forms and the whole-matrix routines above.
+
+def test_modmatmul_entry_brute_force_and_closed_forms():
+    rng = np.random.default_rng(21)
+    ps = op.largest_primes_below(P26, 2) + [5, 97]
+    for trial in range(30):
+        p = ps[trial % len(ps)]
+        m, k, n = (int(v) for v in rng.integers(1, 7, size=3))
+        a = rng.integers(0, p, size=(m, k)).astype(np.uint32)
+        b = rng.integers(0, p, size=(k, n)).astype(np.uint32)
+        want = _brute(a, b, p)
+        for i in range(m):
+            for j in range(n):
+                assert rns.modmatmul_entry(a[i], b[:, j], p) == int(want[i, j])
+    p = 67108859
+    # (p-1)^2 = 1 mod p: a k-term row of p-1 against a column of p-1 gives k
+    for k in (1, 2048, 4099):
+        row = np.full(k, p - 1, dtype=np.uint32)
+        assert rns.modmatmul_entry(row, row, p) == k % p
+    # 2^25 * 2^25 = 2^50: the value mod p depends on p, so a swapped prime shows
+    assert rns.modmatmul_entry(np.array([1 << 25]), np.array([1 << 25]), p) == (1 << 50) % p
+    # an empty sum is 0
+    assert rns.modmatmul_entry(np.zeros(0, np.uint32), np.zeros(0, np.uint32), p) == 0
+
+
+def test_modmatmul_entry_matches_whole_products():
+    p = 67108837
+    rng = np.random.default_rng(22)
+    a = rng.integers(0, p, size=(5, 3000)).astype(np.uint32)
+    b = rng.integers(0, p, size=(3000, 4)).astype(np.uint32)
+    c = native.modmatmul(a, b, p)
+    for i in range(5):
+        for j in range(4):
+            assert rns.modmatmul_entry(a[i], b[:, j], p) == int(c[i, j])
+    # row and column roles: entry (i, j) uses row i of A and column j of B
+    a2 = np.arange(6, dtype=np.uint32).reshape(2, 3)
+    b2 = np.array([[1, 0], [0, 0], [0, 10]], dtype=np.uint32)
+    assert rns.modmatmul_entry(a2[1], b2[:, 1], 97) == (5 * 10) % 97
+    assert rns.modmatmul_entry(a2[0], b2[:, 0], 97) == 0
+
+
+def test_exact_entry_pins():
+    rng = np.random.default_rng(23)
+    a = rng.integers(-(1 << 20), (1 << 20) + 1, size=(4, 777), dtype=np.int64)
+    b = rng.integers(-(1 << 20), (1 << 20) + 1, size=(777, 3), dtype=np.int64)
+    c = native.exact_matmul(a, b)
+    for i in range(4):
+        for j in range(3):
+            want = 0
+            for t in range(777):
+                want += int(a[i, t]) * int(b[t, j])
+            assert rns.exact_entry(a[i], b[:, j]) == want == int(c[i, j])
+    # closed forms: a row of ones sums the column; values beyond int64 stay exact
+    col = np.array([3, -7, 11, 2**40], dtype=np.int64)
+    assert rns.exact_entry(np.ones(4, np.int64), col) == 3 - 7 + 11 + 2**40
+    big = np.full(8, (1 << 62), dtype=np.int64)
+    assert rns.exact_entry(big, big) == 8 * (1 << 124)
+    assert rns.exact_entry(np.array([-(1 << 63)], np.int64), np.array([-1], np.int64)) == 1 << 63
+
+
+@pytest.mark.parametrize("use_native", [False, True])
+def test_modmatmul_planes_prime_per_plane(use_native):
+    ps = op.largest_primes_below(P26, 5)
+    rng = np.random.default_rng(24)
+    L, m, k, n = 5, 3, 4, 2
+    a = np.stack([rng.integers(0, p, size=(m, k)) for p in ps]).astype(np.uint32)
+    b = np.stack([rng.integers(0, p, size=(k, n)) for p in ps]).astype(np.uint32)
+    got = rns.modmatmul_planes(a, b, ps, use_native=use_native)
+    assert got.shape == (L, m, n) and got.dtype == np.uint32
+    for j, p in enumerate(ps):
+        assert np.array_equal(got[j], _brute(a[j], b[j], p)), j
+    # plane j must be reduced by prime j: 2^25 * 2^25 = 2^50 differs per prime
+    one = np.full((L, 1, 1), 1 << 25, dtype=np.uint32)
+    got = rns.modmatmul_planes(one, one, ps, use_native=use_native)
+    assert [int(v) for v in got[:, 0, 0]] == [(1 << 50) % p for p in ps]
+    assert len(set(int(v) for v in got[:, 0, 0])) == L
+    # no primes: an empty stack of the right shape
+    assert rns.modmatmul_planes(a[:0], b[:0], [], use_native=use_native).shape == (0, m, n)
