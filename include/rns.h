@@ -48,7 +48,8 @@ enum {
     RNS_ESINGULAR = 6,  /* the input matrix is singular */
     RNS_ERETRY = 7,     /* the Las Vegas restart budget was exhausted */
     RNS_ENOTSUP = 8,    /* the request is outside what this build implements */
-    RNS_EPENDING = 9    /* a served request has not finished within the wait */
+    RNS_EPENDING = 9,   /* a served request has not finished within the wait */
+    RNS_ESCRATCH = 10   /* larger than the fixed scratch of modmatmul_batched_noalloc */
 };
 
 /* Product paths of modmatmul_batched. */
@@ -191,6 +192,28 @@ int rns_workspace_bytes(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
  */
 int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
                       int path, void *stream);
+
+/*
+ * modmatmul_batched_noalloc -- modmatmul_batched for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and exactness
+ * bounds; it calls no hipMalloc, hipFree or other device allocation.  Its
+ * scratch (the tiled digit or balanced operands, the problem table and the
+ * work counter) is a fixed array of rns_noalloc_scratch_bytes() bytes (64 MiB)
+ * per device, set up once per device by rns_ctx_create and held by the
+ * process until it ends; problems whose tiled operands and table do not fit
+ * return RNS_ESCRATCH and touch nothing.  The problem table is copied from
+ * host memory and the stream is synchronised once after that copy; the
+ * kernels then run asynchronously on `stream`.  Every call on one device
+ * shares the array: calls that overlap on one device (other streams, other
+ * threads, other contexts) race and give unspecified results; the array
+ * keeps the last call's contents.  With kernel tracing (rns_ctx_profile) on,
+ * each traced launch creates two HIP events.
+ */
+int modmatmul_batched_noalloc(rns_ctx *ctx, const rns_gemm_desc *descs, int count,
+                              int path, void *stream);
+/* Size in bytes of that fixed per-device scratch. */
+int rns_noalloc_scratch_bytes(size_t *bytes);
 
 /* ------------------------------------------------------------------------
  * Plans: the same products as modmatmul_batched, set up once and run many

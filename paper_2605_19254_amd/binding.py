@@ -57,7 +57,7 @@ def loaded_hip_runtimes():
         pass
     return sorted(out)
 
-OK, EINVAL, ENOMEM, EDEVICE, EBOUND, EOVERFLOW, ESINGULAR, ERETRY, ENOTSUP, EPENDING = range(10)
+OK, EINVAL, ENOMEM, EDEVICE, EBOUND, EOVERFLOW, ESINGULAR, ERETRY, ENOTSUP, EPENDING, ESCRATCH = range(11)
 PATH_AUTO, PATH_FP64, PATH_INT8 = 0, 1, 2
 _PATHS = {"auto": PATH_AUTO, "fp64": PATH_FP64, "int8": PATH_INT8}
 
@@ -104,6 +104,8 @@ _lib_primes_for_bound = _sig("rns_primes_for_bound", _I32, [_P, _P, _I32, ctypes
 _lib_reduce = _sig("rns_reduce", _I32, [_P, _P, _I64, _I64, _I64, _I32, _I32, _P, _I64, _I64, _P])
 _lib_reduce_mw = _sig("rns_reduce_mw", _I32, [_P, _P, _I32, _I64, _I64, _I64, _I32, _I32, _P, _I64, _I64, _P])
 _lib_modmatmul = _sig("modmatmul_batched", _I32, [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32, _P])
+_lib_modmatmul_noalloc = _sig("modmatmul_batched_noalloc", _I32, [_P, ctypes.POINTER(RnsGemmDesc), _I32, _I32, _P])
+_lib_noalloc_bytes = _sig("rns_noalloc_scratch_bytes", _I32, [ctypes.POINTER(ctypes.c_size_t)])
 _lib_crt = _sig("crt_reconstruct", _I32, [_P, _P, _I64, _I64, _I64, _I64, _I32, _I32, _P, _I32,
                                           _P, _I32, _I64, _P, _P])
 _lib_status = _sig("rns_ctx_status", _I32, [_P, _P])
@@ -180,7 +182,8 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_matmul_plan_info", "rns_matmul_plan_gemm", "rns_matmul_plan_destroy",
            "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
            "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate",
-           "rns_ctx_set_smith_path", "rns_largest_invariant", "rns_lift_step"]
+           "rns_ctx_set_smith_path", "rns_largest_invariant", "rns_lift_step",
+           "modmatmul_batched_noalloc", "rns_noalloc_scratch_bytes"]
 
 
 class RnsError(RuntimeError):
@@ -389,6 +392,21 @@ def modmatmul_batched(ctx: Context, problems: Sequence[GemmProblem], path="auto"
     path = _PATHS[path] if isinstance(path, str) else int(path)
     arr = _descs(problems)
     _check(_lib_modmatmul(ctx.handle, arr, len(problems), path, _stream(stream)), "modmatmul_batched")
+
+
+def modmatmul_batched_noalloc(ctx: Context, problems: Sequence[GemmProblem], path="auto", stream=None):
+    """modmatmul_batched with its scratch in the library's fixed per-device
+    array (no device allocation); RnsError(ESCRATCH) when it does not fit."""
+    path = _PATHS[path] if isinstance(path, str) else int(path)
+    arr = _descs(problems)
+    _check(_lib_modmatmul_noalloc(ctx.handle, arr, len(problems), path, _stream(stream)),
+           "modmatmul_batched_noalloc")
+
+
+def noalloc_scratch_bytes() -> int:
+    out = ctypes.c_size_t()
+    _check(_lib_noalloc_bytes(ctypes.byref(out)), "rns_noalloc_scratch_bytes")
+    return out.value
 
 
 def workspace_bytes(ctx: Context, problems: Sequence[GemmProblem], path="auto") -> int:

@@ -99,6 +99,7 @@ extern "C" const char *rns_strerror(int s) {
     case RNS_ERETRY: return "Las Vegas restart budget exhausted";
     case RNS_ENOTSUP: return "not supported by this build";
     case RNS_EPENDING: return "request still running";
+    case RNS_ESCRATCH: return "request exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -185,6 +186,7 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
     if (hipMemset(ctx->d_status, 0, sizeof(int32_t)) != hipSuccess) return fail(RNS_EDEVICE);
     if (hipMalloc(&ctx->d_counter, sizeof(unsigned)) != hipSuccess) return fail(RNS_ENOMEM);
     if (hipMemset(ctx->d_counter, 0, sizeof(unsigned)) != hipSuccess) return fail(RNS_EDEVICE);
+    (void)scratch_init(device);   // modmatmul_batched_noalloc reports a failure here
     {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)

@@ -440,3 +440,83 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
                     ctx->d_counter, s);
 }
 
+// ------------------------------------------ allocation-free batched call --
+// modmatmul_batched_noalloc keeps its scratch (tiled operands, problem table,
+// work counter) in this fixed array instead of the context's growable
+// workspace.  Each device holds its own copy; host code reaches it only
+// through the address hipGetSymbolAddress returns for that device (kept in
+// g_scratch), never through the array's name.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kScratchDevices] = {};
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+namespace rns {
+// Called by rns_ctx_create with `device` current.  A failure leaves the
+// device without scratch; only modmatmul_batched_noalloc reports it.
+int scratch_init(int device) {
+    if (device < 0 || device >= kScratchDevices) return RNS_EDEVICE;
+    std::lock_guard<std::mutex> guard(g_scratch_mu);
+    if (g_scratch[device]) return RNS_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return RNS_EDEVICE;
+    }
+    g_scratch[device] = static_cast<unsigned char *>(ptr);
+    return RNS_OK;
+}
+}  // namespace rns
+
+extern "C" int rns_noalloc_scratch_bytes(size_t *bytes) {
+    if (!bytes) return RNS_EINVAL;
+    *bytes = kScratchBytes;
+    return RNS_OK;
+}
+
+extern "C" int modmatmul_batched_noalloc(rns_ctx *ctx, const rns_gemm_desc *descs, int count, int path,
+                                         void *stream) {
+    if (!ctx || count < 0 || (count > 0 && !descs)) return RNS_EINVAL;
+    if (path != RNS_PATH_AUTO && path != RNS_PATH_FP64 && path != RNS_PATH_INT8) return RNS_EINVAL;
+    if (count == 0) return RNS_OK;
+    std::lock_guard<std::mutex> guard(ctx->mu);
+    bool int8 = true;
+    Plan plan;
+    int st = make_plan_path(ctx, descs, count, path, int8, plan);
+    if (st != RNS_OK) return st;
+    if (plan.probs.empty()) return RNS_OK;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (ctx->device >= 0 && ctx->device < kScratchDevices) base = g_scratch[ctx->device];
+    }
+    if (!base) return RNS_EDEVICE;
+    // Layout: tiled operands, then the problem table, then the work counter.
+    const size_t work = round256(plan.work_bytes);
+    const size_t tbytes = sizeof(GemmProblem) * plan.probs.size();
+    const size_t need = work + round256(tbytes) + 256;
+    if (need > kScratchBytes) return RNS_ESCRATCH;
+    RNS_HIP(hipSetDevice(ctx->device));
+    for (auto &g : plan.probs) {
+        g.At = reinterpret_cast<char *>(base) + reinterpret_cast<size_t>(g.At);
+        g.Bt = reinterpret_cast<char *>(base) + reinterpret_cast<size_t>(g.Bt);
+    }
+    GemmProblem *table = reinterpret_cast<GemmProblem *>(base + work);
+    unsigned *counter = reinterpret_cast<unsigned *>(base + work + round256(tbytes));
+    hipStream_t s = (hipStream_t)stream;
+    // The table's host copy belongs to this call: the copy must be complete
+    // before returning, so the stream is synchronised once after it (the
+    // launches below stay asynchronous).  The persistent variant's counter is
+    // cleared by the conversion launch before the GEMM reads it.
+    RNS_HIP(hipMemcpyAsync(table, plan.probs.data(), tbytes, hipMemcpyHostToDevice, s));
+    RNS_HIP(hipStreamSynchronize(s));
+    const int variant = choose_variant(ctx, int8, plan);
+    return run_plan(ctx, int8, variant, table, (int)plan.probs.size(), plan.total_tiles, plan.total_units,
+                    nullptr, counter, s);
+}

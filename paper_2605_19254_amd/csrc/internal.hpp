@@ -120,6 +120,9 @@ namespace rns {
     } while (0)
 
 int ensure_workspace(rns_ctx *ctx, size_t bytes);
+// Address of the allocation-free entry point's static scratch on `device`
+// (the device must be current); called once per device at context creation.
+int scratch_init(int device);
 int ensure_desc(rns_ctx *ctx, size_t bytes);
 
 // Small host-side multiword unsigned integers (32-bit limbs, little-endian).
