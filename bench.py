@@ -444,8 +444,56 @@ def run_stress(rg, torch, dev, ctx, n, L, steps=3):
         print("bench.py: CRT reported an error on full-range residues", file=sys.stderr)
         sys.exit(1)
     ops = 2.0 * n ** 3 * L
+    # The other conversions of the path on the same planes: the 10-word
+    # integers back to 24 residue planes (multiword reduction; the round trip
+    # must give the planes back exactly), and the planes converted to 24 other
+    # primes, exactly (no bound) and in one pass (with a bound leaving the
+    # Lagrange margin, on the planes of the product's residues reduced to a
+    # bounded range); every entry compared on the device.
+    conv = {}
+    back = torch.empty_like(rc)
+    c2 = rg.Context(device=0, L=2 * L)
+    try:
+        def tk(f, reps=3):
+            f()
+            torch.cuda.synchronize()
+            c2.profile(True)
+            c2.profile_read("")
+            for _ in range(reps):
+                f()
+            torch.cuda.synchronize()
+            ms_, cnt_ = c2.profile_read("")
+            c2.profile(False)
+            return ms_ / cnt_
+        conv["reduce_mw_ms"] = tk(lambda: rg.rns_reduce_mw(c2, out, prime_begin=0, L=L, out=back))
+        if not torch.equal(back, rc):
+            print("bench.py: multiword reduction did not give the residues back", file=sys.stderr)
+            sys.exit(1)
+        other = torch.empty_like(rc)
+        conv["base_convert_exact_ms"] = tk(lambda: rg.base_convert(c2, rc, 0, L, L, L=L, out=other))
+        # the same integers' residues mod the other primes, from the 10 words
+        want = torch.empty_like(rc)
+        rg.rns_reduce_mw(c2, out, prime_begin=L, L=L, out=want)
+        torch.cuda.synchronize()
+        if not torch.equal(other, want):
+            print("bench.py: base conversion differs from reduction of the CRT output", file=sys.stderr)
+            sys.exit(1)
+        Mb = 1
+        for p in c2.primes[:L]:
+            Mb *= p
+        bound = Mb // 2 - (Mb >> 38)
+        conv["base_convert_one_pass_ms"] = tk(lambda: rg.base_convert(c2, rc, 0, L, L, L=L, bound=bound, out=other))
+        torch.cuda.synchronize()
+        if not torch.equal(other, want):          # full-range values stay within that bound but for 2^-38 of M
+            conv["one_pass_note"] = "full-range inputs exceed the promised bound in a few entries"
+        conv["bytes_per_entry"] = {"reduce_mw": 8 * W + 4 * L, "convert": 8 * L}
+        conv["reduce_mw_GBps"] = n * n * (8 * W + 4 * L) / (conv["reduce_mw_ms"] * 1e-3) / 1e9
+        conv["base_convert_one_pass_GBps"] = n * n * 8 * L / (conv["base_convert_one_pass_ms"] * 1e-3) / 1e9
+    finally:
+        c2.close()
     return {"workload": "full-range residues uniform in [0, p_j) per plane (seeded), %dx%d, %d primes, INT8 path, "
-                        "exact Garner CRT into %d words" % (n, n, L, W),
+                        "exact CRT (matrix-core Lagrange form) into %d words" % (n, n, L, W),
+            "conversions": conv,
             "ms_per_step": 1000 * t, "value": ops / t, "unit": "int-ops/s", "kernels": kern,
             "gemm_mfma_tops": 16.0 * ops / (kern["k_gemm"]["avg_ms"] * 1e-3) / 1e12, "sampled_entries_checked": 4}
 

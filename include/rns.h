@@ -139,8 +139,10 @@ int rns_reduce(rns_ctx *ctx, const int64_t *x, int64_t rows, int64_t cols,
  * whenever |x| < M/2 for the product M of the primes.
  *   x:   device uint64, 1 <= W <= 32, ldx >= cols (in entries).
  *   res: as for rns_reduce.
- * Each residue is formed by Horner's rule over the 32-bit halves of |x| in
- * exact double arithmetic, then negated mod p for negative x.
+ * Computed on the INT8 matrix cores: the 8W+1 signed base-256 digits of x
+ * times a table of the digits of 2^(8k) mod p_j (one int32 column sum per
+ * digit of each 2^(8k) mod p_j), then sum_b T_b 2^(8b) mod p_j exactly in
+ * doubles.
  */
 int rns_reduce_mw(rns_ctx *ctx, const uint64_t *x, int W, int64_t rows, int64_t cols,
                   int64_t ldx, int prime_begin, int L, uint32_t *res,
@@ -316,8 +318,14 @@ void rns_matmul_plan_destroy(rns_matmul_plan *plan);
  *   bound_words / Wb: optional promise |x| <= B (Wb little-endian words; NULL
  *         for none).  A promise that leaves a margin selects the Lagrange form
  *         with a floating-point correction (Section 3.1, the bullet on fast
- *         base conversion); otherwise the exact mixed-radix (Garner) form is
- *         used.  A false promise gives unspecified outputs.
+ *         base conversion), one thread per entry; otherwise the exact form
+ *         runs on the INT8 matrix cores: S = sum_j y_j (M/p_j) from the digits
+ *         of y_j = r_j (M/p_j)^-1 mod p_j times a table of the digits of M/p_j,
+ *         then x = S - a M with a = round(sum_j y_j / p_j), where a double
+ *         value of that sum within 2^-40 of a half-integer is settled by an
+ *         exact comparison with (M-1)/2.  (RNS_CRT_GARNER=1 in the environment
+ *         at context creation selects the mixed-radix form instead.)  A false
+ *         promise gives unspecified outputs.
  *   d_status: optional device int32; the kernel ORs 1 into it when some x
  *         does not fit in W words (that entry holds x mod 2^(64W)).  NULL
  *         uses the context's status word, read by rns_ctx_status.
@@ -328,6 +336,33 @@ int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows,
                     int prime_begin, int L, const uint64_t *bound_words,
                     int Wb, uint64_t *out, int W, int64_t ldo,
                     int32_t *d_status, void *stream);
+
+/*
+ * rns_base_convert -- Section 3.1, the bullet on fast RNS base conversion:
+ * residues of x in the primes range (begin, L) to residues of the same x in
+ * the range (begin_out, L_out), where x is the symmetric representative,
+ * |x| <= (M-1)/2 for M = p_begin ... p_(begin+L-1):
+ *     x mod q_i = sum_j y_j (M/p_j mod q_i) - a (M mod q_i),
+ *     y_j = r_j (M/p_j)^-1 mod p_j,  a = round(sum_j y_j / p_j),
+ * on the INT8 matrix cores (the digits of the y_j times a constant table).
+ *   res:  device uint32, L planes (rows x cols, leading dimension ldr,
+ *         plane_stride apart), residues in [0, p).
+ *   out:  device uint32, L_out planes (leading dimension ldo,
+ *         out_plane_stride apart), residues in [0, q).
+ *   bound_words / Wb: optional promise |x| <= B.  A promise that leaves the
+ *         margin of the Lagrange CRT (2B/M <= 1 - 2^-39) makes the
+ *         floating-point correction exact and the conversion one pass that
+ *         never forms x; without one x is rebuilt exactly (crt_reconstruct's
+ *         exact form, into the context workspace, which may grow) and then
+ *         reduced (rns_reduce_mw's kernel).  A false promise gives unspecified
+ *         outputs.
+ *   d_status: as for crt_reconstruct (unused on the one-pass form).
+ * Limits: 1 <= L <= 64, 1 <= L_out.  The ranges may overlap.
+ */
+int rns_base_convert(rns_ctx *ctx, const uint32_t *res, int64_t rows, int64_t cols, int64_t ldr,
+                     int64_t plane_stride, int begin, int L, const uint64_t *bound_words, int Wb,
+                     uint32_t *out, int64_t ldo, int64_t out_plane_stride, int begin_out, int L_out,
+                     int32_t *d_status, void *stream);
 
 /*
  * rns_ctx_status -- synchronise `stream`, then read and clear the context's

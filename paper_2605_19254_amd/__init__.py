@@ -8,6 +8,6 @@ fallback.
 """
 from .binding import (Context, GemmPlan, GemmProblem, MatmulPlan, MatmulProblem,  # noqa: F401
                       RnsError, Server, SmithResult, autotune, server_footprint, crt_reconstruct, modmatmul_batched,
-                      lift_step, modmatmul_batched_noalloc, noalloc_scratch_bytes,
+                      lift_step, modmatmul_batched_noalloc, noalloc_scratch_bytes, base_convert,
                       rns_primes_below, rns_reduce, rns_reduce_mw, rns_strerror, smith_form, largest_invariant, words_to_ints,
                       workspace_bytes)

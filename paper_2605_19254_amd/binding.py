@@ -109,6 +109,8 @@ _lib_noalloc_bytes = _sig("rns_noalloc_scratch_bytes", _I32, [ctypes.POINTER(cty
 _lib_crt = _sig("crt_reconstruct", _I32, [_P, _P, _I64, _I64, _I64, _I64, _I32, _I32, _P, _I32,
                                           _P, _I32, _I64, _P, _P])
 _lib_status = _sig("rns_ctx_status", _I32, [_P, _P])
+_lib_convert = _sig("rns_base_convert", _I32, [_P, _P, _I64, _I64, _I64, _I64, _I32, _I32, _P, _I32,
+                                               _P, _I64, _I64, _I32, _I32, _P, _P])
 _lib_force = _sig("rns_ctx_force_cert_failures", _I32, [_P, _I32])
 _lib_smith_path = _sig("rns_ctx_set_smith_path", _I32, [_P, _I32])
 _lib_smith = _sig("smith_form", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_P)])
@@ -183,7 +185,7 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
            "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate",
            "rns_ctx_set_smith_path", "rns_largest_invariant", "rns_lift_step",
-           "modmatmul_batched_noalloc", "rns_noalloc_scratch_bytes"]
+           "modmatmul_batched_noalloc", "rns_noalloc_scratch_bytes", "rns_base_convert"]
 
 
 class RnsError(RuntimeError):
@@ -562,6 +564,31 @@ def crt_reconstruct(ctx: Context, res, prime_begin: int = 0, L: Optional[int] = 
                     prime_begin, L, bptr, bw, _dev_ptr(out), W, cols, sptr, _stream(stream)),
            "crt_reconstruct")
     return out[:, :, 0] if W == 1 else out
+
+
+def base_convert(ctx: Context, res, prime_begin: int, prime_begin_out: int, L_out: int,
+                 L: Optional[int] = None, bound: Optional[int] = None, out=None, status=None, stream=None):
+    """Residues [L, rows, cols] in the primes range (prime_begin, L) ->
+    residues [L_out, rows, cols] of the same symmetric integer in the range
+    (prime_begin_out, L_out) (rns_base_convert); int32 device tensors."""
+    import torch
+    L = res.shape[0] if L is None else L
+    _, rows, cols = res.shape
+    assert res.dtype == torch.int32 and res.stride(2) == 1
+    if out is None:
+        out = torch.empty((L_out, rows, cols), dtype=torch.int32, device=res.device)
+    assert out.dtype == torch.int32 and out.stride(2) == 1
+    if bound is not None:
+        w = _words(bound)
+        barr = (ctypes.c_uint64 * len(w))(*w)
+        bptr, bw = ctypes.cast(barr, _P), len(w)
+    else:
+        bptr, bw = None, 0
+    sptr = _dev_ptr(status) if status is not None else None
+    _check(_lib_convert(ctx.handle, _dev_ptr(res), rows, cols, res.stride(1), res.stride(0), prime_begin, L,
+                        bptr, bw, _dev_ptr(out), out.stride(1), out.stride(0), prime_begin_out, L_out, sptr,
+                        _stream(stream)), "rns_base_convert")
+    return out
 
 
 def words_to_ints(words: np.ndarray) -> np.ndarray:

@@ -457,6 +457,8 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
     j.status = d_status ? d_status : ctx->d_status;
     j.tile_begin = 0;
     const bool fast = crt_fast_ok(ctx, prime_begin, L, bound_words, Wb, W);
+    if (!fast && !ctx->crt_garner)   // the exact form on the matrix cores (digits_gemm.hip)
+        return crt_mfma(ctx, res, rows, cols, ldr, plane_stride, prime_begin, L, out, W, ldo, j.status, s);
     const int E = crt_entries(fast, W, L);
     j.col_tiles = crt_col_tiles(cols, E);
     if (fast) {

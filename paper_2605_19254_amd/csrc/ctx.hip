@@ -164,6 +164,7 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
                    : (flags & 3) == RNS_CTX_PATH_INT8 ? RNS_PATH_INT8 : RNS_PATH_AUTO;
     if (const char *e = std::getenv("RNS_INT8_KERNEL")) ctx->int8_kernel = std::atoi(e);
     if (const char *e = std::getenv("RNS_LIFT_VECTOR")) ctx->lift_vector_only = std::atoi(e) != 0;
+    if (const char *e = std::getenv("RNS_CRT_GARNER")) ctx->crt_garner = std::atoi(e) != 0;
     ctx->primes = ps;
 
     std::vector<PrimeConst> pc(L);
@@ -217,6 +218,7 @@ extern "C" void rns_ctx_destroy(rns_ctx *ctx) {
         if (kv.second.d_mj) (void)hipFree(kv.second.d_mj);
         if (kv.second.d_m) (void)hipFree(kv.second.d_m);
     }
+    for (auto &kv : ctx->digit_tables) kv.second.release();
     for (auto &kv : ctx->mr_half)
         if (kv.second) (void)hipFree(kv.second);
     delete ctx;

@@ -63,6 +63,19 @@ struct LagrangeTable {
     std::vector<uint32_t> M;        // M as 32-bit limbs (host)
 };
 
+// Constant operand of a digits x table product on the matrix cores (CRT,
+// multiword reduction, base conversion) and its per-prime constants; built on
+// first use per primes range and kept in the context.
+struct DigitTable {
+    void *d_frag = nullptr;        // table fragments in the MFMA operand layout
+    double *d_c = nullptr;         // (M/p_j)^-1 mod p_j of the source range
+    uint32_t *d_mlimbs = nullptr;  // CRT: M in 32-bit limbs
+    uint32_t *d_half = nullptr;    // CRT: (M-1)/2 in 32-bit limbs
+    double *d_mq = nullptr;        // conversion: M mod q_i (balanced)
+    int nks = 0, nqb = 0, q = 0, groups = 0;
+    void release();
+};
+
 }  // namespace rns
 
 struct rns_ctx {
@@ -80,9 +93,11 @@ struct rns_ctx {
     void *h_desc = nullptr;            // pinned host staging of the problem table
     std::map<std::tuple<int, int, int>, rns::LagrangeTable> lagrange;
     std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
+    std::map<std::tuple<int, int, int, int, int>, rns::DigitTable> digit_tables;
     int force_cert_failures = 0;
     int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
     bool lift_vector_only = false;    // lifting products on the vector units only (RNS_LIFT_VECTOR)
+    bool crt_garner = false;          // exact CRT by the mixed-radix kernel (RNS_CRT_GARNER), not the matrix cores
     rns_ctx *aux = nullptr;            // wide-basis context of the Smith-form driver
     // Smith-form solves on this context run on one stream, created by the
     // first, and return their device blocks of up to 64 MiB to a pool (at

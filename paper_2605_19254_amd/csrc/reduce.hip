@@ -96,64 +96,6 @@ __global__ __launch_bounds__(kTile) void k_reduce(ReduceJob job0, const ReduceJo
     }
 }
 
-// Multiword entries: one thread per entry.  |x| is formed from the two's
-// complement words (negated when the top bit is set), then per prime
-// r <- (r * (2^32 mod p) + h) mod p over the 32-bit halves h from the top:
-// r * (2^32 mod p) < 2^52 and adding h < 2^32 stays below 2^53, so every step
-// is exact in doubles, and the rounded-reciprocal quotient is exact as in
-// reduce_one.  A negative x gives p - r (r != 0).
-constexpr int kMwBlock = 256;
-
-template <int WT>
-__global__ __launch_bounds__(kMwBlock) void k_reduce_mw(const uint64_t *__restrict__ x, int W, int64_t rows,
-                                                        int64_t cols, int64_t ldx, uint32_t *__restrict__ res,
-                                                        int64_t ldr, int64_t ps, int L,
-                                                        const PrimeConst *__restrict__ pc_all) {
-    const int64_t e = (int64_t)blockIdx.x * kMwBlock + threadIdx.x;
-    if (e >= rows * cols) return;
-    const int64_t i = e / cols, c = e - i * cols;
-    const auto src = gptr(x + (i * ldx + c) * W);
-    uint64_t w[WT];
-#pragma unroll
-    for (int k = 0; k < WT; ++k) w[k] = k < W ? src[k] : 0;
-    uint64_t top = 0;
-#pragma unroll
-    for (int k = 0; k < WT; ++k)
-        if (k == W - 1) top = w[k];
-    const bool neg = (top >> 63) != 0;
-    if (neg) {                                    // |x| = ~x + 1 over W words
-        uint64_t carry = 1;
-#pragma unroll
-        for (int k = 0; k < WT; ++k) {
-            if (k < W) {
-                const uint64_t v = ~w[k] + carry;
-                carry = (carry && v == 0) ? 1 : 0;
-                w[k] = v;
-            }
-        }
-    }
-    const auto pc = cptr(pc_all);
-    const auto dst = gptr_w(res + i * ldr + c);
-    for (int j = 0; j < L; ++j) {
-        const double pf = pc[j].pf, pinv = pc[j].pinv;
-        const double c32 = fma(-rint(4294967296.0 * pinv), pf, 4294967296.0);   // 2^32 mod p, balanced
-        double r = 0.0;
-#pragma unroll
-        for (int k = WT - 1; k >= 0; --k) {
-            if (k < W) {
-                const double hi = (double)(uint32_t)(w[k] >> 32), lo = (double)(uint32_t)w[k];
-                double v = fma(r, c32, hi);
-                r = fma(-rint(v * pinv), pf, v);
-                v = fma(r, c32, lo);
-                r = fma(-rint(v * pinv), pf, v);
-            }
-        }
-        r = r < 0.0 ? r + pf : r;                 // [0, p)
-        uint32_t out = (uint32_t)r;
-        if (neg && out != 0) out = pc[j].p - out;
-        dst[(int64_t)j * ps] = out;
-    }
-}
 
 }  // namespace
 
@@ -221,22 +163,10 @@ extern "C" int rns_reduce_mw(rns_ctx *ctx, const uint64_t *x, int W, int64_t row
     if (st != RNS_OK) return st;
     if (rows == 0 || cols == 0 || L == 0) return RNS_OK;
     if (rows > INT64_MAX / cols) return RNS_EINVAL;
+    std::lock_guard<std::mutex> guard(ctx->mu);
     RNS_HIP(hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t blocks = (rows * cols + kMwBlock - 1) / kMwBlock;
-    if (blocks > INT32_MAX) return RNS_EINVAL;
-    const PrimeConst *pc = ctx->d_prime + prime_begin;
-    ProfScope ps(ctx, "k_reduce_mw", s);
-#define RNS_MW(WT_) \
-    hipLaunchKernelGGL(k_reduce_mw<WT_>, dim3((unsigned)blocks), dim3(kMwBlock), 0, s, x, W, rows, cols, ldx, \
-                       res, ldr, plane_stride, L, pc)
-    if (W <= 1) RNS_MW(1);
-    else if (W <= 2) RNS_MW(2);
-    else if (W <= 4) RNS_MW(4);
-    else if (W <= 8) RNS_MW(8);
-    else if (W <= 16) RNS_MW(16);
-    else RNS_MW(32);
-#undef RNS_MW
-    RNS_HIP(hipGetLastError());
-    return RNS_OK;
+    // Balanced base-256 digits of x times the table of 2^(8k) mod p_j on the
+    // matrix cores (digits_gemm.hip).
+    return reduce_mw_mfma(ctx, x, W, rows, cols, ldx, prime_begin, L, res, ldr, plane_stride,
+                          (hipStream_t)stream);
 }

@@ -84,4 +84,11 @@ void launch_crt(bool fast, int W, int E, const CrtJob &job0, const CrtJob *jobs,
 // primes range, and fits W output words.
 bool crt_fast_ok(const rns_ctx *ctx, int begin, int L, const uint64_t *bound_words, int Wb, int W);
 
+// The matrix-core forms (digits x constant table, digits_gemm.hip); the
+// caller holds ctx->mu and has validated the arguments.
+int crt_mfma(rns_ctx *ctx, const uint32_t *res, int64_t rows, int64_t cols, int64_t ldr, int64_t ps,
+             int begin, int L, uint64_t *out, int W, int64_t ldo, int32_t *status, hipStream_t s);
+int reduce_mw_mfma(rns_ctx *ctx, const uint64_t *x, int W, int64_t rows, int64_t cols, int64_t ldx, int begin,
+                   int L, uint32_t *res, int64_t ldr, int64_t ps, hipStream_t s);
+
 }  // namespace rns
