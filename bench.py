@@ -94,7 +94,8 @@ def parse():
                     help="time the full-range residue product with 10-word CRT (0 = skip)")
     ap.add_argument("--serving", type=int, default=200,
                     help="requests per open-loop serving point (0 = skip)")
-    ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving", "lifting"],
+    ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving", "lifting", "smith64",
+                                                 "planted2000", "stress"],
                     help="run only this workload (for profiling)")
     ap.add_argument("--lifting-n", type=int, default=10007,
                     help="matrix order of the --only lifting workload (one random Smith-form solve)")
@@ -368,6 +369,31 @@ def run_smith(rg, reps=10, oracle_bg=None):
                                "seconds": t, "stats": res.stats, "traced": _traced(rg, ctx, pl.a),
                                "cpu_baseline": cb}
     return out
+
+
+def run_smith_one(rg, which, reps=10):
+    """One Smith-form workload alone (for a kernel trace of just that
+    workload): the 64 x 64 matrix (10 solves after a warm-up) or the planted
+    n = 2000 matrix (one solve after a warm-up), with the traced kernel time
+    and launch count of one more solve."""
+    import synth
+    from oracle import smith as osmith
+    with rg.Context(device=0, L=24) as ctx:
+        if which == "smith64":
+            a = synth.small_smith(seed=0)
+            want = osmith.smith_form(a)
+        else:
+            pl = synth.planted_smith(2000, seed=0)
+            a, want, reps = pl.a, pl.s, 1
+        rg.smith_form(ctx, a)
+        t0 = time.perf_counter()
+        for r in range(reps):
+            res = rg.smith_form(ctx, a, seed=r)
+        t = (time.perf_counter() - t0) / reps
+        if res.s != want:
+            raise SystemExit("bench.py: Smith form (%s) differs" % which)
+        return {"workload": which, "ms_per_solve": 1000 * t, "solves": reps, "stats": res.stats,
+                "traced": _traced(rg, ctx, a)}
 
 
 def _serving_stream(count, rate, seed, tail):
@@ -647,6 +673,13 @@ def main():
         return
     if args.only == "lifting":
         print(json.dumps(run_lifting(rg, args.lifting_n)), flush=True)
+        return
+    if args.only in ("smith64", "planted2000"):
+        print(json.dumps(run_smith_one(rg, args.only)), flush=True)
+        return
+    if args.only == "stress":
+        with rg.Context(device=0, L=args.primes) as c:
+            print(json.dumps(run_stress(rg, torch, dev, c, args.n, args.primes)), flush=True)
         return
     a_np, b_np = synth.square_pair(n=n, bound=1 << 20, seed_a=0, seed_b=1)
     A = torch.from_numpy(a_np).to(dev)

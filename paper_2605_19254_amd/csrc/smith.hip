@@ -68,6 +68,7 @@ struct rns_smith_result {
 namespace {
 
 constexpr int kAuxPrimes = 2048;    // basis of the driver's internal context
+constexpr int kDetPanel = 512;      // columns per Schur-complement update of the determinant elimination
 constexpr int kChunk = 16;          // primes added per round
 constexpr int kMaxSolvePrimes = 64; // primes of one GPU CRT call
 constexpr int kMaxRestarts = 4;
@@ -429,8 +430,109 @@ struct Driver {
     // Both products read their operands from the tiled workspace, which the
     // product's own conversion kernel fills before the product writes C, so
     // the update in place is safe.
+    // Forward elimination for the determinant (ld = n) in panels of
+    // kDetPanel columns, so that the Schur complement is updated once per
+    // panel with one residue product of depth kDetPanel instead of once per
+    // 128 columns:
+    //   A. inside the panel, 128 columns at a time: the pivot block's inverse
+    //      W_j (row exchanges across whole rows where needed), its rows
+    //      normalised and the rows below updated, panel columns only;
+    //   B. the panel's rows outside the panel: the same steps j in order
+    //      (rows of block j := W_j rows, later panel rows -= multipliers x them);
+    //   C. rows below the panel, columns beyond it: -= (their panel columns,
+    //      the multipliers of every step) x (the panel rows from B).
+    // C is the sum of the per-block updates of the 128-column form, so the
+    // result, and det, are the same.
+    int eliminate_det(uint32_t *M, int P, int pbeg, uint32_t *det) {
+        const int64_t ld = n;
+        constexpr int kSub = kDetPanel / kGjBlock;
+        DRV_ST(dS.alloc((size_t)P * n * kGjBlock));
+        DRV_ST(dpiv.alloc((size_t)P * kGjBlock));
+        DRV_ST(dW.alloc((size_t)P * kSub * kGjBlock * kGjBlock));
+        DRV_ST(dneed.alloc((size_t)P));
+        std::vector<int32_t> need(P);
+        const int64_t ps = n * ld;
+        const int64_t wps = (int64_t)kGjBlock * kGjBlock;
+        auto prod = [&](rns_gemm_desc *d, int cnt) -> int {
+            for (int i = 0; i < cnt; ++i) {
+                d[i].prime_begin = pbeg;
+                d[i].L = P;
+                st.residue_ops += 2.0 * d[i].m * d[i].n * d[i].k * P;
+            }
+            DRV_ST(modmatmul_batched(aux, d, cnt, RNS_PATH_AUTO, stream));
+            st.products += 1;
+            return RNS_OK;
+        };
+        for (int64_t P0 = 0; P0 < n; P0 += kDetPanel) {
+            const int64_t pend = std::min<int64_t>(n, P0 + kDetPanel);
+            int j = 0;
+            for (int64_t r0 = P0; r0 < pend; r0 += kGjBlock, ++j) {      // A
+                const int bw = (int)std::min<int64_t>(kGjBlock, pend - r0);
+                uint32_t *Wj = dW.p + (size_t)j * P * wps;
+                launch_gj_blockinv(M, n, ld, r0, bw, dpr.p, P, Wj, dsing.p, dneed.p, det, stream);
+                DRV_HIP(hipGetLastError());
+                DRV_HIP(hipMemcpyAsync(need.data(), dneed.p, sizeof(int32_t) * P, hipMemcpyDeviceToHost, stream));
+                DRV_ST(sync());
+                bool any = false;
+                for (int q = 0; q < P; ++q) any |= need[q] != 0;
+                if (any) {
+                    launch_gj_pivoted(M, n, ld, r0, bw, dpr.p, P, dS.p, dpiv.p, dsing.p, dneed.p, det, Wj, stream);
+                    DRV_HIP(hipGetLastError());
+                }
+                rns_gemm_desc d[2]{};
+                d[0].m = bw; d[0].n = pend - r0; d[0].k = bw;
+                d[0].A = Wj; d[0].lda = kGjBlock; d[0].a_plane_stride = wps;
+                d[0].B = M + r0 * ld + r0; d[0].ldb = ld; d[0].b_plane_stride = ps;
+                d[0].C = M + r0 * ld + r0; d[0].ldc = ld; d[0].c_plane_stride = ps;
+                DRV_ST(prod(d, 1));
+                const int64_t cols = pend - r0 - bw, rows = n - r0 - bw;
+                if (cols > 0 && rows > 0) {
+                    d[1].m = rows; d[1].n = cols; d[1].k = bw;
+                    d[1].A = M + (r0 + bw) * ld + r0; d[1].lda = ld; d[1].a_plane_stride = ps;
+                    d[1].B = M + r0 * ld + r0 + bw; d[1].ldb = ld; d[1].b_plane_stride = ps;
+                    d[1].C = M + (r0 + bw) * ld + r0 + bw; d[1].ldc = ld; d[1].c_plane_stride = ps;
+                    d[1].flags = RNS_GEMM_SUBTRACT;
+                    DRV_ST(prod(d + 1, 1));
+                }
+            }
+            const int64_t beyond = ld - pend;
+            if (beyond <= 0) continue;
+            j = 0;
+            for (int64_t r0 = P0; r0 < pend; r0 += kGjBlock, ++j) {      // B
+                const int bw = (int)std::min<int64_t>(kGjBlock, pend - r0);
+                rns_gemm_desc d{};
+                d.m = bw; d.n = beyond; d.k = bw;
+                d.A = dW.p + (size_t)j * P * wps; d.lda = kGjBlock; d.a_plane_stride = wps;
+                d.B = M + r0 * ld + pend; d.ldb = ld; d.b_plane_stride = ps;
+                d.C = M + r0 * ld + pend; d.ldc = ld; d.c_plane_stride = ps;
+                DRV_ST(prod(&d, 1));
+                const int64_t rows = pend - r0 - bw;
+                if (rows > 0) {
+                    rns_gemm_desc e{};
+                    e.m = rows; e.n = beyond; e.k = bw;
+                    e.A = M + (r0 + bw) * ld + r0; e.lda = ld; e.a_plane_stride = ps;
+                    e.B = M + r0 * ld + pend; e.ldb = ld; e.b_plane_stride = ps;
+                    e.C = M + (r0 + bw) * ld + pend; e.ldc = ld; e.c_plane_stride = ps;
+                    e.flags = RNS_GEMM_SUBTRACT;
+                    DRV_ST(prod(&e, 1));
+                }
+            }
+            if (n - pend > 0) {                                          // C
+                rns_gemm_desc d{};
+                d.m = n - pend; d.n = beyond; d.k = pend - P0;
+                d.A = M + pend * ld + P0; d.lda = ld; d.a_plane_stride = ps;
+                d.B = M + P0 * ld + pend; d.ldb = ld; d.b_plane_stride = ps;
+                d.C = M + pend * ld + pend; d.ldc = ld; d.c_plane_stride = ps;
+                d.flags = RNS_GEMM_SUBTRACT;
+                DRV_ST(prod(&d, 1));
+            }
+        }
+        return RNS_OK;
+    }
+
     int eliminate(uint32_t *M, int64_t ld, int P, int pbeg, uint32_t *det) {
         const bool full = ld == 2 * n;
+        if (!full) return eliminate_det(M, P, pbeg, det);
         DRV_ST(dS.alloc((size_t)P * n * kGjBlock));
         DRV_ST(dpiv.alloc((size_t)P * kGjBlock));
         DRV_ST(dW.alloc((size_t)P * kGjBlock * kGjBlock));

@@ -295,3 +295,25 @@ def test_largest_invariant_matches_oracle(ctx, rg, n):
     _say("largest invariant vs oracle, vandermonde", n)
     a = synth.vandermonde_mod(n)
     assert rg.largest_invariant(ctx, a, seed=n).s == [osmith.smith_form(a)[-1]]
+
+
+@pytest.mark.parametrize("n", [700, 1100])
+def test_lifting_certificate_over_several_panels(lifting_ctx, rg, n):
+    """The lifting path at sizes where the determinant elimination of the
+    certificate spans two and three 512-column panels (so the in-panel steps,
+    the panel rows beyond the panel and the deep Schur-complement update all
+    run), with a zero in the (0, 0) position so that the first pivot block
+    needs row exchanges.  The planted invariants are the expected values (a
+    row permutation does not change S), and the certificate must be exact."""
+    ctx = lifting_ctx
+    _say("smith lifting, certificate over panels", n)
+    pl = synth.planted_small(n, seed=n)
+    a = pl.a.copy()
+    rows0 = np.nonzero(a[:, 0] == 0)[0]
+    assert rows0.size > 0
+    a[[0, rows0[0]]] = a[[rows0[0], 0]]
+    assert a[0, 0] == 0
+    ctx.set_smith_path("lifting")
+    res = rg.smith_form(ctx, a, seed=3)
+    assert res.s == pl.s
+    assert res.stats["path"] == 1 and res.stats["cert_exact"] == 1 and res.stats["cert_primes"] >= 1
