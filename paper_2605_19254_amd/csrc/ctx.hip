@@ -213,6 +213,8 @@ extern "C" void rns_ctx_destroy(rns_ctx *ctx) {
     if (ctx->d_work) (void)hipFree(ctx->d_work);
     if (ctx->d_desc) (void)hipFree(ctx->d_desc);
     if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
+    for (int k = 0; k < kDescRing; ++k)
+        if (ctx->desc_ev[k]) (void)hipEventDestroy(ctx->desc_ev[k]);
     for (auto &kv : ctx->lagrange) {
         if (kv.second.d_c) (void)hipFree(kv.second.d_c);
         if (kv.second.d_mj) (void)hipFree(kv.second.d_mj);
@@ -258,9 +260,11 @@ int ensure_desc(rns_ctx *ctx, size_t bytes) {
     ctx->d_desc = nullptr;
     ctx->h_desc = nullptr;
     ctx->desc_bytes = 0;
-    size_t want = std::max<size_t>(bytes * 2, 4096);
-    RNS_HIP(hipMalloc(&ctx->d_desc, want));
-    RNS_HIP(hipHostMalloc(&ctx->h_desc, want, hipHostMallocDefault));
+    size_t want = (std::max<size_t>(bytes * 2, 4096) + 255) & ~(size_t)255;
+    RNS_HIP(hipMalloc(&ctx->d_desc, want * kDescRing));
+    RNS_HIP(hipHostMalloc(&ctx->h_desc, want * kDescRing, hipHostMallocDefault));
+    for (int k = 0; k < kDescRing; ++k)
+        if (!ctx->desc_ev[k]) RNS_HIP(hipEventCreateWithFlags(&ctx->desc_ev[k], hipEventDisableTiming));
     ctx->desc_bytes = want;
     return RNS_OK;
 }

@@ -429,15 +429,23 @@ extern "C" int modmatmul_batched(rns_ctx *ctx, const rns_gemm_desc *descs, int c
     st = ensure_desc(ctx, tbytes);
     if (st != RNS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    // The pinned staging buffer may still be read by an earlier copy on this
-    // stream; wait for it before overwriting.  (Plans avoid this round trip.)
-    RNS_HIP(hipStreamSynchronize(s));
-    std::memcpy(ctx->h_desc, plan.probs.data(), tbytes);
-    RNS_HIP(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, tbytes, hipMemcpyHostToDevice, s));
+    // Next slot of the problem-table ring: its previous call (copy and
+    // kernels) must have finished before the slot is overwritten, which after
+    // kDescRing calls it normally has, so consecutive calls do not wait for
+    // each other.
+    const int k = ctx->desc_next;
+    ctx->desc_next = (k + 1) % kDescRing;
+    RNS_HIP(hipEventSynchronize(ctx->desc_ev[k]));
+    char *h = static_cast<char *>(ctx->h_desc) + (size_t)k * ctx->desc_bytes;
+    char *dd = static_cast<char *>(ctx->d_desc) + (size_t)k * ctx->desc_bytes;
+    std::memcpy(h, plan.probs.data(), tbytes);
+    RNS_HIP(hipMemcpyAsync(dd, h, tbytes, hipMemcpyHostToDevice, s));
     const int variant = choose_variant(ctx, int8, plan);
-    return run_plan(ctx, int8, variant, static_cast<const GemmProblem *>(ctx->d_desc),
-                    (int)plan.probs.size(), plan.total_tiles, plan.total_units, nullptr,
-                    ctx->d_counter, s);
+    st = run_plan(ctx, int8, variant, reinterpret_cast<const GemmProblem *>(dd), (int)plan.probs.size(),
+                  plan.total_tiles, plan.total_units, nullptr, ctx->d_counter, s);
+    if (st != RNS_OK) return st;
+    RNS_HIP(hipEventRecord(ctx->desc_ev[k], s));
+    return RNS_OK;
 }
 
 // ------------------------------------------ allocation-free batched call --

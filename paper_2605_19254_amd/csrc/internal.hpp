@@ -20,6 +20,7 @@ constexpr int kMaxPrimes = 4096;
 constexpr int kCrtMaxL = 64;                 // primes per CRT call
 constexpr int kCrtMaxW = 32;                 // output words per CRT entry
 constexpr int64_t kInt8MaxK = 43690;         // int32 digit sums stay exact below
+constexpr int kDescRing = 16;                // problem-table slots of modmatmul_batched
 
 // Per-prime constants, read by every kernel (Section 3.1: precomputed once
 // per basis).  All doubles hold exact integers except pinv.
@@ -88,9 +89,14 @@ struct rns_ctx {
     int32_t *d_status = nullptr;
     void *d_work = nullptr;
     size_t work_bytes = 0;
-    void *d_desc = nullptr;            // device copy of the problem table
+    // Problem tables of modmatmul_batched: a ring of kDescRing slots of
+    // desc_bytes each (pinned host staging and device copy); a slot is reused
+    // once the event recorded after its call's kernels has completed.
+    void *d_desc = nullptr;
     size_t desc_bytes = 0;
-    void *h_desc = nullptr;            // pinned host staging of the problem table
+    void *h_desc = nullptr;
+    hipEvent_t desc_ev[16] = {};
+    int desc_next = 0;
     std::map<std::tuple<int, int, int>, rns::LagrangeTable> lagrange;
     std::map<std::pair<int, int>, uint32_t *> mr_half;  // (begin, L) -> digits
     std::map<std::tuple<int, int, int, int, int>, rns::DigitTable> digit_tables;
