@@ -390,8 +390,10 @@ typedef struct rns_smith_stats {
     double residue_ops;    /* 2*m*n*k*L summed over all products */
     int cert_primes;       /* path 0: primes of the exact check A X = s I;
                               path 1: primes of det A / s */
-    int columns;           /* columns of the projection J (n: J = I) */
-    int path;              /* 0: residues of s A^-1 (J = I); 1: p-adic lifting */
+    int columns;           /* columns of the projection J (n: J = I; massager:
+                              summed over the batches) */
+    int path;              /* 0: residues of s A^-1 (J = I); 1: p-adic lifting;
+                              2: Smith massager (rns_smith_massager) */
     int cert_exact;        /* 1: the result is certified (path 0: A X = s I
                               exactly; path 1: |det A| = prod s_i with det A / s
                               reconstructed from enough primes to be exact);
@@ -402,6 +404,7 @@ typedef struct rns_smith_stats {
                               lifting, as rns_lift_step's `kernels` bits */
     double t_host_cpu;     /* CPU seconds of the calling thread and of the
                               helper threads it started for this call */
+    int batches;           /* path 2: index-massager batches of Phase 2 */
 } rns_smith_stats;
 
 /*
@@ -427,9 +430,9 @@ int rns_ctx_set_smith_path(rns_ctx *ctx, int path);
  * common denominator of random projections of Y gives s; the Smith form over
  * Z/sZ of s R Y (R random t+2 x n) gives the t largest invariants (t doubles
  * up to 16 while fewer than two of them are 1); the certificate checks
- * prod s_i = |det A| with det A / s rebuilt from det A mod primes (exact when
- * at most 48 primes cover Hadamard's bound over s, else early-terminated:
- * stats.cert_exact says which).  RNS_ENOTSUP when neither path applies;
+ * prod s_i = |det A| with det A / s rebuilt from det A mod primes, enough of
+ * them (the product above 2 H / s + 1 for Hadamard's bound H) for the check to
+ * be exact.  RNS_ENOTSUP when neither path applies;
  * entries must not be INT64_MIN.
  *   A_host: host int64, n x n row-major (copied during the call).
  *   seed:   drives the random choices only; S does not depend on it.
@@ -452,6 +455,56 @@ int smith_form(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
  */
 int rns_largest_invariant(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
                           rns_smith_result **out);
+
+/*
+ * rns_smith_massager -- the Smith form S of a nonsingular A together with a
+ * Smith massager (U, M, T, S) (Section 2.1, Eq. (1)): n x n integer matrices
+ * with T unit upper triangular such that
+ *     B = [A, A M S^-1; U, (T + U M) S^-1]
+ * is integral and unimodular, i.e. A M S^-1 and (T + U M) S^-1 are integral
+ * and |det A| = prod s_i (Section 4.2's checks).  By the three phases of
+ * Section 2.2: Phase 1, s_n from p-adic lifting (as rns_largest_invariant);
+ * Phase 2, index-(m, r) Smith massagers (Definition 2) in batches: each
+ * batch lifts A^-1 J for a random J on the GPU (the resident C = A^-1 mod p),
+ * projects it through the earlier batches (the first block of B^-1 of the
+ * current massaged matrix), takes the Smith form of the n x t projection
+ * over Z/sZ with its transforms (U and M of the batch), and continues with
+ * s = the smallest invariant found; batch sizes grow with how far s fell, and
+ * once s fits a machine word one batch takes all remaining invariants
+ * (Section 3.2); Phase 3, |det A| = prod s_i checked exactly from det A mod
+ * primes (stands in for the unimodularity certification of B; a failure
+ * restarts, Las Vegas).
+ * Positions: the invariants equal to 1 first (their U rows and M columns are
+ * zero, their T columns unit vectors), then each batch in ascending order,
+ * later batches first.  Entries are non-negative and reduced: column j of M
+ * and T modulo s_j, row i of U modulo the modulus of its batch.
+ * Requires n >= 16 and n max|a_ij| < 2^36 (RNS_ENOTSUP otherwise; n = 0 gives
+ * an empty result); entries must not be INT64_MIN.  Read S with
+ * rns_smith_get, the massager with rns_smith_massager_vector; free with
+ * rns_smith_free.  Returns RNS_ESINGULAR when det A = 0, RNS_ERETRY when the
+ * restart budget is exhausted.
+ */
+int rns_smith_massager(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
+                       rns_smith_result **out);
+
+#define RNS_MASSAGER_U 0   /* rows of U */
+#define RNS_MASSAGER_M 1   /* columns of M */
+#define RNS_MASSAGER_T 2   /* columns of T */
+
+/*
+ * rns_smith_massager_width -- 64-bit words per entry of row `index` of U
+ * (which = RNS_MASSAGER_U) or column `index` of M or T; at least 1.  Returns
+ * -RNS_EINVAL for a bad argument or a result without a massager.
+ */
+int rns_smith_massager_width(const rns_smith_result *r, int which, int64_t index);
+
+/*
+ * rns_smith_massager_vector -- copies row `index` of U, or column `index` of
+ * M or T, to out: n entries of W words each (entry k at out[k W ..]),
+ * little-endian, zero-extended.  RNS_EBOUND if W is below the width;
+ * RNS_EINVAL for a bad argument or a result without a massager.
+ */
+int rns_smith_massager_vector(const rns_smith_result *r, int which, int64_t index, uint64_t *out, int W);
 
 /* Invariant factor i (0-based) as little-endian 64-bit magnitude words. */
 int rns_smith_get(const rns_smith_result *r, int64_t i, const uint64_t **words,

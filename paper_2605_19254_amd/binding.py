@@ -81,7 +81,8 @@ class RnsSmithStats(ctypes.Structure):
                 ("restarts", _I32), ("lift_steps", _I32), ("products", _I64),
                 ("residue_ops", ctypes.c_double), ("cert_primes", _I32),
                 ("columns", _I32), ("path", _I32), ("cert_exact", _I32),
-                ("lift_a_bytes", _I32), ("lift_kernels", _I32), ("t_host_cpu", ctypes.c_double)]
+                ("lift_a_bytes", _I32), ("lift_kernels", _I32), ("t_host_cpu", ctypes.c_double),
+                ("batches", _I32)]
 
 
 def _sig(name, res, args):
@@ -120,6 +121,9 @@ _lib_smith_get = _sig("rns_smith_get", _I32, [_P, _I64, ctypes.POINTER(ctypes.PO
 _lib_smith_size = _sig("rns_smith_size", _I64, [_P])
 _lib_smith_stats = _sig("rns_smith_stats_get", _I32, [_P, ctypes.POINTER(RnsSmithStats)])
 _lib_smith_free = _sig("rns_smith_free", None, [_P])
+_lib_massager = _sig("rns_smith_massager", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_P)])
+_lib_massager_width = _sig("rns_smith_massager_width", _I32, [_P, _I32, _I64])
+_lib_massager_vector = _sig("rns_smith_massager_vector", _I32, [_P, _I32, _I64, _P, _I32])
 class RnsPlanInfo(ctypes.Structure):
     _fields_ = [("path", _I32), ("variant", _I32), ("tiles", _I64), ("workspace_bytes", ctypes.c_size_t),
                 ("residue_ops", ctypes.c_double)]
@@ -185,7 +189,8 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_server_create", "rns_server_set_aging", "rns_server_submit", "rns_server_wait",
            "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate",
            "rns_ctx_set_smith_path", "rns_largest_invariant", "rns_lift_step",
-           "modmatmul_batched_noalloc", "rns_noalloc_scratch_bytes", "rns_base_convert"]
+           "modmatmul_batched_noalloc", "rns_noalloc_scratch_bytes", "rns_base_convert",
+           "rns_smith_massager", "rns_smith_massager_width", "rns_smith_massager_vector"]
 
 
 class RnsError(RuntimeError):
@@ -615,21 +620,9 @@ class SmithResult:
 
 def _smith_result(h) -> SmithResult:
     try:
-        s = []
-        words = ctypes.POINTER(ctypes.c_uint64)()
-        nw = _I32()
-        for i in range(_lib_smith_size(h)):
-            _check(_lib_smith_get(h, i, ctypes.byref(words), ctypes.byref(nw)), "rns_smith_get")
-            v = 0
-            for k in range(nw.value):
-                v |= int(words[k]) << (64 * k)
-            s.append(v)
-        st = RnsSmithStats()
-        _check(_lib_smith_stats(h, ctypes.byref(st)), "rns_smith_stats_get")
-        stats = {f: getattr(st, f) for f, _ in RnsSmithStats._fields_}
+        return _smith_result_keep(h)
     finally:
         _lib_smith_free(h)
-    return SmithResult(s, stats)
 
 
 def smith_form(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
@@ -639,6 +632,74 @@ def smith_form(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:
     h = _P()
     _check(_lib_smith(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "smith_form")
     return _smith_result(h)
+
+
+MASSAGER_U, MASSAGER_M, MASSAGER_T = 0, 1, 2
+
+
+@dataclass
+class MassagerResult:
+    """S (list of ints) and the Smith massager U (rows), M and T (columns) as
+    n x n object arrays of Python ints (rns_smith_massager)."""
+    s: List[int]
+    U: np.ndarray
+    M: np.ndarray
+    T: np.ndarray
+    stats: dict
+
+
+def smith_massager(ctx: Context, a: np.ndarray, seed: int = 0) -> MassagerResult:
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    h = _P()
+    _check(_lib_massager(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "rns_smith_massager")
+    try:
+        mats = []
+        for which in (MASSAGER_U, MASSAGER_M, MASSAGER_T):
+            out = np.empty((n, n), dtype=object)
+            for idx in range(n):
+                w = _lib_massager_width(h, which, idx)
+                if w < 1:
+                    raise RnsError(-w, "rns_smith_massager_width")
+                buf = np.zeros(n * w, dtype=np.uint64)
+                _check(_lib_massager_vector(h, which, idx, buf.ctypes.data, w), "rns_smith_massager_vector")
+                vals = words_to_uints(buf.reshape(n, w))
+                if which == MASSAGER_U:
+                    out[idx, :] = vals
+                else:
+                    out[:, idx] = vals
+            mats.append(out)
+        res = _smith_result_keep(h)
+    finally:
+        _lib_smith_free(h)
+    return MassagerResult(res.s, mats[0], mats[1], mats[2], res.stats)
+
+
+def words_to_uints(w: np.ndarray) -> list:
+    """Rows of little-endian 64-bit words as non-negative Python ints."""
+    out = []
+    for row in w:
+        u = 0
+        for k in range(row.shape[0] - 1, -1, -1):
+            u = (u << 64) | int(row[k])
+        out.append(u)
+    return out
+
+
+def _smith_result_keep(h) -> SmithResult:
+    s = []
+    words = ctypes.POINTER(ctypes.c_uint64)()
+    nw = _I32()
+    for i in range(_lib_smith_size(h)):
+        _check(_lib_smith_get(h, i, ctypes.byref(words), ctypes.byref(nw)), "rns_smith_get")
+        v = 0
+        for k in range(nw.value):
+            v |= int(words[k]) << (64 * k)
+        s.append(v)
+    st = RnsSmithStats()
+    _check(_lib_smith_stats(h, ctypes.byref(st)), "rns_smith_stats_get")
+    return SmithResult(s, {f: getattr(st, f) for f, _ in RnsSmithStats._fields_})
 
 
 def largest_invariant(ctx: Context, a: np.ndarray, seed: int = 0) -> SmithResult:

@@ -104,6 +104,7 @@ struct rns_ctx {
     int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
     bool lift_vector_only = false;    // lifting products on the vector units only (RNS_LIFT_VECTOR)
     bool crt_garner = false;          // exact CRT by the mixed-radix kernel (RNS_CRT_GARNER), not the matrix cores
+    int massager_r0 = 4;              // invariants taken by the first massager batch (RNS_MASSAGER_R0)
     rns_ctx *aux = nullptr;            // wide-basis context of the Smith-form driver
     // Smith-form solves on this context run on one stream, created by the
     // first, and return their device blocks of up to 64 MiB to a pool (at

@@ -1,0 +1,382 @@
+// Host algebra of the Smith massager path: the modular Smith form of an
+// n x t projection over Z/sZ with the transforms that give the batch's U and
+// M (Section 2.2, Phase 2, item 2), and the conversion of the top p-adic
+// digits of A^-1 J into Rem(s A^-1 J, s).
+//
+// Notation (Section 2.2, Phase 2): P_1 is n x t over Z/sZ.  The elimination
+// finds unimodular (mod s) E (n x n, kept as its list of row operations) and
+// R (t x t, kept explicitly) with E P_1 R = diag(d_0, ..., d_{t-1}) padded by
+// zero rows, d_0 | d_1 | ... | s, each d_j a divisor of s (d_j = s for a zero
+// entry).  With L = E^-1 this is P_1 R = L [D; 0]; the batch's massager
+// columns are M_j = L_j (the columns of P_1 R divided by d_j, determined
+// modulo s / d_j) and its rows are U_j = -(row j of E), so that
+// -U P_1 R = [D 0] and U M = -I modulo the orders s / d_j.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <functional>
+#include <utility>
+#include <vector>
+
+#include "bigint.hpp"
+
+namespace rns {
+namespace msg {
+
+// Z/sZ on machine words, s < 2^63.
+struct Ring64 {
+    using V = uint64_t;
+    uint64_t s;
+    explicit Ring64(uint64_t m) : s(m) {}
+    V zero() const { return 0; }
+    V one() const { return s == 1 ? 0 : 1; }
+    bool is_zero(V a) const { return a == 0; }
+    V from(const BigInt &x) const {
+        const BigInt r = mod(x, BigInt::from_u64(s));
+        return r.to_u64_mag();
+    }
+    BigInt big(V a) const { return BigInt::from_u64(a); }
+    V mul(V a, V b) const { return (V)((unsigned __int128)a * b % s); }
+    V add(V a, V b) const {
+        const V r = a + b;
+        return r >= s ? r - s : r;
+    }
+    V neg(V a) const { return a ? s - a : 0; }
+    static uint64_t gcd(uint64_t a, uint64_t b) {
+        while (b) {
+            const uint64_t t = a % b;
+            a = b;
+            b = t;
+        }
+        return a;
+    }
+    V gcd_s(V a) const { return gcd(a, s); }
+    bool divides(V g, V b) const { return b % g == 0; }
+    // a^-1 mod m for a prime to m (0 when m = 1), by the extended Euclidean
+    // algorithm on signed 128-bit cofactors.
+    static uint64_t inv(uint64_t a, uint64_t m) {
+        if (m == 1) return 0;
+        __int128 r0 = m, r1 = a % m, t0 = 0, t1 = 1;
+        while (r1) {
+            const __int128 q = r0 / r1;
+            __int128 x = r0 - q * r1;
+            r0 = r1;
+            r1 = x;
+            x = t0 - q * t1;
+            t0 = t1;
+            t1 = x;
+        }
+        if (t0 < 0) t0 += m;
+        return (uint64_t)t0;
+    }
+    static uint64_t mulm(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+    // f with b - f a = 0 (mod s), where g = gcd(a, s) divides b: a = g a',
+    // b = g b', a' prime to s/g, f = b' a'^-1 mod s/g.
+    V quot(V b, V a, V g) const {
+        const uint64_t m = s / g;
+        return mulm((b / g) % m, inv((a / g) % m, m), m);
+    }
+    // x with gcd(a + x b, s) = gcd(a, b, s): with g that gcd, x is the
+    // largest divisor of s/g prime to a/g (then every prime of s/g divides
+    // exactly one of a/g and x b/g).
+    V stab(V a, V b) const {
+        const uint64_t g = gcd(gcd(a, b), s);
+        const uint64_t N = s / g, ap = (a / g) % N;
+        uint64_t d = N, h;
+        while ((h = gcd(d, ap)) > 1) d /= h;
+        return d % s;
+    }
+    // u^-1 mod s for a = g u with u a unit mod s (g = gcd(a, s)).
+    V unit_inv(V a, V g) const {
+        const uint64_t N = s / g, u0 = (a / g) % N;
+        const uint64_t k = stab(u0 % s, N % s);
+        const uint64_t u = (u0 + mulm(k, N, s)) % s;
+        return inv(u, s);
+    }
+    // gcd h of divisors a, b of s with h = x a + y b; x, y mod s.
+    void xgcd(V a, V b, V &h, V &x, V &y) const {
+        __int128 r0 = a, r1 = b, s0 = 1, s1 = 0, t0 = 0, t1 = 1;
+        while (r1) {
+            const __int128 q = r0 / r1;
+            __int128 v = r0 - q * r1;
+            r0 = r1;
+            r1 = v;
+            v = s0 - q * s1;
+            s0 = s1;
+            s1 = v;
+            v = t0 - q * t1;
+            t0 = t1;
+            t1 = v;
+        }
+        h = (V)r0;
+        s0 %= (__int128)s;
+        t0 %= (__int128)s;
+        x = (V)(s0 < 0 ? s0 + s : s0);
+        y = (V)(t0 < 0 ? t0 + s : t0);
+    }
+    V divexact(V a, V b) const { return a / b; }
+    V mulexact(V a, V b) const { return a * b; }   // a b divides s here
+};
+
+// Z/sZ for any s > 1 on big integers.
+struct RingBig {
+    using V = BigInt;
+    BigInt s;
+    ModReducer red;
+    explicit RingBig(const BigInt &m) : s(m), red(m) {}
+    V zero() const { return BigInt(0); }
+    V one() const { return s.is_one() ? BigInt(0) : BigInt(1); }
+    bool is_zero(const V &a) const { return a.is_zero(); }
+    V from(const BigInt &x) const { return red.reduce(x); }
+    BigInt big(const V &a) const { return a; }
+    V mul(const V &a, const V &b) const { return red.reduce(a * b); }
+    V add(const V &a, const V &b) const {
+        BigInt r = a + b;
+        if (BigInt::cmp(r, s) >= 0) r = r - s;
+        return r;
+    }
+    V neg(const V &a) const { return a.is_zero() ? a : s - a; }
+    V gcd_s(const V &a) const { return a.is_zero() ? s : BigInt::gcd(a, s); }
+    bool divides(const V &g, const V &b) const { return mod(b, g).is_zero(); }
+    static BigInt inv(const BigInt &a, const BigInt &m) {
+        if (m.is_one()) return BigInt(0);
+        BigInt x, y;
+        BigInt::xgcd(mod(a, m), m, x, y);
+        return mod(x, m);
+    }
+    V quot(const V &b, const V &a, const V &g) const {
+        const BigInt m = s / g;
+        return mod((b / g) * inv(a / g, m), m);
+    }
+    V stab(const V &a, const V &b) const {
+        const BigInt g = BigInt::gcd(BigInt::gcd(a, b), s);
+        const BigInt N = s / g, ap = mod(a / g, N);
+        BigInt d = N, h;
+        while (!(h = BigInt::gcd(d, ap)).is_one() && !h.is_zero()) d = d / h;
+        return mod(d, s);
+    }
+    V unit_inv(const V &a, const V &g) const {
+        const BigInt N = s / g, u0 = mod(a / g, N);
+        const BigInt k = stab(mod(u0, s), mod(N, s));
+        return inv(mod(u0 + k * N, s), s);
+    }
+    void xgcd(const V &a, const V &b, V &h, V &x, V &y) const {
+        BigInt xx, yy;
+        h = BigInt::xgcd(a, b, xx, yy);
+        x = mod(xx, s);
+        y = mod(yy, s);
+    }
+    V divexact(const V &a, const V &b) const { return a / b; }
+    V mulexact(const V &a, const V &b) const { return a * b; }
+};
+
+// One row operation of the elimination, as a left factor of E:
+// kind 0 exchanges rows a and b; kind 1 adds x times row b to row a.
+template <class V>
+struct RowOp {
+    int kind;
+    int64_t a, b;
+    V x;
+};
+
+template <class Ring>
+struct SnfT {
+    using V = typename Ring::V;
+    std::vector<V> d;                 // t diagonal entries (divisors of s, divisibility order)
+    std::vector<V> R;                 // t x t, row-major
+    std::vector<RowOp<V>> ops;        // E = E_last ... E_first
+    int64_t rank = 0;                 // nonzero diagonal entries
+};
+
+// A loop over [0, count) that may run on host threads; `work` is the cost of
+// one item in ring operations (a hint for whether threads pay off).
+using ParFor = std::function<void(int64_t count, double work, const std::function<void(int64_t)> &)>;
+inline void seq_for(int64_t count, double, const std::function<void(int64_t)> &f) {
+    for (int64_t i = 0; i < count; ++i) f(i);
+}
+
+// Smith form of W (n x t over Z/sZ, row-major, entries reduced) with its
+// transforms.  Each step takes a nonzero pivot and makes it divide its column
+// and row (adding a multiple of another row or column chosen so that the
+// pivot's gcd with s becomes that of the pair), clears both, and scales the
+// pivot to the divisor gcd(pivot, s); a last pass puts the diagonal in
+// divisibility order by 2 x 2 operations that turn (a, b) into
+// (gcd(a, b), lcm(a, b)).
+template <class Ring>
+SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t n, int64_t t,
+                         const ParFor &par = seq_for) {
+    using V = typename Ring::V;
+    SnfT<Ring> out;
+    out.R.assign((size_t)(t * t), F.zero());
+    for (int64_t j = 0; j < t; ++j) out.R[(size_t)(j * t + j)] = F.one();
+    auto at = [&](int64_t i, int64_t j) -> V & { return W[(size_t)(i * t + j)]; };
+    auto Rat = [&](int64_t i, int64_t j) -> V & { return out.R[(size_t)(i * t + j)]; };
+    auto rowswap = [&](int64_t a, int64_t b) {
+        if (a == b) return;
+        for (int64_t j = 0; j < t; ++j) std::swap(at(a, j), at(b, j));
+        out.ops.push_back({0, a, b, F.zero()});
+    };
+    auto colswap = [&](int64_t a, int64_t b) {
+        if (a == b) return;
+        for (int64_t i = 0; i < n; ++i) std::swap(at(i, a), at(i, b));
+        for (int64_t i = 0; i < t; ++i) std::swap(Rat(i, a), Rat(i, b));
+    };
+    auto rowadd = [&](int64_t a, int64_t b, const V &x) {     // row a += x row b
+        for (int64_t j = 0; j < t; ++j) at(a, j) = F.add(at(a, j), F.mul(x, at(b, j)));
+        out.ops.push_back({1, a, b, x});
+    };
+    auto coladd = [&](int64_t a, int64_t b, const V &x) {     // col a += x col b
+        for (int64_t i = 0; i < n; ++i) at(i, a) = F.add(at(i, a), F.mul(x, at(i, b)));
+        for (int64_t i = 0; i < t; ++i) Rat(i, a) = F.add(Rat(i, a), F.mul(x, Rat(i, b)));
+    };
+    const int64_t steps = std::min(n, t);
+    int64_t c = 0;
+    for (; c < steps; ++c) {
+        if (F.is_zero(at(c, c))) {
+            bool found = false;
+            for (int64_t i = c + 1; i < n && !found; ++i)
+                if (!F.is_zero(at(i, c))) {
+                    rowswap(c, i);
+                    found = true;
+                }
+            for (int64_t j = c + 1; j < t && !found; ++j)
+                if (!F.is_zero(at(c, j))) {
+                    colswap(c, j);
+                    found = true;
+                }
+            for (int64_t i = c + 1; i < n && !found; ++i)
+                for (int64_t j = c + 1; j < t && !found; ++j)
+                    if (!F.is_zero(at(i, j))) {
+                        rowswap(c, i);
+                        colswap(c, j);
+                        found = true;
+                    }
+            if (!found) break;                    // the rest is zero
+        }
+        // The pivot's gcd with s only decreases (in the divisor order), so
+        // the loop ends.
+        for (;;) {
+            V a = at(c, c), g = F.gcd_s(a);
+            for (int64_t i = c + 1; i < n; ++i) {
+                const V b = at(i, c);
+                if (!F.is_zero(b) && !F.divides(g, b)) {
+                    rowadd(c, i, F.stab(a, b));
+                    a = at(c, c);
+                    g = F.gcd_s(a);
+                }
+            }
+            bool col_changed = false;
+            for (int64_t j = c + 1; j < t; ++j) {
+                const V b = at(c, j);
+                if (!F.is_zero(b) && !F.divides(g, b)) {
+                    coladd(c, j, F.stab(a, b));
+                    a = at(c, c);
+                    g = F.gcd_s(a);
+                    col_changed = true;
+                }
+            }
+            if (!col_changed) break;
+        }
+        const V a = at(c, c), g = F.gcd_s(a);
+        // Column c below the pivot: row i += f_i row c, rows independent.
+        std::vector<int64_t> rows;
+        std::vector<V> fs;
+        for (int64_t i = c + 1; i < n; ++i)
+            if (!F.is_zero(at(i, c))) {
+                rows.push_back(i);
+                fs.push_back(F.neg(F.quot(at(i, c), a, g)));
+            }
+        par((int64_t)rows.size(), (double)(t - c), [&](int64_t k) {
+            const int64_t i = rows[(size_t)k];
+            const V &f = fs[(size_t)k];
+            for (int64_t j = c; j < t; ++j) at(i, j) = F.add(at(i, j), F.mul(f, at(c, j)));
+        });
+        for (size_t k = 0; k < rows.size(); ++k) out.ops.push_back({1, rows[k], c, fs[k]});
+        // Row c right of the pivot: column j += f_j column c; column c is zero
+        // off the pivot, so in W only entry (c, j) changes.
+        for (int64_t j = c + 1; j < t; ++j) {
+            if (F.is_zero(at(c, j))) continue;
+            const V f = F.neg(F.quot(at(c, j), a, g));
+            at(c, j) = F.zero();
+            for (int64_t i = 0; i < t; ++i) Rat(i, j) = F.add(Rat(i, j), F.mul(f, Rat(i, c)));
+        }
+        // The pivot a = g u (u a unit): column c times u^-1 makes it g.
+        const V ui = F.unit_inv(a, g);
+        for (int64_t i = 0; i < t; ++i) Rat(i, c) = F.mul(Rat(i, c), ui);
+        at(c, c) = F.from(F.big(g));
+    }
+    out.rank = c;
+    out.d.assign((size_t)t, F.s);
+    for (int64_t j = 0; j < c; ++j) out.d[(size_t)j] = F.gcd_s(at(j, j));
+    // Divisibility order among the nonzero entries (the zeros, s, are last
+    // and every d_j divides s).
+    for (int64_t i = 0; i < c; ++i)
+        for (int64_t j = i + 1; j < c; ++j) {
+            const V di = out.d[(size_t)i], dj = out.d[(size_t)j];
+            if (F.divides(di, dj)) continue;
+            V h, x, y;
+            F.xgcd(di, dj, h, x, y);
+            const V l = F.mulexact(F.divexact(di, h), dj);   // lcm, a divisor of s
+            // row i += row j: (d_i, d_j / 0, d_j)
+            out.ops.push_back({1, i, j, F.one()});
+            // columns (i, j) <- (i, j) [[x, -d_j/h], [y, d_i/h]]: row i -> (h, 0),
+            // row j -> (y d_j, l)
+            const V a11 = x, a12 = F.neg(F.from(F.big(F.divexact(dj, h)))), a21 = y,
+                    a22 = F.from(F.big(F.divexact(di, h)));
+            for (int64_t k = 0; k < t; ++k) {
+                const V ci = Rat(k, i), cj = Rat(k, j);
+                Rat(k, i) = F.add(F.mul(ci, a11), F.mul(cj, a21));
+                Rat(k, j) = F.add(F.mul(ci, a12), F.mul(cj, a22));
+            }
+            // row j -= (y d_j / h) row i
+            const V f = F.neg(F.mul(y, F.from(F.big(F.divexact(dj, h)))));
+            out.ops.push_back({1, j, i, f});
+            out.d[(size_t)i] = h;
+            out.d[(size_t)j] = l;
+        }
+    return out;
+}
+
+// Rows 0..r-1 of E (r x n, row-major): the unit rows multiplied on the right
+// by the recorded operations, last to first.
+template <class Ring>
+std::vector<typename Ring::V> left_rows(const Ring &F, const SnfT<Ring> &S, int64_t n, int64_t r,
+                                        const ParFor &par = seq_for) {
+    using V = typename Ring::V;
+    std::vector<V> v((size_t)(r * n), F.zero());
+    par(r, (double)S.ops.size(), [&](int64_t k) {
+        V *row = v.data() + (size_t)(k * n);
+        row[k] = F.one();
+        for (size_t q = S.ops.size(); q-- > 0;) {
+            const RowOp<V> &o = S.ops[q];
+            if (o.kind == 0) {
+                std::swap(row[o.a], row[o.b]);
+            } else if (!F.is_zero(row[o.a])) {      // E_op = I + x e_a e_b^T
+                row[o.b] = F.add(row[o.b], F.mul(o.x, row[o.a]));
+            }
+        }
+    });
+    return v;
+}
+
+// Rem(s_n x, s_n) for x = A^-1 j known p-adically: dig[0..L) are the top L
+// of K digits (dig[L-1] the highest), PL = p^L, negpK = -p^K mod s_n.  With
+// Y = s_n x an integer, |Y| < p^K / 2^22, s_n X_K = Y + c p^K for
+// c = round(s_n X_K / p^K), hence Y = -c p^K (mod s_n); c comes from the top
+// L digits when p^L > 2^24 s_n.  False when the rounding is not within 2^-21
+// of an integer (then s_n x is not an integer).
+inline bool padic_top_mod(const uint32_t *dig, int L, int64_t stride, uint32_t p, const BigInt &sn,
+                          const BigInt &PL, const BigInt &negpK, const ModReducer &red, BigInt &out) {
+    BigInt F(0);
+    for (int l = L - 1; l >= 0; --l) F = F.mul_small(p) + BigInt((int64_t)dig[(size_t)l * stride]);
+    const BigInt N = sn * F;
+    const BigInt c = (N.shl(1) + PL) / PL.shl(1);
+    const BigInt r = N - c * PL;
+    if (BigInt::cmp(BigInt::abs(r).shl(21), PL) >= 0) return false;
+    out = red.reduce(negpK * c);
+    return true;
+}
+
+}  // namespace msg
+}  // namespace rns

@@ -45,12 +45,14 @@
 //     |det A / s| <= H / s for Hadamard's bound H, so enough primes make the
 //     check exact.  A failed check restarts with new random J and R.
 #include "bigint.hpp"
+#include "massager_host.hpp"
 #include "smith_internal.hpp"
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <ctime>
 #include <functional>
 #include <memory>
@@ -63,6 +65,11 @@ using namespace rns;
 struct rns_smith_result {
     std::vector<std::vector<uint64_t>> s;
     rns_smith_stats st{};
+    // The Smith massager, when computed: row i of U and columns j of M and T,
+    // each n entries of wU[i] (wM[j], wT[j]) little-endian words.
+    bool massager = false;
+    std::vector<std::vector<uint64_t>> U, M, T;
+    std::vector<int> wU, wM, wT;
 };
 
 namespace {
@@ -1315,6 +1322,386 @@ struct Driver {
         return RNS_ERETRY;
     }
 
+    // ------------------------------------------------------- Smith massager --
+    // Phase 2 of Section 2.2 with the massaged matrix B of Eq. (1), in batches
+    // of index-(m, r) Smith massagers (Definition 2).  With the batches found
+    // so far, (U_b, M_b) for b = 1..k (oldest first) and the modulus s (the
+    // smallest invariant found, a multiple of every invariant still to come),
+    // the first block row of B^-1 applied to [j; 0; 0] is, modulo integers,
+    // pi(A^-1 j) with pi = (I + M_k U_k) ... (I + M_1 U_1) (block inverse of
+    // Eq. (1)); s pi(A^-1 J) is integral, and P_1 = Rem(s pi(A^-1 J), s) is the
+    // batch's projection.  A^-1 J is lifted p-adically on the GPU (the
+    // resident C = A^-1 mod p), Rem(s_n A^-1 J, s_n) follows from the top
+    // digits, the earlier batches' factors are applied modulo s_n and the
+    // result divided by s_n / s.  The Smith form of P_1 over Z/sZ with its
+    // transforms gives the batch: invariants s / d_j, M_j and U_j with
+    // -U P_1 R = [D 0] (massager_host.hpp).  The next batch's T block against
+    // the earlier ones is -U_new M_old (mod the older invariants); within a
+    // batch T is I.  Batches grow with how far s fell (Section 3.2), and once
+    // s fits a machine word the next batch takes every remaining invariant.
+    struct MBatch {
+        BigInt s;                       // the batch's modulus
+        std::vector<BigInt> S;          // its invariants, ascending
+        std::vector<BigInt> M;          // [r][n]: column j of M, entries mod S[j]
+        std::vector<BigInt> U;          // [r][n]: row j of U, entries mod s
+    };
+
+    // Host threads in contiguous blocks once count x work (ring operations)
+    // repays starting them.
+    static msg::ParFor host_par() {
+        return [](int64_t cnt, double work, const std::function<void(int64_t)> &f) {
+            if (cnt < 2 || (double)cnt * work < 32768.0) {
+                for (int64_t i = 0; i < cnt; ++i) f(i);
+                return;
+            }
+            const int nb = (int)std::min<int64_t>(cnt, 64);
+            parallel_for(nb, [&](int b) {
+                for (int64_t i = cnt * b / nb; i < cnt * (b + 1) / nb; ++i) f(i);
+            });
+        };
+    }
+
+    // The top L of K p-adic digits of A^-1 J for the t columns of J ([t][ldl]
+    // int64, host) into dig ([L][t][ldl]; l = 0 is the digit of step K - L),
+    // lifting at most kLiftMaxCols columns at a time on the GPU.
+    int lift_top(int pidx, const std::vector<int64_t> &J, int64_t t, int64_t K, int L,
+                 std::vector<uint32_t> &dig) {
+        const uint32_t p = aux->primes[pidx];
+        const int64_t tmax = kLiftMaxCols;
+        dig.assign((size_t)L * t * ldl, 0u);
+        DRV_ST(dXh.alloc((size_t)K * tmax * ldl));
+        DRV_ST(dR0.alloc((size_t)tmax * ldl));
+        DRV_ST(dR1.alloc((size_t)tmax * ldl));
+        DRV_ST(dRm0.alloc((size_t)tmax * ldl));
+        DRV_ST(dRm1.alloc((size_t)tmax * ldl));
+        DRV_ST(derr.alloc(1));
+        DRV_ST(dstep.alloc(1));
+        LiftBufs lb{dR0.p, dR1.p, dRm0.p, dRm1.p, dXh.p, derr.p, dstep.p};
+        if (mfma_lift()) {
+            DRV_ST(dCt.alloc(lift_tile_c_bytes(n)));
+            launch_lift_tile_c(dC.p, n, ldl, p, dCt.p, stream);
+            DRV_HIP(hipGetLastError());
+            lb.Ct = dCt.p;
+            if (a_bytes == 2) {
+                DRV_ST(dAt.alloc(lift_tile_a_bytes(n)));
+                launch_lift_tile_a(dA16.p, n, ldl, dAt.p, stream);
+                DRV_HIP(hipGetLastError());
+                DRV_ST(dXd.alloc(lift_frag_bytes(n)));
+                DRV_ST(dRmd.alloc(lift_frag_bytes(n)));
+                lb.At = dAt.p;
+                lb.Xd = dXd.p;
+                lb.Rmd = dRmd.p;
+            }
+        }
+        const void *Adev = a_bytes == 2 ? (const void *)dA16.p : (const void *)dA32.p;
+        std::vector<uint32_t> Jm, top;
+        for (int64_t c0 = 0; c0 < t; c0 += tmax) {
+            const int tc = (int)std::min<int64_t>(tmax, t - c0);
+            const size_t cnt = (size_t)tc * ldl;
+            Jm.assign(cnt, 0u);
+            for (size_t e = 0; e < cnt; ++e) {
+                const int64_t v = J[(size_t)c0 * ldl + e] % (int64_t)p;
+                Jm[e] = (uint32_t)(v < 0 ? v + (int64_t)p : v);
+            }
+            DRV_HIP(hipMemcpyAsync(dR0.p, J.data() + (size_t)c0 * ldl, sizeof(int64_t) * cnt, hipMemcpyHostToDevice,
+                                   stream));
+            DRV_HIP(hipMemcpyAsync(dRm0.p, Jm.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice, stream));
+            DRV_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), stream));
+            DRV_HIP(hipMemsetAsync(dstep.p, 0, sizeof(int64_t), stream));
+            if (lb.Rmd) {
+                launch_lift_frag(dRm0.p, n, ldl, tc, p, dRmd.p, stream);   // the first step's Rm
+                DRV_HIP(hipGetLastError());
+            }
+            launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, tc, p, lb, (int)K, stream);
+            DRV_HIP(hipGetLastError());
+            int32_t err = 0;
+            top.resize((size_t)L * cnt);
+            DRV_HIP(hipMemcpyAsync(top.data(), dXh.p + (size_t)(K - L) * cnt, sizeof(uint32_t) * top.size(),
+                                   hipMemcpyDeviceToHost, stream));
+            DRV_HIP(hipMemcpyAsync(&err, derr.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+            if (err) return RNS_EDEVICE;                 // an inexact division: C is not A^-1 mod p
+            for (int l = 0; l < L; ++l)
+                std::memcpy(dig.data() + ((size_t)l * t + c0) * ldl, top.data() + (size_t)l * cnt,
+                            sizeof(uint32_t) * cnt);
+            st.lift_steps += (int)K;
+        }
+        return RNS_OK;
+    }
+
+    // The batch's projection P_1 = Rem(s pi(A^-1 J), s) (n x t, row-major)
+    // for a random J with entries in [-128, 128].  RNS_EBOUND when s_n A^-1 J
+    // is not integral (s_n misses a factor) or the projected entries are not
+    // multiples of s_n / s (an earlier batch was not maximal).
+    int projection(int pidx, const BigInt &sn, const BigInt &s, const std::vector<MBatch> &B, int64_t t,
+                   SplitMix &rng, std::vector<BigInt> &P1) {
+        const uint32_t p = aux->primes[pidx];
+        const double lp = std::log2((double)p);
+        // |s_n A^-1 J| <= |adj(A) J| <= n 2^7 H: K digits leave a 2^-22 margin,
+        // L top digits resolve s_n X_K / p^K to within 2^-24.
+        const int64_t K = (int64_t)std::ceil((abits + std::log2((double)n) + 7.0 + 24.0) / lp) + 1;
+        const int L = (int)std::min<int64_t>(K, (int64_t)std::ceil(((double)sn.bit_length() + 26.0) / lp) + 1);
+        std::vector<int64_t> J((size_t)t * ldl, 0);
+        for (int64_t c = 0; c < t; ++c)
+            for (int64_t r = 0; r < n; ++r) J[(size_t)c * ldl + r] = (int64_t)(rng.next() % 257) - 128;
+        std::vector<uint32_t> dig;
+        DRV_ST(lift_top(pidx, J, t, K, L, dig));
+        BigInt PL(1), pK(1);
+        for (int l = 0; l < L; ++l) PL = PL.mul_small(p);
+        for (int64_t k = 0; k < K; ++k) pK = pK.mul_small(p);
+        const BigInt negpK = mod(-pK, sn);
+        const ModReducer red(sn);
+        const msg::ParFor par = host_par();
+        const double limbs = (double)sn.mag.size() + 1.0;
+        std::vector<BigInt> Y((size_t)n * t);
+        std::atomic<bool> ok{true};
+        par(n * t, 8.0 * limbs * limbs, [&](int64_t e) {
+            const int64_t i = e / t, c = e % t;
+            if (!msg::padic_top_mod(dig.data() + (size_t)c * ldl + i, L, t * ldl, p, sn, PL, negpK, red,
+                                    Y[(size_t)e]))
+                ok = false;
+        });
+        if (!ok) return RNS_EBOUND;
+        // Earlier batches, oldest first: Y <- Y + M_b (U_b Y) (mod s_n).
+        for (const MBatch &b : B) {
+            const int64_t r = (int64_t)b.S.size();
+            std::vector<BigInt> Z((size_t)r * t);
+            par(r * t, (double)n * limbs * limbs, [&](int64_t e) {
+                const int64_t k = e / t, c = e % t;
+                BigInt acc(0);
+                for (int64_t i = 0; i < n; ++i) {
+                    const BigInt &u = b.U[(size_t)k * n + i];
+                    if (!u.is_zero()) acc = acc + u * Y[(size_t)i * t + c];
+                }
+                Z[(size_t)e] = mod(acc, sn);
+            });
+            par(n, (double)r * t * limbs * limbs, [&](int64_t i) {
+                for (int64_t c = 0; c < t; ++c) {
+                    BigInt acc = Y[(size_t)i * t + c];
+                    for (int64_t k = 0; k < r; ++k) {
+                        const BigInt &mv = b.M[(size_t)k * n + i];
+                        if (!mv.is_zero()) acc = acc + mv * Z[(size_t)k * t + c];
+                    }
+                    Y[(size_t)i * t + c] = mod(acc, sn);
+                }
+            });
+        }
+        const BigInt q = sn / s;
+        P1.assign((size_t)n * t, BigInt(0));
+        par(n * t, 4.0 * limbs * limbs, [&](int64_t e) {
+            BigInt qq, rr;
+            BigInt::divmod_trunc(Y[(size_t)e], q, qq, rr);
+            if (!rr.is_zero()) ok = false;
+            P1[(size_t)e] = std::move(qq);
+        });
+        if (!ok) return RNS_EBOUND;
+        st.columns += (int)t;
+        return RNS_OK;
+    }
+
+    // One batch from the Smith form of P_1 over Z/sZ: the largest orders
+    // s / d_j (all of them when `fin` or when at most t - extra are above 1,
+    // which sets *done), with their M and U.
+    template <class Ring>
+    void batch_from(const Ring &F, const std::vector<BigInt> &P1, int64_t t, const BigInt &s, int64_t extra,
+                    bool fin, MBatch &b, bool *done) {
+        using V = typename Ring::V;
+        const msg::ParFor par = host_par();
+        std::vector<V> W(P1.size());
+        for (size_t e = 0; e < P1.size(); ++e) W[e] = F.from(P1[e]);
+        const msg::SnfT<Ring> S = msg::snf_transform(F, W, n, t, par);
+        int64_t nontriv = 0;
+        while (nontriv < t && !(F.big(S.d[(size_t)nontriv]) == s)) ++nontriv;
+        *done = fin || nontriv <= t - extra;
+        const int64_t take = *done ? nontriv : t - extra;
+        const std::vector<V> E = msg::left_rows(F, S, n, take, par);
+        b.s = s;
+        b.S.assign((size_t)take, BigInt(0));
+        b.M.assign((size_t)(take * n), BigInt(0));
+        b.U.assign((size_t)(take * n), BigInt(0));
+        for (int64_t j = 0; j < take; ++j) b.S[(size_t)(take - 1 - j)] = s / F.big(S.d[(size_t)j]);
+        par(n, (double)take * t, [&](int64_t i) {
+            for (int64_t j = 0; j < take; ++j) {
+                V acc = F.zero();
+                for (int64_t k = 0; k < t; ++k)
+                    acc = F.add(acc, F.mul(W[(size_t)(i * t + k)], S.R[(size_t)(k * t + j)]));
+                // (P_1 R)_j = d_j L_j (mod s): the column of L, reduced mod s / d_j
+                const int64_t a = take - 1 - j;
+                const BigInt d = F.big(S.d[(size_t)j]);
+                b.M[(size_t)(a * n + i)] = mod(F.big(acc) / d, b.S[(size_t)a]);
+                b.U[(size_t)(a * n + i)] = F.big(F.neg(E[(size_t)(j * n + i)]));
+            }
+        });
+    }
+
+    int massager_phase2(int pidx, const BigInt &sn, SplitMix &rng, std::vector<MBatch> &B) {
+        constexpr int64_t kExtra = 4;                    // projection columns beyond the batch
+        B.clear();
+        int64_t m = 0, r = ctx->massager_r0;
+        BigInt s = sn;
+        double pbits = 0;                                // log2 of the product found, from below
+        for (;;) {
+            const bool fin = s.bit_length() <= 62;
+            const int64_t room = n - m;
+            // Every invariant still to come is >= 2 and their product is at
+            // most H / (product found).
+            const int64_t more = (int64_t)std::max(0.0, std::floor(abits - pbits)) + 1;
+            int64_t t = std::min(room, more) + kExtra;
+            if (!fin) t = std::min(t, r + kExtra);
+            std::vector<BigInt> P1;
+            DRV_ST(projection(pidx, sn, s, B, t, rng, P1));
+            MBatch b;
+            bool done = false;
+            if (fin) batch_from(msg::Ring64(s.to_u64_mag()), P1, t, s, kExtra, true, b, &done);
+            else batch_from(msg::RingBig(s), P1, t, s, kExtra, false, b, &done);
+            const int64_t take = (int64_t)b.S.size();
+            for (const BigInt &o : b.S) pbits += (double)o.bit_length() - 1.0;
+            m += take;
+            B.push_back(std::move(b));
+            st.batches += 1;
+            if (done || m >= n || take == 0) return RNS_OK;
+            const size_t prev_bits = s.bit_length();
+            s = B.back().S.front();                      // the smallest invariant just found
+            const double shrink = (double)prev_bits / (double)std::max<size_t>(1, s.bit_length());
+            r = std::min<int64_t>(n - m, (int64_t)std::ceil(std::max(2.0, shrink) * (double)std::max(r, take)));
+        }
+    }
+
+    // Assembles S, U, M, T (positions: the trivial invariants first, then the
+    // batches newest first, each ascending).
+    void massager_output(const std::vector<MBatch> &B, rns_smith_result *res) {
+        int64_t m = 0;
+        for (const MBatch &b : B) m += (int64_t)b.S.size();
+        struct Pos {
+            int b;                                       // batch, -1 for s_i = 1
+            int64_t a;                                   // index in the batch
+        };
+        std::vector<Pos> pos((size_t)n, Pos{-1, 0});
+        int64_t q = n - m;
+        for (int bi = (int)B.size() - 1; bi >= 0; --bi)
+            for (int64_t a = 0; a < (int64_t)B[(size_t)bi].S.size(); ++a) pos[(size_t)q++] = Pos{bi, a};
+        auto words = [](const BigInt &x) { return (int)std::max<size_t>(1, x.mag_words().size()); };
+        auto put = [](std::vector<uint64_t> &dst, int64_t k, int W, const BigInt &x) {
+            const std::vector<uint64_t> w = x.mag_words();
+            for (size_t i = 0; i < w.size() && (int)i < W; ++i) dst[(size_t)k * W + i] = w[i];
+        };
+        res->massager = true;
+        res->s.assign((size_t)n, BigInt(1).mag_words());
+        res->U.assign((size_t)n, {});
+        res->M.assign((size_t)n, {});
+        res->T.assign((size_t)n, {});
+        res->wU.assign((size_t)n, 1);
+        res->wM.assign((size_t)n, 1);
+        res->wT.assign((size_t)n, 1);
+        const msg::ParFor par = host_par();
+        par(n, (double)n * n, [&](int64_t j) {
+            const Pos pj = pos[(size_t)j];
+            if (pj.b < 0) {                              // s_j = 1: U row 0, M column 0, T column e_j
+                res->U[(size_t)j].assign((size_t)n, 0);
+                res->M[(size_t)j].assign((size_t)n, 0);
+                res->T[(size_t)j].assign((size_t)n, 0);
+                res->T[(size_t)j][(size_t)j] = 1;
+                return;
+            }
+            const MBatch &b = B[(size_t)pj.b];
+            const BigInt &sj = b.S[(size_t)pj.a];
+            res->s[(size_t)j] = sj.mag_words();
+            const int wu = words(b.s), wm = words(sj);
+            res->wU[(size_t)j] = wu;
+            res->wM[(size_t)j] = wm;
+            res->wT[(size_t)j] = wm;
+            res->U[(size_t)j].assign((size_t)(n * wu), 0);
+            res->M[(size_t)j].assign((size_t)(n * wm), 0);
+            res->T[(size_t)j].assign((size_t)(n * wm), 0);
+            for (int64_t i = 0; i < n; ++i) {
+                put(res->U[(size_t)j], i, wu, b.U[(size_t)(pj.a * n + i)]);
+                put(res->M[(size_t)j], i, wm, b.M[(size_t)(pj.a * n + i)]);
+            }
+            put(res->T[(size_t)j], j, wm, BigInt(1));
+            // Rows of newer batches: T_ij = -U_i M_j (mod s_j).
+            for (int64_t i = 0; i < j; ++i) {
+                const Pos pi = pos[(size_t)i];
+                if (pi.b < 0 || pi.b <= pj.b) continue;
+                const MBatch &bn = B[(size_t)pi.b];
+                BigInt acc(0);
+                for (int64_t k = 0; k < n; ++k) {
+                    const BigInt &u = bn.U[(size_t)(pi.a * n + k)];
+                    if (!u.is_zero()) acc = acc + u * b.M[(size_t)(pj.a * n + k)];
+                }
+                put(res->T[(size_t)j], i, wm, mod(-acc, sj));
+            }
+        });
+    }
+
+    int run_massager(rns_smith_result *res) {
+        const double t0 = now_s();
+        st.path = 2;
+        DRV_ST(upload_a32());
+        SplitMix rng{seed ^ 0x6A09E667F3BCC909ull};
+        int pidx = 0;
+        uint32_t detp = 0;
+        double tl = now_s();
+        DRV_ST(lift_prime(&pidx, &detp));
+        st.t_lif += now_s() - tl;
+        for (int attempt = 0; attempt <= kMaxRestarts + 3; ++attempt) {
+            if (attempt) st.restarts += 1;
+            // Phase 1: s_n (Monte Carlo; a proper divisor shows up in Phase 2).
+            tl = now_s();
+            BigInt sn;
+            std::vector<BigInt> Xp;
+            const int stl = lift_solve(pidx, 4, rng, sn, Xp);
+            st.t_lif += now_s() - tl;
+            if (stl == RNS_EBOUND) continue;
+            DRV_ST(stl);
+            const double ti = now_s();
+            std::vector<MBatch> B;
+            st.batches = 0;
+            st.columns = 0;
+            const int sp = sn.is_one() ? RNS_OK : massager_phase2(pidx, sn, rng, B);
+            st.t_im += now_s() - ti;
+            if (sp == RNS_EBOUND) continue;
+            DRV_ST(sp);
+            // Phase 3: |det A| = prod s_i, exactly.
+            const double tu = now_s();
+            BigInt prod(1);
+            for (const MBatch &b : B)
+                for (const BigInt &o : b.S) prod = prod * o;
+            bool ok = false;
+            if (sn.is_one()) {
+                const BigInt one(1);
+                DRV_ST(lift_certify(pidx, detp, one, one, &ok));
+            } else {
+                DRV_ST(lift_certify(pidx, detp, sn, prod, &ok));
+            }
+            st.t_uc += now_s() - tu;
+            if (ok && ctx->force_cert_failures > 0) {   // test hook: pretend the check failed
+                ctx->force_cert_failures -= 1;
+                ok = false;
+            }
+            if (!ok) continue;
+            const double to = now_s();
+            massager_output(B, res);
+            st.t_im += now_s() - to;
+            st.cert_exact = 1;
+            st.lift_a_bytes = a_bytes;
+            st.lift_kernels = (mfma_lift() ? 1 : 0) | (mfma_lift() && a_bytes == 2 ? 2 : 0) | (a_bytes == 2 ? 8 : 0);
+            st.t_total = now_s() - t0;
+            res->st = st;
+            return RNS_OK;
+        }
+        return RNS_ERETRY;
+    }
+
+    int solve_massager(rns_smith_result *res) {
+        DRV_HIP(hipSetDevice(ctx->device));
+        DRV_ST(solve_stream(ctx, &stream));
+        DRV_ST(bounds());
+        if (!lifting_applies()) return RNS_ENOTSUP;
+        DRV_ST(dA.alloc((size_t)n * n));
+        DRV_HIP(hipMemcpyAsync(dA.p, A, sizeof(int64_t) * n * n, hipMemcpyHostToDevice, stream));
+        return run_massager(res);
+    }
+
     // Phase 1 alone: the largest invariant factor s_n (Monte Carlo: the lcm of
     // the denominators found divides s_n and equals it with high probability).
     int run_lif(rns_smith_result *res) {
@@ -1495,6 +1882,63 @@ extern "C" int rns_largest_invariant(rns_ctx *ctx, const int64_t *A_host, int64_
         return st;
     }
     *out = res;
+    return RNS_OK;
+}
+
+extern "C" int rns_smith_massager(rns_ctx *ctx, const int64_t *A_host, int64_t n, uint64_t seed,
+                                  rns_smith_result **out) {
+    if (!ctx || !out || n < 0 || (n > 0 && !A_host)) return RNS_EINVAL;
+    *out = nullptr;
+    for (int64_t e = 0; e < n * n; ++e)
+        if (A_host[e] == INT64_MIN) return RNS_EINVAL;
+    rns_smith_result *res = new (std::nothrow) rns_smith_result;
+    if (!res) return RNS_ENOMEM;
+    if (n == 0) {
+        res->massager = true;
+        *out = res;
+        return RNS_OK;
+    }
+    SolveScope scope(ctx);
+    Driver d;
+    d.ctx = ctx;
+    d.n = n;
+    d.A = A_host;
+    d.seed = seed;
+    int st = aux_ctx(ctx, &d.aux);
+    if (st == RNS_OK) {
+        TraceScope trace(ctx, d.aux);
+        st = d.solve_massager(res);
+        res->st.t_host_cpu = trace.cpu_s();
+    }
+    if (st != RNS_OK) {
+        delete res;
+        return st;
+    }
+    *out = res;
+    return RNS_OK;
+}
+
+extern "C" int rns_smith_massager_width(const rns_smith_result *r, int which, int64_t index) {
+    if (!r || !r->massager || index < 0 || index >= (int64_t)r->s.size()) return -RNS_EINVAL;
+    switch (which) {
+    case RNS_MASSAGER_U: return r->wU[(size_t)index];
+    case RNS_MASSAGER_M: return r->wM[(size_t)index];
+    case RNS_MASSAGER_T: return r->wT[(size_t)index];
+    default: return -RNS_EINVAL;
+    }
+}
+
+extern "C" int rns_smith_massager_vector(const rns_smith_result *r, int which, int64_t index, uint64_t *out,
+                                         int W) {
+    const int w = rns_smith_massager_width(r, which, index);
+    if (w < 0 || !out || W < 1) return RNS_EINVAL;
+    if (W < w) return RNS_EBOUND;
+    const std::vector<uint64_t> &src = which == RNS_MASSAGER_U ? r->U[(size_t)index]
+                                       : which == RNS_MASSAGER_M ? r->M[(size_t)index]
+                                                                 : r->T[(size_t)index];
+    const int64_t n = (int64_t)r->s.size();
+    for (int64_t k = 0; k < n; ++k)
+        for (int i = 0; i < W; ++i) out[(size_t)(k * W + i)] = i < w ? src[(size_t)(k * w + i)] : 0;
     return RNS_OK;
 }
 

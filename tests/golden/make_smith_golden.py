@@ -2,8 +2,11 @@
 take the p-adic lifting path, computed by the oracle only (Bareiss
 determinant and gcd elimination modulo it).  Each case names its generator
 in synth/ and its parameters; a planted case is also checked against the
-invariants it was built with.  Run from the repository root:
-    python tests/golden/make_smith_golden.py
+invariants it was built with.  With --vandermonde it writes
+tests/golden/smith_vandermonde.json instead: the Smith forms (and |det A|)
+of the Section 4.1 family A_ij = i^j mod n for n = 101 and 199, by the same
+oracle.  Run from the repository root:
+    python tests/golden/make_smith_golden.py [--vandermonde]
 """
 import json
 import os
@@ -56,5 +59,27 @@ def main():
                    "cases": out}, f, indent=1)
 
 
+def main_vandermonde():
+    out = []
+    for n in (101, 199):
+        t = time.time()
+        a = synth.vandermonde_mod(n)
+        s = osmith.smith_form(a)
+        det = abs(osmith.bareiss_det(a))
+        prod = 1
+        for v in s:
+            prod *= v
+        assert prod == det and osmith.is_divisor_chain(s), n
+        ones = sum(1 for v in s if v == 1)
+        out.append({"n": n, "ones": ones, "tail": [str(v) for v in s[ones:]], "det_abs": str(det)})
+        print("vandermonde", n, "ones", ones, "bits", s[-1].bit_length(), "%.1fs" % (time.time() - t), flush=True)
+    with open(os.path.join(ROOT, "tests", "golden", "smith_vandermonde.json"), "w") as f:
+        json.dump({"source": "oracle.smith.smith_form on synth.vandermonde_mod (tests/golden/make_smith_golden.py "
+                             "--vandermonde)", "cases": out}, f, indent=1)
+
+
 if __name__ == "__main__":
-    main()
+    if "--vandermonde" in sys.argv:
+        main_vandermonde()
+    else:
+        main()

@@ -1,0 +1,166 @@
+"""GPU Smith massager (rns_smith_massager): S against the oracle's Smith form
+and (U, M, T, S) through Section 4.2's checks (oracle/massager.py):
+divisibility, A M S^-1 and (T + U M) S^-1 integral, T unit upper triangular,
+|det A| = prod s_i, and Definition 1 with W = -T^-1 U.
+
+Inputs: the Section 4.1 family A_ij = i^j mod n (synth.vandermonde_mod) for
+the primes 17..53 (oracle computed here) and n = 101, 199 (stored oracle
+values, tests/golden/smith_vandermonde.json); several batches are forced by
+a first batch of one invariant (RNS_MASSAGER_R0=1); random matrices (one
+nontrivial invariant); a unimodular matrix; the edge cases n = 0, n < 16,
+singular input; a forced certificate failure (restart).
+"""
+import json
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import massager as om, smith as osm
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "smith_vandermonde.json")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_19254_amd as rg
+    return rg
+
+
+@pytest.fixture(scope="module")
+def ctx(rg):
+    c = rg.Context(device=0, L=24)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_small_batches(rg):
+    os.environ["RNS_MASSAGER_R0"] = "1"
+    try:
+        c = rg.Context(device=0, L=24)
+    finally:
+        del os.environ["RNS_MASSAGER_R0"]
+    yield c
+    c.close()
+
+
+def _check_massager(a, res, det_abs=None):
+    S = res.s
+    c = om.checks(a, res.U, res.M, res.T, S, det_abs=det_abs)
+    assert all(c.values()), c
+    W = om.definition1_W(res.U, res.T)
+    assert om.definition1(a, res.M, W, S)
+    # reduced entries: M and T columns mod s_j
+    n = len(S)
+    for j in range(n):
+        for i in range(n):
+            assert 0 <= res.M[i, j] < max(S[j], 1) or (S[j] == 1 and res.M[i, j] == 0)
+            if i != j:
+                assert 0 <= res.T[i, j] < max(S[j], 1) or (S[j] == 1 and res.T[i, j] == 0)
+
+
+@pytest.mark.parametrize("n", [17, 19, 23, 29, 31, 37, 41, 43, 47, 53])
+def test_vandermonde_family_matches_oracle(ctx, rg, n):
+    _say("massager vandermonde", n)
+    a = synth.vandermonde_mod(n)
+    res = rg.smith_massager(ctx, a, seed=n)
+    assert res.s == osm.smith_form(a)
+    assert res.stats["path"] == 2 and res.stats["cert_exact"] == 1
+    _check_massager(a, res)
+
+
+@pytest.mark.parametrize("n", [37, 43, 53, 61])
+def test_several_batches(ctx_small_batches, rg, n):
+    """A first batch of one invariant: the projection then runs through one
+    or more earlier batches (the B update of Definition 2)."""
+    _say("massager several batches", n)
+    a = synth.vandermonde_mod(n)
+    res = rg.smith_massager(ctx_small_batches, a, seed=3)
+    assert res.s == osm.smith_form(a)
+    assert res.stats["batches"] >= 3
+    _check_massager(a, res)
+
+
+def test_vandermonde_101_199_golden(ctx, rg):
+    with open(GOLDEN) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        n = case["n"]
+        _say("massager vandermonde golden", n)
+        a = synth.vandermonde_mod(n)
+        res = rg.smith_massager(ctx, a, seed=1)
+        want = [1] * case["ones"] + [int(v) for v in case["tail"]]
+        assert res.s == want
+        assert res.s[-1].bit_length() == int(case["tail"][-1]).bit_length()
+        _check_massager(a, res, det_abs=int(case["det_abs"]))
+
+
+@pytest.mark.parametrize("n,seed", [(20, 1), (64, 2), (100, 3)])
+def test_random_matrices(ctx, rg, n, seed):
+    _say("massager random", n, seed)
+    rng = np.random.default_rng(seed)
+    while True:
+        a = rng.integers(-99, 100, size=(n, n), dtype=np.int64)
+        if osm.bareiss_det(a.tolist()) != 0:
+            break
+    res = rg.smith_massager(ctx, a, seed=seed)
+    assert res.s == osm.smith_form(a.tolist())
+    _check_massager(a, res)
+
+
+def test_unimodular_matrix(ctx, rg):
+    _say("massager unimodular")
+    n = 24
+    rng = random.Random(5)
+    P = [[int(i == j) for j in range(n)] for i in range(n)]
+    for _ in range(2 * n):
+        i, j = rng.sample(range(n), 2)
+        f = rng.choice([-1, 1])
+        P[i] = [x + f * y for x, y in zip(P[i], P[j])]
+    a = np.array(P, dtype=np.int64)
+    assert abs(osm.bareiss_det(P)) == 1
+    res = rg.smith_massager(ctx, a, seed=0)
+    assert res.s == [1] * n
+    _check_massager(a, res)
+    assert all(res.U[i, j] == 0 and res.M[i, j] == 0 for i in range(n) for j in range(n))
+
+
+def test_seeds_agree_and_restart(ctx, rg):
+    _say("massager seeds and forced restart")
+    a = synth.vandermonde_mod(41)
+    want = osm.smith_form(a)
+    for seed in (1, 2, 3):
+        assert rg.smith_massager(ctx, a, seed=seed).s == want
+    ctx.force_cert_failures(1)
+    res = rg.smith_massager(ctx, a, seed=9)
+    assert res.stats["restarts"] >= 1
+    assert res.s == want
+    _check_massager(a, res)
+
+
+def test_edge_cases(ctx, rg):
+    _say("massager edge cases")
+    empty = rg.smith_massager(ctx, np.zeros((0, 0), dtype=np.int64))
+    assert empty.s == []
+    with pytest.raises(rg.RnsError) as e:
+        rg.smith_massager(ctx, synth.vandermonde_mod(13))
+    assert e.value.status == 8                       # RNS_ENOTSUP below n = 16
+    sing = synth.vandermonde_mod(29)
+    sing[5] = sing[3]
+    with pytest.raises(rg.RnsError) as e:
+        rg.smith_massager(ctx, sing)
+    assert e.value.status == 6                       # RNS_ESINGULAR
