@@ -676,14 +676,12 @@ def smith_massager(ctx: Context, a: np.ndarray, seed: int = 0) -> MassagerResult
     return MassagerResult(res.s, mats[0], mats[1], mats[2], res.stats)
 
 
-def words_to_uints(w: np.ndarray) -> list:
-    """Rows of little-endian 64-bit words as non-negative Python ints."""
-    out = []
-    for row in w:
-        u = 0
-        for k in range(row.shape[0] - 1, -1, -1):
-            u = (u << 64) | int(row[k])
-        out.append(u)
+def words_to_uints(w: np.ndarray) -> np.ndarray:
+    """Rows of little-endian 64-bit words as non-negative Python ints (an
+    object array)."""
+    out = w[:, -1].astype(object)
+    for k in range(w.shape[1] - 2, -1, -1):
+        out = (out << 64) | w[:, k].astype(object)
     return out
 
 

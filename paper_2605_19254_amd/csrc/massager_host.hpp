@@ -71,12 +71,27 @@ struct Ring64 {
         return (uint64_t)t0;
     }
     static uint64_t mulm(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+    double cost() const { return 1.0; }               // ring operations, relative to a word product
     // f with b - f a = 0 (mod s), where g = gcd(a, s) divides b: a = g a',
-    // b = g b', a' prime to s/g, f = b' a'^-1 mod s/g.
-    V quot(V b, V a, V g) const {
+    // b = g b', a' prime to s/g, f = b' a'^-1 mod s/g; quot_inv(a, g) is the
+    // part that depends on a alone.
+    V quot_inv(V a, V g) const {
         const uint64_t m = s / g;
-        return mulm((b / g) % m, inv((a / g) % m, m), m);
+        return inv((a / g) % m, m);
     }
+    V quot_by(V b, V g, V ainv) const {
+        const uint64_t m = s / g;
+        return mulm((b / g) % m, ainv, m);
+    }
+    V quot(V b, V a, V g) const { return quot_by(b, g, quot_inv(a, g)); }
+    // sum over l = 1..L of dig[(L - l) stride] B[l], mod s (digits < 2^32,
+    // L < 2^30: the 128-bit sum does not overflow).
+    V dot_digits(const std::vector<V> &B, const uint32_t *dig, int64_t stride, int L) const {
+        unsigned __int128 acc = 0;
+        for (int l = 1; l <= L; ++l) acc += (unsigned __int128)B[(size_t)l] * dig[(size_t)(L - l) * stride];
+        return (V)(acc % s);
+    }
+    V mul_u64(V a, uint64_t e) const { return mulm(a, e % s, s); }
     // x with gcd(a + x b, s) = gcd(a, b, s): with g that gcd, x is the
     // largest divisor of s/g prime to a/g (then every prime of s/g divides
     // exactly one of a/g and x b/g).
@@ -145,10 +160,25 @@ struct RingBig {
         BigInt::xgcd(mod(a, m), m, x, y);
         return mod(x, m);
     }
-    V quot(const V &b, const V &a, const V &g) const {
-        const BigInt m = s / g;
-        return mod((b / g) * inv(a / g, m), m);
+    double cost() const {
+        const double k = (double)s.mag.size();
+        return 4.0 + 3.0 * k * k;
     }
+    V quot_inv(const V &a, const V &g) const {
+        const BigInt m = s / g;
+        return inv(a / g, m);
+    }
+    V quot_by(const V &b, const V &g, const V &ainv) const {
+        const BigInt m = s / g;
+        return mod((b / g) * ainv, m);
+    }
+    V quot(const V &b, const V &a, const V &g) const { return quot_by(b, g, quot_inv(a, g)); }
+    V dot_digits(const std::vector<V> &B, const uint32_t *dig, int64_t stride, int L) const {
+        BigInt acc(0);
+        for (int l = 1; l <= L; ++l) acc = acc + B[(size_t)l].mul_small(dig[(size_t)(L - l) * stride]);
+        return red.reduce(acc);
+    }
+    V mul_u64(const V &a, uint64_t e) const { return red.reduce(a * BigInt::from_u64(e)); }
     V stab(const V &a, const V &b) const {
         const BigInt g = BigInt::gcd(BigInt::gcd(a, b), s);
         const BigInt N = s / g, ap = mod(a / g, N);
@@ -278,29 +308,38 @@ SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t
             }
             if (!col_changed) break;
         }
-        const V a = at(c, c), g = F.gcd_s(a);
+        const V a = at(c, c), g = F.gcd_s(a), ainv = F.quot_inv(a, g);
         // Column c below the pivot: row i += f_i row c, rows independent.
         std::vector<int64_t> rows;
-        std::vector<V> fs;
         for (int64_t i = c + 1; i < n; ++i)
-            if (!F.is_zero(at(i, c))) {
-                rows.push_back(i);
-                fs.push_back(F.neg(F.quot(at(i, c), a, g)));
-            }
-        par((int64_t)rows.size(), (double)(t - c), [&](int64_t k) {
+            if (!F.is_zero(at(i, c))) rows.push_back(i);
+        std::vector<V> fs(rows.size());
+        par((int64_t)rows.size(), F.cost(), [&](int64_t k) {
+            fs[(size_t)k] = F.neg(F.quot_by(at(rows[(size_t)k], c), g, ainv));
+        });
+        par((int64_t)rows.size(), (double)(t - c) * F.cost(), [&](int64_t k) {
             const int64_t i = rows[(size_t)k];
             const V &f = fs[(size_t)k];
             for (int64_t j = c; j < t; ++j) at(i, j) = F.add(at(i, j), F.mul(f, at(c, j)));
         });
         for (size_t k = 0; k < rows.size(); ++k) out.ops.push_back({1, rows[k], c, fs[k]});
         // Row c right of the pivot: column j += f_j column c; column c is zero
-        // off the pivot, so in W only entry (c, j) changes.
+        // off the pivot, so in W only entry (c, j) changes.  R's rows are
+        // independent.
+        std::vector<int64_t> cols;
+        std::vector<V> gs;
         for (int64_t j = c + 1; j < t; ++j) {
             if (F.is_zero(at(c, j))) continue;
-            const V f = F.neg(F.quot(at(c, j), a, g));
+            cols.push_back(j);
+            gs.push_back(F.neg(F.quot_by(at(c, j), g, ainv)));
             at(c, j) = F.zero();
-            for (int64_t i = 0; i < t; ++i) Rat(i, j) = F.add(Rat(i, j), F.mul(f, Rat(i, c)));
         }
+        if (!cols.empty())
+            par(t, (double)cols.size() * F.cost(), [&](int64_t i) {
+                const V rc = Rat(i, c);
+                if (F.is_zero(rc)) return;
+                for (size_t k = 0; k < cols.size(); ++k) Rat(i, cols[k]) = F.add(Rat(i, cols[k]), F.mul(gs[k], rc));
+            });
         // The pivot a = g u (u a unit): column c times u^-1 makes it g.
         const V ui = F.unit_inv(a, g);
         for (int64_t i = 0; i < t; ++i) Rat(i, c) = F.mul(Rat(i, c), ui);
@@ -345,7 +384,7 @@ std::vector<typename Ring::V> left_rows(const Ring &F, const SnfT<Ring> &S, int6
                                         const ParFor &par = seq_for) {
     using V = typename Ring::V;
     std::vector<V> v((size_t)(r * n), F.zero());
-    par(r, (double)S.ops.size(), [&](int64_t k) {
+    par(r, (double)S.ops.size() * F.cost(), [&](int64_t k) {
         V *row = v.data() + (size_t)(k * n);
         row[k] = F.one();
         for (size_t q = S.ops.size(); q-- > 0;) {
@@ -360,23 +399,49 @@ std::vector<typename Ring::V> left_rows(const Ring &F, const SnfT<Ring> &S, int6
     return v;
 }
 
-// Rem(s_n x, s_n) for x = A^-1 j known p-adically: dig[0..L) are the top L
-// of K digits (dig[L-1] the highest), PL = p^L, negpK = -p^K mod s_n.  With
-// Y = s_n x an integer, |Y| < p^K / 2^22, s_n X_K = Y + c p^K for
-// c = round(s_n X_K / p^K), hence Y = -c p^K (mod s_n); c comes from the top
-// L digits when p^L > 2^24 s_n.  False when the rounding is not within 2^-21
-// of an integer (then s_n x is not an integer).
-inline bool padic_top_mod(const uint32_t *dig, int L, int64_t stride, uint32_t p, const BigInt &sn,
-                          const BigInt &PL, const BigInt &negpK, const ModReducer &red, BigInt &out) {
-    BigInt F(0);
-    for (int l = L - 1; l >= 0; --l) F = F.mul_small(p) + BigInt((int64_t)dig[(size_t)l * stride]);
-    const BigInt N = sn * F;
-    const BigInt c = (N.shl(1) + PL) / PL.shl(1);
-    const BigInt r = N - c * PL;
-    if (BigInt::cmp(BigInt::abs(r).shl(21), PL) >= 0) return false;
-    out = red.reduce(negpK * c);
-    return true;
-}
+// Rem(s_n x, M') for x = A^-1 j known by the top L of its K p-adic digits,
+// where M' divides s_n (the ring's modulus).  With d_l the digit of step
+// K - l (l = 1..L) and s_n / p^l = a_l + f_l (a_l an integer, 0 <= f_l < 1):
+// s_n X_K / p^K = sum d_l a_l + sum d_l f_l + (the lower digits' share, below
+// s_n p^-L).  Y = s_n x is an integer with |Y| < p^K 2^-24 and
+// s_n X_K = Y + c p^K, so c = round(s_n X_K / p^K) = sum d_l a_l + e with
+// e = round(sum d_l f_l), and Y = -c p^K (mod s_n).  Hence
+//     Y mod M' = sum d_l B_l + e B_0 (mod M'),  B_l = -a_l p^K, B_0 = -p^K.
+// The f_l are kept as 64-bit fractions; eval fails when sum d_l f_l is not
+// within 2^-21 of an integer (then s_n x is not an integer).
+template <class Ring>
+struct PadicTable {
+    using V = typename Ring::V;
+    const Ring &F;
+    int L;
+    std::vector<V> B;                 // B[0] = B_0, B[l] = B_l
+    std::vector<uint64_t> frac;       // frac[l] = floor(f_l 2^64), l = 1..L
+    PadicTable(const Ring &ring, const BigInt &sn, uint32_t p, int64_t K, int Ltop) : F(ring), L(Ltop) {
+        BigInt pK(1);
+        for (int64_t k = 0; k < K; ++k) pK = pK.mul_small(p);
+        B.assign((size_t)L + 1, F.zero());
+        frac.assign((size_t)L + 1, 0);
+        B[0] = F.from(-pK);
+        BigInt pl(1);
+        for (int l = 1; l <= L; ++l) {
+            pl = pl.mul_small(p);
+            BigInt a, r;
+            BigInt::divmod_trunc(sn, pl, a, r);
+            B[(size_t)l] = F.from(-(a * pK));
+            frac[(size_t)l] = (r.shl(64) / pl).to_u64_mag();
+        }
+    }
+    bool eval(const uint32_t *dig, int64_t stride, V &out) const {
+        unsigned __int128 fs = 0;
+        for (int l = 1; l <= L; ++l) fs += (unsigned __int128)frac[(size_t)l] * dig[(size_t)(L - l) * stride];
+        const uint64_t e = (uint64_t)((fs + ((unsigned __int128)1 << 63)) >> 64);
+        const unsigned __int128 ee = (unsigned __int128)e << 64;
+        const unsigned __int128 dist = fs > ee ? fs - ee : ee - fs;
+        if (dist >= ((unsigned __int128)1 << 43)) return false;
+        out = F.add(F.dot_digits(B, dig, stride, L), F.mul_u64(B[0], e));
+        return true;
+    }
+};
 
 }  // namespace msg
 }  // namespace rns

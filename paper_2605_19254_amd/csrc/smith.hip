@@ -58,6 +58,7 @@
 #include <memory>
 #include <new>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 using namespace rns;
@@ -1362,82 +1363,187 @@ struct Driver {
     }
 
     // The top L of K p-adic digits of A^-1 J for the t columns of J ([t][ldl]
-    // int64, host) into dig ([L][t][ldl]; l = 0 is the digit of step K - L),
-    // lifting at most kLiftMaxCols columns at a time on the GPU.
+    // int64, host) into dig ([L][t][ldl]; l = 0 is the digit of step K - L).
+    // Runs of at most kLiftMaxCols columns are independent liftings: they go
+    // round-robin to kLiftLanes streams, each with its own buffers and its own
+    // captured graph of the K steps (one run fills only n / 16 work-groups),
+    // and copy their top digits into one device array.
+    static constexpr int kLiftLanes = 4;
+    struct LiftLane {
+        hipStream_t s = nullptr;
+        DevBuf<int64_t> R0, R1;
+        DevBuf<uint32_t> Rm0, Rm1, Xh;
+        DevBuf<int32_t> err;
+        DevBuf<int64_t> step;
+        DevBuf<char> Xd, Rmd;
+        StepGraph graph;
+        std::vector<uint32_t> Jm;
+    };
     int lift_top(int pidx, const std::vector<int64_t> &J, int64_t t, int64_t K, int L,
                  std::vector<uint32_t> &dig) {
         const uint32_t p = aux->primes[pidx];
         const int64_t tmax = kLiftMaxCols;
         dig.assign((size_t)L * t * ldl, 0u);
-        DRV_ST(dXh.alloc((size_t)K * tmax * ldl));
-        DRV_ST(dR0.alloc((size_t)tmax * ldl));
-        DRV_ST(dR1.alloc((size_t)tmax * ldl));
-        DRV_ST(dRm0.alloc((size_t)tmax * ldl));
-        DRV_ST(dRm1.alloc((size_t)tmax * ldl));
-        DRV_ST(derr.alloc(1));
-        DRV_ST(dstep.alloc(1));
-        LiftBufs lb{dR0.p, dR1.p, dRm0.p, dRm1.p, dXh.p, derr.p, dstep.p};
+        const char *Ct = nullptr, *At = nullptr;
         if (mfma_lift()) {
             DRV_ST(dCt.alloc(lift_tile_c_bytes(n)));
             launch_lift_tile_c(dC.p, n, ldl, p, dCt.p, stream);
             DRV_HIP(hipGetLastError());
-            lb.Ct = dCt.p;
+            Ct = dCt.p;
             if (a_bytes == 2) {
                 DRV_ST(dAt.alloc(lift_tile_a_bytes(n)));
                 launch_lift_tile_a(dA16.p, n, ldl, dAt.p, stream);
                 DRV_HIP(hipGetLastError());
-                DRV_ST(dXd.alloc(lift_frag_bytes(n)));
-                DRV_ST(dRmd.alloc(lift_frag_bytes(n)));
-                lb.At = dAt.p;
-                lb.Xd = dXd.p;
-                lb.Rmd = dRmd.p;
+                At = dAt.p;
             }
         }
+        DevBuf<uint32_t> dtop;
+        DRV_ST(dtop.alloc((size_t)L * t * ldl));
+        const int64_t runs = (t + tmax - 1) / tmax;
+        const int nl = (int)std::min<int64_t>(kLiftLanes, runs);
+        std::vector<LiftLane> lanes((size_t)nl);
+        hipEvent_t ready = nullptr;
+        DRV_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        DRV_HIP(hipEventRecord(ready, stream));
+        int status = RNS_OK;
+        auto fail = [&](int st_) {
+            if (status == RNS_OK) status = st_;
+        };
         const void *Adev = a_bytes == 2 ? (const void *)dA16.p : (const void *)dA32.p;
-        std::vector<uint32_t> Jm, top;
-        for (int64_t c0 = 0; c0 < t; c0 += tmax) {
+        std::vector<LiftBufs> lbs((size_t)nl, LiftBufs{});
+        for (int k = 0; k < nl && status == RNS_OK; ++k) {
+            LiftLane &ln = lanes[(size_t)k];
+            if (hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) != hipSuccess) {
+                fail(RNS_EDEVICE);
+                break;
+            }
+            if (hipStreamWaitEvent(ln.s, ready, 0) != hipSuccess) fail(RNS_EDEVICE);
+            int a = ln.Xh.alloc((size_t)K * tmax * ldl);
+            if (a == RNS_OK) a = ln.R0.alloc((size_t)tmax * ldl);
+            if (a == RNS_OK) a = ln.R1.alloc((size_t)tmax * ldl);
+            if (a == RNS_OK) a = ln.Rm0.alloc((size_t)tmax * ldl);
+            if (a == RNS_OK) a = ln.Rm1.alloc((size_t)tmax * ldl);
+            if (a == RNS_OK) a = ln.err.alloc(1);
+            if (a == RNS_OK) a = ln.step.alloc(1);
+            LiftBufs lb{ln.R0.p, ln.R1.p, ln.Rm0.p, ln.Rm1.p, ln.Xh.p, ln.err.p, ln.step.p};
+            lb.Ct = Ct;
+            if (a == RNS_OK && At) {
+                a = ln.Xd.alloc(lift_frag_bytes(n));
+                if (a == RNS_OK) a = ln.Rmd.alloc(lift_frag_bytes(n));
+                lb.At = At;
+                lb.Xd = ln.Xd.p;
+                lb.Rmd = ln.Rmd.p;
+            }
+            if (a != RNS_OK) fail(a);
+            if (hipMemsetAsync(ln.err.p, 0, sizeof(int32_t), ln.s) != hipSuccess) fail(RNS_EDEVICE);
+            lbs[(size_t)k] = lb;
+        }
+        for (int64_t run = 0; run < runs && status == RNS_OK; ++run) {
+            LiftLane &ln = lanes[(size_t)(run % nl)];
+            const LiftBufs &lb = lbs[(size_t)(run % nl)];
+            const int64_t c0 = run * tmax;
             const int tc = (int)std::min<int64_t>(tmax, t - c0);
             const size_t cnt = (size_t)tc * ldl;
-            Jm.assign(cnt, 0u);
+            // The lane's previous run must be done with R0 before it is
+            // overwritten: copies are ordered on the lane's stream, and the
+            // host buffer is one per lane, so wait for that stream first.
+            if (run >= nl && hipStreamSynchronize(ln.s) != hipSuccess) {
+                fail(RNS_EDEVICE);
+                break;
+            }
+            ln.Jm.assign(cnt, 0u);
             for (size_t e = 0; e < cnt; ++e) {
                 const int64_t v = J[(size_t)c0 * ldl + e] % (int64_t)p;
-                Jm[e] = (uint32_t)(v < 0 ? v + (int64_t)p : v);
+                ln.Jm[e] = (uint32_t)(v < 0 ? v + (int64_t)p : v);
             }
-            DRV_HIP(hipMemcpyAsync(dR0.p, J.data() + (size_t)c0 * ldl, sizeof(int64_t) * cnt, hipMemcpyHostToDevice,
-                                   stream));
-            DRV_HIP(hipMemcpyAsync(dRm0.p, Jm.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice, stream));
-            DRV_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), stream));
-            DRV_HIP(hipMemsetAsync(dstep.p, 0, sizeof(int64_t), stream));
-            if (lb.Rmd) {
-                launch_lift_frag(dRm0.p, n, ldl, tc, p, dRmd.p, stream);   // the first step's Rm
-                DRV_HIP(hipGetLastError());
+            bool ok = hipMemcpyAsync(ln.R0.p, J.data() + (size_t)c0 * ldl, sizeof(int64_t) * cnt,
+                                     hipMemcpyHostToDevice, ln.s) == hipSuccess;
+            ok = ok && hipMemcpyAsync(ln.Rm0.p, ln.Jm.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice,
+                                      ln.s) == hipSuccess;
+            ok = ok && hipMemsetAsync(ln.step.p, 0, sizeof(int64_t), ln.s) == hipSuccess;
+            if (!ok) {
+                fail(RNS_EDEVICE);
+                break;
             }
-            launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, tc, p, lb, (int)K, stream);
-            DRV_HIP(hipGetLastError());
-            int32_t err = 0;
-            top.resize((size_t)L * cnt);
-            DRV_HIP(hipMemcpyAsync(top.data(), dXh.p + (size_t)(K - L) * cnt, sizeof(uint32_t) * top.size(),
-                                   hipMemcpyDeviceToHost, stream));
-            DRV_HIP(hipMemcpyAsync(&err, derr.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-            DRV_ST(sync());
-            if (err) return RNS_EDEVICE;                 // an inexact division: C is not A^-1 mod p
-            for (int l = 0; l < L; ++l)
-                std::memcpy(dig.data() + ((size_t)l * t + c0) * ldl, top.data() + (size_t)l * cnt,
-                            sizeof(uint32_t) * cnt);
+            if (lb.Rmd) launch_lift_frag(ln.Rm0.p, n, ldl, tc, p, ln.Rmd.p, ln.s);   // the first step's Rm
+            if (tc == tmax && !ln.graph.tried && runs - run > nl) {
+                ln.graph.tried = true;
+                if (!tl_trace && hipStreamBeginCapture(ln.s, hipStreamCaptureModeRelaxed) == hipSuccess) {
+                    launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, (int)tmax, p, lb, (int)K, ln.s);
+                    hipGraph_t gr = nullptr;
+                    if (hipStreamEndCapture(ln.s, &gr) == hipSuccess && gr) {
+                        ln.graph.g = gr;
+                        if (hipGraphInstantiate(&ln.graph.exec, gr, nullptr, nullptr, 0) != hipSuccess)
+                            ln.graph.exec = nullptr;
+                    }
+                    (void)hipGetLastError();
+                }
+            }
+            if (tc == tmax && ln.graph.exec) {
+                if (hipGraphLaunch(ln.graph.exec, ln.s) != hipSuccess) fail(RNS_EDEVICE);
+            } else {
+                launch_lift_steps(dC.p, Adev, a_bytes, n, ldl, tc, p, lb, (int)K, ln.s);
+                if (hipGetLastError() != hipSuccess) fail(RNS_EDEVICE);
+            }
+            // top digits: L rows of tc x ldl words into dtop[l][c0 ..][.]
+            if (hipMemcpy2DAsync(dtop.p + (size_t)c0 * ldl, sizeof(uint32_t) * (size_t)t * ldl,
+                                 ln.Xh.p + (size_t)(K - L) * cnt, sizeof(uint32_t) * cnt, sizeof(uint32_t) * cnt,
+                                 (size_t)L, hipMemcpyDeviceToDevice, ln.s) != hipSuccess)
+                fail(RNS_EDEVICE);
             st.lift_steps += (int)K;
         }
+        int32_t anyerr = 0;
+        for (LiftLane &ln : lanes) {
+            if (!ln.s) continue;
+            int32_t e = 0;
+            if (hipMemcpyAsync(&e, ln.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, ln.s) != hipSuccess ||
+                hipStreamSynchronize(ln.s) != hipSuccess)
+                fail(RNS_EDEVICE);
+            anyerr |= e;
+        }
+        for (LiftLane &ln : lanes)
+            if (ln.s) (void)hipStreamDestroy(ln.s);
+        (void)hipEventDestroy(ready);
+        if (status != RNS_OK) return status;
+        if (anyerr) return RNS_EDEVICE;                  // an inexact division: C is not A^-1 mod p
+        DRV_HIP(hipMemcpyAsync(dig.data(), dtop.p, sizeof(uint32_t) * dig.size(), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
         return RNS_OK;
     }
 
+    // The largest divisor of y prime to s (repeated gcds, no factoring).
+    static BigInt coprime_part(BigInt y, const BigInt &s) {
+        for (;;) {
+            const BigInt g = BigInt::gcd(y, s);
+            if (g.is_one() || g.is_zero()) return y;
+            y = y / g;
+        }
+    }
+
     // The batch's projection P_1 = Rem(s pi(A^-1 J), s) (n x t, row-major)
-    // for a random J with entries in [-128, 128].  RNS_EBOUND when s_n A^-1 J
-    // is not integral (s_n misses a factor) or the projected entries are not
-    // multiples of s_n / s (an earlier batch was not maximal).
+    // for a random J with entries in [-128, 128].  With V = s_n pi(x) (an
+    // integer multiple of q = s_n / s) and P_1 = V / q mod s, only V modulo
+    // M' = s_n / u matters, u the largest divisor of s_n prime to s: with
+    // q = q_b u, (V mod M') / q_b = u (V / q) mod s.  So Y = s_n x and the
+    // earlier batches' factors are applied modulo M' (a machine word when the
+    // primes of s divide s_n only to small powers).  RNS_EBOUND when s_n A^-1 J
+    // is not integral (s_n misses a factor) or V is not a multiple of q (an
+    // earlier batch was not maximal).
     int projection(int pidx, const BigInt &sn, const BigInt &s, const std::vector<MBatch> &B, int64_t t,
                    SplitMix &rng, std::vector<BigInt> &P1) {
+        const BigInt u = coprime_part(sn, s);
+        const BigInt Mp = sn / u;
+        if (Mp.bit_length() <= 62) return projection_in(msg::Ring64(Mp.to_u64_mag()), sn, s, u, B, t, pidx, rng, P1);
+        return projection_in(msg::RingBig(Mp), sn, s, u, B, t, pidx, rng, P1);
+    }
+
+    template <class Ring>
+    int projection_in(const Ring &FM, const BigInt &sn, const BigInt &s, const BigInt &u,
+                      const std::vector<MBatch> &B, int64_t t, int pidx, SplitMix &rng, std::vector<BigInt> &P1) {
+        using V = typename Ring::V;
         const uint32_t p = aux->primes[pidx];
         const double lp = std::log2((double)p);
-        // |s_n A^-1 J| <= |adj(A) J| <= n 2^7 H: K digits leave a 2^-22 margin,
+        // |s_n A^-1 J| <= |adj(A) J| <= n 2^7 H: K digits leave a 2^-24 margin,
         // L top digits resolve s_n X_K / p^K to within 2^-24.
         const int64_t K = (int64_t)std::ceil((abits + std::log2((double)n) + 7.0 + 24.0) / lp) + 1;
         const int L = (int)std::min<int64_t>(K, (int64_t)std::ceil(((double)sn.bit_length() + 26.0) / lp) + 1);
@@ -1446,54 +1552,61 @@ struct Driver {
             for (int64_t r = 0; r < n; ++r) J[(size_t)c * ldl + r] = (int64_t)(rng.next() % 257) - 128;
         std::vector<uint32_t> dig;
         DRV_ST(lift_top(pidx, J, t, K, L, dig));
-        BigInt PL(1), pK(1);
-        for (int l = 0; l < L; ++l) PL = PL.mul_small(p);
-        for (int64_t k = 0; k < K; ++k) pK = pK.mul_small(p);
-        const BigInt negpK = mod(-pK, sn);
-        const ModReducer red(sn);
+        const msg::PadicTable<Ring> tab(FM, sn, p, K, L);
         const msg::ParFor par = host_par();
-        const double limbs = (double)sn.mag.size() + 1.0;
-        std::vector<BigInt> Y((size_t)n * t);
+        std::vector<V> Y((size_t)n * t);
         std::atomic<bool> ok{true};
-        par(n * t, 8.0 * limbs * limbs, [&](int64_t e) {
+        par(n * t, (double)L * FM.cost() / 4.0, [&](int64_t e) {
             const int64_t i = e / t, c = e % t;
-            if (!msg::padic_top_mod(dig.data() + (size_t)c * ldl + i, L, t * ldl, p, sn, PL, negpK, red,
-                                    Y[(size_t)e]))
-                ok = false;
+            if (!tab.eval(dig.data() + (size_t)c * ldl + i, t * ldl, Y[(size_t)e])) ok = false;
         });
         if (!ok) return RNS_EBOUND;
-        // Earlier batches, oldest first: Y <- Y + M_b (U_b Y) (mod s_n).
+        // Earlier batches, oldest first: Y <- Y + M_b (U_b Y) (mod M').
         for (const MBatch &b : B) {
             const int64_t r = (int64_t)b.S.size();
-            std::vector<BigInt> Z((size_t)r * t);
-            par(r * t, (double)n * limbs * limbs, [&](int64_t e) {
-                const int64_t k = e / t, c = e % t;
-                BigInt acc(0);
-                for (int64_t i = 0; i < n; ++i) {
-                    const BigInt &u = b.U[(size_t)k * n + i];
-                    if (!u.is_zero()) acc = acc + u * Y[(size_t)i * t + c];
-                }
-                Z[(size_t)e] = mod(acc, sn);
+            std::vector<V> Ub((size_t)(r * n)), Mb((size_t)(r * n));
+            par(r * n, FM.cost(), [&](int64_t e) {
+                Ub[(size_t)e] = FM.from(b.U[(size_t)e]);
+                Mb[(size_t)e] = FM.from(b.M[(size_t)e]);
             });
-            par(n, (double)r * t * limbs * limbs, [&](int64_t i) {
-                for (int64_t c = 0; c < t; ++c) {
-                    BigInt acc = Y[(size_t)i * t + c];
-                    for (int64_t k = 0; k < r; ++k) {
-                        const BigInt &mv = b.M[(size_t)k * n + i];
-                        if (!mv.is_zero()) acc = acc + mv * Z[(size_t)k * t + c];
-                    }
-                    Y[(size_t)i * t + c] = mod(acc, sn);
+            std::vector<V> Z((size_t)(r * t));
+            par(r * t, (double)n * FM.cost(), [&](int64_t e) {
+                const int64_t k = e / t, c = e % t;
+                V acc = FM.zero();
+                for (int64_t i = 0; i < n; ++i) {
+                    const V &uv = Ub[(size_t)(k * n + i)];
+                    if (!FM.is_zero(uv)) acc = FM.add(acc, FM.mul(uv, Y[(size_t)(i * t + c)]));
+                }
+                Z[(size_t)e] = acc;
+            });
+            par(n, (double)(r * t) * FM.cost(), [&](int64_t i) {
+                for (int64_t k = 0; k < r; ++k) {
+                    const V &mv = Mb[(size_t)(k * n + i)];
+                    if (FM.is_zero(mv)) continue;
+                    for (int64_t c = 0; c < t; ++c)
+                        Y[(size_t)(i * t + c)] = FM.add(Y[(size_t)(i * t + c)], FM.mul(mv, Z[(size_t)(k * t + c)]));
                 }
             });
         }
-        const BigInt q = sn / s;
+        const BigInt Mp = FM.big(FM.s), qb = Mp / s;
+        const BigInt uinv = msg::RingBig::inv(mod(u, s), s);
         P1.assign((size_t)n * t, BigInt(0));
-        par(n * t, 4.0 * limbs * limbs, [&](int64_t e) {
-            BigInt qq, rr;
-            BigInt::divmod_trunc(Y[(size_t)e], q, qq, rr);
-            if (!rr.is_zero()) ok = false;
-            P1[(size_t)e] = std::move(qq);
-        });
+        if constexpr (std::is_same<Ring, msg::Ring64>::value) {
+            const uint64_t q64 = qb.to_u64_mag(), s64 = s.to_u64_mag(), ui64 = uinv.to_u64_mag();
+            par(n * t, 2.0, [&](int64_t e) {
+                const uint64_t v = Y[(size_t)e];
+                if (v % q64) ok = false;
+                P1[(size_t)e] = BigInt::from_u64(msg::Ring64::mulm((v / q64) % s64, ui64, s64));
+            });
+        } else {
+            const double limbs = (double)Mp.mag.size() + 1.0;
+            par(n * t, 4.0 * limbs * limbs, [&](int64_t e) {
+                BigInt qq, rr;
+                BigInt::divmod_trunc(FM.big(Y[(size_t)e]), qb, qq, rr);
+                if (!rr.is_zero()) ok = false;
+                P1[(size_t)e] = mod(qq * uinv, s);
+            });
+        }
         if (!ok) return RNS_EBOUND;
         st.columns += (int)t;
         return RNS_OK;
@@ -1520,7 +1633,7 @@ struct Driver {
         b.M.assign((size_t)(take * n), BigInt(0));
         b.U.assign((size_t)(take * n), BigInt(0));
         for (int64_t j = 0; j < take; ++j) b.S[(size_t)(take - 1 - j)] = s / F.big(S.d[(size_t)j]);
-        par(n, (double)take * t, [&](int64_t i) {
+        par(n, (double)take * t * F.cost(), [&](int64_t i) {
             for (int64_t j = 0; j < take; ++j) {
                 V acc = F.zero();
                 for (int64_t k = 0; k < t; ++k)
@@ -1535,7 +1648,7 @@ struct Driver {
     }
 
     int massager_phase2(int pidx, const BigInt &sn, SplitMix &rng, std::vector<MBatch> &B) {
-        constexpr int64_t kExtra = 4;                    // projection columns beyond the batch
+        constexpr int64_t kExtra = 8;                    // projection columns beyond the batch
         B.clear();
         int64_t m = 0, r = ctx->massager_r0;
         BigInt s = sn;

@@ -210,46 +210,50 @@ int main() {
             check_one(RingBig(s), Pb, n, t, "ringbig multiword");
         }
     }
-    // p-adic top digits: x = N / s_n with |N| small; digits of x mod p^K.
+    // p-adic top digits: x = N / s_n with |N| small; digits of x mod p^K; the
+    // table gives N mod s_n (big ring) and N mod M' for a word-size divisor
+    // M' of s_n (word ring), and refuses x = N / (3 s_n).
     {
         const uint32_t p = 67108859u;
         for (int it = 0; it < 40; ++it) {
-            BigInt sn(1);
+            const uint64_t Mw = (g() % ((1ull << 62) - 3)) + 2;       // word-size factor of s_n
+            BigInt sn = BigInt::from_u64(Mw);
             for (int w = 0; w < 1 + (int)(g() % 6); ++w) sn = sn.shl(32) + BigInt((int64_t)(g() & 0xFFFFFFFF));
-            if (BigInt::gcd(sn, BigInt((int64_t)p)) != BigInt(1)) continue;
+            sn = sn - mod(sn, BigInt::from_u64(Mw));                  // a multiple of Mw
+            if (sn.is_zero() || BigInt::gcd(sn, BigInt((int64_t)p)) != BigInt(1)) continue;
             const int K = 30;
             BigInt pK(1);
             for (int k = 0; k < K; ++k) pK = pK.mul_small(p);
             BigInt N(0);
             for (int w = 0; w < 4; ++w) N = N.shl(32) + BigInt((int64_t)(g() & 0xFFFFFFFF));
             if (g() & 1) N = -N;
-            // x mod p^K = N * sn^-1 mod p^K
-            BigInt xi, yi;
-            BigInt::xgcd(mod(sn, pK), pK, xi, yi);
-            BigInt xK = mod(N * xi, pK);
-            std::vector<uint32_t> dig(K);
-            for (int k = 0; k < K; ++k) {
-                dig[k] = xK.mod_small(p);
-                xK = xK / BigInt((int64_t)p);
-            }
+            auto digits = [&](const BigInt &den, std::vector<uint32_t> &dig) {
+                BigInt xi, yi;
+                BigInt::xgcd(mod(den, pK), pK, xi, yi);
+                BigInt xK = mod(N * xi, pK);
+                dig.assign(K, 0u);
+                for (int k = 0; k < K; ++k) {
+                    dig[k] = xK.mod_small(p);
+                    xK = xK / BigInt((int64_t)p);
+                }
+            };
+            std::vector<uint32_t> dig;
+            digits(sn, dig);
             const int L = (int)((sn.bit_length() + 24) / 25) + 1;
-            BigInt PL(1);
-            for (int k = 0; k < L; ++k) PL = PL.mul_small(p);
-            const BigInt negpK = mod(-pK, sn);
-            const ModReducer red(sn);
+            const RingBig FB(sn);
+            const PadicTable<RingBig> TB(FB, sn, p, K, L);
             BigInt out;
-            const bool ok = padic_top_mod(dig.data() + (K - L), L, 1, p, sn, PL, negpK, red, out);
-            CHECK(ok && out == mod(N, sn), "padic_top_mod wrong at %d", it);
-            // x = N / (3 sn) with 3 not dividing N: s_n x is not an integer.
+            const bool ok = TB.eval(dig.data() + (K - L), 1, out);
+            CHECK(ok && out == mod(N, sn), "padic table (big) wrong at %d", it);
+            const Ring64 FW(Mw);
+            const PadicTable<Ring64> TW(FW, sn, p, K, L);
+            uint64_t ow = 0;
+            const bool okw = TW.eval(dig.data() + (K - L), 1, ow);
+            CHECK(okw && BigInt::from_u64(ow) == mod(N, BigInt::from_u64(Mw)), "padic table (word) wrong at %d", it);
+            // x = N / (3 s_n) with 3 not dividing N: s_n x is not an integer.
             if (mod(N, BigInt(3)).is_zero()) N = N + BigInt(1);
-            BigInt::xgcd(mod(sn.mul_small(3), pK), pK, xi, yi);
-            xK = mod(N * xi, pK);
-            for (int k = 0; k < K; ++k) {
-                dig[k] = xK.mod_small(p);
-                xK = xK / BigInt((int64_t)p);
-            }
-            CHECK(!padic_top_mod(dig.data() + (K - L), L, 1, p, sn, PL, negpK, red, out),
-                  "padic_top_mod accepted a non-integer at %d", it);
+            digits(sn.mul_small(3), dig);
+            CHECK(!TB.eval(dig.data() + (K - L), 1, out), "padic table accepted a non-integer at %d", it);
         }
     }
     printf("bad=%d\n", bad);
