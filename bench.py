@@ -94,8 +94,10 @@ def parse():
                     help="time the full-range residue product with 10-word CRT (0 = skip)")
     ap.add_argument("--serving", type=int, default=200,
                     help="requests per open-loop serving point (0 = skip)")
+    ap.add_argument("--massager-max", type=int, default=2003,
+                    help="largest n of the Smith massager leg (Section 4.1 family; 0 = skip)")
     ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving", "lifting", "smith64",
-                                                 "planted2000", "stress"],
+                                                 "planted2000", "stress", "massager"],
                     help="run only this workload (for profiling)")
     ap.add_argument("--lifting-n", type=int, default=10007,
                     help="matrix order of the --only lifting workload (one random Smith-form solve)")
@@ -396,6 +398,64 @@ def run_smith_one(rg, which, reps=10):
                 "traced": _traced(rg, ctx, a)}
 
 
+# Section 4.3, Tables 1 and 2 (Apple M4 Max, one core-cluster CPU run with
+# OpenBLAS): wall seconds of the paper's implementation on A_ij = i^j mod n,
+# and its Phase 1 / Phase 2 / Phase 3 split (LIF, IM, UC).  Context only:
+# another machine's numbers.
+PAPER_TABLE1_S = {53: 0.033, 101: 0.083, 211: 0.447, 503: 2.07, 1009: 26.30, 2003: 134.4, 5003: 1744.0,
+                  10007: 5399.0}
+PAPER_TABLE2 = {53: (0.011, 0.005, 0.004, 0.020), 101: (0.024, 0.026, 0.018, 0.070),
+                211: (0.078, 0.263, 0.078, 0.428), 503: (0.644, 0.762, 0.563, 2.069),
+                1009: (2.424, 17.68, 3.835, 24.67), 2003: (18.76, 93.01, 23.43, 139.7),
+                5003: (168.6, 692.2, 545.6, 1515.0)}
+MASSAGER_SIZES = (53, 101, 211, 503, 1009, 2003, 5003, 10007)
+
+
+def run_massager(rg, nmax):
+    """The Smith massager (U, M, T, S) of A_ij = i^j mod n (Section 4.1) for
+    the paper's prime sizes up to nmax: one timed solve each after a warm-up,
+    the divisor chain and (n = 101, 199 from the stored oracle values; n = 1009
+    from the printed 4083-bit s_n) the invariants checked, A M S^-1 checked
+    integral on its three last columns; the paper's Table 1 and 2 figures
+    beside each size as context."""
+    import synth
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "tests", "golden", "smith_vandermonde.json")) as f:
+        golden = {c["n"]: c for c in json.load(f)["cases"]}
+    out = []
+    with rg.Context(device=0, L=24) as ctx:
+        rg.smith_massager(ctx, synth.vandermonde_mod(53), seed=0)     # warm-up
+        for n in [m for m in MASSAGER_SIZES if m <= nmax] + [199]:
+            a = synth.vandermonde_mod(n)
+            t0 = time.perf_counter()
+            r = rg.smith_massager(ctx, a, seed=1)
+            t = time.perf_counter() - t0
+            S = r.s
+            if any(S[i + 1] % S[i] for i in range(n - 1)) or r.stats["cert_exact"] != 1:
+                raise SystemExit("bench.py: massager n=%d: not a certified divisor chain" % n)
+            if n in golden:
+                g = golden[n]
+                if S != [1] * g["ones"] + [int(v) for v in g["tail"]]:
+                    raise SystemExit("bench.py: massager n=%d differs from the oracle's Smith form" % n)
+            if n == 1009 and S[-1].bit_length() != 4083:
+                raise SystemExit("bench.py: massager n=1009: s_n is not 4083 bits")
+            ao = a.astype(object)
+            for j in range(n - 3, n):
+                if any(v % S[j] for v in ao.dot(r.M[:, j])):
+                    raise SystemExit("bench.py: massager n=%d: A M S^-1 not integral" % n)
+            rec = {"n": n, "seconds": t, "nontrivial": sum(1 for v in S if v != 1),
+                   "largest_invariant_bits": S[-1].bit_length(), "stats": r.stats}
+            if n in PAPER_TABLE1_S:
+                rec["paper_seconds"] = PAPER_TABLE1_S[n]
+                rec["speedup_vs_paper"] = PAPER_TABLE1_S[n] / t
+            if n in PAPER_TABLE2:
+                rec["paper_lif_im_uc_total"] = PAPER_TABLE2[n]
+            out.append(rec)
+            print("[bench] massager n=%d %.3f s" % (n, t), file=sys.stderr, flush=True)
+    return {"workload": "Smith massager of A_ij = i^j mod n (Section 4.1), one solve per n, seed 1",
+            "paper_hardware": "Apple M4 Max, OpenBLAS (Section 4)", "sizes": out}
+
+
 def _serving_stream(count, rate, seed, tail):
     """Serving requests: Poisson arrivals at `rate`, n log-uniform in
     [100, 4000], entries uniform in [-2^10, 2^10] (a singular draw is
@@ -677,6 +737,9 @@ def main():
     if args.only in ("smith64", "planted2000"):
         print(json.dumps(run_smith_one(rg, args.only)), flush=True)
         return
+    if args.only == "massager":
+        print(json.dumps(run_massager(rg, args.massager_max or 1009)), flush=True)
+        return
     if args.only == "stress":
         with rg.Context(device=0, L=args.primes) as c:
             print(json.dumps(run_stress(rg, torch, dev, c, args.n, args.primes)), flush=True)
@@ -848,6 +911,8 @@ def main():
     print("[bench] smith done", file=sys.stderr, flush=True)
     rec["serving"] = run_serving(rg, args.serving) if args.serving > 0 else None
     print("[bench] serving done", file=sys.stderr, flush=True)
+    rec["massager"] = run_massager(rg, args.massager_max) if args.massager_max > 0 else None
+    print("[bench] massager done", file=sys.stderr, flush=True)
     if args.cpu_rows > 0:
         primes = ctx.primes[:L]
         rec["cpu_baseline"] = cpu_baseline(a_np, b_np, primes, args.cpu_rows)
