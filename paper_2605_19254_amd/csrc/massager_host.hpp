@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <functional>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -32,6 +33,7 @@ struct Ring64 {
     V zero() const { return 0; }
     V one() const { return s == 1 ? 0 : 1; }
     bool is_zero(V a) const { return a == 0; }
+    bool is_one(V a) const { return a == 1; }
     V from(const BigInt &x) const {
         const BigInt r = mod(x, BigInt::from_u64(s));
         return r.to_u64_mag();
@@ -143,6 +145,7 @@ struct RingBig {
     V zero() const { return BigInt(0); }
     V one() const { return s.is_one() ? BigInt(0) : BigInt(1); }
     bool is_zero(const V &a) const { return a.is_zero(); }
+    bool is_one(const V &a) const { return a.is_one(); }
     V from(const BigInt &x) const { return red.reduce(x); }
     BigInt big(const V &a) const { return a; }
     V mul(const V &a, const V &b) const { return red.reduce(a * b); }
@@ -286,11 +289,22 @@ SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t
         }
         // The pivot's gcd with s only decreases (in the divisor order), so
         // the loop ends.
+        std::vector<char> nd;
         for (;;) {
             V a = at(c, c), g = F.gcd_s(a);
-            for (int64_t i = c + 1; i < n; ++i) {
-                const V b = at(i, c);
-                if (!F.is_zero(b) && !F.divides(g, b)) {
+            // Rows whose entry in column c the pivot does not divide (none
+            // when the pivot is a unit); the flags are computed in parallel
+            // and rechecked after each change of the pivot.
+            if (!F.is_one(g)) {
+                nd.assign((size_t)n, 0);
+                par(n - c - 1, F.cost(), [&](int64_t k) {
+                    const V &b = at(c + 1 + k, c);
+                    nd[(size_t)(c + 1 + k)] = !F.is_zero(b) && !F.divides(g, b);
+                });
+                for (int64_t i = c + 1; i < n && !F.is_one(g); ++i) {
+                    if (!nd[(size_t)i]) continue;
+                    const V b = at(i, c);
+                    if (F.divides(g, b)) continue;
                     rowadd(c, i, F.stab(a, b));
                     a = at(c, c);
                     g = F.gcd_s(a);
@@ -430,6 +444,79 @@ struct PadicTable {
             B[(size_t)l] = F.from(-(a * pK));
             frac[(size_t)l] = (r.shl(64) / pl).to_u64_mag();
         }
+    }
+    // eval for cnt entries whose digit planes are contiguous (entry k's digit
+    // of step K - l at dig[(L - l) stride + k]); out[k ostride].  The digit
+    // index is the outer loop, so every plane is read in order.
+    bool eval_block(const uint32_t *dig, int64_t stride, int64_t cnt, V *out, int64_t ostride) const {
+        std::vector<unsigned __int128> fs((size_t)cnt, 0);
+        for (int l = 1; l <= L; ++l) {
+            const uint32_t *d = dig + (size_t)(L - l) * stride;
+            const uint64_t f = frac[(size_t)l];
+            for (int64_t k = 0; k < cnt; ++k) fs[(size_t)k] += (unsigned __int128)f * d[k];
+        }
+        std::vector<uint64_t> ev((size_t)cnt);
+        for (int64_t k = 0; k < cnt; ++k) {
+            const uint64_t e = (uint64_t)((fs[(size_t)k] + ((unsigned __int128)1 << 63)) >> 64);
+            const unsigned __int128 ee = (unsigned __int128)e << 64;
+            const unsigned __int128 dist = fs[(size_t)k] > ee ? fs[(size_t)k] - ee : ee - fs[(size_t)k];
+            if (dist >= ((unsigned __int128)1 << 43)) return false;
+            ev[(size_t)k] = e;
+        }
+        if constexpr (std::is_same<Ring, Ring64>::value) {
+            std::vector<unsigned __int128> acc((size_t)cnt, 0);
+            for (int l = 1; l <= L; ++l) {
+                const uint32_t *d = dig + (size_t)(L - l) * stride;
+                const uint64_t b = B[(size_t)l];
+                for (int64_t k = 0; k < cnt; ++k) acc[(size_t)k] += (unsigned __int128)b * d[k];
+            }
+            for (int64_t k = 0; k < cnt; ++k)
+                out[(size_t)(k * ostride)] = F.add((V)(acc[(size_t)k] % F.s), F.mul_u64(B[0], ev[(size_t)k]));
+        } else {
+            // 64-bit words of the B_l, and a word accumulator per entry
+            // (sum of L products below 2^(64 W + 32 + log2 L)).
+            size_t W = 1;
+            for (int l = 1; l <= L; ++l) W = std::max(W, B[(size_t)l].mag_words().size());
+            std::vector<uint64_t> bw((size_t)(L + 1) * W, 0);
+            for (int l = 1; l <= L; ++l) {
+                const std::vector<uint64_t> w = B[(size_t)l].mag_words();
+                std::copy(w.begin(), w.end(), bw.begin() + (size_t)l * W);
+            }
+            const size_t AW = W + 2;
+            std::vector<uint64_t> acc((size_t)cnt * AW, 0);
+            for (int l = 1; l <= L; ++l) {
+                const uint32_t *d = dig + (size_t)(L - l) * stride;
+                const uint64_t *b = bw.data() + (size_t)l * W;
+                for (int64_t k = 0; k < cnt; ++k) {
+                    const uint64_t dk = d[k];
+                    if (!dk) continue;
+                    uint64_t *a = acc.data() + (size_t)k * AW;
+                    unsigned __int128 carry = 0;
+                    for (size_t w = 0; w < W; ++w) {
+                        const unsigned __int128 v = (unsigned __int128)b[w] * dk + a[w] + carry;
+                        a[w] = (uint64_t)v;
+                        carry = v >> 64;
+                    }
+                    for (size_t w = W; carry && w < AW; ++w) {
+                        const unsigned __int128 v = (unsigned __int128)a[w] + carry;
+                        a[w] = (uint64_t)v;
+                        carry = v >> 64;
+                    }
+                }
+            }
+            for (int64_t k = 0; k < cnt; ++k) {
+                const uint64_t *a = acc.data() + (size_t)k * AW;
+                BigInt x;
+                x.mag.resize(2 * AW);
+                for (size_t w = 0; w < AW; ++w) {
+                    x.mag[2 * w] = (uint32_t)a[w];
+                    x.mag[2 * w + 1] = (uint32_t)(a[w] >> 32);
+                }
+                while (!x.mag.empty() && x.mag.back() == 0) x.mag.pop_back();
+                out[(size_t)(k * ostride)] = F.add(F.from(x), F.mul_u64(B[0], ev[(size_t)k]));
+            }
+        }
+        return true;
     }
     bool eval(const uint32_t *dig, int64_t stride, V &out) const {
         unsigned __int128 fs = 0;

@@ -1511,6 +1511,81 @@ struct Driver {
         return RNS_OK;
     }
 
+    // The first G runs of kLiftMaxCols columns of J ([t][ldl], host) lifted
+    // together (one launch per product and step, blockIdx.y = run; only the
+    // top L digit slots kept, step i in slot i % L), and Y[i t + c] =
+    // Rem(s_n x, m) for those columns computed on the GPU from the digits with
+    // the word table `tab` (modulus m < 2^62).  Y's other columns are left
+    // for the caller.
+    int lift_dot_grouped(int pidx, const std::vector<int64_t> &J, int64_t t, int64_t G, int64_t K, int L,
+                         const msg::PadicTable<msg::Ring64> &tab, std::vector<uint64_t> &Y) {
+        const uint32_t p = aux->primes[pidx];
+        const int64_t tc = kLiftMaxCols, cols = G * tc;
+        const size_t cnt = (size_t)(cols * ldl), fb = lift_frag_bytes(n);
+        DRV_ST(dCt.alloc(lift_tile_c_bytes(n)));
+        launch_lift_tile_c(dC.p, n, ldl, p, dCt.p, stream);
+        DRV_HIP(hipGetLastError());
+        DRV_ST(dAt.alloc(lift_tile_a_bytes(n)));
+        launch_lift_tile_a(dA16.p, n, ldl, dAt.p, stream);
+        DRV_HIP(hipGetLastError());
+        DevBuf<int64_t> R0, R1, step;
+        DevBuf<uint32_t> Rm0, Rm1, Xh;
+        DevBuf<char> Xd, Rmd;
+        DevBuf<int32_t> err;
+        DevBuf<uint64_t> dB, dF, dY;
+        DRV_ST(R0.alloc(cnt));
+        DRV_ST(R1.alloc(cnt));
+        DRV_ST(Rm0.alloc(cnt));
+        DRV_ST(Rm1.alloc(cnt));
+        DRV_ST(Xh.alloc((size_t)(G * L * tc * ldl)));
+        DRV_ST(Xd.alloc((size_t)G * fb));
+        DRV_ST(Rmd.alloc((size_t)G * fb));
+        DRV_ST(err.alloc(2));
+        DRV_ST(step.alloc(1));
+        DRV_ST(dB.alloc((size_t)L + 1));
+        DRV_ST(dF.alloc((size_t)L + 1));
+        DRV_ST(dY.alloc((size_t)(n * t)));
+        std::vector<uint32_t> Jm(cnt);
+        for (size_t e = 0; e < cnt; ++e) {
+            const int64_t v = J[e] % (int64_t)p;
+            Jm[e] = (uint32_t)(v < 0 ? v + (int64_t)p : v);
+        }
+        DRV_HIP(hipMemcpyAsync(R0.p, J.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(Rm0.p, Jm.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(dB.p, tab.B.data(), sizeof(uint64_t) * ((size_t)L + 1), hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(dF.p, tab.frac.data(), sizeof(uint64_t) * ((size_t)L + 1), hipMemcpyHostToDevice,
+                               stream));
+        DRV_HIP(hipMemsetAsync(err.p, 0, 2 * sizeof(int32_t), stream));
+        DRV_HIP(hipMemsetAsync(step.p, 0, sizeof(int64_t), stream));
+        for (int64_t g = 0; g < G; ++g)                  // the first step's Rm, per run
+            launch_lift_frag(Rm0.p + (size_t)(g * tc * ldl), n, ldl, (int)tc, p, Rmd.p + (size_t)g * fb, stream);
+        DRV_HIP(hipGetLastError());
+        LiftBufs lb{R0.p, R1.p, Rm0.p, Rm1.p, Xh.p, err.p, step.p};
+        lb.Ct = dCt.p;
+        lb.At = dAt.p;
+        lb.Xd = Xd.p;
+        lb.Rmd = Rmd.p;
+        lb.grp.groups = (int)G;
+        lb.grp.r = tc * ldl;
+        lb.grp.rm = tc * ldl;
+        lb.grp.xh = L * tc * ldl;
+        lb.grp.frag = (int64_t)(fb / 16);                // v4i_l elements
+        lb.grp.ring = L;
+        if (!lift_groups_ok(lb, a_bytes, (int)tc)) return RNS_EINVAL;
+        launch_lift_steps(dC.p, dA16.p, a_bytes, n, ldl, (int)tc, p, lb, (int)K, stream);
+        DRV_HIP(hipGetLastError());
+        launch_padic_dot(Xh.p, n, ldl, cols, t, lb.grp.xh, L, K, L, dB.p, dF.p, tab.F.s, dY.p, err.p + 1, stream);
+        DRV_HIP(hipGetLastError());
+        int32_t herr[2] = {0, 0};
+        DRV_HIP(hipMemcpyAsync(herr, err.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        DRV_HIP(hipMemcpyAsync(Y.data(), dY.p, sizeof(uint64_t) * (size_t)(n * t), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        if (herr[0]) return RNS_EDEVICE;                 // an inexact division: C is not A^-1 mod p
+        if (herr[1]) return RNS_EBOUND;                  // s_n A^-1 J is not integral
+        st.lift_steps += (int)(K * G);
+        return RNS_OK;
+    }
+
     // The largest divisor of y prime to s (repeated gcds, no factoring).
     static BigInt coprime_part(BigInt y, const BigInt &s) {
         for (;;) {
@@ -1550,16 +1625,36 @@ struct Driver {
         std::vector<int64_t> J((size_t)t * ldl, 0);
         for (int64_t c = 0; c < t; ++c)
             for (int64_t r = 0; r < n; ++r) J[(size_t)c * ldl + r] = (int64_t)(rng.next() % 257) - 128;
-        std::vector<uint32_t> dig;
-        DRV_ST(lift_top(pidx, J, t, K, L, dig));
         const msg::PadicTable<Ring> tab(FM, sn, p, K, L);
         const msg::ParFor par = host_par();
         std::vector<V> Y((size_t)n * t);
         std::atomic<bool> ok{true};
-        par(n * t, (double)L * FM.cost() / 4.0, [&](int64_t e) {
-            const int64_t i = e / t, c = e % t;
-            if (!tab.eval(dig.data() + (size_t)c * ldl + i, t * ldl, Y[(size_t)e])) ok = false;
-        });
+        // With a word modulus and the matrix-core step kernels, the full runs
+        // of 16 columns are lifted in one grouped run and their Y computed on
+        // the GPU; the rest goes through the lanes and the host table.
+        int64_t tg = 0;
+        if constexpr (std::is_same<Ring, msg::Ring64>::value) {
+            const int64_t G = t / kLiftMaxCols;
+            if (G >= 2 && mfma_lift() && a_bytes == 2) {
+                DRV_ST(lift_dot_grouped(pidx, J, t, G, K, L, tab, Y));
+                tg = G * kLiftMaxCols;
+            }
+        }
+        if (tg < t) {
+            const int64_t tr = t - tg;
+            const std::vector<int64_t> Jr(J.begin() + (size_t)(tg * ldl), J.end());
+            std::vector<uint32_t> dig;
+            DRV_ST(lift_top(pidx, Jr, tr, K, L, dig));
+            // Blocks of rows of one column: the digit planes are read in order.
+            const int64_t rb = std::is_same<Ring, msg::Ring64>::value ? 1024 : 256;
+            const int64_t nrb = (n + rb - 1) / rb;
+            par(tr * nrb, (double)rb * L * FM.cost() / 4.0, [&](int64_t q) {
+                const int64_t c = q / nrb, i0 = (q % nrb) * rb, cnt = std::min(rb, n - i0);
+                if (!tab.eval_block(dig.data() + (size_t)c * ldl + i0, tr * ldl, cnt,
+                                    Y.data() + (size_t)(i0 * t + tg + c), t))
+                    ok = false;
+            });
+        }
         if (!ok) return RNS_EBOUND;
         // Earlier batches, oldest first: Y <- Y + M_b (U_b Y) (mod M').
         for (const MBatch &b : B) {

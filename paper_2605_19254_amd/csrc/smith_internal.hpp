@@ -44,6 +44,15 @@ constexpr int kLiftMaxCols = 16;
 // Device state of a lifting run: residuals R[2] (int64) and Rm[2] (mod p),
 // every step's digits Xh ([K][t][ld]), the inexact-division flag and the
 // index of the next step (*base).
+// Several independent liftings of kLiftMaxCols vectors each in one launch
+// (blockIdx.y = group; only the unpacked matrix-core kernels with both
+// operands tiled): group g's buffers start `r`, `rm`, `xh`, `frag` elements
+// after group 0's.  Step i's digits go to slot i % ring of Xh.
+struct LiftGroups {
+    int groups = 1;
+    int64_t r = 0, rm = 0, xh = 0, frag = 0;
+    int64_t ring = INT64_MAX;
+};
 struct LiftBufs {
     int64_t *R0, *R1;
     uint32_t *Rm0, *Rm1;
@@ -54,7 +63,17 @@ struct LiftBufs {
     const char *At = nullptr;   // int16 A as tiled digits (launch_lift_tile_a), or null
     char *Xd = nullptr;         // digit fragments of the step's X and of the next Rm (each
     char *Rmd = nullptr;        // lift_frag_bytes(n)); used when Ct and At are both set
+    LiftGroups grp{};
 };
+// Rem(s_n x, m) (m < 2^62) for the first `cols` lifted vectors (groups of
+// 16) from their top L digits: B[l] = -a_l p^K mod m, F[l] =
+// floor(frac(s_n / p^l) 2^64), B[0] = -p^K mod m, as msg::PadicTable; the
+// digit of step K - l of vector c, row i is
+// Xh[(c / 16) xh + ((K - l) % ring) 16 ld + (c % 16) ld + i].  Entry (i, c)
+// goes to Y[i ystride + c]; *bad = 1 where the rounding is not within 2^-21.
+void launch_padic_dot(const uint32_t *Xh, int64_t n, int64_t ld, int64_t cols, int64_t ystride, int64_t xh,
+                      int64_t ring, int64_t K, int L, const uint64_t *B, const uint64_t *F, uint64_t m, uint64_t *Y,
+                      int32_t *bad, hipStream_t s);
 // Largest n whose lifting products run on the matrix cores (int32 sums of
 // the digit products stay exact for k <= 43690).
 constexpr int64_t kLiftMfmaMaxN = 43690;
@@ -66,6 +85,10 @@ void launch_lift_tile_c(const uint32_t *C, int64_t n, int64_t ld, uint32_t p, ch
 // With both operands tiled and t <= 4 the right operands use the packed
 // fragment (digit d of vector c in MFMA column 4 d + c, 1 KiB per 64 rows).
 inline bool lift_packed(int t) { return t <= 4; }
+// Whether launch_lift_steps can run grouped liftings for these buffers.
+inline bool lift_groups_ok(const LiftBufs &b, int a_bytes, int t) {
+    return b.Ct && b.At && a_bytes == 2 && b.Xd && b.Rmd && !lift_packed(t);
+}
 // Digit fragments of t <= 16 vectors [t][ld] (the right operand of the
 // lifting products; packed when lift_packed(t)); balanced digits of the first
 // step's Rm (entries in [0, p)) for C Rm mod p.

@@ -511,11 +511,18 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_x_mfma(const v4i_l *__
                                                          const uint32_t *__restrict__ Rm1, int t, uint32_t p,
                                                          uint32_t *__restrict__ Xh,
                                                          const int64_t *__restrict__ base, int off,
-                                                         const v4i_l *__restrict__ Rmd, v4i_l *__restrict__ Xd) {
+                                                         const v4i_l *__restrict__ Rmd, v4i_l *__restrict__ Xd,
+                                                         LiftGroups gr) {
     __shared__ v4i_l part[KS][7][64];
+    const int64_t g = blockIdx.y;                        // group: its own vectors and buffers
+    Rm0 += g * gr.rm;
+    Rm1 += g * gr.rm;
+    Xh += g * gr.xh;
+    Rmd += g * gr.frag;
+    Xd += g * gr.frag;
     const int64_t i_step = *base + off;
     const uint32_t *__restrict__ Rm = (i_step & 1) ? Rm1 : Rm0;
-    uint32_t *__restrict__ X = Xh + i_step * t * ld;
+    uint32_t *__restrict__ X = Xh + (i_step % gr.ring) * t * ld;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t rb = blockIdx.x;
@@ -631,10 +638,18 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
                                                                  int32_t *__restrict__ err,
                                                                  const int64_t *__restrict__ base, int off,
                                                                  const v4i_l *__restrict__ Xd,
-                                                                 v4i_l *__restrict__ Rmd) {
+                                                                 v4i_l *__restrict__ Rmd, LiftGroups gr) {
     __shared__ v4i_l part[KS][8][64];
+    const int64_t g = blockIdx.y;                        // group: its own vectors and buffers
+    R0 += g * gr.r;
+    R1 += g * gr.r;
+    Rm0 += g * gr.rm;
+    Rm1 += g * gr.rm;
+    Xh += g * gr.xh;
+    Xd += g * gr.frag;
+    Rmd += g * gr.frag;
     const int64_t i_step = *base + off;
-    const uint32_t *__restrict__ X = Xh + i_step * t * ld;
+    const uint32_t *__restrict__ X = Xh + (i_step % gr.ring) * t * ld;
     const int64_t *__restrict__ R = (i_step & 1) ? R1 : R0;
     int64_t *__restrict__ Rn = (i_step & 1) ? R0 : R1;
     uint32_t *__restrict__ Rmn = (i_step & 1) ? Rm0 : Rm1;
@@ -1376,11 +1391,11 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const v4i_l *ct = reinterpret_cast<const v4i_l *>(b.Ct);
         // Eight waves per 16-row block, two work-groups per CU.
         if (frag)
-            hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(rbs), dim3(512), 0, s, ct, n, ld, KT, b.Rm0, b.Rm1, t, p,
-                               b.Xh, b.base, off, rmd, xd);
+            hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(rbs, (unsigned)b.grp.groups), dim3(512), 0, s, ct, n, ld,
+                               KT, b.Rm0, b.Rm1, t, p, b.Xh, b.base, off, rmd, xd, b.grp);
         else
             hipLaunchKernelGGL((k_lift_x_mfma<8, false>), dim3(rbs), dim3(512), 0, s, ct, n, ld, KT, b.Rm0, b.Rm1, t,
-                               p, b.Xh, b.base, off, rmd, xd);
+                               p, b.Xh, b.base, off, rmd, xd, LiftGroups{});
     } else {
         hipLaunchKernelGGL((k_lift_x<T, RW>), dim3(blocks), dim3(256), 0, s, C, n, ld, b.Rm0, b.Rm1, t, p, b.Xh,
                            b.base, off);
@@ -1392,11 +1407,11 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const v4i_l *xdc = reinterpret_cast<const v4i_l *>(b.Xd);
         v4i_l *rmdw = reinterpret_cast<v4i_l *>(b.Rmd);
         if (frag)
-            hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(rbs), dim3(512), 0, s, at, n, ld, KT, b.Xh, b.R0, b.R1,
-                               b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw);
+            hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(rbs, (unsigned)b.grp.groups), dim3(512), 0, s, at, n,
+                               ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw, b.grp);
         else
             hipLaunchKernelGGL((k_lift_r_mfma<8, false>), dim3(rbs), dim3(512), 0, s, at, n, ld, KT, b.Xh, b.R0,
-                               b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw);
+                               b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw, LiftGroups{});
     } else {
         hipLaunchKernelGGL((k_lift_r<T, RW, AT>), dim3(blocks), dim3(256), 0, s, A, n, ld, b.Xh, b.R0, b.R1,
                            b.Rm0, b.Rm1, t, p, b.err, b.base, off);
@@ -1484,6 +1499,44 @@ void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n,
             lift_step_at(C, static_cast<const int32_t *>(A), n, ld, t, p, b, off, s);
     }
     hipLaunchKernelGGL(k_lift_advance, dim3(1), dim3(64), 0, s, b.base, steps);
+}
+
+// One thread per (row i, vector c): the L-term dot products of reading 21
+// (sum d_l B_l and sum d_l F_l in 128-bit integers), the rounding check and
+// the result modulo m.  The digits of consecutive rows are contiguous.
+__global__ __launch_bounds__(256) void k_padic_dot(const uint32_t *__restrict__ Xh, int64_t n, int64_t ld,
+                                                   int64_t ystride, int64_t xh, int64_t ring, int64_t K, int L,
+                                                   const uint64_t *__restrict__ B, const uint64_t *__restrict__ F,
+                                                   uint64_t m, uint64_t *__restrict__ Y, int32_t *__restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i >= n) return;
+    const uint32_t *__restrict__ d0 = Xh + (c / 16) * xh + (c % 16) * ld + i;
+    const auto *Bc = cptr(B);
+    const auto *Fc = cptr(F);
+    unsigned __int128 acc = 0, fs = 0;
+    for (int l = 1; l <= L; ++l) {
+        const uint64_t d = d0[((K - l) % ring) * 16 * ld];
+        acc += (unsigned __int128)Bc[l] * d;
+        fs += (unsigned __int128)Fc[l] * d;
+    }
+    const uint64_t e = (uint64_t)((fs + ((unsigned __int128)1 << 63)) >> 64);
+    const unsigned __int128 ee = (unsigned __int128)e << 64;
+    const unsigned __int128 dist = fs > ee ? fs - ee : ee - fs;
+    if (dist >= ((unsigned __int128)1 << 43)) atomicOr(bad, 1);
+    const uint64_t r1 = (uint64_t)(acc % m);
+    const uint64_t r2 = (uint64_t)((unsigned __int128)Bc[0] * (e % m) % m);
+    const uint64_t r = r1 + r2;
+    Y[i * ystride + c] = r >= m ? r - m : r;
+}
+
+void launch_padic_dot(const uint32_t *Xh, int64_t n, int64_t ld, int64_t cols, int64_t ystride, int64_t xh,
+                      int64_t ring, int64_t K, int L, const uint64_t *B, const uint64_t *F, uint64_t m, uint64_t *Y,
+                      int32_t *bad, hipStream_t s) {
+    if (n <= 0 || cols <= 0) return;
+    ProfScope trace_(tl_trace, "k_padic_dot", s);
+    hipLaunchKernelGGL(k_padic_dot, dim3((unsigned)((n + 255) / 256), (unsigned)cols), dim3(256), 0, s, Xh, n, ld,
+                       ystride, xh, ring, K, L, B, F, m, Y, bad);
 }
 
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,

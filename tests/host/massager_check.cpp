@@ -250,6 +250,31 @@ int main() {
             uint64_t ow = 0;
             const bool okw = TW.eval(dig.data() + (K - L), 1, ow);
             CHECK(okw && BigInt::from_u64(ow) == mod(N, BigInt::from_u64(Mw)), "padic table (word) wrong at %d", it);
+            // The block form over several entries (digit planes of stride 3,
+            // the entry's digits at offset 1) agrees with the single form.
+            {
+                // entries N, N + 1, -N, 0 side by side (stride 4), outputs at stride 2
+                const BigInt Ns[4] = {N, N + BigInt(1), -N, BigInt(0)};
+                std::vector<uint32_t> planes((size_t)K * 4, 0u);
+                for (int j = 0; j < 4; ++j) {
+                    BigInt xi, yi;
+                    BigInt::xgcd(mod(sn, pK), pK, xi, yi);
+                    BigInt xK = mod(Ns[j] * xi, pK);
+                    for (int k = 0; k < K; ++k) {
+                        planes[(size_t)k * 4 + j] = xK.mod_small(p);
+                        xK = xK / BigInt((int64_t)p);
+                    }
+                }
+                BigInt ob[8];
+                uint64_t owb[8] = {0};
+                const bool okb = TB.eval_block(planes.data() + (size_t)(K - L) * 4, 4, 4, ob, 2);
+                const bool okw2 = TW.eval_block(planes.data() + (size_t)(K - L) * 4, 4, 4, owb, 2);
+                for (int j = 0; j < 4; ++j) {
+                    CHECK(okb && ob[2 * j] == mod(Ns[j], sn), "padic block (big) entry %d at %d", j, it);
+                    CHECK(okw2 && BigInt::from_u64(owb[2 * j]) == mod(Ns[j], BigInt::from_u64(Mw)),
+                          "padic block (word) entry %d at %d", j, it);
+                }
+            }
             // x = N / (3 s_n) with 3 not dividing N: s_n x is not an integer.
             if (mod(N, BigInt(3)).is_zero()) N = N + BigInt(1);
             digits(sn.mul_small(3), dig);
