@@ -134,6 +134,10 @@ struct Ring64 {
     }
     V divexact(V a, V b) const { return a / b; }
     V mulexact(V a, V b) const { return a * b; }   // a b divides s here
+    // Elimination updates: words are always reduced.
+    static constexpr bool kLazy = false;
+    V fma_lazy(V acc, V f, V b) const { return add(acc, mul(f, b)); }
+    V reduce(V a) const { return a; }
 };
 
 // Z/sZ for any s > 1 on big integers.
@@ -202,6 +206,12 @@ struct RingBig {
     }
     V divexact(const V &a, const V &b) const { return a / b; }
     V mulexact(const V &a, const V &b) const { return a * b; }
+    // Elimination updates without reduction (an entry grows by one product
+    // per update; entries are reduced before they are read as a pivot column
+    // or row).
+    static constexpr bool kLazy = true;
+    V fma_lazy(const V &acc, const V &f, const V &b) const { return acc + f * b; }
+    V reduce(const V &a) const { return red.reduce(a); }
 };
 
 // One row operation of the elimination, as a left factor of E:
@@ -265,7 +275,16 @@ SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t
     };
     const int64_t steps = std::min(n, t);
     int64_t c = 0;
+    // Big rings: column c and row c are reduced before they are read (after
+    // any exchange that brings other entries there).
+    auto normalise = [&]() {
+        if constexpr (Ring::kLazy) {
+            par(n - c, F.cost(), [&](int64_t k) { at(c + k, c) = F.reduce(at(c + k, c)); });
+            for (int64_t j = c + 1; j < t; ++j) at(c, j) = F.reduce(at(c, j));
+        }
+    };
     for (; c < steps; ++c) {
+        normalise();
         if (F.is_zero(at(c, c))) {
             bool found = false;
             for (int64_t i = c + 1; i < n && !found; ++i)
@@ -280,12 +299,13 @@ SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t
                 }
             for (int64_t i = c + 1; i < n && !found; ++i)
                 for (int64_t j = c + 1; j < t && !found; ++j)
-                    if (!F.is_zero(at(i, j))) {
+                    if (!F.is_zero(at(i, j) = F.reduce(at(i, j)))) {
                         rowswap(c, i);
                         colswap(c, j);
                         found = true;
                     }
             if (!found) break;                    // the rest is zero
+            normalise();
         }
         // The pivot's gcd with s only decreases (in the divisor order), so
         // the loop ends.
@@ -334,7 +354,8 @@ SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t
         par((int64_t)rows.size(), (double)(t - c) * F.cost(), [&](int64_t k) {
             const int64_t i = rows[(size_t)k];
             const V &f = fs[(size_t)k];
-            for (int64_t j = c; j < t; ++j) at(i, j) = F.add(at(i, j), F.mul(f, at(c, j)));
+            at(i, c) = F.zero();                         // = b + f a = 0 (mod s)
+            for (int64_t j = c + 1; j < t; ++j) at(i, j) = F.fma_lazy(at(i, j), f, at(c, j));
         });
         for (size_t k = 0; k < rows.size(); ++k) out.ops.push_back({1, rows[k], c, fs[k]});
         // Row c right of the pivot: column j += f_j column c; column c is zero

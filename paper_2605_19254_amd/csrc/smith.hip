@@ -1513,12 +1513,13 @@ struct Driver {
 
     // The first G runs of kLiftMaxCols columns of J ([t][ldl], host) lifted
     // together (one launch per product and step, blockIdx.y = run; only the
-    // top L digit slots kept, step i in slot i % L), and Y[i t + c] =
-    // Rem(s_n x, m) for those columns computed on the GPU from the digits with
-    // the word table `tab` (modulus m < 2^62).  Y's other columns are left
-    // for the caller.
-    int lift_dot_grouped(int pidx, const std::vector<int64_t> &J, int64_t t, int64_t G, int64_t K, int L,
-                         const msg::PadicTable<msg::Ring64> &tab, std::vector<uint64_t> &Y) {
+    // top L digit slots kept, step i in slot i % L).  With a word table `tab`
+    // (modulus m < 2^62), Y[i t + c] = Rem(s_n x, m) for those columns is
+    // computed on the GPU from the digits (Y's other columns are left for the
+    // caller); without one, the digits come back as dig ([L][G 16][ldl],
+    // l = 0 the digit of step K - L).
+    int lift_grouped(int pidx, const std::vector<int64_t> &J, int64_t t, int64_t G, int64_t K, int L,
+                     const msg::PadicTable<msg::Ring64> *tab, std::vector<uint64_t> *Y, std::vector<uint32_t> *dig) {
         const uint32_t p = aux->primes[pidx];
         const int64_t tc = kLiftMaxCols, cols = G * tc;
         const size_t cnt = (size_t)(cols * ldl), fb = lift_frag_bytes(n);
@@ -1542,9 +1543,11 @@ struct Driver {
         DRV_ST(Rmd.alloc((size_t)G * fb));
         DRV_ST(err.alloc(2));
         DRV_ST(step.alloc(1));
-        DRV_ST(dB.alloc((size_t)L + 1));
-        DRV_ST(dF.alloc((size_t)L + 1));
-        DRV_ST(dY.alloc((size_t)(n * t)));
+        if (tab) {
+            DRV_ST(dB.alloc((size_t)L + 1));
+            DRV_ST(dF.alloc((size_t)L + 1));
+            DRV_ST(dY.alloc((size_t)(n * t)));
+        }
         std::vector<uint32_t> Jm(cnt);
         for (size_t e = 0; e < cnt; ++e) {
             const int64_t v = J[e] % (int64_t)p;
@@ -1552,9 +1555,12 @@ struct Driver {
         }
         DRV_HIP(hipMemcpyAsync(R0.p, J.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice, stream));
         DRV_HIP(hipMemcpyAsync(Rm0.p, Jm.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice, stream));
-        DRV_HIP(hipMemcpyAsync(dB.p, tab.B.data(), sizeof(uint64_t) * ((size_t)L + 1), hipMemcpyHostToDevice, stream));
-        DRV_HIP(hipMemcpyAsync(dF.p, tab.frac.data(), sizeof(uint64_t) * ((size_t)L + 1), hipMemcpyHostToDevice,
-                               stream));
+        if (tab) {
+            DRV_HIP(hipMemcpyAsync(dB.p, tab->B.data(), sizeof(uint64_t) * ((size_t)L + 1), hipMemcpyHostToDevice,
+                                   stream));
+            DRV_HIP(hipMemcpyAsync(dF.p, tab->frac.data(), sizeof(uint64_t) * ((size_t)L + 1),
+                                   hipMemcpyHostToDevice, stream));
+        }
         DRV_HIP(hipMemsetAsync(err.p, 0, 2 * sizeof(int32_t), stream));
         DRV_HIP(hipMemsetAsync(step.p, 0, sizeof(int64_t), stream));
         for (int64_t g = 0; g < G; ++g)                  // the first step's Rm, per run
@@ -1574,11 +1580,23 @@ struct Driver {
         if (!lift_groups_ok(lb, a_bytes, (int)tc)) return RNS_EINVAL;
         launch_lift_steps(dC.p, dA16.p, a_bytes, n, ldl, (int)tc, p, lb, (int)K, stream);
         DRV_HIP(hipGetLastError());
-        launch_padic_dot(Xh.p, n, ldl, cols, t, lb.grp.xh, L, K, L, dB.p, dF.p, tab.F.s, dY.p, err.p + 1, stream);
-        DRV_HIP(hipGetLastError());
         int32_t herr[2] = {0, 0};
+        if (tab) {
+            launch_padic_dot(Xh.p, n, ldl, cols, t, lb.grp.xh, L, K, L, dB.p, dF.p, tab->F.s, dY.p, err.p + 1,
+                             stream);
+            DRV_HIP(hipGetLastError());
+            DRV_HIP(hipMemcpyAsync(Y->data(), dY.p, sizeof(uint64_t) * (size_t)(n * t), hipMemcpyDeviceToHost,
+                                   stream));
+        } else {
+            // plane l (step K - L + l) of every run: G blocks of 16 ldl words
+            dig->assign((size_t)L * cnt, 0u);
+            const size_t blk = sizeof(uint32_t) * (size_t)(tc * ldl);
+            for (int l = 0; l < L; ++l)
+                DRV_HIP(hipMemcpy2DAsync(dig->data() + (size_t)l * cnt, blk,
+                                         Xh.p + (size_t)(((K - L + l) % L) * tc * ldl), sizeof(uint32_t) * lb.grp.xh,
+                                         blk, (size_t)G, hipMemcpyDeviceToHost, stream));
+        }
         DRV_HIP(hipMemcpyAsync(herr, err.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        DRV_HIP(hipMemcpyAsync(Y.data(), dY.p, sizeof(uint64_t) * (size_t)(n * t), hipMemcpyDeviceToHost, stream));
         DRV_ST(sync());
         if (herr[0]) return RNS_EDEVICE;                 // an inexact division: C is not A^-1 mod p
         if (herr[1]) return RNS_EBOUND;                  // s_n A^-1 J is not integral
@@ -1632,28 +1650,37 @@ struct Driver {
         // With a word modulus and the matrix-core step kernels, the full runs
         // of 16 columns are lifted in one grouped run and their Y computed on
         // the GPU; the rest goes through the lanes and the host table.
+        // Host evaluation of columns c0 .. c0 + tr - 1 from their digits
+        // ([L][tr][ldl]), in blocks of rows of one column (the digit planes
+        // are read in order).
+        auto host_eval = [&](const std::vector<uint32_t> &dig, int64_t c0, int64_t tr) {
+            const int64_t rb = std::is_same<Ring, msg::Ring64>::value ? 1024 : 256;
+            const int64_t nrb = (n + rb - 1) / rb;
+            par(tr * nrb, (double)rb * L * FM.cost() / 4.0, [&](int64_t q) {
+                const int64_t c = q / nrb, i0 = (q % nrb) * rb, cnt = std::min(rb, n - i0);
+                if (!tab.eval_block(dig.data() + (size_t)c * ldl + i0, tr * ldl, cnt,
+                                    Y.data() + (size_t)(i0 * t + c0 + c), t))
+                    ok = false;
+            });
+        };
         int64_t tg = 0;
-        if constexpr (std::is_same<Ring, msg::Ring64>::value) {
-            const int64_t G = t / kLiftMaxCols;
-            if (G >= 2 && mfma_lift() && a_bytes == 2) {
-                DRV_ST(lift_dot_grouped(pidx, J, t, G, K, L, tab, Y));
-                tg = G * kLiftMaxCols;
+        const int64_t G = t / kLiftMaxCols;
+        if (G >= 2 && mfma_lift() && a_bytes == 2) {
+            if constexpr (std::is_same<Ring, msg::Ring64>::value) {
+                DRV_ST(lift_grouped(pidx, J, t, G, K, L, &tab, &Y, nullptr));
+            } else {
+                std::vector<uint32_t> dig;
+                DRV_ST(lift_grouped(pidx, J, t, G, K, L, nullptr, nullptr, &dig));
+                host_eval(dig, 0, G * kLiftMaxCols);
             }
+            tg = G * kLiftMaxCols;
         }
         if (tg < t) {
             const int64_t tr = t - tg;
             const std::vector<int64_t> Jr(J.begin() + (size_t)(tg * ldl), J.end());
             std::vector<uint32_t> dig;
             DRV_ST(lift_top(pidx, Jr, tr, K, L, dig));
-            // Blocks of rows of one column: the digit planes are read in order.
-            const int64_t rb = std::is_same<Ring, msg::Ring64>::value ? 1024 : 256;
-            const int64_t nrb = (n + rb - 1) / rb;
-            par(tr * nrb, (double)rb * L * FM.cost() / 4.0, [&](int64_t q) {
-                const int64_t c = q / nrb, i0 = (q % nrb) * rb, cnt = std::min(rb, n - i0);
-                if (!tab.eval_block(dig.data() + (size_t)c * ldl + i0, tr * ldl, cnt,
-                                    Y.data() + (size_t)(i0 * t + tg + c), t))
-                    ok = false;
-            });
+            host_eval(dig, tg, tr);
         }
         if (!ok) return RNS_EBOUND;
         // Earlier batches, oldest first: Y <- Y + M_b (U_b Y) (mod M').
@@ -1716,7 +1743,10 @@ struct Driver {
         using V = typename Ring::V;
         const msg::ParFor par = host_par();
         std::vector<V> W(P1.size());
-        for (size_t e = 0; e < P1.size(); ++e) W[e] = F.from(P1[e]);
+        par((int64_t)P1.size(), 2.0, [&](int64_t e) {           // entries of P_1 are already in [0, s)
+            if constexpr (std::is_same<Ring, msg::Ring64>::value) W[(size_t)e] = P1[(size_t)e].to_u64_mag();
+            else W[(size_t)e] = P1[(size_t)e];
+        });
         const msg::SnfT<Ring> S = msg::snf_transform(F, W, n, t, par);
         int64_t nontriv = 0;
         while (nontriv < t && !(F.big(S.d[(size_t)nontriv]) == s)) ++nontriv;
@@ -1728,11 +1758,35 @@ struct Driver {
         b.M.assign((size_t)(take * n), BigInt(0));
         b.U.assign((size_t)(take * n), BigInt(0));
         for (int64_t j = 0; j < take; ++j) b.S[(size_t)(take - 1 - j)] = s / F.big(S.d[(size_t)j]);
+        // Word rings: sums of products in 128 bits, reduced once per `run`
+        // products (each below s^2 < 2^124).
+        int64_t run = 1;
+        if constexpr (std::is_same<Ring, msg::Ring64>::value) {
+            const unsigned __int128 sq = (unsigned __int128)F.s * F.s;
+            run = (int64_t)std::min<unsigned __int128>((~(unsigned __int128)0) / (sq ? sq : 1), (unsigned __int128)1 << 30);
+        }
         par(n, (double)take * t * F.cost(), [&](int64_t i) {
             for (int64_t j = 0; j < take; ++j) {
                 V acc = F.zero();
-                for (int64_t k = 0; k < t; ++k)
-                    acc = F.add(acc, F.mul(W[(size_t)(i * t + k)], S.R[(size_t)(k * t + j)]));
+                if constexpr (std::is_same<Ring, msg::Ring64>::value) {
+                    unsigned __int128 a128 = 0;
+                    int64_t cnt = 0;
+                    for (int64_t k = 0; k < t; ++k) {
+                        a128 += (unsigned __int128)W[(size_t)(i * t + k)] * S.R[(size_t)(k * t + j)];
+                        if (++cnt == run) {
+                            a128 %= F.s;
+                            cnt = 1;
+                        }
+                    }
+                    acc = (V)(a128 % F.s);
+                } else {
+                    BigInt sum(0);                           // one reduction per entry
+                    for (int64_t k = 0; k < t; ++k) {
+                        const V &w = W[(size_t)(i * t + k)], &rr = S.R[(size_t)(k * t + j)];
+                        if (!F.is_zero(w) && !F.is_zero(rr)) sum = sum + F.big(w) * F.big(rr);
+                    }
+                    acc = F.from(sum);
+                }
                 // (P_1 R)_j = d_j L_j (mod s): the column of L, reduced mod s / d_j
                 const int64_t a = take - 1 - j;
                 const BigInt d = F.big(S.d[(size_t)j]);
@@ -1749,7 +1803,10 @@ struct Driver {
         BigInt s = sn;
         double pbits = 0;                                // log2 of the product found, from below
         for (;;) {
-            const bool fin = s.bit_length() <= 62;
+            // The last batch takes every remaining invariant; it needs s and the
+            // projection's modulus M' (reading 21) to fit a machine word.
+            const bool word = s.bit_length() <= 62;
+            const bool fin = word && (sn / coprime_part(sn, s)).bit_length() <= 62;
             const int64_t room = n - m;
             // Every invariant still to come is >= 2 and their product is at
             // most H / (product found).
@@ -1760,7 +1817,7 @@ struct Driver {
             DRV_ST(projection(pidx, sn, s, B, t, rng, P1));
             MBatch b;
             bool done = false;
-            if (fin) batch_from(msg::Ring64(s.to_u64_mag()), P1, t, s, kExtra, true, b, &done);
+            if (word) batch_from(msg::Ring64(s.to_u64_mag()), P1, t, s, kExtra, fin, b, &done);
             else batch_from(msg::RingBig(s), P1, t, s, kExtra, false, b, &done);
             const int64_t take = (int64_t)b.S.size();
             for (const BigInt &o : b.S) pbits += (double)o.bit_length() - 1.0;
@@ -1768,10 +1825,10 @@ struct Driver {
             B.push_back(std::move(b));
             st.batches += 1;
             if (done || m >= n || take == 0) return RNS_OK;
-            const size_t prev_bits = s.bit_length();
             s = B.back().S.front();                      // the smallest invariant just found
-            const double shrink = (double)prev_bits / (double)std::max<size_t>(1, s.bit_length());
-            r = std::min<int64_t>(n - m, (int64_t)std::ceil(std::max(2.0, shrink) * (double)std::max(r, take)));
+            // While s is multiword the batches double (Section 2.2's schedule);
+            // once s fits a word the next batch takes every remaining invariant.
+            r = std::min<int64_t>(n - m, 2 * std::max(r, take));
         }
     }
 
@@ -1788,10 +1845,14 @@ struct Driver {
         int64_t q = n - m;
         for (int bi = (int)B.size() - 1; bi >= 0; --bi)
             for (int64_t a = 0; a < (int64_t)B[(size_t)bi].S.size(); ++a) pos[(size_t)q++] = Pos{bi, a};
-        auto words = [](const BigInt &x) { return (int)std::max<size_t>(1, x.mag_words().size()); };
+        auto words = [](const BigInt &x) { return (int)std::max<size_t>(1, (x.mag.size() + 1) / 2); };
         auto put = [](std::vector<uint64_t> &dst, int64_t k, int W, const BigInt &x) {
-            const std::vector<uint64_t> w = x.mag_words();
-            for (size_t i = 0; i < w.size() && (int)i < W; ++i) dst[(size_t)k * W + i] = w[i];
+            const size_t nl = x.mag.size();
+            for (int i = 0; i < W && (size_t)(2 * i) < nl; ++i) {
+                const uint64_t lo = x.mag[(size_t)(2 * i)];
+                const uint64_t hi = (size_t)(2 * i + 1) < nl ? x.mag[(size_t)(2 * i + 1)] : 0;
+                dst[(size_t)k * W + i] = lo | (hi << 32);
+            }
         };
         res->massager = true;
         res->s.assign((size_t)n, BigInt(1).mag_words());
