@@ -551,5 +551,96 @@ struct PadicTable {
     }
 };
 
+// Prime factorisation of a word n < 2^63 (the modulus of a word-size batch,
+// split into prime powers for the local Smith forms): trial division by the
+// primes below 2^10, then Miller-Rabin with the first twelve prime bases
+// (deterministic below 2^64) and Pollard's rho with Brent's cycle search.
+inline uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+inline uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    a %= m;
+    for (; e; e >>= 1) {
+        if (e & 1) r = mulmod64(r, a, m);
+        a = mulmod64(a, a, m);
+    }
+    return r;
+}
+inline bool is_prime64(uint64_t n) {
+    if (n < 2) return false;
+    static const uint64_t small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t q : small)
+        if (n % q == 0) return n == q;
+    uint64_t d = n - 1;
+    int r = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++r;
+    }
+    for (uint64_t a : small) {
+        uint64_t x = powmod64(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < r && comp; ++i) {
+            x = mulmod64(x, x, n);
+            if (x == n - 1) comp = false;
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+// A nontrivial factor of an odd composite n (Brent's variant, batched gcds).
+inline uint64_t rho64(uint64_t n) {
+    for (uint64_t c = 1;; ++c) {
+        auto f = [&](uint64_t x) { return (mulmod64(x, x, n) + c) % n; };
+        uint64_t y = 2, g = 1, q = 1, x = 0, ys = 0;
+        const uint64_t m = 128;
+        for (uint64_t r = 1; g == 1; r <<= 1) {
+            x = y;
+            for (uint64_t i = 0; i < r; ++i) y = f(y);
+            for (uint64_t k = 0; k < r && g == 1; k += m) {
+                ys = y;
+                for (uint64_t i = 0; i < std::min(m, r - k); ++i) {
+                    y = f(y);
+                    q = mulmod64(q, x > y ? x - y : y - x, n);
+                }
+                g = Ring64::gcd(q, n);
+            }
+        }
+        if (g == n) {
+            do {
+                ys = f(ys);
+                g = Ring64::gcd(x > ys ? x - ys : ys - x, n);
+            } while (g == 1);
+        }
+        if (g != n) return g;
+    }
+}
+inline void factor_rec(uint64_t n, std::vector<uint64_t> &out) {
+    if (n == 1) return;
+    if (is_prime64(n)) {
+        out.push_back(n);
+        return;
+    }
+    const uint64_t d = rho64(n);
+    factor_rec(d, out);
+    factor_rec(n / d, out);
+}
+inline std::vector<std::pair<uint64_t, int>> factor64(uint64_t n) {
+    std::vector<uint64_t> ps;
+    for (uint64_t q = 2; q < 1024 && q * q <= n; ++q)
+        while (n % q == 0) {
+            ps.push_back(q);
+            n /= q;
+        }
+    factor_rec(n, ps);
+    std::sort(ps.begin(), ps.end());
+    std::vector<std::pair<uint64_t, int>> out;
+    for (uint64_t q : ps) {
+        if (!out.empty() && out.back().first == q) ++out.back().second;
+        else out.push_back({q, 1});
+    }
+    return out;
+}
+
 }  // namespace msg
 }  // namespace rns

@@ -1796,6 +1796,161 @@ struct Driver {
         });
     }
 
+    // One batch for a word modulus s on the GPU: local Smith forms with
+    // transforms over every prime power of s (massager_kernels.hip), then on
+    // host threads the planes combined by the CRT: the orders s / d_j, M_j =
+    // (P_1 R)_j / d_j and U_j = -(row j of E) (the same batch as batch_from).
+    int gpu_batch(const std::vector<BigInt> &P1, int64_t t, const BigInt &s, int64_t extra, bool fin, MBatch &b,
+                  bool *done) {
+        const uint64_t s64 = s.to_u64_mag();
+        if (n >= (1 << 21) || t >= (1 << 21)) return RNS_ENOTSUP;
+        const auto fac = msg::factor64(s64);
+        const int F = (int)fac.size();
+        std::vector<LsnfPlane> pl((size_t)F);
+        for (int f = 0; f < F; ++f) {
+            LsnfPlane &P0 = pl[(size_t)f];
+            P0.q = fac[(size_t)f].first;
+            P0.e = fac[(size_t)f].second;
+            P0.m = 1;
+            for (int i = 0; i < P0.e; ++i) P0.m *= P0.q;
+            P0.pow2 = P0.q == 2;
+            P0.qinv = P0.qmax = P0.minv = 0;
+            P0.r2 = P0.rinv = 1;
+            if (!P0.pow2) {
+                uint64_t x = P0.q;                        // Newton: q^-1 mod 2^64
+                for (int i = 0; i < 6; ++i) x *= 2 - P0.q * x;
+                P0.qinv = x;
+                P0.qmax = ~0ull / P0.q;
+                uint64_t y = P0.m;
+                for (int i = 0; i < 6; ++i) y *= 2 - P0.m * y;
+                P0.minv = (uint64_t)0 - y;
+                const uint64_t r = (uint64_t)(((unsigned __int128)1 << 64) % P0.m);
+                P0.r2 = (uint64_t)((unsigned __int128)r * r % P0.m);
+                P0.rinv = msg::Ring64::inv(r, P0.m);
+            }
+        }
+        const int64_t nt = n * t;
+        DevBuf<uint64_t> dP, W, Pf, E, R, units, out;
+        DevBuf<int32_t> vals;
+        DevBuf<LsnfStep> dst;
+        DevBuf<LsnfPlane> dpl;
+        DRV_ST(dP.alloc((size_t)nt));
+        DRV_ST(W.alloc((size_t)F * nt));
+        DRV_ST(Pf.alloc((size_t)F * nt));
+        DRV_ST(E.alloc((size_t)F * n * n));
+        DRV_ST(R.alloc((size_t)F * t * t));
+        DRV_ST(units.alloc((size_t)F * t));
+        DRV_ST(vals.alloc((size_t)F * t));
+        DRV_ST(dst.alloc((size_t)F));
+        DRV_ST(dpl.alloc((size_t)F));
+        std::vector<uint64_t> P64((size_t)nt);
+        const msg::ParFor par = host_par();
+        par(nt, 2.0, [&](int64_t e) { P64[(size_t)e] = P1[(size_t)e].to_u64_mag(); });
+        DRV_HIP(hipMemcpyAsync(dP.p, P64.data(), sizeof(uint64_t) * (size_t)nt, hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(dpl.p, pl.data(), sizeof(LsnfPlane) * (size_t)F, hipMemcpyHostToDevice, stream));
+        launch_ls_load(dP.p, n, t, dpl.p, F, W.p, Pf.p, E.p, R.p, dst.p, stream);
+        DRV_HIP(hipGetLastError());
+        const int64_t steps = std::min(n, t);
+        std::vector<LsnfStep> hst((size_t)F);
+        int64_t c = 0;
+        for (; c < steps; ++c) {
+            launch_ls_step(W.p, E.p, R.p, n, t, c, dpl.p, F, dst.p, vals.p, units.p, stream);
+            DRV_HIP(hipGetLastError());
+            if ((c & 63) == 63) {                        // every plane finished: the rest is zero
+                DRV_HIP(hipMemcpyAsync(hst.data(), dst.p, sizeof(LsnfStep) * (size_t)F, hipMemcpyDeviceToHost,
+                                       stream));
+                DRV_ST(sync());
+                bool all = true;
+                for (const LsnfStep &x : hst) all = all && x.done;
+                if (all) {
+                    ++c;
+                    break;
+                }
+            }
+        }
+        std::vector<int32_t> hv((size_t)F * t);
+        std::vector<uint64_t> hu((size_t)F * t);
+        DRV_HIP(hipMemcpyAsync(hv.data(), vals.p, sizeof(int32_t) * hv.size(), hipMemcpyDeviceToHost, stream));
+        DRV_HIP(hipMemcpyAsync(hu.data(), units.p, sizeof(uint64_t) * hu.size(), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        // Steps not run (every plane already finished) have valuation e.
+        auto val = [&](int f, int64_t j) { return j < c ? hv[(size_t)(f * t + j)] : pl[(size_t)f].e; };
+        std::vector<uint64_t> ord((size_t)t, 1);
+        for (int64_t j = 0; j < t; ++j)
+            for (int f = 0; f < F; ++f)
+                for (int i = val(f, j); i < pl[(size_t)f].e; ++i) ord[(size_t)j] *= pl[(size_t)f].q;
+        int64_t nontriv = 0;
+        while (nontriv < t && ord[(size_t)nontriv] > 1) ++nontriv;
+        *done = fin || nontriv <= t - extra;
+        const int64_t take = *done ? nontriv : t - extra;
+        b.s = s;
+        b.S.assign((size_t)take, BigInt(0));
+        b.M.assign((size_t)(take * n), BigInt(0));
+        b.U.assign((size_t)(take * n), BigInt(0));
+        if (take == 0) return RNS_OK;
+        DRV_ST(out.alloc((size_t)F * n * take));
+        launch_ls_plain(E.p, n, take, dpl.p, F, stream);
+        launch_ls_pr(Pf.p, R.p, n, t, take, dpl.p, F, out.p, stream);
+        DRV_HIP(hipGetLastError());
+        std::vector<uint64_t> hE((size_t)F * take * n), hPR((size_t)F * n * take);
+        for (int f = 0; f < F; ++f)
+            DRV_HIP(hipMemcpyAsync(hE.data() + (size_t)f * take * n, E.p + (size_t)f * n * n,
+                                   sizeof(uint64_t) * (size_t)(take * n), hipMemcpyDeviceToHost, stream));
+        DRV_HIP(hipMemcpyAsync(hPR.data(), out.p, sizeof(uint64_t) * hPR.size(), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        // Per position j: the modulus of plane f for M (q^(e - v)), the inverse
+        // of its unit part there, and q^v.
+        std::vector<uint64_t> mm((size_t)F * take), qv((size_t)F * take), ui((size_t)F * take);
+        for (int64_t j = 0; j < take; ++j) {
+            b.S[(size_t)(take - 1 - j)] = BigInt::from_u64(ord[(size_t)j]);
+            for (int f = 0; f < F; ++f) {
+                const LsnfPlane &P0 = pl[(size_t)f];
+                const int v = val(f, j);
+                uint64_t a = 1, bq = 1;
+                for (int i = 0; i < v; ++i) bq *= P0.q;
+                for (int i = v; i < P0.e; ++i) a *= P0.q;
+                const size_t k = (size_t)(f * take + j);
+                mm[k] = a;
+                qv[k] = bq;
+                ui[k] = a > 1 ? msg::Ring64::inv(hu[(size_t)(f * t + j)] % a, a) : 0;
+            }
+        }
+        // CRT over the planes (moduli coprime, product below 2^62).
+        auto crt = [&](const uint64_t *res, const uint64_t *mod, int cnt) -> uint64_t {
+            uint64_t x = 0, M = 1;
+            for (int f = 0; f < cnt; ++f) {
+                if (mod[f] == 1) continue;
+                const uint64_t xm = x % mod[f];
+                const uint64_t d = (res[f] + mod[f] - xm) % mod[f];
+                const uint64_t k = msg::Ring64::mulm(d, msg::Ring64::inv(M % mod[f], mod[f]), mod[f]);
+                x += M * k;
+                M *= mod[f];
+            }
+            return x;
+        };
+        std::vector<uint64_t> mplane((size_t)F);
+        for (int f = 0; f < F; ++f) mplane[(size_t)f] = pl[(size_t)f].m;
+        par(n, (double)take * F * 8.0, [&](int64_t i) {
+            std::vector<uint64_t> r((size_t)F), md((size_t)F);
+            for (int64_t j = 0; j < take; ++j) {
+                const int64_t a = take - 1 - j;
+                for (int f = 0; f < F; ++f) {
+                    const size_t k = (size_t)(f * take + j);
+                    md[(size_t)f] = mm[k];
+                    const uint64_t pr = hPR[(size_t)((f * n + i) * take + j)];
+                    r[(size_t)f] = mm[k] > 1 ? msg::Ring64::mulm((pr / qv[k]) % mm[k], ui[k], mm[k]) : 0;
+                }
+                b.M[(size_t)(a * n + i)] = BigInt::from_u64(crt(r.data(), md.data(), F));
+                for (int f = 0; f < F; ++f) {
+                    const uint64_t e = hE[(size_t)((f * take + j) * n + i)];
+                    r[(size_t)f] = e ? mplane[(size_t)f] - e : 0;
+                }
+                b.U[(size_t)(a * n + i)] = BigInt::from_u64(crt(r.data(), mplane.data(), F));
+            }
+        });
+        return RNS_OK;
+    }
+
     int massager_phase2(int pidx, const BigInt &sn, SplitMix &rng, std::vector<MBatch> &B) {
         constexpr int64_t kExtra = 8;                    // projection columns beyond the batch
         B.clear();
@@ -1817,8 +1972,11 @@ struct Driver {
             DRV_ST(projection(pidx, sn, s, B, t, rng, P1));
             MBatch b;
             bool done = false;
-            if (word) batch_from(msg::Ring64(s.to_u64_mag()), P1, t, s, kExtra, fin, b, &done);
-            else batch_from(msg::RingBig(s), P1, t, s, kExtra, false, b, &done);
+            if (word) {
+                DRV_ST(gpu_batch(P1, t, s, kExtra, fin, b, &done));
+            } else {
+                batch_from(msg::RingBig(s), P1, t, s, kExtra, false, b, &done);
+            }
             const int64_t take = (int64_t)b.S.size();
             for (const BigInt &o : b.S) pbits += (double)o.bit_length() - 1.0;
             m += take;

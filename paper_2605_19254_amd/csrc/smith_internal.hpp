@@ -65,6 +65,37 @@ struct LiftBufs {
     char *Rmd = nullptr;        // lift_frag_bytes(n)); used when Ct and At are both set
     LiftGroups grp{};
 };
+// One prime power m = q^e < 2^62 of a local Smith form with transforms
+// (massager_kernels.hip): constants for exact division by q and for
+// Montgomery products (odd m; a power of two is reduced by masking).
+struct LsnfPlane {
+    uint64_t m, q;
+    uint64_t qinv, qmax;       // odd q: q^-1 mod 2^64, floor((2^64 - 1) / q)
+    uint64_t minv, r2, rinv;   // odd m: -m^-1 mod 2^64, 2^128 mod m, 2^-64 mod m (1, 1, 1 for 2^e)
+    int e, pow2;
+};
+// The current pivot of a plane: the minimal key (v << 42 | row << 21 |
+// column), its valuation, q^v, m / q^v, the inverse of the pivot's unit part
+// modulo m / q^v; done once every remaining entry is zero.
+struct LsnfStep {
+    uint64_t key;
+    int v, done;
+    uint64_t qv, mq, uinv;
+};
+// P (n x t, entries below s) into the F planes W_f (Montgomery form), Pf
+// (plain), E_f = I (n x n) and R_f = I (t x t); n, t < 2^21.
+void launch_ls_load(const uint64_t *P, int64_t n, int64_t t, const LsnfPlane *pl, int F, uint64_t *W, uint64_t *Pf,
+                    uint64_t *E, uint64_t *R, LsnfStep *st, hipStream_t s);
+// Step c of every plane: pivot search, exchanges, pivot record (vals[f][c],
+// units[f][c]), row and column elimination with E_f and R_f.
+void launch_ls_step(uint64_t *W, uint64_t *E, uint64_t *R, int64_t n, int64_t t, int64_t c, const LsnfPlane *pl,
+                    int F, LsnfStep *st, int32_t *vals, uint64_t *units, hipStream_t s);
+// out[f][i][j] = (Pf_f R_f)[i][j] mod m_f, plain, for j < take.
+void launch_ls_pr(const uint64_t *Pf, const uint64_t *R, int64_t n, int64_t t, int64_t take, const LsnfPlane *pl,
+                  int F, uint64_t *out, hipStream_t s);
+// Rows 0 .. rows-1 of every E_f to plain form.
+void launch_ls_plain(uint64_t *E, int64_t n, int64_t rows, const LsnfPlane *pl, int F, hipStream_t s);
+
 // Rem(s_n x, m) (m < 2^62) for the first `cols` lifted vectors (groups of
 // 16) from their top L digits: B[l] = -a_l p^K mod m, F[l] =
 // floor(frac(s_n / p^l) 2^64), B[0] = -p^K mod m, as msg::PadicTable; the

@@ -281,6 +281,42 @@ int main() {
             CHECK(!TB.eval(dig.data() + (K - L), 1, out), "padic table accepted a non-integer at %d", it);
         }
     }
+    // Word factorisation: the product of the prime powers gives n back, every
+    // factor passes trial division (below 2^32) or is checked against a known
+    // prime; semiprimes of two 31-bit primes and prime powers included.
+    {
+        auto tdiv_prime = [](uint64_t q) {
+            if (q < 2) return false;
+            for (uint64_t d = 2; d * d <= q; ++d)
+                if (q % d == 0) return false;
+            return true;
+        };
+        const uint64_t cases[] = {1, 2, 97, 1ull << 61, 3486784401ull /* 3^20 */, 2147483647ull * 2147483629ull,
+                                  2305843009213693951ull /* 2^61 - 1 */, 999999937ull * 999999929ull,
+                                  (1ull << 8) * 27 * 5 * 49 * 13 * 19, 614889782588491410ull};
+        for (uint64_t nv : cases) {
+            const auto f = factor64(nv);
+            unsigned __int128 prod = 1;
+            for (auto &pe : f) {
+                for (int e = 0; e < pe.second; ++e) prod *= pe.first;
+                const bool ok = pe.first < (1ull << 32) ? tdiv_prime(pe.first)
+                                                        : (pe.first == 2305843009213693951ull);
+                CHECK(ok, "factor64(%llu): %llu is not prime", (unsigned long long)nv, (unsigned long long)pe.first);
+            }
+            CHECK(prod == nv, "factor64(%llu): product differs", (unsigned long long)nv);
+        }
+        for (int it = 0; it < 200; ++it) {
+            const uint64_t nv = (g() >> 2) | 1;
+            const auto f = factor64(nv);
+            unsigned __int128 prod = 1;
+            for (auto &pe : f) {
+                for (int e = 0; e < pe.second; ++e) prod *= pe.first;
+                if (pe.first < (1ull << 32)) CHECK(tdiv_prime(pe.first), "random factor not prime");
+                else CHECK(is_prime64(pe.first), "random large factor not prime");
+            }
+            CHECK(prod == nv, "random factor64 product differs");
+        }
+    }
     printf("bad=%d\n", bad);
     return bad != 0;
 }
