@@ -640,40 +640,51 @@ MASSAGER_U, MASSAGER_M, MASSAGER_T = 0, 1, 2
 @dataclass
 class MassagerResult:
     """S (list of ints) and the Smith massager U (rows), M and T (columns) as
-    n x n object arrays of Python ints (rns_smith_massager)."""
+    n x n object arrays of Python ints (rns_smith_massager); a matrix not
+    asked for is None, and m_columns holds the columns of M asked for alone."""
     s: List[int]
-    U: np.ndarray
-    M: np.ndarray
-    T: np.ndarray
+    U: Optional[np.ndarray]
+    M: Optional[np.ndarray]
+    T: Optional[np.ndarray]
     stats: dict
+    m_columns: Optional[dict] = None
 
 
-def smith_massager(ctx: Context, a: np.ndarray, seed: int = 0) -> MassagerResult:
+def _massager_vector(h, which, idx, n):
+    w = _lib_massager_width(h, which, idx)
+    if w < 1:
+        raise RnsError(-w, "rns_smith_massager_width")
+    buf = np.zeros(n * w, dtype=np.uint64)
+    _check(_lib_massager_vector(h, which, idx, buf.ctypes.data, w), "rns_smith_massager_vector")
+    return words_to_uints(buf.reshape(n, w))
+
+
+def smith_massager(ctx: Context, a: np.ndarray, seed: int = 0, fetch=("U", "M", "T"),
+                   m_columns=None) -> MassagerResult:
     a = np.ascontiguousarray(a, dtype=np.int64)
     n = a.shape[0]
     assert a.shape == (n, n)
     h = _P()
     _check(_lib_massager(ctx.handle, a.ctypes.data, n, seed, ctypes.byref(h)), "rns_smith_massager")
     try:
-        mats = []
-        for which in (MASSAGER_U, MASSAGER_M, MASSAGER_T):
+        mats = {}
+        for name, which in (("U", MASSAGER_U), ("M", MASSAGER_M), ("T", MASSAGER_T)):
+            if name not in fetch:
+                mats[name] = None
+                continue
             out = np.empty((n, n), dtype=object)
             for idx in range(n):
-                w = _lib_massager_width(h, which, idx)
-                if w < 1:
-                    raise RnsError(-w, "rns_smith_massager_width")
-                buf = np.zeros(n * w, dtype=np.uint64)
-                _check(_lib_massager_vector(h, which, idx, buf.ctypes.data, w), "rns_smith_massager_vector")
-                vals = words_to_uints(buf.reshape(n, w))
+                vals = _massager_vector(h, which, idx, n)
                 if which == MASSAGER_U:
                     out[idx, :] = vals
                 else:
                     out[:, idx] = vals
-            mats.append(out)
+            mats[name] = out
+        cols = {j: _massager_vector(h, MASSAGER_M, j, n) for j in (m_columns or [])}
         res = _smith_result_keep(h)
     finally:
         _lib_smith_free(h)
-    return MassagerResult(res.s, mats[0], mats[1], mats[2], res.stats)
+    return MassagerResult(res.s, mats["U"], mats["M"], mats["T"], res.stats, cols)
 
 
 def words_to_uints(w: np.ndarray) -> np.ndarray:

@@ -348,8 +348,10 @@ SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t
         for (int64_t i = c + 1; i < n; ++i)
             if (!F.is_zero(at(i, c))) rows.push_back(i);
         std::vector<V> fs(rows.size());
+        const bool unit = F.is_one(g);                   // then f = -b a^-1 (no division by g)
         par((int64_t)rows.size(), F.cost(), [&](int64_t k) {
-            fs[(size_t)k] = F.neg(F.quot_by(at(rows[(size_t)k], c), g, ainv));
+            const V &b = at(rows[(size_t)k], c);
+            fs[(size_t)k] = F.neg(unit ? F.mul(b, ainv) : F.quot_by(b, g, ainv));
         });
         par((int64_t)rows.size(), (double)(t - c) * F.cost(), [&](int64_t k) {
             const int64_t i = rows[(size_t)k];
@@ -366,7 +368,7 @@ SnfT<Ring> snf_transform(const Ring &F, std::vector<typename Ring::V> W, int64_t
         for (int64_t j = c + 1; j < t; ++j) {
             if (F.is_zero(at(c, j))) continue;
             cols.push_back(j);
-            gs.push_back(F.neg(F.quot_by(at(c, j), g, ainv)));
+            gs.push_back(F.neg(unit ? F.mul(at(c, j), ainv) : F.quot_by(at(c, j), g, ainv)));
             at(c, j) = F.zero();
         }
         if (!cols.empty())

@@ -1512,17 +1512,21 @@ struct Driver {
     }
 
     // The first G runs of kLiftMaxCols columns of J ([t][ldl], host) lifted
-    // together (one launch per product and step, blockIdx.y = run; only the
-    // top L digit slots kept, step i in slot i % L).  With a word table `tab`
-    // (modulus m < 2^62), Y[i t + c] = Rem(s_n x, m) for those columns is
-    // computed on the GPU from the digits (Y's other columns are left for the
-    // caller); without one, the digits come back as dig ([L][G 16][ldl],
-    // l = 0 the digit of step K - L).
+    // together (one launch per product and step, blockIdx.y = run; step i's
+    // digits in ring slot i % ring).  With a word table `tab` (modulus
+    // m < 2^62), Y[i t + c] = Rem(s_n x, m) for those columns is computed on
+    // the GPU: after the first K - L steps, the top L digits are folded into
+    // per-entry sums kKeep steps at a time, so the ring holds kKeep slots (Y's
+    // other columns are left for the caller); without one, the ring holds the
+    // top L steps and the digits come back as dig ([L][G 16][ldl], l = 0 the
+    // digit of step K - L).
     int lift_grouped(int pidx, const std::vector<int64_t> &J, int64_t t, int64_t G, int64_t K, int L,
                      const msg::PadicTable<msg::Ring64> *tab, std::vector<uint64_t> *Y, std::vector<uint32_t> *dig) {
+        constexpr int kKeep = 128;
         const uint32_t p = aux->primes[pidx];
         const int64_t tc = kLiftMaxCols, cols = G * tc;
         const size_t cnt = (size_t)(cols * ldl), fb = lift_frag_bytes(n);
+        const int64_t ring = tab ? std::min<int64_t>(L, kKeep) : L;
         DRV_ST(dCt.alloc(lift_tile_c_bytes(n)));
         launch_lift_tile_c(dC.p, n, ldl, p, dCt.p, stream);
         DRV_HIP(hipGetLastError());
@@ -1533,12 +1537,12 @@ struct Driver {
         DevBuf<uint32_t> Rm0, Rm1, Xh;
         DevBuf<char> Xd, Rmd;
         DevBuf<int32_t> err;
-        DevBuf<uint64_t> dB, dF, dY;
+        DevBuf<uint64_t> dB, dF, dY, dacc;
         DRV_ST(R0.alloc(cnt));
         DRV_ST(R1.alloc(cnt));
         DRV_ST(Rm0.alloc(cnt));
         DRV_ST(Rm1.alloc(cnt));
-        DRV_ST(Xh.alloc((size_t)(G * L * tc * ldl)));
+        DRV_ST(Xh.alloc((size_t)(G * ring * tc * ldl)));
         DRV_ST(Xd.alloc((size_t)G * fb));
         DRV_ST(Rmd.alloc((size_t)G * fb));
         DRV_ST(err.alloc(2));
@@ -1547,6 +1551,7 @@ struct Driver {
             DRV_ST(dB.alloc((size_t)L + 1));
             DRV_ST(dF.alloc((size_t)L + 1));
             DRV_ST(dY.alloc((size_t)(n * t)));
+            DRV_ST(dacc.alloc((size_t)(4 * cols * n)));
         }
         std::vector<uint32_t> Jm(cnt);
         for (size_t e = 0; e < cnt; ++e) {
@@ -1560,6 +1565,7 @@ struct Driver {
                                    stream));
             DRV_HIP(hipMemcpyAsync(dF.p, tab->frac.data(), sizeof(uint64_t) * ((size_t)L + 1),
                                    hipMemcpyHostToDevice, stream));
+            DRV_HIP(hipMemsetAsync(dacc.p, 0, sizeof(uint64_t) * (size_t)(4 * cols * n), stream));
         }
         DRV_HIP(hipMemsetAsync(err.p, 0, 2 * sizeof(int32_t), stream));
         DRV_HIP(hipMemsetAsync(step.p, 0, sizeof(int64_t), stream));
@@ -1574,20 +1580,28 @@ struct Driver {
         lb.grp.groups = (int)G;
         lb.grp.r = tc * ldl;
         lb.grp.rm = tc * ldl;
-        lb.grp.xh = L * tc * ldl;
+        lb.grp.xh = ring * tc * ldl;
         lb.grp.frag = (int64_t)(fb / 16);                // v4i_l elements
-        lb.grp.ring = L;
+        lb.grp.ring = ring;
         if (!lift_groups_ok(lb, a_bytes, (int)tc)) return RNS_EINVAL;
-        launch_lift_steps(dC.p, dA16.p, a_bytes, n, ldl, (int)tc, p, lb, (int)K, stream);
-        DRV_HIP(hipGetLastError());
         int32_t herr[2] = {0, 0};
         if (tab) {
-            launch_padic_dot(Xh.p, n, ldl, cols, t, lb.grp.xh, L, K, L, dB.p, dF.p, tab->F.s, dY.p, err.p + 1,
-                             stream);
+            // K - L steps whose digits are not needed, then the top L in
+            // chunks of `ring`, each folded into the sums.
+            if (K > L) launch_lift_steps(dC.p, dA16.p, a_bytes, n, ldl, (int)tc, p, lb, (int)(K - L), stream);
+            for (int64_t done = 0; done < L; done += ring) {
+                const int chunk = (int)std::min<int64_t>(ring, L - done);
+                launch_lift_steps(dC.p, dA16.p, a_bytes, n, ldl, (int)tc, p, lb, chunk, stream);
+                launch_padic_acc(Xh.p, n, ldl, cols, lb.grp.xh, ring, K, K - L + done, chunk, dB.p, dF.p, dacc.p,
+                                 stream);
+            }
+            launch_padic_fin(dacc.p, n, cols, t, dB.p, tab->F.s, dY.p, err.p + 1, stream);
             DRV_HIP(hipGetLastError());
             DRV_HIP(hipMemcpyAsync(Y->data(), dY.p, sizeof(uint64_t) * (size_t)(n * t), hipMemcpyDeviceToHost,
                                    stream));
         } else {
+            launch_lift_steps(dC.p, dA16.p, a_bytes, n, ldl, (int)tc, p, lb, (int)K, stream);
+            DRV_HIP(hipGetLastError());
             // plane l (step K - L + l) of every run: G blocks of 16 ldl words
             dig->assign((size_t)L * cnt, 0u);
             const size_t blk = sizeof(uint32_t) * (size_t)(tc * ldl);
@@ -2045,15 +2059,46 @@ struct Driver {
                 put(res->M[(size_t)j], i, wm, b.M[(size_t)(pj.a * n + i)]);
             }
             put(res->T[(size_t)j], j, wm, BigInt(1));
-            // Rows of newer batches: T_ij = -U_i M_j (mod s_j).
+            // Rows of newer batches: T_ij = -U_i M_j (mod s_j).  Rows with
+            // word entries (the later batches) sum u M_jk in a word
+            // accumulator; M_j's words are unpacked once.
+            std::vector<uint64_t> mw((size_t)(n * wm), 0);
+            for (int64_t k = 0; k < n; ++k) put(mw, k, wm, b.M[(size_t)(pj.a * n + k)]);
+            std::vector<uint64_t> accw((size_t)wm + 2);
             for (int64_t i = 0; i < j; ++i) {
                 const Pos pi = pos[(size_t)i];
                 if (pi.b < 0 || pi.b <= pj.b) continue;
                 const MBatch &bn = B[(size_t)pi.b];
                 BigInt acc(0);
-                for (int64_t k = 0; k < n; ++k) {
-                    const BigInt &u = bn.U[(size_t)(pi.a * n + k)];
-                    if (!u.is_zero()) acc = acc + u * b.M[(size_t)(pj.a * n + k)];
+                if (bn.s.bit_length() <= 64) {
+                    std::fill(accw.begin(), accw.end(), 0);
+                    for (int64_t k = 0; k < n; ++k) {
+                        const uint64_t u = bn.U[(size_t)(pi.a * n + k)].to_u64_mag();
+                        if (!u) continue;
+                        unsigned __int128 carry = 0;
+                        const uint64_t *mk = mw.data() + (size_t)(k * wm);
+                        for (int w = 0; w < wm; ++w) {
+                            const unsigned __int128 v = (unsigned __int128)mk[w] * u + accw[(size_t)w] + carry;
+                            accw[(size_t)w] = (uint64_t)v;
+                            carry = v >> 64;
+                        }
+                        for (size_t w = (size_t)wm; carry && w < accw.size(); ++w) {
+                            const unsigned __int128 v = (unsigned __int128)accw[w] + carry;
+                            accw[w] = (uint64_t)v;
+                            carry = v >> 64;
+                        }
+                    }
+                    acc.mag.resize(2 * accw.size());
+                    for (size_t w = 0; w < accw.size(); ++w) {
+                        acc.mag[2 * w] = (uint32_t)accw[w];
+                        acc.mag[2 * w + 1] = (uint32_t)(accw[w] >> 32);
+                    }
+                    while (!acc.mag.empty() && acc.mag.back() == 0) acc.mag.pop_back();
+                } else {
+                    for (int64_t k = 0; k < n; ++k) {
+                        const BigInt &u = bn.U[(size_t)(pi.a * n + k)];
+                        if (!u.is_zero()) acc = acc + u * b.M[(size_t)(pj.a * n + k)];
+                    }
                 }
                 put(res->T[(size_t)j], i, wm, mod(-acc, sj));
             }

@@ -97,14 +97,18 @@ void launch_ls_pr(const uint64_t *Pf, const uint64_t *R, int64_t n, int64_t t, i
 void launch_ls_plain(uint64_t *E, int64_t n, int64_t rows, const LsnfPlane *pl, int F, hipStream_t s);
 
 // Rem(s_n x, m) (m < 2^62) for the first `cols` lifted vectors (groups of
-// 16) from their top L digits: B[l] = -a_l p^K mod m, F[l] =
-// floor(frac(s_n / p^l) 2^64), B[0] = -p^K mod m, as msg::PadicTable; the
-// digit of step K - l of vector c, row i is
-// Xh[(c / 16) xh + ((K - l) % ring) 16 ld + (c % 16) ld + i].  Entry (i, c)
-// goes to Y[i ystride + c]; *bad = 1 where the rounding is not within 2^-21.
-void launch_padic_dot(const uint32_t *Xh, int64_t n, int64_t ld, int64_t cols, int64_t ystride, int64_t xh,
-                      int64_t ring, int64_t K, int L, const uint64_t *B, const uint64_t *F, uint64_t m, uint64_t *Y,
-                      int32_t *bad, hipStream_t s);
+// 16) from their top L digits, in chunks: launch_padic_acc adds the digits of
+// steps step0 .. step0+cnt-1 (the digit of step st of vector c, row i is
+// Xh[(c / 16) xh + (st % ring) 16 ld + (c % 16) ld + i]) into per-entry
+// 128-bit sums sum d_l B_l and sum d_l F_l, l = K - st, with B[l] = -a_l p^K
+// mod m, F[l] = floor(frac(s_n / p^l) 2^64), B[0] = -p^K mod m as
+// msg::PadicTable (acc: [cols][n][4] words, zero at first); launch_padic_fin
+// writes entry (i, c) to Y[i ystride + c] and sets *bad = 1 where the
+// rounding is not within 2^-21.
+void launch_padic_acc(const uint32_t *Xh, int64_t n, int64_t ld, int64_t cols, int64_t xh, int64_t ring, int64_t K,
+                      int64_t step0, int cnt, const uint64_t *B, const uint64_t *F, uint64_t *acc, hipStream_t s);
+void launch_padic_fin(const uint64_t *acc, int64_t n, int64_t cols, int64_t ystride, const uint64_t *B, uint64_t m,
+                      uint64_t *Y, int32_t *bad, hipStream_t s);
 // Largest n whose lifting products run on the matrix cores (int32 sums of
 // the digit products stay exact for k <= 43690).
 constexpr int64_t kLiftMfmaMaxN = 43690;

@@ -1501,42 +1501,70 @@ void launch_lift_steps(const uint32_t *C, const void *A, int a_bytes, int64_t n,
     hipLaunchKernelGGL(k_lift_advance, dim3(1), dim3(64), 0, s, b.base, steps);
 }
 
-// One thread per (row i, vector c): the L-term dot products of reading 21
-// (sum d_l B_l and sum d_l F_l in 128-bit integers), the rounding check and
-// the result modulo m.  The digits of consecutive rows are contiguous.
-__global__ __launch_bounds__(256) void k_padic_dot(const uint32_t *__restrict__ Xh, int64_t n, int64_t ld,
-                                                   int64_t ystride, int64_t xh, int64_t ring, int64_t K, int L,
-                                                   const uint64_t *__restrict__ B, const uint64_t *__restrict__ F,
-                                                   uint64_t m, uint64_t *__restrict__ Y, int32_t *__restrict__ bad) {
+// One thread per (row i, vector c): the digits of steps step0 .. step0+cnt-1
+// (slot step % ring of the vector's run) added into the entry's two 128-bit
+// sums of reading 21, sum d_l B_l and sum d_l F_l with l = K - step (kept as
+// (low, high) word pairs).  Consecutive rows are contiguous.
+__global__ __launch_bounds__(256) void k_padic_acc(const uint32_t *__restrict__ Xh, int64_t n, int64_t ld,
+                                                   int64_t cols, int64_t xh, int64_t ring, int64_t K, int64_t step0,
+                                                   int cnt, const uint64_t *__restrict__ B,
+                                                   const uint64_t *__restrict__ F, uint64_t *__restrict__ acc) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t c = blockIdx.y;
     if (i >= n) return;
     const uint32_t *__restrict__ d0 = Xh + (c / 16) * xh + (c % 16) * ld + i;
     const auto *Bc = cptr(B);
     const auto *Fc = cptr(F);
-    unsigned __int128 acc = 0, fs = 0;
-    for (int l = 1; l <= L; ++l) {
-        const uint64_t d = d0[((K - l) % ring) * 16 * ld];
-        acc += (unsigned __int128)Bc[l] * d;
-        fs += (unsigned __int128)Fc[l] * d;
+    uint64_t *a = acc + 4 * (c * n + i);
+    unsigned __int128 sa = ((unsigned __int128)a[1] << 64) | a[0];
+    unsigned __int128 sf = ((unsigned __int128)a[3] << 64) | a[2];
+    for (int q = 0; q < cnt; ++q) {
+        const int64_t st = step0 + q, l = K - st;
+        const uint64_t d = d0[(st % ring) * 16 * ld];
+        sa += (unsigned __int128)Bc[l] * d;
+        sf += (unsigned __int128)Fc[l] * d;
     }
-    const uint64_t e = (uint64_t)((fs + ((unsigned __int128)1 << 63)) >> 64);
+    a[0] = (uint64_t)sa;
+    a[1] = (uint64_t)(sa >> 64);
+    a[2] = (uint64_t)sf;
+    a[3] = (uint64_t)(sf >> 64);
+}
+
+// From the sums: e = round(sum d_l F_l / 2^64), the rounding check, and
+// Y[i ystride + c] = (sum d_l B_l + e B_0) mod m.
+__global__ __launch_bounds__(256) void k_padic_fin(const uint64_t *__restrict__ acc, int64_t n, int64_t cols,
+                                                   int64_t ystride, const uint64_t *__restrict__ B, uint64_t m,
+                                                   uint64_t *__restrict__ Y, int32_t *__restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i >= n) return;
+    const uint64_t *a = acc + 4 * (c * n + i);
+    const unsigned __int128 sa = ((unsigned __int128)a[1] << 64) | a[0];
+    const unsigned __int128 sf = ((unsigned __int128)a[3] << 64) | a[2];
+    const uint64_t e = (uint64_t)((sf + ((unsigned __int128)1 << 63)) >> 64);
     const unsigned __int128 ee = (unsigned __int128)e << 64;
-    const unsigned __int128 dist = fs > ee ? fs - ee : ee - fs;
+    const unsigned __int128 dist = sf > ee ? sf - ee : ee - sf;
     if (dist >= ((unsigned __int128)1 << 43)) atomicOr(bad, 1);
-    const uint64_t r1 = (uint64_t)(acc % m);
-    const uint64_t r2 = (uint64_t)((unsigned __int128)Bc[0] * (e % m) % m);
+    const uint64_t r1 = (uint64_t)(sa % m);
+    const uint64_t r2 = (uint64_t)((unsigned __int128)B[0] * (e % m) % m);
     const uint64_t r = r1 + r2;
     Y[i * ystride + c] = r >= m ? r - m : r;
 }
 
-void launch_padic_dot(const uint32_t *Xh, int64_t n, int64_t ld, int64_t cols, int64_t ystride, int64_t xh,
-                      int64_t ring, int64_t K, int L, const uint64_t *B, const uint64_t *F, uint64_t m, uint64_t *Y,
-                      int32_t *bad, hipStream_t s) {
+void launch_padic_acc(const uint32_t *Xh, int64_t n, int64_t ld, int64_t cols, int64_t xh, int64_t ring, int64_t K,
+                      int64_t step0, int cnt, const uint64_t *B, const uint64_t *F, uint64_t *acc, hipStream_t s) {
+    if (n <= 0 || cols <= 0 || cnt <= 0) return;
+    ProfScope trace_(tl_trace, "k_padic_acc", s);
+    hipLaunchKernelGGL(k_padic_acc, dim3((unsigned)((n + 255) / 256), (unsigned)cols), dim3(256), 0, s, Xh, n, ld,
+                       cols, xh, ring, K, step0, cnt, B, F, acc);
+}
+
+void launch_padic_fin(const uint64_t *acc, int64_t n, int64_t cols, int64_t ystride, const uint64_t *B, uint64_t m,
+                      uint64_t *Y, int32_t *bad, hipStream_t s) {
     if (n <= 0 || cols <= 0) return;
-    ProfScope trace_(tl_trace, "k_padic_dot", s);
-    hipLaunchKernelGGL(k_padic_dot, dim3((unsigned)((n + 255) / 256), (unsigned)cols), dim3(256), 0, s, Xh, n, ld,
-                       ystride, xh, ring, K, L, B, F, m, Y, bad);
+    ProfScope trace_(tl_trace, "k_padic_fin", s);
+    hipLaunchKernelGGL(k_padic_fin, dim3((unsigned)((n + 255) / 256), (unsigned)cols), dim3(256), 0, s, acc, n, cols,
+                       ystride, B, m, Y, bad);
 }
 
 void launch_lift_proj(const uint32_t *Xh, int64_t n, int64_t ld, int t, const int32_t *Rp, int tp,

@@ -122,6 +122,22 @@ def test_random_matrices(ctx, rg, n, seed):
     _check_massager(a, res)
 
 
+@pytest.mark.parametrize("name,factors", [
+    ("a 20-bit prime plane", (2, 3, 2, 5, 1048573, 2, 7)),
+    ("powers of two only", (2, 2, 2, 4, 2, 8, 2, 2)),
+    ("15-bit and 10-bit prime planes", (32749, 1009, 2, 3)),
+])
+def test_word_moduli_planted(ctx, rg, name, factors):
+    """Planted chains whose s_n fits a word: every batch runs the local Smith
+    forms on the GPU, with an odd prime plane of Montgomery products, a pure
+    power of two, and several prime powers combined by the CRT."""
+    _say("massager planted word moduli:", name)
+    pl = synth.planted_small(28, seed=3, factors=factors, cap=(1 << 31) - 1)
+    res = rg.smith_massager(ctx, pl.a, seed=2)
+    assert res.s == pl.s
+    _check_massager(pl.a, res)
+
+
 def test_unimodular_matrix(ctx, rg):
     _say("massager unimodular")
     n = 24
