@@ -619,6 +619,46 @@ int rns_lift_step(int device, const uint32_t *C, const int64_t *A, const int64_t
                   uint32_t p, int form, uint32_t *X, int64_t *R_next, uint32_t *Rm_next, int32_t *inexact,
                   int *kernels, void *stream);
 
+/*
+ * rns_unimodular_certify -- Section 2.2, Phase 3: decides whether the integer
+ * matrix D is unimodular (|det D| = 1), deterministically, from high-order
+ * X-adic residues computed by double-plus-one lifting (the certification the
+ * paper takes from Pauderis and Storjohann; this library's reading):
+ *   X = p_0 ... p_{j-1} (the first primes of the internal basis) with
+ *   X >= 4 n^2 max|D|, C = D^-1 mod X, Z_0 = I and
+ *       Z_{2e+1} = (Z_e Z_e - D cmod(C Z_e Z_e, X)) / X      (exact),
+ *   which keeps I - D P_e = X^e Z_e for an integer P_e = D^-1 mod X^e with
+ *   |P_e| < X^e and |Z_e| <= n max|D|.  Z_e = 0 proves D^-1 = P_e integral;
+ *   a unimodular D reaches Z_e = 0 once X^e >= 4 H (H: Hadamard's bound on
+ *   the (n-1)-minors), so the verdict is exact.  Each step is three residue
+ *   products of n x n x n on the matrix cores (Z Z over j + l primes, C Y over
+ *   j, D K over l) and two elementwise passes.
+ *   D_host:    host int64, n x n row-major (leading dimension n); entries
+ *              other than INT64_MIN, with n max|D| < 2^61.
+ *   max_steps: < 0 runs the certificate (until Z_e = 0 or the bound's
+ *              precision); >= 0 runs at most that many steps (Z_e = 0 ends
+ *              early: it stays 0).
+ *   Z_host:    optional host int64 n x n: the last residue Z_e.
+ *   info:      verdict 1 (unimodular), 0 (not), -1 (steps ran out before the
+ *              bound's precision); reason 0 residue vanished, 1 residue
+ *              nonzero at the bound's precision, 2 D singular modulo a prime
+ *              of X (then p | det D), 3 a zero column, 4 step limit; the
+ *              primes of X and of the exact basis, steps run and needed,
+ *              log2 H, log2 X, seconds, residue products.
+ * n = 0 is unimodular.  n <= 43690 (the products' exact depth), else
+ * RNS_ENOTSUP; RNS_EBOUND if n max|D| >= 2^61.  Synchronous.
+ */
+typedef struct rns_unimod_info {
+    int32_t verdict, reason, steps, steps_needed;
+    int32_t x_primes, q_primes;
+    uint32_t x_prime[4], q_prime[4];
+    double log2_bound, log2_x, seconds, residue_ops;
+    int32_t products, reserved;
+} rns_unimod_info;
+
+int rns_unimodular_certify(rns_ctx *ctx, const int64_t *D_host, int64_t n, int max_steps,
+                           int64_t *Z_host, rns_unimod_info *info);
+
 /* Test hook: make the next `count` certifications of this context fail, to
  * exercise the Las Vegas restart (Section 2.2, Phase 3).  0 disables. */
 int rns_ctx_force_cert_failures(rns_ctx *ctx, int count);

@@ -10,5 +10,5 @@ from .binding import (Context, GemmPlan, GemmProblem, MatmulPlan, MatmulProblem,
                       RnsError, Server, SmithResult, autotune, server_footprint, crt_reconstruct, modmatmul_batched,
                       lift_step, modmatmul_batched_noalloc, noalloc_scratch_bytes, base_convert,
                       rns_primes_below, rns_reduce, rns_reduce_mw, rns_strerror, smith_form, largest_invariant, words_to_ints,
-                      smith_massager, MassagerResult,
+                      smith_massager, MassagerResult, unimodular_certify, UnimodularResult,
                       workspace_bytes)

@@ -124,6 +124,18 @@ _lib_smith_free = _sig("rns_smith_free", None, [_P])
 _lib_massager = _sig("rns_smith_massager", _I32, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_P)])
 _lib_massager_width = _sig("rns_smith_massager_width", _I32, [_P, _I32, _I64])
 _lib_massager_vector = _sig("rns_smith_massager_vector", _I32, [_P, _I32, _I64, _P, _I32])
+
+
+class RnsUnimodInfo(ctypes.Structure):
+    _fields_ = [("verdict", _I32), ("reason", _I32), ("steps", _I32), ("steps_needed", _I32),
+                ("x_primes", _I32), ("q_primes", _I32),
+                ("x_prime", ctypes.c_uint32 * 4), ("q_prime", ctypes.c_uint32 * 4),
+                ("log2_bound", ctypes.c_double), ("log2_x", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("residue_ops", ctypes.c_double), ("products", _I32), ("reserved", _I32)]
+
+
+_lib_unimodular = _sig("rns_unimodular_certify", _I32,
+                       [_P, _P, _I64, _I32, _P, ctypes.POINTER(RnsUnimodInfo)])
 class RnsPlanInfo(ctypes.Structure):
     _fields_ = [("path", _I32), ("variant", _I32), ("tiles", _I64), ("workspace_bytes", ctypes.c_size_t),
                 ("residue_ops", ctypes.c_double)]
@@ -190,7 +202,8 @@ EXPORTS = ["rns_strerror", "rns_primes_below", "rns_ctx_create", "rns_ctx_destro
            "rns_server_stats", "rns_server_footprint", "rns_server_destroy", "rns_calibrate",
            "rns_ctx_set_smith_path", "rns_largest_invariant", "rns_lift_step",
            "modmatmul_batched_noalloc", "rns_noalloc_scratch_bytes", "rns_base_convert",
-           "rns_smith_massager", "rns_smith_massager_width", "rns_smith_massager_vector"]
+           "rns_smith_massager", "rns_smith_massager_width", "rns_smith_massager_vector",
+           "rns_unimodular_certify"]
 
 
 class RnsError(RuntimeError):
@@ -685,6 +698,32 @@ def smith_massager(ctx: Context, a: np.ndarray, seed: int = 0, fetch=("U", "M", 
     finally:
         _lib_smith_free(h)
     return MassagerResult(res.s, mats["U"], mats["M"], mats["T"], res.stats, cols)
+
+
+@dataclass
+class UnimodularResult:
+    """rns_unimodular_certify: verdict (True, False, or None when the steps
+    ran out before the bound's precision), the last residue Z (int64 array,
+    if asked for) and the call's info fields (x_prime / q_prime as lists)."""
+    verdict: Optional[bool]
+    Z: Optional[np.ndarray]
+    info: dict
+
+
+def unimodular_certify(ctx: Context, d: np.ndarray, max_steps: int = -1, want_z: bool = False) -> UnimodularResult:
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    n = d.shape[0]
+    assert d.shape == (n, n)
+    z = np.zeros((n, n), dtype=np.int64) if want_z else None
+    info = RnsUnimodInfo()
+    _check(_lib_unimodular(ctx.handle, d.ctypes.data if n else None, n, max_steps,
+                           z.ctypes.data if want_z and n else None, ctypes.byref(info)),
+           "rns_unimodular_certify")
+    out = {f: getattr(info, f) for f, _ in RnsUnimodInfo._fields_}
+    out["x_prime"] = list(info.x_prime)[:info.x_primes]
+    out["q_prime"] = list(info.q_prime)[:info.q_primes]
+    verdict = {1: True, 0: False}.get(info.verdict)
+    return UnimodularResult(verdict, z, out)
 
 
 def words_to_uints(w: np.ndarray) -> np.ndarray:

@@ -2256,6 +2256,179 @@ struct Driver {
 
     // Chooses the path: residues of s A^-1 while its sizes fit the CRT of 64
     // primes, p-adic lifting beyond when the entries are small enough.
+    // ---------------------------------------------- unimodularity certificate
+    // Section 2.2, Phase 3: whether D = this matrix (n x n, host A, device dA)
+    // is unimodular, from high-order X-adic residues computed by
+    // double-plus-one steps (Z_0 = I; Z -> (Z Z - D cmod(C Z Z, X)) / X with
+    // C = D^-1 mod X): Z_e = 0 at precision X^e proves D^-1 integral, and for
+    // a unimodular D it holds once X^e >= 4 H, H Hadamard's bound on the
+    // (n-1)-minors.  X = p_0 .. p_{j-1} >= 4 n^2 max|D| keeps |Z| <= n max|D|;
+    // Z's exact value comes from l further primes with product > 2 n max|D|.
+    // Every product is a residue product of n x n x n (Z Z on j + l planes,
+    // C Y on j, D K on l); k_uc_convert and k_uc_tail do the rest.
+    struct UcInfo {
+        int verdict = -1, reason = 0, steps = 0, steps_needed = 0, j = 0, l = 0;
+        uint32_t P[kUcMaxPrimes]{}, Q[kUcMaxPrimes]{};
+        double log2_bound = 0, log2_x = 0, seconds = 0;
+    };
+    enum { kUcVanished = 0, kUcNonzero = 1, kUcSingularModX = 2, kUcZeroColumn = 3, kUcStepLimit = 4 };
+
+    int uc_run(int max_steps, int64_t *Z_host, UcInfo &info) {
+        const double t0 = now_s();
+        info = UcInfo{};
+        const int64_t N = n;
+        if (N == 0) {
+            info.verdict = 1;
+            return RNS_OK;
+        }
+        if (N > kLiftMfmaMaxN) return RNS_ENOTSUP;
+        // max|D| and the column norms.
+        uint64_t dmax = 0;
+        std::vector<double> col2((size_t)N, 0.0);
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t c = 0; c < N; ++c) {
+                const int64_t v = A[i * N + c];
+                if (v == INT64_MIN) return RNS_EINVAL;
+                const uint64_t a = (uint64_t)(v < 0 ? -v : v);
+                dmax = std::max(dmax, a);
+                col2[(size_t)c] += (double)v * (double)v;
+            }
+        double lsum = 0, lmin = INFINITY;
+        for (int64_t c = 0; c < N; ++c) {
+            if (col2[(size_t)c] == 0.0) {
+                info.verdict = 0;
+                info.reason = kUcZeroColumn;
+                return RNS_OK;
+            }
+            const double l2 = 0.5 * std::log2(col2[(size_t)c]);
+            lsum += l2;
+            lmin = std::min(lmin, l2);
+        }
+        // Rounding of the double sums: a relative 2^-40 per column is far more
+        // than the error of n additions of squares below 2^126.
+        info.log2_bound = N > 1 ? (lsum - lmin) * (1.0 + 1e-12) + 1e-6 * N : 0.0;
+        using u128 = unsigned __int128;
+        const u128 beta_z = (u128)dmax * (u128)N;
+        if (beta_z >= ((u128)1 << 61)) return RNS_EBOUND;
+        const u128 need_x = 4 * beta_z * (u128)N;
+        // X and Q from the first aux primes.
+        UcBasis b{};
+        u128 X = 1, Qp = 1;
+        int idx = 0;
+        while (X < need_x) {
+            if (b.j == kUcMaxPrimes) return RNS_EBOUND;
+            b.p[b.j++] = aux->primes[idx++];
+            X *= b.p[b.j - 1];
+        }
+        while (Qp <= 2 * beta_z) {
+            if (b.l == kUcMaxPrimes) return RNS_EBOUND;
+            b.q[b.l++] = aux->primes[idx++];
+            Qp *= b.q[b.l - 1];
+        }
+        auto inv = [](uint64_t a, uint64_t m) { return (uint32_t)powmod_u64(a % m, m - 2, m); };
+        auto digits = [](u128 v, const uint32_t *m, int k, uint32_t *d) {
+            for (int i = 0; i < k; ++i) {
+                d[i] = (uint32_t)(v % m[i]);
+                v /= m[i];
+            }
+        };
+        for (int a = 0; a < b.j; ++a)
+            for (int c = a + 1; c < b.j; ++c) b.pinv[a][c] = inv(b.p[a], b.p[c]);
+        for (int a = 0; a < b.l; ++a)
+            for (int c = a + 1; c < b.l; ++c) b.qinv[a][c] = inv(b.q[a], b.q[c]);
+        digits((X - 1) / 2, b.p, b.j, b.phalf);
+        digits((Qp - 1) / 2, b.q, b.l, b.qhalf);
+        for (int k = 0; k < b.l; ++k) {
+            b.x_mod_q[k] = (uint32_t)(X % b.q[k]);
+            b.xinv_q[k] = inv(b.x_mod_q[k], b.q[k]);
+        }
+        b.bound = (int64_t)beta_z;
+        info.j = b.j;
+        info.l = b.l;
+        for (int i = 0; i < b.j; ++i) info.P[i] = b.p[i];
+        for (int i = 0; i < b.l; ++i) info.Q[i] = b.q[i];
+        info.log2_x = 0;
+        for (int i = 0; i < b.j; ++i) info.log2_x += std::log2((double)b.p[i]);
+        {
+            const double need = (info.log2_bound + 2.0) / info.log2_x;
+            int k = 0;
+            while ((double)((1ll << k) - 1) < need) ++k;
+            info.steps_needed = k;
+        }
+        const int steps = max_steps >= 0 ? max_steps : info.steps_needed;
+        // C = D^-1 mod p_i (right halves of dM).
+        base = 0;
+        int bad = -1;
+        DRV_ST(invert(b.j, &bad));
+        if (bad >= 0) {
+            info.verdict = 0;
+            info.reason = kUcSingularModX;
+            info.seconds = now_s() - t0;
+            return RNS_OK;
+        }
+        const int L = b.j + b.l;
+        const int64_t ps = N * N;
+        DevBuf<int64_t> dZ;
+        DevBuf<uint32_t> dZr, dYr, dKr, dDq;
+        DevBuf<int32_t> dfl;
+        DRV_ST(dZ.alloc((size_t)ps));
+        DRV_ST(dZr.alloc((size_t)L * ps));
+        DRV_ST(dYr.alloc((size_t)L * ps));
+        DRV_ST(dKr.alloc((size_t)L * ps));
+        DRV_ST(dDq.alloc((size_t)b.l * ps));
+        DRV_ST(dfl.alloc(2));
+        DRV_ST(rns_reduce(aux, dA.p, N, N, N, b.j, b.l, dDq.p, N, ps, stream));
+        launch_uc_identity(dZ.p, N, stream);
+        DRV_HIP(hipGetLastError());
+        DRV_ST(rns_reduce(aux, dZ.p, N, N, N, 0, L, dZr.p, N, ps, stream));
+        int32_t fl[2] = {1, 0};
+        int run = 0;
+        for (run = 0; run < steps; ++run) {
+            DRV_ST(gemm(dZr.p, N, ps, dZr.p, N, ps, dYr.p, N, ps, N, N, N, 0, L));          // Y = Z Z
+            DRV_ST(gemm(dM.p + N, 2 * N, 2 * N * N, dYr.p, N, ps, dKr.p, N, ps, N, N, N, 0, b.j));  // C Y mod p
+            launch_uc_convert(dKr.p, dKr.p + (size_t)b.j * ps, ps, ps, b, stream);
+            DRV_HIP(hipGetLastError());
+            rns_gemm_desc d{};                                                             // Y - D K mod q
+            d.m = N; d.n = N; d.k = N;
+            d.A = dDq.p; d.lda = N; d.a_plane_stride = ps;
+            d.B = dKr.p + (size_t)b.j * ps; d.ldb = N; d.b_plane_stride = ps;
+            d.C = dYr.p + (size_t)b.j * ps; d.ldc = N; d.c_plane_stride = ps;
+            d.prime_begin = b.j; d.L = b.l;
+            d.flags = RNS_GEMM_SUBTRACT;
+            DRV_ST(modmatmul_batched(aux, &d, 1, RNS_PATH_AUTO, stream));
+            st.products += 1;
+            st.residue_ops += 2.0 * N * N * N * b.l;
+            DRV_HIP(hipMemsetAsync(dfl.p, 0, sizeof(int32_t) * 2, stream));
+            launch_uc_tail(dYr.p + (size_t)b.j * ps, dZ.p, ps, ps, b, dfl.p, stream);
+            DRV_HIP(hipGetLastError());
+            DRV_HIP(hipMemcpyAsync(fl, dfl.p, sizeof(fl), hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+            if (fl[1]) return RNS_EBOUND;          // |Z| beyond n max|D|: the bound argument failed
+            if (!fl[0]) {
+                ++run;
+                break;
+            }
+            if (run + 1 < steps) DRV_ST(rns_reduce(aux, dZ.p, N, N, N, 0, L, dZr.p, N, ps, stream));
+        }
+        info.steps = run;
+        if (!fl[0]) {
+            info.verdict = 1;
+            info.reason = kUcVanished;
+        } else if (run >= info.steps_needed) {
+            info.verdict = 0;
+            info.reason = kUcNonzero;
+        } else {
+            info.verdict = -1;
+            info.reason = kUcStepLimit;
+        }
+        if (Z_host) {
+            DRV_HIP(hipMemcpyAsync(Z_host, dZ.p, sizeof(int64_t) * ps, hipMemcpyDeviceToHost, stream));
+            DRV_ST(sync());
+        }
+        info.seconds = now_s() - t0;
+        return RNS_OK;
+    }
+
     int solve(rns_smith_result *res) {
         DRV_HIP(hipSetDevice(ctx->device));
         DRV_ST(solve_stream(ctx, &stream));
@@ -2387,6 +2560,48 @@ extern "C" int rns_smith_massager(rns_ctx *ctx, const int64_t *A_host, int64_t n
         return st;
     }
     *out = res;
+    return RNS_OK;
+}
+
+extern "C" int rns_unimodular_certify(rns_ctx *ctx, const int64_t *D_host, int64_t n, int max_steps,
+                                      int64_t *Z_host, rns_unimod_info *info) {
+    if (!ctx || !info || n < 0 || (n > 0 && !D_host)) return RNS_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    SolveScope scope(ctx);
+    Driver d;
+    d.ctx = ctx;
+    d.n = n;
+    d.A = D_host;
+    int st = aux_ctx(ctx, &d.aux);
+    Driver::UcInfo ui;
+    if (st == RNS_OK) {
+        TraceScope trace(ctx, d.aux);
+        st = [&]() -> int {
+            DRV_HIP(hipSetDevice(ctx->device));
+            DRV_ST(solve_stream(ctx, &d.stream));
+            if (n > 0) {
+                DRV_ST(d.dA.alloc((size_t)n * n));
+                DRV_HIP(hipMemcpyAsync(d.dA.p, D_host, sizeof(int64_t) * n * n, hipMemcpyHostToDevice, d.stream));
+            }
+            return d.uc_run(max_steps, Z_host, ui);
+        }();
+    }
+    if (st != RNS_OK) return st;
+    info->verdict = ui.verdict;
+    info->reason = ui.reason;
+    info->steps = ui.steps;
+    info->steps_needed = ui.steps_needed;
+    info->x_primes = ui.j;
+    info->q_primes = ui.l;
+    for (int i = 0; i < 4; ++i) {
+        info->x_prime[i] = ui.P[i];
+        info->q_prime[i] = ui.Q[i];
+    }
+    info->log2_bound = ui.log2_bound;
+    info->log2_x = ui.log2_x;
+    info->seconds = ui.seconds;
+    info->residue_ops = d.st.residue_ops;
+    info->products = d.st.products;
     return RNS_OK;
 }
 

@@ -159,4 +159,29 @@ void launch_loc_init(const uint64_t *M, int64_t n, const LocalMod *lms, int F, u
 void launch_loc_step(uint64_t *M, int64_t n, int k, const LocalMod *lms, int F, uint64_t *keys, int32_t *val,
                      uint64_t *uinv, hipStream_t s);
 
+// Unimodularity certificate (Section 2.2, Phase 3): the two residue bases of
+// the double-plus-one steps.  X = p_0 ... p_{j-1} is the lifting modulus;
+// the exact residues are recovered from q_0 ... q_{l-1}.  pinv[a][b] =
+// p_a^-1 mod p_b (a < b), likewise qinv; phalf / qhalf are the mixed-radix
+// digits of (X - 1) / 2 and (Q - 1) / 2; bound is the promised max |Z|.
+constexpr int kUcMaxPrimes = 4;
+struct UcBasis {
+    int j, l;
+    uint32_t p[kUcMaxPrimes], q[kUcMaxPrimes];
+    uint32_t pinv[kUcMaxPrimes][kUcMaxPrimes], qinv[kUcMaxPrimes][kUcMaxPrimes];
+    uint32_t phalf[kUcMaxPrimes], qhalf[kUcMaxPrimes];
+    uint32_t x_mod_q[kUcMaxPrimes], xinv_q[kUcMaxPrimes];
+    int64_t bound;
+};
+// Kq (l planes) <- the symmetric K given by Kp (j planes), count entries per
+// plane, planes plane_stride apart.
+void launch_uc_convert(const uint32_t *Kp, uint32_t *Kq, int64_t count, int64_t plane_stride, const UcBasis &b,
+                       hipStream_t s);
+// Z <- (residues Rq of Y - D K) X^-1 as int64; flags[0] |= some entry is
+// nonzero, flags[1] |= some entry exceeds b.bound (then written as 0).
+void launch_uc_tail(const uint32_t *Rq, int64_t *Z, int64_t count, int64_t plane_stride, const UcBasis &b,
+                    int32_t *flags, hipStream_t s);
+// Z <- I (n x n int64).
+void launch_uc_identity(int64_t *Z, int64_t n, hipStream_t s);
+
 }  // namespace rns
