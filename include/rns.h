@@ -405,6 +405,15 @@ typedef struct rns_smith_stats {
     double t_host_cpu;     /* CPU seconds of the calling thread and of the
                               helper threads it started for this call */
     int batches;           /* path 2: index-massager batches of Phase 2 */
+    int cert_kind;         /* 0: |det A| = prod s_i (determinant modulo
+                              primes); 1 (path 2): the massaged matrix B of
+                              Eq. (1) certified unimodular by high-order
+                              residues (rns_unimodular_certify's method) */
+    int uc_steps;          /* cert_kind 1: double-plus-one steps of the last
+                              certificate */
+    int uc_rejects;        /* cert_kind 1: massagers the certificate rejected
+                              (each followed by a restart) */
+    int64_t uc_dim;        /* cert_kind 1: dimension of the linearized B */
 } rns_smith_stats;
 
 /*

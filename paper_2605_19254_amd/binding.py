@@ -82,7 +82,8 @@ class RnsSmithStats(ctypes.Structure):
                 ("residue_ops", ctypes.c_double), ("cert_primes", _I32),
                 ("columns", _I32), ("path", _I32), ("cert_exact", _I32),
                 ("lift_a_bytes", _I32), ("lift_kernels", _I32), ("t_host_cpu", ctypes.c_double),
-                ("batches", _I32)]
+                ("batches", _I32), ("cert_kind", _I32), ("uc_steps", _I32), ("uc_rejects", _I32),
+                ("uc_dim", _I64)]
 
 
 def _sig(name, res, args):

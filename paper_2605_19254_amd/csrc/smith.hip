@@ -2004,28 +2004,349 @@ struct Driver {
         }
     }
 
-    // Assembles S, U, M, T (positions: the trivial invariants first, then the
-    // batches newest first, each ascending).
-    void massager_output(const std::vector<MBatch> &B, rns_smith_result *res) {
+    // ------------------------------------------------ Phase 3 of the massager
+    // The reduced Smith massager over the m nontrivial positions n0 .. n-1
+    // (position order of the output: batches newest first, each ascending):
+    // row t of U reduced mod s_t, T rebuilt from it (T_ab = -U_a M_b mod s_b
+    // for a < b), and the blocks G = A M S^-1 (n x m) and V = (T + U M) S^-1
+    // (m x m) of the massaged matrix B of Eq. (1).  Reducing a row of U mod
+    // its own s_a keeps B integral (the change of (U M)_ab is a multiple of
+    // s_a, which s_b divides for b <= a, and T absorbs it for b > a) and keeps
+    // det B = det A / det S; it brings the bits of row a of B's lower half to
+    // about log2(n s_a), so the whole massager takes O(n log|det A|) words.
+    struct Reduced {
+        int64_t m = 0, n0 = 0;
+        std::vector<BigInt> s;                     // s_t
+        std::vector<int> w;                        // words of s_t
+        std::vector<std::vector<uint64_t>> U, M;   // row t of U, column t of M: n entries of w[t] words
+        std::vector<BigInt> T, V;                  // [b][a] T_ab (a < b);  [a][b] V_ab
+        std::vector<int64_t> G;                    // [i][b]
+    };
+
+    static int words_of(const BigInt &x) { return (int)std::max<size_t>(1, (x.mag.size() + 1) / 2); }
+
+    static void put_words(uint64_t *dst, int W, const BigInt &x) {
+        const size_t nl = x.mag.size();
+        for (int i = 0; i < W; ++i) {
+            const uint64_t lo = (size_t)(2 * i) < nl ? x.mag[(size_t)(2 * i)] : 0;
+            const uint64_t hi = (size_t)(2 * i + 1) < nl ? x.mag[(size_t)(2 * i + 1)] : 0;
+            dst[i] = lo | (hi << 32);
+        }
+    }
+
+    static BigInt from_words(const uint64_t *x, int W) {
+        BigInt r(0);
+        r.mag.resize((size_t)(2 * W));
+        for (int i = 0; i < W; ++i) {
+            r.mag[(size_t)(2 * i)] = (uint32_t)x[i];
+            r.mag[(size_t)(2 * i + 1)] = (uint32_t)(x[i] >> 32);
+        }
+        while (!r.mag.empty() && r.mag.back() == 0) r.mag.pop_back();
+        return r;
+    }
+
+    // C (r x c, W words per entry, two's complement) = A B exactly for int64
+    // A (r x k) and B (k x c), |C| < 2^lb, by residue products over the first
+    // aux primes and the exact CRT.
+    int exact_product(const int64_t *Ah, int64_t r, int64_t k, const int64_t *Bh, int64_t c, double lb,
+                      std::vector<uint64_t> &C, int &W) {
+        const int L = (int)std::ceil((lb + 2.0) / 25.9);
+        W = (int)std::ceil((lb + 2.0) / 64.0);
+        if (L > kMaxSolvePrimes || W > 32) return RNS_ENOTSUP;
+        C.assign((size_t)(r * c * W), 0);
+        if (r == 0 || c == 0) return RNS_OK;
+        DevBuf<int64_t> da, db;
+        DevBuf<uint32_t> ra, rb, rc;
+        DevBuf<uint64_t> dc;
+        DRV_ST(da.alloc((size_t)(r * k)));
+        DRV_ST(db.alloc((size_t)(k * c)));
+        DRV_ST(ra.alloc((size_t)(L * r * k)));
+        DRV_ST(rb.alloc((size_t)(L * k * c)));
+        DRV_ST(rc.alloc((size_t)(L * r * c)));
+        DRV_ST(dc.alloc((size_t)(r * c * W)));
+        DRV_HIP(hipMemcpyAsync(da.p, Ah, sizeof(int64_t) * r * k, hipMemcpyHostToDevice, stream));
+        DRV_HIP(hipMemcpyAsync(db.p, Bh, sizeof(int64_t) * k * c, hipMemcpyHostToDevice, stream));
+        DRV_ST(rns_reduce(aux, da.p, r, k, k, 0, L, ra.p, k, r * k, stream));
+        DRV_ST(rns_reduce(aux, db.p, k, c, c, 0, L, rb.p, c, k * c, stream));
+        DRV_ST(gemm(ra.p, k, r * k, rb.p, c, k * c, rc.p, c, r * c, r, c, k, 0, L));
+        DRV_ST(dstatus.alloc(1));
+        DRV_HIP(hipMemsetAsync(dstatus.p, 0, sizeof(int32_t), stream));
+        DRV_ST(crt_reconstruct(aux, rc.p, r, c, c, r * c, 0, L, nullptr, 0, dc.p, W, c, dstatus.p, stream));
+        DRV_HIP(hipMemcpyAsync(C.data(), dc.p, sizeof(uint64_t) * r * c * W, hipMemcpyDeviceToHost, stream));
+        int32_t ovf = 0;
+        DRV_HIP(hipMemcpyAsync(&ovf, dstatus.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        DRV_ST(sync());
+        return ovf ? RNS_EOVERFLOW : RNS_OK;
+    }
+
+    // Builds the reduced massager; *integral = false when a block of B turns
+    // out not to be integral (then the massager is wrong and the solve
+    // restarts).
+    int massager_reduce(const std::vector<MBatch> &B, Reduced &R, bool *integral) {
+        *integral = true;
         int64_t m = 0;
         for (const MBatch &b : B) m += (int64_t)b.S.size();
-        struct Pos {
-            int b;                                       // batch, -1 for s_i = 1
-            int64_t a;                                   // index in the batch
-        };
-        std::vector<Pos> pos((size_t)n, Pos{-1, 0});
-        int64_t q = n - m;
-        for (int bi = (int)B.size() - 1; bi >= 0; --bi)
-            for (int64_t a = 0; a < (int64_t)B[(size_t)bi].S.size(); ++a) pos[(size_t)q++] = Pos{bi, a};
-        auto words = [](const BigInt &x) { return (int)std::max<size_t>(1, (x.mag.size() + 1) / 2); };
-        auto put = [](std::vector<uint64_t> &dst, int64_t k, int W, const BigInt &x) {
-            const size_t nl = x.mag.size();
-            for (int i = 0; i < W && (size_t)(2 * i) < nl; ++i) {
-                const uint64_t lo = x.mag[(size_t)(2 * i)];
-                const uint64_t hi = (size_t)(2 * i + 1) < nl ? x.mag[(size_t)(2 * i + 1)] : 0;
-                dst[(size_t)k * W + i] = lo | (hi << 32);
+        R = Reduced{};
+        R.m = m;
+        R.n0 = n - m;
+        R.s.resize((size_t)m);
+        R.w.resize((size_t)m);
+        R.U.resize((size_t)m);
+        R.M.resize((size_t)m);
+        std::vector<std::pair<int, int64_t>> src((size_t)m);
+        {
+            int64_t t = 0;
+            for (int bi = (int)B.size() - 1; bi >= 0; --bi)
+                for (int64_t a = 0; a < (int64_t)B[(size_t)bi].S.size(); ++a) src[(size_t)t++] = {bi, a};
+        }
+        const msg::ParFor par = host_par();
+        par(m, (double)n * 64, [&](int64_t t) {
+            const MBatch &b = B[(size_t)src[(size_t)t].first];
+            const int64_t a = src[(size_t)t].second;
+            const BigInt &sa = b.S[(size_t)a];
+            const int W = words_of(sa);
+            R.s[(size_t)t] = sa;
+            R.w[(size_t)t] = W;
+            R.U[(size_t)t].assign((size_t)(n * W), 0);
+            R.M[(size_t)t].assign((size_t)(n * W), 0);
+            const bool word = sa.bit_length() <= 64;
+            const uint64_t sw = word ? sa.to_u64_mag() : 0;
+            for (int64_t k = 0; k < n; ++k) {
+                const BigInt &u = b.U[(size_t)(a * n + k)];
+                if (word && u.bit_length() <= 64) {
+                    R.U[(size_t)t][(size_t)k] = u.to_u64_mag() % sw;
+                } else {
+                    put_words(R.U[(size_t)t].data() + k * W, W, mod(u, sa));
+                }
+                put_words(R.M[(size_t)t].data() + k * W, W, b.M[(size_t)(a * n + k)]);
             }
+        });
+        if (m == 0) return RNS_OK;
+        // Word positions (s_t < 2^62) have their products on the GPU.
+        std::vector<int64_t> wp, bp;
+        for (int64_t t = 0; t < m; ++t) (R.s[(size_t)t].bit_length() <= 62 ? wp : bp).push_back(t);
+        const int64_t mw = (int64_t)wp.size();
+        // G = A M S^-1.
+        R.G.assign((size_t)(n * m), 0);
+        std::atomic<bool> bad{false};
+        if (mw > 0) {
+            std::vector<int64_t> Mh((size_t)(n * mw));
+            for (int64_t c = 0; c < mw; ++c)
+                for (int64_t k = 0; k < n; ++k) Mh[(size_t)(k * mw + c)] = (int64_t)R.M[(size_t)wp[(size_t)c]][(size_t)k];
+            std::vector<uint64_t> C;
+            int W = 0;
+            DRV_ST(exact_product(A, n, n, Mh.data(), mw, std::log2(std::max(amax, 1.0) * (double)n) + 63.0, C, W));
+            par(n, (double)mw * 8, [&](int64_t i) {
+                for (int64_t c = 0; c < mw; ++c) {
+                    const uint64_t *x = C.data() + (size_t)((i * mw + c) * W);
+                    const bool neg = (x[W - 1] >> 63) != 0;
+                    unsigned __int128 v = 0;               // |x| < 2^99 (n max|a| < 2^36)
+                    for (int w = std::min(W, 2) - 1; w >= 0; --w) v = (v << 64) | (neg ? ~x[w] : x[w]);
+                    if (neg) v += 1;
+                    const uint64_t sb = R.s[(size_t)wp[(size_t)c]].to_u64_mag();
+                    if (v % sb) bad = true;
+                    const int64_t g = (int64_t)(uint64_t)(v / sb);
+                    R.G[(size_t)(i * m + wp[(size_t)c])] = neg ? -g : g;
+                }
+            });
+        }
+        par((int64_t)bp.size() * n, (double)n * 64, [&](int64_t e) {
+            const int64_t b = bp[(size_t)(e / n)], i = e % n;
+            const int W = R.w[(size_t)b];
+            BigInt acc(0);
+            for (int64_t k = 0; k < n; ++k) {
+                const int64_t a = A[i * n + k];
+                if (a) acc = acc + from_words(R.M[(size_t)b].data() + k * W, W) * BigInt(a);
+            }
+            BigInt q, r;
+            BigInt::divmod_floor(acc, R.s[(size_t)b], q, r);
+            if (!r.is_zero()) bad = true;
+            R.G[(size_t)(i * m + b)] = q.to_i64();
+        });
+        // X = U M over the nontrivial positions, then T and V.
+        R.T.assign((size_t)(m * m), BigInt(0));
+        R.V.assign((size_t)(m * m), BigInt(0));
+        auto finish = [&](int64_t a, int64_t b, const BigInt &x) {
+            BigInt q, r;
+            BigInt::divmod_floor(x, R.s[(size_t)b], q, r);
+            if (a < b) {
+                if (!r.is_zero()) {
+                    R.T[(size_t)(b * m + a)] = R.s[(size_t)b] - r;
+                    q = q + BigInt(1);
+                }
+            } else if (a == b) {
+                if (!(r + BigInt(1) == R.s[(size_t)b])) bad = true;
+                q = q + BigInt(1);
+            } else if (!r.is_zero()) {
+                bad = true;
+            }
+            R.V[(size_t)(a * m + b)] = q;
         };
+        if (mw > 0) {
+            std::vector<int64_t> Uh((size_t)(mw * n)), Mh((size_t)(n * mw));
+            for (int64_t r = 0; r < mw; ++r)
+                for (int64_t k = 0; k < n; ++k) {
+                    Uh[(size_t)(r * n + k)] = (int64_t)R.U[(size_t)wp[(size_t)r]][(size_t)k];
+                    Mh[(size_t)(k * mw + r)] = (int64_t)R.M[(size_t)wp[(size_t)r]][(size_t)k];
+                }
+            std::vector<uint64_t> C;
+            int W = 0;
+            DRV_ST(exact_product(Uh.data(), mw, n, Mh.data(), mw, 124.0 + std::log2((double)n), C, W));
+            par(mw, (double)mw * 16, [&](int64_t r) {
+                for (int64_t c = 0; c < mw; ++c) finish(wp[(size_t)r], wp[(size_t)c], from_words(C.data() + (size_t)((r * mw + c) * W), W));
+            });
+        }
+        // Pairs with a multiword position: word accumulators over the limbs.
+        std::vector<std::pair<int64_t, int64_t>> pairs;
+        for (int64_t a = 0; a < m; ++a)
+            for (int64_t b = 0; b < m; ++b)
+                if (R.s[(size_t)a].bit_length() > 62 || R.s[(size_t)b].bit_length() > 62) pairs.push_back({a, b});
+        par((int64_t)pairs.size(), (double)n * 64, [&](int64_t e) {
+            const int64_t a = pairs[(size_t)e].first, b = pairs[(size_t)e].second;
+            const int wa = R.w[(size_t)a], wb = R.w[(size_t)b];
+            std::vector<uint64_t> acc((size_t)(wa + wb + 2), 0);
+            for (int64_t k = 0; k < n; ++k) {
+                const uint64_t *u = R.U[(size_t)a].data() + k * wa;
+                const uint64_t *v = R.M[(size_t)b].data() + k * wb;
+                for (int i = 0; i < wa; ++i) {
+                    if (!u[i]) continue;
+                    unsigned __int128 carry = 0;
+                    for (int j = 0; j < wb; ++j) {
+                        const unsigned __int128 t = (unsigned __int128)u[i] * v[j] + acc[(size_t)(i + j)] + carry;
+                        acc[(size_t)(i + j)] = (uint64_t)t;
+                        carry = t >> 64;
+                    }
+                    for (size_t j = (size_t)(i + wb); carry && j < acc.size(); ++j) {
+                        const unsigned __int128 t = (unsigned __int128)acc[j] + carry;
+                        acc[j] = (uint64_t)t;
+                        carry = t >> 64;
+                    }
+                }
+            }
+            finish(a, b, from_words(acc.data(), (int)acc.size()));
+        });
+        *integral = !bad;
+        return RNS_OK;
+    }
+
+    // Phase 3: certifies that B (Eq. (1)) of the reduced massager is
+    // unimodular.  B restricted to the nontrivial positions is
+    //     B' = [ A   G ]        (n + m square; a trivial position contributes
+    //          [ U'  V ]         the unit row and column e_{n+i} of B, which
+    //                            do not change |det B|),
+    // and its lower rows are linearized in base 2^lam (each row r becomes its
+    // digit rows r_0 .. r_{k-1} and k - 1 new columns with 2^lam above and
+    // -1 on the digit rows' diagonal: the same |det|, unimodular exactly when
+    // B' is), so that every entry is small; lam is chosen to minimise the
+    // certificate's estimated product work.
+    int massager_phase3(const Reduced &R, bool *ok, int64_t *dim) {
+        *ok = false;
+        const int64_t m = R.m;
+        std::vector<int> bits((size_t)m, 1);
+        double gmax = std::max(amax, 1.0);
+        for (int64_t e = 0; e < n * m; ++e) gmax = std::max(gmax, std::fabs((double)R.G[(size_t)e]));
+        for (int64_t t = 0; t < m; ++t) {
+            int bt = 1;
+            const int W = R.w[(size_t)t];
+            for (int64_t k = 0; k < n; ++k) {
+                const uint64_t *u = R.U[(size_t)t].data() + k * W;
+                for (int w = W - 1; w >= 0; --w)
+                    if (u[w]) {
+                        bt = std::max(bt, 64 * w + 64 - __builtin_clzll(u[w]));
+                        break;
+                    }
+            }
+            for (int64_t b = 0; b < m; ++b) bt = std::max(bt, (int)R.V[(size_t)(t * m + b)].bit_length());
+            bits[(size_t)t] = bt;
+        }
+        int best = 0;
+        double best_cost = INFINITY;
+        for (int lam = 12; lam <= 56; lam += 4) {
+            int64_t N = n;
+            for (int64_t t = 0; t < m; ++t) N += (bits[(size_t)t] + lam - 1) / lam;
+            const double lb = std::max(std::log2(gmax), (double)lam);
+            const double lbz = lb + std::log2((double)N);
+            if (lbz >= 60.0 || N > kLiftMfmaMaxN) continue;
+            const double lx = lbz + std::log2((double)N) + 2.0;
+            const int j = (int)std::ceil(lx / 25.99), l = (int)std::ceil((lbz + 1.0) / 25.99);
+            const double lh = (double)N * (lb + 0.5 * std::log2((double)N));
+            const double steps = std::ceil(std::log2(lh / (j * 25.99) + 1.0)) + 1.0;
+            const double cost = (double)N * N * N * (2.0 * (j + l) * steps + 2.0 * j);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = lam;
+            }
+        }
+        if (!best) return RNS_ENOTSUP;
+        const int lam = best;
+        int64_t N = n;
+        std::vector<int64_t> row0((size_t)m), ext0((size_t)m);
+        int64_t extra = 0;
+        for (int64_t t = 0; t < m; ++t) extra += (bits[(size_t)t] + lam - 1) / lam - 1;
+        for (int64_t t = 0, r = n, c = n + m; t < m; ++t) {
+            row0[(size_t)t] = r;
+            ext0[(size_t)t] = c;
+            const int64_t k = (bits[(size_t)t] + lam - 1) / lam;
+            r += k;
+            c += k - 1;
+        }
+        N = n + m + extra;
+        *dim = N;
+        std::vector<int64_t> D((size_t)(N * N), 0);
+        const msg::ParFor par = host_par();
+        par(n, (double)N, [&](int64_t i) {
+            int64_t *row = D.data() + (size_t)(i * N);
+            for (int64_t k = 0; k < n; ++k) row[k] = A[i * n + k];
+            for (int64_t b = 0; b < m; ++b) row[n + b] = R.G[(size_t)(i * m + b)];
+        });
+        const uint64_t base = 1ull << lam, mask = base - 1;
+        auto digit = [&](const uint64_t *x, int W, int l) -> int64_t {
+            const int bit = l * lam, w = bit / 64, o = bit % 64;
+            if (w >= W) return 0;
+            uint64_t v = x[w] >> o;
+            if (o && w + 1 < W) v |= x[w + 1] << (64 - o);
+            return (int64_t)(v & mask);
+        };
+        par(m, (double)N * 8, [&](int64_t t) {
+            const int64_t k = (bits[(size_t)t] + lam - 1) / lam;
+            const int W = R.w[(size_t)t];
+            std::vector<std::vector<uint64_t>> vw((size_t)m);
+            int vwid = 1;
+            for (int64_t b = 0; b < m; ++b) vwid = std::max(vwid, words_of(R.V[(size_t)(t * m + b)]));
+            std::vector<uint64_t> vbuf((size_t)(m * vwid), 0);
+            for (int64_t b = 0; b < m; ++b) put_words(vbuf.data() + b * vwid, vwid, R.V[(size_t)(t * m + b)]);
+            for (int64_t l = 0; l < k; ++l) {
+                int64_t *row = D.data() + (size_t)((row0[(size_t)t] + l) * N);
+                for (int64_t c = 0; c < n; ++c) row[c] = digit(R.U[(size_t)t].data() + c * W, W, (int)l);
+                for (int64_t b = 0; b < m; ++b) row[n + b] = digit(vbuf.data() + b * vwid, vwid, (int)l);
+                if (l > 0) row[ext0[(size_t)t] + l - 1] = -1;
+                if (l < k - 1) row[ext0[(size_t)t] + l] = (int64_t)base;
+            }
+        });
+        Driver dd;
+        dd.ctx = ctx;
+        dd.aux = aux;
+        dd.n = N;
+        dd.A = D.data();
+        dd.stream = stream;
+        DRV_ST(dd.dA.alloc((size_t)(N * N)));
+        DRV_HIP(hipMemcpyAsync(dd.dA.p, D.data(), sizeof(int64_t) * N * N, hipMemcpyHostToDevice, stream));
+        UcInfo ui;
+        const int rc = dd.uc_run(-1, nullptr, ui);
+        st.products += dd.st.products;
+        st.residue_ops += dd.st.residue_ops;
+        DRV_ST(dd.sync());
+        DRV_ST(rc);
+        st.uc_steps = ui.steps;
+        st.uc_dim = N;
+        *ok = ui.verdict == 1;
+        return RNS_OK;
+    }
+
+    // Assembles S, U, M, T of the reduced massager (positions: the trivial
+    // invariants first, then the batches newest first, each ascending).
+    void massager_output(const Reduced &R, rns_smith_result *res) {
+        const int64_t m = R.m, n0 = R.n0;
         res->massager = true;
         res->s.assign((size_t)n, BigInt(1).mag_words());
         res->U.assign((size_t)n, {});
@@ -2035,73 +2356,26 @@ struct Driver {
         res->wM.assign((size_t)n, 1);
         res->wT.assign((size_t)n, 1);
         const msg::ParFor par = host_par();
-        par(n, (double)n * n, [&](int64_t j) {
-            const Pos pj = pos[(size_t)j];
-            if (pj.b < 0) {                              // s_j = 1: U row 0, M column 0, T column e_j
+        par(n, (double)n * 4, [&](int64_t j) {
+            if (j < n0) {                                // s_j = 1: U row 0, M column 0, T column e_j
                 res->U[(size_t)j].assign((size_t)n, 0);
                 res->M[(size_t)j].assign((size_t)n, 0);
                 res->T[(size_t)j].assign((size_t)n, 0);
                 res->T[(size_t)j][(size_t)j] = 1;
                 return;
             }
-            const MBatch &b = B[(size_t)pj.b];
-            const BigInt &sj = b.S[(size_t)pj.a];
-            res->s[(size_t)j] = sj.mag_words();
-            const int wu = words(b.s), wm = words(sj);
-            res->wU[(size_t)j] = wu;
-            res->wM[(size_t)j] = wm;
-            res->wT[(size_t)j] = wm;
-            res->U[(size_t)j].assign((size_t)(n * wu), 0);
-            res->M[(size_t)j].assign((size_t)(n * wm), 0);
-            res->T[(size_t)j].assign((size_t)(n * wm), 0);
-            for (int64_t i = 0; i < n; ++i) {
-                put(res->U[(size_t)j], i, wu, b.U[(size_t)(pj.a * n + i)]);
-                put(res->M[(size_t)j], i, wm, b.M[(size_t)(pj.a * n + i)]);
-            }
-            put(res->T[(size_t)j], j, wm, BigInt(1));
-            // Rows of newer batches: T_ij = -U_i M_j (mod s_j).  Rows with
-            // word entries (the later batches) sum u M_jk in a word
-            // accumulator; M_j's words are unpacked once.
-            std::vector<uint64_t> mw((size_t)(n * wm), 0);
-            for (int64_t k = 0; k < n; ++k) put(mw, k, wm, b.M[(size_t)(pj.a * n + k)]);
-            std::vector<uint64_t> accw((size_t)wm + 2);
-            for (int64_t i = 0; i < j; ++i) {
-                const Pos pi = pos[(size_t)i];
-                if (pi.b < 0 || pi.b <= pj.b) continue;
-                const MBatch &bn = B[(size_t)pi.b];
-                BigInt acc(0);
-                if (bn.s.bit_length() <= 64) {
-                    std::fill(accw.begin(), accw.end(), 0);
-                    for (int64_t k = 0; k < n; ++k) {
-                        const uint64_t u = bn.U[(size_t)(pi.a * n + k)].to_u64_mag();
-                        if (!u) continue;
-                        unsigned __int128 carry = 0;
-                        const uint64_t *mk = mw.data() + (size_t)(k * wm);
-                        for (int w = 0; w < wm; ++w) {
-                            const unsigned __int128 v = (unsigned __int128)mk[w] * u + accw[(size_t)w] + carry;
-                            accw[(size_t)w] = (uint64_t)v;
-                            carry = v >> 64;
-                        }
-                        for (size_t w = (size_t)wm; carry && w < accw.size(); ++w) {
-                            const unsigned __int128 v = (unsigned __int128)accw[w] + carry;
-                            accw[w] = (uint64_t)v;
-                            carry = v >> 64;
-                        }
-                    }
-                    acc.mag.resize(2 * accw.size());
-                    for (size_t w = 0; w < accw.size(); ++w) {
-                        acc.mag[2 * w] = (uint32_t)accw[w];
-                        acc.mag[2 * w + 1] = (uint32_t)(accw[w] >> 32);
-                    }
-                    while (!acc.mag.empty() && acc.mag.back() == 0) acc.mag.pop_back();
-                } else {
-                    for (int64_t k = 0; k < n; ++k) {
-                        const BigInt &u = bn.U[(size_t)(pi.a * n + k)];
-                        if (!u.is_zero()) acc = acc + u * b.M[(size_t)(pj.a * n + k)];
-                    }
-                }
-                put(res->T[(size_t)j], i, wm, mod(-acc, sj));
-            }
+            const int64_t t = j - n0;
+            const int W = R.w[(size_t)t];
+            res->s[(size_t)j] = R.s[(size_t)t].mag_words();
+            res->wU[(size_t)j] = W;
+            res->wM[(size_t)j] = W;
+            res->wT[(size_t)j] = W;
+            res->U[(size_t)j] = R.U[(size_t)t];
+            res->M[(size_t)j] = R.M[(size_t)t];
+            std::vector<uint64_t> &T = res->T[(size_t)j];
+            T.assign((size_t)(n * W), 0);
+            for (int64_t a = 0; a < t; ++a) put_words(T.data() + (n0 + a) * W, W, R.T[(size_t)(t * m + a)]);
+            T[(size_t)(j * W)] = 1;
         });
     }
 
@@ -2133,26 +2407,47 @@ struct Driver {
             st.t_im += now_s() - ti;
             if (sp == RNS_EBOUND) continue;
             DRV_ST(sp);
-            // Phase 3: |det A| = prod s_i, exactly.
+            // Phase 3: B of the reduced massager (Eq. (1)) is unimodular,
+            // certified by high-order residues; where the linearized B is
+            // beyond that certificate's limits, |det A| = prod s_i exactly.
             const double tu = now_s();
-            BigInt prod(1);
-            for (const MBatch &b : B)
-                for (const BigInt &o : b.S) prod = prod * o;
-            bool ok = false;
-            if (sn.is_one()) {
-                const BigInt one(1);
-                DRV_ST(lift_certify(pidx, detp, one, one, &ok));
+            bool forced = false;
+            if (ctx->force_cert_failures > 0 && !B.empty()) {
+                // Test hook: drop the last batch, which leaves a valid but not
+                // maximal massager for the certificate to reject.
+                ctx->force_cert_failures -= 1;
+                B.pop_back();
+                forced = true;
+            }
+            Reduced R;
+            bool integral = true, ok = false;
+            DRV_ST(massager_reduce(B, R, &integral));
+            int64_t dim = 0;
+            const int p3 = integral ? massager_phase3(R, &ok, &dim) : RNS_OK;
+            if (p3 == RNS_OK) {
+                st.cert_kind = 1;
+                if (!ok) st.uc_rejects += 1;
+            } else if (p3 == RNS_ENOTSUP) {
+                st.cert_kind = 0;
+                BigInt prod(1);
+                for (const BigInt &o : R.s) prod = prod * o;
+                if (sn.is_one()) {
+                    const BigInt one(1);
+                    DRV_ST(lift_certify(pidx, detp, one, one, &ok));
+                } else {
+                    DRV_ST(lift_certify(pidx, detp, sn, prod, &ok));
+                }
             } else {
-                DRV_ST(lift_certify(pidx, detp, sn, prod, &ok));
+                return p3;
             }
             st.t_uc += now_s() - tu;
-            if (ok && ctx->force_cert_failures > 0) {   // test hook: pretend the check failed
-                ctx->force_cert_failures -= 1;
+            if (ok && !forced && B.empty() && ctx->force_cert_failures > 0) {
+                ctx->force_cert_failures -= 1;         // no batch to drop (A unimodular)
                 ok = false;
             }
             if (!ok) continue;
             const double to = now_s();
-            massager_output(B, res);
+            massager_output(R, res);
             st.t_im += now_s() - to;
             st.cert_exact = 1;
             st.lift_a_bytes = a_bytes;

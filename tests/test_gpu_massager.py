@@ -1,7 +1,10 @@
 """GPU Smith massager (rns_smith_massager): S against the oracle's Smith form
 and (U, M, T, S) through Section 4.2's checks (oracle/massager.py):
 divisibility, A M S^-1 and (T + U M) S^-1 integral, T unit upper triangular,
-|det A| = prod s_i, and Definition 1 with W = -T^-1 U.
+|det A| = prod s_i, and Definition 1 with W = -T^-1 U.  The massager comes
+back reduced (row i of U modulo s_i) and certified by Phase 3 (B unimodular
+by high-order residues); the forced failure drops the last batch, so the
+certificate itself must reject the non-maximal massager and restart.
 
 Inputs: the Section 4.1 family A_ij = i^j mod n (synth.vandermonde_mod) for
 the primes 17..53 (oracle computed here) and n = 101, 199 (stored oracle
@@ -64,10 +67,12 @@ def _check_massager(a, res, det_abs=None):
     assert all(c.values()), c
     W = om.definition1_W(res.U, res.T)
     assert om.definition1(a, res.M, W, S)
-    # reduced entries: M and T columns mod s_j
+    # reduced entries: M and T columns mod s_j, U rows mod s_i
     n = len(S)
+    assert res.stats["cert_kind"] == 1 and res.stats["uc_dim"] >= n
     for j in range(n):
         for i in range(n):
+            assert 0 <= res.U[j, i] < S[j] or (S[j] == 1 and res.U[j, i] == 0)
             assert 0 <= res.M[i, j] < max(S[j], 1) or (S[j] == 1 and res.M[i, j] == 0)
             if i != j:
                 assert 0 <= res.T[i, j] < max(S[j], 1) or (S[j] == 1 and res.T[i, j] == 0)
@@ -164,6 +169,7 @@ def test_seeds_agree_and_restart(ctx, rg):
     ctx.force_cert_failures(1)
     res = rg.smith_massager(ctx, a, seed=9)
     assert res.stats["restarts"] >= 1
+    assert res.stats["uc_rejects"] >= 1 and res.stats["cert_kind"] == 1
     assert res.s == want
     _check_massager(a, res)
 
