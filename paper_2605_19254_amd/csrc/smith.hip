@@ -2392,10 +2392,14 @@ struct Driver {
         for (int attempt = 0; attempt <= kMaxRestarts + 3; ++attempt) {
             if (attempt) st.restarts += 1;
             // Phase 1: s_n (Monte Carlo; a proper divisor shows up in Phase 2).
+            // Eight right-hand sides: a prime power that only s_n carries is
+            // missed with probability at most 2^-8 (each random vector catches
+            // it with probability at least 1/2), at the cost of one lifting
+            // launch of up to 16 columns per step either way.
             tl = now_s();
             BigInt sn;
             std::vector<BigInt> Xp;
-            const int stl = lift_solve(pidx, 4, rng, sn, Xp);
+            const int stl = lift_solve(pidx, 8, rng, sn, Xp);
             st.t_lif += now_s() - tl;
             if (stl == RNS_EBOUND) continue;
             DRV_ST(stl);
