@@ -234,10 +234,118 @@ public:
             add_into(r + off, na + nb - off, t, len + nb);
         }
     }
+    // ---- the same products on 64-bit limbs (128-bit partial products), which
+    // take a quarter of the limb products; mul_mag packs pairs of 32-bit limbs
+    // into them for operands of kMul64Limbs 32-bit limbs and more.
+    static constexpr size_t kKara64Limbs = 48, kMul64Limbs = 16;
+    static void mul_school64(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *r) {
+        std::fill(r, r + na + nb, (uint64_t)0);
+        for (size_t j = 0; j < nb; ++j) {
+            const unsigned __int128 bj = b[j];
+            unsigned __int128 c = 0;
+            if (bj)
+                for (size_t i = 0; i < na; ++i) {
+                    c += a[i] * bj + r[i + j];
+                    r[i + j] = (uint64_t)c;
+                    c >>= 64;
+                }
+            r[j + na] = (uint64_t)c;
+        }
+    }
+    static uint64_t add_into64(uint64_t *r, size_t n, const uint64_t *a, size_t na) {
+        unsigned __int128 c = 0;
+        size_t i = 0;
+        for (; i < na; ++i) {
+            c += (unsigned __int128)r[i] + a[i];
+            r[i] = (uint64_t)c;
+            c >>= 64;
+        }
+        for (; c && i < n; ++i) {
+            c += r[i];
+            r[i] = (uint64_t)c;
+            c >>= 64;
+        }
+        return (uint64_t)c;
+    }
+    static uint64_t sub_into64(uint64_t *r, size_t n, const uint64_t *a, size_t na) {
+        uint64_t br = 0;
+        size_t i = 0;
+        for (; i < na; ++i) {
+            const uint64_t x = r[i], y = a[i];
+            const uint64_t d = x - y - br;
+            br = (x < y) || (x == y && br) ? 1 : 0;
+            r[i] = d;
+        }
+        for (; br && i < n; ++i) {
+            br = r[i] == 0 ? 1 : 0;
+            r[i] -= 1;
+        }
+        return br;
+    }
+    static size_t kara64_scratch(size_t n) {
+        return n < kKara64Limbs ? 0 : 4 * (n - n / 2 + 1) + kara64_scratch(n - n / 2 + 1);
+    }
+    // As kara, on 64-bit limbs.
+    static void kara64(const uint64_t *a, const uint64_t *b, size_t n, uint64_t *r, uint64_t *w) {
+        if (n < kKara64Limbs) {
+            mul_school64(a, n, b, n, r);
+            return;
+        }
+        const size_t lo = n / 2, hi = n - lo;
+        kara64(a, b, lo, r, w);
+        kara64(a + lo, b + lo, hi, r + 2 * lo, w);
+        uint64_t *sa = w, *sb = w + hi + 1, *z1 = w + 2 * (hi + 1);
+        std::copy(a + lo, a + n, sa);
+        sa[hi] = add_into64(sa, hi, a, lo);
+        std::copy(b + lo, b + n, sb);
+        sb[hi] = add_into64(sb, hi, b, lo);
+        kara64(sa, sb, hi + 1, z1, w + 4 * (hi + 1));
+        sub_into64(z1, 2 * hi + 2, r, 2 * lo);
+        sub_into64(z1, 2 * hi + 2, r + 2 * lo, 2 * hi);
+        add_into64(r + lo, 2 * n - lo, z1, std::min(2 * hi + 2, 2 * n - lo));
+    }
+    static void mul_into64(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *r) {
+        if (na < nb) {
+            std::swap(a, b);
+            std::swap(na, nb);
+        }
+        if (nb < kKara64Limbs) {
+            mul_school64(a, na, b, nb, r);
+            return;
+        }
+        const size_t ws = kara64_scratch(nb);
+        std::vector<uint64_t> w(ws + (na == nb ? 0 : 2 * nb));
+        if (na == nb) {
+            kara64(a, b, nb, r, w.data());
+            return;
+        }
+        uint64_t *t = w.data() + ws;
+        std::fill(r, r + na + nb, (uint64_t)0);
+        for (size_t off = 0; off < na; off += nb) {
+            const size_t len = std::min(nb, na - off);
+            if (len == nb)
+                kara64(a + off, b, nb, t, w.data());
+            else
+                mul_into64(a + off, len, b, nb, t);
+            add_into64(r + off, na + nb - off, t, len + nb);
+        }
+    }
     static std::vector<uint32_t> mul_mag(const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) {
         if (a.empty() || b.empty()) return {};
         std::vector<uint32_t> r(a.size() + b.size());
-        mul_into(a.data(), a.size(), b.data(), b.size(), r.data());
+        if (std::min(a.size(), b.size()) < kMul64Limbs) {
+            mul_into(a.data(), a.size(), b.data(), b.size(), r.data());
+        } else {
+            const size_t na = (a.size() + 1) / 2, nb = (b.size() + 1) / 2;
+            std::vector<uint64_t> buf(na + nb + na + nb);
+            uint64_t *a64 = buf.data(), *b64 = a64 + na, *r64 = b64 + nb;
+            for (size_t i = 0; i < na; ++i)
+                a64[i] = a[2 * i] | ((2 * i + 1 < a.size() ? (uint64_t)a[2 * i + 1] : 0) << 32);
+            for (size_t i = 0; i < nb; ++i)
+                b64[i] = b[2 * i] | ((2 * i + 1 < b.size() ? (uint64_t)b[2 * i + 1] : 0) << 32);
+            mul_into64(a64, na, b64, nb, r64);
+            for (size_t i = 0; i < r.size(); ++i) r[i] = (uint32_t)(r64[i / 2] >> (32 * (i % 2)));
+        }
         while (!r.empty() && r.back() == 0) r.pop_back();
         return r;
     }

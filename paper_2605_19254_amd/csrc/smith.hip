@@ -1761,12 +1761,53 @@ struct Driver {
             if constexpr (std::is_same<Ring, msg::Ring64>::value) W[(size_t)e] = P1[(size_t)e].to_u64_mag();
             else W[(size_t)e] = P1[(size_t)e];
         });
-        const msg::SnfT<Ring> S = msg::snf_transform(F, W, n, t, par);
+        // Multiword s with many rows: the Smith form of the compression
+        // G P_1 ((t + 8) x t, G random with 16-bit entries) instead of P_1.
+        // E' = E_G G is then a left transform of P_1 (E' P_1 R = diag(d)), so
+        // -U P_1 R = [D 0] and U M = -I hold as before; G P_1 has the Smith
+        // form of P_1 unless G loses rank on P_1's columns modulo a prime of
+        // s (probability about 2^-8 per prime power), and a smaller batch
+        // that results is caught by the projection checks or Phase 3.
+        constexpr int64_t kCompressRows = 8;
+        const bool compress = !std::is_same<Ring, msg::Ring64>::value && n > 4 * (t + kCompressRows);
+        const int64_t nr = compress ? t + kCompressRows : n;
+        std::vector<uint32_t> G;
+        std::vector<V> Wc;
+        if (compress) {
+            SplitMix g{seed ^ 0x9E3779B97F4A7C15ull ^ ((uint64_t)t << 32) ^ (uint64_t)s.bit_length()};
+            G.resize((size_t)(nr * n));
+            for (auto &v : G) v = (uint32_t)(g.next() & 0xFFFF);
+            Wc.assign((size_t)(nr * t), F.zero());
+            par(nr * t, (double)n * 64, [&](int64_t e) {
+                const int64_t r = e / t, c = e % t;
+                BigInt sum(0);
+                for (int64_t i = 0; i < n; ++i) {
+                    const uint32_t gv = G[(size_t)(r * n + i)];
+                    if (gv) sum = sum + P1[(size_t)(i * t + c)].mul_small(gv);
+                }
+                Wc[(size_t)e] = F.from(sum);
+            });
+        }
+        const msg::SnfT<Ring> S = msg::snf_transform(F, compress ? Wc : W, nr, t, par);
         int64_t nontriv = 0;
         while (nontriv < t && !(F.big(S.d[(size_t)nontriv]) == s)) ++nontriv;
         *done = fin || nontriv <= t - extra;
         const int64_t take = *done ? nontriv : t - extra;
-        const std::vector<V> E = msg::left_rows(F, S, n, take, par);
+        std::vector<V> E = msg::left_rows(F, S, nr, take, par);
+        if (compress) {                                      // E' = E_G G: take x n
+            std::vector<V> Ef((size_t)(take * n));
+            par(take * n, (double)nr * 64, [&](int64_t e) {
+                const int64_t j = e / n, i = e % n;
+                BigInt sum(0);
+                for (int64_t r = 0; r < nr; ++r) {
+                    const uint32_t gv = G[(size_t)(r * n + i)];
+                    const V &ev = E[(size_t)(j * nr + r)];
+                    if (gv && !F.is_zero(ev)) sum = sum + F.big(ev).mul_small(gv);
+                }
+                Ef[(size_t)e] = F.from(sum);
+            });
+            E.swap(Ef);
+        }
         b.s = s;
         b.S.assign((size_t)take, BigInt(0));
         b.M.assign((size_t)(take * n), BigInt(0));
