@@ -97,8 +97,11 @@ def parse():
     ap.add_argument("--massager-max", type=int, default=2003,
                     help="largest n of the Smith massager leg (Section 4.1 family; 0 = skip)")
     ap.add_argument("--only", default="", choices=["", "batched", "smith", "serving", "lifting", "smith64",
-                                                 "planted2000", "stress", "massager"],
+                                                 "planted2000", "stress", "massager", "unimodular"],
                     help="run only this workload (for profiling)")
+    ap.add_argument("--unimodular-n", type=int, default=4096,
+                    help="matrix order of the unimodularity certificate leg (Phase 3's certificate "
+                         "alone; 0 = skip)")
     ap.add_argument("--lifting-n", type=int, default=10007,
                     help="matrix order of the --only lifting workload (one random Smith-form solve)")
     ap.add_argument("--calibrate-iters", type=int, default=300000,
@@ -457,6 +460,49 @@ def run_massager(rg, nmax):
             "paper_hardware": "Apple M4 Max, OpenBLAS (Section 4)", "sizes": out}
 
 
+def run_unimodular(rg, n):
+    """Phase 3's certificate alone (rns_unimodular_certify, Section 2.2) on a
+    unimodular n x n matrix L U (L, U unit triangular with entries in
+    {-1, 0, 1}, rows and columns permuted, seed 0) and on its twin with
+    det = 2 (last row of L doubled): one timed call each after a warm-up.  The
+    verdicts are checked: True for L U, False after exactly the needed steps
+    for the twin (a wrong residue at any step would break one of the two)."""
+    import numpy as np
+
+    def lu(m, det):
+        rng = np.random.default_rng(0)
+        L = np.tril(rng.integers(-1, 2, size=(m, m)), -1) + np.eye(m, dtype=np.int64)
+        U = np.triu(rng.integers(-1, 2, size=(m, m)), 1) + np.eye(m, dtype=np.int64)
+        L[m - 1, :] *= det
+        # |entries| <= 2 m < 2^53: the double product is exact (and uses BLAS)
+        D = np.rint(L.astype(np.float64) @ U.astype(np.float64)).astype(np.int64)
+        pr, pc = rng.permutation(m), rng.permutation(m)
+        return np.ascontiguousarray(D[pr][:, pc])
+
+    out = {"workload": "unimodularity certificate of an n x n unimodular L U product and its det-2 twin "
+                       "(entries of L, U in {-1, 0, 1}, seed 0)", "n": n}
+    with rg.Context(device=0, L=2) as ctx:
+        rg.unimodular_certify(ctx, lu(256, 1))                               # warm-up
+        for name, det in (("unimodular", 1), ("det2", 2)):
+            d = lu(n, det)
+            print("[bench] unimodular %s n=%d: input built" % (name, n), file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            r = rg.unimodular_certify(ctx, d)
+            t = time.perf_counter() - t0
+            want = det == 1
+            if r.verdict is not want or (not want and r.info["steps"] != r.info["steps_needed"]):
+                raise SystemExit("bench.py: unimodular certificate gave the wrong verdict for %s" % name)
+            info = dict(r.info)
+            out[name] = {"seconds": t, "verdict": r.verdict, "steps": info["steps"],
+                         "steps_needed": info["steps_needed"], "x_primes": info["x_primes"],
+                         "q_primes": info["q_primes"], "log2_bound": info["log2_bound"],
+                         "residue_ops": info["residue_ops"], "products": info["products"],
+                         "residue_ops_per_s": info["residue_ops"] / t}
+            print("[bench] unimodular %s n=%d %.3f s (%d steps)" % (name, n, t, info["steps"]),
+                  file=sys.stderr, flush=True)
+    return out
+
+
 def _serving_stream(count, rate, seed, tail):
     """Serving requests: Poisson arrivals at `rate`, n log-uniform in
     [100, 4000], entries uniform in [-2^10, 2^10] (a singular draw is
@@ -723,6 +769,16 @@ def main():
 
     n, L = args.n, args.primes
     dev = torch.device("cuda:0")
+    if args.copy_bytes > 0:
+        src = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.only == "unimodular":
+        print(json.dumps(run_unimodular(rg, args.unimodular_n)), flush=True)
+        return
     if args.only == "batched":
         print(json.dumps(run_batched(rg, torch, dev, args.batched, args.batched_steps)), flush=True)
         return
@@ -749,13 +805,6 @@ def main():
     A = torch.from_numpy(a_np).to(dev)
     B = torch.from_numpy(b_np).to(dev)
     ctx = rg.Context(device=0, L=L)
-    if args.copy_bytes > 0:
-        src = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     ra = torch.empty((L, n, n), dtype=torch.int32, device=dev)
     rb = torch.empty((L, n, n), dtype=torch.int32, device=dev)
     rc = torch.empty((L, n, n), dtype=torch.int32, device=dev)
@@ -913,6 +962,7 @@ def main():
     rec["serving"] = run_serving(rg, args.serving) if args.serving > 0 else None
     print("[bench] serving done", file=sys.stderr, flush=True)
     rec["massager"] = run_massager(rg, args.massager_max) if args.massager_max > 0 else None
+    rec["unimodular"] = run_unimodular(rg, args.unimodular_n) if args.unimodular_n > 0 else None
     print("[bench] massager done", file=sys.stderr, flush=True)
     if args.cpu_rows > 0:
         primes = ctx.primes[:L]

@@ -414,6 +414,11 @@ typedef struct rns_smith_stats {
     int uc_rejects;        /* cert_kind 1: massagers the certificate rejected
                               (each followed by a restart) */
     int64_t uc_dim;        /* cert_kind 1: dimension of the linearized B */
+    double t_uc_cert;      /* cert_kind 1: seconds of the certificate proper
+                              (inverse mod X and the steps); the rest of t_uc
+                              builds the reduced massager and linearized B */
+    int uc_x_primes;       /* cert_kind 1: primes in the lifting modulus X */
+    int uc_lambda;         /* cert_kind 1: linearization base 2^uc_lambda */
 } rns_smith_stats;
 
 /*

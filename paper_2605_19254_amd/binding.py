@@ -83,7 +83,7 @@ class RnsSmithStats(ctypes.Structure):
                 ("columns", _I32), ("path", _I32), ("cert_exact", _I32),
                 ("lift_a_bytes", _I32), ("lift_kernels", _I32), ("t_host_cpu", ctypes.c_double),
                 ("batches", _I32), ("cert_kind", _I32), ("uc_steps", _I32), ("uc_rejects", _I32),
-                ("uc_dim", _I64)]
+                ("uc_dim", _I64), ("t_uc_cert", ctypes.c_double), ("uc_x_primes", _I32), ("uc_lambda", _I32)]
 
 
 def _sig(name, res, args):

@@ -2380,6 +2380,9 @@ struct Driver {
         DRV_ST(rc);
         st.uc_steps = ui.steps;
         st.uc_dim = N;
+        st.t_uc_cert = ui.seconds;
+        st.uc_x_primes = ui.j;
+        st.uc_lambda = lam;
         *ok = ui.verdict == 1;
         return RNS_OK;
     }

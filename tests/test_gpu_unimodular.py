@@ -52,7 +52,8 @@ def _lu(n, seed, det=1):
     L = np.tril(rng.integers(-1, 2, size=(n, n)), -1) + np.eye(n, dtype=np.int64)
     U = np.triu(rng.integers(-1, 2, size=(n, n)), 1) + np.eye(n, dtype=np.int64)
     L[n - 1, :] *= det
-    D = L @ U
+    # |entries| <= 2 n < 2^53: the double product is exact (and fast)
+    D = np.rint(L.astype(np.float64) @ U.astype(np.float64)).astype(np.int64)
     pr, pc = rng.permutation(n), rng.permutation(n)
     return np.ascontiguousarray(D[pr][:, pc]).astype(np.int64)
 
