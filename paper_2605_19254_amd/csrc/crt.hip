@@ -21,11 +21,21 @@
 // below 1 errs by less than 2^-40.9), which the host checks before choosing
 // this form; it also requires B < 2^(64W-1), so the result cannot overflow.
 //
-// Both kernels take one job by value or a table of jobs in device memory
+// Exact Lagrange form (k_crt_exact, no bound needed).  The same sum S over
+// 32-bit limbs: each limb column accumulates y_j times limb k of M/p_j with
+// 32 x 32 -> 64-bit multiply-adds (products below 2^58, so 32 primes fit a
+// 64-bit column before the carries are propagated), then a = floor(alpha)
+// and x = S - a M.  alpha errs by less than 2^-40, so a is floor(S / M) or
+// one off when S / M lies that close to an integer; one addition or
+// subtraction of M brings x into [0, M) in every case, and x > M - x picks
+// the negative representative x - M.  Exact for any residues.
+//
+// The kernels take one job by value or a table of jobs in device memory
 // (every product of a batched plan in one launch).
 #include "reduce_crt.hpp"
 
 #include <algorithm>
+#include <cmath>
 
 using namespace rns;
 
@@ -406,6 +416,168 @@ bool crt_fast_ok(const rns_ctx *ctx, int begin, int L, const uint64_t *bound_wor
     return limbs_cmp(D, T) >= 0;
 }
 
+// One entry per thread; KT bounds the 32-bit limbs K of the computation (K is
+// even: the table's words of M / p_j and M, two limbs each).
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_crt_exact(CrtJob J, int64_t total_tiles,
+                                                     const PrimeConst *__restrict__ pc_all, int W, int K) {
+    const int tid = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        const int64_t i = t / J.col_tiles;
+        const int64_t c_lane = (t - i * J.col_tiles) * kBlock + tid;
+        const bool valid = c_lane < J.cols;
+        const int64_t c = valid ? c_lane : J.cols - 1;        // in bounds; the store is skipped below
+        const auto src = gptr(J.res + i * J.ldr + c);
+        const auto pc = cptr(pc_all + J.prime_begin);
+        const auto cinv = cptr(J.lag_c);
+        const auto mj = cptr(reinterpret_cast<const uint32_t *>(J.lag_mj));
+        const auto m32 = cptr(reinterpret_cast<const uint32_t *>(J.lag_m));
+        const int L = J.L;
+        const int64_t ps = J.ps;
+        uint64_t acc[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) acc[k] = 0;
+        double alpha = 0.0;
+        auto settle = [&]() {                       // carries up, every column below 2^32 again
+            uint64_t carry = 0;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                if (k < K) {
+                    const uint64_t v = acc[k] + carry;
+                    acc[k] = v & 0xFFFFFFFFull;
+                    carry = v >> 32;
+                }
+            }
+        };
+        for (int j0 = 0; j0 < L; j0 += 8) {
+            uint32_t r[8];                          // eight loads in flight at a time
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = src[(int64_t)min(j0 + q, L - 1) * ps];   // in bounds
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + q;
+                if (j >= L) break;
+                const PC2 P{pc[j].pf, pc[j].pinv};
+                double y = modp((double)r[q] * cinv[j], P);
+                y = y < 0.0 ? y + P.pf : y;
+                alpha = fma(y, P.pinv, alpha);
+                const uint64_t yi = (uint64_t)y;
+                const auto m = mj + (int64_t)j * K;
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    if (k < K) acc[k] += yi * (uint64_t)m[k];
+            }
+            if ((j0 & 31) == 24) settle();          // at most 32 terms per column between settles
+        }
+        settle();
+        // x = S - a M with a = floor(alpha) (a < 64), as K limbs with a sign.
+        const uint64_t a = (uint64_t)floor(alpha);
+        int64_t borrow = 0;
+        uint64_t mc = 0;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            if (k < K) {
+                const uint64_t prod = a * (uint64_t)m32[k] + mc;
+                mc = prod >> 32;
+                const int64_t d = (int64_t)acc[k] - (int64_t)(prod & 0xFFFFFFFFull) - borrow;
+                borrow = d < 0 ? 1 : 0;
+                acc[k] = (uint64_t)(d + (borrow << 32));
+            }
+        }
+        const bool below = borrow != 0 || mc != 0;  // x < 0: S < a M
+        // One correction: x + M when below, x - M when x >= M.
+        // x >= M, compared from the top limb (a branch-free scan over the
+        // unrolled limbs: the first difference from the top decides).
+        bool ge = !below, decided = false;
+#pragma unroll
+        for (int k = KT - 1; k >= 0; --k) {
+            if (k < K && !decided && acc[k] != m32[k]) {
+                ge = ge && acc[k] > m32[k];
+                decided = true;
+            }
+        }
+        if (below || ge) {
+            int64_t cb = 0;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                if (k < K) {
+                    const int64_t d = below ? (int64_t)acc[k] + (int64_t)m32[k] + cb
+                                            : (int64_t)acc[k] - (int64_t)m32[k] + cb;
+                    cb = d >> 32;                                   // -1, 0 or 1
+                    acc[k] = (uint64_t)d & 0xFFFFFFFFull;
+                }
+            }
+        }
+        // 0 <= x < M; the negative representative when x > M - x.
+        uint64_t dm[KT];
+        int64_t cb = 0;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            if (k < K) {
+                const int64_t d = (int64_t)m32[k] - (int64_t)acc[k] + cb;
+                cb = d >> 32;
+                dm[k] = (uint64_t)d & 0xFFFFFFFFull;
+            }
+        }
+        bool neg = false, dec = false;
+#pragma unroll
+        for (int k = KT - 1; k >= 0; --k) {
+            if (k < K && !dec && acc[k] != dm[k]) {
+                neg = acc[k] > dm[k];
+                dec = true;
+            }
+        }
+        // Magnitude into W words; it fits when below 2^(64W-1) (or equal, for
+        // a negative value).
+        bool high = false, at_limit = true;
+        uint64_t mag_top = 0;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            if (k >= K) continue;
+            const uint64_t v = neg ? dm[k] : acc[k];
+            if (k >= 2 * W && v) high = true;
+            if (k == 2 * W - 1) mag_top = v;
+            else if (k < 2 * W - 1 && v) at_limit = false;
+        }
+        bool fits = !high && (mag_top >> 31) == 0;
+        if (neg && !high && mag_top == 0x80000000ull && at_limit) fits = true;
+        if (!valid) continue;
+        if (!fits) atomicOr(J.status, 1);
+        const auto dst = gptr_w(J.out + (i * J.ldo + c) * W);
+        uint64_t carry = 1;
+        for (int w = 0; w < W; ++w) {
+            const int k0 = 2 * w, k1 = 2 * w + 1;
+            uint64_t lo = 0, hi = 0;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                if (k == k0 && k < K) lo = neg ? dm[k] : acc[k];
+                if (k == k1 && k < K) hi = neg ? dm[k] : acc[k];
+            }
+            uint64_t v = lo | (hi << 32);
+            if (neg) {
+                const uint64_t nv = ~v;
+                v = nv + carry;
+                carry = (v < nv) ? 1 : 0;
+            }
+            dst[w] = v;
+        }
+    }
+}
+
+int launch_crt_exact(const CrtJob &j, int64_t total_tiles, const PrimeConst *pc, int W, int K, hipStream_t s) {
+    const unsigned grid = (unsigned)std::min<int64_t>(total_tiles, 1 << 20);
+#define RNS_EX(KT_) hipLaunchKernelGGL(k_crt_exact<KT_>, dim3(grid), dim3(kBlock), 0, s, j, total_tiles, pc, W, K)
+    if (K <= 8) RNS_EX(8);
+    else if (K <= 16) RNS_EX(16);
+    else if (K <= 24) RNS_EX(24);
+    else if (K <= 32) RNS_EX(32);
+    else if (K <= 44) RNS_EX(44);
+    else if (K <= 56) RNS_EX(56);
+    else return RNS_ENOTSUP;
+#undef RNS_EX
+    return RNS_OK;
+}
+
 void launch_crt(bool fast, int W, int E, const CrtJob &job0, const CrtJob *jobs, int njobs,
                 int64_t total_tiles, const PrimeConst *pc, const double *garner, hipStream_t s) {
     const int chunk = njobs > 1 ? kChunk : 1;
@@ -457,8 +629,26 @@ extern "C" int crt_reconstruct(rns_ctx *ctx, const uint32_t *res, int64_t rows, 
     j.status = d_status ? d_status : ctx->d_status;
     j.tile_begin = 0;
     const bool fast = crt_fast_ok(ctx, prime_begin, L, bound_words, Wb, W);
-    if (!fast && !ctx->crt_garner)   // the exact form on the matrix cores (digits_gemm.hip)
+    if (!fast && ctx->crt_form == 1)   // the exact form on the matrix cores (digits_gemm.hip)
         return crt_mfma(ctx, res, rows, cols, ldr, plane_stride, prime_begin, L, out, W, ldo, j.status, s);
+    if (!fast && ctx->crt_form == 0) {  // the exact Lagrange form on 32-bit limbs
+        int Wm = 1;                      // words of M, plus one for S < L M
+        {
+            double bits = 0;
+            for (int q = 0; q < L; ++q) bits += std::log2((double)ctx->primes[prime_begin + q]);
+            Wm = (int)((bits + 7.0) / 64.0) + 1;
+        }
+        const LagrangeTable *lt = nullptr;
+        int st = lagrange_table(ctx, prime_begin, L, Wm, &lt, s);
+        if (st != RNS_OK) return st;
+        j.lag_c = lt->d_c; j.lag_mj = lt->d_mj; j.lag_m = lt->d_m;
+        j.col_tiles = crt_col_tiles(cols, 1);
+        ProfScope ps(ctx, "k_crt_exact", s);
+        st = launch_crt_exact(j, crt_tiles(rows, cols, 1), ctx->d_prime, W, 2 * Wm, s);
+        if (st != RNS_OK) return st;
+        RNS_HIP(hipGetLastError());
+        return RNS_OK;
+    }
     const int E = crt_entries(fast, W, L);
     j.col_tiles = crt_col_tiles(cols, E);
     if (fast) {

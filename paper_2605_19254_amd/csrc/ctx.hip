@@ -165,6 +165,11 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
     if (const char *e = std::getenv("RNS_INT8_KERNEL")) ctx->int8_kernel = std::atoi(e);
     if (const char *e = std::getenv("RNS_LIFT_VECTOR")) ctx->lift_vector_only = std::atoi(e) != 0;
     if (const char *e = std::getenv("RNS_CRT_GARNER")) ctx->crt_garner = std::atoi(e) != 0;
+    if (const char *e = std::getenv("RNS_CRT_FORM")) {
+        const std::string f(e);
+        ctx->crt_form = f == "limbs" ? 0 : (f == "garner" ? 2 : 1);
+    }
+    if (ctx->crt_garner) ctx->crt_form = 2;
     if (const char *e = std::getenv("RNS_MASSAGER_R0")) ctx->massager_r0 = std::max(1, std::atoi(e));
     ctx->primes = ps;
 

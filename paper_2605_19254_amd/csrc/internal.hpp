@@ -103,7 +103,9 @@ struct rns_ctx {
     int force_cert_failures = 0;
     int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
     bool lift_vector_only = false;    // lifting products on the vector units only (RNS_LIFT_VECTOR)
-    bool crt_garner = false;          // exact CRT by the mixed-radix kernel (RNS_CRT_GARNER), not the matrix cores
+    bool crt_garner = false;          // exact CRT by the mixed-radix kernel (RNS_CRT_GARNER)
+    int crt_form = 1;                 // exact CRT: 1 the matrix cores (k_crt_mfma), 0 Lagrange on 32-bit limbs
+                                      // (k_crt_exact, RNS_CRT_FORM=limbs), 2 Garner (RNS_CRT_FORM=garner)
     int massager_r0 = 4;              // invariants taken by the first massager batch (RNS_MASSAGER_R0)
     rns_ctx *aux = nullptr;            // wide-basis context of the Smith-form driver
     // Smith-form solves on this context run on one stream, created by the

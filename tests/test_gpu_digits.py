@@ -171,3 +171,45 @@ def test_crt_mixed_radix_form_still_exact(rg=None):
     finally:
         cg.close()
         cm.close()
+
+
+@pytest.mark.parametrize("L,W", [(2, 1), (24, 10), (24, 4), (40, 17), (64, 28)])
+def test_crt_limb_form_matches_oracle(L, W):
+    """The exact Lagrange form on 32-bit limbs (k_crt_exact, selected with
+    RNS_CRT_FORM=limbs when a context is created) against the oracle's CRT:
+    full-range values (both signs, the endpoints +-(M-1)/2, values beyond W
+    words that must raise the status word) with ragged row lengths."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_19254_amd as rg
+    _say("crt limb form", L, W)
+    dev = torch.device("cuda:0")
+    ps = PRIMES[:L]
+    M = orns.CRTBasis(ps).M
+    rng = np.random.default_rng(L * 100 + W)
+    rows, cols = 3, 201
+    vals = _values(rng, M, rows * cols)
+    vals[0], vals[1], vals[2] = (M - 1) // 2, -((M - 1) // 2), 0
+    res = torch.from_numpy(_residues_of(vals, ps, rows, cols)).to(dev)
+    os.environ["RNS_CRT_FORM"] = "limbs"
+    try:
+        cl = rg.Context(device=0, L=L)
+    finally:
+        del os.environ["RNS_CRT_FORM"]
+    try:
+        got = rg.crt_reconstruct(cl, res, L=L, W=W)
+        torch.cuda.synchronize()
+        words = got.cpu().numpy().reshape(rows * cols, W)
+        lim = 1 << (64 * W - 1)
+        overflow = False
+        for e, v in enumerate(vals):
+            if -lim <= v < lim:
+                want = [(v >> (64 * k)) & ((1 << 64) - 1) for k in range(W)]
+                assert [int(x) for x in words[e].astype(np.uint64)] == want, e
+            else:
+                overflow = True
+        assert (cl.status() != 0) == overflow
+    finally:
+        cl.close()
