@@ -2163,48 +2163,74 @@ struct Driver {
             }
         });
         if (m == 0) return RNS_OK;
-        // Word positions (s_t < 2^62) have their products on the GPU.
-        std::vector<int64_t> wp, bp;
-        for (int64_t t = 0; t < m; ++t) (R.s[(size_t)t].bit_length() <= 62 ? wp : bp).push_back(t);
-        const int64_t mw = (int64_t)wp.size();
-        // G = A M S^-1.
-        R.G.assign((size_t)(n * m), 0);
-        std::atomic<bool> bad{false};
-        if (mw > 0) {
-            std::vector<int64_t> Mh((size_t)(n * mw));
-            for (int64_t c = 0; c < mw; ++c)
-                for (int64_t k = 0; k < n; ++k) Mh[(size_t)(k * mw + c)] = (int64_t)R.M[(size_t)wp[(size_t)c]][(size_t)k];
-            std::vector<uint64_t> C;
-            int W = 0;
-            DRV_ST(exact_product(A, n, n, Mh.data(), mw, std::log2(std::max(amax, 1.0) * (double)n) + 63.0, C, W));
-            par(n, (double)mw * 8, [&](int64_t i) {
-                for (int64_t c = 0; c < mw; ++c) {
-                    const uint64_t *x = C.data() + (size_t)((i * mw + c) * W);
-                    const bool neg = (x[W - 1] >> 63) != 0;
-                    unsigned __int128 v = 0;               // |x| < 2^99 (n max|a| < 2^36)
-                    for (int w = std::min(W, 2) - 1; w >= 0; --w) v = (v << 64) | (neg ? ~x[w] : x[w]);
-                    if (neg) v += 1;
-                    const uint64_t sb = R.s[(size_t)wp[(size_t)c]].to_u64_mag();
-                    if (v % sb) bad = true;
-                    const int64_t g = (int64_t)(uint64_t)(v / sb);
-                    R.G[(size_t)(i * m + wp[(size_t)c])] = neg ? -g : g;
+        // Both products on the GPU as exact residue products of 32-bit limbs:
+        // position t contributes 2 w[t] limb rows of U (limb l of every entry)
+        // and 2 w[t] limb columns of M, so with Ul (rows x n) and Ml (n x
+        // cols), (U M)_ab = sum_{l, l'} (Ul Ml)[a_l][b_l'] 2^(32 (l + l')) and
+        // (A M)_ib = sum_l' (A Ml)[i][b_l'] 2^(32 l'); every entry of the
+        // products is below n 2^64 (resp. n max|a| 2^32).
+        std::vector<int64_t> off((size_t)m + 1, 0);
+        for (int64_t t = 0; t < m; ++t) off[(size_t)t + 1] = off[(size_t)t] + 2 * R.w[(size_t)t];
+        const int64_t C = off[(size_t)m];
+        std::vector<int64_t> Ul((size_t)(C * n)), Ml((size_t)(n * C));
+        par(m, (double)n * 8, [&](int64_t t) {
+            const int W = R.w[(size_t)t];
+            for (int l = 0; l < 2 * W; ++l) {
+                const int64_t r = off[(size_t)t] + l;
+                for (int64_t k = 0; k < n; ++k) {
+                    const uint64_t u = R.U[(size_t)t][(size_t)(k * W + l / 2)];
+                    const uint64_t v = R.M[(size_t)t][(size_t)(k * W + l / 2)];
+                    Ul[(size_t)(r * n + k)] = (int64_t)((l & 1) ? u >> 32 : u & 0xFFFFFFFFull);
+                    Ml[(size_t)(k * C + r)] = (int64_t)((l & 1) ? v >> 32 : v & 0xFFFFFFFFull);
                 }
-            });
-        }
-        par((int64_t)bp.size() * n, (double)n * 64, [&](int64_t e) {
-            const int64_t b = bp[(size_t)(e / n)], i = e % n;
-            const int W = R.w[(size_t)b];
-            BigInt acc(0);
-            for (int64_t k = 0; k < n; ++k) {
-                const int64_t a = A[i * n + k];
-                if (a) acc = acc + from_words(R.M[(size_t)b].data() + k * W, W) * BigInt(a);
             }
-            BigInt q, r;
-            BigInt::divmod_floor(acc, R.s[(size_t)b], q, r);
-            if (!r.is_zero()) bad = true;
-            R.G[(size_t)(i * m + b)] = q.to_i64();
         });
-        // X = U M over the nontrivial positions, then T and V.
+        std::vector<uint64_t> PU, PA;
+        int WU = 0, WA = 0;
+        DRV_ST(exact_product(Ul.data(), C, n, Ml.data(), C, 64.0 + std::log2((double)n) + 1.0, PU, WU));
+        DRV_ST(exact_product(A, n, n, Ml.data(), C, std::log2(std::max(amax, 1.0) * (double)n) + 33.0, PA, WA));
+        std::atomic<bool> bad{false};
+        // Sum of 2-word entries shifted by 32-bit limbs into 64-bit slots of
+        // 32-bit digits (each slot receives at most 3 n-independent digits per
+        // term, far below 2^64), then the BigInt of the slots.
+        auto slots_to_big = [](std::vector<uint64_t> &sl) {
+            uint64_t carry = 0;
+            for (auto &v : sl) {
+                const uint64_t x = v + carry;
+                v = x & 0xFFFFFFFFull;
+                carry = x >> 32;
+            }
+            BigInt b(0);
+            b.mag.assign(sl.size(), 0);
+            for (size_t i = 0; i < sl.size(); ++i) b.mag[i] = (uint32_t)sl[i];
+            while (!b.mag.empty() && b.mag.back() == 0) b.mag.pop_back();
+            return b;
+        };
+        // G = A M S^-1: signed sums, positive and negative parts apart.
+        R.G.assign((size_t)(n * m), 0);
+        par(n, (double)C * 4, [&](int64_t i) {
+            std::vector<uint64_t> pos, neg;
+            for (int64_t b = 0; b < m; ++b) {
+                const int Wb = R.w[(size_t)b];
+                pos.assign((size_t)(2 * Wb + 4), 0);
+                neg.assign((size_t)(2 * Wb + 4), 0);
+                for (int l = 0; l < 2 * Wb; ++l) {
+                    const uint64_t *x = PA.data() + (size_t)((i * C + off[(size_t)b] + l) * WA);
+                    const bool ng = (x[WA - 1] >> 63) != 0;
+                    unsigned __int128 v = 0;                    // |x| < 2^100
+                    for (int w = std::min(WA, 2) - 1; w >= 0; --w) v = (v << 64) | (ng ? ~x[w] : x[w]);
+                    if (ng) v += 1;
+                    std::vector<uint64_t> &sl = ng ? neg : pos;
+                    for (int d = 0; d < 4 && v; ++d, v >>= 32) sl[(size_t)(l + d)] += (uint64_t)(v & 0xFFFFFFFFull);
+                }
+                const BigInt num = slots_to_big(pos) - slots_to_big(neg);
+                BigInt q, r;
+                BigInt::divmod_floor(num, R.s[(size_t)b], q, r);
+                if (!r.is_zero() || !q.fits_i64()) bad = true;
+                R.G[(size_t)(i * m + b)] = q.to_i64();
+            }
+        });
+        // X = U M, then T and V.
         R.T.assign((size_t)(m * m), BigInt(0));
         R.V.assign((size_t)(m * m), BigInt(0));
         auto finish = [&](int64_t a, int64_t b, const BigInt &x) {
@@ -2223,48 +2249,18 @@ struct Driver {
             }
             R.V[(size_t)(a * m + b)] = q;
         };
-        if (mw > 0) {
-            std::vector<int64_t> Uh((size_t)(mw * n)), Mh((size_t)(n * mw));
-            for (int64_t r = 0; r < mw; ++r)
-                for (int64_t k = 0; k < n; ++k) {
-                    Uh[(size_t)(r * n + k)] = (int64_t)R.U[(size_t)wp[(size_t)r]][(size_t)k];
-                    Mh[(size_t)(k * mw + r)] = (int64_t)R.M[(size_t)wp[(size_t)r]][(size_t)k];
+        par(m * m, (double)C, [&](int64_t e) {
+            const int64_t a = e / m, b = e % m;
+            const int Wa = R.w[(size_t)a], Wb = R.w[(size_t)b];
+            std::vector<uint64_t> sl((size_t)(2 * Wa + 2 * Wb + 4), 0);
+            for (int la = 0; la < 2 * Wa; ++la)
+                for (int lb = 0; lb < 2 * Wb; ++lb) {
+                    const uint64_t *x = PU.data() + (size_t)(((off[(size_t)a] + la) * C + off[(size_t)b] + lb) * WU);
+                    unsigned __int128 v = x[0];                 // < n 2^64 < 2^96
+                    if (WU > 1) v |= (unsigned __int128)x[1] << 64;
+                    for (int d = 0; d < 4 && v; ++d, v >>= 32) sl[(size_t)(la + lb + d)] += (uint64_t)(v & 0xFFFFFFFFull);
                 }
-            std::vector<uint64_t> C;
-            int W = 0;
-            DRV_ST(exact_product(Uh.data(), mw, n, Mh.data(), mw, 124.0 + std::log2((double)n), C, W));
-            par(mw, (double)mw * 16, [&](int64_t r) {
-                for (int64_t c = 0; c < mw; ++c) finish(wp[(size_t)r], wp[(size_t)c], from_words(C.data() + (size_t)((r * mw + c) * W), W));
-            });
-        }
-        // Pairs with a multiword position: word accumulators over the limbs.
-        std::vector<std::pair<int64_t, int64_t>> pairs;
-        for (int64_t a = 0; a < m; ++a)
-            for (int64_t b = 0; b < m; ++b)
-                if (R.s[(size_t)a].bit_length() > 62 || R.s[(size_t)b].bit_length() > 62) pairs.push_back({a, b});
-        par((int64_t)pairs.size(), (double)n * 64, [&](int64_t e) {
-            const int64_t a = pairs[(size_t)e].first, b = pairs[(size_t)e].second;
-            const int wa = R.w[(size_t)a], wb = R.w[(size_t)b];
-            std::vector<uint64_t> acc((size_t)(wa + wb + 2), 0);
-            for (int64_t k = 0; k < n; ++k) {
-                const uint64_t *u = R.U[(size_t)a].data() + k * wa;
-                const uint64_t *v = R.M[(size_t)b].data() + k * wb;
-                for (int i = 0; i < wa; ++i) {
-                    if (!u[i]) continue;
-                    unsigned __int128 carry = 0;
-                    for (int j = 0; j < wb; ++j) {
-                        const unsigned __int128 t = (unsigned __int128)u[i] * v[j] + acc[(size_t)(i + j)] + carry;
-                        acc[(size_t)(i + j)] = (uint64_t)t;
-                        carry = t >> 64;
-                    }
-                    for (size_t j = (size_t)(i + wb); carry && j < acc.size(); ++j) {
-                        const unsigned __int128 t = (unsigned __int128)acc[j] + carry;
-                        acc[j] = (uint64_t)t;
-                        carry = t >> 64;
-                    }
-                }
-            }
-            finish(a, b, from_words(acc.data(), (int)acc.size()));
+            finish(a, b, slots_to_big(sl));
         });
         *integral = !bad;
         return RNS_OK;
