@@ -1650,9 +1650,20 @@ struct Driver {
         using V = typename Ring::V;
         const uint32_t p = aux->primes[pidx];
         const double lp = std::log2((double)p);
-        // |s_n A^-1 J| <= |adj(A) J| <= n 2^7 H: K digits leave a 2^-24 margin,
-        // L top digits resolve s_n X_K / p^K to within 2^-24.
-        const int64_t K = (int64_t)std::ceil((abits + std::log2((double)n) + 7.0 + 24.0) / lp) + 1;
+        // |s_n A^-1 J| = |adj(A) J| s_n / |det A| <= n 2^7 H s_n / |det A|, and
+        // |det A| >= P, the product of the invariants found so far (the
+        // earlier batches' massager is integral, so det S divides det A);
+        // P includes s_n from the first batch on, so the bound only shrinks.
+        // K digits leave a 2^-24 margin, L top digits resolve s_n X_K / p^K to
+        // within 2^-24.
+        double lpf = 0;                                  // a lower bound on log2 P
+        for (const MBatch &b : B)
+            for (const BigInt &o : b.S) {
+                const double d = o.to_double();
+                lpf += std::isfinite(d) ? std::log2(std::max(1.0, d)) - 1e-9 : (double)o.bit_length() - 1.0;
+            }
+        const double shrink = std::min(0.0, (double)sn.bit_length() - lpf);
+        const int64_t K = (int64_t)std::ceil((abits + std::log2((double)n) + 7.0 + 24.0 + shrink) / lp) + 1;
         const int L = (int)std::min<int64_t>(K, (int64_t)std::ceil(((double)sn.bit_length() + 26.0) / lp) + 1);
         std::vector<int64_t> J((size_t)t * ldl, 0);
         for (int64_t c = 0; c < t; ++c)
