@@ -476,6 +476,20 @@ public:
         r.neg = false;
         return r;
     }
+    // floor(|x| / p) for p > 0 (the magnitude; the caller's values are
+    // non-negative).
+    BigInt div_small(uint32_t p) const {
+        BigInt q;
+        q.mag.resize(mag.size());
+        uint64_t rem = 0;
+        for (size_t i = mag.size(); i-- > 0;) {
+            const uint64_t cur = (rem << 32) | mag[i];
+            q.mag[i] = (uint32_t)(cur / p);
+            rem = cur % p;
+        }
+        while (!q.mag.empty() && q.mag.back() == 0) q.mag.pop_back();
+        return q;
+    }
     uint32_t mod_small(uint32_t p) const {   // non-negative residue
         uint64_t rem = 0;
         for (size_t i = mag.size(); i-- > 0;) rem = ((rem << 32) | mag[i]) % p;

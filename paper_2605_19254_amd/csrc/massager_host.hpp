@@ -453,20 +453,31 @@ struct PadicTable {
     int L;
     std::vector<V> B;                 // B[0] = B_0, B[l] = B_l
     std::vector<uint64_t> frac;       // frac[l] = floor(f_l 2^64), l = 1..L
-    PadicTable(const Ring &ring, const BigInt &sn, uint32_t p, int64_t K, int Ltop) : F(ring), L(Ltop) {
+    // a_l = floor(s_n / p^l) by repeated division by p, whose remainders d_l
+    // give the fractional parts by f_l = (d_l + f_{l-1}) / p (in 64-bit fixed
+    // point: each step adds less than one unit of error and divides the
+    // previous error by p, so frac[l] is within one unit of floor(2^64 f_l));
+    // B_l = -a_l (p^K mod s) mod s, the products independent (par).
+    PadicTable(const Ring &ring, const BigInt &sn, uint32_t p, int64_t K, int Ltop, const ParFor &par = seq_for)
+        : F(ring), L(Ltop) {
         BigInt pK(1);
         for (int64_t k = 0; k < K; ++k) pK = pK.mul_small(p);
         B.assign((size_t)L + 1, F.zero());
         frac.assign((size_t)L + 1, 0);
-        B[0] = F.from(-pK);
-        BigInt pl(1);
+        const V pKm = F.from(pK);
+        B[0] = F.neg(pKm);
+        std::vector<BigInt> a((size_t)L + 1);
+        a[0] = sn;
+        uint64_t fprev = 0;
         for (int l = 1; l <= L; ++l) {
-            pl = pl.mul_small(p);
-            BigInt a, r;
-            BigInt::divmod_trunc(sn, pl, a, r);
-            B[(size_t)l] = F.from(-(a * pK));
-            frac[(size_t)l] = (r.shl(64) / pl).to_u64_mag();
+            const uint32_t d = a[(size_t)l - 1].mod_small(p);
+            a[(size_t)l] = a[(size_t)l - 1].div_small(p);
+            frac[(size_t)l] = (uint64_t)((((unsigned __int128)d << 64) + fprev) / p);
+            fprev = frac[(size_t)l];
         }
+        par(L, 8.0 * F.cost(), [&](int64_t l) {
+            B[(size_t)l + 1] = F.neg(F.mul(F.from(a[(size_t)l + 1]), pKm));
+        });
     }
     // eval for cnt entries whose digit planes are contiguous (entry k's digit
     // of step K - l at dig[(L - l) stride + k]); out[k ostride].  The digit

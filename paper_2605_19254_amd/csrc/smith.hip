@@ -1636,6 +1636,62 @@ struct Driver {
     // primes of s divide s_n only to small powers).  RNS_EBOUND when s_n A^-1 J
     // is not integral (s_n misses a factor) or V is not a multiple of q (an
     // earlier batch was not maximal).
+    // Reading 21's evaluation for a multiword M' on the GPU: the dot
+    // products sum_l d_l B_l of every entry are one exact residue product of
+    // the 32-bit limbs of the B_l ((limbs x L) against the L digit planes, each
+    // sum below L 2^58), recombined per entry on host threads; the rounding
+    // term e comes from the fractions as in PadicTable::eval_block.  dig holds
+    // the top L digits of tr columns ([L][tr][ldl], plane j the digit of step
+    // K - L + j); Y's entries (row i, column c0 + c) are written.
+    int padic_eval_big(const msg::PadicTable<msg::RingBig> &tab, const msg::RingBig &F, const std::vector<uint32_t> &dig,
+                       int64_t tr, int64_t t, int64_t c0, std::vector<BigInt> &Y, bool *good) {
+        const int L = tab.L;
+        int64_t Wb = 1;
+        for (int l = 1; l <= L; ++l) Wb = std::max<int64_t>(Wb, (int64_t)tab.B[(size_t)l].mag.size());
+        const int64_t E = tr * ldl;
+        std::vector<int64_t> Am((size_t)(Wb * L), 0), Bm((size_t)(L * E));
+        for (int j = 0; j < L; ++j) {
+            const BigInt &b = tab.B[(size_t)(L - j)];
+            for (int64_t v = 0; v < (int64_t)b.mag.size(); ++v) Am[(size_t)(v * L + j)] = (int64_t)b.mag[(size_t)v];
+        }
+        const msg::ParFor par = host_par();
+        par(L, (double)E, [&](int64_t j) {
+            for (int64_t e = 0; e < E; ++e) Bm[(size_t)(j * E + e)] = (int64_t)dig[(size_t)(j * E + e)];
+        });
+        std::vector<uint64_t> Out;
+        int Wo = 0;
+        DRV_ST(exact_product(Am.data(), Wb, L, Bm.data(), E, 59.0 + std::log2((double)L), Out, Wo));
+        std::atomic<bool> fine{true};
+        par(tr * n, (double)Wb * 4, [&](int64_t q) {
+            const int64_t c = q / n, i = q % n, e = c * ldl + i;
+            unsigned __int128 fs = 0;
+            for (int l = 1; l <= L; ++l) fs += (unsigned __int128)tab.frac[(size_t)l] * dig[(size_t)((L - l) * E + e)];
+            const uint64_t ev = (uint64_t)((fs + ((unsigned __int128)1 << 63)) >> 64);
+            const unsigned __int128 ee = (unsigned __int128)ev << 64;
+            const unsigned __int128 dist = fs > ee ? fs - ee : ee - fs;
+            if (dist >= ((unsigned __int128)1 << 43)) fine = false;
+            std::vector<uint64_t> sl((size_t)(Wb + 4), 0);
+            for (int64_t v = 0; v < Wb; ++v) {
+                const uint64_t *x = Out.data() + (size_t)((v * E + e) * Wo);
+                unsigned __int128 val = x[0];
+                if (Wo > 1) val |= (unsigned __int128)x[1] << 64;
+                for (int d = 0; d < 4 && val; ++d, val >>= 32) sl[(size_t)(v + d)] += (uint64_t)(val & 0xFFFFFFFFull);
+            }
+            uint64_t carry = 0;
+            BigInt xb(0);
+            xb.mag.resize(sl.size());
+            for (size_t k = 0; k < sl.size(); ++k) {
+                const uint64_t z = sl[k] + carry;
+                xb.mag[k] = (uint32_t)z;
+                carry = z >> 32;
+            }
+            while (!xb.mag.empty() && xb.mag.back() == 0) xb.mag.pop_back();
+            Y[(size_t)(i * t + c0 + c)] = F.add(F.from(xb), F.mul_u64(tab.B[0], ev));
+        });
+        *good = fine;
+        return RNS_OK;
+    }
+
     int projection(int pidx, const BigInt &sn, const BigInt &s, const std::vector<MBatch> &B, int64_t t,
                    SplitMix &rng, std::vector<BigInt> &P1) {
         const BigInt u = coprime_part(sn, s);
@@ -1668,8 +1724,8 @@ struct Driver {
         std::vector<int64_t> J((size_t)t * ldl, 0);
         for (int64_t c = 0; c < t; ++c)
             for (int64_t r = 0; r < n; ++r) J[(size_t)c * ldl + r] = (int64_t)(rng.next() % 257) - 128;
-        const msg::PadicTable<Ring> tab(FM, sn, p, K, L);
         const msg::ParFor par = host_par();
+        const msg::PadicTable<Ring> tab(FM, sn, p, K, L, par);
         std::vector<V> Y((size_t)n * t);
         std::atomic<bool> ok{true};
         // With a word modulus and the matrix-core step kernels, the full runs
@@ -1679,6 +1735,14 @@ struct Driver {
         // ([L][tr][ldl]), in blocks of rows of one column (the digit planes
         // are read in order).
         auto host_eval = [&](const std::vector<uint32_t> &dig, int64_t c0, int64_t tr) {
+            if constexpr (std::is_same<Ring, msg::RingBig>::value) {
+                if (tr * n >= 16384) {                   // the dot products on the GPU
+                    bool good = true;
+                    const int rc = padic_eval_big(tab, FM, dig, tr, t, c0, Y, &good);
+                    if (rc != RNS_OK || !good) ok = false;
+                    return;
+                }
+            }
             const int64_t rb = std::is_same<Ring, msg::Ring64>::value ? 1024 : 256;
             const int64_t nrb = (n + rb - 1) / rb;
             par(tr * nrb, (double)rb * L * FM.cost() / 4.0, [&](int64_t q) {
