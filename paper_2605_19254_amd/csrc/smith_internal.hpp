@@ -52,6 +52,7 @@ struct LiftGroups {
     int groups = 1;
     int64_t r = 0, rm = 0, xh = 0, frag = 0;
     int64_t ring = INT64_MAX;
+    int64_t rbs = 0;        // 16-row blocks (grouped launches: the work items are rbs x groups)
 };
 struct LiftBufs {
     int64_t *R0, *R1;

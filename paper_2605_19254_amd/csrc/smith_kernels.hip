@@ -502,6 +502,30 @@ __global__ __launch_bounds__(64) void k_lift_frag(const uint32_t *__restrict__ v
     for (int i = 0; i < 4; ++i) frag[((int64_t)kt * 4 + i) * 64 + lane] = f[i];
 }
 
+// The work item (16-row block rb, group g) of a lifting launch.  Ungrouped:
+// rb = blockIdx.x.  Grouped (one-dimensional grid of lift_grid_grouped
+// work-groups): windows of kLiftWinR row blocks x kLiftWinG groups are dealt
+// round-robin to the eight XCDs (work-group w runs on XCD w mod 8), so the
+// work-groups of a window run on one XCD at about the same time and share
+// its L2 for their C (or A) blocks and their groups' right operands, instead
+// of each fetching both from beyond the L2.  False for the padding items.
+constexpr int64_t kLiftWinR = 4, kLiftWinG = 8;
+__device__ __forceinline__ bool lift_item(const LiftGroups &gr, int64_t &rb, int64_t &g) {
+    if (gr.groups <= 1) {
+        rb = blockIdx.x;
+        g = 0;
+        return true;
+    }
+    const int64_t w = blockIdx.x, xcd = w % 8, i = w / 8;
+    const int64_t per = kLiftWinR * kLiftWinG;
+    const int64_t st = (i / per) * 8 + xcd;              // window
+    const int64_t wgs = (gr.groups + kLiftWinG - 1) / kLiftWinG;
+    const int64_t within = i % per;
+    rb = (st / wgs) * kLiftWinR + within / kLiftWinG;
+    g = (st % wgs) * kLiftWinG + within % kLiftWinG;
+    return rb < gr.rbs && g < gr.groups;
+}
+
 // X[c][r] = sum_k C[r][k] Rm[c][k] mod p for one 16-row block per work-group;
 // its KS waves take KS slices of the 64-column steps and add their int32
 // sums in LDS.  Same step indexing as k_lift_x.
@@ -514,7 +538,8 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_x_mfma(const v4i_l *__
                                                          const v4i_l *__restrict__ Rmd, v4i_l *__restrict__ Xd,
                                                          LiftGroups gr) {
     __shared__ v4i_l part[KS][7][64];
-    const int64_t g = blockIdx.y;                        // group: its own vectors and buffers
+    int64_t rb, g;                                       // g: the group's own vectors and buffers
+    if (!lift_item(gr, rb, g)) return;
     Rm0 += g * gr.rm;
     Rm1 += g * gr.rm;
     Xh += g * gr.xh;
@@ -525,7 +550,6 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_x_mfma(const v4i_l *__
     uint32_t *__restrict__ X = Xh + (i_step % gr.ring) * t * ld;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t rb = blockIdx.x;
     const int kt0 = (int)((int64_t)KT * wave / KS), kt1 = (int)((int64_t)KT * (wave + 1) / KS);
     const int c = lane & 15;
     const bool cvalid = c < t;
@@ -640,7 +664,8 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
                                                                  const v4i_l *__restrict__ Xd,
                                                                  v4i_l *__restrict__ Rmd, LiftGroups gr) {
     __shared__ v4i_l part[KS][8][64];
-    const int64_t g = blockIdx.y;                        // group: its own vectors and buffers
+    int64_t rb, g;                                       // g: the group's own vectors and buffers
+    if (!lift_item(gr, rb, g)) return;
     R0 += g * gr.r;
     R1 += g * gr.r;
     Rm0 += g * gr.rm;
@@ -655,7 +680,6 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
     uint32_t *__restrict__ Rmn = (i_step & 1) ? Rm0 : Rm1;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t rb = blockIdx.x;
     const int kt0 = (int)((int64_t)KT * wave / KS), kt1 = (int)((int64_t)KT * (wave + 1) / KS);
     const int c = lane & 15;
     const bool cvalid = c < t;
@@ -1364,6 +1388,20 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
     hipLaunchKernelGGL(k_gj_load, grid, dim3(256), 0, s, A, n, ld, M, pr);
 }
 
+
+// Work-groups of a lifting launch: one per 16-row block, or for a grouped
+// launch the windows of lift_item, padded to a multiple of eight windows.
+unsigned lift_grid(unsigned rbs, const LiftGroups &gr) {
+    if (gr.groups <= 1) return rbs;
+    const int64_t wr = (rbs + kLiftWinR - 1) / kLiftWinR, wg = (gr.groups + kLiftWinG - 1) / kLiftWinG;
+    const int64_t windows = (wr * wg + 7) / 8 * 8;
+    return (unsigned)(windows * kLiftWinR * kLiftWinG);
+}
+LiftGroups lift_groups(unsigned rbs, LiftGroups gr) {
+    gr.rbs = rbs;
+    return gr;
+}
+
 template <int T, int RW, typename AT>
 static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, int t, uint32_t p,
                         const LiftBufs &b, int off, hipStream_t s) {
@@ -1391,8 +1429,8 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const v4i_l *ct = reinterpret_cast<const v4i_l *>(b.Ct);
         // Eight waves per 16-row block, two work-groups per CU.
         if (frag)
-            hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(rbs, (unsigned)b.grp.groups), dim3(512), 0, s, ct, n, ld,
-                               KT, b.Rm0, b.Rm1, t, p, b.Xh, b.base, off, rmd, xd, b.grp);
+            hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(lift_grid(rbs, b.grp)), dim3(512), 0, s, ct, n, ld,
+                               KT, b.Rm0, b.Rm1, t, p, b.Xh, b.base, off, rmd, xd, lift_groups(rbs, b.grp));
         else
             hipLaunchKernelGGL((k_lift_x_mfma<8, false>), dim3(rbs), dim3(512), 0, s, ct, n, ld, KT, b.Rm0, b.Rm1, t,
                                p, b.Xh, b.base, off, rmd, xd, LiftGroups{});
@@ -1407,8 +1445,9 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const v4i_l *xdc = reinterpret_cast<const v4i_l *>(b.Xd);
         v4i_l *rmdw = reinterpret_cast<v4i_l *>(b.Rmd);
         if (frag)
-            hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(rbs, (unsigned)b.grp.groups), dim3(512), 0, s, at, n,
-                               ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw, b.grp);
+            hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(lift_grid(rbs, b.grp)), dim3(512), 0, s, at, n,
+                               ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw,
+                               lift_groups(rbs, b.grp));
         else
             hipLaunchKernelGGL((k_lift_r_mfma<8, false>), dim3(rbs), dim3(512), 0, s, at, n, ld, KT, b.Xh, b.R0,
                                b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw, LiftGroups{});
