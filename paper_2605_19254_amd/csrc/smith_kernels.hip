@@ -509,7 +509,7 @@ __global__ __launch_bounds__(64) void k_lift_frag(const uint32_t *__restrict__ v
 // work-groups of a window run on one XCD at about the same time and share
 // its L2 for their C (or A) blocks and their groups' right operands, instead
 // of each fetching both from beyond the L2.  False for the padding items.
-constexpr int64_t kLiftWinR = 4, kLiftWinG = 8;
+constexpr int64_t kLiftWinR = 8, kLiftWinG = 8;
 __device__ __forceinline__ bool lift_item(const LiftGroups &gr, int64_t &rb, int64_t &g) {
     if (gr.groups <= 1) {
         rb = blockIdx.x;
