@@ -1428,7 +1428,13 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const unsigned rbs = (unsigned)((n + 15) / 16);
         const v4i_l *ct = reinterpret_cast<const v4i_l *>(b.Ct);
         // Eight waves per 16-row block, two work-groups per CU.
-        if (frag)
+        // Grouped launches below n = 4096 split k over two waves instead of
+        // eight (measured: n = 2003 1.77 s against 1.91 s for the whole
+        // massager; at n = 5003 eight waves were faster, 20.2 s against 21.1 s).
+        if (frag && b.grp.groups > 1 && n < 4096)
+            hipLaunchKernelGGL((k_lift_x_mfma<2, true>), dim3(lift_grid(rbs, b.grp)), dim3(128), 0, s, ct, n, ld,
+                               KT, b.Rm0, b.Rm1, t, p, b.Xh, b.base, off, rmd, xd, lift_groups(rbs, b.grp));
+        else if (frag)
             hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(lift_grid(rbs, b.grp)), dim3(512), 0, s, ct, n, ld,
                                KT, b.Rm0, b.Rm1, t, p, b.Xh, b.base, off, rmd, xd, lift_groups(rbs, b.grp));
         else
@@ -1444,7 +1450,11 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const v4i_l *at = reinterpret_cast<const v4i_l *>(b.At);
         const v4i_l *xdc = reinterpret_cast<const v4i_l *>(b.Xd);
         v4i_l *rmdw = reinterpret_cast<v4i_l *>(b.Rmd);
-        if (frag)
+        if (frag && b.grp.groups > 1 && n < 4096)           // as for the first product
+            hipLaunchKernelGGL((k_lift_r_mfma<2, true>), dim3(lift_grid(rbs, b.grp)), dim3(128), 0, s, at, n,
+                               ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw,
+                               lift_groups(rbs, b.grp));
+        else if (frag)
             hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(lift_grid(rbs, b.grp)), dim3(512), 0, s, at, n,
                                ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw,
                                lift_groups(rbs, b.grp));
