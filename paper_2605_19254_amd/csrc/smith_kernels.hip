@@ -502,30 +502,6 @@ __global__ __launch_bounds__(64) void k_lift_frag(const uint32_t *__restrict__ v
     for (int i = 0; i < 4; ++i) frag[((int64_t)kt * 4 + i) * 64 + lane] = f[i];
 }
 
-// The work item (16-row block rb, group g) of a lifting launch.  Ungrouped:
-// rb = blockIdx.x.  Grouped (one-dimensional grid of lift_grid_grouped
-// work-groups): windows of kLiftWinR row blocks x kLiftWinG groups are dealt
-// round-robin to the eight XCDs (work-group w runs on XCD w mod 8), so the
-// work-groups of a window run on one XCD at about the same time and share
-// its L2 for their C (or A) blocks and their groups' right operands, instead
-// of each fetching both from beyond the L2.  False for the padding items.
-constexpr int64_t kLiftWinR = 8, kLiftWinG = 8;
-__device__ __forceinline__ bool lift_item(const LiftGroups &gr, int64_t &rb, int64_t &g) {
-    if (gr.groups <= 1) {
-        rb = blockIdx.x;
-        g = 0;
-        return true;
-    }
-    const int64_t w = blockIdx.x, xcd = w % 8, i = w / 8;
-    const int64_t per = kLiftWinR * kLiftWinG;
-    const int64_t st = (i / per) * 8 + xcd;              // window
-    const int64_t wgs = (gr.groups + kLiftWinG - 1) / kLiftWinG;
-    const int64_t within = i % per;
-    rb = (st / wgs) * kLiftWinR + within / kLiftWinG;
-    g = (st % wgs) * kLiftWinG + within % kLiftWinG;
-    return rb < gr.rbs && g < gr.groups;
-}
-
 // X[c][r] = sum_k C[r][k] Rm[c][k] mod p for one 16-row block per work-group;
 // its KS waves take KS slices of the 64-column steps and add their int32
 // sums in LDS.  Same step indexing as k_lift_x.
@@ -538,8 +514,7 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_x_mfma(const v4i_l *__
                                                          const v4i_l *__restrict__ Rmd, v4i_l *__restrict__ Xd,
                                                          LiftGroups gr) {
     __shared__ v4i_l part[KS][7][64];
-    int64_t rb, g;                                       // g: the group's own vectors and buffers
-    if (!lift_item(gr, rb, g)) return;
+    const int64_t rb = blockIdx.x, g = blockIdx.y;     // g: the group's own vectors and buffers
     Rm0 += g * gr.rm;
     Rm1 += g * gr.rm;
     Xh += g * gr.xh;
@@ -664,8 +639,7 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
                                                                  const v4i_l *__restrict__ Xd,
                                                                  v4i_l *__restrict__ Rmd, LiftGroups gr) {
     __shared__ v4i_l part[KS][8][64];
-    int64_t rb, g;                                       // g: the group's own vectors and buffers
-    if (!lift_item(gr, rb, g)) return;
+    const int64_t rb = blockIdx.x, g = blockIdx.y;     // g: the group's own vectors and buffers
     R0 += g * gr.r;
     R1 += g * gr.r;
     Rm0 += g * gr.rm;
@@ -745,6 +719,176 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
         if constexpr (FRAG) tile16[c][4 * (lane >> 4) + v] = rm;
     }
     if constexpr (FRAG) lift_emit_frag<true>(tile16, rb, lane, p, Rmd);
+}
+
+// ------------------------------------------- grouped lifting, wide items
+// The two products of a grouped step with a wider item per work-group: four
+// waves, wave w taking the 16-row block 4 rbq + w against the four groups
+// 4 gq .. 4 gq + 3 (64 columns) over the whole k range, so each C (or A)
+// fragment loaded feeds four groups' MFMAs and no partial sums go through
+// LDS.  The digit fragments, shift groups, int32 bounds and epilogues are
+// those of k_lift_x_mfma and k_lift_r_mfma (each column sum is the same sum,
+// accumulated by one wave).  Items (4 row blocks x 4 groups) are dealt
+// round-robin to the eight XCDs (work-group w runs on XCD w mod 8) in
+// windows of 2 x 2 items, so that a window's C (or A) blocks and its groups'
+// digit fragments are fetched into that XCD's L2 once and shared; the
+// groups hold full runs of 16 vectors.
+__device__ __forceinline__ bool lift_item_wide(const LiftGroups &gr, int64_t &rbq, int64_t &gq) {
+    const int64_t R4 = (gr.rbs + 3) / 4, G4 = (gr.groups + 3) / 4;
+    const int64_t w = blockIdx.x, xcd = w % 8, i = w / 8;
+    constexpr int64_t WR = 2, WG = 2, per = WR * WG;
+    const int64_t st = (i / per) * 8 + xcd;
+    const int64_t wgs = (G4 + WG - 1) / WG;
+    const int64_t within = i % per;
+    rbq = (st / wgs) * WR + within / WG;
+    gq = (st % wgs) * WG + within % WG;
+    return rbq < R4 && gq < G4;
+}
+
+__global__ __launch_bounds__(256, 2) void k_lift_x_wide(const v4i_l *__restrict__ Ct, int64_t n, int64_t ld, int KT,
+                                                       int t, uint32_t p, uint32_t *__restrict__ Xh,
+                                                       const int64_t *__restrict__ base, int off,
+                                                       const v4i_l *__restrict__ Rmd, v4i_l *__restrict__ Xd,
+                                                       LiftGroups gr) {
+    __shared__ uint32_t tile16[4][16][17];
+    int64_t rbq, gq;
+    if (!lift_item_wide(gr, rbq, gq)) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t rb = rbq * 4 + wave;
+    if (rb >= gr.rbs) return;                            // no work-group barrier below
+    const int64_t i_step = *base + off;
+    bool gv[4];
+    const v4i_l *bq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t g = gq * 4 + q;
+        gv[q] = g < gr.groups;
+        bq[q] = Rmd + (gv[q] ? g : 0) * gr.frag + lane;
+    }
+    const v4i_l *cf = Ct + rb * KT * 256 + lane;
+    v4i_l acc[4][7];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int g = 0; g < 7; ++g) acc[q][g] = v4i_l{0, 0, 0, 0};
+    const v4i_l zero{0, 0, 0, 0};
+    for (int kt = 0; kt < KT; ++kt) {
+        v4i_l a[4], b[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = cf[(int64_t)kt * 256 + i * 64];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) b[q][i] = gv[q] ? bq[q][((int64_t)kt * 4 + i) * 64] : zero;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int da = 0; da < 4; ++da)
+#pragma unroll
+                for (int db = 0; db < 4; ++db)
+                    acc[q][da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[q][db], acc[q][da + db], 0, 0, 0);
+    }
+    const double pf = (double)p, pinv = 1.0 / pf;
+    const double w24 = fma(-rint(16777216.0 * pinv), pf, 16777216.0);
+    const double w48 = fma(-rint(281474976710656.0 * pinv), pf, 281474976710656.0);
+    const int c = lane & 15;
+    const bool cvalid = c < t;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!gv[q]) continue;
+        const int64_t g = gq * 4 + q;
+        uint32_t *X = Xh + g * gr.xh + (i_step % gr.ring) * t * ld;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int32_t cs[7];
+#pragma unroll
+            for (int s = 0; s < 7; ++s) cs[s] = acc[q][s][v];
+            const int64_t row = rb * 16 + 4 * (lane >> 4) + v;
+            const uint32_t xr = lift_recombine(cs, pf, pinv, w24, w48);
+            if (cvalid && row < n) X[(int64_t)c * ld + row] = xr;
+            tile16[wave][c][4 * (lane >> 4) + v] = (cvalid && row < n) ? xr : 0u;
+        }
+        lift_emit_frag<false>(tile16[wave], rb, lane, p, Xd + g * gr.frag);
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_lift_r_wide(const v4i_l *__restrict__ At, int64_t n, int64_t ld, int KT,
+                                                       int64_t *__restrict__ R0, int64_t *__restrict__ R1,
+                                                       uint32_t *__restrict__ Rm0, uint32_t *__restrict__ Rm1, int t,
+                                                       uint32_t p, int32_t *__restrict__ err,
+                                                       const int64_t *__restrict__ base, int off,
+                                                       const v4i_l *__restrict__ Xd, v4i_l *__restrict__ Rmd,
+                                                       LiftGroups gr) {
+    __shared__ uint32_t tile16[4][16][17];
+    int64_t rbq, gq;
+    if (!lift_item_wide(gr, rbq, gq)) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t rb = rbq * 4 + wave;
+    if (rb >= gr.rbs) return;
+    const int64_t i_step = *base + off;
+    bool gv[4];
+    const v4i_l *bq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t g = gq * 4 + q;
+        gv[q] = g < gr.groups;
+        bq[q] = Xd + (gv[q] ? g : 0) * gr.frag + lane;
+    }
+    const v4i_l *af = At + rb * KT * 128 + lane;
+    v4i_l acc[4][8];                                     // acc[q][4 i + j]: digit pair (a_i, x_j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int g = 0; g < 8; ++g) acc[q][g] = v4i_l{0, 0, 0, 0};
+    const v4i_l zero{0, 0, 0, 0};
+    for (int kt = 0; kt < KT; ++kt) {
+        v4i_l a[2], b[4][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = af[(int64_t)kt * 128 + i * 64];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) b[q][i] = gv[q] ? bq[q][((int64_t)kt * 4 + i) * 64] : zero;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int da = 0; da < 2; ++da)
+#pragma unroll
+                for (int db = 0; db < 4; ++db)
+                    acc[q][4 * da + db] =
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[q][db], acc[q][4 * da + db], 0, 0, 0);
+    }
+    const int c = lane & 15;
+    const bool cvalid = c < t;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!gv[q]) continue;
+        const int64_t g = gq * 4 + q;
+        const int64_t *R = ((i_step & 1) ? R1 : R0) + g * gr.r;
+        int64_t *Rn = ((i_step & 1) ? R0 : R1) + g * gr.r;
+        uint32_t *Rmn = ((i_step & 1) ? Rm0 : Rm1) + g * gr.rm;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int64_t sum = 0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) sum += (int64_t)acc[q][s][v] << (8 * ((s >> 2) + (s & 3)));
+            const int64_t r = rb * 16 + 4 * (lane >> 4) + v;
+            uint32_t rm = 0;
+            if (cvalid && r < n) {
+                const int64_t num = R[(int64_t)c * ld + r] - sum;
+                const int64_t qq = num / (int64_t)p;
+                if (qq * (int64_t)p != num) atomicOr(err, 1);
+                Rn[(int64_t)c * ld + r] = qq;
+                const int64_t m = qq % (int64_t)p;
+                rm = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+                Rmn[(int64_t)c * ld + r] = rm;
+            }
+            tile16[wave][c][4 * (lane >> 4) + v] = rm;
+        }
+        lift_emit_frag<true>(tile16[wave], rb, lane, p, Rmd + g * gr.frag);
+    }
 }
 
 // ------------------------------- packed right operands for t <= 4 vectors
@@ -1389,13 +1533,12 @@ void launch_gj_load(const int64_t *A, int64_t n, int64_t ld, uint32_t *M, const 
 }
 
 
-// Work-groups of a lifting launch: one per 16-row block, or for a grouped
-// launch the windows of lift_item, padded to a multiple of eight windows.
-unsigned lift_grid(unsigned rbs, const LiftGroups &gr) {
-    if (gr.groups <= 1) return rbs;
-    const int64_t wr = (rbs + kLiftWinR - 1) / kLiftWinR, wg = (gr.groups + kLiftWinG - 1) / kLiftWinG;
-    const int64_t windows = (wr * wg + 7) / 8 * 8;
-    return (unsigned)(windows * kLiftWinR * kLiftWinG);
+// Work-groups of a grouped lifting launch: lift_item_wide's windows, padded
+// to a multiple of eight windows.
+unsigned lift_grid_wide(unsigned rbs, const LiftGroups &gr) {
+    const int64_t r4 = (rbs + 3) / 4, g4 = (gr.groups + 3) / 4;
+    const int64_t windows = (((r4 + 1) / 2) * ((g4 + 1) / 2) + 7) / 8 * 8;
+    return (unsigned)(windows * 4);
 }
 LiftGroups lift_groups(unsigned rbs, LiftGroups gr) {
     gr.rbs = rbs;
@@ -1428,15 +1571,13 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const unsigned rbs = (unsigned)((n + 15) / 16);
         const v4i_l *ct = reinterpret_cast<const v4i_l *>(b.Ct);
         // Eight waves per 16-row block, two work-groups per CU.
-        // Grouped launches below n = 4096 split k over two waves instead of
-        // eight (measured: n = 2003 1.77 s against 1.91 s for the whole
-        // massager; at n = 5003 eight waves were faster, 20.2 s against 21.1 s).
-        if (frag && b.grp.groups > 1 && n < 4096)
-            hipLaunchKernelGGL((k_lift_x_mfma<2, true>), dim3(lift_grid(rbs, b.grp)), dim3(128), 0, s, ct, n, ld,
-                               KT, b.Rm0, b.Rm1, t, p, b.Xh, b.base, off, rmd, xd, lift_groups(rbs, b.grp));
+        // Grouped launches: four row blocks x four groups per work-group.
+        if (frag && b.grp.groups > 1)
+            hipLaunchKernelGGL(k_lift_x_wide, dim3(lift_grid_wide(rbs, b.grp)), dim3(256), 0, s, ct, n, ld, KT, t, p,
+                               b.Xh, b.base, off, rmd, xd, lift_groups(rbs, b.grp));
         else if (frag)
-            hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(lift_grid(rbs, b.grp)), dim3(512), 0, s, ct, n, ld,
-                               KT, b.Rm0, b.Rm1, t, p, b.Xh, b.base, off, rmd, xd, lift_groups(rbs, b.grp));
+            hipLaunchKernelGGL((k_lift_x_mfma<8, true>), dim3(rbs), dim3(512), 0, s, ct, n, ld, KT, b.Rm0, b.Rm1, t,
+                               p, b.Xh, b.base, off, rmd, xd, LiftGroups{});
         else
             hipLaunchKernelGGL((k_lift_x_mfma<8, false>), dim3(rbs), dim3(512), 0, s, ct, n, ld, KT, b.Rm0, b.Rm1, t,
                                p, b.Xh, b.base, off, rmd, xd, LiftGroups{});
@@ -1450,14 +1591,12 @@ static void lift_step_t(const uint32_t *C, const AT *A, int64_t n, int64_t ld, i
         const v4i_l *at = reinterpret_cast<const v4i_l *>(b.At);
         const v4i_l *xdc = reinterpret_cast<const v4i_l *>(b.Xd);
         v4i_l *rmdw = reinterpret_cast<v4i_l *>(b.Rmd);
-        if (frag && b.grp.groups > 1 && n < 4096)           // as for the first product
-            hipLaunchKernelGGL((k_lift_r_mfma<2, true>), dim3(lift_grid(rbs, b.grp)), dim3(128), 0, s, at, n,
-                               ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw,
-                               lift_groups(rbs, b.grp));
+        if (frag && b.grp.groups > 1)
+            hipLaunchKernelGGL(k_lift_r_wide, dim3(lift_grid_wide(rbs, b.grp)), dim3(256), 0, s, at, n, ld, KT, b.R0,
+                               b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw, lift_groups(rbs, b.grp));
         else if (frag)
-            hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(lift_grid(rbs, b.grp)), dim3(512), 0, s, at, n,
-                               ld, KT, b.Xh, b.R0, b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw,
-                               lift_groups(rbs, b.grp));
+            hipLaunchKernelGGL((k_lift_r_mfma<8, true>), dim3(rbs), dim3(512), 0, s, at, n, ld, KT, b.Xh, b.R0,
+                               b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw, LiftGroups{});
         else
             hipLaunchKernelGGL((k_lift_r_mfma<8, false>), dim3(rbs), dim3(512), 0, s, at, n, ld, KT, b.Xh, b.R0,
                                b.R1, b.Rm0, b.Rm1, t, p, b.err, b.base, off, xdc, rmdw, LiftGroups{});
