@@ -52,6 +52,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <ctime>
 #include <functional>
@@ -2542,11 +2543,15 @@ struct Driver {
             bool integral = true, ok = false;
             DRV_ST(massager_reduce(B, R, &integral));
             int64_t dim = 0;
-            const int p3 = integral ? massager_phase3(R, &ok, &dim) : RNS_OK;
+            // RNS_MASSAGER_CERT=det selects the determinant certificate (the
+            // form taken beyond the residue certificate's limits).
+            const char *cert_env = std::getenv("RNS_MASSAGER_CERT");
+            const bool det_cert = cert_env && std::strcmp(cert_env, "det") == 0;
+            const int p3 = !integral ? RNS_OK : (det_cert ? RNS_ENOTSUP : massager_phase3(R, &ok, &dim));
             if (p3 == RNS_OK) {
                 st.cert_kind = 1;
                 if (!ok) st.uc_rejects += 1;
-            } else if (p3 == RNS_ENOTSUP) {
+            } else if (p3 == RNS_ENOTSUP || p3 == RNS_EBOUND) {   // beyond the certificate's limits
                 st.cert_kind = 0;
                 BigInt prod(1);
                 for (const BigInt &o : R.s) prod = prod * o;

@@ -186,3 +186,24 @@ def test_edge_cases(ctx, rg):
     with pytest.raises(rg.RnsError) as e:
         rg.smith_massager(ctx, sing)
     assert e.value.status == 6                       # RNS_ESINGULAR
+
+
+def test_determinant_certificate_form(ctx, rg):
+    """The determinant certificate (|det A| = prod s_i from det A mod primes),
+    which Phase 3 takes where the linearized B is beyond the residue
+    certificate's limits, selected here with RNS_MASSAGER_CERT=det."""
+    _say("massager determinant certificate form")
+    a = synth.vandermonde_mod(43)
+    os.environ["RNS_MASSAGER_CERT"] = "det"
+    try:
+        res = rg.smith_massager(ctx, a, seed=4)
+        ctx.force_cert_failures(1)
+        res2 = rg.smith_massager(ctx, a, seed=5)
+    finally:
+        del os.environ["RNS_MASSAGER_CERT"]
+    want = osm.smith_form(a)
+    assert res.s == want and res.stats["cert_kind"] == 0 and res.stats["cert_exact"] == 1
+    assert res2.s == want and res2.stats["restarts"] >= 1 and res2.stats["cert_kind"] == 0
+    S = res.s
+    c = om.checks(a, res.U, res.M, res.T, S)
+    assert all(c.values()), c
