@@ -312,3 +312,69 @@ def test_matmul_plan_512_uneven_full(ctx, rg, torch_dev, batch512, path):
         _say("  replay", rep, "agrees")
     del g
     plan.close()
+
+
+SMALL_PRIMES = op.largest_primes_below(1 << 15, 8)
+
+
+@pytest.mark.parametrize("variant", [0, 2, 3, 4])
+def test_small_prime_residue_products(rg, torch_dev, variant):
+    """A basis of primes below 2^15 (digits 2 and 3 of every balanced residue
+    are zero) mixed with two 26-bit primes: every residue of every product
+    against the oracle, with residues at 0, 1, p-1 and (p +- 1)/2, ragged
+    shapes past the tile edges, k up to 2100, in four GEMM variants."""
+    torch, dev = torch_dev
+    _say("small primes variant", variant)
+    primes = SMALL_PRIMES + PRIMES[:2]
+    c = rg.Context(device=0, primes=primes)
+    try:
+        rng = np.random.default_rng(100 + variant)
+        shapes = [(1, 1, 1), (65, 129, 130), (130, 300, 2100), (200, 33, 64), (7, 1000, 257)]
+        probs, host = [], []
+        for i, (m, n, k) in enumerate(shapes):
+            begin, L = (i % 3, 6) if i != 4 else (6, 4)  # the last mixes two small and two big primes
+            ps = primes[begin:begin + L]
+            a = np.stack([rng.integers(0, p, size=(m, k)) for p in ps])
+            b = np.stack([rng.integers(0, p, size=(k, n)) for p in ps])
+            for j, p in enumerate(ps):
+                mask = rng.random((m, k)) < 0.3
+                a[j][mask] = rng.choice(np.array([0, 1, p - 1, (p - 1) // 2, (p + 1) // 2]), size=int(mask.sum()))
+            a, b = a.astype(np.int32), b.astype(np.int32)
+            C = torch.full((L, m, n), -1, dtype=torch.int32, device=dev)
+            probs.append(rg.GemmProblem(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), C, begin))
+            host.append((a, b, ps, C))
+        plan = rg.GemmPlan(c, probs, path="int8")
+        plan.set_variant(variant)
+        plan.execute()
+        torch.cuda.synchronize()
+        for a, b, ps, C in host:
+            _check_residues(C.cpu().numpy(), a, b, ps)
+        plan.close()
+    finally:
+        c.close()
+
+
+def test_small_prime_whole_products(rg, torch_dev):
+    """The 512-product batch's shape with three primes below 2^15 per product
+    (|C| <= k 2^32 < M / 2 = 2^44.9 / 2): every entry of every product against
+    the exact integer product."""
+    torch, dev = torch_dev
+    _say("small primes whole products")
+    c = rg.Context(device=0, primes=SMALL_PRIMES[:3])
+    try:
+        batch = synth.uneven_batch(count=40, lo=8, hi=300, bound=1 << 16, seed=43)
+        probs = []
+        for pr in batch:
+            probs.append(rg.MatmulProblem(torch.from_numpy(pr.a).to(dev), torch.from_numpy(pr.b).to(dev),
+                                          torch.empty((pr.m, pr.n), dtype=torch.int64, device=dev),
+                                          prime_begin=0, L=3, bound=pr.k << 32))
+        plan = rg.MatmulPlan(c, probs, path="int8")
+        plan.autotune()
+        plan.execute()
+        torch.cuda.synchronize()
+        assert c.status() == 0
+        for pr, p in zip(batch, probs):
+            assert np.array_equal(p.C.cpu().numpy(), native.exact_matmul(pr.a, pr.b))
+        plan.close()
+    finally:
+        c.close()
