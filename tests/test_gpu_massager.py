@@ -207,3 +207,27 @@ def test_determinant_certificate_form(ctx, rg):
     S = res.s
     c = om.checks(a, res.U, res.M, res.T, S)
     assert all(c.values()), c
+
+
+@pytest.mark.parametrize("n", [120, 400])
+def test_planted_many_invariants(ctx, rg, n):
+    """Planted invariants (A = U diag(s) V from factors among the primes below
+    100) with n random row and column operations, so that n max|A| stays
+    below the massager's 2^36 (the planted workload's 4n operations give
+    entries of 2^42 at n = 2000, beyond it): nearly every s_i nontrivial (111
+    of 120, 370 of 400), S equal to the planted invariants, certified by B's
+    unimodularity; at n = 120 (U, M, T) also pass Section 4.2's checks.
+    The massager refuses the 4n-operation matrix with RNS_ENOTSUP."""
+    _say("massager planted", n)
+    pl = synth.planted_smith(n, seed=0, ops_per_dim=1)
+    assert int(np.abs(pl.a).max()) * n < (1 << 36)
+    res = rg.smith_massager(ctx, pl.a, seed=0, fetch=("U", "M", "T") if n <= 120 else ())
+    assert res.s == pl.s
+    assert res.stats["cert_kind"] == 1 and res.stats["uc_rejects"] == 0
+    if n <= 120:
+        _check_massager(pl.a, res)
+    else:
+        big = synth.planted_smith(n, seed=0)
+        with pytest.raises(rg.RnsError) as e:
+            rg.smith_massager(ctx, big.a)
+        assert e.value.status == 8                   # RNS_ENOTSUP
