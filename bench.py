@@ -168,9 +168,12 @@ def _oracle_timings(conn, n, L, rows1):
 def run_batched(rg, torch, dev, count, steps):
     """512 independent products C_i = A_i B_i, n_i log-uniform in [32, 1024]
     (seed 0), entries uniform in [-2^16, 2^16], 2 primes each (|C| <= n 2^32).
-    One whole-product plan (resident residue planes; reduce, prep, GEMM and CRT
-    launches over the whole batch), autotuned, captured in a HIP graph and
-    replayed.  Ablation: one plan per problem, launched one after another."""
+    One whole-product plan (a conversion launch and a GEMM launch over the
+    whole batch, the GEMM doing both primes of each tile and the two-prime CRT
+    into int64), captured in a HIP graph and replayed.  Ablations: the same
+    plan with the CRT as a launch of its own over resident residue planes
+    (autotuned, and its persistent GEMM), the FP64 path, and one plan per
+    problem launched one after another."""
     import numpy as np
     import synth
     from oracle import native, rns as orns
@@ -223,12 +226,22 @@ def run_batched(rg, torch, dev, count, steps):
         del gg
         return r
 
-    # the same batch with the persistent GEMM (two work-groups per CU take
-    # half-tiles, longest first, from a counter: one GEMM launch that stays
-    # resident for the whole batch)
-    plan.set_variant(2)
-    ms_persistent = replay_ms(plan, steps)
-    plan.set_variant(variant)
+    # ablation: the CRT as a launch of its own over resident C residue planes
+    # (the GEMM autotuned), and that plan with the persistent GEMM (two
+    # work-groups per CU take half-tiles, longest first, from a counter)
+    ctx_sep = rg.Context(device=0, L=2, separate_crt=True)
+    plan_sep = rg.MatmulPlan(ctx_sep, probs, path="int8")
+    variant_sep = plan_sep.autotune()
+    ms_separate = replay_ms(plan_sep, steps)
+    for i in (order[0], order[count // 2], order[-1]):
+        rows = np.array([0, batch[i].m - 1])
+        got = probs[i].C[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        if not np.array_equal(got, native.exact_matmul(batch[i].a[rows], batch[i].b)):
+            raise SystemExit("bench.py: batched result (separate CRT) differs from the oracle")
+    plan_sep.set_variant(2)
+    ms_persistent = replay_ms(plan_sep, steps)
+    plan_sep.close()
+    ctx_sep.close()
     # ablation: every residue product on the FP64 MFMA path
     plan64 = rg.MatmulPlan(ctx, probs, path="fp64")
     ms_fp64 = replay_ms(plan64, max(2, steps // 2))
@@ -241,7 +254,6 @@ def run_batched(rg, torch, dev, count, steps):
     # ablation: a plan per problem, launched in a host loop, no graph
     singles = [rg.MatmulPlan(ctx, [p], path="int8") for p in probs]
     for sp in singles:
-        sp.set_variant(variant)
         sp.execute()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -270,7 +282,8 @@ def run_batched(rg, torch, dev, count, steps):
             "residue_ops": ops, "variant": variant, "tiles": info["tiles"],
             "mfma_frac_of_int8_peak": 16.0 * ops / (ms * 1e-3) / 1e12 / PEAK_INT8_TOPS,
             "per_problem_launch_loop_ms": ms_loop,
-            "persistent_gemm_ms_per_step": ms_persistent,
+            "separate_crt_ms_per_step": ms_separate, "separate_crt_variant": variant_sep,
+            "separate_crt_persistent_gemm_ms_per_step": ms_persistent,
             "fp64_path_ms_per_step": ms_fp64,
             "cpu_baseline": {"value": sops / tc, "unit": "int-ops/s", "cores": native.num_threads(),
                              "kind": "oracle", "sample": "first 24 problems of the batch, %.1f s" % tc}}

@@ -83,8 +83,11 @@ int rns_primes_below(uint64_t bound, int count, uint32_t *out);
  *   L:      1 <= L <= 4096.
  *   flags:  0, or RNS_CTX_PATH_FP64 / RNS_CTX_PATH_INT8: the path that
  *           RNS_PATH_AUTO resolves to in every product of this context (and
- *           of the Smith-form driver working on it); other bits are
- *           reserved and rejected with RNS_EINVAL.
+ *           of the Smith-form driver working on it), optionally or'ed with
+ *           RNS_CTX_SEPARATE_CRT: whole-product plans of this context keep
+ *           the CRT as a launch of its own even where they could fuse it
+ *           into the GEMM launch (see rns_matmul_plan_create); other bits
+ *           are reserved and rejected with RNS_EINVAL.
  * The context owns its device tables and a growable workspace; free it with
  * rns_ctx_destroy.  Returns RNS_EINVAL for a bad basis, RNS_EDEVICE or
  * RNS_ENOMEM on HIP failures.
@@ -92,6 +95,7 @@ int rns_primes_below(uint64_t bound, int count, uint32_t *out);
 /* rns_ctx_create flags (low two bits: the default product path). */
 #define RNS_CTX_PATH_FP64 1u
 #define RNS_CTX_PATH_INT8 2u
+#define RNS_CTX_SEPARATE_CRT 4u
 
 int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes, int L,
                    uint64_t flags);
@@ -239,7 +243,11 @@ typedef struct rns_plan_info {
                               3 LDS-staged, eight waves of 32 x 32 outputs;
                               4 (default) two independent four-wave
                                 work-groups per tile, one per 64-column half,
-                                two work-groups per CU */
+                                two work-groups per CU;
+                              RNS_I8_HALF_CRT (5): whole-product plans that
+                                fuse the CRT: as 4, each work-group taking
+                                both primes of its half-tile and writing
+                                int64 (not selectable by set_variant) */
     int64_t tiles;         /* work-group tiles over all primes and problems */
     size_t workspace_bytes;
     double residue_ops;    /* 2*m*n*k*L summed over the problems */
@@ -282,7 +290,18 @@ int rns_gemm_plan_autotune(rns_gemm_plan *plan, void *stream, int *variant_out);
  *         otherwise the exact mixed-radix form.
  *   prime_begin, L: the primes of the problem, 1 <= L <= 64.
  * Overflow of W words is reported through the context status word.
+ * When W == 1, every problem has L <= 2 and the INT8 path is taken (and the
+ * context lacks RNS_CTX_SEPARATE_CRT), the plan fuses the CRT into the GEMM:
+ * each work-group computes its output tile for both primes, keeps the first
+ * prime's products in registers and writes the CRT of the pair (the unique
+ * x with |x| <= (p0 p1 - 1)/2, exact whatever `bound` says; it always fits
+ * one word) straight into C.  Execution is then two launches and the plan
+ * holds no residue planes of C; rns_matmul_plan_info reports variant
+ * RNS_I8_HALF_CRT.
  */
+/* rns_plan_info.variant of a whole-product plan that fuses the CRT. */
+#define RNS_I8_HALF_CRT 5
+
 typedef struct rns_matmul_desc {
     int64_t m, n, k;
     const int64_t *A;

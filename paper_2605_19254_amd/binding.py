@@ -60,6 +60,8 @@ def loaded_hip_runtimes():
 OK, EINVAL, ENOMEM, EDEVICE, EBOUND, EOVERFLOW, ESINGULAR, ERETRY, ENOTSUP, EPENDING, ESCRATCH = range(11)
 PATH_AUTO, PATH_FP64, PATH_INT8 = 0, 1, 2
 _PATHS = {"auto": PATH_AUTO, "fp64": PATH_FP64, "int8": PATH_INT8}
+CTX_SEPARATE_CRT = 4          # rns_ctx_create flag
+I8_HALF_CRT = 5               # plan info variant of a plan that fuses the CRT into the GEMM
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -255,10 +257,12 @@ class Context:
     """An RNS basis on one GPU (rns_ctx)."""
 
     def __init__(self, device: int = 0, primes: Optional[Sequence[int]] = None, L: int = 24,
-                 path: Optional[str] = None):
+                 path: Optional[str] = None, separate_crt: bool = False):
         """path: None (the library chooses), "fp64" or "int8": what the "auto"
-        path resolves to in this context's products (RNS_CTX_PATH_*)."""
-        flags = {None: 0, "auto": 0, "fp64": 1, "int8": 2}[path]
+        path resolves to in this context's products (RNS_CTX_PATH_*).
+        separate_crt: whole-product plans keep the CRT as a launch of its own
+        even where they could fuse it into the GEMM (RNS_CTX_SEPARATE_CRT)."""
+        flags = {None: 0, "auto": 0, "fp64": 1, "int8": 2}[path] | (CTX_SEPARATE_CRT if separate_crt else 0)
         h = _P()
         if primes is not None:
             arr = (ctypes.c_uint32 * len(primes))(*[int(p) for p in primes])

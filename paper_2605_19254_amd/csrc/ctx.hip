@@ -134,7 +134,7 @@ static void fill_prime_const(uint32_t p, PrimeConst &c) {
 extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
                               int L, uint64_t flags) {
     if (!out || L < 1 || L > kMaxPrimes) return RNS_EINVAL;
-    if ((flags & ~(uint64_t)3) != 0 || (flags & 3) == 3) return RNS_EINVAL;
+    if ((flags & ~(uint64_t)(3 | RNS_CTX_SEPARATE_CRT)) != 0 || (flags & 3) == 3) return RNS_EINVAL;
     *out = nullptr;
     std::vector<uint32_t> ps(L);
     if (primes) {
@@ -160,6 +160,7 @@ extern "C" int rns_ctx_create(rns_ctx **out, int device, const uint32_t *primes,
     ctx->device = device;
     ctx->L = L;
     ctx->flags = flags;
+    ctx->separate_crt = (flags & RNS_CTX_SEPARATE_CRT) != 0;
     ctx->auto_path = (flags & 3) == RNS_CTX_PATH_FP64 ? RNS_PATH_FP64
                    : (flags & 3) == RNS_CTX_PATH_INT8 ? RNS_PATH_INT8 : RNS_PATH_AUTO;
     if (const char *e = std::getenv("RNS_INT8_KERNEL")) ctx->int8_kernel = std::atoi(e);

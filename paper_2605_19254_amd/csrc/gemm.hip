@@ -30,6 +30,7 @@ struct Plan {
     int64_t total_units64 = 0;
     double residue_ops = 0;
     int64_t max_dim = 0;
+    bool fused = false;          // both primes per tile and the CRT in the GEMM launch
 };
 
 int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x, const GemmInt64Src *src) {
@@ -53,9 +54,11 @@ int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x, const GemmInt64Src *s
 
 // Builds the problem table.  Problems are ordered by decreasing tile cost
 // (k, then m*n), so that a persistent launch hands out the longest tiles
-// first; workspace offsets are relative (the caller adds the base).
+// first; workspace offsets are relative (the caller adds the base).  With
+// `fuse` (INT8, int64 sources with int64 results, at most two primes each)
+// a tile covers every prime of its problem.
 int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &plan,
-              const GemmInt64Src *src = nullptr) {
+              const GemmInt64Src *src = nullptr, bool fuse = false) {
     const int TM = int8 ? kI8TileM : kF64TileM;
     const int TN = int8 ? kI8TileN : kF64TileN;
     const int64_t elem = int8 ? 4 : 8;   // bytes per operand entry in the tiled layout
@@ -98,7 +101,15 @@ int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &
         off += (size_t)g.b_plane_bytes * g.L;
         off = (off + 255) & ~(size_t)255;
         g.tile_begin = plan.total_tiles;
-        plan.total_tiles += (int64_t)g.L * g.tm * g.tn;
+        plan.total_tiles += (fuse ? 1 : (int64_t)g.L) * g.tm * g.tn;
+        if (fuse) {
+            g.C64 = src[i].C;
+            g.ldc64 = src[i].ldc;
+            if (g.L == 2) {
+                const uint64_t p0 = ctx->primes[x.prime_begin], p1 = ctx->primes[x.prime_begin + 1];
+                g.crt_inv = (uint32_t)invmod_u64(p0 % p1, p1);
+            }
+        }
         g.unitA_begin = plan.total_units;
         g.unitB_begin = g.unitA_begin + (int64_t)g.L * g.RB * g.KT;
         plan.total_units = g.unitB_begin + (int64_t)g.L * g.CB * g.KT;
@@ -115,7 +126,18 @@ int make_plan(rns_ctx *ctx, const rns_gemm_desc *d, int count, bool int8, Plan &
     }
     plan.work_bytes = off;
     plan.from_int64 = src != nullptr;
+    plan.fused = fuse;
     return RNS_OK;
+}
+
+// Whether a plan of int64 products can fuse the CRT into its GEMM launch:
+// INT8 path, every problem with an int64 result and at most two primes.
+bool can_fuse(const rns_ctx *ctx, const rns_gemm_desc *d, const GemmInt64Src *src, int count, bool int8) {
+    if (!src || !int8 || ctx->separate_crt) return false;
+    for (int i = 0; i < count; ++i)
+        if (d[i].m > 0 && d[i].n > 0 && d[i].L > 0 && (d[i].L > 2 || !src[i].C || src[i].ldc < d[i].n))
+            return false;
+    return true;
 }
 
 // Plans for a path; AUTO takes INT8 unless k exceeds its exactness bound.
@@ -158,8 +180,8 @@ int choose_variant(rns_ctx *ctx, bool int8, const Plan &plan) {
 // units: conversion units (per prime and tile, or per tile for int64 operands).
 int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np, int64_t tiles,
              int64_t units, const int32_t *tile_prob, unsigned *counter, hipStream_t s,
-             bool from_int64 = false) {
-    const bool persistent = int8 && variant == kI8HalfPersistent;
+             bool from_int64 = false, bool fused = false) {
+    const bool persistent = int8 && !fused && variant == kI8HalfPersistent;
     if (from_int64) {
         ProfScope ps(ctx, int8 ? "k_prep_i64_i8" : "k_prep_i64_f64", s);
         launch_prep_i64(int8, dP, np, units, (const PrimeConst *)ctx->d_prime,
@@ -170,7 +192,10 @@ int run_plan(rns_ctx *ctx, bool int8, int variant, const GemmProblem *dP, int np
                     persistent ? counter : nullptr, s);
     }
     RNS_HIP(hipGetLastError());
-    {
+    if (fused) {
+        ProfScope ps(ctx, "k_gemm_i8", s);
+        launch_gemm_i8_crt(dP, np, tiles, (const PrimeConst *)ctx->d_prime, tile_prob, s);
+    } else {
         ProfScope ps(ctx, int8 ? "k_gemm_i8" : "k_gemm_f64", s);
         if (int8)
             launch_gemm_i8(variant, dP, np, tiles, (const PrimeConst *)ctx->d_prime, tile_prob,
@@ -190,6 +215,7 @@ struct rns_gemm_plan {
     rns_ctx *ctx = nullptr;
     bool int8 = true;
     bool from_int64 = false;        // operands are int64 matrices (conversion reduces them)
+    bool fused = false;             // the GEMM launch also does the CRT into int64 results
     int variant = 0;
     int nprob = 0;
     int64_t total_tiles = 0, total_units = 0;
@@ -224,11 +250,17 @@ int gemm_plan_create(rns_ctx *ctx, const rns_gemm_desc *descs, const GemmInt64Sr
     Plan plan;
     int st = make_plan_path(ctx, descs, count, path, int8, plan, src);
     if (st != RNS_OK) return st;
+    if (can_fuse(ctx, descs, src, count, int8)) {
+        plan = Plan();
+        st = make_plan(ctx, descs, count, int8, plan, src, true);
+        if (st != RNS_OK) return st;
+    }
     rns_gemm_plan *p = new (std::nothrow) rns_gemm_plan;
     if (!p) return RNS_ENOMEM;
     p->ctx = ctx;
     p->int8 = int8;
     p->from_int64 = plan.from_int64;
+    p->fused = plan.fused;
     p->nprob = (int)plan.probs.size();
     p->total_tiles = plan.total_tiles;
     p->total_units = plan.from_int64 ? plan.total_units64 : plan.total_units;
@@ -282,6 +314,7 @@ int gemm_plan_create_int64(rns_ctx *ctx, const rns_gemm_desc *descs, const GemmI
     if (count > 0 && !src) return RNS_EINVAL;
     return gemm_plan_create(ctx, descs, src, count, path, out);
 }
+bool gemm_plan_fused_crt(const rns_gemm_plan *p) { return p && p->fused; }
 }  // namespace rns
 
 extern "C" int rns_gemm_plan_execute(rns_gemm_plan *p, void *stream) {
@@ -289,13 +322,14 @@ extern "C" int rns_gemm_plan_execute(rns_gemm_plan *p, void *stream) {
     if (p->nprob == 0) return RNS_OK;
     RNS_HIP(hipSetDevice(p->ctx->device));
     return run_plan(p->ctx, p->int8, p->variant, p->d_probs, p->nprob, p->total_tiles,
-                    p->total_units, p->d_tile_prob, p->d_counter, (hipStream_t)stream, p->from_int64);
+                    p->total_units, p->d_tile_prob, p->d_counter, (hipStream_t)stream, p->from_int64,
+                    p->fused);
 }
 
 extern "C" int rns_gemm_plan_info(const rns_gemm_plan *p, rns_plan_info *info) {
     if (!p || !info) return RNS_EINVAL;
     info->path = p->int8 ? RNS_PATH_INT8 : RNS_PATH_FP64;
-    info->variant = p->variant;
+    info->variant = p->fused ? RNS_I8_HALF_CRT : p->variant;
     info->tiles = p->total_tiles;
     info->workspace_bytes = p->work_bytes;
     info->residue_ops = p->residue_ops;
@@ -304,6 +338,7 @@ extern "C" int rns_gemm_plan_info(const rns_gemm_plan *p, rns_plan_info *info) {
 
 extern "C" int rns_gemm_plan_set_variant(rns_gemm_plan *p, int variant) {
     if (!p || variant < 0 || (p->int8 ? variant >= kI8NumVariants : variant != 0)) return RNS_EINVAL;
+    if (p->fused) return RNS_EINVAL;   // one kernel form
     p->variant = variant;
     return RNS_OK;
 }
@@ -341,6 +376,10 @@ extern "C" int rns_ctx_set_tune_cache(rns_ctx *ctx, const char *path) {
 
 extern "C" int rns_gemm_plan_autotune(rns_gemm_plan *p, void *stream, int *variant_out) {
     if (!p || !variant_out) return RNS_EINVAL;
+    if (p->fused) {   // one kernel form: nothing to choose
+        *variant_out = RNS_I8_HALF_CRT;
+        return RNS_OK;
+    }
     rns_ctx *ctx = p->ctx;
     hipStream_t s = (hipStream_t)stream;
     int best = p->variant, st = RNS_OK;

@@ -30,7 +30,7 @@ struct GemmProblem {
     int32_t tm, tn;              // work-group tiles along m and n
     char *At, *Bt;               // tiled operands in the workspace
     int64_t a_plane_bytes, b_plane_bytes;
-    int64_t tile_begin;          // prefix over problems of L*tm*tn
+    int64_t tile_begin;          // prefix over problems of L*tm*tn (tm*tn with the CRT fused)
     int64_t unitA_begin;         // prefix over problems of prep units (A then B)
     int64_t unitB_begin;
     // int64 operands (whole-product plans): the conversion kernel reduces them
@@ -38,6 +38,11 @@ struct GemmProblem {
     const int64_t *A64, *B64;
     int64_t lda64, ldb64;
     int64_t u64A_begin, u64B_begin;   // prefix over problems of those units (A then B)
+    // Plans with the CRT fused into the GEMM (at most two primes): the int64
+    // result and p_0^{-1} mod p_1 of the problem's two primes.
+    int64_t *C64;
+    int64_t ldc64;
+    uint32_t crt_inv;
 };
 
 __host__ __device__ __forceinline__ int find_problem(const GemmProblem *P, int nprob, int64_t t,
@@ -142,6 +147,9 @@ void launch_prep_i64(bool int8, const GemmProblem *P, int nprob, int64_t units,
 void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
                     const PrimeConst *pc, const int32_t *tile_prob, unsigned *counter,
                     int num_cus, hipStream_t s);
+// Both primes of each tile in one work-group, CRT to int64 in the epilogue.
+void launch_gemm_i8_crt(const GemmProblem *P, int nprob, int64_t tiles, const PrimeConst *pc,
+                        const int32_t *tile_prob, hipStream_t s);
 void launch_gemm_f64(const GemmProblem *P, int nprob, int64_t tiles, const PrimeConst *pc,
                      const int32_t *tile_prob, hipStream_t s);
 

@@ -181,6 +181,40 @@ __device__ __forceinline__ void plain_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// One 64-k step of a work-group tile: wait for this wave's copies of the
+// step, barrier, read this wave's fragments from `cur`, run `next` (which
+// starts the copies of a later step into the other buffer, or does nothing),
+// then the 16 digit-pair MFMAs per block.  (Peeling the last step off the
+// loops, so that the compiler can overlap the reads with the first MFMAs
+// instead of waiting for all of them at the branch join, measured 2 % slower
+// on the n = 4096 product.)
+template <class S, class Next>
+__device__ __forceinline__ void i8_step(const v4i *cur, int lane, int wy, int wx,
+                                        v4i (&acc)[7][S::kRB][S::kCB], Next &&next) {
+    vm_wait_0();
+    plain_barrier();
+    v4i a[S::kRB][4], b[S::kCB][4];
+#pragma unroll
+    for (int i = 0; i < S::kRB; ++i)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) a[i][d] = cur[((wy * S::kRB + i) * 4 + d) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < S::kCB; ++j)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) b[j][d] = cur[(S::kFragA + (wx * S::kCB + j) * 4 + d) * 64 + lane];
+    next();
+#pragma unroll
+    for (int da = 0; da < 4; ++da)
+#pragma unroll
+        for (int db = 0; db < 4; ++db)
+#pragma unroll
+            for (int i = 0; i < S::kRB; ++i)
+#pragma unroll
+                for (int j = 0; j < S::kCB; ++j)
+                    acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i][da], b[j][db],
+                                                                               acc[da + db][i][j], 0, 0, 0);
+}
+
 // One work-group tile: 16-row blocks from rblk0, 16-column blocks from cblk0.
 template <class S>
 __device__ __forceinline__ void i8_lds_tile(const GemmProblem &g, int plane, int rblk0, int cblk0,
@@ -220,31 +254,10 @@ __device__ __forceinline__ void i8_lds_tile(const GemmProblem &g, int plane, int
             for (int j = 0; j < S::kCB; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
 
     issue(sbuf[0], 0);
-    for (int kt = 0; kt < KT; ++kt) {
-        const v4i *cur = sbuf[kt & 1];
-        vm_wait_0();
-        plain_barrier();
-        v4i a[S::kRB][4], b[S::kCB][4];
-#pragma unroll
-        for (int i = 0; i < S::kRB; ++i)
-#pragma unroll
-            for (int d = 0; d < 4; ++d) a[i][d] = cur[((wy * S::kRB + i) * 4 + d) * 64 + lane];
-#pragma unroll
-        for (int j = 0; j < S::kCB; ++j)
-#pragma unroll
-            for (int d = 0; d < 4; ++d) b[j][d] = cur[(S::kFragA + (wx * S::kCB + j) * 4 + d) * 64 + lane];
-        if (kt + 1 < KT) issue(sbuf[(kt + 1) & 1], kt + 1);
-#pragma unroll
-        for (int da = 0; da < 4; ++da)
-#pragma unroll
-            for (int db = 0; db < 4; ++db)
-#pragma unroll
-                for (int i = 0; i < S::kRB; ++i)
-#pragma unroll
-                    for (int j = 0; j < S::kCB; ++j)
-                        acc[da + db][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                            a[i][da], b[j][db], acc[da + db][i][j], 0, 0, 0);
-    }
+    for (int kt = 0; kt < KT; ++kt)
+        i8_step<S>(sbuf[kt & 1], lane, wy, wx, acc, [&] {
+            if (kt + 1 < KT) issue(sbuf[(kt + 1) & 1], kt + 1);
+        });
 
     const PrimeConst pr = pc[g.prime_begin + plane];
     uint32_t *C = g.C + (int64_t)plane * g.cps;
@@ -260,6 +273,145 @@ __device__ __forceinline__ void i8_lds_tile(const GemmProblem &g, int plane, int
                 const int col = (cblk0 + wx * S::kCB + j) * 16 + (lane & 15);
                 if (row < g.m && col < g.n) store_residue(C + (int64_t)row * g.ldc + col, r, pr.p, g.sub);
             }
+}
+
+// ------------------------------------------ two primes, CRT in the epilogue --
+// Whole-product plans whose problems have one or two primes and one output
+// word.  A work-group computes its tile for both primes in turn, as one
+// continuous run of k steps over the same double buffer (the copies of the
+// second prime's first step overlap the first prime's last step). It keeps
+// the first prime's reduced products in registers and writes the CRT of the
+// pair as int64. The C residue planes and the CRT launch are not needed.
+//
+// The CRT of two primes (Section 3.1's reconstruction at L = 2): with
+// r0 = x mod p0 and r1 = x mod p1, u = r0 + p0 t where
+// t = (r1 - r0) p0^{-1} mod p1, so u is in [0, p0 p1), and x = u, or
+// u - p0 p1 when u > (p0 p1 - 1)/2. Every product below is an integer
+// below 2^52, exact in doubles.
+
+// v mod p in [0, p) for an integer 0 <= v < 2^52. The rounded quotient is
+// wrong by at most one, and then only next to a half-integer, so the
+// remainder lands in (-p, p) and one conditional +p fixes it.
+__device__ __forceinline__ double mod_nonneg(double v, const PrimeConst &pr) {
+    const double r = fma(-rint(v * pr.pinv), pr.pf, v);
+    return r < 0.0 ? r + pr.pf : r;
+}
+
+__device__ __forceinline__ int64_t crt_pair(uint32_t r0, uint32_t r1, const PrimeConst &p0,
+                                            const PrimeConst &p1, double inv) {
+    double d = (double)r1 - mod_nonneg((double)r0, p1);
+    d = d < 0.0 ? d + p1.pf : d;
+    const uint64_t t = (uint64_t)mod_nonneg(d * inv, p1);
+    const uint64_t M = (uint64_t)p0.p * p1.p;
+    const uint64_t u = (uint64_t)r0 + (uint64_t)p0.p * t;
+    return u > (M - 1) / 2 ? (int64_t)u - (int64_t)M : (int64_t)u;
+}
+
+template <class S>
+__device__ __forceinline__ void i8_lds_tile_crt(const GemmProblem &g, int rblk0, int cblk0,
+                                                const PrimeConst *__restrict__ pc,
+                                                v4i (*sbuf)[S::kFrag * 64]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wy = wave / S::kWX, wx = wave % S::kWX;
+    const int KT = g.KT;
+    const int L = g.L;   // 1 or 2 (the host checks)
+    const char *Ag = g.At + (int64_t)rblk0 * KT * 4096 + lane * 16;
+    const char *Bg = g.Bt + (int64_t)cblk0 * KT * 4096 + lane * 16;
+    // The fragments this wave copies, as in i8_lds_tile, and the distance
+    // between the planes of their operand.
+    const char *src[S::kFragPerWave];
+    int64_t pstride[S::kFragPerWave];
+#pragma unroll
+    for (int i = 0; i < S::kFragPerWave; ++i) {
+        const int f = wave * S::kFragPerWave + i;
+        const bool isA = f < S::kFragA;
+        src[i] = isA ? Ag + ((int64_t)(f >> 2) * KT) * 4096 + (f & 3) * 1024
+                     : Bg + ((int64_t)((f - S::kFragA) >> 2) * KT) * 4096 + ((f - S::kFragA) & 3) * 1024;
+        pstride[i] = isA ? g.a_plane_bytes : g.b_plane_bytes;
+    }
+    auto issue = [&](v4i *buf, int plane, int kt) {
+#pragma unroll
+        for (int i = 0; i < S::kFragPerWave; ++i) {
+            const int f = wave * S::kFragPerWave + i;
+            __builtin_amdgcn_global_load_lds((const void *)(src[i] + plane * pstride[i] + (int64_t)kt * 4096),
+                                             (lds_void *)(buf + f * 64), 16, 0, 0);
+        }
+    };
+
+    v4i acc[7][S::kRB][S::kCB];
+    // Steps j0 .. j0 + KT - 1 of the run (buffer j & 1) for one plane; the
+    // copy of its first step is already in flight.  The last step starts the
+    // copy of the next plane's first step when there is one.
+    auto run_plane = [&](int plane, int j0) {
+#pragma unroll
+        for (int s = 0; s < 7; ++s)
+#pragma unroll
+            for (int i = 0; i < S::kRB; ++i)
+#pragma unroll
+                for (int j = 0; j < S::kCB; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+        for (int kt = 0; kt < KT; ++kt)
+            i8_step<S>(sbuf[(j0 + kt) & 1], lane, wy, wx, acc, [&] {
+                if (kt + 1 < KT) issue(sbuf[(j0 + kt + 1) & 1], plane, kt + 1);
+                else if (plane + 1 < L) issue(sbuf[(j0 + kt + 1) & 1], plane + 1, 0);
+            });
+    };
+
+    issue(sbuf[0], 0, 0);
+    run_plane(0, 0);
+    const PrimeConst p0 = pc[g.prime_begin];
+    uint32_t r0[S::kRB][S::kCB][4];
+#pragma unroll
+    for (int i = 0; i < S::kRB; ++i)
+#pragma unroll
+        for (int j = 0; j < S::kCB; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                r0[i][j][v] = recombine(acc[0][i][j][v], acc[1][i][j][v], acc[2][i][j][v], acc[3][i][j][v],
+                                        acc[4][i][j][v], acc[5][i][j][v], acc[6][i][j][v], p0);
+    int64_t *C = g.C64;
+    if (L == 2) {
+        run_plane(1, KT);
+        const PrimeConst p1 = pc[g.prime_begin + 1];
+        const double inv = (double)g.crt_inv;
+#pragma unroll
+        for (int i = 0; i < S::kRB; ++i)
+#pragma unroll
+            for (int j = 0; j < S::kCB; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t r1 = recombine(acc[0][i][j][v], acc[1][i][j][v], acc[2][i][j][v],
+                                                  acc[3][i][j][v], acc[4][i][j][v], acc[5][i][j][v],
+                                                  acc[6][i][j][v], p1);
+                    const int row = (rblk0 + wy * S::kRB + i) * 16 + 4 * (lane >> 4) + v;
+                    const int col = (cblk0 + wx * S::kCB + j) * 16 + (lane & 15);
+                    if (row < g.m && col < g.n) C[(int64_t)row * g.ldc64 + col] = crt_pair(r0[i][j][v], r1, p0, p1, inv);
+                }
+    } else {
+#pragma unroll
+        for (int i = 0; i < S::kRB; ++i)
+#pragma unroll
+            for (int j = 0; j < S::kCB; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t r = r0[i][j][v];
+                    const int row = (rblk0 + wy * S::kRB + i) * 16 + 4 * (lane >> 4) + v;
+                    const int col = (cblk0 + wx * S::kCB + j) * 16 + (lane & 15);
+                    if (row < g.m && col < g.n)
+                        C[(int64_t)row * g.ldc64 + col] = r > p0.half ? (int64_t)r - (int64_t)p0.p : (int64_t)r;
+                }
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_gemm_i8_half_crt(const GemmProblem *__restrict__ P, int nprob,
+                                                             int64_t total_tiles,
+                                                             const PrimeConst *__restrict__ pc,
+                                                             const int32_t *__restrict__ tile_prob) {
+    __shared__ v4i sbuf[2][ShapeHalf::kFrag * 64];
+    const int64_t h2 = xcd_window_remap(blockIdx.x, gridDim.x, kXcdWindow2);
+    if (h2 >= 2 * total_tiles) return;
+    const TileCoord tc = map_tile(P, nprob, h2 >> 1, tile_prob);
+    i8_lds_tile_crt<ShapeHalf>(P[tc.q], tc.tm * 4, tc.tn * 8 + (int)(h2 & 1) * 4, pc, sbuf);
 }
 
 __global__ __launch_bounds__(256) void k_gemm_i8_lds(const GemmProblem *__restrict__ P, int nprob,
@@ -338,6 +490,12 @@ void launch_gemm_i8(int variant, const GemmProblem *P, int nprob, int64_t tiles,
         hipLaunchKernelGGL(k_gemm_i8_half, dim3((unsigned)(2 * tiles)), dim3(256), 0, s, P, nprob, tiles,
                            pc, tile_prob);
     }
+}
+
+void launch_gemm_i8_crt(const GemmProblem *P, int nprob, int64_t tiles, const PrimeConst *pc,
+                        const int32_t *tile_prob, hipStream_t s) {
+    hipLaunchKernelGGL(k_gemm_i8_half_crt, dim3((unsigned)(2 * tiles)), dim3(256), 0, s, P, nprob, tiles, pc,
+                       tile_prob);
 }
 
 }  // namespace gemm

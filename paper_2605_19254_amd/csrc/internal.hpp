@@ -104,6 +104,7 @@ struct rns_ctx {
     int smith_path = 0;               // 0 auto, 1 residues of s A^-1, 2 p-adic lifting
     bool lift_vector_only = false;    // lifting products on the vector units only (RNS_LIFT_VECTOR)
     bool crt_garner = false;          // exact CRT by the mixed-radix kernel (RNS_CRT_GARNER)
+    bool separate_crt = false;        // plans never fuse the CRT into the GEMM (RNS_CTX_SEPARATE_CRT)
     int crt_form = 1;                 // exact CRT: 1 the matrix cores (k_crt_mfma), 0 Lagrange on 32-bit limbs
                                       // (k_crt_exact, RNS_CRT_FORM=limbs), 2 Garner (RNS_CRT_FORM=garner)
     int massager_r0 = 4;              // invariants taken by the first massager batch (RNS_MASSAGER_R0)
@@ -186,9 +187,16 @@ struct GemmInt64Src {
     int64_t lda;
     const int64_t *B;
     int64_t ldb;
+    // Optional int64 result (row stride ldc): when every problem of a plan has
+    // one, at most two primes and the INT8 path, the GEMM launch also does the
+    // CRT and writes C here (no residue planes of C).
+    int64_t *C;
+    int64_t ldc;
 };
 int gemm_plan_create_int64(rns_ctx *ctx, const rns_gemm_desc *descs, const GemmInt64Src *src, int count,
                            int path, rns_gemm_plan **out);
+// Whether a plan from gemm_plan_create_int64 writes int64 results itself.
+bool gemm_plan_fused_crt(const rns_gemm_plan *p);
 int mixed_radix_half(rns_ctx *ctx, int begin, int L, const uint32_t **out, hipStream_t s);
 
 }  // namespace rns

@@ -2,7 +2,9 @@
 // of independent integer products (Section 3.1 end to end).  The conversion
 // kernel of the plan's gemm plan reduces A and B straight into the tiled
 // operand layouts (no residue planes of A and B are written); the residue
-// planes of every C stay resident in a plan-owned buffer for the CRT.
+// planes of every C stay resident in a plan-owned buffer for the CRT.  Plans
+// of one-word results with at most two primes per problem instead let the
+// GEMM launch do the CRT (no C planes, two launches per execution).
 #include "reduce_crt.hpp"
 
 #include <algorithm>
@@ -16,6 +18,7 @@ struct rns_matmul_plan {
     int W = 1;
     int crt_E = 1;              // CRT entries per thread (the same for every job)
     bool fast_crt = false;
+    bool fused = false;         // the gemm plan writes C itself
     void *d_planes = nullptr;
     CrtJob *d_cjobs = nullptr;
     int nc = 0;
@@ -61,6 +64,32 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
     if (!p) return RNS_ENOMEM;
     p->ctx = ctx;
     p->W = W;
+    if (W == 1 && max_L <= 2 && path != RNS_PATH_FP64 && !ctx->separate_crt) {
+        // The gemm plan fuses the CRT when its path resolves to INT8.
+        std::vector<rns_gemm_desc> gd;
+        std::vector<GemmInt64Src> src;
+        for (int i = 0; i < count; ++i) {
+            const rns_matmul_desc &x = d[i];
+            if (x.m == 0 || x.n == 0) continue;
+            rns_gemm_desc g{};
+            g.m = x.m; g.n = x.n; g.k = x.k;
+            g.prime_begin = x.prime_begin; g.L = x.L;
+            // C residue pointers are unused by a fused plan, but the
+            // descriptor check asks for a non-null C.
+            g.C = reinterpret_cast<uint32_t *>(x.C); g.ldc = x.n; g.c_plane_stride = x.m * x.n;
+            gd.push_back(g);
+            src.push_back(GemmInt64Src{x.A, x.lda, x.B, x.ldb, reinterpret_cast<int64_t *>(x.C), x.ldc});
+        }
+        int st = gemm_plan_create_int64(ctx, gd.data(), src.data(), (int)gd.size(), path, &p->gemm);
+        if (st != RNS_OK) { delete p; return st; }
+        if (gemm_plan_fused_crt(p->gemm) || gd.empty()) {
+            p->fused = true;
+            *out = p;
+            return RNS_OK;
+        }
+        rns_gemm_plan_destroy(p->gemm);
+        p->gemm = nullptr;
+    }
     p->fast_crt = all_fast;
     p->crt_E = crt_entries(all_fast, W, max_L);
     auto fail = [&](int s) { rns_matmul_plan_destroy(p); return s; };
@@ -81,7 +110,7 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
         g.C = C; g.ldc = x.n; g.c_plane_stride = x.m * x.n;
         g.prime_begin = x.prime_begin; g.L = x.L;
         gd.push_back(g);
-        src.push_back(GemmInt64Src{x.A, x.lda, x.B, x.ldb});
+        src.push_back(GemmInt64Src{x.A, x.lda, x.B, x.ldb, nullptr, 0});
         // A contiguous C is one row of m*n entries for the CRT, so that
         // small problems fill whole tiles.
         CrtJob c{};

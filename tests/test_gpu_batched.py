@@ -142,6 +142,73 @@ def test_matmul_plan_uneven_batch(ctx, rg, torch_dev, with_bound):
     p1.close()
 
 
+def _symmetric_mod(x, M):
+    """x mod M in the symmetric range [-(M-1)/2, (M-1)/2] (M odd), elementwise
+    over an object array of Python ints."""
+    h = (M - 1) // 2
+    return np.vectorize(lambda v: (v + h) % M - h, otypes=[object])(x)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_matmul_plan_fused_crt(ctx, rg, torch_dev, seed):
+    """Whole-product plans with one or two primes per problem and one output
+    word fuse the CRT into the GEMM launch (both primes of a tile in one
+    work-group).  Entries across the whole int64 range, so that products
+    exceed p0 p1 and the result is the symmetric residue mod p0 p1; ragged
+    shapes over several tiles, k up to 700, prime pairs across the basis (and
+    in reversed order of size), L = 1 beside L = 2: every entry against the
+    exact product reduced in Python integers, and against the same plan with
+    the CRT as its own launch."""
+    torch, dev = torch_dev
+    _say("fused CRT plan", seed)
+    rng = np.random.default_rng(300 + seed)
+    lim = np.iinfo(np.int64)
+    shapes = [(1, 1, 1), (70, 130, 90), (129, 700, 65), (64, 64, 64), (200, 33, 250), (5, 300, 131)]
+    problems, hosts = [], []
+    for i, (m, k, n) in enumerate(shapes):
+        L = 1 if i % 3 == 2 else 2
+        begin = (7 * i + seed) % (26 - L)
+        a = rng.integers(lim.min, lim.max, size=(m, k), dtype=np.int64, endpoint=True)
+        b = rng.integers(lim.min, lim.max, size=(k, n), dtype=np.int64, endpoint=True)
+        if i == 4:   # small entries: products inside the symmetric range
+            a = rng.integers(-(1 << 16), 1 << 16, size=(m, k), dtype=np.int64, endpoint=True)
+            b = rng.integers(-(1 << 16), 1 << 16, size=(k, n), dtype=np.int64, endpoint=True)
+        M = 1
+        for p in PRIMES[begin:begin + L]:
+            M *= p
+        hosts.append((a, b, M))
+        problems.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev), begin, L))
+    exact = [a.astype(object).dot(b.astype(object)) for a, b, _ in hosts]
+    # one basis with the primes in increasing order too, so that p0 < p1
+    rev = rg.Context(device=0, primes=PRIMES[::-1][:4])
+    sep = rg.Context(device=0, L=26, separate_crt=True)
+    try:
+        for c, reversed_basis in ((ctx, False), (rev, True), (sep, False)):
+            probs = []
+            for (A, B, begin, L) in problems:
+                if reversed_basis:
+                    begin = begin % (4 - L + 1)
+                probs.append(rg.MatmulProblem(A, B, torch.full((A.shape[0], B.shape[1]), 77, dtype=torch.int64,
+                                                               device=dev), prime_begin=begin, L=L))
+            plan = rg.MatmulPlan(c, probs, path="int8")
+            assert (plan.info()["variant"] == rg.binding.I8_HALF_CRT) == (c is not sep)
+            plan.execute()
+            torch.cuda.synchronize()
+            assert c.status() == 0
+            for j, ((a, b, M), p) in enumerate(zip(hosts, probs)):
+                if reversed_basis:
+                    M = 1
+                    for q in c.primes[p.prime_begin:p.prime_begin + p.L]:
+                        M *= q
+                want = _symmetric_mod(exact[j], M)
+                got = p.C.cpu().numpy().astype(object)
+                assert np.array_equal(got, want), (j, shapes[j], reversed_basis)
+            plan.close()
+    finally:
+        rev.close()
+        sep.close()
+
+
 @pytest.mark.parametrize("path", ["int8", "fp64"])
 def test_matmul_plan_full_range_int64(ctx, rg, torch_dev, path):
     """Whole-product plans convert int64 operands straight into the tiled
@@ -211,7 +278,9 @@ def test_matmul_plan_degenerate_shapes(ctx, rg, torch_dev, path):
 def test_matmul_plan_graph_replay(ctx, rg, torch_dev):
     """Capture the whole product (reduce, prep, GEMM, CRT) into a HIP graph and
     replay it several times with eager work in between; every replay must equal
-    the eager result for the current inputs."""
+    the eager result for the current inputs.  The plan that fuses the CRT into
+    the GEMM, and the plan with a CRT launch of its own in three GEMM
+    variants."""
     torch, dev = torch_dev
     _say("graph replay")
     batch = synth.uneven_batch(count=12, lo=16, hi=160, bound=1 << 16, seed=51)
@@ -221,9 +290,13 @@ def test_matmul_plan_graph_replay(ctx, rg, torch_dev):
                                       torch.empty((pr.m, pr.n), dtype=torch.int64, device=dev),
                                       prime_begin=0, L=2, bound=pr.k << 32))
     want = [native.exact_matmul(pr.a, pr.b) for pr in batch]
-    for variant in (0, 2, 4):
-        plan = rg.MatmulPlan(ctx, probs, path="int8")
-        plan.set_variant(variant)
+    sep = rg.Context(device=0, L=4, separate_crt=True)
+    for c, variant in ((ctx, None), (sep, 0), (sep, 2), (sep, 4)):
+        plan = rg.MatmulPlan(c, probs, path="int8")
+        if variant is None:
+            assert plan.info()["variant"] == rg.binding.I8_HALF_CRT
+        else:
+            plan.set_variant(variant)
         plan.execute()                       # warm-up outside the capture
         torch.cuda.synchronize()
         s = torch.cuda.Stream()
@@ -245,7 +318,8 @@ def test_matmul_plan_graph_replay(ctx, rg, torch_dev):
                 assert np.array_equal(p.C.cpu().numpy(), sign * w), (variant, rep)
         del g
         plan.close()
-    assert ctx.status() == 0
+    assert ctx.status() == 0 and sep.status() == 0
+    sep.close()
 
 
 def test_autotune_and_cache(ctx, rg, torch_dev):

@@ -262,7 +262,8 @@ def test_modmatmul_digit_extremes_at_max_k(ctx, rg, torch_dev, variant):
 
 def test_context_path_flag(rg, torch_dev):
     """rns_ctx_create flags: RNS_CTX_PATH_FP64 / _INT8 fix what the auto path
-    resolves to; other flag bits are rejected."""
+    resolves to (also with RNS_CTX_SEPARATE_CRT beside them); both path bits
+    together and other flag bits are rejected."""
     import ctypes
     from paper_2605_19254_amd import binding
     torch, dev = torch_dev
@@ -284,8 +285,11 @@ def test_context_path_flag(rg, torch_dev):
                 want = native.modmatmul(a[j].astype(np.uint32), b[j].astype(np.uint32), p).astype(np.int32)
                 assert np.array_equal(got[j], want)
     h = ctypes.c_void_p()
-    for flags in (3, 4, 1 << 40):
+    for flags in (3, 7, 8, 1 << 40):
         assert binding._lib_ctx_create(ctypes.byref(h), 0, None, 3, flags) == binding.EINVAL
+    for flags in (4, 5, 6):
+        assert binding._lib_ctx_create(ctypes.byref(h), 0, None, 3, flags) == binding.OK
+        binding._lib_ctx_destroy(h)
 
 
 def test_modmatmul_batch_equals_single_and_paths_agree(ctx, rg, torch_dev):
