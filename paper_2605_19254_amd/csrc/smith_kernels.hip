@@ -726,13 +726,19 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
 // waves, wave w taking the 16-row block 4 rbq + w against the four groups
 // 4 gq .. 4 gq + 3 (64 columns) over the whole k range, so each C (or A)
 // fragment loaded feeds four groups' MFMAs and no partial sums go through
-// LDS.  The digit fragments, shift groups, int32 bounds and epilogues are
-// those of k_lift_x_mfma and k_lift_r_mfma (each column sum is the same sum,
-// accumulated by one wave).  Items (4 row blocks x 4 groups) are dealt
-// round-robin to the eight XCDs (work-group w runs on XCD w mod 8) in
-// windows of 2 x 2 items, so that a window's C (or A) blocks and its groups'
-// digit fragments are fetched into that XCD's L2 once and shared; the
-// groups hold full runs of 16 vectors.
+// LDS.  The four groups' digit fragments of a step (16 KiB, the same for
+// every wave of the work-group) are copied once into LDS with 16-byte direct
+// loads, wave w copying group 4 gq + w's four, into one of two buffers:
+// after a barrier each wave reads them from LDS, starts the copies of the
+// next step and loads its own next C (or A) fragments into registers, then
+// runs the step's MFMAs.  (Loading them from L2 into every wave's registers
+// moved 2.5 times the bytes per MFMA.)  The digit fragments, shift groups,
+// int32 bounds and epilogues are those of k_lift_x_mfma and k_lift_r_mfma
+// (each column sum is the same sum, accumulated by one wave).  Items (4 row
+// blocks x 4 groups) are dealt round-robin to the eight XCDs (work-group w
+// runs on XCD w mod 8) in windows of 2 x 2 items, so that a window's C (or A)
+// blocks and its groups' digit fragments are fetched into that XCD's L2 once
+// and shared; the groups hold full runs of 16 vectors.
 __device__ __forceinline__ bool lift_item_wide(const LiftGroups &gr, int64_t &rbq, int64_t &gq) {
     const int64_t R4 = (gr.rbs + 3) / 4, G4 = (gr.groups + 3) / 4;
     const int64_t w = blockIdx.x, xcd = w % 8, i = w / 8;
@@ -745,42 +751,86 @@ __device__ __forceinline__ bool lift_item_wide(const LiftGroups &gr, int64_t &rb
     return rbq < R4 && gq < G4;
 }
 
+typedef __attribute__((address_space(3))) void lds_void_l;
+
+__device__ __forceinline__ void lift_vm_wait_0() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
+__device__ __forceinline__ void lift_barrier() {
+    // The copies this barrier covers were waited for by every wave; the empty
+    // asm statements keep the compiler from moving memory accesses across.
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// The k loop of a wide item: right operands (the groups' 4 digit fragments
+// per step, frag_base + g * gr.frag, group 0's standing in for a group past
+// the last one, whose sums are never stored) through LDS, this wave's NA
+// left fragments per step (a_base, NA * 64 v4i apart per step) straight into
+// registers one step ahead; `mfma(a, b)` runs one step's products.
+template <int NA, class Mfma>
+__device__ __forceinline__ void lift_wide_loop(const v4i_l *__restrict__ a_base, const v4i_l *__restrict__ frag_base,
+                                               const LiftGroups &gr, int64_t gq, int KT, int lane, int wave,
+                                               v4i_l (*bbuf)[16 * 64], Mfma &&mfma) {
+    const int64_t gw = gq * 4 + wave;
+    const char *bsrc = reinterpret_cast<const char *>(frag_base + (gw < gr.groups ? gw : 0) * gr.frag + lane);
+    auto issue = [&](int buf, int kt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_amdgcn_global_load_lds((const void *)(bsrc + ((int64_t)kt * 4 + i) * 1024),
+                                             (lds_void_l *)(&bbuf[buf][(wave * 4 + i) * 64]), 16, 0, 0);
+    };
+    v4i_l a[NA], an[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) a[i] = a_base[i * 64];
+    issue(0, 0);
+    for (int kt = 0; kt < KT; ++kt) {
+        lift_vm_wait_0();
+        lift_barrier();
+        v4i_l b[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) b[q][i] = bbuf[kt & 1][(q * 4 + i) * 64 + lane];
+        if (kt + 1 < KT) {
+            issue((kt + 1) & 1, kt + 1);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) an[i] = a_base[((int64_t)kt + 1) * NA * 64 + i * 64];
+        }
+        mfma(a, b);
+        if (kt + 1 < KT) {
+#pragma unroll
+            for (int i = 0; i < NA; ++i) a[i] = an[i];
+        }
+    }
+}
+
 __global__ __launch_bounds__(256, 2) void k_lift_x_wide(const v4i_l *__restrict__ Ct, int64_t n, int64_t ld, int KT,
                                                        int t, uint32_t p, uint32_t *__restrict__ Xh,
                                                        const int64_t *__restrict__ base, int off,
                                                        const v4i_l *__restrict__ Rmd, v4i_l *__restrict__ Xd,
                                                        LiftGroups gr) {
     __shared__ uint32_t tile16[4][16][17];
+    __shared__ v4i_l bbuf[2][16 * 64];
     int64_t rbq, gq;
-    if (!lift_item_wide(gr, rbq, gq)) return;
+    if (!lift_item_wide(gr, rbq, gq)) return;            // the same for every wave of the work-group
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t rb = rbq * 4 + wave;
-    if (rb >= gr.rbs) return;                            // no work-group barrier below
+    // A wave past the last row block takes part in the copies and barriers
+    // (on row block 0's fragments) and stores nothing.
+    const bool rvalid = rb < gr.rbs;
     const int64_t i_step = *base + off;
     bool gv[4];
-    const v4i_l *bq[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t g = gq * 4 + q;
-        gv[q] = g < gr.groups;
-        bq[q] = Rmd + (gv[q] ? g : 0) * gr.frag + lane;
-    }
-    const v4i_l *cf = Ct + rb * KT * 256 + lane;
+    for (int q = 0; q < 4; ++q) gv[q] = gq * 4 + q < gr.groups;
+    const v4i_l *cf = Ct + (rvalid ? rb : 0) * KT * 256 + lane;
     v4i_l acc[4][7];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int g = 0; g < 7; ++g) acc[q][g] = v4i_l{0, 0, 0, 0};
-    const v4i_l zero{0, 0, 0, 0};
-    for (int kt = 0; kt < KT; ++kt) {
-        v4i_l a[4], b[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = cf[(int64_t)kt * 256 + i * 64];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) b[q][i] = gv[q] ? bq[q][((int64_t)kt * 4 + i) * 64] : zero;
+    lift_wide_loop<4>(cf, Rmd, gr, gq, KT, lane, wave, bbuf, [&](const v4i_l (&a)[4], const v4i_l (&b)[4][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -788,7 +838,8 @@ __global__ __launch_bounds__(256, 2) void k_lift_x_wide(const v4i_l *__restrict_
 #pragma unroll
                 for (int db = 0; db < 4; ++db)
                     acc[q][da + db] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[q][db], acc[q][da + db], 0, 0, 0);
-    }
+    });
+    if (!rvalid) return;                                 // no barrier below
     const double pf = (double)p, pinv = 1.0 / pf;
     const double w24 = fma(-rint(16777216.0 * pinv), pf, 16777216.0);
     const double w48 = fma(-rint(281474976710656.0 * pinv), pf, 281474976710656.0);
@@ -821,36 +872,24 @@ __global__ __launch_bounds__(256, 2) void k_lift_r_wide(const v4i_l *__restrict_
                                                        const v4i_l *__restrict__ Xd, v4i_l *__restrict__ Rmd,
                                                        LiftGroups gr) {
     __shared__ uint32_t tile16[4][16][17];
+    __shared__ v4i_l bbuf[2][16 * 64];
     int64_t rbq, gq;
-    if (!lift_item_wide(gr, rbq, gq)) return;
+    if (!lift_item_wide(gr, rbq, gq)) return;            // the same for every wave of the work-group
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t rb = rbq * 4 + wave;
-    if (rb >= gr.rbs) return;
+    const bool rvalid = rb < gr.rbs;                     // as in k_lift_x_wide
     const int64_t i_step = *base + off;
     bool gv[4];
-    const v4i_l *bq[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t g = gq * 4 + q;
-        gv[q] = g < gr.groups;
-        bq[q] = Xd + (gv[q] ? g : 0) * gr.frag + lane;
-    }
-    const v4i_l *af = At + rb * KT * 128 + lane;
+    for (int q = 0; q < 4; ++q) gv[q] = gq * 4 + q < gr.groups;
+    const v4i_l *af = At + (rvalid ? rb : 0) * KT * 128 + lane;
     v4i_l acc[4][8];                                     // acc[q][4 i + j]: digit pair (a_i, x_j)
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int g = 0; g < 8; ++g) acc[q][g] = v4i_l{0, 0, 0, 0};
-    const v4i_l zero{0, 0, 0, 0};
-    for (int kt = 0; kt < KT; ++kt) {
-        v4i_l a[2], b[4][4];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = af[(int64_t)kt * 128 + i * 64];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) b[q][i] = gv[q] ? bq[q][((int64_t)kt * 4 + i) * 64] : zero;
+    lift_wide_loop<2>(af, Xd, gr, gq, KT, lane, wave, bbuf, [&](const v4i_l (&a)[2], const v4i_l (&b)[4][4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -859,7 +898,8 @@ __global__ __launch_bounds__(256, 2) void k_lift_r_wide(const v4i_l *__restrict_
                 for (int db = 0; db < 4; ++db)
                     acc[q][4 * da + db] =
                         __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da], b[q][db], acc[q][4 * da + db], 0, 0, 0);
-    }
+    });
+    if (!rvalid) return;                                 // no barrier below
     const int c = lane & 15;
     const bool cvalid = c < t;
 #pragma unroll
