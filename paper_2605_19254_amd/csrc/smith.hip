@@ -1539,6 +1539,7 @@ struct Driver {
         DevBuf<char> Xd, Rmd;
         DevBuf<int32_t> err;
         DevBuf<uint64_t> dB, dF, dY, dacc;
+        DevBuf<uint32_t> dtop;
         DRV_ST(R0.alloc(cnt));
         DRV_ST(R1.alloc(cnt));
         DRV_ST(Rm0.alloc(cnt));
@@ -1603,13 +1604,18 @@ struct Driver {
         } else {
             launch_lift_steps(dC.p, dA16.p, a_bytes, n, ldl, (int)tc, p, lb, (int)K, stream);
             DRV_HIP(hipGetLastError());
-            // plane l (step K - L + l) of every run: G blocks of 16 ldl words
-            dig->assign((size_t)L * cnt, 0u);
+            // plane l (step K - L + l) of every run: G blocks of 16 ldl words,
+            // gathered on the device, then one contiguous copy to the host
+            // (not one strided device-to-host copy per plane)
+            DRV_ST(dtop.alloc((size_t)L * cnt));
             const size_t blk = sizeof(uint32_t) * (size_t)(tc * ldl);
             for (int l = 0; l < L; ++l)
-                DRV_HIP(hipMemcpy2DAsync(dig->data() + (size_t)l * cnt, blk,
+                DRV_HIP(hipMemcpy2DAsync(dtop.p + (size_t)l * cnt, blk,
                                          Xh.p + (size_t)(((K - L + l) % L) * tc * ldl), sizeof(uint32_t) * lb.grp.xh,
-                                         blk, (size_t)G, hipMemcpyDeviceToHost, stream));
+                                         blk, (size_t)G, hipMemcpyDeviceToDevice, stream));
+            dig->assign((size_t)L * cnt, 0u);
+            DRV_HIP(hipMemcpyAsync(dig->data(), dtop.p, sizeof(uint32_t) * (size_t)L * cnt, hipMemcpyDeviceToHost,
+                                   stream));
         }
         DRV_HIP(hipMemcpyAsync(herr, err.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         DRV_ST(sync());
