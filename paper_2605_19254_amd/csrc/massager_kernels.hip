@@ -4,7 +4,9 @@
 //
 // s is split into prime powers m_f = q_f^e_f on the host; plane f holds
 // W_f = P_1 mod m_f (n x t), its row transform E_f (n x n) and column
-// transform R_f (t x t).  Step c takes, in every plane at once, an entry of
+// transform R_f (t x t), the latter stored transposed (row j of the buffer
+// is column j of R_f), so that the column operations of the elimination
+// read and write contiguous rows.  Step c takes, in every plane at once, an entry of
 // minimal q-adic valuation v in rows >= c and columns >= c (a global minimum
 // of keys (v, row, column)), exchanges it to (c, c), and clears column c below
 // it and row c right of it; v is minimal, so the pivot divides every entry it
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(256) void k_ls_swap_rows(uint64_t *__restrict__ W, 
     }
 }
 
-// Column exchange c <-> pivot column in W and R.
+// Column exchange c <-> pivot column in W and R (rows of the transposed R).
 __global__ __launch_bounds__(256) void k_ls_swap_cols(uint64_t *__restrict__ W, uint64_t *__restrict__ R, int64_t n,
                                                       int64_t t, int64_t c, const LsnfStep *__restrict__ st) {
     const int f = blockIdx.y;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_ls_swap_cols(uint64_t *__restrict__ W, 
         *b = x;
     }
     if (k < t) {
-        uint64_t *a = R + f * t * t + k * t + c, *b = R + f * t * t + k * t + j;
+        uint64_t *a = R + f * t * t + c * t + k, *b = R + f * t * t + j * t + k;
         const uint64_t x = *a;
         *a = *b;
         *b = x;
@@ -225,8 +227,9 @@ __global__ __launch_bounds__(256) void k_ls_elim_rows(uint64_t *__restrict__ W, 
     if (threadIdx.x == 0) Wf[r * t + c] = 0;
 }
 
-// Columns j > c: column j -= g_j column c in R, W[c][j] = 0,
-// g_j = (W[c][j] / q^v) (a / q^v)^-1 mod m / q^v; one work-group per column.
+// Columns j > c: column j -= g_j column c in R (row j of the transposed
+// buffer -= g_j row c), W[c][j] = 0, g_j = (W[c][j] / q^v) (a / q^v)^-1
+// mod m / q^v; one work-group per column.
 __global__ __launch_bounds__(256) void k_ls_elim_cols(uint64_t *__restrict__ W, uint64_t *__restrict__ R, int64_t n,
                                                       int64_t t, int64_t c, const LsnfPlane *__restrict__ pl,
                                                       const LsnfStep *__restrict__ st) {
@@ -240,25 +243,57 @@ __global__ __launch_bounds__(256) void k_ls_elim_cols(uint64_t *__restrict__ W, 
     if (w == 0) return;
     const uint64_t g = ls_mulmod(ls_divq(P0, w, S.v) % S.mq, S.uinv, S.mq);
     const uint64_t gm = ls_mul(P0, g, P0.r2);
-    for (int64_t k = threadIdx.x; k < t; k += 256) Rf[k * t + j] = ls_sub(P0, Rf[k * t + j], ls_mul(P0, gm, Rf[k * t + c]));
+    for (int64_t k = threadIdx.x; k < t; k += 256) Rf[j * t + k] = ls_sub(P0, Rf[j * t + k], ls_mul(P0, gm, Rf[c * t + k]));
     __syncthreads();
     if (threadIdx.x == 0) Wf[c * t + j] = 0;
 }
 
-// out[f][i][j] = sum_k Pf[i][k] R_f[k][j] (plain, mod m_f) for j < take.
+// out[f][i][j] = sum_k Pf[i][k] R_f[k][j] (plain, mod m_f) for j < take, R_f
+// from its transposed buffer.  A work-group takes 16 rows i x 64 columns j:
+// chunks of 32 k of those 16 rows of Pf and of the 64 rows j of the
+// transposed R are staged in LDS (both read along k, contiguously), and
+// thread (w, l) accumulates rows 4 w .. 4 w + 3 against column l.
+constexpr int kPrTI = 16, kPrTJ = 64, kPrKC = 32;
 __global__ __launch_bounds__(256) void k_ls_pr(const uint64_t *__restrict__ Pf, const uint64_t *__restrict__ R,
                                                int64_t n, int64_t t, int64_t take, const LsnfPlane *__restrict__ pl,
                                                uint64_t *__restrict__ out) {
+    __shared__ uint64_t ps[kPrTI][kPrKC + 1];
+    __shared__ uint64_t rs[kPrTJ][kPrKC + 1];
     const int f = blockIdx.z;
     const LsnfPlane P0 = pl[f];
-    const int64_t i = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= take) return;
-    const uint64_t *p = Pf + f * n * t + i * t;
+    const int64_t i0 = (int64_t)blockIdx.y * kPrTI, j0 = (int64_t)blockIdx.x * kPrTJ;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t *pf = Pf + f * n * t;
     const uint64_t *rf = R + f * t * t;
-    uint64_t acc = 0;
-    for (int64_t k = 0; k < t; ++k) acc = ls_add(P0, acc, ls_mul(P0, p[k], rf[k * t + j]));   // plain x Montgomery
-    out[(f * n + i) * take + j] = acc;
+    uint64_t acc[4] = {0, 0, 0, 0};
+    for (int64_t k0 = 0; k0 < t; k0 += kPrKC) {
+        // 16 x 32 of Pf and 64 x 32 of the transposed R, zero past the edges
+        for (int e = threadIdx.x; e < kPrTI * kPrKC; e += 256) {
+            const int r = e / kPrKC, kk = e % kPrKC;
+            const int64_t i = i0 + r, k = k0 + kk;
+            ps[r][kk] = i < n && k < t ? pf[i * t + k] : 0;
+        }
+        for (int e = threadIdx.x; e < kPrTJ * kPrKC; e += 256) {
+            const int r = e / kPrKC, kk = e % kPrKC;
+            const int64_t j = j0 + r, k = k0 + kk;
+            rs[r][kk] = j < take && k < t ? rf[j * t + k] : 0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kPrKC; ++kk) {
+            const uint64_t rv = rs[lane][kk];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a] = ls_add(P0, acc[a], ls_mul(P0, ps[4 * w + a][kk], rv));   // plain x Montgomery
+        }
+        __syncthreads();
+    }
+    const int64_t j = j0 + lane;
+    if (j >= take) return;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t i = i0 + 4 * w + a;
+        if (i < n) out[(f * n + i) * take + j] = acc[a];
+    }
 }
 
 // Rows 0 .. rows-1 of every E_f from Montgomery to plain form.
@@ -302,8 +337,8 @@ void launch_ls_pr(const uint64_t *Pf, const uint64_t *R, int64_t n, int64_t t, i
                   int F, uint64_t *out, hipStream_t s) {
     if (take <= 0) return;
     ProfScope trace_(tl_trace, "k_ls_pr", s);
-    hipLaunchKernelGGL(k_ls_pr, dim3((unsigned)((take + 255) / 256), (unsigned)n, (unsigned)F), dim3(256), 0, s, Pf,
-                       R, n, t, take, pl, out);
+    hipLaunchKernelGGL(k_ls_pr, dim3((unsigned)((take + kPrTJ - 1) / kPrTJ), (unsigned)((n + kPrTI - 1) / kPrTI),
+                                     (unsigned)F), dim3(256), 0, s, Pf, R, n, t, take, pl, out);
 }
 
 void launch_ls_plain(uint64_t *E, int64_t n, int64_t rows, const LsnfPlane *pl, int F, hipStream_t s) {

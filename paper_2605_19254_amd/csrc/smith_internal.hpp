@@ -84,7 +84,8 @@ struct LsnfStep {
     uint64_t qv, mq, uinv;
 };
 // P (n x t, entries below s) into the F planes W_f (Montgomery form), Pf
-// (plain), E_f = I (n x n) and R_f = I (t x t); n, t < 2^21.
+// (plain), E_f = I (n x n) and R_f = I (t x t, stored transposed: row j of
+// the buffer is column j of R_f); n, t < 2^21.
 void launch_ls_load(const uint64_t *P, int64_t n, int64_t t, const LsnfPlane *pl, int F, uint64_t *W, uint64_t *Pf,
                     uint64_t *E, uint64_t *R, LsnfStep *st, hipStream_t s);
 // Step c of every plane: pivot search, exchanges, pivot record (vals[f][c],
