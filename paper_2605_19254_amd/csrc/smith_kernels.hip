@@ -290,6 +290,46 @@ constexpr int kLiftMaxT = 16;
 // X[c][r] = sum_k C[r][k] Rm[c][k] mod p.  Each lane sums at most ld/64
 // products below 2^52 per row (ld <= 65536 keeps that below 2^62), reduces
 // its sums mod p, and the wave adds the 64 reduced sums.
+// The residual update's division by p (exact for a correct C): q = num / p
+// rounded toward zero, and q mod p in [0, p).  For odd p, v = num p^-1 mod
+// 2^64 satisfies v p = num mod 2^64, so when |v| <= lim with lim p < 2^63,
+// v p = num exactly and v is the quotient; a correct step's quotients are far
+// below lim = min(6.9e18 / p, 2^50), so the integer division runs only where
+// the step is wrong (or its quotient is that large), and there it decides
+// exactness as before.  Below 2^50, q - p rint(q / p) in doubles is exact:
+// the rounding error of q / p stays below 1 / (4p), while q / p lies at
+// least 1 / (2p) from every half-integer (p odd); one +p then gives [0, p).
+struct LiftDiv {
+    uint64_t pinv64;   // p^-1 mod 2^64
+    int64_t lim;
+    uint32_t p;
+    double pf, pinv;
+    __device__ explicit LiftDiv(uint32_t p_) : p(p_) {
+        uint64_t x = p;                                  // p^-1 mod 2^3 (odd p)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) x *= 2 - (uint64_t)p * x;   // Newton: 3 -> 6 -> ... -> 96 bits
+        pinv64 = x;
+        pf = (double)p;
+        pinv = 1.0 / pf;
+        const double l = 6.9e18 * pinv;
+        lim = l < 0x1p50 ? (int64_t)l : ((int64_t)1 << 50);
+    }
+    // false when p does not divide num
+    __device__ __forceinline__ bool div(int64_t num, int64_t &q, uint32_t &qm) const {
+        q = (int64_t)((uint64_t)num * pinv64);
+        if (q <= lim && q >= -lim) {
+            const double qd = (double)q;
+            const double r = fma(-rint(qd * pinv), pf, qd);
+            qm = (uint32_t)(r < 0.0 ? r + pf : r);
+            return true;
+        }
+        q = num / (int64_t)p;
+        const int64_t m = q % (int64_t)p;
+        qm = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+        return q * (int64_t)p == num;
+    }
+};
+
 // Step i = *base + off: it reads Rm[i & 1] and R[i & 1], writes its digits to
 // Xh + i t ld and the next residuals to the other buffers.  *base lives in
 // device memory and is advanced by k_lift_advance after a run of steps, so a
@@ -709,11 +749,9 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma(const v4i_l *__
         uint32_t rm = 0;
         if (cvalid && r < n) {
             const int64_t num = R[(int64_t)c * ld + r] - sum;
-            const int64_t qq = num / (int64_t)p;
-            if (qq * (int64_t)p != num) atomicOr(err, 1);
+            int64_t qq;
+            if (!LiftDiv(p).div(num, qq, rm)) atomicOr(err, 1);
             Rn[(int64_t)c * ld + r] = qq;
-            const int64_t m = qq % (int64_t)p;
-            rm = (uint32_t)(m < 0 ? m + (int64_t)p : m);
             Rmn[(int64_t)c * ld + r] = rm;
         }
         if constexpr (FRAG) tile16[c][4 * (lane >> 4) + v] = rm;
@@ -902,6 +940,7 @@ __global__ __launch_bounds__(256, 2) void k_lift_r_wide(const v4i_l *__restrict_
     if (!rvalid) return;                                 // no barrier below
     const int c = lane & 15;
     const bool cvalid = c < t;
+    const LiftDiv ldiv(p);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (!gv[q]) continue;
@@ -918,11 +957,9 @@ __global__ __launch_bounds__(256, 2) void k_lift_r_wide(const v4i_l *__restrict_
             uint32_t rm = 0;
             if (cvalid && r < n) {
                 const int64_t num = R[(int64_t)c * ld + r] - sum;
-                const int64_t qq = num / (int64_t)p;
-                if (qq * (int64_t)p != num) atomicOr(err, 1);
+                int64_t qq;
+                if (!ldiv.div(num, qq, rm)) atomicOr(err, 1);
                 Rn[(int64_t)c * ld + r] = qq;
-                const int64_t m = qq % (int64_t)p;
-                rm = (uint32_t)(m < 0 ? m + (int64_t)p : m);
                 Rmn[(int64_t)c * ld + r] = rm;
             }
             tile16[wave][c][4 * (lane >> 4) + v] = rm;
@@ -1114,11 +1151,9 @@ __global__ __launch_bounds__(64 * KS, 8 / KS) void k_lift_r_mfma_pk(const v4i_l 
     uint32_t rm = 0;
     if (c < t && grow < n) {
         const int64_t num = R[(int64_t)c * ld + grow] - sum;
-        const int64_t qq = num / (int64_t)p;
-        if (qq * (int64_t)p != num) atomicOr(err, 1);
+        int64_t qq;
+        if (!LiftDiv(p).div(num, qq, rm)) atomicOr(err, 1);
         Rn[(int64_t)c * ld + grow] = qq;
-        const int64_t m = qq % (int64_t)p;
-        rm = (uint32_t)(m < 0 ? m + (int64_t)p : m);
         Rmn[(int64_t)c * ld + grow] = rm;
     }
     tile16[c][row] = rm;
@@ -1221,11 +1256,11 @@ __global__ __launch_bounds__(256) void k_lift_r(const AT *__restrict__ A, int64_
         if (rr < kLiftRows && c < t && r < n) {
             const int64_t v = part[0][rr][c] + part[1][rr][c] + part[2][rr][c] + part[3][rr][c];
             const int64_t num = R[(int64_t)c * ld + r] - v;
-            const int64_t qq = num / (int64_t)p;
-            if (qq * (int64_t)p != num) atomicOr(err, 1);
+            int64_t qq;
+            uint32_t rm;
+            if (!LiftDiv(p).div(num, qq, rm)) atomicOr(err, 1);
             Rn[(int64_t)c * ld + r] = qq;
-            const int64_t m = qq % (int64_t)p;
-            Rmn[(int64_t)c * ld + r] = (uint32_t)(m < 0 ? m + (int64_t)p : m);
+            Rmn[(int64_t)c * ld + r] = rm;
         }
     }
 }
