@@ -249,11 +249,14 @@ def test_matmul_plan_full_range_int64(ctx, rg, torch_dev, path):
 
 
 @pytest.mark.parametrize("path", ["int8", "fp64"])
-def test_matmul_plan_degenerate_shapes(ctx, rg, torch_dev, path):
+@pytest.mark.parametrize("L", [4, 2])
+def test_matmul_plan_degenerate_shapes(ctx, rg, torch_dev, path, L):
     """Whole-product plans with k = 0 (C = 0), empty problems (m = 0 or n = 0)
-    and 1 x 1 products in one batch, beside an ordinary product."""
+    and 1 x 1 products in one batch, beside an ordinary product; with two
+    primes (the INT8 plan then fuses the CRT into the GEMM) the results are
+    the symmetric residues mod p0 p1."""
     torch, dev = torch_dev
-    _say("matmul plan degenerate shapes", path)
+    _say("matmul plan degenerate shapes", path, L)
     rng = np.random.default_rng(7)
     shapes = [(5, 0, 7), (0, 4, 3), (6, 4, 0), (1, 1, 1), (33, 65, 17)]
     probs, hosts = [], []
@@ -263,14 +266,18 @@ def test_matmul_plan_degenerate_shapes(ctx, rg, torch_dev, path):
         A = torch.from_numpy(a).to(dev) if a.size else torch.zeros((m, k), dtype=torch.int64, device=dev)
         B = torch.from_numpy(b).to(dev) if b.size else torch.zeros((k, n), dtype=torch.int64, device=dev)
         C = torch.full((m, n), 123, dtype=torch.int64, device=dev)
-        probs.append(rg.MatmulProblem(A, B, C, prime_begin=0, L=4, bound=max(k, 1) << 50))
+        probs.append(rg.MatmulProblem(A, B, C, prime_begin=0, L=L, bound=max(k, 1) << 50 if L == 4 else 0))
         hosts.append((a, b))
     plan = rg.MatmulPlan(ctx, probs, path=path)
+    assert (plan.info()["variant"] == rg.binding.I8_HALF_CRT) == (L == 2 and path == "int8")
     plan.execute()
     torch.cuda.synchronize()
     assert ctx.status() == 0
+    M = PRIMES[0] * PRIMES[1]
     for (a, b), p in zip(hosts, probs):
         want = a.astype(object).dot(b.astype(object)) if a.shape[1] else np.zeros((a.shape[0], b.shape[1]), dtype=object)
+        if L == 2 and want.size:
+            want = _symmetric_mod(want, M)
         assert np.array_equal(p.C.cpu().numpy().astype(object), want)
     plan.close()
 
