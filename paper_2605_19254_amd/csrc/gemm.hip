@@ -39,7 +39,9 @@ int check_desc(const rns_ctx *ctx, const rns_gemm_desc &x, const GemmInt64Src *s
     if (x.prime_begin < 0 || x.prime_begin + x.L > ctx->L) return RNS_EINVAL;
     if (x.m > INT32_MAX / 2 || x.n > INT32_MAX / 2 || x.k > INT32_MAX / 2) return RNS_EINVAL;
     if (x.m == 0 || x.n == 0 || x.L == 0) return RNS_OK;
-    if (!x.C || x.ldc < x.n) return RNS_EINVAL;
+    // An int64 result given with the source (a plan that may fuse the CRT)
+    // stands in for the residue planes of C.
+    if ((!x.C && !(src && src->C)) || x.ldc < x.n) return RNS_EINVAL;
     if (x.L > 1 && x.c_plane_stride < (x.m - 1) * x.ldc + x.n) return RNS_EINVAL;
     if (x.k > 0 && src) {
         if (!src->A || !src->B || src->lda < x.k || src->ldb < x.n) return RNS_EINVAL;

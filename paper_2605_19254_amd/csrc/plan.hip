@@ -74,9 +74,7 @@ extern "C" int rns_matmul_plan_create(rns_ctx *ctx, const rns_matmul_desc *d, in
             rns_gemm_desc g{};
             g.m = x.m; g.n = x.n; g.k = x.k;
             g.prime_begin = x.prime_begin; g.L = x.L;
-            // C residue pointers are unused by a fused plan, but the
-            // descriptor check asks for a non-null C.
-            g.C = reinterpret_cast<uint32_t *>(x.C); g.ldc = x.n; g.c_plane_stride = x.m * x.n;
+            g.ldc = x.n; g.c_plane_stride = x.m * x.n;   // no residue planes: the int64 C below
             gd.push_back(g);
             src.push_back(GemmInt64Src{x.A, x.lda, x.B, x.ldb, reinterpret_cast<int64_t *>(x.C), x.ldc});
         }

@@ -4,8 +4,8 @@ determinant and gcd elimination modulo it).  Each case names its generator
 in synth/ and its parameters; a planted case is also checked against the
 invariants it was built with.  With --vandermonde it writes
 tests/golden/smith_vandermonde.json instead: the Smith forms (and |det A|)
-of the Section 4.1 family A_ij = i^j mod n for n = 101 and 199, by the same
-oracle.  Run from the repository root:
+of the Section 4.1 family A_ij = i^j mod n for n = 101, 199, 211 and 307, by
+the same oracle.  Run from the repository root:
     python tests/golden/make_smith_golden.py [--vandermonde]
 """
 import json
@@ -23,6 +23,8 @@ CASES = [
     {"gen": "small_smith", "n": 80, "seed": 11, "bound": 1024},
     {"gen": "small_smith", "n": 120, "seed": 12, "bound": 1024},
     {"gen": "small_smith", "n": 160, "seed": 13, "bound": 1024},
+    {"gen": "small_smith", "n": 240, "seed": 14, "bound": 1024},
+    {"gen": "small_smith", "n": 320, "seed": 15, "bound": 1024},
     {"gen": "planted_small", "n": 48, "seed": 3},
     {"gen": "planted_small", "n": 96, "seed": 4},
 ]
@@ -61,7 +63,7 @@ def main():
 
 def main_vandermonde():
     out = []
-    for n in (101, 199):
+    for n in (101, 199, 211, 307):
         t = time.time()
         a = synth.vandermonde_mod(n)
         s = osmith.smith_form(a)
