@@ -209,6 +209,32 @@ def test_matmul_plan_fused_crt(ctx, rg, torch_dev, seed):
         sep.close()
 
 
+def test_matmul_plan_two_primes_beyond_int8_bound(ctx, rg, torch_dev):
+    """k = 43691 is beyond the INT8 path's exactness bound: a two-prime plan
+    on the auto path takes the FP64 path with a CRT launch of its own (no
+    fusion) and is still exact; on the INT8 path it is refused."""
+    torch, dev = torch_dev
+    _say("two-prime plan, k = 43691")
+    rng = np.random.default_rng(17)
+    m, k, n = 3, 43691, 5
+    a = rng.integers(-(1 << 12), 1 << 12, size=(m, k), dtype=np.int64)
+    b = rng.integers(-(1 << 12), 1 << 12, size=(k, n), dtype=np.int64)
+    A, B = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    C = torch.zeros((m, n), dtype=torch.int64, device=dev)
+    prob = rg.MatmulProblem(A, B, C, prime_begin=3, L=2)
+    plan = rg.MatmulPlan(ctx, [prob], path="auto")
+    info = plan.info()
+    assert info["path"] == "fp64" and info["variant"] != rg.binding.I8_HALF_CRT
+    plan.execute()
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    assert np.array_equal(C.cpu().numpy(), native.exact_matmul(a, b))
+    plan.close()
+    with pytest.raises(rg.binding.RnsError) as e:
+        rg.MatmulPlan(ctx, [prob], path="int8")
+    assert e.value.status == rg.binding.EBOUND
+
+
 @pytest.mark.parametrize("path", ["int8", "fp64"])
 def test_matmul_plan_full_range_int64(ctx, rg, torch_dev, path):
     """Whole-product plans convert int64 operands straight into the tiled
