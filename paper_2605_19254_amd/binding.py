@@ -616,17 +616,12 @@ def base_convert(ctx: Context, res, prime_begin: int, prime_begin_out: int, L_ou
 
 def words_to_ints(words: np.ndarray) -> np.ndarray:
     """int64 [..., W] two's-complement words -> object array of Python ints."""
-    w = np.asarray(words).astype(np.uint64)
+    w = np.ascontiguousarray(np.asarray(words).astype("<u8"))
     W = w.shape[-1]
     flat = w.reshape(-1, W)
     out = np.empty(flat.shape[0], dtype=object)
     for e in range(flat.shape[0]):
-        u = 0
-        for k in range(W):
-            u |= int(flat[e, k]) << (64 * k)
-        if u >> (64 * W - 1):
-            u -= 1 << (64 * W)
-        out[e] = u
+        out[e] = int.from_bytes(flat[e].tobytes(), "little", signed=True)
     return out.reshape(w.shape[:-1])
 
 
@@ -734,9 +729,10 @@ def unimodular_certify(ctx: Context, d: np.ndarray, max_steps: int = -1, want_z:
 def words_to_uints(w: np.ndarray) -> np.ndarray:
     """Rows of little-endian 64-bit words as non-negative Python ints (an
     object array)."""
-    out = w[:, -1].astype(object)
-    for k in range(w.shape[1] - 2, -1, -1):
-        out = (out << 64) | w[:, k].astype(object)
+    w = np.ascontiguousarray(w, dtype="<u8")
+    out = np.empty(w.shape[0], dtype=object)
+    for i in range(w.shape[0]):            # linear in the words, unlike shifts
+        out[i] = int.from_bytes(w[i].tobytes(), "little")
     return out
 
 
@@ -746,10 +742,7 @@ def _smith_result_keep(h) -> SmithResult:
     nw = _I32()
     for i in range(_lib_smith_size(h)):
         _check(_lib_smith_get(h, i, ctypes.byref(words), ctypes.byref(nw)), "rns_smith_get")
-        v = 0
-        for k in range(nw.value):
-            v |= int(words[k]) << (64 * k)
-        s.append(v)
+        s.append(int.from_bytes(ctypes.string_at(words, 8 * nw.value), "little") if nw.value else 0)
     st = RnsSmithStats()
     _check(_lib_smith_stats(h, ctypes.byref(st)), "rns_smith_stats_get")
     return SmithResult(s, {f: getattr(st, f) for f, _ in RnsSmithStats._fields_})
