@@ -4,9 +4,10 @@ determinant and gcd elimination modulo it).  Each case names its generator
 in synth/ and its parameters; a planted case is also checked against the
 invariants it was built with.  With --vandermonde it writes
 tests/golden/smith_vandermonde.json instead: the Smith forms (and |det A|)
-of the Section 4.1 family A_ij = i^j mod n for n = 101, 199, 211 and 307, by
-the same oracle.  Run from the repository root:
-    python tests/golden/make_smith_golden.py [--vandermonde]
+of the Section 4.1 family A_ij = i^j mod n for n = 101, 199, 211, 307 and 503,
+by the same oracle (or for the sizes given after the flag, replacing those
+cases and keeping the others).  Run from the repository root:
+    python tests/golden/make_smith_golden.py [--vandermonde [n ...]]
 """
 import json
 import os
@@ -61,9 +62,14 @@ def main():
                    "cases": out}, f, indent=1)
 
 
-def main_vandermonde():
+def main_vandermonde(sizes):
+    path = os.path.join(ROOT, "tests", "golden", "smith_vandermonde.json")
+    kept = []
+    if os.path.exists(path):       # cases of other sizes stay as stored
+        with open(path) as f:
+            kept = [c for c in json.load(f)["cases"] if c["n"] not in sizes]
     out = []
-    for n in (101, 199, 211, 307):
+    for n in sizes:
         t = time.time()
         a = synth.vandermonde_mod(n)
         s = osmith.smith_form(a)
@@ -75,13 +81,17 @@ def main_vandermonde():
         ones = sum(1 for v in s if v == 1)
         out.append({"n": n, "ones": ones, "tail": [str(v) for v in s[ones:]], "det_abs": str(det)})
         print("vandermonde", n, "ones", ones, "bits", s[-1].bit_length(), "%.1fs" % (time.time() - t), flush=True)
-    with open(os.path.join(ROOT, "tests", "golden", "smith_vandermonde.json"), "w") as f:
+    out = sorted(kept + out, key=lambda c: c["n"])
+    with open(path, "w") as f:
         json.dump({"source": "oracle.smith.smith_form on synth.vandermonde_mod (tests/golden/make_smith_golden.py "
                              "--vandermonde)", "cases": out}, f, indent=1)
 
 
 if __name__ == "__main__":
     if "--vandermonde" in sys.argv:
-        main_vandermonde()
+        # sizes after the flag, else the stored set (n = 503 takes the oracle
+        # over an hour)
+        sizes = [int(a) for a in sys.argv[sys.argv.index("--vandermonde") + 1:]] or [101, 199, 211, 307, 503]
+        main_vandermonde(sizes)
     else:
         main()
