@@ -101,7 +101,7 @@ def test_several_batches(ctx_small_batches, rg, n):
 
 
 def test_vandermonde_golden(ctx, rg):
-    """The Section 4.1 family at n = 101, 199, 211 and 307: S equals the
+    """The Section 4.1 family at n = 101, 199, 211, 307 and 503: S equals the
     oracle's (stored by tests/golden/make_smith_golden.py --vandermonde);
     up to n = 199 also the massager's checks in exact integers, with
     |det A| from the oracle (above that the Python-integer products take
